@@ -1,0 +1,186 @@
+"""The defect-correction preconditioner (Section 3.1, eqs. (3.1)-(3.4)).
+Test infrastructure (oracle).
+
+One application to a residual r (the error propagator of eq. (3.1)):
+  level 0 (K0):   x0 = 0;  nu1 pre-relaxation sweeps on K0 x0 = r
+                  r0 = r - K0 x0;  b1 = eta R0 r0            (eq. (3.2))
+  levels 1..L-1:  the multilevel cycle of eq. (3.4) on the P1isoP2/P1
+                  hierarchy of Algorithm 1 (pre-relax, residual, restrict with
+                  P_l^T, recurse, prolong with P_l, post-relax)
+  level L:        exact solve (dense LU of K_L bordered with the coarse
+                  pressure null vector when the pressure is only defined up
+                  to a constant)
+  back on K0:     x0 += P0 x1;  nu2 post-relaxation sweeps.
+Transfers (Section 3.1): Taylor-Hood P0 = R0 = I.  Scott-Vogelius: velocity
+identity, P0^p duplicates a continuous P1 pressure onto the discontinuous
+DoFs, R0^p = M_cg^{-1} (P0^p)^T M_dg (an L2 projection, solved exactly here).
+Schedules (Section 4): "all" relaxes on every level but the coarsest,
+"skip1" skips level 1, "skip0" skips level 0.
+Dirichlet rows are identity rows: the preconditioner returns r there.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+import scipy.sparse.linalg as spla
+
+from . import vanka
+from .dlsc import DLSCLevel
+from .sa import stokes_hierarchy
+from .sparse import submatrix
+
+
+@dataclass
+class Params:
+    relax: str = "vanka"  # "vanka" or "dlsc"
+    schedule: str = "all"  # "all", "skip1", "skip0"
+    nu1: int = 1
+    nu2: int = 1
+    omega0: float = 0.5
+    omega: float = 0.5
+    eta_u: float = 1.0
+    eta_p: float = 1.0
+    cheb: tuple | None = None  # DLSC Chebyshev degrees (momentum, continuity, pressure)
+    theta: float = 0.02
+    max_coarse: int = 300
+    max_levels: int = 10
+    seed: int = 0x5EED
+
+
+class DCPreconditioner:
+    def __init__(self, prob, par: Params):
+        self.par = par
+        d = self.dim = prob.dim
+        self.disc = prob.disc
+        self.n0 = prob.n0
+        self.free0 = np.nonzero(~prob.dir0)[0]
+        self.dir0 = np.nonzero(prob.dir0)[0]
+        free1 = np.nonzero(~prob.dir1)[0]
+        self.K0 = submatrix(prob.K0, self.free0, self.free0)
+        self.f0 = prob.field0[self.free0]
+        K1 = submatrix(prob.K1, free1, free1)
+        f1 = prob.field1[free1]
+        self.levels = stokes_hierarchy(K1, f1, prob.Ap, d, par.theta, par.max_coarse, par.max_levels)
+        self.nvel = int((self.f0 < d).sum())
+        assert self.nvel == int((f1 < d).sum())
+        L = len(self.levels)
+        relax_l = [True] * (L + 1)  # index 0 = K0, 1.. = hierarchy entries; the coarsest is solved
+        if par.schedule == "skip1":
+            relax_l[1] = False
+        elif par.schedule == "skip0":
+            relax_l[0] = False
+        self.relax_on = relax_l
+        cheb = par.cheb or ((3, 3, 6) if d == 2 else (4, 4, 16))
+        # relaxation data, level 0 and levels 1..L-1 (hierarchy entries 0..L-2)
+        self.relax = []
+        ops = [(self.K0, self.f0)] + [(lv.K, lv.field) for lv in self.levels[:-1]]
+        for l, (K, f) in enumerate(ops):
+            if par.relax == "vanka":
+                if l == 0 and self.disc == "SV":
+                    pos = -np.ones(self.n0, dtype=np.int64)
+                    pos[self.free0] = np.arange(self.free0.size)
+                    seeds = pos[prob.elem_p0]
+                    self.relax.append(vanka.patches_element_seeds(K, f, d, seeds))
+                else:
+                    self.relax.append(vanka.patches_single_seed(K, f, d))
+            else:
+                nv = int((f < d).sum())
+                mu = prob.mu_diag0[self.free0[:nv]] if l == 0 else np.ones(nv)
+                self.relax.append(DLSCLevel(K, f, d, mu, cheb, par.seed + 2 * l))
+        # coarsest level: dense LU of the (bordered) operator
+        last = self.levels[-1]
+        Kc = last.K.toarray()
+        self.singular = bool(prob.p_nullspace)
+        if self.singular:
+            nvec = np.zeros(Kc.shape[0])
+            nvec[last.field == d] = last.null_p
+            nvec /= np.linalg.norm(nvec)
+            Kb = np.zeros((Kc.shape[0] + 1,) * 2)
+            Kb[:-1, :-1] = Kc
+            Kb[:-1, -1] = nvec
+            Kb[-1, :-1] = nvec
+            self.Kc = Kb
+        else:
+            self.Kc = Kc
+        if self.disc == "SV":
+            fp0 = self.free0[self.nvel:] - prob.meta["n_u"]
+            self.Pp = prob.Pp0.tocsr()[fp0]
+            self.Mdg = submatrix(prob.Mdg, fp0, fp0)
+            self.Mcg_lu = spla.splu(prob.Mcg.tocsc())
+
+    # -- pieces -------------------------------------------------------------
+    def _relax(self, l: int, K, b, x, sweeps: int, omega: float):
+        R = self.relax[l]
+        if isinstance(R, vanka.Patches):
+            for _ in range(sweeps):
+                x = vanka.sweep(K, R, b, x, omega)
+            return x
+        return R.relax(b, x, sweeps)
+
+    def _coarse(self, b):
+        if self.singular:
+            y = np.linalg.solve(self.Kc, np.concatenate([b, [0.0]]))
+            return y[:-1]
+        return np.linalg.solve(self.Kc, b)
+
+    def _vcycle(self, j: int, b: np.ndarray) -> np.ndarray:
+        """Cycle on hierarchy entry j (paper level l = j + 1)."""
+        lv = self.levels[j]
+        if j == len(self.levels) - 1:
+            return self._coarse(b)
+        p = self.par
+        x = np.zeros_like(b)
+        relax = self.relax_on[j + 1]
+        if relax:
+            x = self._relax(j + 1, lv.K, b, x, p.nu1, p.omega)
+        r = b - lv.K @ x
+        xc = self._vcycle(j + 1, lv.P.T @ r)
+        x = x + lv.P @ xc
+        if relax:
+            x = self._relax(j + 1, lv.K, b, x, p.nu2, p.omega)
+        return x
+
+    def restrict0(self, r0: np.ndarray) -> np.ndarray:
+        p, nv = self.par, self.nvel
+        out = np.empty(self.levels[0].K.shape[0])
+        out[:nv] = p.eta_u * r0[:nv]
+        if self.disc == "TH":
+            out[nv:] = p.eta_p * r0[nv:]
+        else:
+            out[nv:] = p.eta_p * self.Mcg_lu.solve(self.Pp.T @ (self.Mdg @ r0[nv:]))
+        return out
+
+    def prolong0(self, x1: np.ndarray) -> np.ndarray:
+        nv = self.nvel
+        if self.disc == "TH":
+            return x1.copy()
+        return np.concatenate([x1[:nv], self.Pp @ x1[nv:]])
+
+    def apply(self, r: np.ndarray) -> np.ndarray:
+        p = self.par
+        b = r[self.free0]
+        x = np.zeros_like(b)
+        if self.relax_on[0]:
+            x = self._relax(0, self.K0, b, x, p.nu1, p.omega0)
+        r0 = b - self.K0 @ x
+        x1 = self._vcycle(0, self.restrict0(r0))
+        x = x + self.prolong0(x1)
+        if self.relax_on[0]:
+            x = self._relax(0, self.K0, b, x, p.nu2, p.omega0)
+        z = np.empty(self.n0)
+        z[self.free0] = x
+        z[self.dir0] = r[self.dir0]
+        return z
+
+
+def default_params(prob, relax: str = "vanka", **over) -> Params:
+    if prob.disc == "SV":
+        p = Params(relax=relax, omega0=0.78, omega=0.5, eta_u=1.0, eta_p=2.68)
+    else:
+        p = Params(relax=relax)
+    if relax == "dlsc":
+        p.nu1 = p.nu2 = 2
+    for k, v in over.items():
+        setattr(p, k, v)
+    return p
