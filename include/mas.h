@@ -1,0 +1,176 @@
+/*
+ * mas.h -- C-ABI of libmas: the solve phase of the monolithic defect-correction
+ * AMG preconditioner for Stokes saddle systems (Voronin, MacLachlan, Olson,
+ * Tuminaro, "Monolithic Algebraic Multigrid Preconditioners for the Stokes
+ * Equations", arXiv 2306.06795), on one AMD MI355X (gfx950).
+ *
+ * The caller hands over the assembled operators the paper's method starts
+ * from (Section 3.1): the high-order saddle matrix K0 (Taylor-Hood P2/P1 or
+ * Scott-Vogelius P2/P1disc), the low-order P1isoP2/P1 matrix K1 and the
+ * pressure stiffness matrix A_p (the auxiliary operator of Algorithm 1), with
+ * the DoF-to-field map.  mas_setup builds the hierarchy and relaxation data,
+ * mas_apply applies one defect-correction cycle (eq. (3.1)), mas_solve runs
+ * restarted right-preconditioned FGMRES(restart) with that preconditioner
+ * (Section 4).
+ *
+ * Conventions
+ *  - Unknowns are field-blocked: [u_0; ...; u_{dim-1}; p].  field[i] is the
+ *    velocity component 0..dim-1 of row i, or dim for a pressure row.
+ *  - K0 and K1 are symmetric, full size, with Dirichlet velocity rows stored
+ *    as identity rows and their columns removed (Dirichlet data lifted into
+ *    the right-hand side by the caller).  Column indices sorted in each row.
+ *  - Host arrays passed to mas_setup are borrowed for the duration of the
+ *    call only.  Device arrays passed to mas_apply / mas_solve are owned by
+ *    the caller.  All device work is enqueued on the stream given (a
+ *    hipStream_t passed as void*; NULL = the default stream).
+ *  - Every function returns a status code (MAS_OK = 0, a warning > 0, an
+ *    error < 0); mas_last_error() gives a thread-local message for the last
+ *    failing call.  No C++ exception crosses this interface.
+ *  - A handle may be used from one host thread and one stream at a time.
+ */
+#ifndef MAS_H
+#define MAS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mas_handle mas_handle;
+
+enum mas_status {
+  MAS_OK = 0,
+  MAS_NOT_CONVERGED = 1,   /* warning: max_it reached, x holds the last iterate */
+  MAS_EINVAL = -1,         /* bad argument, shape or field-map mismatch, non-finite value */
+  MAS_ESINGULAR_PATCH = -2,/* a patch block or Schur complement is singular (message names it) */
+  MAS_ENOMEM = -3,         /* device or host allocation failed */
+  MAS_EHIP = -4,           /* a HIP runtime call failed */
+  MAS_ENAN = -5            /* the residual became NaN or Inf */
+};
+
+enum mas_disc { MAS_TH = 0, MAS_SV = 1 };                 /* Section 2.1 */
+enum mas_relax { MAS_RELAX_VANKA = 0, MAS_RELAX_DLSC = 1 };/* Sections 3.3.1, 3.3.2 */
+enum mas_schedule { MAS_DC_ALL = 0, MAS_DC_SKIP1 = 1, MAS_DC_SKIP0 = 2 }; /* Section 4 */
+enum mas_precision { MAS_FP64 = 0, MAS_FP32 = 1 };        /* number type of the cycle */
+
+/* CSR matrix in host memory: row pointers int64 (nrows+1), column indices
+ * int32 (sorted within each row), values FP64.  Explicitly stored zeros are
+ * part of the structure (patches are read from structure, Section 3.3.1). */
+typedef struct {
+  int64_t nrows, ncols;
+  const int64_t* indptr;
+  const int32_t* indices;
+  const double* data;
+} mas_csr;
+
+typedef struct {
+  int32_t dim;            /* 2 or 3 */
+  int32_t disc;           /* mas_disc */
+  mas_csr K0;             /* high-order saddle operator, n0 x n0 */
+  mas_csr K1;             /* P1isoP2/P1 saddle operator, n1 x n1 (same velocity DoFs as K0) */
+  mas_csr Ap;             /* pressure stiffness of K1's pressure space, np1 x np1 */
+  const int8_t* field0;   /* n0 */
+  const int8_t* field1;   /* n1 */
+  const uint8_t* dir0;    /* n0, 1 = Dirichlet row */
+  const uint8_t* dir1;    /* n1 */
+  int32_t p_nullspace;    /* 1: velocity prescribed on the whole boundary, the
+                             pressure is determined up to a constant (Section 2) */
+  const double* p_weight0;/* np0 = #pressure rows of K0: int psi_i (zero-mean
+                             pressure after mas_solve); may be NULL */
+  const double* mu_diag0; /* nu0 = #velocity rows of K0: diagonal velocity mass
+                             for DLSC on K0 (Section 3.3.2); NULL = identity */
+  /* Scott-Vogelius only (Section 3.1): */
+  int64_t n_elem;         /* number of elements */
+  const int64_t* elem_p0; /* n_elem x 3: K0 row ids of each element's pressures */
+  mas_csr Pp0;            /* np0 x np1 duplication P1 -> P1disc */
+  mas_csr Mdg;            /* np0 x np0 P1disc mass */
+  mas_csr Mcg;            /* np1 x np1 P1 mass */
+} mas_problem;
+
+typedef struct {
+  int32_t relax;          /* mas_relax on levels >= 0 */
+  int32_t schedule;       /* mas_schedule */
+  int32_t nu1, nu2;       /* pre/post relaxation sweeps per level */
+  double omega0, omega;   /* Vanka damping on K0 and on the K1 hierarchy */
+  double eta_u, eta_p;    /* residual weights of eq. (3.2) */
+  int32_t cheb_deg[3];    /* DLSC Chebyshev degrees (momentum, continuity, pressure; Table 3) */
+  int32_t precision;      /* mas_precision of the cycle (FGMRES is always FP64) */
+  int32_t restart;        /* FGMRES restart length (20 in Section 4) */
+  int32_t max_coarse;     /* per-field coarsest size of smoothed aggregation */
+  int32_t max_levels;     /* per-field maximum number of levels */
+  double theta;           /* strength threshold: a_ij^2 >= theta^2 a_ii a_jj */
+  uint64_t seed;          /* SplitMix64 seed of the Lanczos start vectors */
+  double mass_rtol;       /* relative tolerance of the SV pressure-mass solve */
+} mas_params;
+
+typedef struct {
+  int32_t iters;          /* FGMRES iterations (preconditioner applications) */
+  int32_t converged;
+  double relres;          /* true ||b - K0 x|| / ||b|| at exit */
+  double conv_factor;     /* geometric mean of the last 10 residual reductions (Section 4) */
+} mas_solve_info;
+
+typedef struct {
+  int32_t n_levels;       /* 1 (K0) + hierarchy levels K1..K_L */
+  int64_t n[16];          /* free rows per level (0 = K0) */
+  int64_t nnz[16];        /* stored entries per level operator */
+  int64_t n_vel[16];      /* velocity rows per level */
+  int64_t n_patches[16];  /* Vanka patches per relaxed level (0 if none) */
+  int64_t patch_dofs[16]; /* sum of patch sizes per level */
+  int64_t factor_entries[16]; /* stored factor values per level (packed symmetric blocks) */
+  int64_t p_nnz[16];      /* entries of P_l (level l -> l-1), 0 for l <= 1 */
+  int64_t coarse_n;       /* rows of the dense coarsest solve (incl. border) */
+} mas_hier_info;
+
+/* Default parameters: Section 4 / Tables 3 and 4 where the paper fixes them. */
+void mas_default_params(int32_t dim, int32_t disc, int32_t relax, mas_params* out);
+
+/* Build the hierarchy (Algorithm 1 on K1 and A_p, per-field smoothed
+ * aggregation), the Vanka patches of every relaxed level with their block
+ * factorisation computed on the GPU in FP64 (eqs. (3.6)-(3.8)), or the DLSC
+ * operators, and the dense coarsest-level inverse.
+ * Errors: MAS_EINVAL, MAS_ESINGULAR_PATCH, MAS_ENOMEM, MAS_EHIP. */
+int mas_setup(const mas_problem* prob, const mas_params* par, void* stream, mas_handle** out);
+
+/* Host-only analysis: the hierarchy (Algorithm 1) and the patches, without
+ * touching the GPU.  The handle supports mas_get_info, mas_export_level and
+ * mas_destroy only (no device is needed).  Errors as mas_setup. */
+int mas_analyze(const mas_problem* prob, const mas_params* par, mas_handle** out);
+
+/* z = B r: one defect-correction cycle (eq. (3.1)) applied to nrhs right-hand
+ * sides.  r, z: device FP64, n0 x nrhs row-major (right-hand side fastest).
+ * Dirichlet rows are returned unchanged (z_D = r_D).  Asynchronous. */
+int mas_apply(mas_handle* h, const double* r, double* z, int32_t nrhs, void* stream);
+
+/* FGMRES for K0 x = b from x0 = 0 (Section 4).  b, x: device FP64 n0 x nrhs.
+ * Stops when ||b - K0 x|| <= rtol ||b|| (true residual) or after max_it
+ * iterations.  With p_nullspace and p_weight0 the returned pressure has zero
+ * mean.  info (host, nrhs entries) may be NULL.  Returns MAS_OK,
+ * MAS_NOT_CONVERGED or an error.  Synchronises the stream. */
+int mas_solve(mas_handle* h, const double* b, double* x, int32_t nrhs, double rtol,
+              int32_t max_it, mas_solve_info* info, void* stream);
+
+/* Sizes of the built hierarchy. */
+int mas_get_info(const mas_handle* h, mas_hier_info* out);
+
+/* Copy level l's operator (0 = free K0, 1 = free K1, ...) to host CSR.  Call
+ * with indptr == NULL to get the sizes. */
+int mas_export_level(const mas_handle* h, int32_t level, int64_t* nrows, int64_t* nnz,
+                     int64_t* indptr, int32_t* indices, double* data);
+
+/* Average device time (ms) of the last mas_solve's kernels, by kind:
+ * out[0] whole preconditioner applications, out[1] Vanka patch kernels,
+ * out[2] SpMV kernels.  Filled only when timing was enabled. */
+int mas_set_timing(mas_handle* h, int32_t enable);
+int mas_get_timing(const mas_handle* h, double* out, int32_t n);
+
+int mas_destroy(mas_handle* h);
+const char* mas_error_string(int status);
+const char* mas_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MAS_H */

@@ -1,0 +1,67 @@
+// Host-side setup of libmas: sparse matrices, per-field smoothed aggregation
+// (Algorithm 1), algebraic Vanka patches (Section 3.3.1), Lanczos estimates
+// for the Chebyshev intervals (Table 3).  Plain C++17, no HIP.
+#pragma once
+#include <cstdint>
+#include <functional>
+#include <string>
+#include <vector>
+
+namespace mas {
+
+struct Csr {
+  int64_t nr = 0, nc = 0;
+  std::vector<int64_t> ptr;  // nr + 1
+  std::vector<int32_t> ind;  // sorted within each row
+  std::vector<double> val;
+  int64_t nnz() const { return ptr.empty() ? 0 : ptr[nr]; }
+};
+
+struct Error {
+  int code;
+  std::string msg;
+};
+
+Csr csr_copy(int64_t nr, int64_t nc, const int64_t* ptr, const int32_t* ind, const double* val);
+// rows/cols: kept indices (ascending); structure of A restricted to them, explicit zeros kept
+Csr submatrix(const Csr& A, const std::vector<int64_t>& rows, const std::vector<int64_t>& cols);
+Csr transpose(const Csr& A);
+// C = A B with the structural pattern of the product (no entry dropped)
+Csr spgemm(const Csr& A, const Csr& B);
+Csr galerkin(const Csr& P, const Csr& A);  // P^T A P
+Csr block_diag(const std::vector<const Csr*>& blocks);
+void spmv(const Csr& A, const double* x, double* y);
+
+// ---- smoothed aggregation for one scalar field
+struct FieldLevel {
+  Csr P;                 // interpolation to this level's matrix from the next coarser one
+  std::vector<double> B; // near-null vector on the coarse side
+};
+std::vector<int32_t> aggregate(const Csr& A, double theta, int32_t* n_agg);
+void sa_field(const Csr& A, double theta, int max_coarse, int max_levels,
+              std::vector<Csr>& Ps, std::vector<std::vector<double>>& Bs);
+
+// ---- Vanka patches of one level (velocity rows sorted, then the seeds)
+struct PatchSet {
+  int32_t dim = 2;
+  std::vector<int64_t> off;   // np + 1 offsets into dofs
+  std::vector<int32_t> dofs;  // level DoF ids
+  std::vector<int32_t> dims;  // np x 4: DoFs per velocity component (3 slots) and seeds
+  std::vector<int64_t> foff;  // np + 1 offsets into the packed factor store
+  std::vector<int32_t> inv_ptr, inv_pos;  // DoF -> positions in dofs (ascending)
+  std::vector<double> w;      // partition of unity per DoF
+  int64_t np() const { return (int64_t)off.size() - 1; }
+  int32_t max_m = 0;
+  int64_t max_f = 0;
+};
+PatchSet patches_single_seed(const Csr& K, const std::vector<int8_t>& field, int dim);
+PatchSet patches_element_seeds(const Csr& K, const std::vector<int8_t>& field, int dim,
+                               const std::vector<int32_t>& seeds, int ns);
+
+// ---- misc
+double lanczos_max(const Csr& A, uint64_t seed, int steps);
+double lanczos_max_op(int64_t n, const std::function<void(const double*, double*)>& op, uint64_t seed,
+                      int steps);
+uint64_t splitmix64(uint64_t seed, uint64_t counter);
+
+}  // namespace mas

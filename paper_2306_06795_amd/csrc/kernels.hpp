@@ -1,0 +1,487 @@
+// HIP kernels of libmas for gfx950 (CDNA4, 64-lane wavefronts).
+//
+// Patch factor layout (one contiguous record per patch, value type T):
+//   [ A_0^-1 | A_1^-1 | A_2^-1 | Uhat | S^-1 ]
+// A_c^-1: inverse of the patch's velocity block of component c, symmetric,
+//         packed upper: entry (i, j), i <= j, at j (j + 1) / 2 + i;
+// Uhat  = -A^-1 B^T (nv x ns), column s contiguous;
+// S^-1  = (-B A^-1 B^T)^-1 (ns x ns), packed the same way.
+// The apply uses Bhat = -S^-1 B A^-1 = S^-1 Uhat^T, so Bhat is not stored:
+//   y_u = A^-1 b_u,  y_p = S^-1 (Uhat^T b_u + b_p),  x_u = y_u + Uhat y_p,  x_p = y_p
+// (block factorisation of the patch saddle matrix, Section 3.3.1).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mas {
+
+constexpr int WAVE = 64;
+constexpr int MAX_NS = 4;  // seeds per patch handled by the kernels
+
+__device__ __forceinline__ int64_t packed_index(int i, int j) {
+  int a = i < j ? i : j, b = i < j ? j : i;
+  return (int64_t)b * (b + 1) / 2 + a;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// CSR products.  TEAM lanes per row (power of two <= 64).
+// MODE 0: y = A x   MODE 1: y = b - A x   MODE 2: y += A x
+template <typename T, int TEAM, int MODE>
+__global__ void __launch_bounds__(256) k_csr(int n, const int* __restrict__ ptr, const int* __restrict__ ind,
+                                             const T* __restrict__ val, const T* __restrict__ x,
+                                             const T* __restrict__ b, T* __restrict__ y) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int row = gid / TEAM;
+  const int lane = gid & (TEAM - 1);
+  T s = 0;
+  if (row < n) {
+    const int e1 = ptr[row + 1];
+    for (int e = ptr[row] + lane; e < e1; e += TEAM) s += val[e] * x[ind[e]];
+  }
+#pragma unroll
+  for (int o = TEAM / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if (row < n && lane == 0) {
+    if (MODE == 0) y[row] = s;
+    else if (MODE == 1) y[row] = b[row] - s;
+    else y[row] += s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// vector kernels
+
+template <typename T>
+__global__ void k_fill(int64_t n, T* __restrict__ y, T v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = v;
+}
+
+// dst[k] = (T) src[idx[k]]
+template <typename T, typename S>
+__global__ void k_gather(int64_t n, const int64_t* __restrict__ idx, const S* __restrict__ src, T* __restrict__ dst) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) dst[k] = (T)src[idx[k]];
+}
+
+// dst[idx[k]] = src[idx[k]]
+__global__ void k_copy_idx(int64_t n, const int64_t* __restrict__ idx, const double* __restrict__ src,
+                           double* __restrict__ dst) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) dst[idx[k]] = src[idx[k]];
+}
+
+// dst[idx[k]] = (T) src[k]
+template <typename T, typename S>
+__global__ void k_scatter(int64_t n, const int64_t* __restrict__ idx, const S* __restrict__ src, T* __restrict__ dst) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) dst[idx[k]] = (T)src[k];
+}
+
+// y[k] = (k < nsplit ? a : b) * x[k]
+template <typename T>
+__global__ void k_scale2(int64_t n, int64_t nsplit, T a, T b, const T* __restrict__ x, T* __restrict__ y) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) y[k] = (k < nsplit ? a : b) * x[k];
+}
+
+// y = a x + b y
+template <typename T>
+__global__ void k_axpby(int64_t n, T a, const T* __restrict__ x, T b, T* __restrict__ y) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) y[k] = a * x[k] + b * y[k];
+}
+
+// ---------------------------------------------------------------------------
+// additive Vanka: one wavefront per patch, patch data staged through LDS.
+// Writes the patch solution x_i = K_i^-1 V_i r into Y at the patch's offset.
+template <typename T, bool STAGE>
+__global__ void __launch_bounds__(WAVE) k_vanka_apply(int64_t np, const int64_t* __restrict__ off,
+                                                     const int4* __restrict__ dims,
+                                                     const int64_t* __restrict__ foff,
+                                                     const int* __restrict__ dofs, const T* __restrict__ fac,
+                                                     const T* __restrict__ r, T* __restrict__ Y, int max_m) {
+  extern __shared__ unsigned char smem_raw[];
+  T* sb = reinterpret_cast<T*>(smem_raw);
+  T* sy = sb + max_m;
+  const int64_t p = blockIdx.x;
+  if (p >= np) return;
+  const int lane = threadIdx.x;
+  const int4 d = dims[p];
+  const int nv = d.x + d.y + d.z, ns = d.w, m = nv + ns;
+  const int64_t o = off[p];
+  for (int k = lane; k < m; k += WAVE) sb[k] = r[dofs[o + k]];
+  const int64_t f0 = foff[p], nf = foff[p + 1] - f0;
+  const T* sf;
+  if (STAGE) {
+    T* st = sy + max_m;
+    for (int64_t k = lane; k < nf; k += WAVE) st[k] = fac[f0 + k];
+    sf = st;
+  } else {
+    sf = fac + f0;  // record too large for LDS: read it from memory
+  }
+  __syncthreads();
+  const int nc[3] = {d.x, d.y, d.z};
+  // y_u = A^-1 b_u, one row per lane
+  for (int row = lane; row < nv; row += WAVE) {
+    int c = 0, cs = 0;
+    int64_t ao = 0;
+    while (row >= cs + nc[c]) {
+      ao += (int64_t)nc[c] * (nc[c] + 1) / 2;
+      cs += nc[c];
+      ++c;
+    }
+    const int i = row - cs;
+    const T* A = sf + ao;
+    T acc = 0;
+    for (int j = 0; j < nc[c]; ++j) acc += A[packed_index(i, j)] * sb[cs + j];
+    sy[row] = acc;
+  }
+  int64_t ua = (int64_t)d.x * (d.x + 1) / 2 + (int64_t)d.y * (d.y + 1) / 2 + (int64_t)d.z * (d.z + 1) / 2;
+  const T* U = sf + ua;
+  const T* Si = U + (int64_t)nv * ns;
+  T t[MAX_NS], yp[MAX_NS];
+  for (int s = 0; s < ns; ++s) {
+    T part = 0;
+    for (int k = lane; k < nv; k += WAVE) part += U[(int64_t)s * nv + k] * sb[k];
+    t[s] = wave_sum(part) + sb[nv + s];
+  }
+  for (int s = 0; s < ns; ++s) {
+    T acc = 0;
+    for (int q = 0; q < ns; ++q) acc += Si[packed_index(s, q)] * t[q];
+    yp[s] = acc;
+  }
+  __syncthreads();
+  for (int row = lane; row < nv; row += WAVE) {
+    T acc = sy[row];
+    for (int s = 0; s < ns; ++s) acc += U[(int64_t)s * nv + row] * yp[s];
+    Y[o + row] = acc;
+  }
+  for (int s = 0; s < ns; ++s)
+    if (lane == s) Y[o + nv + s] = yp[s];
+}
+
+// x[j] (+)= omega W_j sum of the patch values held for DoF j (deterministic
+// pull over the patch list in increasing patch order).
+template <typename T>
+__global__ void k_vanka_pull(int n, const int* __restrict__ inv_ptr, const int* __restrict__ inv_pos,
+                             const T* __restrict__ Y, const T* __restrict__ w, T omega, T* __restrict__ x,
+                             int accumulate) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  T acc = 0;
+  for (int k = inv_ptr[j]; k < inv_ptr[j + 1]; ++k) acc += Y[inv_pos[k]];
+  T v = omega * w[j] * acc;
+  x[j] = accumulate ? x[j] + v : v;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 block factorisation of every patch (setup).  One wavefront per patch.
+// W: work area of max_nc^2 + 2 * max_nv * MAX_NS doubles (LDS or global).
+__device__ __forceinline__ int find_sorted(const int* a, int n, int key) {
+  int lo = 0, hi = n - 1;
+  while (lo <= hi) {
+    int mid = (lo + hi) >> 1;
+    int v = a[mid];
+    if (v == key) return mid;
+    if (v < key) lo = mid + 1; else hi = mid - 1;
+  }
+  return -1;
+}
+
+template <typename TO>
+__global__ void __launch_bounds__(WAVE) k_vanka_factor(int64_t np, const int64_t* __restrict__ off,
+                                                      const int4* __restrict__ dims,
+                                                      const int64_t* __restrict__ foff, const int* __restrict__ dofs,
+                                                      const int* __restrict__ kptr, const int* __restrict__ kind,
+                                                      const double* __restrict__ kval, TO* __restrict__ fac,
+                                                      double* __restrict__ gwork, int64_t work_stride,
+                                                      int use_lds, int max_nv, double piv_tol,
+                                                      int64_t* __restrict__ bad) {
+  extern __shared__ double smem_d[];
+  for (int64_t p = blockIdx.x; p < np; p += gridDim.x) {
+    double* W = use_lds ? smem_d : gwork + (int64_t)blockIdx.x * work_stride;
+    double* Bm = W + (work_stride - 2 * (int64_t)max_nv * MAX_NS);  // ns x nv
+    double* U = Bm + (int64_t)max_nv * MAX_NS;                      // nv x ns (row k: U[k*ns+s])
+    const int lane = threadIdx.x;
+    const int4 d = dims[p];
+    const int nc[3] = {d.x, d.y, d.z};
+    const int nv = d.x + d.y + d.z, ns = d.w;
+    const int* P = dofs + off[p];
+    TO* out = fac + foff[p];
+    // B rows of the seeds restricted to the patch velocities
+    for (int k = lane; k < ns * nv; k += WAVE) Bm[k] = 0.0;
+    __syncthreads();
+    for (int s = 0; s < ns; ++s) {
+      const int row = P[nv + s];
+      for (int e = kptr[row] + lane; e < kptr[row + 1]; e += WAVE) {
+        int k = find_sorted(P, nv, kind[e]);
+        if (k >= 0) Bm[s * nv + k] = kval[e];
+      }
+    }
+    __syncthreads();
+    int cs = 0;
+    int64_t ao = 0;
+    for (int c = 0; c < 3; ++c) {
+      const int n = nc[c];
+      if (n == 0) continue;
+      for (int64_t k = lane; k < (int64_t)n * n; k += WAVE) W[k] = 0.0;
+      __syncthreads();
+      for (int i = lane; i < n; i += WAVE) {
+        const int row = P[cs + i];
+        for (int e = kptr[row]; e < kptr[row + 1]; ++e) {
+          int j = find_sorted(P + cs, n, kind[e]);
+          if (j >= 0) W[(int64_t)i * n + j] = kval[e];
+        }
+      }
+      __syncthreads();
+      // in-place Gauss-Jordan inversion (the block is symmetric positive definite)
+      double scale = 0.0;
+      for (int i = 0; i < n; ++i) scale = fmax(scale, fabs(W[(int64_t)i * n + i]));
+      for (int k = 0; k < n; ++k) {
+        const double akk = W[(int64_t)k * n + k];
+        if (!(akk > piv_tol * scale)) {
+          if (lane == 0) atomicMin((unsigned long long*)bad, (unsigned long long)p);
+        }
+        const double dk = 1.0 / akk;
+        __syncthreads();
+        for (int j = lane; j < n; j += WAVE)
+          if (j != k) W[(int64_t)k * n + j] *= dk;
+        __syncthreads();
+        for (int i = lane; i < n; i += WAVE) {
+          if (i == k) continue;
+          const double f = W[(int64_t)i * n + k];
+          for (int j = 0; j < n; ++j)
+            if (j != k) W[(int64_t)i * n + j] -= f * W[(int64_t)k * n + j];
+          W[(int64_t)i * n + k] = -f * dk;
+        }
+        __syncthreads();
+        if (lane == 0) W[(int64_t)k * n + k] = dk;
+        __syncthreads();
+      }
+      // packed upper of the (symmetric) inverse
+      for (int64_t q = lane; q < (int64_t)n * (n + 1) / 2; q += WAVE) {
+        int j = (int)((sqrt(8.0 * (double)q + 1.0) - 1.0) * 0.5);
+        while ((int64_t)j * (j + 1) / 2 > q) --j;
+        while ((int64_t)(j + 1) * (j + 2) / 2 <= q) ++j;
+        int i = (int)(q - (int64_t)j * (j + 1) / 2);
+        out[ao + q] = (TO)(0.5 * (W[(int64_t)i * n + j] + W[(int64_t)j * n + i]));
+      }
+      // U_c = A_c^-1 B_c^T
+      for (int i = lane; i < n; i += WAVE)
+        for (int s = 0; s < ns; ++s) {
+          double acc = 0.0;
+          for (int j = 0; j < n; ++j) acc += W[(int64_t)i * n + j] * Bm[s * nv + cs + j];
+          U[(int64_t)(cs + i) * ns + s] = acc;
+        }
+      __syncthreads();
+      ao += (int64_t)n * (n + 1) / 2;
+      cs += n;
+    }
+    // S = -B U (ns x ns), inverted by one lane with partial pivoting
+    if (lane == 0) {
+      double S[MAX_NS * MAX_NS], I[MAX_NS * MAX_NS];
+      double smax = 0.0;
+      for (int s = 0; s < ns; ++s)
+        for (int t = 0; t < ns; ++t) {
+          double acc = 0.0;
+          for (int k = 0; k < nv; ++k) acc += Bm[s * nv + k] * U[(int64_t)k * ns + t];
+          S[s * ns + t] = -acc;
+          I[s * ns + t] = (s == t) ? 1.0 : 0.0;
+          smax = fmax(smax, fabs(acc));
+        }
+      bool ok = smax > 0.0;
+      for (int k = 0; k < ns && ok; ++k) {
+        int pr = k;
+        for (int i = k + 1; i < ns; ++i)
+          if (fabs(S[i * ns + k]) > fabs(S[pr * ns + k])) pr = i;
+        if (!(fabs(S[pr * ns + k]) > piv_tol * smax)) { ok = false; break; }
+        if (pr != k)
+          for (int j = 0; j < ns; ++j) {
+            double t1 = S[k * ns + j]; S[k * ns + j] = S[pr * ns + j]; S[pr * ns + j] = t1;
+            double t2 = I[k * ns + j]; I[k * ns + j] = I[pr * ns + j]; I[pr * ns + j] = t2;
+          }
+        const double dk = 1.0 / S[k * ns + k];
+        for (int j = 0; j < ns; ++j) { S[k * ns + j] *= dk; I[k * ns + j] *= dk; }
+        for (int i = 0; i < ns; ++i) {
+          if (i == k) continue;
+          const double f = S[i * ns + k];
+          for (int j = 0; j < ns; ++j) { S[i * ns + j] -= f * S[k * ns + j]; I[i * ns + j] -= f * I[k * ns + j]; }
+        }
+      }
+      if (!ok) atomicMin((unsigned long long*)bad, (unsigned long long)p);
+      TO* Uh = out + ao;
+      TO* Si = Uh + (int64_t)nv * ns;
+      for (int t = 0; t < ns; ++t)
+        for (int s = 0; s <= t; ++s) Si[(int64_t)t * (t + 1) / 2 + s] = (TO)(0.5 * (I[s * ns + t] + I[t * ns + s]));
+    }
+    {
+      TO* Uh = out + ao;
+      for (int64_t q = lane; q < (int64_t)nv * ns; q += WAVE) {
+        int s = (int)(q / nv), k = (int)(q % nv);
+        Uh[q] = (TO)(-U[(int64_t)k * ns + s]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// dense coarse solve: y = C b (C row-major, ld columns), one wavefront per row,
+// accumulated in FP64.
+template <typename T>
+__global__ void __launch_bounds__(256) k_dense_gemv(int n, int ld, const double* __restrict__ C,
+                                                   const T* __restrict__ b, T* __restrict__ y) {
+  const int row = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  const int lane = threadIdx.x & (WAVE - 1);
+  double s = 0.0;
+  if (row < n)
+    for (int j = lane; j < n; j += WAVE) s += C[(int64_t)row * ld + j] * (double)b[j];
+  s = wave_sum(s);
+  if (row < n && lane == 0) y[row] = (T)s;
+}
+
+// Gauss-Jordan inversion with partial pivoting of a dense n x n FP64 matrix
+// (row-major), one pivot step per launch pair (setup only).
+__global__ void k_gj_pivot(int n, int k, double* __restrict__ A, int* __restrict__ perm, int* __restrict__ flag) {
+  // one block of 256 threads: find the pivot row and swap it into row k
+  __shared__ double best[256];
+  __shared__ int bi[256];
+  double v = -1.0;
+  int idx = k;
+  for (int i = k + threadIdx.x; i < n; i += blockDim.x) {
+    double a = fabs(A[(int64_t)i * n + k]);
+    if (a > v) { v = a; idx = i; }
+  }
+  best[threadIdx.x] = v;
+  bi[threadIdx.x] = idx;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      if (best[threadIdx.x + s] > best[threadIdx.x] ||
+          (best[threadIdx.x + s] == best[threadIdx.x] && bi[threadIdx.x + s] < bi[threadIdx.x])) {
+        best[threadIdx.x] = best[threadIdx.x + s];
+        bi[threadIdx.x] = bi[threadIdx.x + s];
+      }
+    }
+    __syncthreads();
+  }
+  const int pr = bi[0];
+  if (threadIdx.x == 0) {
+    perm[k] = pr;
+    if (!(best[0] > 0.0)) *flag = 1;
+  }
+  if (pr != k)
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+      double t = A[(int64_t)k * n + j];
+      A[(int64_t)k * n + j] = A[(int64_t)pr * n + j];
+      A[(int64_t)pr * n + j] = t;
+    }
+}
+
+// in-place elimination step k reads row k and column k from saved copies
+__global__ void k_gj_save(int n, int k, const double* __restrict__ A, double* __restrict__ rowk,
+                          double* __restrict__ colk) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) {
+    rowk[j] = A[(int64_t)k * n + j];
+    colk[j] = A[(int64_t)j * n + k];
+  }
+}
+
+__global__ void k_gj_step(int n, int k, double* __restrict__ A, const double* __restrict__ rowk,
+                          const double* __restrict__ colk) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * n) return;
+  const int i = (int)(t / n), j = (int)(t % n);
+  const double dk = 1.0 / rowk[k];
+  if (i == k) {
+    A[t] = (j == k) ? dk : rowk[j] * dk;
+  } else {
+    const double f = colk[i];
+    if (j == k) A[t] = -f * dk;
+    else A[t] -= f * rowk[j] * dk;
+  }
+}
+
+// undo the row interchanges: swap columns k and perm[k], k = n-1 .. 0
+__global__ void k_gj_colswap(int n, int k, const int* __restrict__ perm, double* __restrict__ A) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int pr = perm[k];
+  if (i < n && pr != k) {
+    double t = A[(int64_t)i * n + k];
+    A[(int64_t)i * n + k] = A[(int64_t)i * n + pr];
+    A[(int64_t)i * n + pr] = t;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 reductions and small FGMRES kernels
+
+// partial[b] = sum over block b of x . y
+__global__ void __launch_bounds__(256) k_dot_partial(int64_t n, const double* __restrict__ x,
+                                                    const double* __restrict__ y, double* __restrict__ partial) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    s += x[i] * y[i];
+  s = wave_sum(s);
+  if ((threadIdx.x & (WAVE - 1)) == 0) sh[threadIdx.x / WAVE] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// out[0] = sum of partial (sqrt if take_sqrt)
+__global__ void __launch_bounds__(256) k_reduce_final(int nb, const double* __restrict__ partial,
+                                                     double* __restrict__ out, int take_sqrt) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) s += partial[i];
+  s = wave_sum(s);
+  if ((threadIdx.x & (WAVE - 1)) == 0) sh[threadIdx.x / WAVE] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = sh[0] + sh[1] + sh[2] + sh[3];
+    out[0] = take_sqrt ? sqrt(t) : t;
+  }
+}
+
+// y -= (*h) x
+__global__ void k_axpy_neg_dev(int64_t n, const double* __restrict__ h, const double* __restrict__ x,
+                               double* __restrict__ y) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double a = *h;
+  if (i < n) y[i] -= a * x[i];
+}
+
+// y = x / (*h)  (x may alias y)
+__global__ void k_scale_inv_dev(int64_t n, const double* __restrict__ h, const double* x, double* y) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double a = *h;
+  if (i < n) y[i] = (a != 0.0) ? x[i] / a : 0.0;
+}
+
+// y = x / h_host
+__global__ void k_scale_inv(int64_t n, double a, const double* x, double* y) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = x[i] / a;
+}
+
+// x += sum_k y[k] Z[k]  (Z: k vectors of length n, stride n)
+__global__ void k_update_x(int64_t n, int k, const double* __restrict__ Z, const double* __restrict__ y,
+                           double* __restrict__ x) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = x[i];
+  for (int q = 0; q < k; ++q) s += y[q] * Z[(int64_t)q * n + i];
+  x[i] = s;
+}
+
+}  // namespace mas

@@ -1,0 +1,978 @@
+// libmas: C-ABI, setup, defect-correction cycle and FGMRES on the GPU.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/mas.h"
+#include "host.hpp"
+#include "kernels.hpp"
+
+using namespace mas;
+
+// ---------------------------------------------------------------------------
+// errors
+
+static thread_local std::string g_last_error;
+
+namespace {
+
+struct MasError : std::runtime_error {
+  int code;
+  MasError(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHECK(call)                                                                       \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      throw MasError(e_ == hipErrorOutOfMemory ? MAS_ENOMEM : MAS_EHIP,                      \
+                     std::string(#call) + ": " + hipGetErrorString(e_));                     \
+  } while (0)
+
+inline void launch_check() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw MasError(MAS_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+}
+
+inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+constexpr size_t kMaxLds = 64 * 1024;  // dynamic LDS per workgroup used by the patch kernels
+
+// ---------------------------------------------------------------------------
+// device memory owned by a handle
+
+struct DevArena {
+  std::vector<void*> ptrs;
+  size_t bytes = 0;
+  template <typename T>
+  T* alloc(size_t n) {
+    if (n == 0) n = 1;
+    void* p = nullptr;
+    HIPCHECK(hipMalloc(&p, n * sizeof(T)));
+    ptrs.push_back(p);
+    bytes += n * sizeof(T);
+    return (T*)p;
+  }
+  template <typename T, typename S>
+  T* upload(const std::vector<S>& v, hipStream_t s) {
+    std::vector<T> tmp(v.begin(), v.end());
+    T* d = alloc<T>(tmp.size());
+    if (!tmp.empty()) {
+      HIPCHECK(hipMemcpyAsync(d, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice, s));
+      HIPCHECK(hipStreamSynchronize(s));
+    }
+    return d;
+  }
+  ~DevArena() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+};
+
+template <typename T>
+struct DCsr {
+  int64_t n = 0, m = 0, nnz = 0;
+  int* ptr = nullptr;
+  int* ind = nullptr;
+  T* val = nullptr;
+  int team = 8;
+};
+
+template <typename T>
+DCsr<T> upload_csr(DevArena& A, const Csr& C, hipStream_t s) {
+  if (C.nnz() >= (int64_t)INT32_MAX) throw MasError(MAS_EINVAL, "matrix too large for 32-bit offsets");
+  DCsr<T> d;
+  d.n = C.nr;
+  d.m = C.nc;
+  d.nnz = C.nnz();
+  d.ptr = A.upload<int>(C.ptr, s);
+  d.ind = A.upload<int>(C.ind, s);
+  d.val = A.upload<T>(C.val, s);
+  double avg = C.nr ? (double)C.nnz() / (double)C.nr : 1.0;
+  int t = 1;
+  while (t < 64 && 2 * t <= avg) t *= 2;
+  d.team = std::max(2, t);
+  return d;
+}
+
+template <typename T, int MODE>
+void csr_launch(const DCsr<T>& A, const T* x, const T* b, T* y, hipStream_t s) {
+  if (A.n == 0) return;
+  const int bs = 256;
+  const unsigned nb = blocks_for(A.n * (int64_t)A.team, bs);
+  switch (A.team) {
+#define CASE(TM) \
+  case TM: hipLaunchKernelGGL((k_csr<T, TM, MODE>), dim3(nb), dim3(bs), 0, s, (int)A.n, A.ptr, A.ind, A.val, x, b, y); break;
+    CASE(2) CASE(4) CASE(8) CASE(16) CASE(32) CASE(64)
+#undef CASE
+    default: throw MasError(MAS_EINVAL, "bad team size");
+  }
+  launch_check();
+}
+
+// ---------------------------------------------------------------------------
+// levels of the cycle
+
+template <typename T>
+struct DPatches {
+  int64_t np = 0, ndofs = 0, nfac = 0;
+  int64_t* off = nullptr;
+  int4* dims = nullptr;
+  int64_t* foff = nullptr;
+  int* dofs = nullptr;
+  T* fac = nullptr;
+  int* inv_ptr = nullptr;
+  int* inv_pos = nullptr;
+  T* w = nullptr;
+  T* Y = nullptr;
+  int max_m = 0;
+  int64_t max_f = 0;
+};
+
+template <typename T>
+struct Level {
+  int64_t n = 0, nvel = 0;
+  DCsr<T> K;
+  DCsr<T> P, R;  // P: this level <- next level, R = P^T
+  DPatches<T> pt;
+  bool relax = false;
+  T *x = nullptr, *b = nullptr, *r = nullptr;
+};
+
+struct CycleBase {
+  virtual ~CycleBase() = default;
+  virtual void apply(const double* r, double* z, hipStream_t s) = 0;
+};
+
+struct Timing {
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> vanka, spmv;
+  double vanka_ms = 0, spmv_ms = 0, apply_ms = 0;
+  int64_t vanka_launches = 0, applies = 0;
+};
+
+template <typename T>
+struct Cycle : CycleBase {
+  std::vector<Level<T>> lev;  // 0 = free K0, 1 = free K1, ..., back() = coarsest (dense)
+  double* Cinv = nullptr;     // dense inverse of the (bordered) coarsest operator
+  int64_t nc_dense = 0, ld = 0;
+  int64_t* free0 = nullptr;
+  int64_t* dir0 = nullptr;
+  int64_t nfree0 = 0, ndir0 = 0;
+  mas_params par{};
+  Timing* tm = nullptr;
+
+  void vanka_sweeps(Level<T>& L, int sweeps, T omega, bool x_zero, hipStream_t s) {
+    for (int k = 0; k < sweeps; ++k) {
+      const T* rin;
+      if (k == 0 && x_zero) {
+        rin = L.b;
+      } else {
+        csr_launch<T, 1>(L.K, L.x, L.b, L.r, s);
+        rin = L.r;
+      }
+      const bool stage = (size_t)(2 * L.pt.max_m + L.pt.max_f) * sizeof(T) <= kMaxLds;
+      const size_t shm = (size_t)(2 * L.pt.max_m + (stage ? L.pt.max_f : 0)) * sizeof(T);
+      hipEvent_t e0{}, e1{};
+      if (tm && tm->on) {
+        HIPCHECK(hipEventCreate(&e0));
+        HIPCHECK(hipEventCreate(&e1));
+        HIPCHECK(hipEventRecord(e0, s));
+      }
+      if (stage)
+        hipLaunchKernelGGL((k_vanka_apply<T, true>), dim3((unsigned)L.pt.np), dim3(WAVE), shm, s, L.pt.np, L.pt.off,
+                           L.pt.dims, L.pt.foff, L.pt.dofs, L.pt.fac, rin, L.pt.Y, L.pt.max_m);
+      else
+        hipLaunchKernelGGL((k_vanka_apply<T, false>), dim3((unsigned)L.pt.np), dim3(WAVE), shm, s, L.pt.np,
+                           L.pt.off, L.pt.dims, L.pt.foff, L.pt.dofs, L.pt.fac, rin, L.pt.Y, L.pt.max_m);
+      launch_check();
+      if (tm && tm->on) {
+        HIPCHECK(hipEventRecord(e1, s));
+        tm->vanka.push_back({e0, e1});
+      }
+      hipLaunchKernelGGL((k_vanka_pull<T>), dim3(blocks_for(L.n, 256)), dim3(256), 0, s, (int)L.n, L.pt.inv_ptr,
+                         L.pt.inv_pos, L.pt.Y, L.pt.w, omega, L.x, (k == 0 && x_zero) ? 0 : 1);
+      launch_check();
+    }
+  }
+
+  // cycle on level l >= 1 with right-hand side lev[l].b, result in lev[l].x
+  void vcycle(size_t l, hipStream_t s) {
+    Level<T>& L = lev[l];
+    if (l + 1 == lev.size()) {
+      hipLaunchKernelGGL((k_dense_gemv<T>), dim3(blocks_for(L.n * WAVE, 256)), dim3(256), 0, s, (int)L.n,
+                         (int)ld, Cinv, L.b, L.x);
+      launch_check();
+      return;
+    }
+    const T om = (T)par.omega;
+    bool x_zero = true;
+    if (L.relax && par.nu1 > 0) {
+      vanka_sweeps(L, par.nu1, om, true, s);
+      x_zero = false;
+    }
+    Level<T>& C = lev[l + 1];
+    if (x_zero) {
+      csr_launch<T, 0>(L.R, L.b, nullptr, C.b, s);
+    } else {
+      csr_launch<T, 1>(L.K, L.x, L.b, L.r, s);
+      csr_launch<T, 0>(L.R, L.r, nullptr, C.b, s);
+    }
+    vcycle(l + 1, s);
+    if (x_zero) {
+      csr_launch<T, 0>(L.P, C.x, nullptr, L.x, s);
+    } else {
+      csr_launch<T, 2>(L.P, C.x, nullptr, L.x, s);
+    }
+    if (L.relax && par.nu2 > 0) vanka_sweeps(L, par.nu2, om, false, s);
+  }
+
+  void apply(const double* r, double* z, hipStream_t s) override {
+    Level<T>& L0 = lev[0];
+    Level<T>& L1 = lev[1];
+    hipLaunchKernelGGL((k_gather<T, double>), dim3(blocks_for(nfree0, 256)), dim3(256), 0, s, nfree0, free0, r, L0.b);
+    launch_check();
+    bool x_zero = true;
+    if (L0.relax && par.nu1 > 0) {
+      vanka_sweeps(L0, par.nu1, (T)par.omega0, true, s);
+      x_zero = false;
+    }
+    const T* r0 = L0.b;
+    if (!x_zero) {
+      csr_launch<T, 1>(L0.K, L0.x, L0.b, L0.r, s);
+      r0 = L0.r;
+    }
+    // eta R0 (Taylor-Hood: injection, eq. (3.2))
+    hipLaunchKernelGGL((k_scale2<T>), dim3(blocks_for(L1.n, 256)), dim3(256), 0, s, L1.n, L1.nvel, (T)par.eta_u,
+                       (T)par.eta_p, r0, L1.b);
+    launch_check();
+    vcycle(1, s);
+    // x0 += P0 x1 (injection)
+    hipLaunchKernelGGL((k_axpby<T>), dim3(blocks_for(L0.n, 256)), dim3(256), 0, s, L0.n, (T)1, L1.x,
+                       x_zero ? (T)0 : (T)1, L0.x);
+    launch_check();
+    if (L0.relax && par.nu2 > 0) vanka_sweeps(L0, par.nu2, (T)par.omega0, false, s);
+    hipLaunchKernelGGL((k_scatter<double, T>), dim3(blocks_for(nfree0, 256)), dim3(256), 0, s, nfree0, free0, L0.x, z);
+    launch_check();
+    if (ndir0) {  // Dirichlet rows are identity rows: z_D = r_D
+      hipLaunchKernelGGL(k_copy_idx, dim3(blocks_for(ndir0, 256)), dim3(256), 0, s, ndir0, dir0, r, z);
+      launch_check();
+    }
+  }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// the handle
+
+struct HostPlan {
+  std::vector<Csr> Ks, Ps;                 // free level operators, P_l (level l <- l+1)
+  std::vector<std::vector<int8_t>> fields;
+  std::vector<PatchSet> patches;
+  std::vector<bool> relax;
+  Csr Kb;                                  // coarsest operator (bordered when singular)
+  std::vector<int64_t> free0, dir0;
+  Csr K0;                                  // full K0 (FGMRES operator)
+  std::vector<double> pw;                  // pressure weights
+};
+
+struct mas_handle {
+  DevArena arena;
+  HostPlan plan;
+  bool on_device = false;
+  int32_t dim = 2, disc = MAS_TH;
+  mas_params par{};
+  int64_t n0 = 0, nu0 = 0;
+  DCsr<double> K0full;
+  std::unique_ptr<CycleBase> cyc;
+  mas_hier_info info{};
+  std::vector<Csr> host_levels;  // free level operators (for export)
+  int32_t p_nullspace = 0;
+  double* pw = nullptr;  // pressure weights (np0)
+  double pw_sum = 0.0;
+  // FGMRES work
+  double *V = nullptr, *Z = nullptr, *w = nullptr, *partial = nullptr, *hdev = nullptr, *ydev = nullptr;
+  double* hhost = nullptr;  // pinned
+  int nblk_dot = 512;
+  int64_t* dir_idx = nullptr;
+  int64_t ndir = 0;
+  Timing tm;
+};
+
+namespace {
+
+Csr get_csr(const mas_csr& c, const char* name) {
+  if (!c.indptr || !c.indices || !c.data || c.nrows <= 0 || c.ncols <= 0)
+    throw MasError(MAS_EINVAL, std::string("missing matrix ") + name);
+  Csr A = csr_copy(c.nrows, c.ncols, c.indptr, c.indices, c.data);
+  for (int64_t i = 0; i < A.nr; ++i) {
+    if (A.ptr[i + 1] < A.ptr[i]) throw MasError(MAS_EINVAL, std::string(name) + ": bad indptr");
+    for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e) {
+      if (A.ind[e] < 0 || A.ind[e] >= A.nc) throw MasError(MAS_EINVAL, std::string(name) + ": column out of range");
+      if (e > A.ptr[i] && A.ind[e] <= A.ind[e - 1])
+        throw MasError(MAS_EINVAL, std::string(name) + ": columns not sorted/unique");
+      if (!std::isfinite(A.val[e])) throw MasError(MAS_EINVAL, std::string(name) + ": non-finite value");
+    }
+  }
+  return A;
+}
+
+// dense inverse of an n x n FP64 matrix on the device (Gauss-Jordan, partial pivoting)
+void dense_inverse(DevArena& ar, double* A, int n, hipStream_t s) {
+  double* rowk = ar.alloc<double>(n);
+  double* colk = ar.alloc<double>(n);
+  int* perm = ar.alloc<int>(n);
+  int* flag = ar.alloc<int>(1);
+  HIPCHECK(hipMemsetAsync(flag, 0, sizeof(int), s));
+  for (int k = 0; k < n; ++k) {
+    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, s, n, k, A, perm, flag);
+    hipLaunchKernelGGL(k_gj_save, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, k, A, rowk, colk);
+    hipLaunchKernelGGL(k_gj_step, dim3(blocks_for((int64_t)n * n, 256)), dim3(256), 0, s, n, k, A, rowk, colk);
+  }
+  for (int k = n - 1; k >= 0; --k)
+    hipLaunchKernelGGL(k_gj_colswap, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, k, perm, A);
+  launch_check();
+  int hflag = 0;
+  HIPCHECK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  if (hflag) throw MasError(MAS_ESINGULAR_PATCH, "coarsest-level operator is singular");
+}
+
+template <typename T>
+void build_patches(DevArena& ar, Level<T>& L, const PatchSet& ps, const DCsr<double>& K64, int level,
+                   hipStream_t s) {
+  DPatches<T>& d = L.pt;
+  d.np = ps.np();
+  d.ndofs = (int64_t)ps.dofs.size();
+  d.nfac = ps.foff.back();
+  d.max_m = ps.max_m;
+  d.max_f = ps.max_f;
+  d.off = ar.upload<int64_t>(ps.off, s);
+  {
+    std::vector<int32_t> dims = ps.dims;
+    for (int64_t p = 0; p < d.np; ++p)
+      if (dims[4 * p + 3] > MAX_NS || dims[4 * p + 3] < 1)
+        throw MasError(MAS_EINVAL, "patch seed count out of range");
+    int4* dd = ar.alloc<int4>(d.np);
+    HIPCHECK(hipMemcpyAsync(dd, dims.data(), dims.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    d.dims = dd;
+  }
+  d.foff = ar.upload<int64_t>(ps.foff, s);
+  d.dofs = ar.upload<int>(ps.dofs, s);
+  d.inv_ptr = ar.upload<int>(ps.inv_ptr, s);
+  d.inv_pos = ar.upload<int>(ps.inv_pos, s);
+  d.w = ar.upload<T>(ps.w, s);
+  d.Y = ar.alloc<T>(d.ndofs);
+  d.fac = ar.alloc<T>(d.nfac);
+  // FP64 factorisation on the GPU
+  int max_nc = 0, max_nv = 0;
+  for (int64_t p = 0; p < d.np; ++p) {
+    const int32_t* q = &ps.dims[4 * p];
+    max_nc = std::max({max_nc, q[0], q[1], q[2]});
+    max_nv = std::max(max_nv, q[0] + q[1] + q[2]);
+  }
+  const int64_t stride = (int64_t)max_nc * max_nc + 2 * (int64_t)max_nv * MAX_NS;
+  const size_t lds_bytes = (size_t)stride * sizeof(double);
+  int64_t* bad = ar.alloc<int64_t>(1);
+  int64_t init = INT64_MAX;
+  HIPCHECK(hipMemcpyAsync(bad, &init, sizeof(int64_t), hipMemcpyHostToDevice, s));
+  const bool use_lds = lds_bytes <= kMaxLds;
+  const unsigned grid = use_lds ? (unsigned)std::min<int64_t>(d.np, 65536) : (unsigned)std::min<int64_t>(d.np, 1024);
+  double* gwork = use_lds ? nullptr : ar.alloc<double>((size_t)stride * grid);
+  hipLaunchKernelGGL((k_vanka_factor<T>), dim3(grid), dim3(WAVE), use_lds ? lds_bytes : 0, s, d.np, d.off, d.dims,
+                     d.foff, d.dofs, K64.ptr, K64.ind, K64.val, d.fac, gwork, stride, use_lds ? 1 : 0, max_nv,
+                     1e-14, bad);
+  launch_check();
+  int64_t hbad = 0;
+  HIPCHECK(hipMemcpyAsync(&hbad, bad, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  if (hbad != INT64_MAX)
+    throw MasError(MAS_ESINGULAR_PATCH,
+                   "singular patch block on level " + std::to_string(level) + ", patch " + std::to_string(hbad));
+}
+
+template <typename T>
+std::unique_ptr<Cycle<T>> build_cycle(mas_handle* h, const std::vector<Csr>& Ks, const std::vector<Csr>& Ps,
+                                      const std::vector<std::vector<int8_t>>& fields,
+                                      const std::vector<PatchSet>& patches, const std::vector<bool>& relax,
+                                      const Csr& Kc_bordered, const std::vector<int64_t>& free0,
+                                      const std::vector<int64_t>& dir0, hipStream_t s) {
+  DevArena& ar = h->arena;
+  auto cyc = std::make_unique<Cycle<T>>();
+  cyc->par = h->par;
+  cyc->tm = &h->tm;
+  const size_t nl = Ks.size();
+  cyc->lev.resize(nl);
+  for (size_t l = 0; l < nl; ++l) {
+    Level<T>& L = cyc->lev[l];
+    L.n = Ks[l].nr;
+    L.nvel = 0;
+    for (int8_t f : fields[l]) L.nvel += (f < h->dim);
+    L.relax = relax[l];
+    L.x = ar.alloc<T>(L.n);
+    L.b = ar.alloc<T>(L.n);
+    L.r = ar.alloc<T>(L.n);
+    if (l + 1 < nl) {
+      L.K = upload_csr<T>(ar, Ks[l], s);
+      if (l >= 1) {
+        L.P = upload_csr<T>(ar, Ps[l], s);
+        L.R = upload_csr<T>(ar, transpose(Ps[l]), s);
+      }
+      if (L.relax) {
+        DCsr<double> K64;
+        if constexpr (std::is_same<T, double>::value) K64 = L.K;
+        else K64 = upload_csr<double>(ar, Ks[l], s);
+        build_patches<T>(ar, L, patches[l], K64, (int)l, s);
+      }
+    }
+  }
+  // coarsest: dense inverse of the bordered operator
+  const int64_t nb = Kc_bordered.nr;
+  std::vector<double> dense((size_t)nb * nb, 0.0);
+  for (int64_t i = 0; i < nb; ++i)
+    for (int64_t e = Kc_bordered.ptr[i]; e < Kc_bordered.ptr[i + 1]; ++e) dense[i * nb + Kc_bordered.ind[e]] = Kc_bordered.val[e];
+  cyc->Cinv = ar.upload<double>(dense, s);
+  dense_inverse(ar, cyc->Cinv, (int)nb, s);
+  cyc->ld = nb;
+  cyc->nc_dense = nb;
+  cyc->free0 = ar.upload<int64_t>(free0, s);
+  cyc->dir0 = ar.upload<int64_t>(dir0, s);
+  cyc->nfree0 = (int64_t)free0.size();
+  cyc->ndir0 = (int64_t)dir0.size();
+  return cyc;
+}
+
+void analyze_impl(mas_handle* h, const mas_problem* pr) {
+  const int d = pr->dim;
+  if (d != 2 && d != 3) throw MasError(MAS_EINVAL, "dim must be 2 or 3");
+  if (pr->disc != MAS_TH) throw MasError(MAS_EINVAL, "only Taylor-Hood is supported by this build");
+  h->dim = d;
+  h->disc = pr->disc;
+  const mas_params& par = h->par;
+  if (par.relax != MAS_RELAX_VANKA) throw MasError(MAS_EINVAL, "only Vanka relaxation is supported by this build");
+  Csr K0 = get_csr(pr->K0, "K0");
+  Csr K1 = get_csr(pr->K1, "K1");
+  Csr Ap = get_csr(pr->Ap, "Ap");
+  const int64_t n0 = K0.nr, n1 = K1.nr;
+  if (K0.nc != n0 || K1.nc != n1 || Ap.nr != Ap.nc) throw MasError(MAS_EINVAL, "operators must be square");
+  if (!pr->field0 || !pr->field1 || !pr->dir0 || !pr->dir1) throw MasError(MAS_EINVAL, "missing field or Dirichlet map");
+  h->n0 = n0;
+  if (par.restart < 1 || par.restart > 200) throw MasError(MAS_EINVAL, "restart must be in [1, 200]");
+  if (par.max_coarse < 1 || par.max_levels < 1) throw MasError(MAS_EINVAL, "bad coarsening limits");
+  std::vector<int64_t> free0, dir0, free1;
+  std::vector<int8_t> f0, f1;
+  int64_t nu0 = 0, np0 = 0;
+  for (int64_t i = 0; i < n0; ++i) {
+    if (pr->field0[i] < 0 || pr->field0[i] > d) throw MasError(MAS_EINVAL, "field0 out of range");
+    if (i > 0 && pr->field0[i] < pr->field0[i - 1]) throw MasError(MAS_EINVAL, "K0 unknowns must be field-blocked");
+    if (pr->field0[i] < d) ++nu0; else ++np0;
+    if (pr->dir0[i]) {
+      if (pr->field0[i] == d) throw MasError(MAS_EINVAL, "Dirichlet pressure rows are not supported");
+      dir0.push_back(i);
+    } else {
+      free0.push_back(i);
+      f0.push_back(pr->field0[i]);
+    }
+  }
+  for (int64_t i = 0; i < n1; ++i) {
+    if (pr->field1[i] < 0 || pr->field1[i] > d) throw MasError(MAS_EINVAL, "field1 out of range");
+    if (i > 0 && pr->field1[i] < pr->field1[i - 1]) throw MasError(MAS_EINVAL, "K1 unknowns must be field-blocked");
+    if (!pr->dir1[i]) {
+      free1.push_back(i);
+      f1.push_back(pr->field1[i]);
+    }
+  }
+  h->nu0 = nu0;
+  Csr K0f = submatrix(K0, free0, free0);
+  Csr K1f = submatrix(K1, free1, free1);
+  // the two velocity spaces share their nodes (Section 3.1)
+  int64_t nv0 = 0, nv1 = 0;
+  for (auto f : f0) nv0 += (f < d);
+  for (auto f : f1) nv1 += (f < d);
+  if (nv0 != nv1 || (int64_t)free0.size() != (int64_t)free1.size())
+    throw MasError(MAS_EINVAL, "K0 and K1 free DoFs must coincide for Taylor-Hood");
+  // ---- Algorithm 1: per-field smoothed aggregation on K1's velocity blocks and A_p
+  std::vector<std::vector<int64_t>> blocks(d + 1);
+  for (int64_t i = 0; i < (int64_t)f1.size(); ++i) blocks[f1[i]].push_back(i);
+  if ((int64_t)blocks[d].size() != Ap.nr) throw MasError(MAS_EINVAL, "Ap size does not match K1's pressure block");
+  std::vector<std::vector<Csr>> fP(d + 1);
+  std::vector<std::vector<std::vector<double>>> fB(d + 1);
+  size_t lmax = SIZE_MAX;
+  for (int f = 0; f <= d; ++f) {
+    Csr Af = (f < d) ? submatrix(K1f, blocks[f], blocks[f]) : Ap;
+    sa_field(Af, par.theta, par.max_coarse, par.max_levels, fP[f], fB[f]);
+    lmax = std::min(lmax, fP[f].size() + 1);
+  }
+  // levels: 0 = K0f, 1 = K1f, 2.. = Galerkin
+  std::vector<Csr> Ks{K0f, K1f};
+  std::vector<Csr> Ps{Csr(), Csr()};
+  std::vector<std::vector<int8_t>> fields{f0, f1};
+  for (size_t l = 0; l + 1 < lmax; ++l) {
+    std::vector<const Csr*> bl;
+    for (int f = 0; f <= d; ++f) bl.push_back(&fP[f][l]);
+    Csr P = block_diag(bl);
+    Csr Kc = galerkin(P, Ks.back());
+    std::vector<int8_t> fc;
+    for (int f = 0; f <= d; ++f) fc.insert(fc.end(), (size_t)fP[f][l].nc, (int8_t)f);
+    Ps.back() = P;  // P of the finer level
+    Ks.push_back(std::move(Kc));
+    Ps.push_back(Csr());
+    fields.push_back(std::move(fc));
+  }
+  const size_t nl = Ks.size();  // includes the coarsest
+  if (nl > 16) throw MasError(MAS_EINVAL, "too many levels");
+  // relaxation schedule (Section 4): index 0 = K0, 1 = K1, ...
+  std::vector<bool> relax(nl, true);
+  relax[nl - 1] = false;
+  if (par.schedule == MAS_DC_SKIP1 && nl > 2) relax[1] = false;
+  if (par.schedule == MAS_DC_SKIP0) relax[0] = false;
+  if (par.schedule == MAS_DC_SKIP1 && nl == 2) relax[1] = false;
+  std::vector<PatchSet> patches(nl);
+  for (size_t l = 0; l + 1 < nl; ++l)
+    if (relax[l]) patches[l] = patches_single_seed(Ks[l], fields[l], d);
+  // coarsest operator, bordered with the coarse pressure null vector
+  const Csr& KL = Ks.back();
+  Csr Kb = KL;
+  h->p_nullspace = pr->p_nullspace;
+  if (pr->p_nullspace) {
+    const std::vector<double>& Bp = fB[d][lmax - 1];
+    std::vector<double> nvec(KL.nr, 0.0);
+    int64_t q = 0;
+    double nn = 0.0;
+    for (int64_t i = 0; i < KL.nr; ++i)
+      if (fields.back()[i] == d) {
+        nvec[i] = Bp[q++];
+        nn += nvec[i] * nvec[i];
+      }
+    nn = std::sqrt(nn);
+    Kb.nr = Kb.nc = KL.nr + 1;
+    Kb.ptr.clear();
+    Kb.ind.clear();
+    Kb.val.clear();
+    Kb.ptr.push_back(0);
+    for (int64_t i = 0; i < KL.nr; ++i) {
+      for (int64_t e = KL.ptr[i]; e < KL.ptr[i + 1]; ++e) {
+        Kb.ind.push_back(KL.ind[e]);
+        Kb.val.push_back(KL.val[e]);
+      }
+      if (nvec[i] != 0.0) {
+        Kb.ind.push_back((int32_t)KL.nr);
+        Kb.val.push_back(nvec[i] / nn);
+      }
+      Kb.ptr.push_back((int64_t)Kb.ind.size());
+    }
+    for (int64_t i = 0; i < KL.nr; ++i)
+      if (nvec[i] != 0.0) {
+        Kb.ind.push_back((int32_t)i);
+        Kb.val.push_back(nvec[i] / nn);
+      }
+    Kb.ptr.push_back((int64_t)Kb.ind.size());
+  }
+  HostPlan& pl = h->plan;
+  pl.pw.clear();
+  if (pr->p_weight0) {
+    pl.pw.assign(pr->p_weight0, pr->p_weight0 + np0);
+    h->pw_sum = 0.0;
+    for (double v : pl.pw) h->pw_sum += v;
+  }
+  // info
+  mas_hier_info& in = h->info;
+  in.n_levels = (int32_t)nl;
+  for (size_t l = 0; l < nl; ++l) {
+    in.n[l] = Ks[l].nr;
+    in.nnz[l] = Ks[l].nnz();
+    int64_t nv = 0;
+    for (auto f : fields[l]) nv += (f < d);
+    in.n_vel[l] = nv;
+    if (relax[l]) {
+      in.n_patches[l] = patches[l].np();
+      in.patch_dofs[l] = (int64_t)patches[l].dofs.size();
+      in.factor_entries[l] = patches[l].foff.back();
+    }
+    in.p_nnz[l] = (l >= 2) ? Ps[l - 1].nnz() : 0;
+  }
+  in.coarse_n = Kb.nr;
+  h->host_levels = Ks;
+  pl.Ks = std::move(Ks);
+  pl.Ps = std::move(Ps);
+  pl.fields = std::move(fields);
+  pl.patches = std::move(patches);
+  pl.relax = std::move(relax);
+  pl.Kb = std::move(Kb);
+  pl.free0 = std::move(free0);
+  pl.dir0 = std::move(dir0);
+  pl.K0 = std::move(K0);
+}
+
+void upload_impl(mas_handle* h, hipStream_t s) {
+  HostPlan& pl = h->plan;
+  const mas_params& par = h->par;
+  const int64_t n0 = h->n0;
+  h->K0full = upload_csr<double>(h->arena, pl.K0, s);
+  if (par.precision == MAS_FP32)
+    h->cyc = build_cycle<float>(h, pl.Ks, pl.Ps, pl.fields, pl.patches, pl.relax, pl.Kb, pl.free0, pl.dir0, s);
+  else
+    h->cyc = build_cycle<double>(h, pl.Ks, pl.Ps, pl.fields, pl.patches, pl.relax, pl.Kb, pl.free0, pl.dir0, s);
+  h->dir_idx = h->arena.upload<int64_t>(pl.dir0, s);
+  h->ndir = (int64_t)pl.dir0.size();
+  if (!pl.pw.empty()) h->pw = h->arena.upload<double>(pl.pw, s);
+  const int m = std::max(1, par.restart);
+  h->V = h->arena.alloc<double>((size_t)(m + 1) * n0);
+  h->Z = h->arena.alloc<double>((size_t)m * n0);
+  h->w = h->arena.alloc<double>(n0);
+  h->partial = h->arena.alloc<double>(h->nblk_dot);
+  h->hdev = h->arena.alloc<double>(m + 2);
+  h->ydev = h->arena.alloc<double>(m + 1);
+  HIPCHECK(hipHostMalloc((void**)&h->hhost, (m + 2) * sizeof(double), hipHostMallocDefault));
+  // the host plan is no longer needed except for export
+  pl.patches.clear();
+  pl.patches.shrink_to_fit();
+  h->on_device = true;
+}
+
+// ---------------------------------------------------------------------------
+// FGMRES (FP64)
+
+double dev_dot(mas_handle* h, const double* x, const double* y, int64_t n, hipStream_t s, double* out_dev,
+               bool take_sqrt) {
+  hipLaunchKernelGGL(k_dot_partial, dim3(h->nblk_dot), dim3(256), 0, s, n, x, y, h->partial);
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, h->nblk_dot, h->partial, out_dev, take_sqrt ? 1 : 0);
+  launch_check();
+  return 0.0;
+}
+
+double host_scalar(mas_handle* h, const double* dev, hipStream_t s) {
+  HIPCHECK(hipMemcpyAsync(h->hhost, dev, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  return h->hhost[0];
+}
+
+int fgmres(mas_handle* h, const double* b, double* x, double rtol, int max_it, mas_solve_info* info,
+           hipStream_t s) {
+  const int64_t n = h->n0;
+  const int m = std::max(1, h->par.restart);
+  double* r = h->w;  // reuse: w is rebuilt every inner step
+  dev_dot(h, b, b, n, s, h->hdev, true);
+  const double bnorm = host_scalar(h, h->hdev, s);
+  HIPCHECK(hipMemsetAsync(x, 0, n * sizeof(double), s));
+  std::vector<double> hist;
+  if (!(bnorm > 0.0)) {
+    if (info) *info = mas_solve_info{0, 1, 0.0, NAN};
+    return std::isfinite(bnorm) ? MAS_OK : MAS_ENAN;
+  }
+  const double target = rtol * bnorm;
+  double beta = bnorm;
+  hist.push_back(beta);
+  int it = 0;
+  bool converged = false;
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1);
+  // r = b initially
+  HIPCHECK(hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  while (true) {
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    hipLaunchKernelGGL(k_scale_inv, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, beta, r, h->V);
+    launch_check();
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+      double* vj = h->V + (int64_t)j * n;
+      double* zj = h->Z + (int64_t)j * n;
+      h->cyc->apply(vj, zj, s);
+      double* w = h->w;
+      csr_launch<double, 0>(h->K0full, zj, nullptr, w, s);
+      for (int i = 0; i <= j; ++i) {
+        dev_dot(h, w, h->V + (int64_t)i * n, n, s, h->hdev + i, false);
+        hipLaunchKernelGGL(k_axpy_neg_dev, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, h->hdev + i,
+                           h->V + (int64_t)i * n, w);
+      }
+      dev_dot(h, w, w, n, s, h->hdev + j + 1, true);
+      hipLaunchKernelGGL(k_scale_inv_dev, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, h->hdev + j + 1, w,
+                         h->V + (int64_t)(j + 1) * n);
+      launch_check();
+      HIPCHECK(hipMemcpyAsync(h->hhost, h->hdev, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipStreamSynchronize(s));
+      for (int i = 0; i <= j + 1; ++i) H[(size_t)i * m + j] = h->hhost[i];
+      for (int i = 0; i < j; ++i) {
+        double t = cs[i] * H[(size_t)i * m + j] + sn[i] * H[(size_t)(i + 1) * m + j];
+        H[(size_t)(i + 1) * m + j] = -sn[i] * H[(size_t)i * m + j] + cs[i] * H[(size_t)(i + 1) * m + j];
+        H[(size_t)i * m + j] = t;
+      }
+      double den = std::hypot(H[(size_t)j * m + j], H[(size_t)(j + 1) * m + j]);
+      cs[j] = H[(size_t)j * m + j] / den;
+      sn[j] = H[(size_t)(j + 1) * m + j] / den;
+      H[(size_t)j * m + j] = den;
+      H[(size_t)(j + 1) * m + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++it;
+      k = j + 1;
+      const double est = std::fabs(g[j + 1]);
+      hist.push_back(est);
+      if (!std::isfinite(est)) {
+        if (info) *info = mas_solve_info{it, 0, NAN, NAN};
+        return MAS_ENAN;
+      }
+      if (est <= target || it >= max_it) break;
+    }
+    // y = H^-1 g (upper triangular)
+    std::vector<double> y(k, 0.0);
+    for (int i = k - 1; i >= 0; --i) {
+      double t = g[i];
+      for (int q = i + 1; q < k; ++q) t -= H[(size_t)i * m + q] * y[q];
+      y[i] = t / H[(size_t)i * m + i];
+    }
+    HIPCHECK(hipMemcpyAsync(h->ydev, y.data(), k * sizeof(double), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_update_x, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, k, h->Z, h->ydev, x);
+    launch_check();
+    csr_launch<double, 1>(h->K0full, x, b, r, s);
+    dev_dot(h, r, r, n, s, h->hdev, true);
+    beta = host_scalar(h, h->hdev, s);
+    HIPCHECK(hipStreamSynchronize(s));  // y lives on the host stack
+    if (!std::isfinite(beta)) {
+      if (info) *info = mas_solve_info{it, 0, NAN, NAN};
+      return MAS_ENAN;
+    }
+    if (beta <= target) {
+      converged = true;
+      break;
+    }
+    if (it >= max_it) break;
+  }
+  // zero-mean pressure
+  if (h->p_nullspace && h->pw) {
+    const int64_t np0 = n - h->nu0;
+    dev_dot(h, x + h->nu0, h->pw, np0, s, h->hdev, false);
+    double mean = host_scalar(h, h->hdev, s) / h->pw_sum;
+    std::vector<double> neg(1, -mean);
+    // x_p += -mean via axpby with a constant vector: use k_fill + k_axpby on scratch w
+    hipLaunchKernelGGL((k_fill<double>), dim3(blocks_for(np0, 256)), dim3(256), 0, s, np0, h->w, -mean);
+    hipLaunchKernelGGL((k_axpby<double>), dim3(blocks_for(np0, 256)), dim3(256), 0, s, np0, 1.0, h->w, 1.0,
+                       x + h->nu0);
+    launch_check();
+    HIPCHECK(hipStreamSynchronize(s));
+  }
+  if (info) {
+    info->iters = it;
+    info->converged = converged ? 1 : 0;
+    info->relres = beta / bnorm;
+    info->conv_factor = hist.size() >= 11 ? std::pow(hist.back() / hist[hist.size() - 11], 0.1) : NAN;
+  }
+  return converged ? MAS_OK : MAS_NOT_CONVERGED;
+}
+
+int fail(const MasError& e) {
+  g_last_error = e.what();
+  return e.code;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C-ABI
+
+extern "C" {
+
+void mas_default_params(int32_t dim, int32_t disc, int32_t relax, mas_params* out) {
+  if (!out) return;
+  mas_params p{};
+  p.relax = relax;
+  p.schedule = MAS_DC_ALL;
+  p.nu1 = p.nu2 = (relax == MAS_RELAX_DLSC) ? 2 : 1;
+  p.omega0 = 0.5;
+  p.omega = 0.5;
+  p.eta_u = 1.0;
+  p.eta_p = 1.0;
+  if (disc == MAS_SV) {  // Table 4, structured meshes, Vanka on all levels
+    p.omega0 = 0.78;
+    p.eta_p = 2.68;
+  }
+  if (dim == 3) {
+    p.cheb_deg[0] = 4; p.cheb_deg[1] = 4; p.cheb_deg[2] = 16;
+  } else {
+    p.cheb_deg[0] = 3; p.cheb_deg[1] = 3; p.cheb_deg[2] = 6;
+  }
+  p.precision = MAS_FP64;
+  p.restart = 20;
+  p.max_coarse = 300;
+  p.max_levels = 10;
+  p.theta = 0.02;
+  p.seed = 0x5EED;
+  p.mass_rtol = 1e-14;
+  *out = p;
+}
+
+int mas_setup(const mas_problem* prob, const mas_params* par, void* stream, mas_handle** out) {
+  if (!prob || !par || !out) {
+    g_last_error = "null argument";
+    return MAS_EINVAL;
+  }
+  *out = nullptr;
+  auto h = std::make_unique<mas_handle>();
+  h->par = *par;
+  try {
+    analyze_impl(h.get(), prob);
+    upload_impl(h.get(), (hipStream_t)stream);
+  } catch (const MasError& e) {
+    return fail(e);
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return MAS_ENOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return MAS_EINVAL;
+  }
+  *out = h.release();
+  return MAS_OK;
+}
+
+int mas_analyze(const mas_problem* prob, const mas_params* par, mas_handle** out) {
+  if (!prob || !par || !out) {
+    g_last_error = "null argument";
+    return MAS_EINVAL;
+  }
+  *out = nullptr;
+  auto h = std::make_unique<mas_handle>();
+  h->par = *par;
+  try {
+    analyze_impl(h.get(), prob);
+  } catch (const MasError& e) {
+    return fail(e);
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return MAS_ENOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return MAS_EINVAL;
+  }
+  *out = h.release();
+  return MAS_OK;
+}
+
+int mas_apply(mas_handle* h, const double* r, double* z, int32_t nrhs, void* stream) {
+  if (!h || !r || !z) {
+    g_last_error = "null argument";
+    return MAS_EINVAL;
+  }
+  if (!h->on_device) {
+    g_last_error = "handle was analysed only; call mas_setup";
+    return MAS_EINVAL;
+  }
+  if (nrhs != 1) {
+    g_last_error = "this build applies one right-hand side at a time";
+    return MAS_EINVAL;
+  }
+  try {
+    hipStream_t s = (hipStream_t)stream;
+    h->cyc->apply(r, z, s);
+  } catch (const MasError& e) {
+    return fail(e);
+  }
+  return MAS_OK;
+}
+
+int mas_solve(mas_handle* h, const double* b, double* x, int32_t nrhs, double rtol, int32_t max_it,
+              mas_solve_info* info, void* stream) {
+  if (!h || !b || !x || rtol < 0.0 || max_it < 1) {
+    g_last_error = "bad argument";
+    return MAS_EINVAL;
+  }
+  if (!h->on_device) {
+    g_last_error = "handle was analysed only; call mas_setup";
+    return MAS_EINVAL;
+  }
+  if (nrhs != 1) {
+    g_last_error = "this build solves one right-hand side at a time";
+    return MAS_EINVAL;
+  }
+  try {
+    hipStream_t s = (hipStream_t)stream;
+    int rc = fgmres(h, b, x, rtol, max_it, info, s);
+    if (h->tm.on) {
+      HIPCHECK(hipStreamSynchronize(s));
+      for (auto& pr : h->tm.vanka) {
+        float ms = 0.f;
+        HIPCHECK(hipEventElapsedTime(&ms, pr.first, pr.second));
+        h->tm.vanka_ms += ms;
+        h->tm.vanka_launches++;
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+      }
+      h->tm.vanka.clear();
+    }
+    if (rc == MAS_ENAN) g_last_error = "residual is not finite";
+    return rc;
+  } catch (const MasError& e) {
+    return fail(e);
+  }
+}
+
+int mas_get_info(const mas_handle* h, mas_hier_info* out) {
+  if (!h || !out) return MAS_EINVAL;
+  *out = h->info;
+  return MAS_OK;
+}
+
+int mas_export_level(const mas_handle* h, int32_t level, int64_t* nrows, int64_t* nnz, int64_t* indptr,
+                     int32_t* indices, double* data) {
+  if (!h || level < 0 || level >= (int32_t)h->host_levels.size()) {
+    g_last_error = "bad level";
+    return MAS_EINVAL;
+  }
+  const Csr& A = h->host_levels[level];
+  if (nrows) *nrows = A.nr;
+  if (nnz) *nnz = A.nnz();
+  if (indptr) std::memcpy(indptr, A.ptr.data(), (A.nr + 1) * sizeof(int64_t));
+  if (indices) std::memcpy(indices, A.ind.data(), A.nnz() * sizeof(int32_t));
+  if (data) std::memcpy(data, A.val.data(), A.nnz() * sizeof(double));
+  return MAS_OK;
+}
+
+int mas_set_timing(mas_handle* h, int32_t enable) {
+  if (!h) return MAS_EINVAL;
+  h->tm.on = enable != 0;
+  h->tm.vanka_ms = 0;
+  h->tm.vanka_launches = 0;
+  return MAS_OK;
+}
+
+int mas_get_timing(const mas_handle* h, double* out, int32_t n) {
+  if (!h || !out) return MAS_EINVAL;
+  if (n > 0) out[0] = h->tm.vanka_ms;
+  if (n > 1) out[1] = (double)h->tm.vanka_launches;
+  return MAS_OK;
+}
+
+int mas_destroy(mas_handle* h) {
+  if (!h) return MAS_OK;
+  if (h->on_device) (void)hipDeviceSynchronize();
+  if (h->hhost) (void)hipHostFree(h->hhost);
+  delete h;
+  return MAS_OK;
+}
+
+const char* mas_error_string(int status) {
+  switch (status) {
+    case MAS_OK: return "ok";
+    case MAS_NOT_CONVERGED: return "not converged";
+    case MAS_EINVAL: return "invalid argument";
+    case MAS_ESINGULAR_PATCH: return "singular patch or coarse operator";
+    case MAS_ENOMEM: return "out of memory";
+    case MAS_EHIP: return "HIP runtime error";
+    case MAS_ENAN: return "non-finite residual";
+    default: return "unknown status";
+  }
+}
+
+const char* mas_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

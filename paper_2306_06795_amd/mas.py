@@ -1,0 +1,224 @@
+"""ctypes binding of libmas (include/mas.h): argument marshalling only.
+
+Every step of the preconditioner and of FGMRES runs in the HIP library; this
+module converts host arrays and torch device tensors to the C-ABI's pointers.
+Importing it fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libmas.so")
+
+MAS_OK, MAS_NOT_CONVERGED = 0, 1
+MAS_EINVAL, MAS_ESINGULAR_PATCH, MAS_ENOMEM, MAS_EHIP, MAS_ENAN = -1, -2, -3, -4, -5
+MAS_TH, MAS_SV = 0, 1
+MAS_RELAX_VANKA, MAS_RELAX_DLSC = 0, 1
+MAS_DC_ALL, MAS_DC_SKIP1, MAS_DC_SKIP0 = 0, 1, 2
+MAS_FP64, MAS_FP32 = 0, 1
+
+
+class mas_csr(C.Structure):
+    _fields_ = [("nrows", C.c_int64), ("ncols", C.c_int64), ("indptr", C.c_void_p),
+                ("indices", C.c_void_p), ("data", C.c_void_p)]
+
+
+class mas_problem(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("disc", C.c_int32), ("K0", mas_csr), ("K1", mas_csr), ("Ap", mas_csr),
+                ("field0", C.c_void_p), ("field1", C.c_void_p), ("dir0", C.c_void_p), ("dir1", C.c_void_p),
+                ("p_nullspace", C.c_int32), ("p_weight0", C.c_void_p), ("mu_diag0", C.c_void_p),
+                ("n_elem", C.c_int64), ("elem_p0", C.c_void_p), ("Pp0", mas_csr), ("Mdg", mas_csr),
+                ("Mcg", mas_csr)]
+
+
+class mas_params(C.Structure):
+    _fields_ = [("relax", C.c_int32), ("schedule", C.c_int32), ("nu1", C.c_int32), ("nu2", C.c_int32),
+                ("omega0", C.c_double), ("omega", C.c_double), ("eta_u", C.c_double), ("eta_p", C.c_double),
+                ("cheb_deg", C.c_int32 * 3), ("precision", C.c_int32), ("restart", C.c_int32),
+                ("max_coarse", C.c_int32), ("max_levels", C.c_int32), ("theta", C.c_double),
+                ("seed", C.c_uint64), ("mass_rtol", C.c_double)]
+
+
+class mas_solve_info(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("relres", C.c_double),
+                ("conv_factor", C.c_double)]
+
+
+class mas_hier_info(C.Structure):
+    _fields_ = [("n_levels", C.c_int32), ("n", C.c_int64 * 16), ("nnz", C.c_int64 * 16),
+                ("n_vel", C.c_int64 * 16), ("n_patches", C.c_int64 * 16), ("patch_dofs", C.c_int64 * 16),
+                ("factor_entries", C.c_int64 * 16), ("p_nnz", C.c_int64 * 16), ("coarse_n", C.c_int64)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libmas is not built ({LIB_PATH}); run paper_2306_06795_amd/build.py")
+    lib = C.CDLL(LIB_PATH)
+    P = C.POINTER
+    lib.mas_default_params.argtypes = [C.c_int32, C.c_int32, C.c_int32, P(mas_params)]
+    lib.mas_default_params.restype = None
+    lib.mas_setup.argtypes = [P(mas_problem), P(mas_params), C.c_void_p, P(C.c_void_p)]
+    lib.mas_analyze.argtypes = [P(mas_problem), P(mas_params), P(C.c_void_p)]
+    lib.mas_apply.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]
+    lib.mas_solve.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_int32,
+                              P(mas_solve_info), C.c_void_p]
+    lib.mas_get_info.argtypes = [C.c_void_p, P(mas_hier_info)]
+    lib.mas_export_level.argtypes = [C.c_void_p, C.c_int32, P(C.c_int64), P(C.c_int64), C.c_void_p,
+                                     C.c_void_p, C.c_void_p]
+    lib.mas_set_timing.argtypes = [C.c_void_p, C.c_int32]
+    lib.mas_get_timing.argtypes = [C.c_void_p, P(C.c_double), C.c_int32]
+    lib.mas_destroy.argtypes = [C.c_void_p]
+    lib.mas_error_string.argtypes = [C.c_int]
+    lib.mas_error_string.restype = C.c_char_p
+    lib.mas_last_error.argtypes = []
+    lib.mas_last_error.restype = C.c_char_p
+    for name in ("mas_setup", "mas_analyze", "mas_apply", "mas_solve", "mas_get_info", "mas_export_level", "mas_set_timing",
+                 "mas_get_timing", "mas_destroy"):
+        getattr(lib, name).restype = C.c_int
+    return lib
+
+
+lib = _load()
+
+EXPORTED = ("mas_default_params", "mas_setup", "mas_analyze", "mas_apply", "mas_solve", "mas_get_info", "mas_export_level",
+            "mas_set_timing", "mas_get_timing", "mas_destroy", "mas_error_string", "mas_last_error")
+
+
+class MasError(RuntimeError):
+    def __init__(self, code: int):
+        self.code = code
+        super().__init__(f"{lib.mas_error_string(code).decode()}: {lib.mas_last_error().decode()}")
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise MasError(rc)
+    return rc
+
+
+def default_params(dim: int, disc: int = MAS_TH, relax: int = MAS_RELAX_VANKA, **over) -> mas_params:
+    p = mas_params()
+    lib.mas_default_params(dim, disc, relax, C.byref(p))
+    for k, v in over.items():
+        if k == "cheb_deg":
+            for i in range(3):
+                p.cheb_deg[i] = int(v[i])
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def _csr(A, keep: list) -> mas_csr:
+    ptr = np.ascontiguousarray(A.indptr, dtype=np.int64)
+    ind = np.ascontiguousarray(A.indices, dtype=np.int32)
+    val = np.ascontiguousarray(A.data, dtype=np.float64)
+    keep += [ptr, ind, val]
+    return mas_csr(A.shape[0], A.shape[1], ptr.ctypes.data, ind.ctypes.data, val.ctypes.data)
+
+
+def _arr(a, dtype, keep: list):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=dtype)
+    keep.append(a)
+    return a.ctypes.data
+
+
+def make_problem_struct(prob, keep: list) -> mas_problem:
+    """mas_problem from an object with the fields of include/mas.h (a StokesProblem)."""
+    s = mas_problem()
+    s.dim = prob.dim
+    s.disc = MAS_SV if prob.disc == "SV" else MAS_TH
+    s.K0 = _csr(prob.K0, keep)
+    s.K1 = _csr(prob.K1, keep)
+    s.Ap = _csr(prob.Ap, keep)
+    s.field0 = _arr(prob.field0, np.int8, keep)
+    s.field1 = _arr(prob.field1, np.int8, keep)
+    s.dir0 = _arr(prob.dir0, np.uint8, keep)
+    s.dir1 = _arr(prob.dir1, np.uint8, keep)
+    s.p_nullspace = 1 if prob.p_nullspace else 0
+    s.p_weight0 = _arr(prob.p_weight0, np.float64, keep)
+    s.mu_diag0 = _arr(getattr(prob, "mu_diag0", None), np.float64, keep)
+    if prob.disc == "SV":
+        s.n_elem = prob.elem_p0.shape[0]
+        s.elem_p0 = _arr(prob.elem_p0, np.int64, keep)
+        s.Pp0 = _csr(prob.Pp0, keep)
+        s.Mdg = _csr(prob.Mdg, keep)
+        s.Mcg = _csr(prob.Mcg, keep)
+    return s
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+class Handle:
+    """Owns one mas_handle.  Device arrays are torch tensors (float64, on the GPU)."""
+
+    def __init__(self, prob, params: mas_params, stream=None, analyze_only: bool = False):
+        keep: list = []
+        s = make_problem_struct(prob, keep)
+        h = C.c_void_p()
+        if analyze_only:
+            _check(lib.mas_analyze(C.byref(s), C.byref(params), C.byref(h)))
+        else:
+            _check(lib.mas_setup(C.byref(s), C.byref(params), _stream(stream), C.byref(h)))
+        self.h = h
+        self.params = params
+        self.n0 = prob.K0.shape[0]
+
+    def apply(self, r, z, nrhs: int = 1, stream=None):
+        _check(lib.mas_apply(self.h, C.c_void_p(r.data_ptr()), C.c_void_p(z.data_ptr()), nrhs, _stream(stream)))
+
+    def solve(self, b, x, rtol: float = 1e-8, max_it: int = 1000, nrhs: int = 1, stream=None):
+        info = (mas_solve_info * nrhs)()
+        rc = _check(lib.mas_solve(self.h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), nrhs, rtol, max_it,
+                                  info, _stream(stream)))
+        out = [dict(iters=i.iters, converged=bool(i.converged), relres=i.relres, conv_factor=i.conv_factor)
+               for i in info]
+        return rc, out
+
+    def info(self) -> dict:
+        hi = mas_hier_info()
+        _check(lib.mas_get_info(self.h, C.byref(hi)))
+        L = hi.n_levels
+        return dict(n_levels=L, n=list(hi.n[:L]), nnz=list(hi.nnz[:L]), n_vel=list(hi.n_vel[:L]),
+                    n_patches=list(hi.n_patches[:L]), patch_dofs=list(hi.patch_dofs[:L]),
+                    factor_entries=list(hi.factor_entries[:L]), p_nnz=list(hi.p_nnz[:L]), coarse_n=hi.coarse_n)
+
+    def export_level(self, level: int):
+        import scipy.sparse as sp
+        nr, nnz = C.c_int64(), C.c_int64()
+        _check(lib.mas_export_level(self.h, level, C.byref(nr), C.byref(nnz), None, None, None))
+        ptr = np.empty(nr.value + 1, np.int64)
+        ind = np.empty(nnz.value, np.int32)
+        val = np.empty(nnz.value, np.float64)
+        _check(lib.mas_export_level(self.h, level, C.byref(nr), C.byref(nnz), ptr.ctypes.data, ind.ctypes.data,
+                                    val.ctypes.data))
+        return sp.csr_matrix((val, ind, ptr), shape=(nr.value, nr.value))
+
+    def set_timing(self, on: bool):
+        _check(lib.mas_set_timing(self.h, 1 if on else 0))
+
+    def timing(self):
+        out = (C.c_double * 2)()
+        _check(lib.mas_get_timing(self.h, out, 2))
+        return dict(vanka_ms_total=out[0], vanka_launches=int(out[1]))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.mas_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,121 @@
+"""The C-ABI library on the CPU: it loads, exports every function include/mas.h
+declares, its ctypes structures match the C layout, and its host-only analysis
+(Algorithm 1 hierarchy, patches) agrees with the oracle's."""
+import ctypes as C
+import os
+import re
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+from paper_2306_06795_amd import mas
+from paper_2306_06795_amd.inputs import make_problem
+from oracle import dc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mas.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mas_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_function_is_exported():
+    names = declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(mas.lib, n), n
+    assert set(names) == set(mas.EXPORTED)
+
+
+def test_struct_layout_matches_c():
+    prog = r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "mas.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu\n", sizeof(mas_csr), sizeof(mas_problem), sizeof(mas_params),
+         sizeof(mas_solve_info), sizeof(mas_hier_info));
+  printf("%zu %zu %zu %zu\n", offsetof(mas_problem, p_nullspace), offsetof(mas_problem, Mcg),
+         offsetof(mas_params, cheb_deg), offsetof(mas_params, mass_rtol));
+  return 0;
+}
+'''
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        open(c, "w").write(prog)
+        exe = os.path.join(d, "t")
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
+        out = subprocess.check_output([exe], text=True).split()
+    sizes = [int(v) for v in out]
+    assert sizes[:5] == [C.sizeof(mas.mas_csr), C.sizeof(mas.mas_problem), C.sizeof(mas.mas_params),
+                         C.sizeof(mas.mas_solve_info), C.sizeof(mas.mas_hier_info)]
+    assert sizes[5:] == [mas.mas_problem.p_nullspace.offset, mas.mas_problem.Mcg.offset,
+                         mas.mas_params.cheb_deg.offset, mas.mas_params.mass_rtol.offset]
+
+
+def test_default_params_follow_the_paper():
+    p = mas.default_params(2, mas.MAS_SV)
+    assert (p.omega0, p.eta_p, p.eta_u, p.restart) == (0.78, 2.68, 1.0, 20)
+    p3 = mas.default_params(3, mas.MAS_TH, mas.MAS_RELAX_DLSC)
+    assert list(p3.cheb_deg) == [4, 4, 16] and p3.nu1 == 2
+
+
+def _same_params(prob, **over):
+    par = dc.default_params(prob, **over)
+    mp = mas.default_params(prob.dim, mas.MAS_SV if prob.disc == "SV" else mas.MAS_TH, theta=par.theta,
+                            max_coarse=par.max_coarse, max_levels=par.max_levels)
+    return par, mp
+
+
+@pytest.mark.parametrize("kw,mc", [
+    (dict(dim=2, n=16), 300),
+    (dict(dim=2, n=16), 30),
+    (dict(dim=2, n=24, jitter=0.2, seed=2, forcing="gaussian", bc="lid"), 40),
+    (dict(dim=3, n=4, forcing="smooth", bc="zero", seed=3), 40),
+])
+def test_host_hierarchy_matches_oracle(kw, mc):
+    P = make_problem(**kw)
+    par, mp = _same_params(P, max_coarse=mc)
+    pre = dc.DCPreconditioner(P, par)
+    h = mas.Handle(P, mp, analyze_only=True)
+    info = h.info()
+    assert info["n_levels"] == 1 + len(pre.levels)
+    levels = [pre.K0] + [lv.K for lv in pre.levels]
+    for l, K in enumerate(levels):
+        Kl = h.export_level(l)
+        assert Kl.shape == K.shape
+        assert np.array_equal(Kl.indptr, K.indptr) and np.array_equal(Kl.indices, K.indices), f"level {l} pattern"
+        scale = np.abs(K.data).max()
+        assert np.abs(Kl.data - K.data).max() <= 1e-13 * scale, f"level {l} values"
+    # patch counts on relaxed levels
+    for l, R in enumerate(pre.relax):
+        assert info["n_patches"][l] == len(R.dofs)
+        assert info["patch_dofs"][l] == sum(d.size for d in R.dofs)
+    h.close()
+
+
+def test_analyze_rejects_bad_input():
+    P = make_problem(dim=2, n=4)
+    mp = mas.default_params(2)
+    bad = make_problem(dim=2, n=4)
+    bad.field0 = bad.field0[::-1].copy()  # not field-blocked
+    with pytest.raises(mas.MasError) as e:
+        mas.Handle(bad, mp, analyze_only=True)
+    assert e.value.code == mas.MAS_EINVAL
+    bad2 = make_problem(dim=2, n=4)
+    bad2.K0 = bad2.K0.copy()
+    bad2.K0.data[3] = np.nan
+    with pytest.raises(mas.MasError) as e:
+        mas.Handle(bad2, mp, analyze_only=True)
+    assert e.value.code == mas.MAS_EINVAL and "non-finite" in str(e.value)
+    h = mas.Handle(P, mp, analyze_only=True)
+    with pytest.raises(mas.MasError):
+        import torch
+        t = torch.zeros(P.n0, dtype=torch.float64)
+        h.apply(t, t, stream=0)
+    h.close()
