@@ -107,7 +107,8 @@ __global__ void __launch_bounds__(WAVE) k_vanka_apply(int64_t np, const int64_t*
                                                      const int4* __restrict__ dims,
                                                      const int64_t* __restrict__ foff,
                                                      const int* __restrict__ dofs, const T* __restrict__ fac,
-                                                     const T* __restrict__ r, T* __restrict__ Y, int max_m) {
+                                                     const T* __restrict__ r, T* __restrict__ Y, int max_m,
+                                                     int64_t yshift) {
   extern __shared__ unsigned char smem_raw[];
   T* sb = reinterpret_cast<T*>(smem_raw);
   T* sy = sb + max_m;
@@ -118,7 +119,10 @@ __global__ void __launch_bounds__(WAVE) k_vanka_apply(int64_t np, const int64_t*
   const int nv = d.x + d.y + d.z, ns = d.w, m = nv + ns;
   const int64_t o = off[p];
   for (int k = lane; k < m; k += WAVE) sb[k] = r[dofs[o + k]];
-  const int64_t f0 = foff[p], nf = foff[p + 1] - f0;
+  // record length from the shape (foff holds per-patch base offsets only)
+  const int64_t f0 = foff[p];
+  const int64_t nf = (int64_t)d.x * (d.x + 1) / 2 + (int64_t)d.y * (d.y + 1) / 2 + (int64_t)d.z * (d.z + 1) / 2 +
+                     (int64_t)nv * ns + (int64_t)ns * (ns + 1) / 2;
   const T* sf;
   if (STAGE) {
     T* st = sy + max_m;
@@ -162,10 +166,72 @@ __global__ void __launch_bounds__(WAVE) k_vanka_apply(int64_t np, const int64_t*
   for (int row = lane; row < nv; row += WAVE) {
     T acc = sy[row];
     for (int s = 0; s < ns; ++s) acc += U[(int64_t)s * nv + row] * yp[s];
-    Y[o + row] = acc;
+    Y[o - yshift + row] = acc;
   }
   for (int s = 0; s < ns; ++s)
-    if (lane == s) Y[o + nv + s] = yp[s];
+    if (lane == s) Y[o - yshift + nv + s] = yp[s];
+}
+
+// additive Vanka for a bucket of P patches of one fixed shape: one thread per
+// patch, DoF lists and factor records interleaved across the bucket (element q
+// of patch p at q * Ppad + p), so every load of a wavefront is one contiguous
+// 64-element segment.  Uhat and S^-1 are applied first, then the packed A^-1
+// blocks are streamed: x_u = Uhat y_p + A^-1 b_u.
+template <typename T, int N0, int N1, int N2, int NS>
+__global__ void __launch_bounds__(256) k_vanka_tpp(int64_t P, int64_t Ppad, const int* __restrict__ dofs,
+                                                  const T* __restrict__ fac, const T* __restrict__ r,
+                                                  T* __restrict__ Y) {
+  constexpr int NV = N0 + N1 + N2, M = NV + NS;
+  constexpr int FA = N0 * (N0 + 1) / 2 + N1 * (N1 + 1) / 2 + N2 * (N2 + 1) / 2;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const T* f = fac + p;
+  T b[M];
+#pragma unroll
+  for (int k = 0; k < M; ++k) b[k] = r[dofs[(int64_t)k * Ppad + p]];
+  T u[NV * NS], t[NS], yp[NS], y[NV];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) t[s] = b[NV + s];
+#pragma unroll
+  for (int s = 0; s < NS; ++s)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      u[s * NV + k] = f[(int64_t)(FA + s * NV + k) * Ppad];
+      t[s] += u[s * NV + k] * b[k];
+    }
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    T acc = 0;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+      const int a = s < q ? s : q, c = s < q ? q : s;
+      acc += f[(int64_t)(FA + NV * NS + c * (c + 1) / 2 + a) * Ppad] * t[q];
+    }
+    yp[s] = acc;
+  }
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    T acc = 0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) acc += u[s * NV + k] * yp[s];
+    y[k] = acc;
+  }
+  int q = 0;
+#define MAS_BLOCK(CS, N)                                   \
+  _Pragma("unroll") for (int j = 0; j < (N); ++j)          \
+    _Pragma("unroll") for (int i = 0; i <= j; ++i) {       \
+      const T a = f[(int64_t)(q++) * Ppad];                \
+      y[(CS) + i] += a * b[(CS) + j];                      \
+      if (i != j) y[(CS) + j] += a * b[(CS) + i];          \
+    }
+  MAS_BLOCK(0, N0)
+  MAS_BLOCK(N0, N1)
+  MAS_BLOCK(N0 + N1, N2)
+#undef MAS_BLOCK
+#pragma unroll
+  for (int k = 0; k < NV; ++k) Y[(int64_t)k * Ppad + p] = y[k];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) Y[(int64_t)(NV + s) * Ppad + p] = yp[s];
 }
 
 // x[j] (+)= omega W_j sum of the patch values held for DoF j (deterministic
@@ -179,6 +245,32 @@ __global__ void k_vanka_pull(int n, const int* __restrict__ inv_ptr, const int* 
   T acc = 0;
   for (int k = inv_ptr[j]; k < inv_ptr[j + 1]; ++k) acc += Y[inv_pos[k]];
   T v = omega * w[j] * acc;
+  x[j] = accumulate ? x[j] + v : v;
+}
+
+// Same as k_vanka_pull with the DoF -> patch-value map stored slot-major
+// (pos[s * n + j], -1 = empty slot): index loads are coalesced and the gathers
+// of one DoF are independent.  W_j = 1 / (number of patches holding j).
+template <typename T>
+__global__ void k_vanka_pull_ell(int n, int width, const int* __restrict__ pos, const T* __restrict__ Y, T omega,
+                                 T* __restrict__ x, int accumulate) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  T acc = 0;
+  int cnt = 0;
+#pragma unroll 4
+  for (int s = 0; s < width; ++s) {
+    const int q = pos[(int64_t)s * n + j];
+    if (q >= 0) {
+      acc += Y[q];
+      ++cnt;
+    }
+  }
+  if (cnt == 0) {
+    if (!accumulate) x[j] = 0;
+    return;
+  }
+  const T v = omega * acc / (T)cnt;
   x[j] = accumulate ? x[j] + v : v;
 }
 
@@ -199,7 +291,8 @@ __device__ __forceinline__ int find_sorted(const int* a, int n, int key) {
 template <typename TO>
 __global__ void __launch_bounds__(WAVE) k_vanka_factor(int64_t np, const int64_t* __restrict__ off,
                                                       const int4* __restrict__ dims,
-                                                      const int64_t* __restrict__ foff, const int* __restrict__ dofs,
+                                                      const int64_t* __restrict__ foff,
+                                                      const int64_t* __restrict__ fstride, const int* __restrict__ dofs,
                                                       const int* __restrict__ kptr, const int* __restrict__ kind,
                                                       const double* __restrict__ kval, TO* __restrict__ fac,
                                                       double* __restrict__ gwork, int64_t work_stride,
@@ -216,6 +309,7 @@ __global__ void __launch_bounds__(WAVE) k_vanka_factor(int64_t np, const int64_t
     const int nv = d.x + d.y + d.z, ns = d.w;
     const int* P = dofs + off[p];
     TO* out = fac + foff[p];
+    const int64_t fs = fstride[p];  // 1: contiguous record; P: interleaved across a bucket of P patches
     // B rows of the seeds restricted to the patch velocities
     for (int k = lane; k < ns * nv; k += WAVE) Bm[k] = 0.0;
     __syncthreads();
@@ -272,7 +366,7 @@ __global__ void __launch_bounds__(WAVE) k_vanka_factor(int64_t np, const int64_t
         while ((int64_t)j * (j + 1) / 2 > q) --j;
         while ((int64_t)(j + 1) * (j + 2) / 2 <= q) ++j;
         int i = (int)(q - (int64_t)j * (j + 1) / 2);
-        out[ao + q] = (TO)(0.5 * (W[(int64_t)i * n + j] + W[(int64_t)j * n + i]));
+        out[(ao + q) * fs] = (TO)(0.5 * (W[(int64_t)i * n + j] + W[(int64_t)j * n + i]));
       }
       // U_c = A_c^-1 B_c^T
       for (int i = lane; i < n; i += WAVE)
@@ -317,17 +411,14 @@ __global__ void __launch_bounds__(WAVE) k_vanka_factor(int64_t np, const int64_t
         }
       }
       if (!ok) atomicMin((unsigned long long*)bad, (unsigned long long)p);
-      TO* Uh = out + ao;
-      TO* Si = Uh + (int64_t)nv * ns;
+      const int64_t so = ao + (int64_t)nv * ns;
       for (int t = 0; t < ns; ++t)
-        for (int s = 0; s <= t; ++s) Si[(int64_t)t * (t + 1) / 2 + s] = (TO)(0.5 * (I[s * ns + t] + I[t * ns + s]));
+        for (int s = 0; s <= t; ++s)
+          out[(so + (int64_t)t * (t + 1) / 2 + s) * fs] = (TO)(0.5 * (I[s * ns + t] + I[t * ns + s]));
     }
-    {
-      TO* Uh = out + ao;
-      for (int64_t q = lane; q < (int64_t)nv * ns; q += WAVE) {
-        int s = (int)(q / nv), k = (int)(q % nv);
-        Uh[q] = (TO)(-U[(int64_t)k * ns + s]);
-      }
+    for (int64_t q = lane; q < (int64_t)nv * ns; q += WAVE) {
+      int s = (int)(q / nv), k = (int)(q % nv);
+      out[(ao + q) * fs] = (TO)(-U[(int64_t)k * ns + s]);
     }
     __syncthreads();
   }

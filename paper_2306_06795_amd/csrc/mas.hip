@@ -2,8 +2,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <map>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <stdexcept>
@@ -45,6 +48,18 @@ inline void launch_check() {
 inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 constexpr size_t kMaxLds = 64 * 1024;  // dynamic LDS per workgroup used by the patch kernels
+
+// Patch shapes (DoFs per velocity component x3, seeds) served by the
+// thread-per-patch kernel: interior 2D Taylor-Hood / P1isoP2 patches, interior
+// Scott-Vogelius element patches and the small P1isoP2/P1 patches of the
+// barycentric mesh.
+#define MAS_FAST_SHAPES(X) X(19, 19, 0, 1) X(6, 6, 0, 3) X(10, 10, 0, 1)
+static bool is_fast_shape(const int32_t* d) {
+#define MAS_IS(A, B, C, D) if (d[0] == A && d[1] == B && d[2] == C && d[3] == D) return true;
+  MAS_FAST_SHAPES(MAS_IS)
+#undef MAS_IS
+  return false;
+}
 
 // ---------------------------------------------------------------------------
 // device memory owned by a handle
@@ -117,23 +132,69 @@ void csr_launch(const DCsr<T>& A, const T* x, const T* b, T* y, hipStream_t s) {
   launch_check();
 }
 
+// Pick the lanes-per-row of a CSR product by timing every choice once on the
+// actual operand (setup-time autotuning; vectors may hold any values).
+template <typename T>
+void autotune_team(DCsr<T>& A, const T* x, T* y, hipStream_t s) {
+  if (A.n == 0 || A.nnz < 4096 || std::getenv("MAS_NO_AUTOTUNE")) return;
+  hipEvent_t e0, e1;
+  HIPCHECK(hipEventCreate(&e0));
+  HIPCHECK(hipEventCreate(&e1));
+  float best = 1e30f;
+  int best_team = A.team;
+  for (int team : {2, 4, 8, 16, 32, 64}) {
+    A.team = team;
+    csr_launch<T, 0>(A, x, nullptr, y, s);  // warm
+    HIPCHECK(hipEventRecord(e0, s));
+    for (int rep = 0; rep < 3; ++rep) csr_launch<T, 0>(A, x, nullptr, y, s);
+    HIPCHECK(hipEventRecord(e1, s));
+    HIPCHECK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) {
+      best = ms;
+      best_team = team;
+    }
+  }
+  A.team = best_team;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+}
+
 // ---------------------------------------------------------------------------
 // levels of the cycle
 
+// One fixed-shape bucket handled by the thread-per-patch kernel.
+struct FastBucket {
+  int shape[4] = {0, 0, 0, 0};
+  int64_t P = 0, Ppad = 0;
+  int* dofs = nullptr;  // interleaved DoF lists, M x Ppad
+  int64_t fbase = 0;    // offset of the bucket's interleaved records in fac
+  int64_t ybase = 0;    // offset of the bucket's outputs in Y
+};
+
 template <typename T>
 struct DPatches {
-  int64_t np = 0, ndofs = 0, nfac = 0;
+  int64_t np = 0, ndofs = 0, nfac = 0, ny = 0;
+  // all patches (fast buckets first), used by the factorisation
   int64_t* off = nullptr;
   int4* dims = nullptr;
   int64_t* foff = nullptr;
+  int64_t* fstride = nullptr;
   int* dofs = nullptr;
   T* fac = nullptr;
-  int* inv_ptr = nullptr;
-  int* inv_pos = nullptr;
-  T* w = nullptr;
-  T* Y = nullptr;
+  // generic patches: indices [g0, np) of the arrays above
+  int64_t g0 = 0, yshift = 0;
   int max_m = 0;
   int64_t max_f = 0;
+  std::vector<FastBucket> fast;
+  // DoF -> outputs map: CSR (inv_ptr, inv_pos) or slot-major ELL (ell, width)
+  int* inv_ptr = nullptr;
+  int* inv_pos = nullptr;
+  int* ell = nullptr;
+  int ell_width = 0;
+  T* w = nullptr;
+  T* Y = nullptr;
 };
 
 template <typename T>
@@ -169,6 +230,35 @@ struct Cycle : CycleBase {
   mas_params par{};
   Timing* tm = nullptr;
 
+  void patch_solve(Level<T>& L, const T* rin, hipStream_t s) {
+    DPatches<T>& pt = L.pt;
+    for (const FastBucket& fb : pt.fast) {
+      const unsigned nb = blocks_for(fb.P, 256);
+      const int* d = fb.dofs;
+      const T* f = pt.fac + fb.fbase;
+      T* y = pt.Y + fb.ybase;
+#define MAS_TPP(A, B, C, D)                                                                                    \
+  if (fb.shape[0] == A && fb.shape[1] == B && fb.shape[2] == C && fb.shape[3] == D) {                         \
+    hipLaunchKernelGGL((k_vanka_tpp<T, A, B, C, D>), dim3(nb), dim3(256), 0, s, fb.P, fb.Ppad, d, f, rin, y); \
+  } else
+      MAS_FAST_SHAPES(MAS_TPP) { throw MasError(MAS_EINVAL, "unknown patch bucket shape"); }
+#undef MAS_TPP
+      launch_check();
+    }
+    const int64_t ng = pt.np - pt.g0;
+    if (ng > 0) {
+      const bool stage = (size_t)(2 * pt.max_m + pt.max_f) * sizeof(T) <= kMaxLds;
+      const size_t shm = (size_t)(2 * pt.max_m + (stage ? pt.max_f : 0)) * sizeof(T);
+      if (stage)
+        hipLaunchKernelGGL((k_vanka_apply<T, true>), dim3((unsigned)ng), dim3(WAVE), shm, s, ng, pt.off + pt.g0,
+                           pt.dims + pt.g0, pt.foff + pt.g0, pt.dofs, pt.fac, rin, pt.Y, pt.max_m, pt.yshift);
+      else
+        hipLaunchKernelGGL((k_vanka_apply<T, false>), dim3((unsigned)ng), dim3(WAVE), shm, s, ng, pt.off + pt.g0,
+                           pt.dims + pt.g0, pt.foff + pt.g0, pt.dofs, pt.fac, rin, pt.Y, pt.max_m, pt.yshift);
+      launch_check();
+    }
+  }
+
   void vanka_sweeps(Level<T>& L, int sweeps, T omega, bool x_zero, hipStream_t s) {
     for (int k = 0; k < sweeps; ++k) {
       const T* rin;
@@ -178,27 +268,24 @@ struct Cycle : CycleBase {
         csr_launch<T, 1>(L.K, L.x, L.b, L.r, s);
         rin = L.r;
       }
-      const bool stage = (size_t)(2 * L.pt.max_m + L.pt.max_f) * sizeof(T) <= kMaxLds;
-      const size_t shm = (size_t)(2 * L.pt.max_m + (stage ? L.pt.max_f : 0)) * sizeof(T);
       hipEvent_t e0{}, e1{};
       if (tm && tm->on) {
         HIPCHECK(hipEventCreate(&e0));
         HIPCHECK(hipEventCreate(&e1));
         HIPCHECK(hipEventRecord(e0, s));
       }
-      if (stage)
-        hipLaunchKernelGGL((k_vanka_apply<T, true>), dim3((unsigned)L.pt.np), dim3(WAVE), shm, s, L.pt.np, L.pt.off,
-                           L.pt.dims, L.pt.foff, L.pt.dofs, L.pt.fac, rin, L.pt.Y, L.pt.max_m);
-      else
-        hipLaunchKernelGGL((k_vanka_apply<T, false>), dim3((unsigned)L.pt.np), dim3(WAVE), shm, s, L.pt.np,
-                           L.pt.off, L.pt.dims, L.pt.foff, L.pt.dofs, L.pt.fac, rin, L.pt.Y, L.pt.max_m);
-      launch_check();
+      patch_solve(L, rin, s);
       if (tm && tm->on) {
         HIPCHECK(hipEventRecord(e1, s));
         tm->vanka.push_back({e0, e1});
       }
-      hipLaunchKernelGGL((k_vanka_pull<T>), dim3(blocks_for(L.n, 256)), dim3(256), 0, s, (int)L.n, L.pt.inv_ptr,
-                         L.pt.inv_pos, L.pt.Y, L.pt.w, omega, L.x, (k == 0 && x_zero) ? 0 : 1);
+      const int acc = (k == 0 && x_zero) ? 0 : 1;
+      if (L.pt.ell)
+        hipLaunchKernelGGL((k_vanka_pull_ell<T>), dim3(blocks_for(L.n, 256)), dim3(256), 0, s, (int)L.n,
+                           L.pt.ell_width, L.pt.ell, L.pt.Y, omega, L.x, acc);
+      else
+        hipLaunchKernelGGL((k_vanka_pull<T>), dim3(blocks_for(L.n, 256)), dim3(256), 0, s, (int)L.n, L.pt.inv_ptr,
+                           L.pt.inv_pos, L.pt.Y, L.pt.w, omega, L.x, acc);
       launch_check();
     }
   }
@@ -350,32 +437,137 @@ template <typename T>
 void build_patches(DevArena& ar, Level<T>& L, const PatchSet& ps, const DCsr<double>& K64, int level,
                    hipStream_t s) {
   DPatches<T>& d = L.pt;
-  d.np = ps.np();
+  const int64_t np = ps.np();
+  d.np = np;
   d.ndofs = (int64_t)ps.dofs.size();
-  d.nfac = ps.foff.back();
   d.max_m = ps.max_m;
   d.max_f = ps.max_f;
-  d.off = ar.upload<int64_t>(ps.off, s);
+  for (int64_t p = 0; p < np; ++p)
+    if (ps.dims[4 * p + 3] > MAX_NS || ps.dims[4 * p + 3] < 1) throw MasError(MAS_EINVAL, "patch seed count out of range");
+  // ---- order: fast buckets (one per shape, at least 64 patches) first, then the rest
+  std::vector<std::vector<int64_t>> groups;
+  std::vector<std::array<int, 4>> gshape;
+  std::vector<int64_t> generic;
   {
-    std::vector<int32_t> dims = ps.dims;
-    for (int64_t p = 0; p < d.np; ++p)
-      if (dims[4 * p + 3] > MAX_NS || dims[4 * p + 3] < 1)
-        throw MasError(MAS_EINVAL, "patch seed count out of range");
-    int4* dd = ar.alloc<int4>(d.np);
+    std::vector<int64_t> cnt_idx;
+    std::map<std::array<int, 4>, std::vector<int64_t>> by;
+    for (int64_t p = 0; p < np; ++p) {
+      const int32_t* q = &ps.dims[4 * p];
+      if (is_fast_shape(q)) by[{q[0], q[1], q[2], q[3]}].push_back(p);
+      else generic.push_back(p);
+    }
+    const char* env_min = std::getenv("MAS_TPP_MIN_PATCHES");
+    const int64_t min_bucket = env_min ? std::atoll(env_min) : 64;
+    for (auto& kv : by) {
+      if ((int64_t)kv.second.size() >= min_bucket) {
+        gshape.push_back(kv.first);
+        groups.push_back(kv.second);
+      } else {
+        generic.insert(generic.end(), kv.second.begin(), kv.second.end());
+      }
+    }
+    std::sort(generic.begin(), generic.end());
+  }
+  std::vector<int64_t> order;
+  for (auto& g : groups) order.insert(order.end(), g.begin(), g.end());
+  const int64_t g0 = (int64_t)order.size();
+  order.insert(order.end(), generic.begin(), generic.end());
+  // ---- arrays in the new order
+  std::vector<int64_t> off(np + 1, 0), foff(np), fstr(np);
+  std::vector<int32_t> dims(4 * np), dofs;
+  dofs.reserve(ps.dofs.size());
+  std::vector<int64_t> ypos;  // output position of every (patch, slot), in the order of dofs
+  ypos.reserve(ps.dofs.size());
+  int64_t fcur = 0, ycur = 0;
+  d.fast.clear();
+  int64_t pnew = 0;
+  for (size_t b = 0; b < groups.size(); ++b) {
+    FastBucket fb;
+    for (int c = 0; c < 4; ++c) fb.shape[c] = gshape[b][c];
+    fb.P = (int64_t)groups[b].size();
+    fb.Ppad = (fb.P + 63) / 64 * 64;
+    const int M = fb.shape[0] + fb.shape[1] + fb.shape[2] + fb.shape[3];
+    const int64_t F = ps.foff[groups[b][0] + 1] - ps.foff[groups[b][0]];
+    fb.fbase = fcur;
+    fb.ybase = ycur;
+    std::vector<int32_t> il((size_t)M * fb.Ppad, 0);
+    for (int64_t i = 0; i < fb.P; ++i, ++pnew) {
+      const int64_t p = groups[b][i];
+      for (int c = 0; c < 4; ++c) dims[4 * pnew + c] = ps.dims[4 * p + c];
+      foff[pnew] = fcur + i;
+      fstr[pnew] = fb.Ppad;
+      for (int k = 0; k < M; ++k) {
+        const int32_t j = ps.dofs[ps.off[p] + k];
+        dofs.push_back(j);
+        ypos.push_back(ycur + (int64_t)k * fb.Ppad + i);
+        il[(size_t)k * fb.Ppad + i] = j;
+      }
+      off[pnew + 1] = (int64_t)dofs.size();
+    }
+    fb.dofs = ar.upload<int>(il, s);
+    fcur += F * fb.Ppad;
+    ycur += (int64_t)M * fb.Ppad;
+    d.fast.push_back(fb);
+  }
+  d.g0 = g0;
+  d.yshift = (int64_t)dofs.size() - ycur;  // generic outputs follow the fast buckets in Y
+  for (int64_t p : generic) {
+    for (int c = 0; c < 4; ++c) dims[4 * pnew + c] = ps.dims[4 * p + c];
+    foff[pnew] = fcur;
+    fstr[pnew] = 1;
+    fcur += ps.foff[p + 1] - ps.foff[p];
+    for (int64_t k = ps.off[p]; k < ps.off[p + 1]; ++k) {
+      ypos.push_back(ycur);
+      ++ycur;
+      dofs.push_back(ps.dofs[k]);
+    }
+    off[pnew + 1] = (int64_t)dofs.size();
+    ++pnew;
+  }
+  d.nfac = fcur;
+  d.ny = ycur;
+  // ---- DoF -> output positions, in patch order (deterministic sums)
+  const int64_t n = L.n;
+  std::vector<int32_t> cnt(n, 0);
+  for (int32_t j : dofs) cnt[j]++;
+  std::vector<int32_t> iptr(n + 1, 0);
+  for (int64_t j = 0; j < n; ++j) iptr[j + 1] = iptr[j] + cnt[j];
+  std::vector<int32_t> ipos(dofs.size());
+  std::vector<int32_t> fillp(iptr.begin(), iptr.end() - 1);
+  for (size_t k = 0; k < dofs.size(); ++k) ipos[fillp[dofs[k]]++] = (int32_t)ypos[k];
+  int width = 0;
+  for (int64_t j = 0; j < n; ++j) width = std::max(width, cnt[j]);
+  const double avg = n ? (double)dofs.size() / (double)n : 1.0;
+  const bool force_csr = std::getenv("MAS_PULL_CSR") != nullptr;
+  if (!force_csr && width <= 16 && width <= 2.5 * avg + 1) {
+    std::vector<int32_t> ell((size_t)width * n, -1);
+    for (int64_t j = 0; j < n; ++j)
+      for (int32_t q = iptr[j]; q < iptr[j + 1]; ++q) ell[(size_t)(q - iptr[j]) * n + j] = ipos[q];
+    d.ell = ar.upload<int>(ell, s);
+    d.ell_width = width;
+  } else {
+    d.inv_ptr = ar.upload<int>(iptr, s);
+    d.inv_pos = ar.upload<int>(ipos, s);
+    std::vector<double> w(n, 0.0);
+    for (int64_t j = 0; j < n; ++j)
+      if (cnt[j] > 0) w[j] = 1.0 / (double)cnt[j];
+    d.w = ar.upload<T>(w, s);
+  }
+  d.off = ar.upload<int64_t>(off, s);
+  {
+    int4* dd = ar.alloc<int4>(np);
     HIPCHECK(hipMemcpyAsync(dd, dims.data(), dims.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     HIPCHECK(hipStreamSynchronize(s));
     d.dims = dd;
   }
-  d.foff = ar.upload<int64_t>(ps.foff, s);
-  d.dofs = ar.upload<int>(ps.dofs, s);
-  d.inv_ptr = ar.upload<int>(ps.inv_ptr, s);
-  d.inv_pos = ar.upload<int>(ps.inv_pos, s);
-  d.w = ar.upload<T>(ps.w, s);
-  d.Y = ar.alloc<T>(d.ndofs);
+  d.foff = ar.upload<int64_t>(foff, s);
+  d.fstride = ar.upload<int64_t>(fstr, s);
+  d.dofs = ar.upload<int>(dofs, s);
+  d.Y = ar.alloc<T>(d.ny);
   d.fac = ar.alloc<T>(d.nfac);
-  // FP64 factorisation on the GPU
+  // ---- FP64 factorisation on the GPU
   int max_nc = 0, max_nv = 0;
-  for (int64_t p = 0; p < d.np; ++p) {
+  for (int64_t p = 0; p < np; ++p) {
     const int32_t* q = &ps.dims[4 * p];
     max_nc = std::max({max_nc, q[0], q[1], q[2]});
     max_nv = std::max(max_nv, q[0] + q[1] + q[2]);
@@ -386,18 +578,20 @@ void build_patches(DevArena& ar, Level<T>& L, const PatchSet& ps, const DCsr<dou
   int64_t init = INT64_MAX;
   HIPCHECK(hipMemcpyAsync(bad, &init, sizeof(int64_t), hipMemcpyHostToDevice, s));
   const bool use_lds = lds_bytes <= kMaxLds;
-  const unsigned grid = use_lds ? (unsigned)std::min<int64_t>(d.np, 65536) : (unsigned)std::min<int64_t>(d.np, 1024);
+  const unsigned grid = use_lds ? (unsigned)std::min<int64_t>(np, 65536) : (unsigned)std::min<int64_t>(np, 1024);
   double* gwork = use_lds ? nullptr : ar.alloc<double>((size_t)stride * grid);
-  hipLaunchKernelGGL((k_vanka_factor<T>), dim3(grid), dim3(WAVE), use_lds ? lds_bytes : 0, s, d.np, d.off, d.dims,
-                     d.foff, d.dofs, K64.ptr, K64.ind, K64.val, d.fac, gwork, stride, use_lds ? 1 : 0, max_nv,
-                     1e-14, bad);
+  hipLaunchKernelGGL((k_vanka_factor<T>), dim3(grid), dim3(WAVE), use_lds ? lds_bytes : 0, s, np, d.off, d.dims,
+                     d.foff, d.fstride, d.dofs, K64.ptr, K64.ind, K64.val, d.fac, gwork, stride, use_lds ? 1 : 0,
+                     max_nv, 1e-14, bad);
   launch_check();
   int64_t hbad = 0;
   HIPCHECK(hipMemcpyAsync(&hbad, bad, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipStreamSynchronize(s));
-  if (hbad != INT64_MAX)
+  if (hbad != INT64_MAX) {
+    const int64_t orig = order[hbad];
     throw MasError(MAS_ESINGULAR_PATCH,
-                   "singular patch block on level " + std::to_string(level) + ", patch " + std::to_string(hbad));
+                   "singular patch block on level " + std::to_string(level) + ", patch " + std::to_string(orig));
+  }
 }
 
 template <typename T>
@@ -433,6 +627,16 @@ std::unique_ptr<Cycle<T>> build_cycle(mas_handle* h, const std::vector<Csr>& Ks,
         else K64 = upload_csr<double>(ar, Ks[l], s);
         build_patches<T>(ar, L, patches[l], K64, (int)l, s);
       }
+    }
+  }
+  // lanes per row of every sparse product, timed on the operands
+  for (size_t l = 0; l + 1 < nl; ++l) {
+    Level<T>& L = cyc->lev[l];
+    autotune_team<T>(L.K, L.x, L.r, s);
+    if (l >= 1) {
+      Level<T>& C = cyc->lev[l + 1];
+      autotune_team<T>(L.R, L.r, C.b, s);
+      autotune_team<T>(L.P, C.x, L.x, s);
     }
   }
   // coarsest: dense inverse of the bordered operator
@@ -618,6 +822,12 @@ void upload_impl(mas_handle* h, hipStream_t s) {
   const mas_params& par = h->par;
   const int64_t n0 = h->n0;
   h->K0full = upload_csr<double>(h->arena, pl.K0, s);
+  {
+    double* tx = h->arena.alloc<double>(n0);
+    double* ty = h->arena.alloc<double>(n0);
+    HIPCHECK(hipMemsetAsync(tx, 0, n0 * sizeof(double), s));
+    autotune_team<double>(h->K0full, tx, ty, s);
+  }
   if (par.precision == MAS_FP32)
     h->cyc = build_cycle<float>(h, pl.Ks, pl.Ps, pl.fields, pl.patches, pl.relax, pl.Kb, pl.free0, pl.dir0, s);
   else
