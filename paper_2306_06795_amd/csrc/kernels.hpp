@@ -55,6 +55,41 @@ __global__ void __launch_bounds__(256) k_csr(int n, const int* __restrict__ ptr,
   }
 }
 
+// Sliced ELL, 64 rows per slice (one wavefront, one lane per row), entries of a
+// slice stored column-major so that every load of the wavefront is one
+// contiguous segment; padded entries have value 0 and a valid column.
+template <typename T, int MODE>
+__global__ void __launch_bounds__(256) k_sell(int n, int64_t nslices, const int64_t* __restrict__ soff,
+                                              const int* __restrict__ swidth, const int* __restrict__ ind,
+                                              const T* __restrict__ val, const T* __restrict__ x,
+                                              const T* __restrict__ b, T* __restrict__ y) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t slice = row >> 6;
+  if (slice >= nslices) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t base = soff[slice] + lane;
+  const int w = swidth[slice];
+  T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  int c = 0;
+  for (; c + 3 < w; c += 4) {
+    const int64_t e = base + (int64_t)c * 64;
+    s0 += val[e] * x[ind[e]];
+    s1 += val[e + 64] * x[ind[e + 64]];
+    s2 += val[e + 128] * x[ind[e + 128]];
+    s3 += val[e + 192] * x[ind[e + 192]];
+  }
+  for (; c < w; ++c) {
+    const int64_t e = base + (int64_t)c * 64;
+    s0 += val[e] * x[ind[e]];
+  }
+  const T s = (s0 + s1) + (s2 + s3);
+  if (row < n) {
+    if (MODE == 0) y[row] = s;
+    else if (MODE == 1) y[row] = b[row] - s;
+    else y[row] += s;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // vector kernels
 
@@ -542,6 +577,31 @@ __global__ void __launch_bounds__(256) k_reduce_final(int nb, const double* __re
     double t = sh[0] + sh[1] + sh[2] + sh[3];
     out[0] = take_sqrt ? sqrt(t) : t;
   }
+}
+
+// One modified Gram-Schmidt step, fused: w -= (*hprev) vprev (when vprev is
+// given), then partial[b] = block b's share of w . vnext (mode 0) or w . w
+// (mode 1).  k_reduce_final adds the partials in block order.  (A last-block
+// reduction inside this kernel would need a device-scope fence per block,
+// which writes back the non-coherent per-XCD L2 caches and costs far more.)
+__global__ void __launch_bounds__(256) k_mgs_step(int64_t n, double* __restrict__ w, const double* __restrict__ vprev,
+                                                 const double* __restrict__ hprev, const double* __restrict__ vnext,
+                                                 double* __restrict__ partial, int mode) {
+  __shared__ double sh[4];
+  const double a = vprev ? *hprev : 0.0;
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double wi = w[i];
+    if (vprev) {
+      wi -= a * vprev[i];
+      w[i] = wi;
+    }
+    s += wi * (mode == 0 ? vnext[i] : wi);
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & (WAVE - 1)) == 0) sh[threadIdx.x / WAVE] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
 // y -= (*h) x

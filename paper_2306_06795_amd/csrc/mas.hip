@@ -91,6 +91,9 @@ struct DevArena {
   }
 };
 
+// Sparse operator on the device: CSR (TEAM lanes per row) and, when the
+// padding is small, a sliced-ELL copy (64-row slices).  The product kernel is
+// chosen by timing at setup.
 template <typename T>
 struct DCsr {
   int64_t n = 0, m = 0, nnz = 0;
@@ -98,6 +101,12 @@ struct DCsr {
   int* ind = nullptr;
   T* val = nullptr;
   int team = 8;
+  int64_t nslices = 0;
+  int64_t* soff = nullptr;
+  int* swidth = nullptr;
+  int* sind = nullptr;
+  T* sval = nullptr;
+  bool use_sell = false;
 };
 
 template <typename T>
@@ -114,6 +123,38 @@ DCsr<T> upload_csr(DevArena& A, const Csr& C, hipStream_t s) {
   int t = 1;
   while (t < 64 && 2 * t <= avg) t *= 2;
   d.team = std::max(2, t);
+  // sliced ELL when it pads little
+  const int64_t ns = (C.nr + 63) / 64;
+  std::vector<int64_t> soff(ns + 1, 0);
+  std::vector<int> sw(ns, 0);
+  for (int64_t sl = 0; sl < ns; ++sl) {
+    int w = 0;
+    for (int64_t r = sl * 64; r < std::min<int64_t>(C.nr, sl * 64 + 64); ++r)
+      w = std::max<int>(w, (int)(C.ptr[r + 1] - C.ptr[r]));
+    sw[sl] = w;
+    soff[sl + 1] = soff[sl] + (int64_t)w * 64;
+  }
+  if (ns > 0 && soff[ns] <= (int64_t)(1.3 * (double)C.nnz()) + 64) {
+    std::vector<int> sind(soff[ns], 0);
+    std::vector<double> sval(soff[ns], 0.0);
+    for (int64_t sl = 0; sl < ns; ++sl)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int64_t r = sl * 64 + lane;
+        int c = 0;
+        if (r < C.nr)
+          for (int64_t e = C.ptr[r]; e < C.ptr[r + 1]; ++e, ++c) {
+            sind[soff[sl] + (int64_t)c * 64 + lane] = C.ind[e];
+            sval[soff[sl] + (int64_t)c * 64 + lane] = C.val[e];
+          }
+        const int pad_col = (r < C.nr && C.ptr[r + 1] > C.ptr[r]) ? C.ind[C.ptr[r]] : 0;
+        for (; c < sw[sl]; ++c) sind[soff[sl] + (int64_t)c * 64 + lane] = pad_col;
+      }
+    d.nslices = ns;
+    d.soff = A.upload<int64_t>(soff, s);
+    d.swidth = A.upload<int>(sw, s);
+    d.sind = A.upload<int>(sind, s);
+    d.sval = A.upload<T>(sval, s);
+  }
   return d;
 }
 
@@ -121,6 +162,12 @@ template <typename T, int MODE>
 void csr_launch(const DCsr<T>& A, const T* x, const T* b, T* y, hipStream_t s) {
   if (A.n == 0) return;
   const int bs = 256;
+  if (A.use_sell) {
+    hipLaunchKernelGGL((k_sell<T, MODE>), dim3(blocks_for(A.nslices * 64, bs)), dim3(bs), 0, s, (int)A.n, A.nslices,
+                       A.soff, A.swidth, A.sind, A.sval, x, b, y);
+    launch_check();
+    return;
+  }
   const unsigned nb = blocks_for(A.n * (int64_t)A.team, bs);
   switch (A.team) {
 #define CASE(TM) \
@@ -136,27 +183,42 @@ void csr_launch(const DCsr<T>& A, const T* x, const T* b, T* y, hipStream_t s) {
 // actual operand (setup-time autotuning; vectors may hold any values).
 template <typename T>
 void autotune_team(DCsr<T>& A, const T* x, T* y, hipStream_t s) {
-  if (A.n == 0 || A.nnz < 4096 || std::getenv("MAS_NO_AUTOTUNE")) return;
+  if (A.n == 0 || A.nnz < 4096 || std::getenv("MAS_NO_AUTOTUNE")) {
+    A.use_sell = A.nslices > 0;
+    return;
+  }
   hipEvent_t e0, e1;
   HIPCHECK(hipEventCreate(&e0));
   HIPCHECK(hipEventCreate(&e1));
-  float best = 1e30f;
-  int best_team = A.team;
-  for (int team : {2, 4, 8, 16, 32, 64}) {
-    A.team = team;
+  auto time_it = [&]() {
     csr_launch<T, 0>(A, x, nullptr, y, s);  // warm
     HIPCHECK(hipEventRecord(e0, s));
-    for (int rep = 0; rep < 3; ++rep) csr_launch<T, 0>(A, x, nullptr, y, s);
+    for (int rep = 0; rep < 10; ++rep) csr_launch<T, 0>(A, x, nullptr, y, s);
     HIPCHECK(hipEventRecord(e1, s));
     HIPCHECK(hipEventSynchronize(e1));
     float ms = 0.f;
     HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best) {
+    return ms;
+  };
+  const int heuristic = A.team;
+  A.use_sell = false;
+  float best = time_it();  // heuristic lanes per row
+  int best_team = heuristic;
+  for (int team : {2, 4, 8, 16, 32, 64}) {
+    if (team == heuristic) continue;
+    A.team = team;
+    const float ms = time_it();
+    if (ms < 0.95f * best) {  // change only for a clear gain
       best = ms;
       best_team = team;
     }
   }
   A.team = best_team;
+  if (A.nslices > 0) {
+    A.use_sell = true;
+    const float ms = time_it();
+    A.use_sell = ms < best;
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
 }
@@ -389,6 +451,10 @@ struct mas_handle {
   double *V = nullptr, *Z = nullptr, *w = nullptr, *partial = nullptr, *hdev = nullptr, *ydev = nullptr;
   double* hhost = nullptr;  // pinned
   int nblk_dot = 512;
+  hipStream_t gs = nullptr;     // internal stream: solves run here (graphs cannot capture the null stream)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  std::vector<hipGraphExec_t> iter_graph;  // one captured FGMRES inner iteration per Krylov index
+  bool use_graphs = true;
   int64_t* dir_idx = nullptr;
   int64_t ndir = 0;
   Timing tm;
@@ -843,6 +909,12 @@ void upload_impl(mas_handle* h, hipStream_t s) {
   h->hdev = h->arena.alloc<double>(m + 2);
   h->ydev = h->arena.alloc<double>(m + 1);
   HIPCHECK(hipHostMalloc((void**)&h->hhost, (m + 2) * sizeof(double), hipHostMallocDefault));
+  HIPCHECK(hipStreamCreateWithFlags(&h->gs, hipStreamNonBlocking));
+  HIPCHECK(hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming));
+  HIPCHECK(hipEventCreateWithFlags(&h->ev_out, hipEventDisableTiming));
+  h->iter_graph.assign(m, nullptr);
+  h->use_graphs = std::getenv("MAS_NO_GRAPHS") == nullptr;
+  HIPCHECK(hipStreamSynchronize(s));
   // the host plan is no longer needed except for export
   pl.patches.clear();
   pl.patches.shrink_to_fit();
@@ -852,12 +924,61 @@ void upload_impl(mas_handle* h, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // FGMRES (FP64)
 
-double dev_dot(mas_handle* h, const double* x, const double* y, int64_t n, hipStream_t s, double* out_dev,
-               bool take_sqrt) {
-  hipLaunchKernelGGL(k_dot_partial, dim3(h->nblk_dot), dim3(256), 0, s, n, x, y, h->partial);
+// *out = x . y (or ||x|| when take_sqrt and x == y), reduced on the device
+void dev_dot(mas_handle* h, const double* x, const double* y, int64_t n, hipStream_t s, double* out_dev,
+             bool take_sqrt) {
+  hipLaunchKernelGGL(k_mgs_step, dim3(h->nblk_dot), dim3(256), 0, s, n, const_cast<double*>(x), nullptr, nullptr,
+                     take_sqrt ? nullptr : y, h->partial, take_sqrt ? 1 : 0);
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, h->nblk_dot, h->partial, out_dev, take_sqrt ? 1 : 0);
   launch_check();
-  return 0.0;
+}
+
+// FGMRES inner iteration j: z_j = B v_j, w = K0 z_j, modified Gram-Schmidt
+// against v_0..v_j (fused steps), v_{j+1} = w / ||w||, H column -> pinned host.
+void inner_iteration(mas_handle* h, int j, hipStream_t s) {
+  const int64_t n = h->n0;
+  double* vj = h->V + (int64_t)j * n;
+  double* zj = h->Z + (int64_t)j * n;
+  h->cyc->apply(vj, zj, s);
+  double* w = h->w;
+  csr_launch<double, 0>(h->K0full, zj, nullptr, w, s);
+  for (int i = 0; i <= j + 1; ++i) {
+    const double* vprev = i > 0 ? h->V + (int64_t)(i - 1) * n : nullptr;
+    const double* hprev = i > 0 ? h->hdev + (i - 1) : nullptr;
+    const double* vnext = i <= j ? h->V + (int64_t)i * n : nullptr;
+    hipLaunchKernelGGL(k_mgs_step, dim3(h->nblk_dot), dim3(256), 0, s, n, w, vprev, hprev, vnext, h->partial,
+                       i <= j ? 0 : 1);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, h->nblk_dot, h->partial, h->hdev + i,
+                       i <= j ? 0 : 1);
+  }
+  hipLaunchKernelGGL(k_scale_inv_dev, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, h->hdev + j + 1, w,
+                     h->V + (int64_t)(j + 1) * n);
+  launch_check();
+  HIPCHECK(hipMemcpyAsync(h->hhost, h->hdev, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
+}
+
+void run_inner_iteration(mas_handle* h, int j, hipStream_t s) {
+  if (!h->use_graphs || h->tm.on) {
+    inner_iteration(h, j, s);
+    return;
+  }
+  if (!h->iter_graph[j]) {
+    hipGraph_t g = nullptr;
+    HIPCHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    try {
+      inner_iteration(h, j, s);
+    } catch (...) {
+      (void)hipStreamEndCapture(s, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    HIPCHECK(hipStreamEndCapture(s, &g));
+    hipGraphExec_t ex = nullptr;
+    HIPCHECK(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+    (void)hipGraphDestroy(g);
+    h->iter_graph[j] = ex;
+  }
+  HIPCHECK(hipGraphLaunch(h->iter_graph[j], s));
 }
 
 double host_scalar(mas_handle* h, const double* dev, hipStream_t s) {
@@ -870,12 +991,14 @@ int fgmres(mas_handle* h, const double* b, double* x, double rtol, int max_it, m
            hipStream_t s) {
   const int64_t n = h->n0;
   const int m = std::max(1, h->par.restart);
-  double* r = h->w;  // reuse: w is rebuilt every inner step
+  double* r = h->w;  // the residual lives in w between cycles
   dev_dot(h, b, b, n, s, h->hdev, true);
   const double bnorm = host_scalar(h, h->hdev, s);
-  HIPCHECK(hipMemsetAsync(x, 0, n * sizeof(double), s));
+  hipLaunchKernelGGL((k_fill<double>), dim3(blocks_for(n, 256)), dim3(256), 0, s, n, x, 0.0);
+  launch_check();
   std::vector<double> hist;
   if (!(bnorm > 0.0)) {
+    HIPCHECK(hipStreamSynchronize(s));
     if (info) *info = mas_solve_info{0, 1, 0.0, NAN};
     return std::isfinite(bnorm) ? MAS_OK : MAS_ENAN;
   }
@@ -885,7 +1008,6 @@ int fgmres(mas_handle* h, const double* b, double* x, double rtol, int max_it, m
   int it = 0;
   bool converged = false;
   std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1);
-  // r = b initially
   HIPCHECK(hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
   while (true) {
     std::fill(H.begin(), H.end(), 0.0);
@@ -895,21 +1017,7 @@ int fgmres(mas_handle* h, const double* b, double* x, double rtol, int max_it, m
     launch_check();
     int k = 0;
     for (int j = 0; j < m; ++j) {
-      double* vj = h->V + (int64_t)j * n;
-      double* zj = h->Z + (int64_t)j * n;
-      h->cyc->apply(vj, zj, s);
-      double* w = h->w;
-      csr_launch<double, 0>(h->K0full, zj, nullptr, w, s);
-      for (int i = 0; i <= j; ++i) {
-        dev_dot(h, w, h->V + (int64_t)i * n, n, s, h->hdev + i, false);
-        hipLaunchKernelGGL(k_axpy_neg_dev, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, h->hdev + i,
-                           h->V + (int64_t)i * n, w);
-      }
-      dev_dot(h, w, w, n, s, h->hdev + j + 1, true);
-      hipLaunchKernelGGL(k_scale_inv_dev, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, h->hdev + j + 1, w,
-                         h->V + (int64_t)(j + 1) * n);
-      launch_check();
-      HIPCHECK(hipMemcpyAsync(h->hhost, h->hdev, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
+      run_inner_iteration(h, j, s);
       HIPCHECK(hipStreamSynchronize(s));
       for (int i = 0; i <= j + 1; ++i) H[(size_t)i * m + j] = h->hhost[i];
       for (int i = 0; i < j; ++i) {
@@ -934,20 +1042,20 @@ int fgmres(mas_handle* h, const double* b, double* x, double rtol, int max_it, m
       }
       if (est <= target || it >= max_it) break;
     }
-    // y = H^-1 g (upper triangular)
+    // y = H^-1 g (upper triangular), x += Z y, true residual
     std::vector<double> y(k, 0.0);
     for (int i = k - 1; i >= 0; --i) {
       double t = g[i];
       for (int q = i + 1; q < k; ++q) t -= H[(size_t)i * m + q] * y[q];
       y[i] = t / H[(size_t)i * m + i];
     }
-    HIPCHECK(hipMemcpyAsync(h->ydev, y.data(), k * sizeof(double), hipMemcpyHostToDevice, s));
+    std::memcpy(h->hhost, y.data(), k * sizeof(double));
+    HIPCHECK(hipMemcpyAsync(h->ydev, h->hhost, k * sizeof(double), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_update_x, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, k, h->Z, h->ydev, x);
     launch_check();
     csr_launch<double, 1>(h->K0full, x, b, r, s);
     dev_dot(h, r, r, n, s, h->hdev, true);
     beta = host_scalar(h, h->hdev, s);
-    HIPCHECK(hipStreamSynchronize(s));  // y lives on the host stack
     if (!std::isfinite(beta)) {
       if (info) *info = mas_solve_info{it, 0, NAN, NAN};
       return MAS_ENAN;
@@ -962,9 +1070,7 @@ int fgmres(mas_handle* h, const double* b, double* x, double rtol, int max_it, m
   if (h->p_nullspace && h->pw) {
     const int64_t np0 = n - h->nu0;
     dev_dot(h, x + h->nu0, h->pw, np0, s, h->hdev, false);
-    double mean = host_scalar(h, h->hdev, s) / h->pw_sum;
-    std::vector<double> neg(1, -mean);
-    // x_p += -mean via axpby with a constant vector: use k_fill + k_axpby on scratch w
+    const double mean = host_scalar(h, h->hdev, s) / h->pw_sum;
     hipLaunchKernelGGL((k_fill<double>), dim3(blocks_for(np0, 256)), dim3(256), 0, s, np0, h->w, -mean);
     hipLaunchKernelGGL((k_axpby<double>), dim3(blocks_for(np0, 256)), dim3(256), 0, s, np0, 1.0, h->w, 1.0,
                        x + h->nu0);
@@ -1105,8 +1211,13 @@ int mas_solve(mas_handle* h, const double* b, double* x, int32_t nrhs, double rt
     return MAS_EINVAL;
   }
   try {
-    hipStream_t s = (hipStream_t)stream;
+    hipStream_t us = (hipStream_t)stream;
+    hipStream_t s = h->gs;
+    HIPCHECK(hipEventRecord(h->ev_in, us));
+    HIPCHECK(hipStreamWaitEvent(s, h->ev_in, 0));
     int rc = fgmres(h, b, x, rtol, max_it, info, s);
+    HIPCHECK(hipEventRecord(h->ev_out, s));
+    HIPCHECK(hipStreamWaitEvent(us, h->ev_out, 0));
     if (h->tm.on) {
       HIPCHECK(hipStreamSynchronize(s));
       for (auto& pr : h->tm.vanka) {
@@ -1165,6 +1276,11 @@ int mas_get_timing(const mas_handle* h, double* out, int32_t n) {
 int mas_destroy(mas_handle* h) {
   if (!h) return MAS_OK;
   if (h->on_device) (void)hipDeviceSynchronize();
+  for (hipGraphExec_t g : h->iter_graph)
+    if (g) (void)hipGraphExecDestroy(g);
+  if (h->gs) (void)hipStreamDestroy(h->gs);
+  if (h->ev_in) (void)hipEventDestroy(h->ev_in);
+  if (h->ev_out) (void)hipEventDestroy(h->ev_out);
   if (h->hhost) (void)hipHostFree(h->hhost);
   delete h;
   return MAS_OK;
