@@ -21,6 +21,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+WORKLOADS = {
+    "th2d_256": "2D Taylor-Hood P2/P1, 256x256 squares split into triangles, interior vertices jittered "
+                "U(-0.2h,0.2h), lid-driven cavity + Gaussian forcing",
+    "th3d_32": "3D Taylor-Hood P2/P1, 32^3 cubes split into 6 tetrahedra, smooth random forcing, "
+               "homogeneous Dirichlet",
+    "th2d_16": "2D Taylor-Hood P2/P1, 16x16, manufactured solution",
+}
 
 
 def parse():
@@ -145,8 +152,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if prec == mas.MAS_FP64 else "f32 cycle / f64 FGMRES",
         "data": "synthetic",
-        "config": {"workload": f"{a.config}: 2D Taylor-Hood P2/P1 256x256 jittered lid-driven cavity, "
-                               f"{a.relax} DC-all V(1,1), FGMRES(20) rtol {a.rtol:g}",
+        "config": {"workload": f"{a.config}: {WORKLOADS.get(a.config, a.config)}, {a.relax} DC-all, "
+                               f"FGMRES(20) rtol {a.rtol:g}",
                    "n0": prob.n0, "levels": info["n"], "relax": a.relax, "cycle_precision": a.precision},
         "iters": iters[-1],
         "true_relres": relres,

@@ -153,15 +153,43 @@ __global__ void __launch_bounds__(WAVE) k_vanka_apply(int64_t np, const int64_t*
   const int4 d = dims[p];
   const int nv = d.x + d.y + d.z, ns = d.w, m = nv + ns;
   const int64_t o = off[p];
-  for (int k = lane; k < m; k += WAVE) sb[k] = r[dofs[o + k]];
+  // gather: all index loads first, then all value loads (several in flight)
+  for (int k0 = 0; k0 < m; k0 += 4 * WAVE) {
+    int idx[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + u * WAVE + lane;
+      idx[u] = k < m ? dofs[o + k] : 0;
+    }
+    T v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = (k0 + u * WAVE + lane < m) ? r[idx[u]] : (T)0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (k0 + u * WAVE + lane < m) sb[k0 + u * WAVE + lane] = v[u];
+  }
   // record length from the shape (foff holds per-patch base offsets only)
   const int64_t f0 = foff[p];
   const int64_t nf = (int64_t)d.x * (d.x + 1) / 2 + (int64_t)d.y * (d.y + 1) / 2 + (int64_t)d.z * (d.z + 1) / 2 +
                      (int64_t)nv * ns + (int64_t)ns * (ns + 1) / 2;
   const T* sf;
   if (STAGE) {
+    // stage the record with 16 independent loads in flight per lane
     T* st = sy + max_m;
-    for (int64_t k = lane; k < nf; k += WAVE) st[k] = fac[f0 + k];
+    constexpr int U = 16;
+    for (int64_t k0 = 0; k0 < nf; k0 += U * WAVE) {
+      T v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t k = k0 + u * WAVE + lane;
+        v[u] = k < nf ? fac[f0 + k] : (T)0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t k = k0 + u * WAVE + lane;
+        if (k < nf) st[k] = v[u];
+      }
+    }
     sf = st;
   } else {
     sf = fac + f0;  // record too large for LDS: read it from memory
@@ -208,9 +236,11 @@ __global__ void __launch_bounds__(WAVE) k_vanka_apply(int64_t np, const int64_t*
 }
 
 // additive Vanka for a bucket of P patches of one fixed shape: one thread per
-// patch, DoF lists and factor records interleaved across the bucket (element q
-// of patch p at q * Ppad + p), so every load of a wavefront is one contiguous
-// 64-element segment.  Uhat and S^-1 are applied first, then the packed A^-1
+// patch, DoF lists, factor records and outputs interleaved across the whole
+// bucket (element q of patch p at q * Ppad + p).  Every load of a wavefront is
+// one contiguous 64-element segment, and since the wavefronts advance through q
+// at similar rates, the accesses in flight at any time cover a few contiguous
+// regions (a per-wavefront blocked layout measured 3x slower).  Uhat and S^-1 are applied first, then the packed A^-1
 // blocks are streamed: x_u = Uhat y_p + A^-1 b_u.
 template <typename T, int N0, int N1, int N2, int NS>
 __global__ void __launch_bounds__(256) k_vanka_tpp(int64_t P, int64_t Ppad, const int* __restrict__ dofs,
@@ -579,16 +609,36 @@ __global__ void __launch_bounds__(256) k_reduce_final(int nb, const double* __re
   }
 }
 
-// One modified Gram-Schmidt step, fused: w -= (*hprev) vprev (when vprev is
-// given), then partial[b] = block b's share of w . vnext (mode 0) or w . w
-// (mode 1).  k_reduce_final adds the partials in block order.  (A last-block
-// reduction inside this kernel would need a device-scope fence per block,
-// which writes back the non-coherent per-XCD L2 caches and costs far more.)
+// Sum of the nb partials of the previous reduction, in block order, computed by
+// every calling block (identical result everywhere).  (A last-block reduction
+// would need a device-scope fence per block, which writes back the
+// non-coherent per-XCD L2 caches and costs far more.)
+__device__ __forceinline__ double sum_partials(int nb, const double* __restrict__ partial) {
+  __shared__ double red[4];
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) v += partial[b];
+  v = wave_sum(v);
+  if ((threadIdx.x & (WAVE - 1)) == 0) red[threadIdx.x / WAVE] = v;
+  __syncthreads();
+  const double t = red[0] + red[1] + red[2] + red[3];
+  __syncthreads();
+  return t;
+}
+
+// One modified Gram-Schmidt step: when prev_partial is given, a = sum of the
+// previous step's partials (= h of that step, stored by block 0 into *hprev) and
+// w -= a vprev; then partial_out[b] = block b's share of w . vnext (mode 0) or
+// w . w (mode 1).  Two partial buffers alternate between consecutive steps.
 __global__ void __launch_bounds__(256) k_mgs_step(int64_t n, double* __restrict__ w, const double* __restrict__ vprev,
-                                                 const double* __restrict__ hprev, const double* __restrict__ vnext,
-                                                 double* __restrict__ partial, int mode) {
+                                                 double* __restrict__ hprev, const double* __restrict__ prev_partial,
+                                                 const double* __restrict__ vnext, double* __restrict__ partial_out,
+                                                 int mode) {
   __shared__ double sh[4];
-  const double a = vprev ? *hprev : 0.0;
+  double a = 0.0;
+  if (prev_partial) {
+    a = sum_partials(gridDim.x, prev_partial);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *hprev = a;
+  }
   double s = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     double wi = w[i];
@@ -601,7 +651,17 @@ __global__ void __launch_bounds__(256) k_mgs_step(int64_t n, double* __restrict_
   s = wave_sum(s);
   if ((threadIdx.x & (WAVE - 1)) == 0) sh[threadIdx.x / WAVE] = s;
   __syncthreads();
-  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+  if (threadIdx.x == 0) partial_out[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// v = w / sqrt(sum of partials); block 0 stores the norm into *hout
+__global__ void __launch_bounds__(256) k_normalize(int64_t n, const double* __restrict__ partial, int nb,
+                                                  double* __restrict__ hout, const double* __restrict__ w,
+                                                  double* __restrict__ v) {
+  const double nrm = sqrt(sum_partials(nb, partial));
+  if (blockIdx.x == 0 && threadIdx.x == 0) *hout = nrm;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    v[i] = nrm != 0.0 ? w[i] / nrm : 0.0;
 }
 
 // y -= (*h) x

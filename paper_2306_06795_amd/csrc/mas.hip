@@ -556,6 +556,7 @@ void build_patches(DevArena& ar, Level<T>& L, const PatchSet& ps, const DCsr<dou
     const int64_t F = ps.foff[groups[b][0] + 1] - ps.foff[groups[b][0]];
     fb.fbase = fcur;
     fb.ybase = ycur;
+    // interleaved across the bucket: element q of patch i at q * Ppad + i
     std::vector<int32_t> il((size_t)M * fb.Ppad, 0);
     for (int64_t i = 0; i < fb.P; ++i, ++pnew) {
       const int64_t p = groups[b][i];
@@ -905,7 +906,7 @@ void upload_impl(mas_handle* h, hipStream_t s) {
   h->V = h->arena.alloc<double>((size_t)(m + 1) * n0);
   h->Z = h->arena.alloc<double>((size_t)m * n0);
   h->w = h->arena.alloc<double>(n0);
-  h->partial = h->arena.alloc<double>(h->nblk_dot);
+  h->partial = h->arena.alloc<double>(2 * h->nblk_dot);
   h->hdev = h->arena.alloc<double>(m + 2);
   h->ydev = h->arena.alloc<double>(m + 1);
   HIPCHECK(hipHostMalloc((void**)&h->hhost, (m + 2) * sizeof(double), hipHostMallocDefault));
@@ -928,13 +929,14 @@ void upload_impl(mas_handle* h, hipStream_t s) {
 void dev_dot(mas_handle* h, const double* x, const double* y, int64_t n, hipStream_t s, double* out_dev,
              bool take_sqrt) {
   hipLaunchKernelGGL(k_mgs_step, dim3(h->nblk_dot), dim3(256), 0, s, n, const_cast<double*>(x), nullptr, nullptr,
-                     take_sqrt ? nullptr : y, h->partial, take_sqrt ? 1 : 0);
+                     nullptr, take_sqrt ? nullptr : y, h->partial, take_sqrt ? 1 : 0);
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, h->nblk_dot, h->partial, out_dev, take_sqrt ? 1 : 0);
   launch_check();
 }
 
 // FGMRES inner iteration j: z_j = B v_j, w = K0 z_j, modified Gram-Schmidt
-// against v_0..v_j (fused steps), v_{j+1} = w / ||w||, H column -> pinned host.
+// against v_0..v_j (one kernel per step), v_{j+1} = w / ||w||, H column ->
+// pinned host memory.
 void inner_iteration(mas_handle* h, int j, hipStream_t s) {
   const int64_t n = h->n0;
   double* vj = h->V + (int64_t)j * n;
@@ -942,17 +944,17 @@ void inner_iteration(mas_handle* h, int j, hipStream_t s) {
   h->cyc->apply(vj, zj, s);
   double* w = h->w;
   csr_launch<double, 0>(h->K0full, zj, nullptr, w, s);
+  double* part[2] = {h->partial, h->partial + h->nblk_dot};
   for (int i = 0; i <= j + 1; ++i) {
     const double* vprev = i > 0 ? h->V + (int64_t)(i - 1) * n : nullptr;
-    const double* hprev = i > 0 ? h->hdev + (i - 1) : nullptr;
+    double* hprev = i > 0 ? h->hdev + (i - 1) : nullptr;
+    const double* pprev = i > 0 ? part[(i - 1) & 1] : nullptr;
     const double* vnext = i <= j ? h->V + (int64_t)i * n : nullptr;
-    hipLaunchKernelGGL(k_mgs_step, dim3(h->nblk_dot), dim3(256), 0, s, n, w, vprev, hprev, vnext, h->partial,
-                       i <= j ? 0 : 1);
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, h->nblk_dot, h->partial, h->hdev + i,
-                       i <= j ? 0 : 1);
+    hipLaunchKernelGGL(k_mgs_step, dim3(h->nblk_dot), dim3(256), 0, s, n, w, vprev, hprev, pprev, vnext,
+                       part[i & 1], i <= j ? 0 : 1);
   }
-  hipLaunchKernelGGL(k_scale_inv_dev, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, h->hdev + j + 1, w,
-                     h->V + (int64_t)(j + 1) * n);
+  hipLaunchKernelGGL(k_normalize, dim3(h->nblk_dot), dim3(256), 0, s, n, part[(j + 1) & 1], h->nblk_dot,
+                     h->hdev + j + 1, w, h->V + (int64_t)(j + 1) * n);
   launch_check();
   HIPCHECK(hipMemcpyAsync(h->hhost, h->hdev, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
 }
