@@ -160,9 +160,12 @@ int mas_get_info(const mas_handle* h, mas_hier_info* out);
 int mas_export_level(const mas_handle* h, int32_t level, int64_t* nrows, int64_t* nnz,
                      int64_t* indptr, int32_t* indices, double* data);
 
-/* Average device time (ms) of the last mas_solve's kernels, by kind:
- * out[0] whole preconditioner applications, out[1] Vanka patch kernels,
- * out[2] SpMV kernels.  Filled only when timing was enabled. */
+/* Event timing of the cycle's kernels during mas_solve (for measurement; it
+ * disables graph replay while on).  mas_get_timing fills up to n of:
+ * out[0] patch-solve time (ms, summed), out[1] patch-solve launches,
+ * out[2] their algorithmic bytes (factor records, DoF lists, patch outputs, one
+ * read of the level vector), out[3] sparse-product time (ms), out[4] launches,
+ * out[5] their algorithmic bytes (values, column and row indices, vectors). */
 int mas_set_timing(mas_handle* h, int32_t enable);
 int mas_get_timing(const mas_handle* h, double* out, int32_t n);
 

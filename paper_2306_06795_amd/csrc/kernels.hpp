@@ -33,7 +33,7 @@ __device__ __forceinline__ T wave_sum(T v) {
 
 // ---------------------------------------------------------------------------
 // CSR products.  TEAM lanes per row (power of two <= 64).
-// MODE 0: y = A x   MODE 1: y = b - A x   MODE 2: y += A x
+// MODE 0: y = A x   MODE 1: y = b - A x   MODE 2: y += A x   MODE 3: y -= A x
 template <typename T, int TEAM, int MODE>
 __global__ void __launch_bounds__(256) k_csr(int n, const int* __restrict__ ptr, const int* __restrict__ ind,
                                              const T* __restrict__ val, const T* __restrict__ x,
@@ -51,7 +51,8 @@ __global__ void __launch_bounds__(256) k_csr(int n, const int* __restrict__ ptr,
   if (row < n && lane == 0) {
     if (MODE == 0) y[row] = s;
     else if (MODE == 1) y[row] = b[row] - s;
-    else y[row] += s;
+    else if (MODE == 2) y[row] += s;
+    else y[row] -= s;
   }
 }
 
@@ -86,7 +87,8 @@ __global__ void __launch_bounds__(256) k_sell(int n, int64_t nslices, const int6
   if (row < n) {
     if (MODE == 0) y[row] = s;
     else if (MODE == 1) y[row] = b[row] - s;
-    else y[row] += s;
+    else if (MODE == 2) y[row] += s;
+    else y[row] -= s;
   }
 }
 
@@ -132,6 +134,55 @@ template <typename T>
 __global__ void k_axpby(int64_t n, T a, const T* __restrict__ x, T b, T* __restrict__ y) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) y[k] = a * x[k] + b * y[k];
+}
+
+// ---------------------------------------------------------------------------
+// Chebyshev semi-iteration and DLSC helpers (Algorithm 2, Table 3)
+
+// d = r / theta, res = r, y = d
+template <typename T>
+__global__ void k_cheb_init(int64_t n, const T* __restrict__ r, T inv_theta, T* __restrict__ d, T* __restrict__ res,
+                            T* __restrict__ y) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const T ri = r[i];
+    const T di = ri * inv_theta;
+    d[i] = di;
+    res[i] = ri;
+    y[i] = di;
+  }
+}
+
+// d = a d + c res; y += d
+template <typename T>
+__global__ void k_cheb_update(int64_t n, T a, T c, const T* __restrict__ res, T* __restrict__ d, T* __restrict__ y) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const T di = a * d[i] + c * res[i];
+    d[i] = di;
+    y[i] += di;
+  }
+}
+
+// x[i] *= m[i]
+template <typename T>
+__global__ void k_mul(int64_t n, const T* __restrict__ m, T* __restrict__ x) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] *= m[i];
+}
+
+// z = x + y
+template <typename T>
+__global__ void k_add(int64_t n, const T* __restrict__ x, const T* __restrict__ y, T* __restrict__ z) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) z[i] = x[i] + y[i];
+}
+
+// x += y + z
+template <typename T>
+__global__ void k_add3(int64_t n, T* __restrict__ x, const T* __restrict__ y, const T* __restrict__ z) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] += y[i] + z[i];
 }
 
 // ---------------------------------------------------------------------------

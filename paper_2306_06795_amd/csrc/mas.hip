@@ -238,6 +238,7 @@ struct FastBucket {
 template <typename T>
 struct DPatches {
   int64_t np = 0, ndofs = 0, nfac = 0, ny = 0;
+  int64_t nfac_alg = 0;  // factor entries actually read (bucket padding excluded)
   // all patches (fast buckets first), used by the factorisation
   int64_t* off = nullptr;
   int4* dims = nullptr;
@@ -260,11 +261,24 @@ struct DPatches {
 };
 
 template <typename T>
+struct DDlsc {
+  bool on = false;
+  DCsr<T> A, B, Bt, S;
+  T* minv = nullptr;
+  double lamA = 0.0, lamS = 0.0;
+  int64_t nv = 0, np = 0;
+  T *ru = nullptr, *vs = nullptr, *tmp = nullptr, *t1 = nullptr, *t2 = nullptr;  // velocity-sized
+  T *rp = nullptr, *q = nullptr, *dp = nullptr;                                 // pressure-sized
+  T *cd = nullptr, *cres = nullptr;                                             // Chebyshev work (max size)
+};
+
+template <typename T>
 struct Level {
   int64_t n = 0, nvel = 0;
   DCsr<T> K;
   DCsr<T> P, R;  // P: this level <- next level, R = P^T
   DPatches<T> pt;
+  DDlsc<T> dl;
   bool relax = false;
   T *x = nullptr, *b = nullptr, *r = nullptr;
 };
@@ -274,11 +288,42 @@ struct CycleBase {
   virtual void apply(const double* r, double* z, hipStream_t s) = 0;
 };
 
+// Optional event timing of the two kernel families of the cycle, with the
+// algorithmic bytes each timed launch has to move.
 struct Timing {
+  struct Rec {
+    hipEvent_t a, b;
+    double bytes;
+  };
   bool on = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> vanka, spmv;
-  double vanka_ms = 0, spmv_ms = 0, apply_ms = 0;
-  int64_t vanka_launches = 0, applies = 0;
+  std::vector<Rec> vanka, spmv;
+  double vanka_ms = 0, spmv_ms = 0, vanka_bytes = 0, spmv_bytes = 0;
+  int64_t vanka_launches = 0, spmv_launches = 0;
+  void begin(hipEvent_t& e0, hipEvent_t& e1, hipStream_t s) {
+    HIPCHECK(hipEventCreate(&e0));
+    HIPCHECK(hipEventCreate(&e1));
+    HIPCHECK(hipEventRecord(e0, s));
+  }
+  void collect() {
+    for (auto* v : {&vanka, &spmv}) {
+      for (auto& r : *v) {
+        float ms = 0.f;
+        HIPCHECK(hipEventElapsedTime(&ms, r.a, r.b));
+        if (v == &vanka) {
+          vanka_ms += ms;
+          vanka_bytes += r.bytes;
+          vanka_launches++;
+        } else {
+          spmv_ms += ms;
+          spmv_bytes += r.bytes;
+          spmv_launches++;
+        }
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+      }
+      v->clear();
+    }
+  }
 };
 
 template <typename T>
@@ -290,7 +335,82 @@ struct Cycle : CycleBase {
   int64_t* dir0 = nullptr;
   int64_t nfree0 = 0, ndir0 = 0;
   mas_params par{};
+  int dim = 2;
   Timing* tm = nullptr;
+
+  // sparse product, timed (with its algorithmic bytes) when timing is on
+  template <int MODE>
+  void spmv(const DCsr<T>& A, const T* x, const T* b, T* y, hipStream_t s) {
+    hipEvent_t e0{}, e1{};
+    const bool t = tm && tm->on;
+    if (t) tm->begin(e0, e1, s);
+    csr_launch<T, MODE>(A, x, b, y, s);
+    if (t) {
+      HIPCHECK(hipEventRecord(e1, s));
+      const double sz = sizeof(T);
+      const double vec = A.m * sz + A.n * sz * (MODE == 0 ? 1.0 : 2.0);
+      tm->spmv.push_back({e0, e1, A.nnz * (sz + 4.0) + (A.n + 1) * 4.0 + vec});
+    }
+  }
+
+  // y = X^{-1} r approximated by `deg` Chebyshev steps on [0.5^dim lam, 1.1 lam] from y = 0
+  void chebyshev(DCsr<T>& X, const T* r, T* y, double lam, int deg, DDlsc<T>& D, hipStream_t s) {
+    const int64_t n = X.n;
+    const double lo = std::pow(0.5, dim) * lam, hi = 1.1 * lam;
+    const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    const unsigned nb = blocks_for(n, 256);
+    hipLaunchKernelGGL((k_cheb_init<T>), dim3(nb), dim3(256), 0, s, n, r, (T)(1.0 / theta), D.cd, D.cres, y);
+    launch_check();
+    for (int k = 0; k + 1 < deg; ++k) {
+      spmv<3>(X, D.cd, nullptr, D.cres, s);
+      const double rho_new = 1.0 / (2.0 * sigma - rho);
+      hipLaunchKernelGGL((k_cheb_update<T>), dim3(nb), dim3(256), 0, s, n, (T)(rho_new * rho),
+                         (T)(2.0 * rho_new / delta), D.cres, D.cd, y);
+      launch_check();
+      rho = rho_new;
+    }
+  }
+
+  // one DLSC sweep (Algorithm 2) on level L: x = (u, p), b = (f, g)
+  void dlsc_sweep(Level<T>& L, hipStream_t s) {
+    DDlsc<T>& D = L.dl;
+    const int64_t nv = D.nv, np = D.np;
+    T* u = L.x;
+    T* p = L.x + nv;
+    const T* f = L.b;
+    const T* g = L.b + nv;
+    const unsigned bv = blocks_for(nv, 256), bp = blocks_for(np, 256);
+    spmv<1>(D.A, u, f, D.ru, s);  // ru = f - A u - B^T p
+    spmv<3>(D.Bt, p, nullptr, D.ru, s);
+    chebyshev(D.A, D.ru, D.vs, D.lamA, par.cheb_deg[0], D, s);  // momentum
+    hipLaunchKernelGGL((k_add<T>), dim3(bv), dim3(256), 0, s, nv, u, D.vs, D.tmp);
+    spmv<1>(D.B, D.tmp, g, D.rp, s);  // rp = g - B (u + v*)
+    chebyshev(D.S, D.rp, D.q, D.lamS, par.cheb_deg[1], D, s);  // continuity
+    spmv<0>(D.Bt, D.q, nullptr, D.t1, s);  // t1 = M^-1 B^T q
+    hipLaunchKernelGGL((k_mul<T>), dim3(bv), dim3(256), 0, s, nv, D.minv, D.t1);
+    spmv<0>(D.A, D.t1, nullptr, D.t2, s);  // t2 = M^-1 A M^-1 B^T q
+    hipLaunchKernelGGL((k_mul<T>), dim3(bv), dim3(256), 0, s, nv, D.minv, D.t2);
+    spmv<0>(D.B, D.t2, nullptr, D.rp, s);  // rp = B t2; the right-hand side is -rp
+    hipLaunchKernelGGL((k_axpby<T>), dim3(bp), dim3(256), 0, s, np, (T)0, D.rp, (T)-1, D.rp);
+    chebyshev(D.S, D.rp, D.dp, D.lamS, par.cheb_deg[2], D, s);  // pressure correction
+    hipLaunchKernelGGL((k_add3<T>), dim3(bv), dim3(256), 0, s, nv, u, D.vs, D.t1);  // u += v* + M^-1 B^T q
+    hipLaunchKernelGGL((k_axpby<T>), dim3(bp), dim3(256), 0, s, np, (T)1, D.dp, (T)1, p);  // p += dp
+    launch_check();
+  }
+
+  // `sweeps` relaxation sweeps on L (Vanka or DLSC); x_zero: L.x is to be taken as 0
+  void relax_level(Level<T>& L, int sweeps, T omega, bool x_zero, hipStream_t s) {
+    if (L.dl.on) {
+      if (x_zero) {
+        hipLaunchKernelGGL((k_fill<T>), dim3(blocks_for(L.n, 256)), dim3(256), 0, s, L.n, L.x, (T)0);
+        launch_check();
+      }
+      for (int k = 0; k < sweeps; ++k) dlsc_sweep(L, s);
+      return;
+    }
+    vanka_sweeps(L, sweeps, omega, x_zero, s);
+  }
 
   void patch_solve(Level<T>& L, const T* rin, hipStream_t s) {
     DPatches<T>& pt = L.pt;
@@ -327,19 +447,18 @@ struct Cycle : CycleBase {
       if (k == 0 && x_zero) {
         rin = L.b;
       } else {
-        csr_launch<T, 1>(L.K, L.x, L.b, L.r, s);
+        spmv<1>(L.K, L.x, L.b, L.r, s);
         rin = L.r;
       }
       hipEvent_t e0{}, e1{};
-      if (tm && tm->on) {
-        HIPCHECK(hipEventCreate(&e0));
-        HIPCHECK(hipEventCreate(&e1));
-        HIPCHECK(hipEventRecord(e0, s));
-      }
+      if (tm && tm->on) tm->begin(e0, e1, s);
       patch_solve(L, rin, s);
       if (tm && tm->on) {
         HIPCHECK(hipEventRecord(e1, s));
-        tm->vanka.push_back({e0, e1});
+        const double sz = sizeof(T);
+        // factor records + DoF lists + patch outputs + one read of the level vector
+        const double bytes = L.pt.nfac_alg * sz + L.pt.ndofs * (4.0 + sz) + L.n * sz;
+        tm->vanka.push_back({e0, e1, bytes});
       }
       const int acc = (k == 0 && x_zero) ? 0 : 1;
       if (L.pt.ell)
@@ -364,23 +483,23 @@ struct Cycle : CycleBase {
     const T om = (T)par.omega;
     bool x_zero = true;
     if (L.relax && par.nu1 > 0) {
-      vanka_sweeps(L, par.nu1, om, true, s);
+      relax_level(L, par.nu1, om, true, s);
       x_zero = false;
     }
     Level<T>& C = lev[l + 1];
     if (x_zero) {
-      csr_launch<T, 0>(L.R, L.b, nullptr, C.b, s);
+      spmv<0>(L.R, L.b, nullptr, C.b, s);
     } else {
-      csr_launch<T, 1>(L.K, L.x, L.b, L.r, s);
-      csr_launch<T, 0>(L.R, L.r, nullptr, C.b, s);
+      spmv<1>(L.K, L.x, L.b, L.r, s);
+      spmv<0>(L.R, L.r, nullptr, C.b, s);
     }
     vcycle(l + 1, s);
     if (x_zero) {
-      csr_launch<T, 0>(L.P, C.x, nullptr, L.x, s);
+      spmv<0>(L.P, C.x, nullptr, L.x, s);
     } else {
-      csr_launch<T, 2>(L.P, C.x, nullptr, L.x, s);
+      spmv<2>(L.P, C.x, nullptr, L.x, s);
     }
-    if (L.relax && par.nu2 > 0) vanka_sweeps(L, par.nu2, om, false, s);
+    if (L.relax && par.nu2 > 0) relax_level(L, par.nu2, om, false, s);
   }
 
   void apply(const double* r, double* z, hipStream_t s) override {
@@ -390,12 +509,12 @@ struct Cycle : CycleBase {
     launch_check();
     bool x_zero = true;
     if (L0.relax && par.nu1 > 0) {
-      vanka_sweeps(L0, par.nu1, (T)par.omega0, true, s);
+      relax_level(L0, par.nu1, (T)par.omega0, true, s);
       x_zero = false;
     }
     const T* r0 = L0.b;
     if (!x_zero) {
-      csr_launch<T, 1>(L0.K, L0.x, L0.b, L0.r, s);
+      spmv<1>(L0.K, L0.x, L0.b, L0.r, s);
       r0 = L0.r;
     }
     // eta R0 (Taylor-Hood: injection, eq. (3.2))
@@ -407,7 +526,7 @@ struct Cycle : CycleBase {
     hipLaunchKernelGGL((k_axpby<T>), dim3(blocks_for(L0.n, 256)), dim3(256), 0, s, L0.n, (T)1, L1.x,
                        x_zero ? (T)0 : (T)1, L0.x);
     launch_check();
-    if (L0.relax && par.nu2 > 0) vanka_sweeps(L0, par.nu2, (T)par.omega0, false, s);
+    if (L0.relax && par.nu2 > 0) relax_level(L0, par.nu2, (T)par.omega0, false, s);
     hipLaunchKernelGGL((k_scatter<double, T>), dim3(blocks_for(nfree0, 256)), dim3(256), 0, s, nfree0, free0, L0.x, z);
     launch_check();
     if (ndir0) {  // Dirichlet rows are identity rows: z_D = r_D
@@ -422,8 +541,15 @@ struct Cycle : CycleBase {
 // ---------------------------------------------------------------------------
 // the handle
 
+struct HostDlsc {
+  Csr A, B, Bt, S;            // velocity block, divergence block, its transpose, B M^-1 B^T
+  std::vector<double> minv;   // M_u^-1 (diagonal)
+  double lamA = 0.0, lamS = 0.0;
+};
+
 struct HostPlan {
   std::vector<Csr> Ks, Ps;                 // free level operators, P_l (level l <- l+1)
+  std::vector<HostDlsc> dlsc;              // per relaxed level when the relaxation is DLSC
   std::vector<std::vector<int8_t>> fields;
   std::vector<PatchSet> patches;
   std::vector<bool> relax;
@@ -592,6 +718,7 @@ void build_patches(DevArena& ar, Level<T>& L, const PatchSet& ps, const DCsr<dou
     ++pnew;
   }
   d.nfac = fcur;
+  d.nfac_alg = ps.foff.back();
   d.ny = ycur;
   // ---- DoF -> output positions, in patch order (deterministic sums)
   const int64_t n = L.n;
@@ -664,12 +791,14 @@ void build_patches(DevArena& ar, Level<T>& L, const PatchSet& ps, const DCsr<dou
 template <typename T>
 std::unique_ptr<Cycle<T>> build_cycle(mas_handle* h, const std::vector<Csr>& Ks, const std::vector<Csr>& Ps,
                                       const std::vector<std::vector<int8_t>>& fields,
-                                      const std::vector<PatchSet>& patches, const std::vector<bool>& relax,
+                                      const std::vector<PatchSet>& patches, const std::vector<HostDlsc>& dlsc,
+                                      const std::vector<bool>& relax,
                                       const Csr& Kc_bordered, const std::vector<int64_t>& free0,
                                       const std::vector<int64_t>& dir0, hipStream_t s) {
   DevArena& ar = h->arena;
   auto cyc = std::make_unique<Cycle<T>>();
   cyc->par = h->par;
+  cyc->dim = h->dim;
   cyc->tm = &h->tm;
   const size_t nl = Ks.size();
   cyc->lev.resize(nl);
@@ -688,11 +817,29 @@ std::unique_ptr<Cycle<T>> build_cycle(mas_handle* h, const std::vector<Csr>& Ks,
         L.P = upload_csr<T>(ar, Ps[l], s);
         L.R = upload_csr<T>(ar, transpose(Ps[l]), s);
       }
-      if (L.relax) {
+      if (L.relax && !patches[l].off.empty()) {
         DCsr<double> K64;
         if constexpr (std::is_same<T, double>::value) K64 = L.K;
         else K64 = upload_csr<double>(ar, Ks[l], s);
         build_patches<T>(ar, L, patches[l], K64, (int)l, s);
+      }
+      if (L.relax && dlsc[l].A.nr > 0) {
+        const HostDlsc& H = dlsc[l];
+        DDlsc<T>& D = L.dl;
+        D.on = true;
+        D.nv = H.A.nr;
+        D.np = H.B.nr;
+        D.A = upload_csr<T>(ar, H.A, s);
+        D.B = upload_csr<T>(ar, H.B, s);
+        D.Bt = upload_csr<T>(ar, H.Bt, s);
+        D.S = upload_csr<T>(ar, H.S, s);
+        D.minv = ar.upload<T>(H.minv, s);
+        D.lamA = H.lamA;
+        D.lamS = H.lamS;
+        for (T** v : {&D.ru, &D.vs, &D.tmp, &D.t1, &D.t2}) *v = ar.alloc<T>(D.nv);
+        for (T** v : {&D.rp, &D.q, &D.dp}) *v = ar.alloc<T>(D.np);
+        D.cd = ar.alloc<T>(std::max(D.nv, D.np));
+        D.cres = ar.alloc<T>(std::max(D.nv, D.np));
       }
     }
   }
@@ -700,6 +847,12 @@ std::unique_ptr<Cycle<T>> build_cycle(mas_handle* h, const std::vector<Csr>& Ks,
   for (size_t l = 0; l + 1 < nl; ++l) {
     Level<T>& L = cyc->lev[l];
     autotune_team<T>(L.K, L.x, L.r, s);
+    if (L.dl.on) {
+      autotune_team<T>(L.dl.A, L.dl.ru, L.dl.vs, s);
+      autotune_team<T>(L.dl.S, L.dl.rp, L.dl.q, s);
+      autotune_team<T>(L.dl.B, L.dl.ru, L.dl.rp, s);
+      autotune_team<T>(L.dl.Bt, L.dl.rp, L.dl.ru, s);
+    }
     if (l >= 1) {
       Level<T>& C = cyc->lev[l + 1];
       autotune_team<T>(L.R, L.r, C.b, s);
@@ -729,7 +882,9 @@ void analyze_impl(mas_handle* h, const mas_problem* pr) {
   h->dim = d;
   h->disc = pr->disc;
   const mas_params& par = h->par;
-  if (par.relax != MAS_RELAX_VANKA) throw MasError(MAS_EINVAL, "only Vanka relaxation is supported by this build");
+  if (par.relax != MAS_RELAX_VANKA && par.relax != MAS_RELAX_DLSC) throw MasError(MAS_EINVAL, "unknown relaxation");
+  for (int q = 0; q < 3; ++q)
+    if (par.relax == MAS_RELAX_DLSC && par.cheb_deg[q] < 1) throw MasError(MAS_EINVAL, "Chebyshev degrees must be >= 1");
   Csr K0 = get_csr(pr->K0, "K0");
   Csr K1 = get_csr(pr->K1, "K1");
   Csr Ap = get_csr(pr->Ap, "Ap");
@@ -808,8 +963,37 @@ void analyze_impl(mas_handle* h, const mas_problem* pr) {
   if (par.schedule == MAS_DC_SKIP0) relax[0] = false;
   if (par.schedule == MAS_DC_SKIP1 && nl == 2) relax[1] = false;
   std::vector<PatchSet> patches(nl);
-  for (size_t l = 0; l + 1 < nl; ++l)
-    if (relax[l]) patches[l] = patches_single_seed(Ks[l], fields[l], d);
+  std::vector<HostDlsc> dl(nl);
+  for (size_t l = 0; l + 1 < nl; ++l) {
+    if (!relax[l]) continue;
+    if (par.relax == MAS_RELAX_VANKA) {
+      patches[l] = patches_single_seed(Ks[l], fields[l], d);
+      continue;
+    }
+    // DLSC (Algorithm 2): blocks of K_l, M_u = diag(P2 mass) on K0, I on the iso levels
+    std::vector<int64_t> iv, ip;
+    for (int64_t i = 0; i < Ks[l].nr; ++i) (fields[l][i] < d ? iv : ip).push_back(i);
+    HostDlsc& D = dl[l];
+    D.A = submatrix(Ks[l], iv, iv);
+    D.B = submatrix(Ks[l], ip, iv);
+    D.Bt = transpose(D.B);
+    D.minv.assign(iv.size(), 1.0);
+    if (l == 0 && pr->mu_diag0) {
+      int64_t q = 0;
+      for (int64_t i = 0; i < n0; ++i) {
+        if (pr->field0[i] >= d || pr->dir0[i]) continue;
+        const double m = pr->mu_diag0[i];
+        if (!(m > 0.0) || !std::isfinite(m)) throw MasError(MAS_EINVAL, "mu_diag0 must be positive");
+        D.minv[q++] = 1.0 / m;
+      }
+    }
+    Csr BM = D.B;
+    for (int64_t i = 0; i < BM.nr; ++i)
+      for (int64_t e = BM.ptr[i]; e < BM.ptr[i + 1]; ++e) BM.val[e] *= D.minv[BM.ind[e]];
+    D.S = spgemm(BM, D.Bt);
+    D.lamA = lanczos_max(D.A, par.seed + 2 * l, 20);
+    D.lamS = lanczos_max(D.S, par.seed + 2 * l + 1, 20);
+  }
   // coarsest operator, bordered with the coarse pressure null vector
   const Csr& KL = Ks.back();
   Csr Kb = KL;
@@ -864,7 +1048,7 @@ void analyze_impl(mas_handle* h, const mas_problem* pr) {
     int64_t nv = 0;
     for (auto f : fields[l]) nv += (f < d);
     in.n_vel[l] = nv;
-    if (relax[l]) {
+    if (relax[l] && !patches[l].off.empty()) {
       in.n_patches[l] = patches[l].np();
       in.patch_dofs[l] = (int64_t)patches[l].dofs.size();
       in.factor_entries[l] = patches[l].foff.back();
@@ -877,6 +1061,7 @@ void analyze_impl(mas_handle* h, const mas_problem* pr) {
   pl.Ps = std::move(Ps);
   pl.fields = std::move(fields);
   pl.patches = std::move(patches);
+  pl.dlsc = std::move(dl);
   pl.relax = std::move(relax);
   pl.Kb = std::move(Kb);
   pl.free0 = std::move(free0);
@@ -896,9 +1081,11 @@ void upload_impl(mas_handle* h, hipStream_t s) {
     autotune_team<double>(h->K0full, tx, ty, s);
   }
   if (par.precision == MAS_FP32)
-    h->cyc = build_cycle<float>(h, pl.Ks, pl.Ps, pl.fields, pl.patches, pl.relax, pl.Kb, pl.free0, pl.dir0, s);
+    h->cyc = build_cycle<float>(h, pl.Ks, pl.Ps, pl.fields, pl.patches, pl.dlsc, pl.relax, pl.Kb, pl.free0, pl.dir0,
+                                s);
   else
-    h->cyc = build_cycle<double>(h, pl.Ks, pl.Ps, pl.fields, pl.patches, pl.relax, pl.Kb, pl.free0, pl.dir0, s);
+    h->cyc = build_cycle<double>(h, pl.Ks, pl.Ps, pl.fields, pl.patches, pl.dlsc, pl.relax, pl.Kb, pl.free0, pl.dir0,
+                                 s);
   h->dir_idx = h->arena.upload<int64_t>(pl.dir0, s);
   h->ndir = (int64_t)pl.dir0.size();
   if (!pl.pw.empty()) h->pw = h->arena.upload<double>(pl.pw, s);
@@ -919,6 +1106,8 @@ void upload_impl(mas_handle* h, hipStream_t s) {
   // the host plan is no longer needed except for export
   pl.patches.clear();
   pl.patches.shrink_to_fit();
+  pl.dlsc.clear();
+  pl.dlsc.shrink_to_fit();
   h->on_device = true;
 }
 
@@ -1222,15 +1411,7 @@ int mas_solve(mas_handle* h, const double* b, double* x, int32_t nrhs, double rt
     HIPCHECK(hipStreamWaitEvent(us, h->ev_out, 0));
     if (h->tm.on) {
       HIPCHECK(hipStreamSynchronize(s));
-      for (auto& pr : h->tm.vanka) {
-        float ms = 0.f;
-        HIPCHECK(hipEventElapsedTime(&ms, pr.first, pr.second));
-        h->tm.vanka_ms += ms;
-        h->tm.vanka_launches++;
-        (void)hipEventDestroy(pr.first);
-        (void)hipEventDestroy(pr.second);
-      }
-      h->tm.vanka.clear();
+      h->tm.collect();
     }
     if (rc == MAS_ENAN) g_last_error = "residual is not finite";
     return rc;
@@ -1263,15 +1444,16 @@ int mas_export_level(const mas_handle* h, int32_t level, int64_t* nrows, int64_t
 int mas_set_timing(mas_handle* h, int32_t enable) {
   if (!h) return MAS_EINVAL;
   h->tm.on = enable != 0;
-  h->tm.vanka_ms = 0;
-  h->tm.vanka_launches = 0;
+  h->tm.vanka_ms = h->tm.spmv_ms = h->tm.vanka_bytes = h->tm.spmv_bytes = 0;
+  h->tm.vanka_launches = h->tm.spmv_launches = 0;
   return MAS_OK;
 }
 
 int mas_get_timing(const mas_handle* h, double* out, int32_t n) {
   if (!h || !out) return MAS_EINVAL;
-  if (n > 0) out[0] = h->tm.vanka_ms;
-  if (n > 1) out[1] = (double)h->tm.vanka_launches;
+  const double v[6] = {h->tm.vanka_ms, (double)h->tm.vanka_launches, h->tm.vanka_bytes,
+                       h->tm.spmv_ms, (double)h->tm.spmv_launches, h->tm.spmv_bytes};
+  for (int i = 0; i < n && i < 6; ++i) out[i] = v[i];
   return MAS_OK;
 }
 

@@ -208,9 +208,10 @@ class Handle:
         _check(lib.mas_set_timing(self.h, 1 if on else 0))
 
     def timing(self):
-        out = (C.c_double * 2)()
-        _check(lib.mas_get_timing(self.h, out, 2))
-        return dict(vanka_ms_total=out[0], vanka_launches=int(out[1]))
+        out = (C.c_double * 6)()
+        _check(lib.mas_get_timing(self.h, out, 6))
+        return dict(vanka_ms=out[0], vanka_launches=int(out[1]), vanka_bytes=out[2],
+                    spmv_ms=out[3], spmv_launches=int(out[4]), spmv_bytes=out[5])
 
     def close(self):
         if getattr(self, "h", None):

@@ -27,6 +27,11 @@ CASES = {
                    dict(max_coarse=30, schedule="skip1")),
     "th16_skip0": (dict(dim=2, n=16, jitter=0.2, seed=5, forcing="gaussian", bc="lid"),
                    dict(max_coarse=30, schedule="skip0")),
+    "th24_dlsc": (dict(dim=2, n=24, jitter=0.2, seed=2, forcing="gaussian", bc="lid"),
+                  dict(max_coarse=40, relax="dlsc")),
+    "th3d4_dlsc": (dict(dim=3, n=4, forcing="smooth", bc="zero", seed=3), dict(max_coarse=40, relax="dlsc")),
+    "th16_dlsc_skip1": (dict(dim=2, n=16, jitter=0.2, seed=5, forcing="gaussian", bc="lid"),
+                        dict(max_coarse=30, relax="dlsc", schedule="skip1")),
 }
 SCHED = {"all": mas.MAS_DC_ALL, "skip1": mas.MAS_DC_SKIP1, "skip0": mas.MAS_DC_SKIP0}
 
@@ -34,11 +39,15 @@ SCHED = {"all": mas.MAS_DC_ALL, "skip1": mas.MAS_DC_SKIP1, "skip0": mas.MAS_DC_S
 def build(name, precision=mas.MAS_FP64):
     kw, over = CASES[name]
     P = make_problem(**kw)
-    par = dc.default_params(P, **over)
-    mp = mas.default_params(P.dim, mas.MAS_TH, theta=par.theta, max_coarse=par.max_coarse,
+    relax = over.pop("relax", "vanka") if "relax" in over else "vanka"
+    over = dict(over)
+    par = dc.default_params(P, relax=relax, **over)
+    CASES[name][1]["relax"] = relax
+    mrelax = mas.MAS_RELAX_DLSC if relax == "dlsc" else mas.MAS_RELAX_VANKA
+    mp = mas.default_params(P.dim, mas.MAS_TH, mrelax, theta=par.theta, max_coarse=par.max_coarse,
                             max_levels=par.max_levels, omega0=par.omega0, omega=par.omega,
                             eta_u=par.eta_u, eta_p=par.eta_p, schedule=SCHED[par.schedule],
-                            precision=precision)
+                            precision=precision, seed=par.seed)
     print(f"[case {name}] n0={P.n0} precision={precision}", flush=True)
     return P, par, mp
 
@@ -63,7 +72,7 @@ def test_apply_fp64_matches_oracle(name):
     h.close()
 
 
-@pytest.mark.parametrize("name", ["th16_2lvl", "th24_lid", "th3d4", "th16_skip1"])
+@pytest.mark.parametrize("name", ["th16_2lvl", "th24_lid", "th3d4", "th16_skip1", "th24_dlsc", "th3d4_dlsc"])
 def test_solve_fp64_matches_oracle(name):
     P, par, mp = build(name)
     pre = dc.DCPreconditioner(P, par)
@@ -86,7 +95,7 @@ def test_solve_fp64_matches_oracle(name):
     h.close()
 
 
-@pytest.mark.parametrize("name", ["th16_3lvl", "th24_lid", "th3d4"])
+@pytest.mark.parametrize("name", ["th16_3lvl", "th24_lid", "th3d4", "th24_dlsc"])
 def test_solve_fp32_cycle_reaches_1e8(name):
     P, par, mp = build(name, precision=mas.MAS_FP32)
     h = mas.Handle(P, mp)
