@@ -139,26 +139,28 @@ __global__ void k_axpby(int64_t n, T a, const T* __restrict__ x, T b, T* __restr
 // ---------------------------------------------------------------------------
 // Chebyshev semi-iteration and DLSC helpers (Algorithm 2, Table 3)
 
-// d = r / theta, res = r, y = d
+// d = D^-1 r / theta, res = r, y = d   (D^-1 = dinv, identity when null)
 template <typename T>
-__global__ void k_cheb_init(int64_t n, const T* __restrict__ r, T inv_theta, T* __restrict__ d, T* __restrict__ res,
-                            T* __restrict__ y) {
+__global__ void k_cheb_init(int64_t n, const T* __restrict__ r, T inv_theta, const T* __restrict__ dinv,
+                            T* __restrict__ d, T* __restrict__ res, T* __restrict__ y) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
     const T ri = r[i];
-    const T di = ri * inv_theta;
+    const T di = (dinv ? dinv[i] * ri : ri) * inv_theta;
     d[i] = di;
     res[i] = ri;
     y[i] = di;
   }
 }
 
-// d = a d + c res; y += d
+// d = a d + c D^-1 res; y += d
 template <typename T>
-__global__ void k_cheb_update(int64_t n, T a, T c, const T* __restrict__ res, T* __restrict__ d, T* __restrict__ y) {
+__global__ void k_cheb_update(int64_t n, T a, T c, const T* __restrict__ dinv, const T* __restrict__ res,
+                              T* __restrict__ d, T* __restrict__ y) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
-    const T di = a * d[i] + c * res[i];
+    const T ri = dinv ? dinv[i] * res[i] : res[i];
+    const T di = a * d[i] + c * ri;
     d[i] = di;
     y[i] += di;
   }

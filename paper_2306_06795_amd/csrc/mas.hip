@@ -337,6 +337,49 @@ struct Cycle : CycleBase {
   mas_params par{};
   int dim = 2;
   Timing* tm = nullptr;
+  // Scott-Vogelius pressure transfers (Section 3.1): P0^p duplication, R0^p = M_cg^-1 (P0^p)^T M_dg
+  bool sv = false;
+  int64_t np0 = 0, np1 = 0;
+  DCsr<T> Mdg, P0t, P0p, Mcg;
+  T* mcg_dinv = nullptr;
+  int mass_steps = 0;
+  T *sv_t0 = nullptr, *sv_t1 = nullptr, *sv_z = nullptr, *sv_cd = nullptr, *sv_cres = nullptr;
+
+  // b1 = eta R0 r0
+  void restrict0(const T* r0, Level<T>& L1, hipStream_t s) {
+    const int64_t nv = L1.nvel;
+    if (!sv) {  // Taylor-Hood: injection
+      hipLaunchKernelGGL((k_scale2<T>), dim3(blocks_for(L1.n, 256)), dim3(256), 0, s, L1.n, nv, (T)par.eta_u,
+                         (T)par.eta_p, r0, L1.b);
+      launch_check();
+      return;
+    }
+    hipLaunchKernelGGL((k_scale2<T>), dim3(blocks_for(nv, 256)), dim3(256), 0, s, nv, nv, (T)par.eta_u,
+                       (T)par.eta_u, r0, L1.b);
+    spmv<0>(Mdg, r0 + nv, nullptr, sv_t0, s);   // M_dg r0_p
+    spmv<0>(P0t, sv_t0, nullptr, sv_t1, s);     // (P0^p)^T M_dg r0_p
+    // M_cg z = t1: Jacobi-preconditioned Chebyshev with the P1 bounds lambda(D^-1 M) in [1/2, 2]
+    chebyshev_iv(Mcg, sv_t1, sv_z, 0.5, 2.0, mass_steps, mcg_dinv, sv_cd, sv_cres, s);
+    hipLaunchKernelGGL((k_axpby<T>), dim3(blocks_for(np1, 256)), dim3(256), 0, s, np1, (T)par.eta_p, sv_z, (T)0,
+                       L1.b + nv);
+    launch_check();
+  }
+
+  // x0 (+)= P0 x1
+  void prolong0(Level<T>& L1, Level<T>& L0, bool x_zero, hipStream_t s) {
+    if (!sv) {
+      hipLaunchKernelGGL((k_axpby<T>), dim3(blocks_for(L0.n, 256)), dim3(256), 0, s, L0.n, (T)1, L1.x,
+                         x_zero ? (T)0 : (T)1, L0.x);
+      launch_check();
+      return;
+    }
+    const int64_t nv = L1.nvel;
+    hipLaunchKernelGGL((k_axpby<T>), dim3(blocks_for(nv, 256)), dim3(256), 0, s, nv, (T)1, L1.x,
+                       x_zero ? (T)0 : (T)1, L0.x);
+    launch_check();
+    if (x_zero) spmv<0>(P0p, L1.x + nv, nullptr, L0.x + nv, s);
+    else spmv<2>(P0p, L1.x + nv, nullptr, L0.x + nv, s);
+  }
 
   // sparse product, timed (with its algorithmic bytes) when timing is on
   template <int MODE>
@@ -353,23 +396,29 @@ struct Cycle : CycleBase {
     }
   }
 
-  // y = X^{-1} r approximated by `deg` Chebyshev steps on [0.5^dim lam, 1.1 lam] from y = 0
-  void chebyshev(DCsr<T>& X, const T* r, T* y, double lam, int deg, DDlsc<T>& D, hipStream_t s) {
+  // y ~ X^{-1} r: `deg` steps of the Chebyshev semi-iteration from y = 0 for the
+  // spectrum interval [lo, hi] of D^-1 X (D^-1 = dinv, identity when null)
+  void chebyshev_iv(DCsr<T>& X, const T* r, T* y, double lo, double hi, int deg, const T* dinv, T* cd, T* cres,
+                    hipStream_t s) {
     const int64_t n = X.n;
-    const double lo = std::pow(0.5, dim) * lam, hi = 1.1 * lam;
     const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
     double rho = 1.0 / sigma;
     const unsigned nb = blocks_for(n, 256);
-    hipLaunchKernelGGL((k_cheb_init<T>), dim3(nb), dim3(256), 0, s, n, r, (T)(1.0 / theta), D.cd, D.cres, y);
+    hipLaunchKernelGGL((k_cheb_init<T>), dim3(nb), dim3(256), 0, s, n, r, (T)(1.0 / theta), dinv, cd, cres, y);
     launch_check();
     for (int k = 0; k + 1 < deg; ++k) {
-      spmv<3>(X, D.cd, nullptr, D.cres, s);
+      spmv<3>(X, cd, nullptr, cres, s);
       const double rho_new = 1.0 / (2.0 * sigma - rho);
       hipLaunchKernelGGL((k_cheb_update<T>), dim3(nb), dim3(256), 0, s, n, (T)(rho_new * rho),
-                         (T)(2.0 * rho_new / delta), D.cres, D.cd, y);
+                         (T)(2.0 * rho_new / delta), dinv, cres, cd, y);
       launch_check();
       rho = rho_new;
     }
+  }
+
+  // DLSC inner solves: interval [0.5^dim lam, 1.1 lam] (Table 3)
+  void chebyshev(DCsr<T>& X, const T* r, T* y, double lam, int deg, DDlsc<T>& D, hipStream_t s) {
+    chebyshev_iv(X, r, y, std::pow(0.5, dim) * lam, 1.1 * lam, deg, nullptr, D.cd, D.cres, s);
   }
 
   // one DLSC sweep (Algorithm 2) on level L: x = (u, p), b = (f, g)
@@ -517,15 +566,9 @@ struct Cycle : CycleBase {
       spmv<1>(L0.K, L0.x, L0.b, L0.r, s);
       r0 = L0.r;
     }
-    // eta R0 (Taylor-Hood: injection, eq. (3.2))
-    hipLaunchKernelGGL((k_scale2<T>), dim3(blocks_for(L1.n, 256)), dim3(256), 0, s, L1.n, L1.nvel, (T)par.eta_u,
-                       (T)par.eta_p, r0, L1.b);
-    launch_check();
+    restrict0(r0, L1, s);  // eta R0 r0 (eq. (3.2))
     vcycle(1, s);
-    // x0 += P0 x1 (injection)
-    hipLaunchKernelGGL((k_axpby<T>), dim3(blocks_for(L0.n, 256)), dim3(256), 0, s, L0.n, (T)1, L1.x,
-                       x_zero ? (T)0 : (T)1, L0.x);
-    launch_check();
+    prolong0(L1, L0, x_zero, s);  // x0 += P0 x1
     if (L0.relax && par.nu2 > 0) relax_level(L0, par.nu2, (T)par.omega0, false, s);
     hipLaunchKernelGGL((k_scatter<double, T>), dim3(blocks_for(nfree0, 256)), dim3(256), 0, s, nfree0, free0, L0.x, z);
     launch_check();
@@ -557,6 +600,10 @@ struct HostPlan {
   std::vector<int64_t> free0, dir0;
   Csr K0;                                  // full K0 (FGMRES operator)
   std::vector<double> pw;                  // pressure weights
+  bool sv = false;
+  Csr Mdg, P0t, P0p, Mcg;                  // Scott-Vogelius transfer data (free pressure numbering)
+  std::vector<double> mcg_dinv;
+  int mass_steps = 0;
 };
 
 struct mas_handle {
@@ -872,13 +919,32 @@ std::unique_ptr<Cycle<T>> build_cycle(mas_handle* h, const std::vector<Csr>& Ks,
   cyc->dir0 = ar.upload<int64_t>(dir0, s);
   cyc->nfree0 = (int64_t)free0.size();
   cyc->ndir0 = (int64_t)dir0.size();
+  const HostPlan& pl = h->plan;
+  if (pl.sv) {
+    cyc->sv = true;
+    cyc->np0 = pl.Mdg.nr;
+    cyc->np1 = pl.Mcg.nr;
+    cyc->Mdg = upload_csr<T>(ar, pl.Mdg, s);
+    cyc->P0t = upload_csr<T>(ar, pl.P0t, s);
+    cyc->P0p = upload_csr<T>(ar, pl.P0p, s);
+    cyc->Mcg = upload_csr<T>(ar, pl.Mcg, s);
+    cyc->mcg_dinv = ar.upload<T>(pl.mcg_dinv, s);
+    cyc->mass_steps = pl.mass_steps;
+    cyc->sv_t0 = ar.alloc<T>(cyc->np0);
+    cyc->sv_t1 = ar.alloc<T>(cyc->np1);
+    cyc->sv_z = ar.alloc<T>(cyc->np1);
+    cyc->sv_cd = ar.alloc<T>(cyc->np1);
+    cyc->sv_cres = ar.alloc<T>(cyc->np1);
+    for (DCsr<T>* A : {&cyc->Mdg, &cyc->P0t, &cyc->P0p, &cyc->Mcg}) A->use_sell = false;
+  }
   return cyc;
 }
 
 void analyze_impl(mas_handle* h, const mas_problem* pr) {
   const int d = pr->dim;
   if (d != 2 && d != 3) throw MasError(MAS_EINVAL, "dim must be 2 or 3");
-  if (pr->disc != MAS_TH) throw MasError(MAS_EINVAL, "only Taylor-Hood is supported by this build");
+  if (pr->disc != MAS_TH && pr->disc != MAS_SV) throw MasError(MAS_EINVAL, "unknown discretisation");
+  if (pr->disc == MAS_SV && d != 2) throw MasError(MAS_EINVAL, "Scott-Vogelius is supported in 2D");
   h->dim = d;
   h->disc = pr->disc;
   const mas_params& par = h->par;
@@ -924,7 +990,8 @@ void analyze_impl(mas_handle* h, const mas_problem* pr) {
   int64_t nv0 = 0, nv1 = 0;
   for (auto f : f0) nv0 += (f < d);
   for (auto f : f1) nv1 += (f < d);
-  if (nv0 != nv1 || (int64_t)free0.size() != (int64_t)free1.size())
+  if (nv0 != nv1) throw MasError(MAS_EINVAL, "K0 and K1 must share their free velocity DoFs");
+  if (pr->disc == MAS_TH && (int64_t)free0.size() != (int64_t)free1.size())
     throw MasError(MAS_EINVAL, "K0 and K1 free DoFs must coincide for Taylor-Hood");
   // ---- Algorithm 1: per-field smoothed aggregation on K1's velocity blocks and A_p
   std::vector<std::vector<int64_t>> blocks(d + 1);
@@ -967,7 +1034,21 @@ void analyze_impl(mas_handle* h, const mas_problem* pr) {
   for (size_t l = 0; l + 1 < nl; ++l) {
     if (!relax[l]) continue;
     if (par.relax == MAS_RELAX_VANKA) {
-      patches[l] = patches_single_seed(Ks[l], fields[l], d);
+      if (l == 0 && pr->disc == MAS_SV) {
+        // three pressure seeds per element (Section 3.3.1)
+        if (!pr->elem_p0 || pr->n_elem <= 0) throw MasError(MAS_EINVAL, "elem_p0 is required for Scott-Vogelius");
+        std::vector<int64_t> pos(n0, -1);
+        for (size_t q = 0; q < free0.size(); ++q) pos[free0[q]] = (int64_t)q;
+        std::vector<int32_t> seeds((size_t)pr->n_elem * 3);
+        for (int64_t e = 0; e < pr->n_elem * 3; ++e) {
+          const int64_t g = pr->elem_p0[e];
+          if (g < 0 || g >= n0 || pr->field0[g] != d) throw MasError(MAS_EINVAL, "elem_p0 must name pressure rows");
+          seeds[e] = (int32_t)pos[g];
+        }
+        patches[l] = patches_element_seeds(Ks[l], fields[l], d, seeds, 3);
+      } else {
+        patches[l] = patches_single_seed(Ks[l], fields[l], d);
+      }
       continue;
     }
     // DLSC (Algorithm 2): blocks of K_l, M_u = diag(P2 mass) on K0, I on the iso levels
@@ -1033,6 +1114,24 @@ void analyze_impl(mas_handle* h, const mas_problem* pr) {
     Kb.ptr.push_back((int64_t)Kb.ind.size());
   }
   HostPlan& pl = h->plan;
+  pl.sv = pr->disc == MAS_SV;
+  if (pl.sv) {
+    const int64_t np1 = (int64_t)blocks[d].size();
+    Csr Pp = get_csr(pr->Pp0, "Pp0"), Md = get_csr(pr->Mdg, "Mdg"), Mc = get_csr(pr->Mcg, "Mcg");
+    if (Pp.nr != np0 || Pp.nc != np1 || Md.nr != np0 || Md.nc != np0 || Mc.nr != np1 || Mc.nc != np1)
+      throw MasError(MAS_EINVAL, "Scott-Vogelius transfer operators have wrong shapes");
+    pl.P0p = Pp;
+    pl.P0t = transpose(Pp);
+    pl.Mdg = Md;
+    pl.Mcg = Mc;
+    pl.mcg_dinv.assign(np1, 0.0);
+    for (int64_t i = 0; i < np1; ++i)
+      for (int64_t e = Mc.ptr[i]; e < Mc.ptr[i + 1]; ++e)
+        if (Mc.ind[e] == i) pl.mcg_dinv[i] = 1.0 / Mc.val[e];
+    // Chebyshev steps for the mass solve: error <= 2 (1/3)^k for the P1 interval [1/2, 2]
+    const double tol = std::max(par.mass_rtol, 1e-16);
+    pl.mass_steps = (int)std::ceil(std::log(2.0 / tol) / std::log(3.0));
+  }
   pl.pw.clear();
   if (pr->p_weight0) {
     pl.pw.assign(pr->p_weight0, pr->p_weight0 + np0);

@@ -113,6 +113,9 @@ def default_params(dim: int, disc: int = MAS_TH, relax: int = MAS_RELAX_VANKA, *
 
 
 def _csr(A, keep: list) -> mas_csr:
+    A = A.tocsr()
+    if not A.has_sorted_indices:
+        A = A.sorted_indices()
     ptr = np.ascontiguousarray(A.indptr, dtype=np.int64)
     ind = np.ascontiguousarray(A.indices, dtype=np.int32)
     val = np.ascontiguousarray(A.data, dtype=np.float64)

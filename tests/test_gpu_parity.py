@@ -32,6 +32,8 @@ CASES = {
     "th3d4_dlsc": (dict(dim=3, n=4, forcing="smooth", bc="zero", seed=3), dict(max_coarse=40, relax="dlsc")),
     "th16_dlsc_skip1": (dict(dim=2, n=16, jitter=0.2, seed=5, forcing="gaussian", bc="lid"),
                         dict(max_coarse=30, relax="dlsc", schedule="skip1")),
+    "sv6": (dict(dim=2, n=6, disc="SV", seed=4, forcing="gaussian", bc="zero"), dict(max_coarse=40)),
+    "sv8_lid": (dict(dim=2, n=8, disc="SV", jitter=0.2, seed=4, forcing="gaussian", bc="lid"), dict(max_coarse=40)),
 }
 SCHED = {"all": mas.MAS_DC_ALL, "skip1": mas.MAS_DC_SKIP1, "skip0": mas.MAS_DC_SKIP0}
 
@@ -44,7 +46,8 @@ def build(name, precision=mas.MAS_FP64):
     par = dc.default_params(P, relax=relax, **over)
     CASES[name][1]["relax"] = relax
     mrelax = mas.MAS_RELAX_DLSC if relax == "dlsc" else mas.MAS_RELAX_VANKA
-    mp = mas.default_params(P.dim, mas.MAS_TH, mrelax, theta=par.theta, max_coarse=par.max_coarse,
+    disc = mas.MAS_SV if P.disc == "SV" else mas.MAS_TH
+    mp = mas.default_params(P.dim, disc, mrelax, theta=par.theta, max_coarse=par.max_coarse,
                             max_levels=par.max_levels, omega0=par.omega0, omega=par.omega,
                             eta_u=par.eta_u, eta_p=par.eta_p, schedule=SCHED[par.schedule],
                             precision=precision, seed=par.seed)
@@ -72,7 +75,8 @@ def test_apply_fp64_matches_oracle(name):
     h.close()
 
 
-@pytest.mark.parametrize("name", ["th16_2lvl", "th24_lid", "th3d4", "th16_skip1", "th24_dlsc", "th3d4_dlsc"])
+@pytest.mark.parametrize("name", ["th16_2lvl", "th24_lid", "th3d4", "th16_skip1", "th24_dlsc", "th3d4_dlsc",
+                                  "sv6", "sv8_lid"])
 def test_solve_fp64_matches_oracle(name):
     P, par, mp = build(name)
     pre = dc.DCPreconditioner(P, par)
@@ -95,7 +99,7 @@ def test_solve_fp64_matches_oracle(name):
     h.close()
 
 
-@pytest.mark.parametrize("name", ["th16_3lvl", "th24_lid", "th3d4", "th24_dlsc"])
+@pytest.mark.parametrize("name", ["th16_3lvl", "th24_lid", "th3d4", "th24_dlsc", "sv8_lid"])
 def test_solve_fp32_cycle_reaches_1e8(name):
     P, par, mp = build(name, precision=mas.MAS_FP32)
     h = mas.Handle(P, mp)

@@ -110,3 +110,13 @@ def test_lid_data_is_compatible():
     P = make_problem(dim=2, n=16, jitter=0.2, seed=2, forcing="gaussian", bc="lid")
     nu = P.meta["n_u"]
     assert abs(P.b[nu:].sum()) <= 1e-12 * np.abs(P.b).max()
+
+
+def test_jacobi_scaled_p1_mass_spectrum():
+    """Wathen's bounds: for linear triangles the eigenvalues of diag(M)^-1 M lie in
+    [1/2, 2] (the interval the library's Chebyshev mass solve relies on)."""
+    P = make_problem(dim=2, n=5, disc="SV", jitter=0.2, seed=6)
+    M = P.Mcg.toarray()
+    d = np.sqrt(np.diag(M))
+    ev = np.linalg.eigvalsh(M / d[:, None] / d[None, :])
+    assert ev.min() >= 0.5 - 1e-12 and ev.max() <= 2.0 + 1e-12
