@@ -103,6 +103,7 @@ typedef struct {
   double theta;           /* strength threshold: a_ij^2 >= theta^2 a_ii a_jj */
   uint64_t seed;          /* SplitMix64 seed of the Lanczos start vectors */
   double mass_rtol;       /* relative tolerance of the SV pressure-mass solve */
+  int32_t nrhs_max;       /* most right-hand sides one mas_apply / mas_solve may carry (1..64) */
 } mas_params;
 
 typedef struct {

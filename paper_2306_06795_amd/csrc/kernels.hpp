@@ -129,24 +129,25 @@ __global__ void k_scale2(int64_t n, int64_t nsplit, T a, T b, const T* __restric
   if (k < n) y[k] = (k < nsplit ? a : b) * x[k];
 }
 
-// y = a x + b y
+// y = a x + b y; y is not read when b == 0 (it may hold uninitialised memory)
 template <typename T>
 __global__ void k_axpby(int64_t n, T a, const T* __restrict__ x, T b, T* __restrict__ y) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) y[k] = a * x[k] + b * y[k];
+  if (k < n) y[k] = (b == (T)0) ? a * x[k] : a * x[k] + b * y[k];
 }
 
 // ---------------------------------------------------------------------------
 // Chebyshev semi-iteration and DLSC helpers (Algorithm 2, Table 3)
 
-// d = D^-1 r / theta, res = r, y = d   (D^-1 = dinv, identity when null)
+// d = D^-1 r / theta, res = r, y = d   (D^-1 = dinv, identity when null; nr
+// right-hand sides interleaved, entry i belongs to row i / nr)
 template <typename T>
 __global__ void k_cheb_init(int64_t n, const T* __restrict__ r, T inv_theta, const T* __restrict__ dinv,
-                            T* __restrict__ d, T* __restrict__ res, T* __restrict__ y) {
+                            T* __restrict__ d, T* __restrict__ res, T* __restrict__ y, int nr) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
     const T ri = r[i];
-    const T di = (dinv ? dinv[i] * ri : ri) * inv_theta;
+    const T di = (dinv ? dinv[i / nr] * ri : ri) * inv_theta;
     d[i] = di;
     res[i] = ri;
     y[i] = di;
@@ -156,21 +157,298 @@ __global__ void k_cheb_init(int64_t n, const T* __restrict__ r, T inv_theta, con
 // d = a d + c D^-1 res; y += d
 template <typename T>
 __global__ void k_cheb_update(int64_t n, T a, T c, const T* __restrict__ dinv, const T* __restrict__ res,
-                              T* __restrict__ d, T* __restrict__ y) {
+                              T* __restrict__ d, T* __restrict__ y, int nr) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
-    const T ri = dinv ? dinv[i] * res[i] : res[i];
+    const T ri = dinv ? dinv[i / nr] * res[i] : res[i];
     const T di = a * d[i] + c * ri;
     d[i] = di;
     y[i] += di;
   }
 }
 
-// x[i] *= m[i]
+// x[i] *= m[i / nr]
 template <typename T>
-__global__ void k_mul(int64_t n, const T* __restrict__ m, T* __restrict__ x) {
+__global__ void k_mul(int64_t n, const T* __restrict__ m, T* __restrict__ x, int nr) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) x[i] *= m[i];
+  if (i < n) x[i] *= m[i / nr];
+}
+
+// ---------------------------------------------------------------------------
+// batched kernels: nr right-hand sides interleaved, entry (i, k) at i * nr + k
+
+// dst[q * nr + k] = (T) src[idx[q] * nr + k]
+template <typename T, typename S>
+__global__ void k_gather_nr(int64_t n, int nr, const int64_t* __restrict__ idx, const S* __restrict__ src,
+                            T* __restrict__ dst) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n * nr) dst[t] = (T)src[idx[t / nr] * nr + t % nr];
+}
+
+// dst[idx[q] * nr + k] = (T) src[q * nr + k]
+template <typename T, typename S>
+__global__ void k_scatter_nr(int64_t n, int nr, const int64_t* __restrict__ idx, const S* __restrict__ src,
+                             T* __restrict__ dst) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n * nr) dst[idx[t / nr] * nr + t % nr] = (T)src[t];
+}
+
+__global__ void k_copy_idx_nr(int64_t n, int nr, const int64_t* __restrict__ idx, const double* __restrict__ src,
+                              double* __restrict__ dst) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n * nr) {
+    const int64_t e = idx[t / nr] * nr + t % nr;
+    dst[e] = src[e];
+  }
+}
+
+// Y = A X for nr interleaved right-hand sides (CSR): one thread per (row, rhs);
+// the threads of a row read the same matrix entries and contiguous X rows.
+template <typename T, int MODE>
+__global__ void __launch_bounds__(256) k_spmm(int64_t n, int nr, const int* __restrict__ ptr,
+                                              const int* __restrict__ ind, const T* __restrict__ val,
+                                              const T* __restrict__ x, const T* __restrict__ b,
+                                              T* __restrict__ y) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * nr) return;
+  const int64_t row = t / nr;
+  const int k = (int)(t % nr);
+  T s = 0;
+  for (int e = ptr[row]; e < ptr[row + 1]; ++e) s += val[e] * x[(int64_t)ind[e] * nr + k];
+  if (MODE == 0) y[t] = s;
+  else if (MODE == 1) y[t] = b[t] - s;
+  else if (MODE == 2) y[t] += s;
+  else y[t] -= s;
+}
+
+// dense coarse solve for nr right-hand sides: y = C b, FP64 accumulation
+template <typename T>
+__global__ void __launch_bounds__(256) k_dense_gemm(int n, int ld, int nr, const double* __restrict__ C,
+                                                   const T* __restrict__ b, T* __restrict__ y) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * nr) return;
+  const int64_t row = t / nr;
+  const int k = (int)(t % nr);
+  double s = 0.0;
+  for (int j = 0; j < n; ++j) s += C[row * ld + j] * (double)b[(int64_t)j * nr + k];
+  y[t] = (T)s;
+}
+
+// patch solves for nr right-hand sides: one workgroup per patch and chunk of
+// right-hand sides, one lane per right-hand side; the factor record is staged
+// in LDS (element q of patch p at foff[p] + q * fstride[p]) and read as
+// broadcasts, the patch's right-hand sides and results live in LDS.
+// Y holds the result of slot s of patch p at (off[p] + s) * nr + k.
+template <typename T>
+__global__ void __launch_bounds__(64) k_vanka_apply_nr(int64_t np, int nr, const int64_t* __restrict__ off,
+                                                      const int4* __restrict__ dims,
+                                                      const int64_t* __restrict__ foff,
+                                                      const int64_t* __restrict__ fstride,
+                                                      const int* __restrict__ dofs, const T* __restrict__ fac,
+                                                      const T* __restrict__ r, T* __restrict__ Y, int max_m,
+                                                      int64_t max_f, int chunk) {
+  extern __shared__ unsigned char smem_raw[];
+  T* sf = reinterpret_cast<T*>(smem_raw);
+  T* sb = sf + max_f;
+  T* sy = sb + (int64_t)max_m * chunk;
+  const int64_t p = blockIdx.x;
+  if (p >= np) return;
+  const int lane = threadIdx.x;
+  const int k0 = blockIdx.y * chunk;
+  const int kk = k0 + lane;
+  const bool active = lane < chunk && kk < nr;
+  const int4 d = dims[p];
+  const int nc[3] = {d.x, d.y, d.z};
+  const int nv = d.x + d.y + d.z, ns = d.w, m = nv + ns;
+  const int64_t nf = (int64_t)d.x * (d.x + 1) / 2 + (int64_t)d.y * (d.y + 1) / 2 + (int64_t)d.z * (d.z + 1) / 2 +
+                     (int64_t)nv * ns + (int64_t)ns * (ns + 1) / 2;
+  const int64_t o = off[p], f0 = foff[p], fs = fstride[p];
+  for (int64_t q = lane; q < nf; q += WAVE) sf[q] = fac[f0 + q * fs];
+  if (active)
+    for (int j = 0; j < m; ++j) sb[j * chunk + lane] = r[(int64_t)dofs[o + j] * nr + kk];
+  __syncthreads();
+  if (active) {
+    int cs = 0;
+    int64_t ao = 0;
+    for (int c = 0; c < 3; ++c) {
+      const int n = nc[c];
+      const T* A = sf + ao;
+      for (int i = 0; i < n; ++i) {
+        T acc = 0;
+        for (int j = 0; j < n; ++j) acc += A[packed_index(i, j)] * sb[(cs + j) * chunk + lane];
+        sy[(cs + i) * chunk + lane] = acc;
+      }
+      ao += (int64_t)n * (n + 1) / 2;
+      cs += n;
+    }
+    const T* U = sf + ao;
+    const T* Si = U + (int64_t)nv * ns;
+    T t[MAX_NS], yp[MAX_NS];
+    for (int s = 0; s < ns; ++s) {
+      T acc = sb[(nv + s) * chunk + lane];
+      for (int q = 0; q < nv; ++q) acc += U[(int64_t)s * nv + q] * sb[q * chunk + lane];
+      t[s] = acc;
+    }
+    for (int s = 0; s < ns; ++s) {
+      T acc = 0;
+      for (int q = 0; q < ns; ++q) acc += Si[packed_index(s, q)] * t[q];
+      yp[s] = acc;
+    }
+    for (int row = 0; row < nv; ++row) {
+      T acc = sy[row * chunk + lane];
+      for (int s = 0; s < ns; ++s) acc += U[(int64_t)s * nv + row] * yp[s];
+      Y[(o + row) * nr + kk] = acc;
+    }
+    for (int s = 0; s < ns; ++s) Y[(o + nv + s) * nr + kk] = yp[s];
+  }
+}
+
+// x[j, k] (+)= omega / count_j * sum of the patch values held for DoF j (slot-major map)
+template <typename T>
+__global__ void k_vanka_pull_ell_nr(int n, int nr, int width, const int* __restrict__ pos, const T* __restrict__ Y,
+                                    T omega, T* __restrict__ x, int accumulate) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * nr) return;
+  const int64_t j = t / nr;
+  const int k = (int)(t % nr);
+  T acc = 0;
+  int cnt = 0;
+  for (int s = 0; s < width; ++s) {
+    const int q = pos[(int64_t)s * n + j];
+    if (q >= 0) {
+      acc += Y[(int64_t)q * nr + k];
+      ++cnt;
+    }
+  }
+  if (cnt == 0) {
+    if (!accumulate) x[t] = 0;
+    return;
+  }
+  const T v = omega * acc / (T)cnt;
+  x[t] = accumulate ? x[t] + v : v;
+}
+
+// x[j, k] (+)= omega W_j sum ... (CSR map)
+template <typename T>
+__global__ void k_vanka_pull_nr(int n, int nr, const int* __restrict__ inv_ptr, const int* __restrict__ inv_pos,
+                                const T* __restrict__ Y, const T* __restrict__ w, T omega, T* __restrict__ x,
+                                int accumulate) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * nr) return;
+  const int64_t j = t / nr;
+  const int k = (int)(t % nr);
+  T acc = 0;
+  for (int q = inv_ptr[j]; q < inv_ptr[j + 1]; ++q) acc += Y[(int64_t)inv_pos[q] * nr + k];
+  const T v = omega * w[j] * acc;
+  x[t] = accumulate ? x[t] + v : v;
+}
+
+// per-column partial dot products of w and v (or w and w) over a block's rows,
+// w -= a_k vprev when vprev is given, a_k = sum of the previous partials of
+// column k.  Block layout: 256 threads = (256 / nrp) row groups x nrp columns.
+__global__ void __launch_bounds__(256) k_mgs_step_nr(int64_t n, int nr, int nrp, double* __restrict__ w,
+                                                    const double* __restrict__ vprev, double* __restrict__ hprev,
+                                                    const double* __restrict__ prev_partial,
+                                                    const double* __restrict__ vnext,
+                                                    double* __restrict__ partial_out, int mode) {
+  __shared__ double sh[256];
+  const int k = threadIdx.x % nrp, g = threadIdx.x / nrp, ng = 256 / nrp;
+  const bool col = k < nr;
+  double a = 0.0;
+  if (prev_partial && col) {
+    for (unsigned b = 0; b < gridDim.x; ++b) a += prev_partial[(int64_t)b * nr + k];
+    if (blockIdx.x == 0 && g == 0) hprev[k] = a;
+  }
+  double s = 0.0;
+  if (col)
+    for (int64_t i = (int64_t)blockIdx.x * ng + g; i < n; i += (int64_t)gridDim.x * ng) {
+      const int64_t e = i * nr + k;
+      double wi = w[e];
+      if (vprev) {
+        wi -= a * vprev[e];
+        w[e] = wi;
+      }
+      s += wi * (mode == 0 ? vnext[e] : wi);
+    }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  if (g == 0 && col) {
+    double t = 0.0;
+    for (int q = 0; q < ng; ++q) t += sh[q * nrp + k];
+    partial_out[(int64_t)blockIdx.x * nr + k] = t;
+  }
+}
+
+// v[:, k] = w[:, k] / sqrt(sum of partials of column k); block 0 stores the norms
+__global__ void __launch_bounds__(256) k_normalize_nr(int64_t n, int nr, const double* __restrict__ partial, int nb,
+                                                     double* __restrict__ hout, const double* __restrict__ w,
+                                                     double* __restrict__ v) {
+  __shared__ double nrm[64];
+  for (int k = threadIdx.x; k < nr; k += blockDim.x) {
+    double t = 0.0;
+    for (int b = 0; b < nb; ++b) t += partial[(int64_t)b * nr + k];
+    nrm[k] = sqrt(t);
+    if (blockIdx.x == 0) hout[k] = nrm[k];
+  }
+  __syncthreads();
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n * nr; t += (int64_t)gridDim.x * blockDim.x) {
+    const double q = nrm[t % nr];
+    v[t] = q != 0.0 ? w[t] / q : 0.0;
+  }
+}
+
+// out[k] = sum_b partial[b * nr + k] (sqrt if take_sqrt)
+__global__ void k_reduce_final_nr(int nb, int nr, const double* __restrict__ partial, double* __restrict__ out,
+                                  int take_sqrt) {
+  const int k = threadIdx.x;
+  if (k >= nr) return;
+  double t = 0.0;
+  for (int b = 0; b < nb; ++b) t += partial[(int64_t)b * nr + k];
+  out[k] = take_sqrt ? sqrt(t) : t;
+}
+
+// v[:, k] = r[:, k] / beta[k] (0 when beta[k] == 0)
+__global__ void k_scale_cols(int64_t n, int nr, const double* __restrict__ beta, const double* __restrict__ r,
+                             double* __restrict__ v) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n * nr) {
+    const double q = beta[t % nr];
+    v[t] = q != 0.0 ? r[t] / q : 0.0;
+  }
+}
+
+// x[:, k] += sum_q y[q * nr + k] Z_q[:, k]
+__global__ void k_update_x_nr(int64_t n, int nr, int kmax, const double* __restrict__ Z, const double* __restrict__ y,
+                              double* __restrict__ x) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * nr) return;
+  const int k = (int)(t % nr);
+  double s = x[t];
+  for (int q = 0; q < kmax; ++q) s += y[(int64_t)q * nr + k] * Z[(int64_t)q * n * nr + t];
+  x[t] = s;
+}
+
+// x[i, k] += c_k for the rows i of one block (zero-mean pressure shift)
+__global__ void k_add_cols(int64_t n, int nr, const double* __restrict__ c, double* __restrict__ x) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n * nr) x[t] += c[t % nr];
+}
+
+// partial[b * nr + k] = sum over a block's rows of w[i] * x[i, k] (weighted column sums)
+__global__ void __launch_bounds__(256) k_wdot_nr(int64_t n, int nr, int nrp, const double* __restrict__ w,
+                                                const double* __restrict__ x, double* __restrict__ partial) {
+  __shared__ double sh[256];
+  const int k = threadIdx.x % nrp, g = threadIdx.x / nrp, ng = 256 / nrp;
+  double s = 0.0;
+  if (k < nr)
+    for (int64_t i = (int64_t)blockIdx.x * ng + g; i < n; i += (int64_t)gridDim.x * ng) s += w[i] * x[i * nr + k];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  if (g == 0 && k < nr) {
+    double t = 0.0;
+    for (int q = 0; q < ng; ++q) t += sh[q * nrp + k];
+    partial[(int64_t)blockIdx.x * nr + k] = t;
+  }
 }
 
 // z = x + y

@@ -258,6 +258,12 @@ struct DPatches {
   int ell_width = 0;
   T* w = nullptr;
   T* Y = nullptr;
+  // batched path: outputs at (off[p] + slot) * nr + k, maps in that numbering
+  int* ell_c = nullptr;
+  int* inv_ptr_c = nullptr;
+  int* inv_pos_c = nullptr;
+  T* Ynr = nullptr;
+  int nr_chunk = 0;  // right-hand sides per workgroup of the batched patch kernel (LDS bound)
 };
 
 template <typename T>
@@ -286,6 +292,7 @@ struct Level {
 struct CycleBase {
   virtual ~CycleBase() = default;
   virtual void apply(const double* r, double* z, hipStream_t s) = 0;
+  virtual void set_nr(int nr) = 0;
 };
 
 // Optional event timing of the two kernel families of the cycle, with the
@@ -336,6 +343,7 @@ struct Cycle : CycleBase {
   int64_t nfree0 = 0, ndir0 = 0;
   mas_params par{};
   int dim = 2;
+  int nr = 1, nr_max = 1;  // right-hand sides of the current application / allocated for
   Timing* tm = nullptr;
   // Scott-Vogelius pressure transfers (Section 3.1): P0^p duplication, R0^p = M_cg^-1 (P0^p)^T M_dg
   bool sv = false;
@@ -347,10 +355,10 @@ struct Cycle : CycleBase {
 
   // b1 = eta R0 r0
   void restrict0(const T* r0, Level<T>& L1, hipStream_t s) {
-    const int64_t nv = L1.nvel;
+    const int64_t nv = L1.nvel * nr;
     if (!sv) {  // Taylor-Hood: injection
-      hipLaunchKernelGGL((k_scale2<T>), dim3(blocks_for(L1.n, 256)), dim3(256), 0, s, L1.n, nv, (T)par.eta_u,
-                         (T)par.eta_p, r0, L1.b);
+      hipLaunchKernelGGL((k_scale2<T>), dim3(blocks_for(L1.n * nr, 256)), dim3(256), 0, s, L1.n * nr, nv,
+                         (T)par.eta_u, (T)par.eta_p, r0, L1.b);
       launch_check();
       return;
     }
@@ -360,20 +368,20 @@ struct Cycle : CycleBase {
     spmv<0>(P0t, sv_t0, nullptr, sv_t1, s);     // (P0^p)^T M_dg r0_p
     // M_cg z = t1: Jacobi-preconditioned Chebyshev with the P1 bounds lambda(D^-1 M) in [1/2, 2]
     chebyshev_iv(Mcg, sv_t1, sv_z, 0.5, 2.0, mass_steps, mcg_dinv, sv_cd, sv_cres, s);
-    hipLaunchKernelGGL((k_axpby<T>), dim3(blocks_for(np1, 256)), dim3(256), 0, s, np1, (T)par.eta_p, sv_z, (T)0,
-                       L1.b + nv);
+    hipLaunchKernelGGL((k_axpby<T>), dim3(blocks_for(np1 * nr, 256)), dim3(256), 0, s, np1 * nr, (T)par.eta_p,
+                       sv_z, (T)0, L1.b + nv);
     launch_check();
   }
 
   // x0 (+)= P0 x1
   void prolong0(Level<T>& L1, Level<T>& L0, bool x_zero, hipStream_t s) {
     if (!sv) {
-      hipLaunchKernelGGL((k_axpby<T>), dim3(blocks_for(L0.n, 256)), dim3(256), 0, s, L0.n, (T)1, L1.x,
+      hipLaunchKernelGGL((k_axpby<T>), dim3(blocks_for(L0.n * nr, 256)), dim3(256), 0, s, L0.n * nr, (T)1, L1.x,
                          x_zero ? (T)0 : (T)1, L0.x);
       launch_check();
       return;
     }
-    const int64_t nv = L1.nvel;
+    const int64_t nv = L1.nvel * nr;
     hipLaunchKernelGGL((k_axpby<T>), dim3(blocks_for(nv, 256)), dim3(256), 0, s, nv, (T)1, L1.x,
                        x_zero ? (T)0 : (T)1, L0.x);
     launch_check();
@@ -387,11 +395,17 @@ struct Cycle : CycleBase {
     hipEvent_t e0{}, e1{};
     const bool t = tm && tm->on;
     if (t) tm->begin(e0, e1, s);
-    csr_launch<T, MODE>(A, x, b, y, s);
+    if (nr == 1) {
+      csr_launch<T, MODE>(A, x, b, y, s);
+    } else if (A.n > 0) {
+      hipLaunchKernelGGL((k_spmm<T, MODE>), dim3(blocks_for(A.n * nr, 256)), dim3(256), 0, s, A.n, nr, A.ptr, A.ind,
+                         A.val, x, b, y);
+      launch_check();
+    }
     if (t) {
       HIPCHECK(hipEventRecord(e1, s));
       const double sz = sizeof(T);
-      const double vec = A.m * sz + A.n * sz * (MODE == 0 ? 1.0 : 2.0);
+      const double vec = (A.m * sz + A.n * sz * (MODE == 0 ? 1.0 : 2.0)) * nr;
       tm->spmv.push_back({e0, e1, A.nnz * (sz + 4.0) + (A.n + 1) * 4.0 + vec});
     }
   }
@@ -400,17 +414,17 @@ struct Cycle : CycleBase {
   // spectrum interval [lo, hi] of D^-1 X (D^-1 = dinv, identity when null)
   void chebyshev_iv(DCsr<T>& X, const T* r, T* y, double lo, double hi, int deg, const T* dinv, T* cd, T* cres,
                     hipStream_t s) {
-    const int64_t n = X.n;
+    const int64_t n = X.n * nr;
     const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
     double rho = 1.0 / sigma;
     const unsigned nb = blocks_for(n, 256);
-    hipLaunchKernelGGL((k_cheb_init<T>), dim3(nb), dim3(256), 0, s, n, r, (T)(1.0 / theta), dinv, cd, cres, y);
+    hipLaunchKernelGGL((k_cheb_init<T>), dim3(nb), dim3(256), 0, s, n, r, (T)(1.0 / theta), dinv, cd, cres, y, nr);
     launch_check();
     for (int k = 0; k + 1 < deg; ++k) {
       spmv<3>(X, cd, nullptr, cres, s);
       const double rho_new = 1.0 / (2.0 * sigma - rho);
       hipLaunchKernelGGL((k_cheb_update<T>), dim3(nb), dim3(256), 0, s, n, (T)(rho_new * rho),
-                         (T)(2.0 * rho_new / delta), dinv, cres, cd, y);
+                         (T)(2.0 * rho_new / delta), dinv, cres, cd, y, nr);
       launch_check();
       rho = rho_new;
     }
@@ -424,7 +438,7 @@ struct Cycle : CycleBase {
   // one DLSC sweep (Algorithm 2) on level L: x = (u, p), b = (f, g)
   void dlsc_sweep(Level<T>& L, hipStream_t s) {
     DDlsc<T>& D = L.dl;
-    const int64_t nv = D.nv, np = D.np;
+    const int64_t nv = D.nv * nr, np = D.np * nr;
     T* u = L.x;
     T* p = L.x + nv;
     const T* f = L.b;
@@ -437,9 +451,9 @@ struct Cycle : CycleBase {
     spmv<1>(D.B, D.tmp, g, D.rp, s);  // rp = g - B (u + v*)
     chebyshev(D.S, D.rp, D.q, D.lamS, par.cheb_deg[1], D, s);  // continuity
     spmv<0>(D.Bt, D.q, nullptr, D.t1, s);  // t1 = M^-1 B^T q
-    hipLaunchKernelGGL((k_mul<T>), dim3(bv), dim3(256), 0, s, nv, D.minv, D.t1);
+    hipLaunchKernelGGL((k_mul<T>), dim3(bv), dim3(256), 0, s, nv, D.minv, D.t1, nr);
     spmv<0>(D.A, D.t1, nullptr, D.t2, s);  // t2 = M^-1 A M^-1 B^T q
-    hipLaunchKernelGGL((k_mul<T>), dim3(bv), dim3(256), 0, s, nv, D.minv, D.t2);
+    hipLaunchKernelGGL((k_mul<T>), dim3(bv), dim3(256), 0, s, nv, D.minv, D.t2, nr);
     spmv<0>(D.B, D.t2, nullptr, D.rp, s);  // rp = B t2; the right-hand side is -rp
     hipLaunchKernelGGL((k_axpby<T>), dim3(bp), dim3(256), 0, s, np, (T)0, D.rp, (T)-1, D.rp);
     chebyshev(D.S, D.rp, D.dp, D.lamS, par.cheb_deg[2], D, s);  // pressure correction
@@ -452,7 +466,7 @@ struct Cycle : CycleBase {
   void relax_level(Level<T>& L, int sweeps, T omega, bool x_zero, hipStream_t s) {
     if (L.dl.on) {
       if (x_zero) {
-        hipLaunchKernelGGL((k_fill<T>), dim3(blocks_for(L.n, 256)), dim3(256), 0, s, L.n, L.x, (T)0);
+        hipLaunchKernelGGL((k_fill<T>), dim3(blocks_for(L.n * nr, 256)), dim3(256), 0, s, L.n * nr, L.x, (T)0);
         launch_check();
       }
       for (int k = 0; k < sweeps; ++k) dlsc_sweep(L, s);
@@ -463,6 +477,16 @@ struct Cycle : CycleBase {
 
   void patch_solve(Level<T>& L, const T* rin, hipStream_t s) {
     DPatches<T>& pt = L.pt;
+    if (nr > 1) {
+      if (pt.nr_chunk < 1) throw MasError(MAS_EINVAL, "patches too large for the batched kernel");
+      const int chunk = std::min(pt.nr_chunk, nr);
+      const size_t shm = (size_t)(pt.max_f + 2 * (int64_t)pt.max_m * chunk) * sizeof(T);
+      hipLaunchKernelGGL((k_vanka_apply_nr<T>), dim3((unsigned)pt.np, (unsigned)((nr + chunk - 1) / chunk)), dim3(WAVE),
+                         shm, s, pt.np, nr, pt.off, pt.dims, pt.foff, pt.fstride, pt.dofs, pt.fac, rin, pt.Ynr,
+                         pt.max_m, pt.max_f, chunk);
+      launch_check();
+      return;
+    }
     for (const FastBucket& fb : pt.fast) {
       const unsigned nb = blocks_for(fb.P, 256);
       const int* d = fb.dofs;
@@ -506,10 +530,21 @@ struct Cycle : CycleBase {
         HIPCHECK(hipEventRecord(e1, s));
         const double sz = sizeof(T);
         // factor records + DoF lists + patch outputs + one read of the level vector
-        const double bytes = L.pt.nfac_alg * sz + L.pt.ndofs * (4.0 + sz) + L.n * sz;
+        const double bytes = L.pt.nfac_alg * sz + L.pt.ndofs * (4.0 + sz * nr) + L.n * sz * nr;
         tm->vanka.push_back({e0, e1, bytes});
       }
       const int acc = (k == 0 && x_zero) ? 0 : 1;
+      if (nr > 1) {
+        const unsigned nb = blocks_for(L.n * nr, 256);
+        if (L.pt.ell_c)
+          hipLaunchKernelGGL((k_vanka_pull_ell_nr<T>), dim3(nb), dim3(256), 0, s, (int)L.n, nr, L.pt.ell_width,
+                             L.pt.ell_c, L.pt.Ynr, omega, L.x, acc);
+        else
+          hipLaunchKernelGGL((k_vanka_pull_nr<T>), dim3(nb), dim3(256), 0, s, (int)L.n, nr, L.pt.inv_ptr_c,
+                             L.pt.inv_pos_c, L.pt.Ynr, L.pt.w, omega, L.x, acc);
+        launch_check();
+        continue;
+      }
       if (L.pt.ell)
         hipLaunchKernelGGL((k_vanka_pull_ell<T>), dim3(blocks_for(L.n, 256)), dim3(256), 0, s, (int)L.n,
                            L.pt.ell_width, L.pt.ell, L.pt.Y, omega, L.x, acc);
@@ -524,8 +559,12 @@ struct Cycle : CycleBase {
   void vcycle(size_t l, hipStream_t s) {
     Level<T>& L = lev[l];
     if (l + 1 == lev.size()) {
-      hipLaunchKernelGGL((k_dense_gemv<T>), dim3(blocks_for(L.n * WAVE, 256)), dim3(256), 0, s, (int)L.n,
-                         (int)ld, Cinv, L.b, L.x);
+      if (nr == 1)
+        hipLaunchKernelGGL((k_dense_gemv<T>), dim3(blocks_for(L.n * WAVE, 256)), dim3(256), 0, s, (int)L.n,
+                           (int)ld, Cinv, L.b, L.x);
+      else
+        hipLaunchKernelGGL((k_dense_gemm<T>), dim3(blocks_for(L.n * nr, 256)), dim3(256), 0, s, (int)L.n, (int)ld,
+                           nr, Cinv, L.b, L.x);
       launch_check();
       return;
     }
@@ -551,10 +590,17 @@ struct Cycle : CycleBase {
     if (L.relax && par.nu2 > 0) relax_level(L, par.nu2, om, false, s);
   }
 
+  void set_nr(int k) override { nr = k; }
+
   void apply(const double* r, double* z, hipStream_t s) override {
     Level<T>& L0 = lev[0];
     Level<T>& L1 = lev[1];
-    hipLaunchKernelGGL((k_gather<T, double>), dim3(blocks_for(nfree0, 256)), dim3(256), 0, s, nfree0, free0, r, L0.b);
+    if (nr == 1)
+      hipLaunchKernelGGL((k_gather<T, double>), dim3(blocks_for(nfree0, 256)), dim3(256), 0, s, nfree0, free0, r,
+                         L0.b);
+    else
+      hipLaunchKernelGGL((k_gather_nr<T, double>), dim3(blocks_for(nfree0 * nr, 256)), dim3(256), 0, s, nfree0, nr,
+                         free0, r, L0.b);
     launch_check();
     bool x_zero = true;
     if (L0.relax && par.nu1 > 0) {
@@ -570,12 +616,18 @@ struct Cycle : CycleBase {
     vcycle(1, s);
     prolong0(L1, L0, x_zero, s);  // x0 += P0 x1
     if (L0.relax && par.nu2 > 0) relax_level(L0, par.nu2, (T)par.omega0, false, s);
-    hipLaunchKernelGGL((k_scatter<double, T>), dim3(blocks_for(nfree0, 256)), dim3(256), 0, s, nfree0, free0, L0.x, z);
-    launch_check();
-    if (ndir0) {  // Dirichlet rows are identity rows: z_D = r_D
-      hipLaunchKernelGGL(k_copy_idx, dim3(blocks_for(ndir0, 256)), dim3(256), 0, s, ndir0, dir0, r, z);
-      launch_check();
+    if (nr == 1) {
+      hipLaunchKernelGGL((k_scatter<double, T>), dim3(blocks_for(nfree0, 256)), dim3(256), 0, s, nfree0, free0, L0.x,
+                         z);
+      if (ndir0)  // Dirichlet rows are identity rows: z_D = r_D
+        hipLaunchKernelGGL(k_copy_idx, dim3(blocks_for(ndir0, 256)), dim3(256), 0, s, ndir0, dir0, r, z);
+    } else {
+      hipLaunchKernelGGL((k_scatter_nr<double, T>), dim3(blocks_for(nfree0 * nr, 256)), dim3(256), 0, s, nfree0, nr,
+                         free0, L0.x, z);
+      if (ndir0)
+        hipLaunchKernelGGL(k_copy_idx_nr, dim3(blocks_for(ndir0 * nr, 256)), dim3(256), 0, s, ndir0, nr, dir0, r, z);
     }
+    launch_check();
   }
 };
 
@@ -673,7 +725,7 @@ void dense_inverse(DevArena& ar, double* A, int n, hipStream_t s) {
 }
 
 template <typename T>
-void build_patches(DevArena& ar, Level<T>& L, const PatchSet& ps, const DCsr<double>& K64, int level,
+void build_patches(DevArena& ar, Level<T>& L, const PatchSet& ps, const DCsr<double>& K64, int level, int nr_max,
                    hipStream_t s) {
   DPatches<T>& d = L.pt;
   const int64_t np = ps.np();
@@ -794,6 +846,24 @@ void build_patches(DevArena& ar, Level<T>& L, const PatchSet& ps, const DCsr<dou
       if (cnt[j] > 0) w[j] = 1.0 / (double)cnt[j];
     d.w = ar.upload<T>(w, s);
   }
+  if (nr_max > 1) {
+    // batched path: outputs at (off[p] + slot) * nr + k
+    std::vector<int32_t> cpos(dofs.size());
+    std::vector<int32_t> fillc(iptr.begin(), iptr.end() - 1);
+    for (size_t q = 0; q < dofs.size(); ++q) cpos[fillc[dofs[q]]++] = (int32_t)q;
+    if (d.ell) {
+      std::vector<int32_t> ellc((size_t)width * n, -1);
+      for (int64_t j = 0; j < n; ++j)
+        for (int32_t q = iptr[j]; q < iptr[j + 1]; ++q) ellc[(size_t)(q - iptr[j]) * n + j] = cpos[q];
+      d.ell_c = ar.upload<int>(ellc, s);
+    } else {
+      d.inv_ptr_c = d.inv_ptr;
+      d.inv_pos_c = ar.upload<int>(cpos, s);
+    }
+    d.Ynr = ar.alloc<T>((size_t)d.ndofs * nr_max);
+    const int64_t room = (int64_t)(kMaxLds / sizeof(T)) - d.max_f;
+    d.nr_chunk = room > 0 ? (int)std::min<int64_t>(WAVE, room / (2 * (int64_t)d.max_m)) : 0;
+  }
   d.off = ar.upload<int64_t>(off, s);
   {
     int4* dd = ar.alloc<int4>(np);
@@ -846,6 +916,7 @@ std::unique_ptr<Cycle<T>> build_cycle(mas_handle* h, const std::vector<Csr>& Ks,
   auto cyc = std::make_unique<Cycle<T>>();
   cyc->par = h->par;
   cyc->dim = h->dim;
+  cyc->nr_max = std::max(1, h->par.nrhs_max);
   cyc->tm = &h->tm;
   const size_t nl = Ks.size();
   cyc->lev.resize(nl);
@@ -855,9 +926,9 @@ std::unique_ptr<Cycle<T>> build_cycle(mas_handle* h, const std::vector<Csr>& Ks,
     L.nvel = 0;
     for (int8_t f : fields[l]) L.nvel += (f < h->dim);
     L.relax = relax[l];
-    L.x = ar.alloc<T>(L.n);
-    L.b = ar.alloc<T>(L.n);
-    L.r = ar.alloc<T>(L.n);
+    L.x = ar.alloc<T>((size_t)L.n * cyc->nr_max);
+    L.b = ar.alloc<T>((size_t)L.n * cyc->nr_max);
+    L.r = ar.alloc<T>((size_t)L.n * cyc->nr_max);
     if (l + 1 < nl) {
       L.K = upload_csr<T>(ar, Ks[l], s);
       if (l >= 1) {
@@ -868,7 +939,7 @@ std::unique_ptr<Cycle<T>> build_cycle(mas_handle* h, const std::vector<Csr>& Ks,
         DCsr<double> K64;
         if constexpr (std::is_same<T, double>::value) K64 = L.K;
         else K64 = upload_csr<double>(ar, Ks[l], s);
-        build_patches<T>(ar, L, patches[l], K64, (int)l, s);
+        build_patches<T>(ar, L, patches[l], K64, (int)l, cyc->nr_max, s);
       }
       if (L.relax && dlsc[l].A.nr > 0) {
         const HostDlsc& H = dlsc[l];
@@ -883,10 +954,11 @@ std::unique_ptr<Cycle<T>> build_cycle(mas_handle* h, const std::vector<Csr>& Ks,
         D.minv = ar.upload<T>(H.minv, s);
         D.lamA = H.lamA;
         D.lamS = H.lamS;
-        for (T** v : {&D.ru, &D.vs, &D.tmp, &D.t1, &D.t2}) *v = ar.alloc<T>(D.nv);
-        for (T** v : {&D.rp, &D.q, &D.dp}) *v = ar.alloc<T>(D.np);
-        D.cd = ar.alloc<T>(std::max(D.nv, D.np));
-        D.cres = ar.alloc<T>(std::max(D.nv, D.np));
+        const int64_t R = cyc->nr_max;
+        for (T** v : {&D.ru, &D.vs, &D.tmp, &D.t1, &D.t2}) *v = ar.alloc<T>(D.nv * R);
+        for (T** v : {&D.rp, &D.q, &D.dp}) *v = ar.alloc<T>(D.np * R);
+        D.cd = ar.alloc<T>(std::max(D.nv, D.np) * R);
+        D.cres = ar.alloc<T>(std::max(D.nv, D.np) * R);
       }
     }
   }
@@ -930,11 +1002,12 @@ std::unique_ptr<Cycle<T>> build_cycle(mas_handle* h, const std::vector<Csr>& Ks,
     cyc->Mcg = upload_csr<T>(ar, pl.Mcg, s);
     cyc->mcg_dinv = ar.upload<T>(pl.mcg_dinv, s);
     cyc->mass_steps = pl.mass_steps;
-    cyc->sv_t0 = ar.alloc<T>(cyc->np0);
-    cyc->sv_t1 = ar.alloc<T>(cyc->np1);
-    cyc->sv_z = ar.alloc<T>(cyc->np1);
-    cyc->sv_cd = ar.alloc<T>(cyc->np1);
-    cyc->sv_cres = ar.alloc<T>(cyc->np1);
+    const int64_t R = cyc->nr_max;
+    cyc->sv_t0 = ar.alloc<T>(cyc->np0 * R);
+    cyc->sv_t1 = ar.alloc<T>(cyc->np1 * R);
+    cyc->sv_z = ar.alloc<T>(cyc->np1 * R);
+    cyc->sv_cd = ar.alloc<T>(cyc->np1 * R);
+    cyc->sv_cres = ar.alloc<T>(cyc->np1 * R);
     for (DCsr<T>* A : {&cyc->Mdg, &cyc->P0t, &cyc->P0p, &cyc->Mcg}) A->use_sell = false;
   }
   return cyc;
@@ -959,6 +1032,7 @@ void analyze_impl(mas_handle* h, const mas_problem* pr) {
   if (!pr->field0 || !pr->field1 || !pr->dir0 || !pr->dir1) throw MasError(MAS_EINVAL, "missing field or Dirichlet map");
   h->n0 = n0;
   if (par.restart < 1 || par.restart > 200) throw MasError(MAS_EINVAL, "restart must be in [1, 200]");
+  if (par.nrhs_max < 1 || par.nrhs_max > 64) throw MasError(MAS_EINVAL, "nrhs_max must be in [1, 64]");
   if (par.max_coarse < 1 || par.max_levels < 1) throw MasError(MAS_EINVAL, "bad coarsening limits");
   std::vector<int64_t> free0, dir0, free1;
   std::vector<int8_t> f0, f1;
@@ -1189,13 +1263,14 @@ void upload_impl(mas_handle* h, hipStream_t s) {
   h->ndir = (int64_t)pl.dir0.size();
   if (!pl.pw.empty()) h->pw = h->arena.upload<double>(pl.pw, s);
   const int m = std::max(1, par.restart);
-  h->V = h->arena.alloc<double>((size_t)(m + 1) * n0);
-  h->Z = h->arena.alloc<double>((size_t)m * n0);
-  h->w = h->arena.alloc<double>(n0);
-  h->partial = h->arena.alloc<double>(2 * h->nblk_dot);
-  h->hdev = h->arena.alloc<double>(m + 2);
-  h->ydev = h->arena.alloc<double>(m + 1);
-  HIPCHECK(hipHostMalloc((void**)&h->hhost, (m + 2) * sizeof(double), hipHostMallocDefault));
+  const int64_t R = std::max(1, par.nrhs_max);
+  h->V = h->arena.alloc<double>((size_t)(m + 1) * n0 * R);
+  h->Z = h->arena.alloc<double>((size_t)m * n0 * R);
+  h->w = h->arena.alloc<double>((size_t)n0 * R);
+  h->partial = h->arena.alloc<double>((size_t)2 * h->nblk_dot * R);
+  h->hdev = h->arena.alloc<double>((size_t)(m + 2) * R);
+  h->ydev = h->arena.alloc<double>((size_t)(m + 1) * R);
+  HIPCHECK(hipHostMalloc((void**)&h->hhost, (size_t)(m + 2) * R * sizeof(double), hipHostMallocDefault));
   HIPCHECK(hipStreamCreateWithFlags(&h->gs, hipStreamNonBlocking));
   HIPCHECK(hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming));
   HIPCHECK(hipEventCreateWithFlags(&h->ev_out, hipEventDisableTiming));
@@ -1376,6 +1451,194 @@ int fgmres(mas_handle* h, const double* b, double* x, double rtol, int max_it, m
   return converged ? MAS_OK : MAS_NOT_CONVERGED;
 }
 
+// FGMRES for nr right-hand sides at once: independent Krylov spaces per column,
+// advanced in lockstep so every cycle application is batched.  Each column has
+// its own Givens rotations and tolerance; a column stops rotating once its
+// estimate reaches its tolerance, and its iterate uses its own Krylov size.
+int fgmres_nr(mas_handle* h, const double* b, double* x, int nr, double rtol, int max_it, mas_solve_info* info,
+              hipStream_t s) {
+  const int64_t n = h->n0;
+  const int m = std::max(1, h->par.restart);
+  int nrp = 1;
+  while (nrp < nr) nrp *= 2;
+  const unsigned nb = (unsigned)h->nblk_dot;
+  double* r = h->w;
+  auto col_norms = [&](const double* v, std::vector<double>& out) {
+    hipLaunchKernelGGL(k_mgs_step_nr, dim3(nb), dim3(256), 0, s, n, nr, nrp, const_cast<double*>(v), nullptr, nullptr,
+                       nullptr, nullptr, h->partial, 1);
+    hipLaunchKernelGGL(k_reduce_final_nr, dim3(1), dim3(64), 0, s, (int)nb, nr, h->partial, h->hdev, 1);
+    launch_check();
+    HIPCHECK(hipMemcpyAsync(h->hhost, h->hdev, nr * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    out.assign(h->hhost, h->hhost + nr);
+  };
+  std::vector<double> bnorm, beta;
+  col_norms(b, bnorm);
+  hipLaunchKernelGGL((k_fill<double>), dim3(blocks_for(n * nr, 256)), dim3(256), 0, s, n * nr, x, 0.0);
+  HIPCHECK(hipMemcpyAsync(r, b, n * nr * sizeof(double), hipMemcpyDeviceToDevice, s));
+  std::vector<double> target(nr);
+  std::vector<int> done(nr, 0), iters(nr, 0);
+  std::vector<std::vector<double>> hist(nr);
+  for (int k = 0; k < nr; ++k) {
+    if (!std::isfinite(bnorm[k])) {
+      if (info) for (int q = 0; q < nr; ++q) info[q] = mas_solve_info{0, 0, NAN, NAN};
+      return MAS_ENAN;
+    }
+    target[k] = rtol * bnorm[k];
+    done[k] = bnorm[k] == 0.0;
+    hist[k].push_back(bnorm[k]);
+  }
+  beta = bnorm;
+  int it = 0;
+  std::vector<double> H((size_t)nr * (m + 1) * m), cs((size_t)nr * m), sn((size_t)nr * m), g((size_t)nr * (m + 1));
+  std::vector<int> kcol(nr);
+  h->cyc->set_nr(nr);
+  while (true) {
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    std::vector<int> active(nr);
+    for (int k = 0; k < nr; ++k) {
+      g[(size_t)k * (m + 1)] = beta[k];
+      active[k] = !done[k];
+      kcol[k] = 0;
+    }
+    std::memcpy(h->hhost, beta.data(), nr * sizeof(double));
+    HIPCHECK(hipMemcpyAsync(h->hdev, h->hhost, nr * sizeof(double), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_scale_cols, dim3(blocks_for(n * nr, 256)), dim3(256), 0, s, n, nr, h->hdev, r, h->V);
+    launch_check();
+    int kk = 0;
+    for (int j = 0; j < m; ++j) {
+      double* vj = h->V + (int64_t)j * n * nr;
+      double* zj = h->Z + (int64_t)j * n * nr;
+      h->cyc->apply(vj, zj, s);
+      double* w = h->w;
+      hipLaunchKernelGGL((k_spmm<double, 0>), dim3(blocks_for(n * nr, 256)), dim3(256), 0, s, n, nr, h->K0full.ptr,
+                         h->K0full.ind, h->K0full.val, zj, nullptr, w);
+      double* part[2] = {h->partial, h->partial + (size_t)nb * nr};
+      for (int i = 0; i <= j + 1; ++i) {
+        const double* vprev = i > 0 ? h->V + (int64_t)(i - 1) * n * nr : nullptr;
+        double* hprev = i > 0 ? h->hdev + (size_t)(i - 1) * nr : nullptr;
+        const double* pprev = i > 0 ? part[(i - 1) & 1] : nullptr;
+        const double* vnext = i <= j ? h->V + (int64_t)i * n * nr : nullptr;
+        hipLaunchKernelGGL(k_mgs_step_nr, dim3(nb), dim3(256), 0, s, n, nr, nrp, w, vprev, hprev, pprev, vnext,
+                           part[i & 1], i <= j ? 0 : 1);
+      }
+      hipLaunchKernelGGL(k_normalize_nr, dim3(nb), dim3(256), 0, s, n, nr, part[(j + 1) & 1], (int)nb,
+                         h->hdev + (size_t)(j + 1) * nr, w, h->V + (int64_t)(j + 1) * n * nr);
+      launch_check();
+      HIPCHECK(hipMemcpyAsync(h->hhost, h->hdev, (size_t)(j + 2) * nr * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipStreamSynchronize(s));
+      ++it;
+      kk = j + 1;
+      bool any = false;
+      if (std::getenv("MAS_DEBUG_FGMRES")) {
+        std::fprintf(stderr, "[fgmres_nr] it %d j %d h:", it, j);
+        for (int k = 0; k < nr; ++k) std::fprintf(stderr, " %.3e/%.3e", h->hhost[(size_t)j * nr + k], h->hhost[(size_t)(j + 1) * nr + k]);
+        std::fprintf(stderr, "\n");
+      }
+      for (int k = 0; k < nr; ++k) {
+        if (!active[k]) continue;
+        double* Hk = &H[(size_t)k * (m + 1) * m];
+        double* ck = &cs[(size_t)k * m];
+        double* sk = &sn[(size_t)k * m];
+        double* gk = &g[(size_t)k * (m + 1)];
+        for (int i = 0; i <= j + 1; ++i) Hk[(size_t)i * m + j] = h->hhost[(size_t)i * nr + k];
+        for (int i = 0; i < j; ++i) {
+          double t = ck[i] * Hk[(size_t)i * m + j] + sk[i] * Hk[(size_t)(i + 1) * m + j];
+          Hk[(size_t)(i + 1) * m + j] = -sk[i] * Hk[(size_t)i * m + j] + ck[i] * Hk[(size_t)(i + 1) * m + j];
+          Hk[(size_t)i * m + j] = t;
+        }
+        const double den = std::hypot(Hk[(size_t)j * m + j], Hk[(size_t)(j + 1) * m + j]);
+        kcol[k] = j + 1;
+        if (den == 0.0) {  // breakdown: the column is solved in this space
+          active[k] = 0;
+          continue;
+        }
+        ck[j] = Hk[(size_t)j * m + j] / den;
+        sk[j] = Hk[(size_t)(j + 1) * m + j] / den;
+        Hk[(size_t)j * m + j] = den;
+        Hk[(size_t)(j + 1) * m + j] = 0.0;
+        gk[j + 1] = -sk[j] * gk[j];
+        gk[j] = ck[j] * gk[j];
+        const double est = std::fabs(gk[j + 1]);
+        hist[k].push_back(est);
+        if (!std::isfinite(est)) {
+          if (info) for (int q = 0; q < nr; ++q) info[q] = mas_solve_info{it, 0, NAN, NAN};
+          h->cyc->set_nr(1);
+          return MAS_ENAN;
+        }
+        if (est <= target[k]) active[k] = 0;
+        else any = true;
+      }
+      if (!any || it >= max_it) break;
+    }
+    // per-column least-squares solutions, x += Z y
+    std::vector<double> y((size_t)kk * nr, 0.0);
+    for (int k = 0; k < nr; ++k) {
+      const double* Hk = &H[(size_t)k * (m + 1) * m];
+      const double* gk = &g[(size_t)k * (m + 1)];
+      const int kc = kcol[k];
+      for (int i = kc - 1; i >= 0; --i) {
+        if (Hk[(size_t)i * m + i] == 0.0) continue;
+        double t = gk[i];
+        for (int q = i + 1; q < kc; ++q) t -= Hk[(size_t)i * m + q] * y[(size_t)q * nr + k];
+        y[(size_t)i * nr + k] = t / Hk[(size_t)i * m + i];
+      }
+    }
+    std::memcpy(h->hhost, y.data(), y.size() * sizeof(double));
+    HIPCHECK(hipMemcpyAsync(h->ydev, h->hhost, y.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_update_x_nr, dim3(blocks_for(n * nr, 256)), dim3(256), 0, s, n, nr, kk, h->Z, h->ydev, x);
+    hipLaunchKernelGGL((k_spmm<double, 1>), dim3(blocks_for(n * nr, 256)), dim3(256), 0, s, n, nr, h->K0full.ptr,
+                       h->K0full.ind, h->K0full.val, x, b, r);
+    launch_check();
+    col_norms(r, beta);
+    bool all = true;
+    for (int k = 0; k < nr; ++k) {
+      if (!std::isfinite(beta[k])) {
+        if (info) for (int q = 0; q < nr; ++q) info[q] = mas_solve_info{it, 0, NAN, NAN};
+        h->cyc->set_nr(1);
+        return MAS_ENAN;
+      }
+      if (!done[k] && beta[k] <= target[k]) {
+        done[k] = 1;
+        iters[k] = it - kk + kcol[k];
+      }
+      all = all && done[k];
+    }
+    if (all || it >= max_it) break;
+  }
+  for (int k = 0; k < nr; ++k)
+    if (!done[k]) iters[k] = it;
+  // zero-mean pressure per column
+  if (h->p_nullspace && h->pw) {
+    const int64_t np0 = n - h->nu0;
+    hipLaunchKernelGGL(k_wdot_nr, dim3(nb), dim3(256), 0, s, np0, nr, nrp, h->pw, x + h->nu0 * nr, h->partial);
+    hipLaunchKernelGGL(k_reduce_final_nr, dim3(1), dim3(64), 0, s, (int)nb, nr, h->partial, h->hdev, 0);
+    launch_check();
+    HIPCHECK(hipMemcpyAsync(h->hhost, h->hdev, nr * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    for (int k = 0; k < nr; ++k) h->hhost[k] = -h->hhost[k] / h->pw_sum;
+    HIPCHECK(hipMemcpyAsync(h->hdev, h->hhost, nr * sizeof(double), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_add_cols, dim3(blocks_for(np0 * nr, 256)), dim3(256), 0, s, np0, nr, h->hdev,
+                       x + h->nu0 * nr);
+    launch_check();
+    HIPCHECK(hipStreamSynchronize(s));
+  }
+  h->cyc->set_nr(1);
+  bool all = true;
+  for (int k = 0; k < nr; ++k) {
+    all = all && done[k];
+    if (info) {
+      info[k].iters = iters[k];
+      info[k].converged = done[k];
+      info[k].relres = bnorm[k] > 0 ? beta[k] / bnorm[k] : 0.0;
+      const auto& hh = hist[k];
+      info[k].conv_factor = hh.size() >= 11 ? std::pow(hh.back() / hh[hh.size() - 11], 0.1) : NAN;
+    }
+  }
+  return all ? MAS_OK : MAS_NOT_CONVERGED;
+}
+
 int fail(const MasError& e) {
   g_last_error = e.what();
   return e.code;
@@ -1414,6 +1677,7 @@ void mas_default_params(int32_t dim, int32_t disc, int32_t relax, mas_params* ou
   p.theta = 0.02;
   p.seed = 0x5EED;
   p.mass_rtol = 1e-14;
+  p.nrhs_max = 1;
   *out = p;
 }
 
@@ -1473,14 +1737,17 @@ int mas_apply(mas_handle* h, const double* r, double* z, int32_t nrhs, void* str
     g_last_error = "handle was analysed only; call mas_setup";
     return MAS_EINVAL;
   }
-  if (nrhs != 1) {
-    g_last_error = "this build applies one right-hand side at a time";
+  if (nrhs < 1 || nrhs > std::max(1, h->par.nrhs_max)) {
+    g_last_error = "nrhs must be in [1, nrhs_max]";
     return MAS_EINVAL;
   }
   try {
     hipStream_t s = (hipStream_t)stream;
+    h->cyc->set_nr(nrhs);
     h->cyc->apply(r, z, s);
+    h->cyc->set_nr(1);
   } catch (const MasError& e) {
+    h->cyc->set_nr(1);
     return fail(e);
   }
   return MAS_OK;
@@ -1496,8 +1763,8 @@ int mas_solve(mas_handle* h, const double* b, double* x, int32_t nrhs, double rt
     g_last_error = "handle was analysed only; call mas_setup";
     return MAS_EINVAL;
   }
-  if (nrhs != 1) {
-    g_last_error = "this build solves one right-hand side at a time";
+  if (nrhs < 1 || nrhs > std::max(1, h->par.nrhs_max)) {
+    g_last_error = "nrhs must be in [1, nrhs_max]";
     return MAS_EINVAL;
   }
   try {
@@ -1505,7 +1772,7 @@ int mas_solve(mas_handle* h, const double* b, double* x, int32_t nrhs, double rt
     hipStream_t s = h->gs;
     HIPCHECK(hipEventRecord(h->ev_in, us));
     HIPCHECK(hipStreamWaitEvent(s, h->ev_in, 0));
-    int rc = fgmres(h, b, x, rtol, max_it, info, s);
+    int rc = nrhs == 1 ? fgmres(h, b, x, rtol, max_it, info, s) : fgmres_nr(h, b, x, nrhs, rtol, max_it, info, s);
     HIPCHECK(hipEventRecord(h->ev_out, s));
     HIPCHECK(hipStreamWaitEvent(us, h->ev_out, 0));
     if (h->tm.on) {
