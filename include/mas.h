@@ -123,6 +123,7 @@ typedef struct {
   int64_t factor_entries[16]; /* stored factor values per level (packed symmetric blocks) */
   int64_t p_nnz[16];      /* entries of P_l (level l -> l-1), 0 for l <= 1 */
   int64_t coarse_n;       /* rows of the dense coarsest solve (incl. border) */
+  int64_t device_bytes;   /* device memory held by the handle (0 after mas_analyze) */
 } mas_hier_info;
 
 /* Default parameters: Section 4 / Tables 3 and 4 where the paper fixes them. */
@@ -155,6 +156,17 @@ int mas_solve(mas_handle* h, const double* b, double* x, int32_t nrhs, double rt
 
 /* Sizes of the built hierarchy. */
 int mas_get_info(const mas_handle* h, mas_hier_info* out);
+
+/* x (device FP64, n0 x nrhs row-major): velocity rows of column k times s_u[k],
+ * pressure rows times s_p[k] (s_u, s_p: host arrays of nrhs); with
+ * dirichlet_inverse, Dirichlet rows get 1 / s_u[k] instead.  With
+ * S = diag(sqrt(nu) I, I / sqrt(nu)) the free-free block of the operator with
+ * viscosity nu is S K S (K the nu = 1 operator, Dirichlet rows identity in
+ * both), so several viscosities can share one hierarchy: c = S^-1 b on free
+ * rows and S b on Dirichlet rows (dirichlet_inverse = 1), solve K y = c, then
+ * x = S^-1 y (dirichlet_inverse = 0).  Synchronises the stream. */
+int mas_scale_rows(mas_handle* h, double* x, int32_t nrhs, const double* s_u, const double* s_p,
+                   int32_t dirichlet_inverse, void* stream);
 
 /* Copy level l's operator (0 = free K0, 1 = free K1, ...) to host CSR.  Call
  * with indptr == NULL to get the sizes. */

@@ -428,6 +428,24 @@ __global__ void k_update_x_nr(int64_t n, int nr, int kmax, const double* __restr
   x[t] = s;
 }
 
+// x[i, k] *= (i < nsplit ? su[k] : sp[k])  (field scaling of nr columns)
+__global__ void k_scale_rows_nr(int64_t n, int nr, int64_t nsplit, const double* __restrict__ su,
+                                const double* __restrict__ sp, double* __restrict__ x) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n * nr) {
+    const int64_t i = t / nr;
+    const int k = (int)(t % nr);
+    x[t] *= (i < nsplit ? su[k] : sp[k]);
+  }
+}
+
+// x[idx[q], k] *= c[k]
+__global__ void k_scale_idx_nr(int64_t n, int nr, const int64_t* __restrict__ idx, const double* __restrict__ c,
+                               double* __restrict__ x) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n * nr) x[idx[t / nr] * nr + t % nr] *= c[t % nr];
+}
+
 // x[i, k] += c_k for the rows i of one block (zero-mean pressure shift)
 __global__ void k_add_cols(int64_t n, int nr, const double* __restrict__ c, double* __restrict__ x) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -1789,6 +1789,45 @@ int mas_solve(mas_handle* h, const double* b, double* x, int32_t nrhs, double rt
 int mas_get_info(const mas_handle* h, mas_hier_info* out) {
   if (!h || !out) return MAS_EINVAL;
   *out = h->info;
+  out->device_bytes = (int64_t)h->arena.bytes;
+  return MAS_OK;
+}
+
+int mas_scale_rows(mas_handle* h, double* x, int32_t nrhs, const double* s_u, const double* s_p,
+                   int32_t dirichlet_inverse, void* stream) {
+  if (!h || !x || !s_u || !s_p || nrhs < 1 || nrhs > 64) {
+    g_last_error = "bad argument";
+    return MAS_EINVAL;
+  }
+  if (!h->on_device) {
+    g_last_error = "handle was analysed only; call mas_setup";
+    return MAS_EINVAL;
+  }
+  try {
+    hipStream_t s = (hipStream_t)stream;
+    double* d = h->ydev;  // 2 * nrhs factors staged through pinned memory
+    if ((size_t)(h->par.restart + 1) * std::max(1, h->par.nrhs_max) < (size_t)2 * nrhs)
+      throw MasError(MAS_EINVAL, "nrhs too large for this handle");
+    HIPCHECK(hipStreamSynchronize(s));
+    std::memcpy(h->hhost, s_u, nrhs * sizeof(double));
+    std::memcpy(h->hhost + nrhs, s_p, nrhs * sizeof(double));
+    HIPCHECK(hipMemcpyAsync(d, h->hhost, 2 * nrhs * sizeof(double), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_scale_rows_nr, dim3(blocks_for(h->n0 * nrhs, 256)), dim3(256), 0, s, h->n0, nrhs, h->nu0, d,
+                       d + nrhs, x);
+    launch_check();
+    if (dirichlet_inverse && h->ndir) {
+      // identity rows: net factor 1 / s_u
+      HIPCHECK(hipStreamSynchronize(s));
+      for (int k = 0; k < nrhs; ++k) h->hhost[k] = 1.0 / (s_u[k] * s_u[k]);
+      HIPCHECK(hipMemcpyAsync(d, h->hhost, nrhs * sizeof(double), hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(k_scale_idx_nr, dim3(blocks_for(h->ndir * nrhs, 256)), dim3(256), 0, s, h->ndir, nrhs,
+                         h->dir_idx, d, x);
+      launch_check();
+    }
+    HIPCHECK(hipStreamSynchronize(s));
+  } catch (const MasError& e) {
+    return fail(e);
+  }
   return MAS_OK;
 }
 

@@ -51,7 +51,8 @@ class mas_solve_info(C.Structure):
 class mas_hier_info(C.Structure):
     _fields_ = [("n_levels", C.c_int32), ("n", C.c_int64 * 16), ("nnz", C.c_int64 * 16),
                 ("n_vel", C.c_int64 * 16), ("n_patches", C.c_int64 * 16), ("patch_dofs", C.c_int64 * 16),
-                ("factor_entries", C.c_int64 * 16), ("p_nnz", C.c_int64 * 16), ("coarse_n", C.c_int64)]
+                ("factor_entries", C.c_int64 * 16), ("p_nnz", C.c_int64 * 16), ("coarse_n", C.c_int64),
+                ("device_bytes", C.c_int64)]
 
 
 def _load():
@@ -69,6 +70,8 @@ def _load():
     lib.mas_get_info.argtypes = [C.c_void_p, P(mas_hier_info)]
     lib.mas_export_level.argtypes = [C.c_void_p, C.c_int32, P(C.c_int64), P(C.c_int64), C.c_void_p,
                                      C.c_void_p, C.c_void_p]
+    lib.mas_scale_rows.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, P(C.c_double), P(C.c_double), C.c_int32,
+                                   C.c_void_p]
     lib.mas_set_timing.argtypes = [C.c_void_p, C.c_int32]
     lib.mas_get_timing.argtypes = [C.c_void_p, P(C.c_double), C.c_int32]
     lib.mas_destroy.argtypes = [C.c_void_p]
@@ -76,7 +79,7 @@ def _load():
     lib.mas_error_string.restype = C.c_char_p
     lib.mas_last_error.argtypes = []
     lib.mas_last_error.restype = C.c_char_p
-    for name in ("mas_setup", "mas_analyze", "mas_apply", "mas_solve", "mas_get_info", "mas_export_level", "mas_set_timing",
+    for name in ("mas_setup", "mas_analyze", "mas_scale_rows", "mas_apply", "mas_solve", "mas_get_info", "mas_export_level", "mas_set_timing",
                  "mas_get_timing", "mas_destroy"):
         getattr(lib, name).restype = C.c_int
     return lib
@@ -84,7 +87,7 @@ def _load():
 
 lib = _load()
 
-EXPORTED = ("mas_default_params", "mas_setup", "mas_analyze", "mas_apply", "mas_solve", "mas_get_info", "mas_export_level",
+EXPORTED = ("mas_default_params", "mas_setup", "mas_analyze", "mas_scale_rows", "mas_apply", "mas_solve", "mas_get_info", "mas_export_level",
             "mas_set_timing", "mas_get_timing", "mas_destroy", "mas_error_string", "mas_last_error")
 
 
@@ -194,7 +197,14 @@ class Handle:
         L = hi.n_levels
         return dict(n_levels=L, n=list(hi.n[:L]), nnz=list(hi.nnz[:L]), n_vel=list(hi.n_vel[:L]),
                     n_patches=list(hi.n_patches[:L]), patch_dofs=list(hi.patch_dofs[:L]),
-                    factor_entries=list(hi.factor_entries[:L]), p_nnz=list(hi.p_nnz[:L]), coarse_n=hi.coarse_n)
+                    factor_entries=list(hi.factor_entries[:L]), p_nnz=list(hi.p_nnz[:L]), coarse_n=hi.coarse_n,
+                    device_bytes=hi.device_bytes)
+
+    def scale_rows(self, x, s_u, s_p, nrhs: int = 1, dirichlet_inverse: bool = False, stream=None):
+        su = (C.c_double * nrhs)(*[float(v) for v in s_u])
+        sp = (C.c_double * nrhs)(*[float(v) for v in s_p])
+        _check(lib.mas_scale_rows(self.h, C.c_void_p(x.data_ptr()), nrhs, su, sp, 1 if dirichlet_inverse else 0,
+                                  _stream(stream)))
 
     def export_level(self, level: int):
         import scipy.sparse as sp
