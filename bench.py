@@ -43,6 +43,13 @@ def parse():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-its", type=int, default=2)
+    ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate / closed-loop capacity")
+    ap.add_argument("--serve-sweep", type=float, nargs="*", default=[])
+    ap.add_argument("--serve-batch", type=int, default=32)
+    ap.add_argument("--serve-workers", type=int, default=4)
+    ap.add_argument("--serve-small-gb", type=float, default=0.0)
+    ap.add_argument("--serve-baseline-open", action="store_true")
     return ap.parse_args()
 
 
@@ -64,12 +71,139 @@ def cpu_baseline(prob, its_gpu, sample_its):
                       f"{its_gpu} iterations of one solve; oracle setup and patch-matrix extraction untimed"}
 
 
+def run_stream(srv, stream, rhs, rate, serving):
+    """Submit the stream with Poisson arrivals at ``rate`` requests/s (0 = all
+    at once, closed loop) and wait for every result."""
+    reqs = [serving.Request(mesh=q["mesh"], nu=q["nu"], b=rhs[i]) for i, q in enumerate(stream)]
+    t0 = time.perf_counter()
+    t_next = t0
+    for q, r in zip(stream, reqs):
+        if rate > 0:
+            t_next += q["gap"] / rate
+            dt = t_next - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+        srv.submit(r)
+    for r in reqs:
+        assert r.done.wait(600), "request not finished after 600 s"
+    t1 = max(r.t_done for r in reqs)
+    bad = [r.error for r in reqs if r.error is not None]
+    assert not bad, f"{len(bad)} requests failed: {bad[:3]}"
+    out = {"solves_per_s": len(reqs) / (t1 - t0), "wall_s": t1 - t0,
+           "mean_batch": float(np.mean([r.batch for r in reqs])),
+           "iters_mean": float(np.mean([r.iters for r in reqs]))}
+    out.update(serving.latency_percentiles(reqs))
+    return out, reqs
+
+
+def bench_serve(a):
+    """Serving stream: 512 requests with Poisson arrivals over eight meshes
+    (2D Taylor-Hood 32^2..256^2, 3D 8^3..24^3), viscosity log-uniform in
+    [1e-2, 1], Gaussian forcing, hierarchies resident on the device."""
+    import torch
+
+    from paper_2306_06795_amd import mas, serving
+    from paper_2306_06795_amd.inputs import SERVE_MESHES, make_serve_mesh, random_rhs, serve_stream
+
+    t0 = time.perf_counter()
+    probs = {f"th{d}d_{n}": make_serve_mesh(d, n) for d, n in SERVE_MESHES}
+    stream = serve_stream(a.serve_requests, seed=5)
+    rhs = [random_rhs(probs[q["mesh"]], np.random.default_rng(q["rhs_seed"])) for q in stream]
+    t_gen = time.perf_counter() - t0
+    full = int(torch.cuda.get_device_properties(0).total_memory * 0.8)
+
+    def server(budget, precision, max_batch, workers):
+        srv = serving.StokesServer(budget, max_batch=max_batch, workers=workers, precision=precision)
+        for k, P in probs.items():
+            srv.add_mesh(k, P)
+        srv.start()
+        return srv
+
+    def warm(srv):  # first upload of every hierarchy, outside the timed streams
+        for k, P in probs.items():
+            r = srv.submit(serving.Request(mesh=k, nu=1.0, b=random_rhs(P, np.random.default_rng(0))))
+            assert r.done.wait(600), "warm-up request not finished after 600 s"
+            assert r.error is None, r.error
+
+    t0 = time.perf_counter()
+    srv = server(full, mas.MAS_FP32, a.serve_batch, a.serve_workers)
+    try:  # the worker threads must be joined before the interpreter exits, also on failure
+        warm(srv)
+        t_setup = time.perf_counter() - t0
+        print(f"[serve] {len(stream)} requests, inputs {t_gen:.1f}s, analysis+upload {t_setup:.1f}s, "
+              f"resident {srv.stats()['resident_bytes'] / 2**30:.2f} GiB", file=sys.stderr, flush=True)
+        closed, _ = run_stream(srv, stream, rhs, 0.0, serving)
+        cap = closed["solves_per_s"]
+        print(f"[serve] closed loop: {closed}", file=sys.stderr, flush=True)
+        rate = a.serve_load * cap
+        main_run, reqs = run_stream(srv, stream, rhs, rate, serving)
+        print(f"[serve] open loop at {rate:.1f}/s: {main_run}", file=sys.stderr, flush=True)
+        sweep = {}
+        for f in a.serve_sweep:
+            sweep[f"{f:g}x"], _ = run_stream(srv, stream, rhs, f * cap, serving)
+            print(f"[serve] {f:g}x: {sweep[f'{f:g}x']}", file=sys.stderr, flush=True)
+        st_full = srv.stats()
+    finally:
+        srv.shutdown()
+    # forced small budget: evictions and re-uploads inside the stream
+    small = None
+    if a.serve_small_gb > 0:
+        srv = server(int(a.serve_small_gb * 2**30), mas.MAS_FP32, a.serve_batch, a.serve_workers)
+        try:
+            small, _ = run_stream(srv, stream, rhs, rate, serving)
+            small.update(budget_gib=a.serve_small_gb, **{k: v for k, v in srv.stats().items()
+                                                           if k in ("uploads", "evictions", "peak_resident_bytes")})
+        finally:
+            srv.shutdown()
+        print(f"[serve] budget {a.serve_small_gb} GiB: {small}", file=sys.stderr, flush=True)
+    # baseline: the same stream one request at a time, plain FP64 cycle
+    srv = server(full, mas.MAS_FP64, 1, 1)
+    try:
+        warm(srv)
+        base_closed, _ = run_stream(srv, stream, rhs, 0.0, serving)
+        base_open, _ = run_stream(srv, stream, rhs, rate, serving) if a.serve_baseline_open else (None, None)
+    finally:
+        srv.shutdown()
+    print(f"[serve] one-at-a-time FP64: {base_closed}", file=sys.stderr, flush=True)
+    out = {
+        "metric": "serving solves/s to 1e-8 rel. residual (p50/p99 latency)",
+        "value": main_run["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": len(stream),
+        "warmup": len(probs),
+        "ms_per_step": 1e3 / main_run["solves_per_s"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 cycle / f64 FGMRES",
+        "data": "synthetic",
+        "config": {"workload": "serve: 512 Poisson-arrival requests (seed 5), Taylor-Hood meshes 2D 32^2/64^2/"
+                               "128^2/256^2 and 3D 8^3/12^3/16^3/24^3, viscosity log-uniform [1e-2,1], Gaussian "
+                               "forcing, homogeneous Dirichlet, FGMRES(20) rtol 1e-8",
+                   "arrival_rate_per_s": rate, "load_factor": a.serve_load, "max_batch": a.serve_batch,
+                   "workers": a.serve_workers, "hbm_budget_gib": full / 2**30},
+        "p50_ms": main_run["p50_ms"],
+        "p99_ms": main_run["p99_ms"],
+        "closed_loop": closed,
+        "open_loop": main_run,
+        "load_sweep": sweep,
+        "small_budget": small,
+        "baseline_one_at_a_time_fp64": {"closed_loop": base_closed, "open_loop_same_rate": base_open},
+        "throughput_vs_one_at_a_time": cap / base_closed["solves_per_s"],
+        "resident_gib": st_full["peak_resident_bytes"] / 2**30,
+    }
+    print(json.dumps(out))
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the multi-GPU layout is a design note, "
               "not built", file=sys.stderr)
         sys.exit(2)
+    if a.config == "serve":
+        return bench_serve(a)
     import torch
 
     from paper_2306_06795_amd import mas

@@ -137,9 +137,22 @@ void mas_default_params(int32_t dim, int32_t disc, int32_t relax, mas_params* ou
 int mas_setup(const mas_problem* prob, const mas_params* par, void* stream, mas_handle** out);
 
 /* Host-only analysis: the hierarchy (Algorithm 1) and the patches, without
- * touching the GPU.  The handle supports mas_get_info, mas_export_level and
- * mas_destroy only (no device is needed).  Errors as mas_setup. */
+ * touching the GPU.  Until mas_upload the handle supports mas_get_info,
+ * mas_export_level and mas_destroy only (no device is needed).  Errors as
+ * mas_setup. */
 int mas_analyze(const mas_problem* prob, const mas_params* par, mas_handle** out);
+
+/* Move an analysed (or released) handle onto the current device: the device
+ * half of mas_setup (operator upload, patch factorisation, coarse inverse,
+ * solver workspace).  No-op for a handle already on the device.  On error the
+ * handle is left analysed-only.  Errors: MAS_ENOMEM, MAS_ESINGULAR_PATCH,
+ * MAS_EHIP. */
+int mas_upload(mas_handle* h, void* stream);
+
+/* Free every device resource of the handle (waits for the device first),
+ * keeping the host analysis so that mas_upload can restore it without
+ * repeating Algorithm 1.  mas_get_info then reports device_bytes = 0. */
+int mas_release(mas_handle* h);
 
 /* z = B r: one defect-correction cycle (eq. (3.1)) applied to nrhs right-hand
  * sides.  r, z: device FP64, n0 x nrhs row-major (right-hand side fastest).
@@ -153,6 +166,14 @@ int mas_apply(mas_handle* h, const double* r, double* z, int32_t nrhs, void* str
  * MAS_NOT_CONVERGED or an error.  Synchronises the stream. */
 int mas_solve(mas_handle* h, const double* b, double* x, int32_t nrhs, double rtol,
               int32_t max_it, mas_solve_info* info, void* stream);
+
+/* mas_solve with one tolerance per right-hand side (rtol: host array of nrhs,
+ * each >= 0).  Column k stops updating once ||b_k - K0 x_k|| <= rtol[k] ||b_k||,
+ * so a column's result does not depend on the tolerances of the columns
+ * solved beside it.  Errors as mas_solve (MAS_EINVAL for a negative or NaN
+ * tolerance). */
+int mas_solve_rtols(mas_handle* h, const double* b, double* x, int32_t nrhs, const double* rtol,
+                    int32_t max_it, mas_solve_info* info, void* stream);
 
 /* Sizes of the built hierarchy. */
 int mas_get_info(const mas_handle* h, mas_hier_info* out);

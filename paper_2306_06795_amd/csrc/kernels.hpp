@@ -214,7 +214,18 @@ __global__ void __launch_bounds__(256) k_spmm(int64_t n, int nr, const int* __re
   const int64_t row = t / nr;
   const int k = (int)(t % nr);
   T s = 0;
-  for (int e = ptr[row]; e < ptr[row + 1]; ++e) s += val[e] * x[(int64_t)ind[e] * nr + k];
+  int e = ptr[row];
+  const int end = ptr[row + 1];
+  for (; e + 3 < end; e += 4) {  // four gathers in flight, sums in the same order
+    const int c0 = ind[e], c1 = ind[e + 1], c2 = ind[e + 2], c3 = ind[e + 3];
+    const T x0 = x[(int64_t)c0 * nr + k], x1 = x[(int64_t)c1 * nr + k];
+    const T x2 = x[(int64_t)c2 * nr + k], x3 = x[(int64_t)c3 * nr + k];
+    s += val[e] * x0;
+    s += val[e + 1] * x1;
+    s += val[e + 2] * x2;
+    s += val[e + 3] * x3;
+  }
+  for (; e < end; ++e) s += val[e] * x[(int64_t)ind[e] * nr + k];
   if (MODE == 0) y[t] = s;
   else if (MODE == 1) y[t] = b[t] - s;
   else if (MODE == 2) y[t] += s;
@@ -234,72 +245,115 @@ __global__ void __launch_bounds__(256) k_dense_gemm(int n, int ld, int nr, const
   y[t] = (T)s;
 }
 
-// patch solves for nr right-hand sides: one workgroup per patch and chunk of
-// right-hand sides, one lane per right-hand side; the factor record is staged
-// in LDS (element q of patch p at foff[p] + q * fstride[p]) and read as
-// broadcasts, the patch's right-hand sides and results live in LDS.
-// Y holds the result of slot s of patch p at (off[p] + s) * nr + k.
-template <typename T>
-__global__ void __launch_bounds__(64) k_vanka_apply_nr(int64_t np, int nr, const int64_t* __restrict__ off,
-                                                      const int4* __restrict__ dims,
-                                                      const int64_t* __restrict__ foff,
-                                                      const int64_t* __restrict__ fstride,
-                                                      const int* __restrict__ dofs, const T* __restrict__ fac,
-                                                      const T* __restrict__ r, T* __restrict__ Y, int max_m,
-                                                      int64_t max_f, int chunk) {
+template <typename T, int KT>
+struct __attribute__((aligned(sizeof(T) * KT > 16 ? 16 : sizeof(T) * KT))) VecT {
+  T v[KT];
+};
+
+// Patch solves for nr right-hand sides: one 256-thread workgroup per patch and
+// chunk of C right-hand sides (C a multiple of KT).  The patch's right-hand
+// sides sit in LDS as an m x C block; thread t owns velocity row t / G
+// (G = C / KT) for the KT right-hand sides of group t % G, keeps their sums in
+// registers and reads its row of the factor block once per KT right-hand
+// sides.  The factor record (element q of patch p at foff[p] + q * fstride[p])
+// is staged in LDS (STAGE) or, when too large, read from global memory; the
+// G threads of a row read the same address.  Y holds the result of slot s of
+// patch p at (off[p] + s) * nr + k.
+template <typename T, int KT, bool STAGE>
+__global__ void __launch_bounds__(256) k_vanka_apply_nr(int64_t np, int nr, int C, const int64_t* __restrict__ off,
+                                                       const int4* __restrict__ dims,
+                                                       const int64_t* __restrict__ foff,
+                                                       const int64_t* __restrict__ fstride,
+                                                       const int* __restrict__ dofs, const T* __restrict__ fac,
+                                                       const T* __restrict__ r, T* __restrict__ Y, int max_m,
+                                                       int64_t max_f) {
   extern __shared__ unsigned char smem_raw[];
-  T* sf = reinterpret_cast<T*>(smem_raw);
-  T* sb = sf + max_f;
-  T* sy = sb + (int64_t)max_m * chunk;
+  T* sb = reinterpret_cast<T*>(smem_raw);   // max_m x C
+  T* st = sb + (int64_t)max_m * C;          // MAX_NS x C: Uhat^T b_u + b_p
+  T* syp = st + MAX_NS * C;                 // MAX_NS x C: y_p
+  T* sf = syp + MAX_NS * C;                 // record (STAGE)
+  int* sd = reinterpret_cast<int*>(sf + (STAGE ? max_f : 0));  // patch DoFs
   const int64_t p = blockIdx.x;
   if (p >= np) return;
-  const int lane = threadIdx.x;
-  const int k0 = blockIdx.y * chunk;
-  const int kk = k0 + lane;
-  const bool active = lane < chunk && kk < nr;
+  const int tid = threadIdx.x;
+  const int k0 = blockIdx.y * C;
   const int4 d = dims[p];
-  const int nc[3] = {d.x, d.y, d.z};
-  const int nv = d.x + d.y + d.z, ns = d.w, m = nv + ns;
-  const int64_t nf = (int64_t)d.x * (d.x + 1) / 2 + (int64_t)d.y * (d.y + 1) / 2 + (int64_t)d.z * (d.z + 1) / 2 +
-                     (int64_t)nv * ns + (int64_t)ns * (ns + 1) / 2;
+  const int n0 = d.x, n1 = d.y, n2 = d.z;
+  const int nv = n0 + n1 + n2, ns = d.w, m = nv + ns;
+  const int64_t a1 = (int64_t)n0 * (n0 + 1) / 2, a2 = a1 + (int64_t)n1 * (n1 + 1) / 2;
+  const int64_t uo = a2 + (int64_t)n2 * (n2 + 1) / 2, so = uo + (int64_t)nv * ns;
+  const int64_t nf = so + (int64_t)ns * (ns + 1) / 2;
   const int64_t o = off[p], f0 = foff[p], fs = fstride[p];
-  for (int64_t q = lane; q < nf; q += WAVE) sf[q] = fac[f0 + q * fs];
-  if (active)
-    for (int j = 0; j < m; ++j) sb[j * chunk + lane] = r[(int64_t)dofs[o + j] * nr + kk];
+  for (int j = tid; j < m; j += 256) sd[j] = dofs[o + j];
+  if (STAGE)
+    for (int64_t q = tid; q < nf; q += 256) sf[q] = fac[f0 + q * fs];
   __syncthreads();
-  if (active) {
-    int cs = 0;
-    int64_t ao = 0;
-    for (int c = 0; c < 3; ++c) {
-      const int n = nc[c];
-      const T* A = sf + ao;
-      for (int i = 0; i < n; ++i) {
-        T acc = 0;
-        for (int j = 0; j < n; ++j) acc += A[packed_index(i, j)] * sb[(cs + j) * chunk + lane];
-        sy[(cs + i) * chunk + lane] = acc;
-      }
-      ao += (int64_t)n * (n + 1) / 2;
-      cs += n;
+  for (int idx = tid; idx < m * C; idx += 256) {
+    const int j = idx / C, k = idx - j * C;
+    sb[idx] = k0 + k < nr ? r[(int64_t)sd[j] * nr + k0 + k] : (T)0;
+  }
+  __syncthreads();
+  auto F = [&](int64_t q) -> T { return STAGE ? sf[q] : fac[f0 + q * fs]; };
+  // t = Uhat^T b_u + b_p, then y_p = S^-1 t
+  for (int idx = tid; idx < ns * C; idx += 256) {
+    const int s = idx / C, k = idx - s * C;
+    T acc = sb[(nv + s) * C + k];
+    for (int q = 0; q < nv; ++q) acc += F(uo + (int64_t)s * nv + q) * sb[q * C + k];
+    st[idx] = acc;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < ns * C; idx += 256) {
+    const int s = idx / C, k = idx - s * C;
+    T acc = 0;
+    for (int q = 0; q < ns; ++q) acc += F(so + packed_index(s, q)) * st[q * C + k];
+    syp[idx] = acc;
+    if (k0 + k < nr) Y[(o + nv + s) * nr + k0 + k] = acc;
+  }
+  __syncthreads();
+  // x_u = A^-1 b_u + Uhat y_p, row by row
+  const int G = C / KT;
+  const int kg = tid % G;
+  for (int row = tid / G; row < nv; row += 256 / G) {
+    int cs, n, i;
+    int64_t ao;
+    if (row < n0) {
+      cs = 0, n = n0, i = row, ao = 0;
+    } else if (row < n0 + n1) {
+      cs = n0, n = n1, i = row - n0, ao = a1;
+    } else {
+      cs = n0 + n1, n = n2, i = row - n0 - n1, ao = a2;
     }
-    const T* U = sf + ao;
-    const T* Si = U + (int64_t)nv * ns;
-    T t[MAX_NS], yp[MAX_NS];
+    T acc[KT];
+#pragma unroll
+    for (int kk = 0; kk < KT; ++kk) acc[kk] = 0;
+    const T* bcol = sb + kg * KT;
+    // j < i: packed entries i (i + 1) / 2 + j are contiguous
+    const int64_t base = ao + (int64_t)i * (i + 1) / 2;
+    for (int j = 0; j < i; ++j) {
+      const T a = F(base + j);
+      const VecT<T, KT> bv = *reinterpret_cast<const VecT<T, KT>*>(bcol + (cs + j) * C);
+#pragma unroll
+      for (int kk = 0; kk < KT; ++kk) acc[kk] += a * bv.v[kk];
+    }
+    // j >= i: entry at j (j + 1) / 2 + i
+    int64_t q = base + i;
+    for (int j = i; j < n; ++j) {
+      const T a = F(q);
+      q += j + 1;
+      const VecT<T, KT> bv = *reinterpret_cast<const VecT<T, KT>*>(bcol + (cs + j) * C);
+#pragma unroll
+      for (int kk = 0; kk < KT; ++kk) acc[kk] += a * bv.v[kk];
+    }
     for (int s = 0; s < ns; ++s) {
-      T acc = sb[(nv + s) * chunk + lane];
-      for (int q = 0; q < nv; ++q) acc += U[(int64_t)s * nv + q] * sb[q * chunk + lane];
-      t[s] = acc;
+      const T u = F(uo + (int64_t)s * nv + row);
+      const VecT<T, KT> yv = *reinterpret_cast<const VecT<T, KT>*>(syp + s * C + kg * KT);
+#pragma unroll
+      for (int kk = 0; kk < KT; ++kk) acc[kk] += u * yv.v[kk];
     }
-    for (int s = 0; s < ns; ++s) {
-      T acc = 0;
-      for (int q = 0; q < ns; ++q) acc += Si[packed_index(s, q)] * t[q];
-      yp[s] = acc;
-    }
-    for (int row = 0; row < nv; ++row) {
-      T acc = sy[row * chunk + lane];
-      for (int s = 0; s < ns; ++s) acc += U[(int64_t)s * nv + row] * yp[s];
-      Y[(o + row) * nr + kk] = acc;
-    }
-    for (int s = 0; s < ns; ++s) Y[(o + nv + s) * nr + kk] = yp[s];
+    T* yrow = Y + (o + row) * nr + k0 + kg * KT;
+#pragma unroll
+    for (int kk = 0; kk < KT; ++kk)
+      if (k0 + kg * KT + kk < nr) yrow[kk] = acc[kk];
   }
 }
 
@@ -313,7 +367,22 @@ __global__ void k_vanka_pull_ell_nr(int n, int nr, int width, const int* __restr
   const int k = (int)(t % nr);
   T acc = 0;
   int cnt = 0;
-  for (int s = 0; s < width; ++s) {
+  int s = 0;
+  for (; s + 3 < width; s += 4) {  // four gathers in flight, sums in slot order
+    int q[4];
+    T v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) q[u] = pos[(int64_t)(s + u) * n + j];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = q[u] >= 0 ? Y[(int64_t)q[u] * nr + k] : (T)0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (q[u] >= 0) {
+        acc += v[u];
+        ++cnt;
+      }
+  }
+  for (; s < width; ++s) {
     const int q = pos[(int64_t)s * n + j];
     if (q >= 0) {
       acc += Y[(int64_t)q * nr + k];
@@ -352,16 +421,45 @@ __global__ void __launch_bounds__(256) k_mgs_step_nr(int64_t n, int nr, int nrp,
                                                     const double* __restrict__ vnext,
                                                     double* __restrict__ partial_out, int mode) {
   __shared__ double sh[256];
+  __shared__ double sa[64];
   const int k = threadIdx.x % nrp, g = threadIdx.x / nrp, ng = 256 / nrp;
   const bool col = k < nr;
   double a = 0.0;
-  if (prev_partial && col) {
-    for (unsigned b = 0; b < gridDim.x; ++b) a += prev_partial[(int64_t)b * nr + k];
-    if (blockIdx.x == 0 && g == 0) hprev[k] = a;
+  if (prev_partial) {  // h of the previous step: the block's groups split the partial sums
+    double t = 0.0;
+    if (col)
+      for (unsigned b = g; b < gridDim.x; b += ng) t += prev_partial[(int64_t)b * nr + k];
+    sh[threadIdx.x] = t;
+    __syncthreads();
+    if (g == 0 && col) {
+      double u = 0.0;
+      for (int q = 0; q < ng; ++q) u += sh[q * nrp + k];
+      sa[k] = u;
+      if (blockIdx.x == 0) hprev[k] = u;
+    }
+    __syncthreads();
+    if (col) a = sa[k];
   }
   double s = 0.0;
-  if (col)
-    for (int64_t i = (int64_t)blockIdx.x * ng + g; i < n; i += (int64_t)gridDim.x * ng) {
+  if (col) {
+    const int64_t stride = (int64_t)gridDim.x * ng;
+    int64_t i = (int64_t)blockIdx.x * ng + g;
+    for (; i + 3 * stride < n; i += 4 * stride) {  // four rows in flight
+      double wi[4], vn[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t e = (i + u * stride) * nr + k;
+        wi[u] = w[e];
+        if (vprev) wi[u] -= a * vprev[e];
+        vn[u] = mode == 0 ? vnext[e] : wi[u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (vprev) w[(i + u * stride) * nr + k] = wi[u];
+        s += wi[u] * vn[u];
+      }
+    }
+    for (; i < n; i += stride) {
       const int64_t e = i * nr + k;
       double wi = w[e];
       if (vprev) {
@@ -370,6 +468,8 @@ __global__ void __launch_bounds__(256) k_mgs_step_nr(int64_t n, int nr, int nrp,
       }
       s += wi * (mode == 0 ? vnext[e] : wi);
     }
+  }
+  __syncthreads();
   sh[threadIdx.x] = s;
   __syncthreads();
   if (g == 0 && col) {
@@ -384,13 +484,23 @@ __global__ void __launch_bounds__(256) k_normalize_nr(int64_t n, int nr, const d
                                                      double* __restrict__ hout, const double* __restrict__ w,
                                                      double* __restrict__ v) {
   __shared__ double nrm[64];
-  for (int k = threadIdx.x; k < nr; k += blockDim.x) {
+  __shared__ double sh[256];
+  {  // the block's threads split the partial sums of each column
+    const int nrp = nr <= 1 ? 1 : 1 << (32 - __clz(nr - 1));
+    const int k = threadIdx.x % nrp, g = threadIdx.x / nrp, ng = 256 / nrp;
     double t = 0.0;
-    for (int b = 0; b < nb; ++b) t += partial[(int64_t)b * nr + k];
-    nrm[k] = sqrt(t);
-    if (blockIdx.x == 0) hout[k] = nrm[k];
+    if (k < nr)
+      for (int b = g; b < nb; b += ng) t += partial[(int64_t)b * nr + k];
+    sh[threadIdx.x] = t;
+    __syncthreads();
+    if (g == 0 && k < nr) {
+      double u = 0.0;
+      for (int q = 0; q < ng; ++q) u += sh[q * nrp + k];
+      nrm[k] = sqrt(u);
+      if (blockIdx.x == 0) hout[k] = nrm[k];
+    }
+    __syncthreads();
   }
-  __syncthreads();
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n * nr; t += (int64_t)gridDim.x * blockDim.x) {
     const double q = nrm[t % nr];
     v[t] = q != 0.0 ? w[t] / q : 0.0;

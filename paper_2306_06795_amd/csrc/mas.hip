@@ -48,6 +48,14 @@ inline void launch_check() {
 inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 constexpr size_t kMaxLds = 64 * 1024;  // dynamic LDS per workgroup used by the patch kernels
+constexpr int kNrKT = 4;                // right-hand sides per thread in the batched patch kernel
+
+// LDS of the batched patch kernel: m x C block, two MAX_NS x C blocks, the
+// staged record (f values) and the patch DoF list
+template <typename T>
+size_t nr_lds_bytes(int64_t max_m, int C, int64_t f) {
+  return (size_t)(max_m * C + 2 * MAX_NS * C + f) * sizeof(T) + (size_t)max_m * sizeof(int);
+}
 
 // Patch shapes (DoFs per velocity component x3, seeds) served by the
 // thread-per-patch kernel: interior 2D Taylor-Hood / P1isoP2 patches, interior
@@ -86,9 +94,12 @@ struct DevArena {
     }
     return d;
   }
-  ~DevArena() {
+  void release() {
     for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+    bytes = 0;
   }
+  ~DevArena() { release(); }
 };
 
 // Sparse operator on the device: CSR (TEAM lanes per row) and, when the
@@ -264,6 +275,7 @@ struct DPatches {
   int* inv_pos_c = nullptr;
   T* Ynr = nullptr;
   int nr_chunk = 0;  // right-hand sides per workgroup of the batched patch kernel (LDS bound)
+  bool nr_stage = true;  // the batched kernel stages factor records in LDS
 };
 
 template <typename T>
@@ -479,11 +491,16 @@ struct Cycle : CycleBase {
     DPatches<T>& pt = L.pt;
     if (nr > 1) {
       if (pt.nr_chunk < 1) throw MasError(MAS_EINVAL, "patches too large for the batched kernel");
-      const int chunk = std::min(pt.nr_chunk, nr);
-      const size_t shm = (size_t)(pt.max_f + 2 * (int64_t)pt.max_m * chunk) * sizeof(T);
-      hipLaunchKernelGGL((k_vanka_apply_nr<T>), dim3((unsigned)pt.np, (unsigned)((nr + chunk - 1) / chunk)), dim3(WAVE),
-                         shm, s, pt.np, nr, pt.off, pt.dims, pt.foff, pt.fstride, pt.dofs, pt.fac, rin, pt.Ynr,
-                         pt.max_m, pt.max_f, chunk);
+      int C = kNrKT;
+      while (C < nr && C < pt.nr_chunk) C *= 2;
+      const dim3 grid((unsigned)pt.np, (unsigned)((nr + C - 1) / C));
+      const size_t shm = nr_lds_bytes<T>(pt.max_m, C, pt.nr_stage ? pt.max_f : 0);
+      if (pt.nr_stage)
+        hipLaunchKernelGGL((k_vanka_apply_nr<T, kNrKT, true>), grid, dim3(256), shm, s, pt.np, nr, C, pt.off, pt.dims,
+                           pt.foff, pt.fstride, pt.dofs, pt.fac, rin, pt.Ynr, pt.max_m, pt.max_f);
+      else
+        hipLaunchKernelGGL((k_vanka_apply_nr<T, kNrKT, false>), grid, dim3(256), shm, s, pt.np, nr, C, pt.off, pt.dims,
+                           pt.foff, pt.fstride, pt.dofs, pt.fac, rin, pt.Ynr, pt.max_m, pt.max_f);
       launch_check();
       return;
     }
@@ -861,8 +878,19 @@ void build_patches(DevArena& ar, Level<T>& L, const PatchSet& ps, const DCsr<dou
       d.inv_pos_c = ar.upload<int>(cpos, s);
     }
     d.Ynr = ar.alloc<T>((size_t)d.ndofs * nr_max);
-    const int64_t room = (int64_t)(kMaxLds / sizeof(T)) - d.max_f;
-    d.nr_chunk = room > 0 ? (int)std::min<int64_t>(WAVE, room / (2 * (int64_t)d.max_m)) : 0;
+    // right-hand sides per workgroup (a power of two from kNrKT to 64) of the
+    // batched kernel: its m x C block must fit in LDS.  The factor record is
+    // staged too when that still leaves room for min(16, nr_max) of them.
+    auto max_c = [&](int64_t f) {
+      int c = 0;
+      for (int t = kNrKT; t <= 64; t *= 2)
+        if (nr_lds_bytes<T>(d.max_m, t, f) <= kMaxLds) c = t;
+      return c;
+    };
+    const int want = std::min(16, std::max(kNrKT, nr_max));
+    const int c_stage = max_c(d.max_f), c_plain = max_c(0);
+    d.nr_stage = c_stage >= want;
+    d.nr_chunk = d.nr_stage ? c_stage : c_plain;
   }
   d.off = ar.upload<int64_t>(off, s);
   {
@@ -1277,12 +1305,30 @@ void upload_impl(mas_handle* h, hipStream_t s) {
   h->iter_graph.assign(m, nullptr);
   h->use_graphs = std::getenv("MAS_NO_GRAPHS") == nullptr;
   HIPCHECK(hipStreamSynchronize(s));
-  // the host plan is no longer needed except for export
-  pl.patches.clear();
-  pl.patches.shrink_to_fit();
-  pl.dlsc.clear();
-  pl.dlsc.shrink_to_fit();
-  h->on_device = true;
+  h->on_device = true;  // the host plan stays: mas_release / mas_upload rebuild from it
+}
+
+// Frees every device resource of the handle; the host analysis stays.
+void release_device(mas_handle* h) {
+  if (!h->on_device && !h->gs && !h->hhost && h->arena.ptrs.empty()) return;  // nothing on the device
+  (void)hipDeviceSynchronize();  // work of the caller's streams may still read the handle's arrays
+  for (hipGraphExec_t& g : h->iter_graph)
+    if (g) (void)hipGraphExecDestroy(g);
+  h->iter_graph.clear();
+  h->cyc.reset();
+  h->arena.release();
+  if (h->gs) (void)hipStreamDestroy(h->gs);
+  if (h->ev_in) (void)hipEventDestroy(h->ev_in);
+  if (h->ev_out) (void)hipEventDestroy(h->ev_out);
+  if (h->hhost) (void)hipHostFree(h->hhost);
+  h->gs = nullptr;
+  h->ev_in = h->ev_out = nullptr;
+  h->hhost = nullptr;
+  h->V = h->Z = h->w = h->partial = h->hdev = h->ydev = nullptr;
+  h->pw = nullptr;
+  h->dir_idx = nullptr;
+  h->K0full = DCsr<double>{};
+  h->on_device = false;
 }
 
 // ---------------------------------------------------------------------------
@@ -1455,8 +1501,8 @@ int fgmres(mas_handle* h, const double* b, double* x, double rtol, int max_it, m
 // advanced in lockstep so every cycle application is batched.  Each column has
 // its own Givens rotations and tolerance; a column stops rotating once its
 // estimate reaches its tolerance, and its iterate uses its own Krylov size.
-int fgmres_nr(mas_handle* h, const double* b, double* x, int nr, double rtol, int max_it, mas_solve_info* info,
-              hipStream_t s) {
+int fgmres_nr(mas_handle* h, const double* b, double* x, int nr, const double* rtol, int max_it,
+              mas_solve_info* info, hipStream_t s) {
   const int64_t n = h->n0;
   const int m = std::max(1, h->par.restart);
   int nrp = 1;
@@ -1484,7 +1530,7 @@ int fgmres_nr(mas_handle* h, const double* b, double* x, int nr, double rtol, in
       if (info) for (int q = 0; q < nr; ++q) info[q] = mas_solve_info{0, 0, NAN, NAN};
       return MAS_ENAN;
     }
-    target[k] = rtol * bnorm[k];
+    target[k] = rtol[k] * bnorm[k];
     done[k] = bnorm[k] == 0.0;
     hist[k].push_back(bnorm[k]);
   }
@@ -1693,11 +1739,14 @@ int mas_setup(const mas_problem* prob, const mas_params* par, void* stream, mas_
     analyze_impl(h.get(), prob);
     upload_impl(h.get(), (hipStream_t)stream);
   } catch (const MasError& e) {
+    release_device(h.get());
     return fail(e);
   } catch (const std::bad_alloc&) {
+    release_device(h.get());
     g_last_error = "host allocation failed";
     return MAS_ENOMEM;
   } catch (const std::exception& e) {
+    release_device(h.get());
     g_last_error = e.what();
     return MAS_EINVAL;
   }
@@ -1753,9 +1802,9 @@ int mas_apply(mas_handle* h, const double* r, double* z, int32_t nrhs, void* str
   return MAS_OK;
 }
 
-int mas_solve(mas_handle* h, const double* b, double* x, int32_t nrhs, double rtol, int32_t max_it,
-              mas_solve_info* info, void* stream) {
-  if (!h || !b || !x || rtol < 0.0 || max_it < 1) {
+static int solve_impl(mas_handle* h, const double* b, double* x, int32_t nrhs, const double* rtol, int32_t max_it,
+                      mas_solve_info* info, void* stream) {
+  if (!h || !b || !x || !rtol || max_it < 1) {
     g_last_error = "bad argument";
     return MAS_EINVAL;
   }
@@ -1767,12 +1816,17 @@ int mas_solve(mas_handle* h, const double* b, double* x, int32_t nrhs, double rt
     g_last_error = "nrhs must be in [1, nrhs_max]";
     return MAS_EINVAL;
   }
+  for (int k = 0; k < nrhs; ++k)
+    if (!(rtol[k] >= 0.0)) {
+      g_last_error = "bad argument";
+      return MAS_EINVAL;
+    }
   try {
     hipStream_t us = (hipStream_t)stream;
     hipStream_t s = h->gs;
     HIPCHECK(hipEventRecord(h->ev_in, us));
     HIPCHECK(hipStreamWaitEvent(s, h->ev_in, 0));
-    int rc = nrhs == 1 ? fgmres(h, b, x, rtol, max_it, info, s) : fgmres_nr(h, b, x, nrhs, rtol, max_it, info, s);
+    int rc = nrhs == 1 ? fgmres(h, b, x, rtol[0], max_it, info, s) : fgmres_nr(h, b, x, nrhs, rtol, max_it, info, s);
     HIPCHECK(hipEventRecord(h->ev_out, s));
     HIPCHECK(hipStreamWaitEvent(us, h->ev_out, 0));
     if (h->tm.on) {
@@ -1784,6 +1838,22 @@ int mas_solve(mas_handle* h, const double* b, double* x, int32_t nrhs, double rt
   } catch (const MasError& e) {
     return fail(e);
   }
+}
+
+int mas_solve(mas_handle* h, const double* b, double* x, int32_t nrhs, double rtol, int32_t max_it,
+              mas_solve_info* info, void* stream) {
+  if (nrhs < 1 || nrhs > 64) {
+    g_last_error = "nrhs must be in [1, nrhs_max]";
+    return MAS_EINVAL;
+  }
+  double tols[64];
+  for (int k = 0; k < nrhs; ++k) tols[k] = rtol;
+  return solve_impl(h, b, x, nrhs, tols, max_it, info, stream);
+}
+
+int mas_solve_rtols(mas_handle* h, const double* b, double* x, int32_t nrhs, const double* rtol, int32_t max_it,
+                    mas_solve_info* info, void* stream) {
+  return solve_impl(h, b, x, nrhs, rtol, max_it, info, stream);
 }
 
 int mas_get_info(const mas_handle* h, mas_hier_info* out) {
@@ -1862,15 +1932,41 @@ int mas_get_timing(const mas_handle* h, double* out, int32_t n) {
   return MAS_OK;
 }
 
+int mas_release(mas_handle* h) {
+  if (!h) {
+    g_last_error = "null argument";
+    return MAS_EINVAL;
+  }
+  release_device(h);
+  return MAS_OK;
+}
+
+int mas_upload(mas_handle* h, void* stream) {
+  if (!h) {
+    g_last_error = "null argument";
+    return MAS_EINVAL;
+  }
+  if (h->on_device) return MAS_OK;
+  try {
+    upload_impl(h, (hipStream_t)stream);
+  } catch (const MasError& e) {
+    release_device(h);
+    return fail(e);
+  } catch (const std::bad_alloc&) {
+    release_device(h);
+    g_last_error = "host allocation failed";
+    return MAS_ENOMEM;
+  } catch (const std::exception& e) {
+    release_device(h);
+    g_last_error = e.what();
+    return MAS_EINVAL;
+  }
+  return MAS_OK;
+}
+
 int mas_destroy(mas_handle* h) {
   if (!h) return MAS_OK;
-  if (h->on_device) (void)hipDeviceSynchronize();
-  for (hipGraphExec_t g : h->iter_graph)
-    if (g) (void)hipGraphExecDestroy(g);
-  if (h->gs) (void)hipStreamDestroy(h->gs);
-  if (h->ev_in) (void)hipEventDestroy(h->ev_in);
-  if (h->ev_out) (void)hipEventDestroy(h->ev_out);
-  if (h->hhost) (void)hipHostFree(h->hhost);
+  release_device(h);
   delete h;
   return MAS_OK;
 }

@@ -247,3 +247,45 @@ def make_config(name: str, **over) -> StokesProblem:
     kw = config(name)
     kw.update(over)
     return make_problem(**kw)
+
+
+# ---------------------------------------------------------------------------
+# the serving stream: Poisson arrivals over a mix of meshes and viscosities
+
+SERVE_MESHES = [(2, 32), (2, 64), (2, 128), (2, 256), (3, 8), (3, 12), (3, 16), (3, 24)]
+
+
+def serve_mesh_key(dim: int, n: int) -> str:
+    return f"th{dim}d_{n}"
+
+
+def make_serve_mesh(dim: int, n: int) -> StokesProblem:
+    """A serving mesh at viscosity 1: Taylor-Hood on the unit square / cube,
+    homogeneous Dirichlet velocity (the requests bring their own forcing)."""
+    return make_problem(dim=dim, n=n, disc="TH", forcing="gaussian", bc="zero", seed=100 * dim + n)
+
+
+def random_rhs(prob: StokesProblem, rng) -> np.ndarray:
+    """Right-hand side of a request: N(0, 1) nodal forcing weighted by the
+    diagonal of the velocity mass matrix, zero on Dirichlet rows and on the
+    continuity rows (homogeneous boundary data)."""
+    nu = prob.meta["n_u"]
+    b = np.zeros(prob.K0.shape[0])
+    b[:nu] = prob.mu_diag0 * rng.standard_normal(nu)
+    b[prob.dir0] = 0.0
+    return b
+
+
+def serve_stream(n_req: int = 512, seed: int = 5, meshes=None):
+    """The request stream: mesh drawn uniformly (half 2D, half 3D), viscosity
+    log-uniform in [1e-2, 1], forcing seed, and unit-rate exponential
+    inter-arrival gaps (scaled to the wanted rate by the caller)."""
+    meshes = meshes or SERVE_MESHES
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n_req):
+        dim, n = meshes[int(rng.integers(len(meshes)))]
+        nu = float(10.0 ** rng.uniform(-2.0, 0.0))
+        out.append(dict(mesh=serve_mesh_key(dim, n), dim=dim, n=n, nu=nu, rhs_seed=int(rng.integers(2**31)),
+                        gap=float(rng.exponential(1.0))))
+    return out

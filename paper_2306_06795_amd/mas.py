@@ -56,6 +56,10 @@ class mas_hier_info(C.Structure):
 
 
 def _load():
+    # torch first: the process must hold ONE HIP runtime, and torch ships its
+    # own libamdhip64.so.7.  Loaded after libmas, torch would start a second
+    # runtime beside the one libmas pulled in, and the two cannot share the GPU.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libmas is not built ({LIB_PATH}); run paper_2306_06795_amd/build.py")
     lib = C.CDLL(LIB_PATH)
@@ -64,9 +68,13 @@ def _load():
     lib.mas_default_params.restype = None
     lib.mas_setup.argtypes = [P(mas_problem), P(mas_params), C.c_void_p, P(C.c_void_p)]
     lib.mas_analyze.argtypes = [P(mas_problem), P(mas_params), P(C.c_void_p)]
+    lib.mas_upload.argtypes = [C.c_void_p, C.c_void_p]
+    lib.mas_release.argtypes = [C.c_void_p]
     lib.mas_apply.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]
     lib.mas_solve.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_int32,
                               P(mas_solve_info), C.c_void_p]
+    lib.mas_solve_rtols.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, P(C.c_double), C.c_int32,
+                                    P(mas_solve_info), C.c_void_p]
     lib.mas_get_info.argtypes = [C.c_void_p, P(mas_hier_info)]
     lib.mas_export_level.argtypes = [C.c_void_p, C.c_int32, P(C.c_int64), P(C.c_int64), C.c_void_p,
                                      C.c_void_p, C.c_void_p]
@@ -87,8 +95,9 @@ def _load():
 
 lib = _load()
 
-EXPORTED = ("mas_default_params", "mas_setup", "mas_analyze", "mas_scale_rows", "mas_apply", "mas_solve", "mas_get_info", "mas_export_level",
-            "mas_set_timing", "mas_get_timing", "mas_destroy", "mas_error_string", "mas_last_error")
+EXPORTED = ("mas_default_params", "mas_setup", "mas_analyze", "mas_upload", "mas_release", "mas_apply", "mas_solve", "mas_solve_rtols",
+            "mas_get_info", "mas_scale_rows", "mas_export_level", "mas_set_timing", "mas_get_timing", "mas_destroy",
+            "mas_error_string", "mas_last_error")
 
 
 class MasError(RuntimeError):
@@ -180,13 +189,27 @@ class Handle:
         self.params = params
         self.n0 = prob.K0.shape[0]
 
+    def upload(self, stream=None):
+        """Device half of the setup for an analysed or released handle."""
+        _check(lib.mas_upload(self.h, _stream(stream)))
+
+    def release(self):
+        """Free the device memory, keep the host analysis."""
+        _check(lib.mas_release(self.h))
+
     def apply(self, r, z, nrhs: int = 1, stream=None):
         _check(lib.mas_apply(self.h, C.c_void_p(r.data_ptr()), C.c_void_p(z.data_ptr()), nrhs, _stream(stream)))
 
-    def solve(self, b, x, rtol: float = 1e-8, max_it: int = 1000, nrhs: int = 1, stream=None):
+    def solve(self, b, x, rtol=1e-8, max_it: int = 1000, nrhs: int = 1, stream=None):
+        """rtol: one tolerance, or a sequence of nrhs (mas_solve_rtols)."""
         info = (mas_solve_info * nrhs)()
-        rc = _check(lib.mas_solve(self.h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), nrhs, rtol, max_it,
-                                  info, _stream(stream)))
+        if np.ndim(rtol) == 0:
+            rc = _check(lib.mas_solve(self.h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), nrhs, float(rtol),
+                                      max_it, info, _stream(stream)))
+        else:
+            tols = (C.c_double * nrhs)(*[float(v) for v in rtol])
+            rc = _check(lib.mas_solve_rtols(self.h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), nrhs, tols,
+                                            max_it, info, _stream(stream)))
         out = [dict(iters=i.iters, converged=bool(i.converged), relres=i.relres, conv_factor=i.conv_factor)
                for i in info]
         return rc, out

@@ -1,0 +1,295 @@
+"""Continuous-batching request loop for Stokes solves on one GPU.
+
+A request names a mesh, a viscosity nu and a right-hand side.  Each mesh is
+analysed once on the host (Algorithm 1, patches) at registration.  Its device
+half (operators, patch factors, coarse inverse, solver workspace for
+``max_batch`` right-hand sides) is uploaded when a request for it is admitted
+and stays resident until the HBM budget needs the room.
+
+Viscosity: the hierarchy is built for nu = 1.  With
+S = diag(sqrt(nu) I_u, I_p / sqrt(nu)) the free block of the nu operator is
+S K_1 S, so a request is solved as c = S^-1 b (S b on Dirichlet rows),
+K_1 y = c, x = S^-1 y (mas_scale_rows).  Residuals relate by
+||b - K_nu x|| <= max(sqrt(nu), 1/sqrt(nu)) ||c - K_1 y|| and
+||c|| <= max(sqrt(nu), 1/sqrt(nu)) ||b||, so solving the scaled system to
+rtol / max(nu, 1/nu) bounds the relative residual of the nu system by rtol.
+
+Scheduling: each worker thread owns a stream.  It takes the mesh whose oldest
+waiting request is the oldest overall (among meshes that are idle and fit the
+budget) and solves all of that mesh's waiting requests, up to ``max_batch``,
+as one batched solve (right-hand sides interleaved in one cycle, each with its
+own tolerance, so a result does not depend on its batch-mates).  Requests
+arriving meanwhile join the next batch of their mesh; batches of different
+meshes run at the same time on their own streams.  Idle hierarchies are
+released least-recently-used to admit a new one (their host analysis stays, so
+re-admission costs one upload and factorisation); a mesh whose hierarchy does
+not fit the budget even alone is refused at submission.
+"""
+from __future__ import annotations
+
+import math
+import threading
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import mas
+
+
+@dataclass
+class Request:
+    mesh: str
+    nu: float
+    b: np.ndarray
+    rtol: float = 1e-8
+    t_arrival: float = 0.0
+    t_start: float = 0.0
+    t_done: float = 0.0
+    x: np.ndarray | None = None
+    iters: int = 0
+    relres: float = float("nan")
+    batch: int = 0
+    error: str | None = None
+    done: threading.Event = field(default_factory=threading.Event)
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.t_arrival
+
+
+class _Mesh:
+    def __init__(self, key, problem, handle, est_bytes):
+        self.key = key
+        self.n0 = problem.K0.shape[0]
+        self.handle: mas.Handle = handle  # analysed; on the device while resident
+        self.est_bytes = est_bytes        # device bytes (estimate until the first upload)
+        self.resident = False
+        self.busy = False
+        self.last_used = 0.0
+        self.queue: deque[Request] = deque()
+
+
+def estimate_device_bytes(info: dict, precision: int, max_batch: int) -> int:
+    """Upper estimate of the device memory of a handle from its host analysis."""
+    s = 4 if precision == mas.MAS_FP32 else 8
+    L = info["n_levels"]
+    R = max_batch
+    # level operators (CSR + a sliced-ELL copy) and per-level vectors
+    ops = sum(info["nnz"][l] * 2 * (s + 4) + info["n"][l] * (8 + 4 * s * R) for l in range(L))
+    ops += sum(info["p_nnz"]) * 2 * 2 * (s + 4)  # P and P^T
+    # patch factors, DoF lists, inverse maps, patch outputs
+    pat = sum(info["factor_entries"][l] * s + info["patch_dofs"][l] * (16 + s * (1 + R)) for l in range(L))
+    coarse = info["coarse_n"] ** 2 * 8 * 2
+    # FP64 K0 copy and FGMRES(20) basis V, Z for R right-hand sides
+    n0 = info["n"][0]
+    k0 = info["nnz"][0] * 2 * 12 + n0 * 8 * (2 * 20 + 4) * R
+    return int(1.3 * (ops + pat + coarse + k0)) + (16 << 20)
+
+
+class StokesServer:
+    def __init__(self, hbm_budget: int, max_batch: int = 32, workers: int = 4,
+                 precision: int = mas.MAS_FP32, params: dict | None = None):
+        self.budget = int(hbm_budget)
+        self.max_batch = int(max_batch)
+        self.precision = precision
+        self.params = params or {}
+        self.meshes: dict[str, _Mesh] = {}
+        self.cv = threading.Condition()
+        self.stop = False
+        self.paused = False
+        self.resident = 0
+        self.peak_resident = 0
+        self.uploads = 0
+        self.evictions = 0
+        self.batches = 0
+        self.batch_sizes: list[int] = []
+        self.n_workers = workers
+        self.threads: list[threading.Thread] = []
+
+    # ------------------------------------------------------------------ API
+    def add_mesh(self, key: str, problem, device_bytes: int | None = None) -> int:
+        """Analyse a mesh (host only) and register it; returns the device-byte
+        figure used for admission: ``device_bytes`` when the caller knows it
+        (from an earlier upload with the same parameters), else an upper
+        estimate from the analysis.  The exact size replaces it at the first
+        upload."""
+        disc = mas.MAS_SV if problem.disc == "SV" else mas.MAS_TH
+        par = mas.default_params(problem.dim, disc, precision=self.precision, nrhs_max=self.max_batch,
+                                 **self.params)
+        h = mas.Handle(problem, par, analyze_only=True)
+        est = int(device_bytes) if device_bytes else estimate_device_bytes(h.info(), self.precision,
+                                                                             self.max_batch)
+        with self.cv:
+            old = self.meshes.get(key)
+            if old is not None:
+                if old.busy or old.queue or old.resident:
+                    h.close()
+                    raise RuntimeError(f"mesh {key} is in use")
+                old.handle.close()
+            self.meshes[key] = _Mesh(key, problem, h, est)
+        return est
+
+    def start(self):
+        self.threads = [threading.Thread(target=self._worker, daemon=True) for _ in range(self.n_workers)]
+        for t in self.threads:
+            t.start()
+
+    def submit(self, req: Request) -> Request:
+        req.t_arrival = time.perf_counter()
+        with self.cv:
+            m = self.meshes.get(req.mesh)
+            err = None
+            if m is None:
+                err = "unknown mesh"
+            elif m.est_bytes > self.budget:
+                err = "hierarchy does not fit the HBM budget"
+            elif np.shape(req.b) != (m.n0,):
+                err = "right-hand side has the wrong length"
+            elif not (req.nu > 0.0 and math.isfinite(req.nu)):
+                err = "viscosity must be positive"
+            if err is not None:
+                req.error = err
+                req.t_done = req.t_arrival
+                req.done.set()
+                return req
+            m.queue.append(req)
+            self.cv.notify()
+        return req
+
+    def pause(self):
+        """Hold new batches (running ones finish); requests keep queueing."""
+        with self.cv:
+            self.paused = True
+
+    def resume(self):
+        with self.cv:
+            self.paused = False
+            self.cv.notify_all()
+
+    def shutdown(self):
+        with self.cv:
+            self.stop = True
+            self.cv.notify_all()
+        for t in self.threads:
+            t.join()
+        self.threads = []
+        for m in self.meshes.values():
+            m.handle.close()
+        self.meshes.clear()
+
+    def stats(self) -> dict:
+        with self.cv:
+            return dict(resident_bytes=self.resident, peak_resident_bytes=self.peak_resident, uploads=self.uploads,
+                        evictions=self.evictions, batches=self.batches,
+                        mean_batch=float(np.mean(self.batch_sizes)) if self.batch_sizes else 0.0)
+
+    # ------------------------------------------------------------ internals
+    def _fits(self, m: _Mesh) -> bool:
+        """Make room for m (evicting idle residents, least recently used first).
+        Called with the lock held."""
+        if m.resident or self.resident + m.est_bytes <= self.budget:
+            return True
+        idle = sorted((o for o in self.meshes.values() if o.resident and not o.busy), key=lambda o: o.last_used)
+        need = self.resident + m.est_bytes - self.budget
+        if sum(o.est_bytes for o in idle) < need:
+            return False
+        for o in idle:
+            if self.resident + m.est_bytes <= self.budget:
+                break
+            o.handle.release()
+            o.resident = False
+            self.resident -= o.est_bytes
+            self.evictions += 1
+        return True
+
+    def _pick(self):
+        """Idle mesh with the oldest waiting request that fits (lock held)."""
+        if self.paused:
+            return None
+        cands = sorted((m for m in self.meshes.values() if m.queue and not m.busy),
+                       key=lambda m: m.queue[0].t_arrival)
+        for m in cands:
+            if self._fits(m):
+                return m
+        return None
+
+    def _worker(self):
+        import torch
+        stream = torch.cuda.Stream()
+        while True:
+            with self.cv:
+                while True:
+                    if self.stop:
+                        return
+                    m = self._pick()
+                    if m is not None:
+                        break
+                    self.cv.wait(0.05)
+                m.busy = True
+                batch = [m.queue.popleft() for _ in range(min(self.max_batch, len(m.queue)))]
+                if not m.resident:
+                    self.resident += m.est_bytes  # reserved while uploading
+                    self.peak_resident = max(self.peak_resident, self.resident)
+            try:
+                with torch.cuda.stream(stream):
+                    self._run_batch(m, batch, stream, torch)
+            except Exception as e:  # the batch fails, the server keeps going
+                for r in batch:
+                    r.error = str(e)
+                    r.t_done = time.perf_counter()
+                    r.done.set()
+            with self.cv:
+                if not m.resident and m.handle.info()["device_bytes"] == 0:
+                    self.resident -= m.est_bytes  # upload failed
+                m.busy = False
+                m.last_used = time.perf_counter()
+                self.cv.notify_all()
+
+    def _run_batch(self, m: _Mesh, batch, stream, torch):
+        st = stream.cuda_stream
+        h = m.handle
+        if not m.resident:
+            h.upload(stream=st)
+            nbytes = h.info()["device_bytes"]
+            with self.cv:
+                self.resident += nbytes - m.est_bytes
+                self.peak_resident = max(self.peak_resident, self.resident)
+                m.est_bytes = nbytes  # exact from now on
+                m.resident = True
+                self.uploads += 1
+        t0 = time.perf_counter()
+        nr = len(batch)
+        for r in batch:
+            r.t_start = t0
+            r.batch = nr
+        B = np.stack([np.asarray(r.b, dtype=np.float64) for r in batch], 1)
+        Bd = torch.from_numpy(np.ascontiguousarray(B)).to("cuda:0", non_blocking=False)
+        Xd = torch.empty_like(Bd)
+        su = [1.0 / math.sqrt(r.nu) for r in batch]  # S^-1 on velocity rows
+        sp = [math.sqrt(r.nu) for r in batch]        # S^-1 on pressure rows
+        h.scale_rows(Bd, su, sp, nrhs=nr, dirichlet_inverse=True, stream=st)
+        tols = [r.rtol / max(r.nu, 1.0 / r.nu) for r in batch]
+        rc, info = h.solve(Bd, Xd, rtol=tols if nr > 1 else tols[0], nrhs=nr, stream=st)
+        h.scale_rows(Xd, su, sp, nrhs=nr, stream=st)
+        X = Xd.cpu().numpy().reshape(m.n0, nr)
+        t1 = time.perf_counter()
+        with self.cv:
+            self.batches += 1
+            self.batch_sizes.append(nr)
+        for k, r in enumerate(batch):
+            r.x = np.ascontiguousarray(X[:, k])
+            r.iters = info[k]["iters"]
+            r.relres = info[k]["relres"]
+            if not info[k]["converged"]:
+                r.error = "not converged"
+            r.t_done = t1
+            r.done.set()
+
+
+def latency_percentiles(reqs, qs=(50, 99)) -> dict:
+    lat = np.array([r.latency for r in reqs if r.error is None])
+    if lat.size == 0:
+        return {f"p{q}_ms": None for q in qs}
+    return {f"p{q}_ms": float(np.percentile(lat, q) * 1e3) for q in qs}

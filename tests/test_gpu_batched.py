@@ -18,6 +18,8 @@ CASES = {
     "th12_dlsc": (dict(dim=2, n=12, jitter=0.2, seed=2, forcing="gaussian", bc="lid", nrhs=4), "dlsc"),
     "sv6": (dict(dim=2, n=6, disc="SV", seed=4, forcing="gaussian", bc="zero", nrhs=8), "vanka"),
     "th3d3": (dict(dim=3, n=3, forcing="smooth", bc="zero", seed=3, nrhs=3), "vanka"),
+    # level-2 patches of up to 424 DoFs: factor records too large for LDS (global-memory path)
+    "th3d6": (dict(dim=3, n=6, forcing="smooth", bc="zero", seed=3, nrhs=6), "vanka"),
 }
 
 

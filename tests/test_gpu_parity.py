@@ -23,6 +23,7 @@ CASES = {
     "th16_3lvl": (dict(dim=2, n=16), dict(max_coarse=30)),
     "th24_lid": (dict(dim=2, n=24, jitter=0.2, seed=2, forcing="gaussian", bc="lid"), dict(max_coarse=40)),
     "th3d4": (dict(dim=3, n=4, forcing="smooth", bc="zero", seed=3), dict(max_coarse=40)),
+    "th3d6_3lvl": (dict(dim=3, n=6, forcing="smooth", bc="zero", seed=3), dict(max_coarse=30)),
     "th16_skip1": (dict(dim=2, n=16, jitter=0.2, seed=5, forcing="gaussian", bc="lid"),
                    dict(max_coarse=30, schedule="skip1")),
     "th16_skip0": (dict(dim=2, n=16, jitter=0.2, seed=5, forcing="gaussian", bc="lid"),
