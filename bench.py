@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-its", type=int, default=2)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="copy this many MiB with one plain device copy first (the scale of HBM byte counters)")
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate / closed-loop capacity")
     ap.add_argument("--serve-sweep", type=float, nargs="*", default=[])
@@ -210,6 +212,12 @@ def main():
     from paper_2306_06795_amd.inputs import make_config
 
     dev = "cuda:0"
+    if a.copy_probe_mib > 0:  # one copy kernel of known size: reference for HBM byte counters
+        src = torch.ones(a.copy_probe_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     t0 = time.perf_counter()
     prob = make_config(a.config)
     t_gen = time.perf_counter() - t0

@@ -764,7 +764,7 @@ template <typename T>
 __global__ void k_vanka_pull(int n, const int* __restrict__ inv_ptr, const int* __restrict__ inv_pos,
                              const T* __restrict__ Y, const T* __restrict__ w, T omega, T* __restrict__ x,
                              int accumulate) {
-  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   T acc = 0;
   for (int k = inv_ptr[j]; k < inv_ptr[j + 1]; ++k) acc += Y[inv_pos[k]];
@@ -860,7 +860,10 @@ __global__ void __launch_bounds__(WAVE) k_vanka_factor(int64_t np, const int64_t
         }
       }
       __syncthreads();
-      // in-place Gauss-Jordan inversion (the block is symmetric positive definite)
+      // in-place Gauss-Jordan inversion (the block is symmetric positive
+      // definite).  The lanes share each row (lane j owns columns j, j + 64, ...),
+      // so every row update is a contiguous access; the lane owning column k
+      // writes the pivot column.
       double scale = 0.0;
       for (int i = 0; i < n; ++i) scale = fmax(scale, fabs(W[(int64_t)i * n + i]));
       for (int k = 0; k < n; ++k) {
@@ -873,30 +876,36 @@ __global__ void __launch_bounds__(WAVE) k_vanka_factor(int64_t np, const int64_t
         for (int j = lane; j < n; j += WAVE)
           if (j != k) W[(int64_t)k * n + j] *= dk;
         __syncthreads();
-        for (int i = lane; i < n; i += WAVE) {
+        const double* wk = W + (int64_t)k * n;
+        for (int i = 0; i < n; ++i) {
           if (i == k) continue;
-          const double f = W[(int64_t)i * n + k];
-          for (int j = 0; j < n; ++j)
-            if (j != k) W[(int64_t)i * n + j] -= f * W[(int64_t)k * n + j];
-          W[(int64_t)i * n + k] = -f * dk;
+          double* wi = W + (int64_t)i * n;
+          const double f = wi[k];
+          for (int j = lane; j < n; j += WAVE)
+            if (j != k) wi[j] -= f * wk[j];
+          if (lane == k % WAVE) wi[k] = -f * dk;
         }
         __syncthreads();
         if (lane == 0) W[(int64_t)k * n + k] = dk;
         __syncthreads();
       }
-      // packed upper of the (symmetric) inverse
+      // symmetrise the inverse: both halves take the mean of the pair
       for (int64_t q = lane; q < (int64_t)n * (n + 1) / 2; q += WAVE) {
         int j = (int)((sqrt(8.0 * (double)q + 1.0) - 1.0) * 0.5);
         while ((int64_t)j * (j + 1) / 2 > q) --j;
         while ((int64_t)(j + 1) * (j + 2) / 2 <= q) ++j;
-        int i = (int)(q - (int64_t)j * (j + 1) / 2);
-        out[(ao + q) * fs] = (TO)(0.5 * (W[(int64_t)i * n + j] + W[(int64_t)j * n + i]));
+        const int i = (int)(q - (int64_t)j * (j + 1) / 2);
+        const double v = 0.5 * (W[(int64_t)i * n + j] + W[(int64_t)j * n + i]);
+        W[(int64_t)i * n + j] = v;
+        W[(int64_t)j * n + i] = v;
+        out[(ao + q) * fs] = (TO)v;  // packed upper
       }
-      // U_c = A_c^-1 B_c^T
+      __syncthreads();
+      // U_c = A_c^-1 B_c^T (column i of the symmetric inverse, read along rows j)
       for (int i = lane; i < n; i += WAVE)
         for (int s = 0; s < ns; ++s) {
           double acc = 0.0;
-          for (int j = 0; j < n; ++j) acc += W[(int64_t)i * n + j] * Bm[s * nv + cs + j];
+          for (int j = 0; j < n; ++j) acc += W[(int64_t)j * n + i] * Bm[s * nv + cs + j];
           U[(int64_t)(cs + i) * ns + s] = acc;
         }
       __syncthreads();
