@@ -194,12 +194,16 @@ int mas_scale_rows(mas_handle* h, double* x, int32_t nrhs, const double* s_u, co
 int mas_export_level(const mas_handle* h, int32_t level, int64_t* nrows, int64_t* nnz,
                      int64_t* indptr, int32_t* indices, double* data);
 
-/* Event timing of the cycle's kernels during mas_solve (for measurement; it
- * disables graph replay while on).  mas_get_timing fills up to n of:
- * out[0] patch-solve time (ms, summed), out[1] patch-solve launches,
- * out[2] their algorithmic bytes (factor records, DoF lists, patch outputs, one
- * read of the level vector), out[3] sparse-product time (ms), out[4] launches,
- * out[5] their algorithmic bytes (values, column and row indices, vectors). */
+/* Event timing of the cycle's kernel launches during mas_solve / mas_apply
+ * (for measurement; it disables graph replay while on).  mas_get_timing fills
+ * up to n (at most 18) values, three per kernel kind k: out[3k] summed time
+ * (ms), out[3k+1] launches, out[3k+2] their summed algorithmic bytes.  Kinds:
+ * 0 thread-per-patch bucket kernel, 1 wavefront-per-patch kernel, 2 batched
+ * (several right-hand sides) patch kernel, 3 sliced-ELL product, 4 CSR
+ * product, 5 batched CSR product.  Patch-kernel
+ * bytes: factor records, DoF lists, patch outputs, and each distinct level
+ * vector entry read once; sparse products: values, column and row indices,
+ * vectors. */
 int mas_set_timing(mas_handle* h, int32_t enable);
 int mas_get_timing(const mas_handle* h, double* out, int32_t n);
 

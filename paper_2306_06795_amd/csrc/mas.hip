@@ -307,41 +307,42 @@ struct CycleBase {
   virtual void set_nr(int nr) = 0;
 };
 
-// Optional event timing of the two kernel families of the cycle, with the
+// Optional event timing of the cycle's kernels, per kernel kind, with the
 // algorithmic bytes each timed launch has to move.
+enum TimedKind { TK_TPP = 0, TK_GENERIC = 1, TK_BATCHED = 2, TK_SELL = 3, TK_CSR = 4, TK_SPMM = 5, TK_KINDS = 6 };
 struct Timing {
   struct Rec {
     hipEvent_t a, b;
     double bytes;
+    int kind;
   };
   bool on = false;
-  std::vector<Rec> vanka, spmv;
-  double vanka_ms = 0, spmv_ms = 0, vanka_bytes = 0, spmv_bytes = 0;
-  int64_t vanka_launches = 0, spmv_launches = 0;
+  std::vector<Rec> recs;
+  double ms[TK_KINDS] = {}, bytes[TK_KINDS] = {};
+  int64_t launches[TK_KINDS] = {};
   void begin(hipEvent_t& e0, hipEvent_t& e1, hipStream_t s) {
     HIPCHECK(hipEventCreate(&e0));
     HIPCHECK(hipEventCreate(&e1));
     HIPCHECK(hipEventRecord(e0, s));
   }
+  void end(hipEvent_t e0, hipEvent_t e1, hipStream_t s, double nbytes, int kind) {
+    HIPCHECK(hipEventRecord(e1, s));
+    recs.push_back({e0, e1, nbytes, kind});
+  }
+  void reset() {
+    for (int k = 0; k < TK_KINDS; ++k) ms[k] = bytes[k] = 0, launches[k] = 0;
+  }
   void collect() {
-    for (auto* v : {&vanka, &spmv}) {
-      for (auto& r : *v) {
-        float ms = 0.f;
-        HIPCHECK(hipEventElapsedTime(&ms, r.a, r.b));
-        if (v == &vanka) {
-          vanka_ms += ms;
-          vanka_bytes += r.bytes;
-          vanka_launches++;
-        } else {
-          spmv_ms += ms;
-          spmv_bytes += r.bytes;
-          spmv_launches++;
-        }
-        (void)hipEventDestroy(r.a);
-        (void)hipEventDestroy(r.b);
-      }
-      v->clear();
+    for (auto& r : recs) {
+      float t = 0.f;
+      HIPCHECK(hipEventElapsedTime(&t, r.a, r.b));
+      ms[r.kind] += t;
+      bytes[r.kind] += r.bytes;
+      launches[r.kind]++;
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
     }
+    recs.clear();
   }
 };
 
@@ -415,10 +416,9 @@ struct Cycle : CycleBase {
       launch_check();
     }
     if (t) {
-      HIPCHECK(hipEventRecord(e1, s));
       const double sz = sizeof(T);
       const double vec = (A.m * sz + A.n * sz * (MODE == 0 ? 1.0 : 2.0)) * nr;
-      tm->spmv.push_back({e0, e1, A.nnz * (sz + 4.0) + (A.n + 1) * 4.0 + vec});
+      tm->end(e0, e1, s, A.nnz * (sz + 4.0) + (A.n + 1) * 4.0 + vec, nr > 1 ? TK_SPMM : A.use_sell ? TK_SELL : TK_CSR);
     }
   }
 
@@ -487,14 +487,25 @@ struct Cycle : CycleBase {
     vanka_sweeps(L, sweeps, omega, x_zero, s);
   }
 
+  // Algorithmic bytes of one patch-solve launch over a set of patches: their
+  // factor records, DoF lists and outputs, plus each distinct level-vector
+  // entry they read once (at most the level size).
+  double patch_bytes(const Level<T>& L, double fac_entries, double slots) const {
+    const double sz = sizeof(T);
+    return fac_entries * sz + slots * (4.0 + sz * nr) + std::min<double>(slots, (double)L.n) * sz * nr;
+  }
+
   void patch_solve(Level<T>& L, const T* rin, hipStream_t s) {
     DPatches<T>& pt = L.pt;
+    const bool timed = tm && tm->on;
+    hipEvent_t e0{}, e1{};
     if (nr > 1) {
       if (pt.nr_chunk < 1) throw MasError(MAS_EINVAL, "patches too large for the batched kernel");
       int C = kNrKT;
       while (C < nr && C < pt.nr_chunk) C *= 2;
       const dim3 grid((unsigned)pt.np, (unsigned)((nr + C - 1) / C));
       const size_t shm = nr_lds_bytes<T>(pt.max_m, C, pt.nr_stage ? pt.max_f : 0);
+      if (timed) tm->begin(e0, e1, s);
       if (pt.nr_stage)
         hipLaunchKernelGGL((k_vanka_apply_nr<T, kNrKT, true>), grid, dim3(256), shm, s, pt.np, nr, C, pt.off, pt.dims,
                            pt.foff, pt.fstride, pt.dofs, pt.fac, rin, pt.Ynr, pt.max_m, pt.max_f);
@@ -502,13 +513,22 @@ struct Cycle : CycleBase {
         hipLaunchKernelGGL((k_vanka_apply_nr<T, kNrKT, false>), grid, dim3(256), shm, s, pt.np, nr, C, pt.off, pt.dims,
                            pt.foff, pt.fstride, pt.dofs, pt.fac, rin, pt.Ynr, pt.max_m, pt.max_f);
       launch_check();
+      if (timed) tm->end(e0, e1, s, patch_bytes(L, (double)pt.nfac_alg, (double)pt.ndofs), TK_BATCHED);
       return;
     }
+    double fast_fac = 0.0, fast_slots = 0.0;
     for (const FastBucket& fb : pt.fast) {
       const unsigned nb = blocks_for(fb.P, 256);
       const int* d = fb.dofs;
       const T* f = pt.fac + fb.fbase;
       T* y = pt.Y + fb.ybase;
+      const int n0 = fb.shape[0], n1 = fb.shape[1], n2 = fb.shape[2], nsd = fb.shape[3];
+      const int nvb = n0 + n1 + n2;
+      const double rec = (double)n0 * (n0 + 1) / 2 + (double)n1 * (n1 + 1) / 2 + (double)n2 * (n2 + 1) / 2 +
+                         (double)nvb * nsd + (double)nsd * (nsd + 1) / 2;
+      fast_fac += rec * fb.P;
+      fast_slots += (double)(nvb + nsd) * fb.P;
+      if (timed) tm->begin(e0, e1, s);
 #define MAS_TPP(A, B, C, D)                                                                                    \
   if (fb.shape[0] == A && fb.shape[1] == B && fb.shape[2] == C && fb.shape[3] == D) {                         \
     hipLaunchKernelGGL((k_vanka_tpp<T, A, B, C, D>), dim3(nb), dim3(256), 0, s, fb.P, fb.Ppad, d, f, rin, y); \
@@ -516,11 +536,13 @@ struct Cycle : CycleBase {
       MAS_FAST_SHAPES(MAS_TPP) { throw MasError(MAS_EINVAL, "unknown patch bucket shape"); }
 #undef MAS_TPP
       launch_check();
+      if (timed) tm->end(e0, e1, s, patch_bytes(L, rec * fb.P, (double)(nvb + nsd) * fb.P), TK_TPP);
     }
     const int64_t ng = pt.np - pt.g0;
     if (ng > 0) {
       const bool stage = (size_t)(2 * pt.max_m + pt.max_f) * sizeof(T) <= kMaxLds;
       const size_t shm = (size_t)(2 * pt.max_m + (stage ? pt.max_f : 0)) * sizeof(T);
+      if (timed) tm->begin(e0, e1, s);
       if (stage)
         hipLaunchKernelGGL((k_vanka_apply<T, true>), dim3((unsigned)ng), dim3(WAVE), shm, s, ng, pt.off + pt.g0,
                            pt.dims + pt.g0, pt.foff + pt.g0, pt.dofs, pt.fac, rin, pt.Y, pt.max_m, pt.yshift);
@@ -528,6 +550,8 @@ struct Cycle : CycleBase {
         hipLaunchKernelGGL((k_vanka_apply<T, false>), dim3((unsigned)ng), dim3(WAVE), shm, s, ng, pt.off + pt.g0,
                            pt.dims + pt.g0, pt.foff + pt.g0, pt.dofs, pt.fac, rin, pt.Y, pt.max_m, pt.yshift);
       launch_check();
+      if (timed)
+        tm->end(e0, e1, s, patch_bytes(L, (double)pt.nfac_alg - fast_fac, (double)pt.ndofs - fast_slots), TK_GENERIC);
     }
   }
 
@@ -540,16 +564,7 @@ struct Cycle : CycleBase {
         spmv<1>(L.K, L.x, L.b, L.r, s);
         rin = L.r;
       }
-      hipEvent_t e0{}, e1{};
-      if (tm && tm->on) tm->begin(e0, e1, s);
       patch_solve(L, rin, s);
-      if (tm && tm->on) {
-        HIPCHECK(hipEventRecord(e1, s));
-        const double sz = sizeof(T);
-        // factor records + DoF lists + patch outputs + one read of the level vector
-        const double bytes = L.pt.nfac_alg * sz + L.pt.ndofs * (4.0 + sz * nr) + L.n * sz * nr;
-        tm->vanka.push_back({e0, e1, bytes});
-      }
       const int acc = (k == 0 && x_zero) ? 0 : 1;
       if (nr > 1) {
         const unsigned nb = blocks_for(L.n * nr, 256);
@@ -1919,16 +1934,17 @@ int mas_export_level(const mas_handle* h, int32_t level, int64_t* nrows, int64_t
 int mas_set_timing(mas_handle* h, int32_t enable) {
   if (!h) return MAS_EINVAL;
   h->tm.on = enable != 0;
-  h->tm.vanka_ms = h->tm.spmv_ms = h->tm.vanka_bytes = h->tm.spmv_bytes = 0;
-  h->tm.vanka_launches = h->tm.spmv_launches = 0;
+  h->tm.reset();
   return MAS_OK;
 }
 
 int mas_get_timing(const mas_handle* h, double* out, int32_t n) {
   if (!h || !out) return MAS_EINVAL;
-  const double v[6] = {h->tm.vanka_ms, (double)h->tm.vanka_launches, h->tm.vanka_bytes,
-                       h->tm.spmv_ms, (double)h->tm.spmv_launches, h->tm.spmv_bytes};
-  for (int i = 0; i < n && i < 6; ++i) out[i] = v[i];
+  for (int k = 0; k < TK_KINDS; ++k) {
+    const double v[3] = {h->tm.ms[k], (double)h->tm.launches[k], h->tm.bytes[k]};
+    for (int q = 0; q < 3; ++q)
+      if (3 * k + q < n) out[3 * k + q] = v[q];
+  }
   return MAS_OK;
 }
 

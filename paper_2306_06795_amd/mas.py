@@ -243,11 +243,13 @@ class Handle:
     def set_timing(self, on: bool):
         _check(lib.mas_set_timing(self.h, 1 if on else 0))
 
+    TIMED_KINDS = ("tpp", "generic", "batched", "sell", "csr", "spmm")
+
     def timing(self):
-        out = (C.c_double * 6)()
-        _check(lib.mas_get_timing(self.h, out, 6))
-        return dict(vanka_ms=out[0], vanka_launches=int(out[1]), vanka_bytes=out[2],
-                    spmv_ms=out[3], spmv_launches=int(out[4]), spmv_bytes=out[5])
+        """{kind: (ms, launches, bytes)} for the kernel kinds of mas_get_timing."""
+        out = (C.c_double * 18)()
+        _check(lib.mas_get_timing(self.h, out, 18))
+        return {k: (out[3 * i], int(out[3 * i + 1]), out[3 * i + 2]) for i, k in enumerate(self.TIMED_KINDS)}
 
     def close(self):
         if getattr(self, "h", None):
