@@ -594,38 +594,42 @@ __global__ void k_add3(int64_t n, T* __restrict__ x, const T* __restrict__ y, co
 }
 
 // ---------------------------------------------------------------------------
-// additive Vanka: one wavefront per patch, patch data staged through LDS.
-// Writes the patch solution x_i = K_i^-1 V_i r into Y at the patch's offset.
-template <typename T, bool STAGE>
-__global__ void __launch_bounds__(WAVE) k_vanka_apply(int64_t np, const int64_t* __restrict__ off,
-                                                     const int4* __restrict__ dims,
-                                                     const int64_t* __restrict__ foff,
-                                                     const int* __restrict__ dofs, const T* __restrict__ fac,
-                                                     const T* __restrict__ r, T* __restrict__ Y, int max_m,
-                                                     int64_t yshift) {
+// additive Vanka: one workgroup of TPB threads (one or four wavefronts) per
+// patch, patch data staged through LDS.  Writes the patch solution
+// x_i = K_i^-1 V_i r into Y at the patch's offset.  Large patches take four
+// wavefronts: four times the loads in flight while the record is staged and
+// one velocity row per thread afterwards.
+template <typename T, bool STAGE, int TPB>
+__global__ void __launch_bounds__(TPB) k_vanka_apply(int64_t np, const int64_t* __restrict__ off,
+                                                    const int4* __restrict__ dims,
+                                                    const int64_t* __restrict__ foff,
+                                                    const int* __restrict__ dofs, const T* __restrict__ fac,
+                                                    const T* __restrict__ r, T* __restrict__ Y, int max_m,
+                                                    int64_t yshift) {
   extern __shared__ unsigned char smem_raw[];
   T* sb = reinterpret_cast<T*>(smem_raw);
   T* sy = sb + max_m;
+  __shared__ T sred[TPB / WAVE][MAX_NS];
   const int64_t p = blockIdx.x;
   if (p >= np) return;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
   const int4 d = dims[p];
   const int nv = d.x + d.y + d.z, ns = d.w, m = nv + ns;
   const int64_t o = off[p];
   // gather: all index loads first, then all value loads (several in flight)
-  for (int k0 = 0; k0 < m; k0 += 4 * WAVE) {
+  for (int k0 = 0; k0 < m; k0 += 4 * TPB) {
     int idx[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int k = k0 + u * WAVE + lane;
+      const int k = k0 + u * TPB + tid;
       idx[u] = k < m ? dofs[o + k] : 0;
     }
     T v[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) v[u] = (k0 + u * WAVE + lane < m) ? r[idx[u]] : (T)0;
+    for (int u = 0; u < 4; ++u) v[u] = (k0 + u * TPB + tid < m) ? r[idx[u]] : (T)0;
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-      if (k0 + u * WAVE + lane < m) sb[k0 + u * WAVE + lane] = v[u];
+      if (k0 + u * TPB + tid < m) sb[k0 + u * TPB + tid] = v[u];
   }
   // record length from the shape (foff holds per-patch base offsets only)
   const int64_t f0 = foff[p];
@@ -633,19 +637,19 @@ __global__ void __launch_bounds__(WAVE) k_vanka_apply(int64_t np, const int64_t*
                      (int64_t)nv * ns + (int64_t)ns * (ns + 1) / 2;
   const T* sf;
   if (STAGE) {
-    // stage the record with 16 independent loads in flight per lane
+    // stage the record with 16 independent loads in flight per thread
     T* st = sy + max_m;
     constexpr int U = 16;
-    for (int64_t k0 = 0; k0 < nf; k0 += U * WAVE) {
+    for (int64_t k0 = 0; k0 < nf; k0 += U * TPB) {
       T v[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int64_t k = k0 + u * WAVE + lane;
+        const int64_t k = k0 + u * TPB + tid;
         v[u] = k < nf ? fac[f0 + k] : (T)0;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int64_t k = k0 + u * WAVE + lane;
+        const int64_t k = k0 + u * TPB + tid;
         if (k < nf) st[k] = v[u];
       }
     }
@@ -655,8 +659,8 @@ __global__ void __launch_bounds__(WAVE) k_vanka_apply(int64_t np, const int64_t*
   }
   __syncthreads();
   const int nc[3] = {d.x, d.y, d.z};
-  // y_u = A^-1 b_u, one row per lane
-  for (int row = lane; row < nv; row += WAVE) {
+  // y_u = A^-1 b_u, one row per thread
+  for (int row = tid; row < nv; row += TPB) {
     int c = 0, cs = 0;
     int64_t ao = 0;
     while (row >= cs + nc[c]) {
@@ -676,8 +680,21 @@ __global__ void __launch_bounds__(WAVE) k_vanka_apply(int64_t np, const int64_t*
   T t[MAX_NS], yp[MAX_NS];
   for (int s = 0; s < ns; ++s) {
     T part = 0;
-    for (int k = lane; k < nv; k += WAVE) part += U[(int64_t)s * nv + k] * sb[k];
-    t[s] = wave_sum(part) + sb[nv + s];
+    for (int k = tid; k < nv; k += TPB) part += U[(int64_t)s * nv + k] * sb[k];
+    part = wave_sum(part);
+    if (TPB == WAVE) {
+      t[s] = part + sb[nv + s];
+    } else {
+      if (lane == 0) sred[wv][s] = part;
+    }
+  }
+  if (TPB > WAVE) {
+    __syncthreads();
+    for (int s = 0; s < ns; ++s) {
+      T acc = sred[0][s];
+      for (int q = 1; q < TPB / WAVE; ++q) acc += sred[q][s];
+      t[s] = acc + sb[nv + s];
+    }
   }
   for (int s = 0; s < ns; ++s) {
     T acc = 0;
@@ -685,13 +702,13 @@ __global__ void __launch_bounds__(WAVE) k_vanka_apply(int64_t np, const int64_t*
     yp[s] = acc;
   }
   __syncthreads();
-  for (int row = lane; row < nv; row += WAVE) {
+  for (int row = tid; row < nv; row += TPB) {
     T acc = sy[row];
     for (int s = 0; s < ns; ++s) acc += U[(int64_t)s * nv + row] * yp[s];
     Y[o - yshift + row] = acc;
   }
   for (int s = 0; s < ns; ++s)
-    if (lane == s) Y[o - yshift + nv + s] = yp[s];
+    if (tid == s) Y[o - yshift + nv + s] = yp[s];
 }
 
 // additive Vanka for a bucket of P patches of one fixed shape: one thread per

@@ -49,6 +49,7 @@ inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) /
 
 constexpr size_t kMaxLds = 64 * 1024;  // dynamic LDS per workgroup used by the patch kernels
 constexpr int kNrKT = 4;                // right-hand sides per thread in the batched patch kernel
+constexpr int kWidePatch = 128;         // patches of this many DoFs or more get a 256-thread workgroup
 
 // LDS of the batched patch kernel: m x C block, two MAX_NS x C blocks, the
 // staged record (f values) and the patch DoF list
@@ -543,12 +544,17 @@ struct Cycle : CycleBase {
       const bool stage = (size_t)(2 * pt.max_m + pt.max_f) * sizeof(T) <= kMaxLds;
       const size_t shm = (size_t)(2 * pt.max_m + (stage ? pt.max_f : 0)) * sizeof(T);
       if (timed) tm->begin(e0, e1, s);
-      if (stage)
-        hipLaunchKernelGGL((k_vanka_apply<T, true>), dim3((unsigned)ng), dim3(WAVE), shm, s, ng, pt.off + pt.g0,
-                           pt.dims + pt.g0, pt.foff + pt.g0, pt.dofs, pt.fac, rin, pt.Y, pt.max_m, pt.yshift);
-      else
-        hipLaunchKernelGGL((k_vanka_apply<T, false>), dim3((unsigned)ng), dim3(WAVE), shm, s, ng, pt.off + pt.g0,
-                           pt.dims + pt.g0, pt.foff + pt.g0, pt.dofs, pt.fac, rin, pt.Y, pt.max_m, pt.yshift);
+      // four wavefronts per patch for large patches (more loads in flight, a row per thread)
+      const bool wide = pt.max_m >= kWidePatch;
+#define MAS_GENERIC(ST, TB)                                                                                     \
+  hipLaunchKernelGGL((k_vanka_apply<T, ST, TB>), dim3((unsigned)ng), dim3(TB), shm, s, ng, pt.off + pt.g0,     \
+                     pt.dims + pt.g0, pt.foff + pt.g0, pt.dofs, pt.fac, rin, pt.Y, pt.max_m, pt.yshift)
+      if (stage && wide) MAS_GENERIC(true, 256);
+      else if (stage) MAS_GENERIC(true, WAVE);
+      else if (pt.max_m >= 4 * kWidePatch) MAS_GENERIC(false, 1024);
+      else if (wide) MAS_GENERIC(false, 256);
+      else MAS_GENERIC(false, WAVE);
+#undef MAS_GENERIC
       launch_check();
       if (timed)
         tm->end(e0, e1, s, patch_bytes(L, (double)pt.nfac_alg - fast_fac, (double)pt.ndofs - fast_slots), TK_GENERIC);
