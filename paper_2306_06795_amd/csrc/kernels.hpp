@@ -829,8 +829,8 @@ __device__ __forceinline__ int find_sorted(const int* a, int n, int key) {
   return -1;
 }
 
-template <typename TO>
-__global__ void __launch_bounds__(WAVE) k_vanka_factor(int64_t np, const int64_t* __restrict__ off,
+template <typename TO, int TPB>
+__global__ void __launch_bounds__(TPB) k_vanka_factor(int64_t np, const int64_t* __restrict__ off,
                                                       const int4* __restrict__ dims,
                                                       const int64_t* __restrict__ foff,
                                                       const int64_t* __restrict__ fstride, const int* __restrict__ dofs,
@@ -844,7 +844,8 @@ __global__ void __launch_bounds__(WAVE) k_vanka_factor(int64_t np, const int64_t
     double* W = use_lds ? smem_d : gwork + (int64_t)blockIdx.x * work_stride;
     double* Bm = W + (work_stride - 2 * (int64_t)max_nv * MAX_NS);  // ns x nv
     double* U = Bm + (int64_t)max_nv * MAX_NS;                      // nv x ns (row k: U[k*ns+s])
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
+    constexpr int NW = TPB / WAVE;
     const int4 d = dims[p];
     const int nc[3] = {d.x, d.y, d.z};
     const int nv = d.x + d.y + d.z, ns = d.w;
@@ -852,11 +853,11 @@ __global__ void __launch_bounds__(WAVE) k_vanka_factor(int64_t np, const int64_t
     TO* out = fac + foff[p];
     const int64_t fs = fstride[p];  // 1: contiguous record; P: interleaved across a bucket of P patches
     // B rows of the seeds restricted to the patch velocities
-    for (int k = lane; k < ns * nv; k += WAVE) Bm[k] = 0.0;
+    for (int k = tid; k < ns * nv; k += TPB) Bm[k] = 0.0;
     __syncthreads();
     for (int s = 0; s < ns; ++s) {
       const int row = P[nv + s];
-      for (int e = kptr[row] + lane; e < kptr[row + 1]; e += WAVE) {
+      for (int e = kptr[row] + tid; e < kptr[row + 1]; e += TPB) {
         int k = find_sorted(P, nv, kind[e]);
         if (k >= 0) Bm[s * nv + k] = kval[e];
       }
@@ -867,9 +868,9 @@ __global__ void __launch_bounds__(WAVE) k_vanka_factor(int64_t np, const int64_t
     for (int c = 0; c < 3; ++c) {
       const int n = nc[c];
       if (n == 0) continue;
-      for (int64_t k = lane; k < (int64_t)n * n; k += WAVE) W[k] = 0.0;
+      for (int64_t k = tid; k < (int64_t)n * n; k += TPB) W[k] = 0.0;
       __syncthreads();
-      for (int i = lane; i < n; i += WAVE) {
+      for (int i = tid; i < n; i += TPB) {
         const int row = P[cs + i];
         for (int e = kptr[row]; e < kptr[row + 1]; ++e) {
           int j = find_sorted(P + cs, n, kind[e]);
@@ -886,15 +887,15 @@ __global__ void __launch_bounds__(WAVE) k_vanka_factor(int64_t np, const int64_t
       for (int k = 0; k < n; ++k) {
         const double akk = W[(int64_t)k * n + k];
         if (!(akk > piv_tol * scale)) {
-          if (lane == 0) atomicMin((unsigned long long*)bad, (unsigned long long)p);
+          if (tid == 0) atomicMin((unsigned long long*)bad, (unsigned long long)p);
         }
         const double dk = 1.0 / akk;
         __syncthreads();
-        for (int j = lane; j < n; j += WAVE)
+        for (int j = tid; j < n; j += TPB)
           if (j != k) W[(int64_t)k * n + j] *= dk;
         __syncthreads();
         const double* wk = W + (int64_t)k * n;
-        for (int i = 0; i < n; ++i) {
+        for (int i = wv; i < n; i += NW) {  // wavefront wv updates rows wv, wv + NW, ...
           if (i == k) continue;
           double* wi = W + (int64_t)i * n;
           const double f = wi[k];
@@ -903,11 +904,11 @@ __global__ void __launch_bounds__(WAVE) k_vanka_factor(int64_t np, const int64_t
           if (lane == k % WAVE) wi[k] = -f * dk;
         }
         __syncthreads();
-        if (lane == 0) W[(int64_t)k * n + k] = dk;
+        if (tid == 0) W[(int64_t)k * n + k] = dk;
         __syncthreads();
       }
       // symmetrise the inverse: both halves take the mean of the pair
-      for (int64_t q = lane; q < (int64_t)n * (n + 1) / 2; q += WAVE) {
+      for (int64_t q = tid; q < (int64_t)n * (n + 1) / 2; q += TPB) {
         int j = (int)((sqrt(8.0 * (double)q + 1.0) - 1.0) * 0.5);
         while ((int64_t)j * (j + 1) / 2 > q) --j;
         while ((int64_t)(j + 1) * (j + 2) / 2 <= q) ++j;
@@ -919,7 +920,7 @@ __global__ void __launch_bounds__(WAVE) k_vanka_factor(int64_t np, const int64_t
       }
       __syncthreads();
       // U_c = A_c^-1 B_c^T (column i of the symmetric inverse, read along rows j)
-      for (int i = lane; i < n; i += WAVE)
+      for (int i = tid; i < n; i += TPB)
         for (int s = 0; s < ns; ++s) {
           double acc = 0.0;
           for (int j = 0; j < n; ++j) acc += W[(int64_t)j * n + i] * Bm[s * nv + cs + j];
@@ -930,7 +931,7 @@ __global__ void __launch_bounds__(WAVE) k_vanka_factor(int64_t np, const int64_t
       cs += n;
     }
     // S = -B U (ns x ns), inverted by one lane with partial pivoting
-    if (lane == 0) {
+    if (tid == 0) {
       double S[MAX_NS * MAX_NS], I[MAX_NS * MAX_NS];
       double smax = 0.0;
       for (int s = 0; s < ns; ++s)
@@ -966,7 +967,7 @@ __global__ void __launch_bounds__(WAVE) k_vanka_factor(int64_t np, const int64_t
         for (int s = 0; s <= t; ++s)
           out[(so + (int64_t)t * (t + 1) / 2 + s) * fs] = (TO)(0.5 * (I[s * ns + t] + I[t * ns + s]));
     }
-    for (int64_t q = lane; q < (int64_t)nv * ns; q += WAVE) {
+    for (int64_t q = tid; q < (int64_t)nv * ns; q += TPB) {
       int s = (int)(q / nv), k = (int)(q % nv);
       out[(ao + q) * fs] = (TO)(-U[(int64_t)k * ns + s]);
     }

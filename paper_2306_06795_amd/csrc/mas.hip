@@ -940,9 +940,14 @@ void build_patches(DevArena& ar, Level<T>& L, const PatchSet& ps, const DCsr<dou
   const bool use_lds = lds_bytes <= kMaxLds;
   const unsigned grid = use_lds ? (unsigned)std::min<int64_t>(np, 65536) : (unsigned)std::min<int64_t>(np, 1024);
   double* gwork = use_lds ? nullptr : ar.alloc<double>((size_t)stride * grid);
-  hipLaunchKernelGGL((k_vanka_factor<T>), dim3(grid), dim3(WAVE), use_lds ? lds_bytes : 0, s, np, d.off, d.dims,
-                     d.foff, d.fstride, d.dofs, K64.ptr, K64.ind, K64.val, d.fac, gwork, stride, use_lds ? 1 : 0,
-                     max_nv, 1e-14, bad);
+  // 4 (blocks in LDS) or 16 (blocks in global memory) wavefronts per patch: the
+  // row updates of a Gauss-Jordan step are split between them
+  if (use_lds)
+    hipLaunchKernelGGL((k_vanka_factor<T, 256>), dim3(grid), dim3(256), lds_bytes, s, np, d.off, d.dims, d.foff,
+                       d.fstride, d.dofs, K64.ptr, K64.ind, K64.val, d.fac, gwork, stride, 1, max_nv, 1e-14, bad);
+  else
+    hipLaunchKernelGGL((k_vanka_factor<T, 1024>), dim3(grid), dim3(1024), 0, s, np, d.off, d.dims, d.foff,
+                       d.fstride, d.dofs, K64.ptr, K64.ind, K64.val, d.fac, gwork, stride, 0, max_nv, 1e-14, bad);
   launch_check();
   int64_t hbad = 0;
   HIPCHECK(hipMemcpyAsync(&hbad, bad, sizeof(int64_t), hipMemcpyDeviceToHost, s));
