@@ -120,7 +120,8 @@ typedef struct {
   int64_t n_vel[16];      /* velocity rows per level */
   int64_t n_patches[16];  /* Vanka patches per relaxed level (0 if none) */
   int64_t patch_dofs[16]; /* sum of patch sizes per level */
-  int64_t factor_entries[16]; /* stored factor values per level (packed symmetric blocks) */
+  int64_t factor_entries[16]; /* stored factor values per level (packed symmetric blocks; full
+                                 blocks on levels whose patches reach 512 DoFs) */
   int64_t p_nnz[16];      /* entries of P_l (level l -> l-1), 0 for l <= 1 */
   int64_t coarse_n;       /* rows of the dense coarsest solve (incl. border) */
   int64_t device_bytes;   /* device memory held by the handle (0 after mas_analyze) */

@@ -19,6 +19,12 @@ namespace mas {
 constexpr int WAVE = 64;
 constexpr int MAX_NS = 4;  // seeds per patch handled by the kernels
 
+// values of one velocity block: packed upper triangle, or the full n x n
+// matrix (levels with very large patches, read with coalesced row sweeps)
+__device__ __forceinline__ int64_t blk_size(int n, int full) {
+  return full ? (int64_t)n * n : (int64_t)n * (n + 1) / 2;
+}
+
 __device__ __forceinline__ int64_t packed_index(int i, int j) {
   int a = i < j ? i : j, b = i < j ? j : i;
   return (int64_t)b * (b + 1) / 2 + a;
@@ -266,7 +272,7 @@ __global__ void __launch_bounds__(256) k_vanka_apply_nr(int64_t np, int nr, int 
                                                        const int64_t* __restrict__ fstride,
                                                        const int* __restrict__ dofs, const T* __restrict__ fac,
                                                        const T* __restrict__ r, T* __restrict__ Y, int max_m,
-                                                       int64_t max_f) {
+                                                       int64_t max_f, int full) {
   extern __shared__ unsigned char smem_raw[];
   T* sb = reinterpret_cast<T*>(smem_raw);   // max_m x C
   T* st = sb + (int64_t)max_m * C;          // MAX_NS x C: Uhat^T b_u + b_p
@@ -280,8 +286,8 @@ __global__ void __launch_bounds__(256) k_vanka_apply_nr(int64_t np, int nr, int 
   const int4 d = dims[p];
   const int n0 = d.x, n1 = d.y, n2 = d.z;
   const int nv = n0 + n1 + n2, ns = d.w, m = nv + ns;
-  const int64_t a1 = (int64_t)n0 * (n0 + 1) / 2, a2 = a1 + (int64_t)n1 * (n1 + 1) / 2;
-  const int64_t uo = a2 + (int64_t)n2 * (n2 + 1) / 2, so = uo + (int64_t)nv * ns;
+  const int64_t a1 = blk_size(n0, full), a2 = a1 + blk_size(n1, full);
+  const int64_t uo = a2 + blk_size(n2, full), so = uo + (int64_t)nv * ns;
   const int64_t nf = so + (int64_t)ns * (ns + 1) / 2;
   const int64_t o = off[p], f0 = foff[p], fs = fstride[p];
   for (int j = tid; j < m; j += 256) sd[j] = dofs[o + j];
@@ -327,9 +333,17 @@ __global__ void __launch_bounds__(256) k_vanka_apply_nr(int64_t np, int nr, int 
 #pragma unroll
     for (int kk = 0; kk < KT; ++kk) acc[kk] = 0;
     const T* bcol = sb + kg * KT;
+    if (full) {  // entry (i, j) at j n + i: the threads of a row sweep read consecutive rows
+      for (int j = 0; j < n; ++j) {
+        const T a = F(ao + (int64_t)j * n + i);
+        const VecT<T, KT> bv = *reinterpret_cast<const VecT<T, KT>*>(bcol + (cs + j) * C);
+#pragma unroll
+        for (int kk = 0; kk < KT; ++kk) acc[kk] += a * bv.v[kk];
+      }
+    }
     // j < i: packed entries i (i + 1) / 2 + j are contiguous
     const int64_t base = ao + (int64_t)i * (i + 1) / 2;
-    for (int j = 0; j < i; ++j) {
+    for (int j = 0; j < (full ? 0 : i); ++j) {
       const T a = F(base + j);
       const VecT<T, KT> bv = *reinterpret_cast<const VecT<T, KT>*>(bcol + (cs + j) * C);
 #pragma unroll
@@ -337,7 +351,7 @@ __global__ void __launch_bounds__(256) k_vanka_apply_nr(int64_t np, int nr, int 
     }
     // j >= i: entry at j (j + 1) / 2 + i
     int64_t q = base + i;
-    for (int j = i; j < n; ++j) {
+    for (int j = i; j < (full ? 0 : n); ++j) {
       const T a = F(q);
       q += j + 1;
       const VecT<T, KT> bv = *reinterpret_cast<const VecT<T, KT>*>(bcol + (cs + j) * C);
@@ -605,7 +619,7 @@ __global__ void __launch_bounds__(TPB) k_vanka_apply(int64_t np, const int64_t* 
                                                     const int64_t* __restrict__ foff,
                                                     const int* __restrict__ dofs, const T* __restrict__ fac,
                                                     const T* __restrict__ r, T* __restrict__ Y, int max_m,
-                                                    int64_t yshift) {
+                                                    int64_t yshift, int full) {
   extern __shared__ unsigned char smem_raw[];
   T* sb = reinterpret_cast<T*>(smem_raw);
   T* sy = sb + max_m;
@@ -633,8 +647,8 @@ __global__ void __launch_bounds__(TPB) k_vanka_apply(int64_t np, const int64_t* 
   }
   // record length from the shape (foff holds per-patch base offsets only)
   const int64_t f0 = foff[p];
-  const int64_t nf = (int64_t)d.x * (d.x + 1) / 2 + (int64_t)d.y * (d.y + 1) / 2 + (int64_t)d.z * (d.z + 1) / 2 +
-                     (int64_t)nv * ns + (int64_t)ns * (ns + 1) / 2;
+  const int64_t ua = blk_size(d.x, full) + blk_size(d.y, full) + blk_size(d.z, full);
+  const int64_t nf = ua + (int64_t)nv * ns + (int64_t)ns * (ns + 1) / 2;
   const T* sf;
   if (STAGE) {
     // stage the record with 16 independent loads in flight per thread
@@ -664,17 +678,19 @@ __global__ void __launch_bounds__(TPB) k_vanka_apply(int64_t np, const int64_t* 
     int c = 0, cs = 0;
     int64_t ao = 0;
     while (row >= cs + nc[c]) {
-      ao += (int64_t)nc[c] * (nc[c] + 1) / 2;
+      ao += blk_size(nc[c], full);
       cs += nc[c];
       ++c;
     }
     const int i = row - cs;
     const T* A = sf + ao;
     T acc = 0;
-    for (int j = 0; j < nc[c]; ++j) acc += A[packed_index(i, j)] * sb[cs + j];
+    if (full)  // entry (i, j) at j n + i: consecutive threads read consecutive values
+      for (int j = 0; j < nc[c]; ++j) acc += A[(int64_t)j * nc[c] + i] * sb[cs + j];
+    else
+      for (int j = 0; j < nc[c]; ++j) acc += A[packed_index(i, j)] * sb[cs + j];
     sy[row] = acc;
   }
-  int64_t ua = (int64_t)d.x * (d.x + 1) / 2 + (int64_t)d.y * (d.y + 1) / 2 + (int64_t)d.z * (d.z + 1) / 2;
   const T* U = sf + ua;
   const T* Si = U + (int64_t)nv * ns;
   T t[MAX_NS], yp[MAX_NS];
@@ -838,7 +854,7 @@ __global__ void __launch_bounds__(TPB) k_vanka_factor(int64_t np, const int64_t*
                                                       const double* __restrict__ kval, TO* __restrict__ fac,
                                                       double* __restrict__ gwork, int64_t work_stride,
                                                       int use_lds, int max_nv, double piv_tol,
-                                                      int64_t* __restrict__ bad) {
+                                                      int64_t* __restrict__ bad, int full) {
   extern __shared__ double smem_d[];
   for (int64_t p = blockIdx.x; p < np; p += gridDim.x) {
     double* W = use_lds ? smem_d : gwork + (int64_t)blockIdx.x * work_stride;
@@ -916,9 +932,11 @@ __global__ void __launch_bounds__(TPB) k_vanka_factor(int64_t np, const int64_t*
         const double v = 0.5 * (W[(int64_t)i * n + j] + W[(int64_t)j * n + i]);
         W[(int64_t)i * n + j] = v;
         W[(int64_t)j * n + i] = v;
-        out[(ao + q) * fs] = (TO)v;  // packed upper
+        if (!full) out[(ao + q) * fs] = (TO)v;  // packed upper
       }
       __syncthreads();
+      if (full)
+        for (int64_t q = tid; q < (int64_t)n * n; q += TPB) out[(ao + q) * fs] = (TO)W[q];
       // U_c = A_c^-1 B_c^T (column i of the symmetric inverse, read along rows j)
       for (int i = tid; i < n; i += TPB)
         for (int s = 0; s < ns; ++s) {
@@ -927,7 +945,7 @@ __global__ void __launch_bounds__(TPB) k_vanka_factor(int64_t np, const int64_t*
           U[(int64_t)(cs + i) * ns + s] = acc;
         }
       __syncthreads();
-      ao += (int64_t)n * (n + 1) / 2;
+      ao += blk_size(n, full);
       cs += n;
     }
     // S = -B U (ns x ns), inverted by one lane with partial pivoting

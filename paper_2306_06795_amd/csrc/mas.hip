@@ -50,6 +50,7 @@ inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) /
 constexpr size_t kMaxLds = 64 * 1024;  // dynamic LDS per workgroup used by the patch kernels
 constexpr int kNrKT = 4;                // right-hand sides per thread in the batched patch kernel
 constexpr int kWidePatch = 128;         // patches of this many DoFs or more get a 256-thread workgroup
+constexpr int kFullPatch = 512;         // levels with patches this large store full velocity blocks
 
 // LDS of the batched patch kernel: m x C block, two MAX_NS x C blocks, the
 // staged record (f values) and the patch DoF list
@@ -262,6 +263,7 @@ struct DPatches {
   int64_t g0 = 0, yshift = 0;
   int max_m = 0;
   int64_t max_f = 0;
+  int full = 0;  // velocity blocks stored as full matrices (levels of very large patches)
   std::vector<FastBucket> fast;
   // DoF -> outputs map: CSR (inv_ptr, inv_pos) or slot-major ELL (ell, width)
   int* inv_ptr = nullptr;
@@ -509,10 +511,10 @@ struct Cycle : CycleBase {
       if (timed) tm->begin(e0, e1, s);
       if (pt.nr_stage)
         hipLaunchKernelGGL((k_vanka_apply_nr<T, kNrKT, true>), grid, dim3(256), shm, s, pt.np, nr, C, pt.off, pt.dims,
-                           pt.foff, pt.fstride, pt.dofs, pt.fac, rin, pt.Ynr, pt.max_m, pt.max_f);
+                           pt.foff, pt.fstride, pt.dofs, pt.fac, rin, pt.Ynr, pt.max_m, pt.max_f, pt.full);
       else
         hipLaunchKernelGGL((k_vanka_apply_nr<T, kNrKT, false>), grid, dim3(256), shm, s, pt.np, nr, C, pt.off, pt.dims,
-                           pt.foff, pt.fstride, pt.dofs, pt.fac, rin, pt.Ynr, pt.max_m, pt.max_f);
+                           pt.foff, pt.fstride, pt.dofs, pt.fac, rin, pt.Ynr, pt.max_m, pt.max_f, pt.full);
       launch_check();
       if (timed) tm->end(e0, e1, s, patch_bytes(L, (double)pt.nfac_alg, (double)pt.ndofs), TK_BATCHED);
       return;
@@ -548,10 +550,10 @@ struct Cycle : CycleBase {
       const bool wide = pt.max_m >= kWidePatch;
 #define MAS_GENERIC(ST, TB)                                                                                     \
   hipLaunchKernelGGL((k_vanka_apply<T, ST, TB>), dim3((unsigned)ng), dim3(TB), shm, s, ng, pt.off + pt.g0,     \
-                     pt.dims + pt.g0, pt.foff + pt.g0, pt.dofs, pt.fac, rin, pt.Y, pt.max_m, pt.yshift)
+                     pt.dims + pt.g0, pt.foff + pt.g0, pt.dofs, pt.fac, rin, pt.Y, pt.max_m, pt.yshift, pt.full)
       if (stage && wide) MAS_GENERIC(true, 256);
       else if (stage) MAS_GENERIC(true, WAVE);
-      else if (pt.max_m >= 4 * kWidePatch) MAS_GENERIC(false, 1024);
+      else if (pt.max_m >= kFullPatch) MAS_GENERIC(false, 1024);
       else if (wide) MAS_GENERIC(false, 256);
       else MAS_GENERIC(false, WAVE);
 #undef MAS_GENERIC
@@ -841,11 +843,28 @@ void build_patches(DevArena& ar, Level<T>& L, const PatchSet& ps, const DCsr<dou
   }
   d.g0 = g0;
   d.yshift = (int64_t)dofs.size() - ycur;  // generic outputs follow the fast buckets in Y
+  // Levels of very large patches keep full velocity blocks: twice the values of
+  // the packed triangle, but every row sweep of the patch kernels reads them
+  // with consecutive addresses across threads.
+  int full_min = kFullPatch;
+  if (const char* e = std::getenv("MAS_FULL_PATCH")) full_min = std::max(1, std::atoi(e));  // threshold override
+  d.full = (groups.empty() && ps.max_m >= full_min) ? 1 : 0;
+  int64_t alg = 0;
+  d.max_f = 0;
   for (int64_t p : generic) {
     for (int c = 0; c < 4; ++c) dims[4 * pnew + c] = ps.dims[4 * p + c];
     foff[pnew] = fcur;
     fstr[pnew] = 1;
-    fcur += ps.foff[p + 1] - ps.foff[p];
+    int64_t rec = ps.foff[p + 1] - ps.foff[p];
+    if (d.full) {
+      const int32_t* q = &ps.dims[4 * p];
+      const int64_t nvp = q[0] + q[1] + q[2];
+      rec = (int64_t)q[0] * q[0] + (int64_t)q[1] * q[1] + (int64_t)q[2] * q[2] + nvp * q[3] +
+            (int64_t)q[3] * (q[3] + 1) / 2;
+    }
+    fcur += rec;
+    alg += rec;
+    d.max_f = std::max(d.max_f, rec);
     for (int64_t k = ps.off[p]; k < ps.off[p + 1]; ++k) {
       ypos.push_back(ycur);
       ++ycur;
@@ -855,7 +874,8 @@ void build_patches(DevArena& ar, Level<T>& L, const PatchSet& ps, const DCsr<dou
     ++pnew;
   }
   d.nfac = fcur;
-  d.nfac_alg = ps.foff.back();
+  d.nfac_alg = d.full ? alg : ps.foff.back();
+  if (!d.full) d.max_f = ps.max_f;
   d.ny = ycur;
   // ---- DoF -> output positions, in patch order (deterministic sums)
   const int64_t n = L.n;
@@ -944,10 +964,12 @@ void build_patches(DevArena& ar, Level<T>& L, const PatchSet& ps, const DCsr<dou
   // row updates of a Gauss-Jordan step are split between them
   if (use_lds)
     hipLaunchKernelGGL((k_vanka_factor<T, 256>), dim3(grid), dim3(256), lds_bytes, s, np, d.off, d.dims, d.foff,
-                       d.fstride, d.dofs, K64.ptr, K64.ind, K64.val, d.fac, gwork, stride, 1, max_nv, 1e-14, bad);
+                       d.fstride, d.dofs, K64.ptr, K64.ind, K64.val, d.fac, gwork, stride, 1, max_nv, 1e-14, bad,
+                       d.full);
   else
     hipLaunchKernelGGL((k_vanka_factor<T, 1024>), dim3(grid), dim3(1024), 0, s, np, d.off, d.dims, d.foff,
-                       d.fstride, d.dofs, K64.ptr, K64.ind, K64.val, d.fac, gwork, stride, 0, max_nv, 1e-14, bad);
+                       d.fstride, d.dofs, K64.ptr, K64.ind, K64.val, d.fac, gwork, stride, 0, max_nv, 1e-14, bad,
+                       d.full);
   launch_check();
   int64_t hbad = 0;
   HIPCHECK(hipMemcpyAsync(&hbad, bad, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -1279,6 +1301,16 @@ void analyze_impl(mas_handle* h, const mas_problem* pr) {
       in.n_patches[l] = patches[l].np();
       in.patch_dofs[l] = (int64_t)patches[l].dofs.size();
       in.factor_entries[l] = patches[l].foff.back();
+      if (patches[l].max_m >= kFullPatch) {  // stored as full blocks (unless fixed-shape buckets exist)
+        int64_t fe = 0;
+        const PatchSet& ps = patches[l];
+        for (int64_t p = 0; p < ps.np(); ++p) {
+          const int32_t* q = &ps.dims[4 * p];
+          fe += (int64_t)q[0] * q[0] + (int64_t)q[1] * q[1] + (int64_t)q[2] * q[2] +
+                (int64_t)(q[0] + q[1] + q[2]) * q[3] + (int64_t)q[3] * (q[3] + 1) / 2;
+        }
+        in.factor_entries[l] = fe;
+      }
     }
     in.p_nnz[l] = (l >= 2) ? Ps[l - 1].nnz() : 0;
   }
