@@ -38,12 +38,37 @@ __device__ __forceinline__ T wave_sum(T v) {
 }
 
 // ---------------------------------------------------------------------------
+// One step of the Chebyshev semi-iteration fused into a product (MODE 4): with
+// y the residual and x the current direction d, row i computes
+// r_i = y_i - (A d)_i, d'_i = a d_i + c Dinv_i r_i, writes y_i = r_i,
+// dnew_i = d'_i and adds d'_i to acc_i -- the same operations, in the same
+// order, as a MODE 3 product followed by the update d = a d + c Dinv r, acc += d.
+template <typename T>
+struct ChebStep {
+  T a, c;
+  const T* dinv;  // per row of the operator, or null (identity)
+  T* dnew;
+  T* acc;
+};
+
+template <typename T>
+__device__ __forceinline__ void cheb_row(int64_t e, int64_t row, T s, const T* __restrict__ x, T* __restrict__ y,
+                                         const ChebStep<T>& cs) {
+  const T r = y[e] - s;
+  y[e] = r;
+  const T ri = cs.dinv ? cs.dinv[row] * r : r;
+  const T di = cs.a * x[e] + cs.c * ri;
+  cs.dnew[e] = di;
+  cs.acc[e] += di;
+}
+
 // CSR products.  TEAM lanes per row (power of two <= 64).
 // MODE 0: y = A x   MODE 1: y = b - A x   MODE 2: y += A x   MODE 3: y -= A x
+// MODE 4: Chebyshev step (ChebStep)
 template <typename T, int TEAM, int MODE>
 __global__ void __launch_bounds__(256) k_csr(int n, const int* __restrict__ ptr, const int* __restrict__ ind,
                                              const T* __restrict__ val, const T* __restrict__ x,
-                                             const T* __restrict__ b, T* __restrict__ y) {
+                                             const T* __restrict__ b, T* __restrict__ y, ChebStep<T> cs) {
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int row = gid / TEAM;
   const int lane = gid & (TEAM - 1);
@@ -58,7 +83,8 @@ __global__ void __launch_bounds__(256) k_csr(int n, const int* __restrict__ ptr,
     if (MODE == 0) y[row] = s;
     else if (MODE == 1) y[row] = b[row] - s;
     else if (MODE == 2) y[row] += s;
-    else y[row] -= s;
+    else if (MODE == 3) y[row] -= s;
+    else cheb_row(row, row, s, x, y, cs);
   }
 }
 
@@ -69,7 +95,7 @@ template <typename T, int MODE>
 __global__ void __launch_bounds__(256) k_sell(int n, int64_t nslices, const int64_t* __restrict__ soff,
                                               const int* __restrict__ swidth, const int* __restrict__ ind,
                                               const T* __restrict__ val, const T* __restrict__ x,
-                                              const T* __restrict__ b, T* __restrict__ y) {
+                                              const T* __restrict__ b, T* __restrict__ y, ChebStep<T> cs) {
   const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t slice = row >> 6;
   if (slice >= nslices) return;
@@ -94,7 +120,8 @@ __global__ void __launch_bounds__(256) k_sell(int n, int64_t nslices, const int6
     if (MODE == 0) y[row] = s;
     else if (MODE == 1) y[row] = b[row] - s;
     else if (MODE == 2) y[row] += s;
-    else y[row] -= s;
+    else if (MODE == 3) y[row] -= s;
+    else cheb_row(row, row, s, x, y, cs);
   }
 }
 
@@ -160,19 +187,6 @@ __global__ void k_cheb_init(int64_t n, const T* __restrict__ r, T inv_theta, con
   }
 }
 
-// d = a d + c D^-1 res; y += d
-template <typename T>
-__global__ void k_cheb_update(int64_t n, T a, T c, const T* __restrict__ dinv, const T* __restrict__ res,
-                              T* __restrict__ d, T* __restrict__ y, int nr) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) {
-    const T ri = dinv ? dinv[i / nr] * res[i] : res[i];
-    const T di = a * d[i] + c * ri;
-    d[i] = di;
-    y[i] += di;
-  }
-}
-
 // x[i] *= m[i / nr]
 template <typename T>
 __global__ void k_mul(int64_t n, const T* __restrict__ m, T* __restrict__ x, int nr) {
@@ -214,7 +228,7 @@ template <typename T, int MODE>
 __global__ void __launch_bounds__(256) k_spmm(int64_t n, int nr, const int* __restrict__ ptr,
                                               const int* __restrict__ ind, const T* __restrict__ val,
                                               const T* __restrict__ x, const T* __restrict__ b,
-                                              T* __restrict__ y) {
+                                              T* __restrict__ y, ChebStep<T> cs) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n * nr) return;
   const int64_t row = t / nr;
@@ -235,7 +249,8 @@ __global__ void __launch_bounds__(256) k_spmm(int64_t n, int nr, const int* __re
   if (MODE == 0) y[t] = s;
   else if (MODE == 1) y[t] = b[t] - s;
   else if (MODE == 2) y[t] += s;
-  else y[t] -= s;
+  else if (MODE == 3) y[t] -= s;
+  else cheb_row(t, row, s, x, y, cs);
 }
 
 // dense coarse solve for nr right-hand sides: y = C b, FP64 accumulation

@@ -172,19 +172,21 @@ DCsr<T> upload_csr(DevArena& A, const Csr& C, hipStream_t s) {
 }
 
 template <typename T, int MODE>
-void csr_launch(const DCsr<T>& A, const T* x, const T* b, T* y, hipStream_t s) {
+void csr_launch(const DCsr<T>& A, const T* x, const T* b, T* y, hipStream_t s, ChebStep<T> cs = {}) {
   if (A.n == 0) return;
   const int bs = 256;
   if (A.use_sell) {
     hipLaunchKernelGGL((k_sell<T, MODE>), dim3(blocks_for(A.nslices * 64, bs)), dim3(bs), 0, s, (int)A.n, A.nslices,
-                       A.soff, A.swidth, A.sind, A.sval, x, b, y);
+                       A.soff, A.swidth, A.sind, A.sval, x, b, y, cs);
     launch_check();
     return;
   }
   const unsigned nb = blocks_for(A.n * (int64_t)A.team, bs);
   switch (A.team) {
 #define CASE(TM) \
-  case TM: hipLaunchKernelGGL((k_csr<T, TM, MODE>), dim3(nb), dim3(bs), 0, s, (int)A.n, A.ptr, A.ind, A.val, x, b, y); break;
+  case TM:                                                                                                 \
+    hipLaunchKernelGGL((k_csr<T, TM, MODE>), dim3(nb), dim3(bs), 0, s, (int)A.n, A.ptr, A.ind, A.val, x, b, y, cs); \
+    break;
     CASE(2) CASE(4) CASE(8) CASE(16) CASE(32) CASE(64)
 #undef CASE
     default: throw MasError(MAS_EINVAL, "bad team size");
@@ -290,7 +292,7 @@ struct DDlsc {
   int64_t nv = 0, np = 0;
   T *ru = nullptr, *vs = nullptr, *tmp = nullptr, *t1 = nullptr, *t2 = nullptr;  // velocity-sized
   T *rp = nullptr, *q = nullptr, *dp = nullptr;                                 // pressure-sized
-  T *cd = nullptr, *cres = nullptr;                                             // Chebyshev work (max size)
+  T *cd = nullptr, *cd2 = nullptr, *cres = nullptr;                             // Chebyshev work (max size)
 };
 
 template <typename T>
@@ -367,7 +369,7 @@ struct Cycle : CycleBase {
   DCsr<T> Mdg, P0t, P0p, Mcg;
   T* mcg_dinv = nullptr;
   int mass_steps = 0;
-  T *sv_t0 = nullptr, *sv_t1 = nullptr, *sv_z = nullptr, *sv_cd = nullptr, *sv_cres = nullptr;
+  T *sv_t0 = nullptr, *sv_t1 = nullptr, *sv_z = nullptr, *sv_cd = nullptr, *sv_cd2 = nullptr, *sv_cres = nullptr;
 
   // b1 = eta R0 r0
   void restrict0(const T* r0, Level<T>& L1, hipStream_t s) {
@@ -383,7 +385,7 @@ struct Cycle : CycleBase {
     spmv<0>(Mdg, r0 + nv, nullptr, sv_t0, s);   // M_dg r0_p
     spmv<0>(P0t, sv_t0, nullptr, sv_t1, s);     // (P0^p)^T M_dg r0_p
     // M_cg z = t1: Jacobi-preconditioned Chebyshev with the P1 bounds lambda(D^-1 M) in [1/2, 2]
-    chebyshev_iv(Mcg, sv_t1, sv_z, 0.5, 2.0, mass_steps, mcg_dinv, sv_cd, sv_cres, s);
+    chebyshev_iv(Mcg, sv_t1, sv_z, 0.5, 2.0, mass_steps, mcg_dinv, sv_cd, sv_cd2, sv_cres, s);
     hipLaunchKernelGGL((k_axpby<T>), dim3(blocks_for(np1 * nr, 256)), dim3(256), 0, s, np1 * nr, (T)par.eta_p,
                        sv_z, (T)0, L1.b + nv);
     launch_check();
@@ -407,47 +409,50 @@ struct Cycle : CycleBase {
 
   // sparse product, timed (with its algorithmic bytes) when timing is on
   template <int MODE>
-  void spmv(const DCsr<T>& A, const T* x, const T* b, T* y, hipStream_t s) {
+  void spmv(const DCsr<T>& A, const T* x, const T* b, T* y, hipStream_t s, ChebStep<T> cs = {}) {
     hipEvent_t e0{}, e1{};
     const bool t = tm && tm->on;
     if (t) tm->begin(e0, e1, s);
     if (nr == 1) {
-      csr_launch<T, MODE>(A, x, b, y, s);
+      csr_launch<T, MODE>(A, x, b, y, s, cs);
     } else if (A.n > 0) {
       hipLaunchKernelGGL((k_spmm<T, MODE>), dim3(blocks_for(A.n * nr, 256)), dim3(256), 0, s, A.n, nr, A.ptr, A.ind,
-                         A.val, x, b, y);
+                         A.val, x, b, y, cs);
       launch_check();
     }
     if (t) {
       const double sz = sizeof(T);
-      const double vec = (A.m * sz + A.n * sz * (MODE == 0 ? 1.0 : 2.0)) * nr;
+      // MODE 4 also reads the direction once more and writes the new direction and the sum
+      const double vec = (A.m * sz + A.n * sz * (MODE == 0 ? 1.0 : MODE == 4 ? 5.0 : 2.0)) * nr;
       tm->end(e0, e1, s, A.nnz * (sz + 4.0) + (A.n + 1) * 4.0 + vec, nr > 1 ? TK_SPMM : A.use_sell ? TK_SELL : TK_CSR);
     }
   }
 
   // y ~ X^{-1} r: `deg` steps of the Chebyshev semi-iteration from y = 0 for the
   // spectrum interval [lo, hi] of D^-1 X (D^-1 = dinv, identity when null)
-  void chebyshev_iv(DCsr<T>& X, const T* r, T* y, double lo, double hi, int deg, const T* dinv, T* cd, T* cres,
-                    hipStream_t s) {
+  void chebyshev_iv(DCsr<T>& X, const T* r, T* y, double lo, double hi, int deg, const T* dinv, T* cd, T* cd2,
+                    T* cres, hipStream_t s) {
     const int64_t n = X.n * nr;
     const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
     double rho = 1.0 / sigma;
     const unsigned nb = blocks_for(n, 256);
     hipLaunchKernelGGL((k_cheb_init<T>), dim3(nb), dim3(256), 0, s, n, r, (T)(1.0 / theta), dinv, cd, cres, y, nr);
     launch_check();
+    // each step is one fused product (residual update, direction, sum); the
+    // directions alternate between cd and cd2
+    T* dcur = cd;
+    T* dnext = cd2;
     for (int k = 0; k + 1 < deg; ++k) {
-      spmv<3>(X, cd, nullptr, cres, s);
       const double rho_new = 1.0 / (2.0 * sigma - rho);
-      hipLaunchKernelGGL((k_cheb_update<T>), dim3(nb), dim3(256), 0, s, n, (T)(rho_new * rho),
-                         (T)(2.0 * rho_new / delta), dinv, cres, cd, y, nr);
-      launch_check();
+      spmv<4>(X, dcur, nullptr, cres, s, ChebStep<T>{(T)(rho_new * rho), (T)(2.0 * rho_new / delta), dinv, dnext, y});
+      std::swap(dcur, dnext);
       rho = rho_new;
     }
   }
 
   // DLSC inner solves: interval [0.5^dim lam, 1.1 lam] (Table 3)
   void chebyshev(DCsr<T>& X, const T* r, T* y, double lam, int deg, DDlsc<T>& D, hipStream_t s) {
-    chebyshev_iv(X, r, y, std::pow(0.5, dim) * lam, 1.1 * lam, deg, nullptr, D.cd, D.cres, s);
+    chebyshev_iv(X, r, y, std::pow(0.5, dim) * lam, 1.1 * lam, deg, nullptr, D.cd, D.cd2, D.cres, s);
   }
 
   // one DLSC sweep (Algorithm 2) on level L: x = (u, p), b = (f, g)
@@ -1034,6 +1039,7 @@ std::unique_ptr<Cycle<T>> build_cycle(mas_handle* h, const std::vector<Csr>& Ks,
         for (T** v : {&D.ru, &D.vs, &D.tmp, &D.t1, &D.t2}) *v = ar.alloc<T>(D.nv * R);
         for (T** v : {&D.rp, &D.q, &D.dp}) *v = ar.alloc<T>(D.np * R);
         D.cd = ar.alloc<T>(std::max(D.nv, D.np) * R);
+        D.cd2 = ar.alloc<T>(std::max(D.nv, D.np) * R);
         D.cres = ar.alloc<T>(std::max(D.nv, D.np) * R);
       }
     }
@@ -1083,6 +1089,7 @@ std::unique_ptr<Cycle<T>> build_cycle(mas_handle* h, const std::vector<Csr>& Ks,
     cyc->sv_t1 = ar.alloc<T>(cyc->np1 * R);
     cyc->sv_z = ar.alloc<T>(cyc->np1 * R);
     cyc->sv_cd = ar.alloc<T>(cyc->np1 * R);
+    cyc->sv_cd2 = ar.alloc<T>(cyc->np1 * R);
     cyc->sv_cres = ar.alloc<T>(cyc->np1 * R);
     for (DCsr<T>* A : {&cyc->Mdg, &cyc->P0t, &cyc->P0p, &cyc->Mcg}) A->use_sell = false;
   }
@@ -1617,7 +1624,7 @@ int fgmres_nr(mas_handle* h, const double* b, double* x, int nr, const double* r
       h->cyc->apply(vj, zj, s);
       double* w = h->w;
       hipLaunchKernelGGL((k_spmm<double, 0>), dim3(blocks_for(n * nr, 256)), dim3(256), 0, s, n, nr, h->K0full.ptr,
-                         h->K0full.ind, h->K0full.val, zj, nullptr, w);
+                         h->K0full.ind, h->K0full.val, zj, nullptr, w, ChebStep<double>{});
       double* part[2] = {h->partial, h->partial + (size_t)nb * nr};
       for (int i = 0; i <= j + 1; ++i) {
         const double* vprev = i > 0 ? h->V + (int64_t)(i - 1) * n * nr : nullptr;
@@ -1693,7 +1700,7 @@ int fgmres_nr(mas_handle* h, const double* b, double* x, int nr, const double* r
     HIPCHECK(hipMemcpyAsync(h->ydev, h->hhost, y.size() * sizeof(double), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_update_x_nr, dim3(blocks_for(n * nr, 256)), dim3(256), 0, s, n, nr, kk, h->Z, h->ydev, x);
     hipLaunchKernelGGL((k_spmm<double, 1>), dim3(blocks_for(n * nr, 256)), dim3(256), 0, s, n, nr, h->K0full.ptr,
-                       h->K0full.ind, h->K0full.val, x, b, r);
+                       h->K0full.ind, h->K0full.val, x, b, r, ChebStep<double>{});
     launch_check();
     col_norms(r, beta);
     bool all = true;
