@@ -88,9 +88,46 @@ def estimate_device_bytes(info: dict, precision: int, max_batch: int) -> int:
     return int(1.3 * (ops + pat + coarse + k0)) + (16 << 20)
 
 
+class TorchDevice:
+    """Streams and device arrays of the server, through torch (one GPU)."""
+
+    def __init__(self):
+        import torch
+        self.torch = torch
+
+    def new_stream(self):
+        return self.torch.cuda.Stream()  # default priority
+
+    def stream_handle(self, stream):
+        return stream.cuda_stream
+
+    def on_stream(self, stream):
+        return self.torch.cuda.stream(stream)
+
+    def upload(self, a: np.ndarray):
+        return self.torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+    def empty_like(self, t):
+        return self.torch.empty_like(t)
+
+    def download(self, t) -> np.ndarray:
+        return t.cpu().numpy()
+
+
+def _analysed_handle(problem, par):
+    return mas.Handle(problem, par, analyze_only=True)
+
+
 class StokesServer:
+    """``device`` (streams, arrays) and ``handle_factory(problem, params)``
+    (an analysed handle with upload/release/info/scale_rows/solve/close) default
+    to torch on cuda:0 and libmas; other implementations serve to test the
+    scheduling on the host."""
+
     def __init__(self, hbm_budget: int, max_batch: int = 32, workers: int = 4,
-                 precision: int = mas.MAS_FP32, params: dict | None = None):
+                 precision: int = mas.MAS_FP32, params: dict | None = None, device=None, handle_factory=None):
+        self.device = device
+        self.handle_factory = handle_factory or _analysed_handle
         self.budget = int(hbm_budget)
         self.max_batch = int(max_batch)
         self.precision = precision
@@ -118,7 +155,7 @@ class StokesServer:
         disc = mas.MAS_SV if problem.disc == "SV" else mas.MAS_TH
         par = mas.default_params(problem.dim, disc, precision=self.precision, nrhs_max=self.max_batch,
                                  **self.params)
-        h = mas.Handle(problem, par, analyze_only=True)
+        h = self.handle_factory(problem, par)
         est = int(device_bytes) if device_bytes else estimate_device_bytes(h.info(), self.precision,
                                                                              self.max_batch)
         with self.cv:
@@ -132,6 +169,8 @@ class StokesServer:
         return est
 
     def start(self):
+        if self.device is None:
+            self.device = TorchDevice()
         self.threads = [threading.Thread(target=self._worker, daemon=True) for _ in range(self.n_workers)]
         for t in self.threads:
             t.start()
@@ -216,8 +255,8 @@ class StokesServer:
         return None
 
     def _worker(self):
-        import torch
-        stream = torch.cuda.Stream()
+        dev = self.device
+        stream = dev.new_stream()
         while True:
             with self.cv:
                 while True:
@@ -233,8 +272,8 @@ class StokesServer:
                     self.resident += m.est_bytes  # reserved while uploading
                     self.peak_resident = max(self.peak_resident, self.resident)
             try:
-                with torch.cuda.stream(stream):
-                    self._run_batch(m, batch, stream, torch)
+                with dev.on_stream(stream):
+                    self._run_batch(m, batch, dev, stream)
             except Exception as e:  # the batch fails, the server keeps going
                 for r in batch:
                     r.error = str(e)
@@ -247,8 +286,8 @@ class StokesServer:
                 m.last_used = time.perf_counter()
                 self.cv.notify_all()
 
-    def _run_batch(self, m: _Mesh, batch, stream, torch):
-        st = stream.cuda_stream
+    def _run_batch(self, m: _Mesh, batch, dev, stream):
+        st = dev.stream_handle(stream)
         h = m.handle
         if not m.resident:
             h.upload(stream=st)
@@ -265,15 +304,15 @@ class StokesServer:
             r.t_start = t0
             r.batch = nr
         B = np.stack([np.asarray(r.b, dtype=np.float64) for r in batch], 1)
-        Bd = torch.from_numpy(np.ascontiguousarray(B)).to("cuda:0", non_blocking=False)
-        Xd = torch.empty_like(Bd)
+        Bd = dev.upload(B)
+        Xd = dev.empty_like(Bd)
         su = [1.0 / math.sqrt(r.nu) for r in batch]  # S^-1 on velocity rows
         sp = [math.sqrt(r.nu) for r in batch]        # S^-1 on pressure rows
         h.scale_rows(Bd, su, sp, nrhs=nr, dirichlet_inverse=True, stream=st)
         tols = [r.rtol / max(r.nu, 1.0 / r.nu) for r in batch]
         rc, info = h.solve(Bd, Xd, rtol=tols if nr > 1 else tols[0], nrhs=nr, stream=st)
         h.scale_rows(Xd, su, sp, nrhs=nr, stream=st)
-        X = Xd.cpu().numpy().reshape(m.n0, nr)
+        X = dev.download(Xd).reshape(m.n0, nr)
         t1 = time.perf_counter()
         with self.cv:
             self.batches += 1
