@@ -46,7 +46,7 @@ __device__ __forceinline__ T wave_sum(T v) {
 template <typename T>
 struct ChebStep {
   T a, c;
-  const T* dinv;  // per row of the operator, or null (identity)
+  const T* dinv;  // per row of the operator, or null (identity); MODE 5: the row scale m
   T* dnew;
   T* acc;
 };
@@ -64,7 +64,7 @@ __device__ __forceinline__ void cheb_row(int64_t e, int64_t row, T s, const T* _
 
 // CSR products.  TEAM lanes per row (power of two <= 64).
 // MODE 0: y = A x   MODE 1: y = b - A x   MODE 2: y += A x   MODE 3: y -= A x
-// MODE 4: Chebyshev step (ChebStep)
+// MODE 4: Chebyshev step (ChebStep)   MODE 5: y = a m (A x), m = cs.dinv per row (or 1)
 template <typename T, int TEAM, int MODE>
 __global__ void __launch_bounds__(256) k_csr(int n, const int* __restrict__ ptr, const int* __restrict__ ind,
                                              const T* __restrict__ val, const T* __restrict__ x,
@@ -84,7 +84,8 @@ __global__ void __launch_bounds__(256) k_csr(int n, const int* __restrict__ ptr,
     else if (MODE == 1) y[row] = b[row] - s;
     else if (MODE == 2) y[row] += s;
     else if (MODE == 3) y[row] -= s;
-    else cheb_row(row, row, s, x, y, cs);
+    else if (MODE == 4) cheb_row(row, row, s, x, y, cs);
+    else y[row] = cs.a * (cs.dinv ? cs.dinv[row] * s : s);
   }
 }
 
@@ -121,7 +122,8 @@ __global__ void __launch_bounds__(256) k_sell(int n, int64_t nslices, const int6
     else if (MODE == 1) y[row] = b[row] - s;
     else if (MODE == 2) y[row] += s;
     else if (MODE == 3) y[row] -= s;
-    else cheb_row(row, row, s, x, y, cs);
+    else if (MODE == 4) cheb_row(row, row, s, x, y, cs);
+    else y[row] = cs.a * (cs.dinv ? cs.dinv[row] * s : s);
   }
 }
 
@@ -187,6 +189,15 @@ __global__ void k_cheb_init(int64_t n, const T* __restrict__ r, T inv_theta, con
   }
 }
 
+// end of a DLSC sweep on x = (u, p): u += v + t (first nu entries), p += dp
+template <typename T>
+__global__ void k_dlsc_update(int64_t nu, int64_t np, T* __restrict__ x, const T* __restrict__ v,
+                              const T* __restrict__ t, const T* __restrict__ dp) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nu) x[i] += v[i] + t[i];
+  else if (i < nu + np) x[i] += dp[i - nu];
+}
+
 // x[i] *= m[i / nr]
 template <typename T>
 __global__ void k_mul(int64_t n, const T* __restrict__ m, T* __restrict__ x, int nr) {
@@ -250,7 +261,8 @@ __global__ void __launch_bounds__(256) k_spmm(int64_t n, int nr, const int* __re
   else if (MODE == 1) y[t] = b[t] - s;
   else if (MODE == 2) y[t] += s;
   else if (MODE == 3) y[t] -= s;
-  else cheb_row(t, row, s, x, y, cs);
+  else if (MODE == 4) cheb_row(t, row, s, x, y, cs);
+  else y[t] = cs.a * (cs.dinv ? cs.dinv[row] * s : s);
 }
 
 // dense coarse solve for nr right-hand sides: y = C b, FP64 accumulation

@@ -463,22 +463,21 @@ struct Cycle : CycleBase {
     T* p = L.x + nv;
     const T* f = L.b;
     const T* g = L.b + nv;
-    const unsigned bv = blocks_for(nv, 256), bp = blocks_for(np, 256);
+    const unsigned bv = blocks_for(nv, 256);
     spmv<1>(D.A, u, f, D.ru, s);  // ru = f - A u - B^T p
     spmv<3>(D.Bt, p, nullptr, D.ru, s);
     chebyshev(D.A, D.ru, D.vs, D.lamA, par.cheb_deg[0], D, s);  // momentum
     hipLaunchKernelGGL((k_add<T>), dim3(bv), dim3(256), 0, s, nv, u, D.vs, D.tmp);
     spmv<1>(D.B, D.tmp, g, D.rp, s);  // rp = g - B (u + v*)
     chebyshev(D.S, D.rp, D.q, D.lamS, par.cheb_deg[1], D, s);  // continuity
-    spmv<0>(D.Bt, D.q, nullptr, D.t1, s);  // t1 = M^-1 B^T q
-    hipLaunchKernelGGL((k_mul<T>), dim3(bv), dim3(256), 0, s, nv, D.minv, D.t1, nr);
-    spmv<0>(D.A, D.t1, nullptr, D.t2, s);  // t2 = M^-1 A M^-1 B^T q
-    hipLaunchKernelGGL((k_mul<T>), dim3(bv), dim3(256), 0, s, nv, D.minv, D.t2, nr);
-    spmv<0>(D.B, D.t2, nullptr, D.rp, s);  // rp = B t2; the right-hand side is -rp
-    hipLaunchKernelGGL((k_axpby<T>), dim3(bp), dim3(256), 0, s, np, (T)0, D.rp, (T)-1, D.rp);
+    // scaled products (MODE 5: y = a m (A x)) fold the M^-1 scalings and the sign in
+    spmv<5>(D.Bt, D.q, nullptr, D.t1, s, ChebStep<T>{(T)1, (T)0, D.minv, nullptr, nullptr});  // t1 = M^-1 B^T q
+    spmv<5>(D.A, D.t1, nullptr, D.t2, s, ChebStep<T>{(T)1, (T)0, D.minv, nullptr, nullptr});  // t2 = M^-1 A t1
+    spmv<5>(D.B, D.t2, nullptr, D.rp, s, ChebStep<T>{(T)-1, (T)0, nullptr, nullptr, nullptr});  // rp = -B t2
     chebyshev(D.S, D.rp, D.dp, D.lamS, par.cheb_deg[2], D, s);  // pressure correction
-    hipLaunchKernelGGL((k_add3<T>), dim3(bv), dim3(256), 0, s, nv, u, D.vs, D.t1);  // u += v* + M^-1 B^T q
-    hipLaunchKernelGGL((k_axpby<T>), dim3(bp), dim3(256), 0, s, np, (T)1, D.dp, (T)1, p);  // p += dp
+    // u += v* + M^-1 B^T q, p += dp (u and p are contiguous in L.x)
+    hipLaunchKernelGGL((k_dlsc_update<T>), dim3(blocks_for(nv + np, 256)), dim3(256), 0, s, nv, np, u, D.vs, D.t1,
+                       D.dp);
     launch_check();
   }
 
