@@ -49,7 +49,19 @@ struct ChebStep {
   const T* dinv;  // per row of the operator, or null (identity); MODE 5: the row scale m
   T* dnew;
   T* acc;
+  T* res = nullptr;  // MODES 1, 3, 5 with res set: also start a Chebyshev iteration from
+                     // the row value v: res = v, dnew = acc = c * (Dinv v) (Dinv = cinv)
+  const T* cinv = nullptr;
 };
+
+// start of a Chebyshev iteration from the residual value v of row `row`
+template <typename T>
+__device__ __forceinline__ void cheb_start(int64_t e, int64_t row, T v, const ChebStep<T>& cs) {
+  const T di = (cs.cinv ? cs.cinv[row] * v : v) * cs.c;
+  cs.dnew[e] = di;
+  cs.res[e] = v;
+  cs.acc[e] = di;
+}
 
 template <typename T>
 __device__ __forceinline__ void cheb_row(int64_t e, int64_t row, T s, const T* __restrict__ x, T* __restrict__ y,
@@ -62,9 +74,28 @@ __device__ __forceinline__ void cheb_row(int64_t e, int64_t row, T s, const T* _
   cs.acc[e] += di;
 }
 
+// the result s = (A x)_row of a product, stored as the mode asks (entry e of
+// the interleaved vectors)
+template <typename T, int MODE>
+__device__ __forceinline__ void store_row(int64_t e, int64_t row, T s, const T* __restrict__ x,
+                                          const T* __restrict__ b, T* __restrict__ y, const ChebStep<T>& cs) {
+  if (MODE == 0) {
+    y[e] = s;
+  } else if (MODE == 2) {
+    y[e] += s;
+  } else if (MODE == 4) {
+    cheb_row(e, row, s, x, y, cs);
+  } else {
+    const T v = MODE == 1 ? b[e] - s : MODE == 3 ? y[e] - s : cs.a * (cs.dinv ? cs.dinv[row] * s : s);
+    y[e] = v;
+    if (cs.res) cheb_start(e, row, v, cs);
+  }
+}
+
 // CSR products.  TEAM lanes per row (power of two <= 64).
 // MODE 0: y = A x   MODE 1: y = b - A x   MODE 2: y += A x   MODE 3: y -= A x
 // MODE 4: Chebyshev step (ChebStep)   MODE 5: y = a m (A x), m = cs.dinv per row (or 1)
+// MODES 1, 3, 5 start a Chebyshev iteration from the stored value when cs.res is set
 template <typename T, int TEAM, int MODE>
 __global__ void __launch_bounds__(256) k_csr(int n, const int* __restrict__ ptr, const int* __restrict__ ind,
                                              const T* __restrict__ val, const T* __restrict__ x,
@@ -79,14 +110,7 @@ __global__ void __launch_bounds__(256) k_csr(int n, const int* __restrict__ ptr,
   }
 #pragma unroll
   for (int o = TEAM / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
-  if (row < n && lane == 0) {
-    if (MODE == 0) y[row] = s;
-    else if (MODE == 1) y[row] = b[row] - s;
-    else if (MODE == 2) y[row] += s;
-    else if (MODE == 3) y[row] -= s;
-    else if (MODE == 4) cheb_row(row, row, s, x, y, cs);
-    else y[row] = cs.a * (cs.dinv ? cs.dinv[row] * s : s);
-  }
+  if (row < n && lane == 0) store_row<T, MODE>(row, row, s, x, b, y, cs);
 }
 
 // Sliced ELL, 64 rows per slice (one wavefront, one lane per row), entries of a
@@ -117,14 +141,7 @@ __global__ void __launch_bounds__(256) k_sell(int n, int64_t nslices, const int6
     s0 += val[e] * x[ind[e]];
   }
   const T s = (s0 + s1) + (s2 + s3);
-  if (row < n) {
-    if (MODE == 0) y[row] = s;
-    else if (MODE == 1) y[row] = b[row] - s;
-    else if (MODE == 2) y[row] += s;
-    else if (MODE == 3) y[row] -= s;
-    else if (MODE == 4) cheb_row(row, row, s, x, y, cs);
-    else y[row] = cs.a * (cs.dinv ? cs.dinv[row] * s : s);
-  }
+  if (row < n) store_row<T, MODE>(row, row, s, x, b, y, cs);
 }
 
 // ---------------------------------------------------------------------------
@@ -257,12 +274,7 @@ __global__ void __launch_bounds__(256) k_spmm(int64_t n, int nr, const int* __re
     s += val[e + 3] * x3;
   }
   for (; e < end; ++e) s += val[e] * x[(int64_t)ind[e] * nr + k];
-  if (MODE == 0) y[t] = s;
-  else if (MODE == 1) y[t] = b[t] - s;
-  else if (MODE == 2) y[t] += s;
-  else if (MODE == 3) y[t] -= s;
-  else if (MODE == 4) cheb_row(t, row, s, x, y, cs);
-  else y[t] = cs.a * (cs.dinv ? cs.dinv[row] * s : s);
+  store_row<T, MODE>(t, row, s, x, b, y, cs);
 }
 
 // dense coarse solve for nr right-hand sides: y = C b, FP64 accumulation

@@ -430,14 +430,18 @@ struct Cycle : CycleBase {
 
   // y ~ X^{-1} r: `deg` steps of the Chebyshev semi-iteration from y = 0 for the
   // spectrum interval [lo, hi] of D^-1 X (D^-1 = dinv, identity when null)
+  // The start of the iteration (d = Dinv r / theta, res = r, y = d) is done
+  // here, or, when `started`, by the product that produced r (cheb_start below).
   void chebyshev_iv(DCsr<T>& X, const T* r, T* y, double lo, double hi, int deg, const T* dinv, T* cd, T* cd2,
-                    T* cres, hipStream_t s) {
+                    T* cres, hipStream_t s, bool started = false) {
     const int64_t n = X.n * nr;
     const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
     double rho = 1.0 / sigma;
     const unsigned nb = blocks_for(n, 256);
-    hipLaunchKernelGGL((k_cheb_init<T>), dim3(nb), dim3(256), 0, s, n, r, (T)(1.0 / theta), dinv, cd, cres, y, nr);
-    launch_check();
+    if (!started) {
+      hipLaunchKernelGGL((k_cheb_init<T>), dim3(nb), dim3(256), 0, s, n, r, (T)(1.0 / theta), dinv, cd, cres, y, nr);
+      launch_check();
+    }
     // each step is one fused product (residual update, direction, sum); the
     // directions alternate between cd and cd2
     T* dcur = cd;
@@ -451,8 +455,19 @@ struct Cycle : CycleBase {
   }
 
   // DLSC inner solves: interval [0.5^dim lam, 1.1 lam] (Table 3)
-  void chebyshev(DCsr<T>& X, const T* r, T* y, double lam, int deg, DDlsc<T>& D, hipStream_t s) {
-    chebyshev_iv(X, r, y, std::pow(0.5, dim) * lam, 1.1 * lam, deg, nullptr, D.cd, D.cd2, D.cres, s);
+  void chebyshev(DCsr<T>& X, const T* r, T* y, double lam, int deg, DDlsc<T>& D, hipStream_t s,
+                 bool started = false) {
+    chebyshev_iv(X, r, y, std::pow(0.5, dim) * lam, 1.1 * lam, deg, nullptr, D.cd, D.cd2, D.cres, s, started);
+  }
+
+  // epilogue for the product that produces the right-hand side of a DLSC
+  // Chebyshev solve (sign a for MODE 5): it also starts that iteration
+  ChebStep<T> cheb_start(double lam, T* y, DDlsc<T>& D, T a = (T)1) const {
+    const double theta = 0.5 * (std::pow(0.5, dim) * lam + 1.1 * lam);
+    ChebStep<T> cs{a, (T)(1.0 / theta), nullptr, D.cd, y};
+    cs.res = D.cres;
+    cs.cinv = nullptr;
+    return cs;
   }
 
   // one DLSC sweep (Algorithm 2) on level L: x = (u, p), b = (f, g)
@@ -464,17 +479,18 @@ struct Cycle : CycleBase {
     const T* f = L.b;
     const T* g = L.b + nv;
     const unsigned bv = blocks_for(nv, 256);
+    // each product that produces a Chebyshev right-hand side also starts that iteration
     spmv<1>(D.A, u, f, D.ru, s);  // ru = f - A u - B^T p
-    spmv<3>(D.Bt, p, nullptr, D.ru, s);
-    chebyshev(D.A, D.ru, D.vs, D.lamA, par.cheb_deg[0], D, s);  // momentum
+    spmv<3>(D.Bt, p, nullptr, D.ru, s, cheb_start(D.lamA, D.vs, D));
+    chebyshev(D.A, D.ru, D.vs, D.lamA, par.cheb_deg[0], D, s, true);  // momentum
     hipLaunchKernelGGL((k_add<T>), dim3(bv), dim3(256), 0, s, nv, u, D.vs, D.tmp);
-    spmv<1>(D.B, D.tmp, g, D.rp, s);  // rp = g - B (u + v*)
-    chebyshev(D.S, D.rp, D.q, D.lamS, par.cheb_deg[1], D, s);  // continuity
+    spmv<1>(D.B, D.tmp, g, D.rp, s, cheb_start(D.lamS, D.q, D));  // rp = g - B (u + v*)
+    chebyshev(D.S, D.rp, D.q, D.lamS, par.cheb_deg[1], D, s, true);  // continuity
     // scaled products (MODE 5: y = a m (A x)) fold the M^-1 scalings and the sign in
     spmv<5>(D.Bt, D.q, nullptr, D.t1, s, ChebStep<T>{(T)1, (T)0, D.minv, nullptr, nullptr});  // t1 = M^-1 B^T q
     spmv<5>(D.A, D.t1, nullptr, D.t2, s, ChebStep<T>{(T)1, (T)0, D.minv, nullptr, nullptr});  // t2 = M^-1 A t1
-    spmv<5>(D.B, D.t2, nullptr, D.rp, s, ChebStep<T>{(T)-1, (T)0, nullptr, nullptr, nullptr});  // rp = -B t2
-    chebyshev(D.S, D.rp, D.dp, D.lamS, par.cheb_deg[2], D, s);  // pressure correction
+    spmv<5>(D.B, D.t2, nullptr, D.rp, s, cheb_start(D.lamS, D.dp, D, (T)-1));  // rp = -B t2
+    chebyshev(D.S, D.rp, D.dp, D.lamS, par.cheb_deg[2], D, s, true);  // pressure correction
     // u += v* + M^-1 B^T q, p += dp (u and p are contiguous in L.x)
     hipLaunchKernelGGL((k_dlsc_update<T>), dim3(blocks_for(nv + np, 256)), dim3(256), 0, s, nv, np, u, D.vs, D.t1,
                        D.dp);
