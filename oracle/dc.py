@@ -46,6 +46,8 @@ class Params:
     max_coarse: int = 300
     max_levels: int = 10
     seed: int = 0x5EED
+    krylov_its: int = 0  # >0: FGMRES(krylov_its)-wrapped Vanka instead of damped sweeps (Section 3.3.1);
+                         # Scott-Vogelius keeps the stationary sweep on K0
 
 
 class DCPreconditioner:
@@ -113,6 +115,8 @@ class DCPreconditioner:
     def _relax(self, l: int, K, b, x, sweeps: int, omega: float):
         R = self.relax[l]
         if isinstance(R, vanka.Patches):
+            if self.par.krylov_its > 0 and not (self.disc == "SV" and l == 0):
+                return vanka.krylov_relax(K, R, b, x, self.par.krylov_its)  # one wrapped relaxation
             for _ in range(sweeps):
                 x = vanka.sweep(K, R, b, x, omega)
             return x

@@ -90,3 +90,35 @@ def sweep(K: sp.csr_matrix, P: Patches, b: np.ndarray, x: np.ndarray, omega: flo
         yi = np.linalg.solve(Ki, r[idx][..., None])[..., 0]  # dense LU per patch
         np.add.at(upd, idx.ravel(), (P.weight[idx] * yi).ravel())
     return x + omega * upd
+
+
+def krylov_relax(K: sp.csr_matrix, P: Patches, b: np.ndarray, x: np.ndarray, its: int) -> np.ndarray:
+    """Relaxation accelerated by FGMRES (Section 3.3.1, the relaxation wrapper
+    that replaces the damping parameter): `its` iterations of flexible,
+    right-preconditioned GMRES on K e = b - K x from e = 0, the preconditioner
+    being one undamped additive Vanka sweep; returns x + e.  Arnoldi with
+    modified Gram-Schmidt; the small least-squares problem is solved directly."""
+    r = b - K @ x
+    beta = np.linalg.norm(r)
+    if beta == 0.0:
+        return x.copy()
+    V = [r / beta]
+    Z = []
+    H = np.zeros((its + 1, its))
+    k = 0
+    for j in range(its):
+        z = sweep(K, P, V[j], np.zeros_like(x), 1.0)
+        Z.append(z)
+        w = K @ z
+        for i in range(j + 1):
+            H[i, j] = V[i] @ w
+            w = w - H[i, j] * V[i]
+        H[j + 1, j] = np.linalg.norm(w)
+        k = j + 1
+        if H[j + 1, j] == 0.0:  # the correction lies in the space built so far
+            break
+        V.append(w / H[j + 1, j])
+    g = np.zeros(k + 1)
+    g[0] = beta
+    y = np.linalg.lstsq(H[:k + 1, :k], g, rcond=None)[0]
+    return x + np.column_stack(Z[:k]) @ y

@@ -96,6 +96,84 @@ def test_single_patch_vanka_is_exact():
 
 
 # --------------------------------------------------------------------------
+# FGMRES-wrapped relaxation (Section 3.3.1)
+
+def small_saddle(seed, nv=9):
+    rng = np.random.default_rng(seed)
+    G = rng.standard_normal((nv, nv))
+    A = G @ G.T + nv * np.eye(nv)
+    bt = rng.standard_normal((1, nv))
+    return rng, sp.csr_matrix(np.block([[A, bt.T], [bt, np.zeros((1, 1))]]))
+
+
+def test_wrapped_relaxation_exact_with_one_patch():
+    """With a single patch the preconditioner is K^-1: one iteration solves."""
+    rng, K = small_saddle(7)
+    fld = np.array([0] * 5 + [1] * 4 + [2], dtype=np.int8)
+    pt = vanka.patches_single_seed(K, fld, 2)
+    b = rng.standard_normal(10)
+    x0 = rng.standard_normal(10)
+    x = vanka.krylov_relax(K, pt, b, x0, 1)
+    assert np.linalg.norm(K @ x - b) <= 1e-12 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("its", [1, 2, 3])
+def test_wrapped_relaxation_beats_every_damping(its):
+    """FGMRES minimises the residual over a space holding omega M r for every
+    omega, so its residual is at most that of the best damped sweep (scanned
+    here), and the first iteration equals the best damping exactly."""
+    P = make_problem(dim=2, n=6, jitter=0.2, seed=3, forcing="gaussian", bc="lid")
+    pre = dc.DCPreconditioner(P, dc.default_params(P, max_coarse=30))
+    K, pt = pre.K0, pre.relax[0]
+    rng = np.random.default_rng(1)
+    b = rng.standard_normal(K.shape[0])
+    x0 = 0.1 * rng.standard_normal(K.shape[0])
+    x = vanka.krylov_relax(K, pt, b, x0, its)
+    res = np.linalg.norm(b - K @ x)
+    r0 = b - K @ x0
+    d = vanka.sweep(K, pt, r0, np.zeros_like(x0), 1.0)
+    Kd = K @ d
+    best = min(np.linalg.norm(r0 - w * Kd) for w in np.linspace(0.0, 2.0, 2001))
+    assert res <= best * (1 + 1e-12)
+    if its == 1:  # one iteration: the residual-minimising damping in closed form
+        w_opt = (Kd @ r0) / (Kd @ Kd)
+        assert np.linalg.norm(x - (x0 + w_opt * d)) <= 1e-10 * np.linalg.norm(x)
+
+
+def test_wrapped_relaxation_zero_residual_and_scaling():
+    """A zero residual leaves x unchanged (exactly when it is exactly zero);
+    scaling b and x scales the result."""
+    P = make_problem(dim=2, n=4, seed=2, forcing="gaussian", bc="zero")
+    pre = dc.DCPreconditioner(P, dc.default_params(P, max_coarse=30))
+    K, pt = pre.K0, pre.relax[0]
+    rng = np.random.default_rng(2)
+    x0 = rng.standard_normal(K.shape[0])
+    assert np.array_equal(vanka.krylov_relax(K, pt, np.zeros_like(x0), np.zeros_like(x0), 2), np.zeros_like(x0))
+    assert np.linalg.norm(vanka.krylov_relax(K, pt, K @ x0, x0, 2) - x0) <= 1e-13 * np.linalg.norm(x0)
+    b = rng.standard_normal(K.shape[0])
+    x1 = vanka.krylov_relax(K, pt, b, x0, 2)
+    x2 = vanka.krylov_relax(K, pt, 3.0 * b, 3.0 * x0, 2)
+    assert np.linalg.norm(x2 - 3.0 * x1) <= 1e-12 * np.linalg.norm(x2)
+
+
+def test_wrapped_cycle_converges_and_sv_keeps_stationary_k0():
+    for kw in (dict(dim=2, n=8, jitter=0.2, seed=5, forcing="gaussian", bc="lid"),
+               dict(dim=2, n=4, disc="SV", seed=4, forcing="gaussian", bc="zero")):
+        P = make_problem(**kw)
+        par = dc.default_params(P, max_coarse=30, krylov_its=2)
+        pre = dc.DCPreconditioner(P, par)
+        out = fgmres.solve(P, pre, rtol=1e-10)
+        assert out.converged
+        assert np.linalg.norm(P.b - P.K0 @ out.x) <= 1e-10 * np.linalg.norm(P.b)
+        if P.disc == "SV":  # K0 relaxation is the damped sweep: linear in r there
+            r = np.random.default_rng(0).standard_normal(P.n0)
+            b = r[pre.free0]
+            a = pre._relax(0, pre.K0, b, np.zeros_like(b), 1, par.omega0)
+            c = pre._relax(0, pre.K0, 2.0 * b, np.zeros_like(b), 1, par.omega0)
+            assert np.linalg.norm(c - 2.0 * a) <= 1e-12 * np.linalg.norm(c)
+
+
+# --------------------------------------------------------------------------
 # Chebyshev and DLSC (Algorithm 2, Table 3)
 
 def cheb_T(k, x):
