@@ -104,6 +104,10 @@ typedef struct {
   uint64_t seed;          /* SplitMix64 seed of the Lanczos start vectors */
   double mass_rtol;       /* relative tolerance of the SV pressure-mass solve */
   int32_t nrhs_max;       /* most right-hand sides one mas_apply / mas_solve may carry (1..64) */
+  int32_t krylov_its;     /* 0: damped stationary Vanka sweeps (omega0, omega); k = 1..8: each
+                             pre/post relaxation is k iterations of FGMRES preconditioned by one
+                             undamped Vanka sweep (Section 3.3.1), on every Vanka level except
+                             K0 of Scott-Vogelius (stationary there); one right-hand side per call */
 } mas_params;
 
 typedef struct {

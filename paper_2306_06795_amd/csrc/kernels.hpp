@@ -1172,9 +1172,12 @@ __device__ __forceinline__ double sum_partials(int nb, const double* __restrict_
 // previous step's partials (= h of that step, stored by block 0 into *hprev) and
 // w -= a vprev; then partial_out[b] = block b's share of w . vnext (mode 0) or
 // w . w (mode 1).  Two partial buffers alternate between consecutive steps.
-__global__ void __launch_bounds__(256) k_mgs_step(int64_t n, double* __restrict__ w, const double* __restrict__ vprev,
+// Vectors of type T, sums and coefficients in FP64 (T = double for FGMRES, the
+// cycle's type for the relaxation wrapper).
+template <typename T>
+__global__ void __launch_bounds__(256) k_mgs_step(int64_t n, T* __restrict__ w, const T* __restrict__ vprev,
                                                  double* __restrict__ hprev, const double* __restrict__ prev_partial,
-                                                 const double* __restrict__ vnext, double* __restrict__ partial_out,
+                                                 const T* __restrict__ vnext, double* __restrict__ partial_out,
                                                  int mode) {
   __shared__ double sh[4];
   double a = 0.0;
@@ -1186,10 +1189,10 @@ __global__ void __launch_bounds__(256) k_mgs_step(int64_t n, double* __restrict_
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     double wi = w[i];
     if (vprev) {
-      wi -= a * vprev[i];
-      w[i] = wi;
+      wi -= a * (double)vprev[i];
+      w[i] = (T)wi;
     }
-    s += wi * (mode == 0 ? vnext[i] : wi);
+    s += wi * (mode == 0 ? (double)vnext[i] : wi);
   }
   s = wave_sum(s);
   if ((threadIdx.x & (WAVE - 1)) == 0) sh[threadIdx.x / WAVE] = s;
@@ -1198,13 +1201,55 @@ __global__ void __launch_bounds__(256) k_mgs_step(int64_t n, double* __restrict_
 }
 
 // v = w / sqrt(sum of partials); block 0 stores the norm into *hout
+template <typename T>
 __global__ void __launch_bounds__(256) k_normalize(int64_t n, const double* __restrict__ partial, int nb,
-                                                  double* __restrict__ hout, const double* __restrict__ w,
-                                                  double* __restrict__ v) {
+                                                  double* __restrict__ hout, const T* __restrict__ w,
+                                                  T* __restrict__ v) {
   const double nrm = sqrt(sum_partials(nb, partial));
   if (blockIdx.x == 0 && threadIdx.x == 0) *hout = nrm;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    v[i] = nrm != 0.0 ? w[i] / nrm : 0.0;
+    v[i] = nrm != 0.0 ? (T)((double)w[i] / nrm) : (T)0;
+}
+
+// Least-squares step of the relaxation wrapper (one thread): Givens rotations
+// reduce the (m+1) x m Hessenberg matrix H (row-major, h[i * m + j]) with
+// right-hand side beta e_1; y (m values) solves the triangular system, a zero
+// pivot (breakdown) leaving its coefficient at zero.
+__global__ void k_krylov_ls(int m, const double* __restrict__ H, const double* __restrict__ beta,
+                            double* __restrict__ y) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double R[9 * 8], g[9], c[8], sn[8];
+  for (int i = 0; i < (m + 1) * m; ++i) R[i] = H[i];
+  for (int i = 0; i <= m; ++i) g[i] = 0.0;
+  g[0] = *beta;
+  int k = m;
+  for (int j = 0; j < m; ++j) {
+    for (int i = 0; i < j; ++i) {
+      const double t = c[i] * R[i * m + j] + sn[i] * R[(i + 1) * m + j];
+      R[(i + 1) * m + j] = -sn[i] * R[i * m + j] + c[i] * R[(i + 1) * m + j];
+      R[i * m + j] = t;
+    }
+    const double den = hypot(R[j * m + j], R[(j + 1) * m + j]);
+    if (den == 0.0) {
+      k = j;
+      break;
+    }
+    c[j] = R[j * m + j] / den;
+    sn[j] = R[(j + 1) * m + j] / den;
+    R[j * m + j] = den;
+    R[(j + 1) * m + j] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = c[j] * g[j];
+  }
+  for (int i = m - 1; i >= 0; --i) {
+    if (i >= k || R[i * m + i] == 0.0) {
+      y[i] = 0.0;
+      continue;
+    }
+    double t = g[i];
+    for (int q = i + 1; q < k; ++q) t -= R[i * m + q] * y[q];
+    y[i] = t / R[i * m + i];
+  }
 }
 
 // y -= (*h) x
@@ -1229,13 +1274,14 @@ __global__ void k_scale_inv(int64_t n, double a, const double* x, double* y) {
 }
 
 // x += sum_k y[k] Z[k]  (Z: k vectors of length n, stride n)
-__global__ void k_update_x(int64_t n, int k, const double* __restrict__ Z, const double* __restrict__ y,
-                           double* __restrict__ x) {
+template <typename T>
+__global__ void k_update_x(int64_t n, int k, const T* __restrict__ Z, const double* __restrict__ y,
+                           T* __restrict__ x) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double s = x[i];
-  for (int q = 0; q < k; ++q) s += y[q] * Z[(int64_t)q * n + i];
-  x[i] = s;
+  for (int q = 0; q < k; ++q) s += y[q] * (double)Z[(int64_t)q * n + i];
+  x[i] = (T)s;
 }
 
 }  // namespace mas

@@ -303,6 +303,7 @@ struct Level {
   DPatches<T> pt;
   DDlsc<T> dl;
   bool relax = false;
+  bool krylov = false;  // relaxation wrapped in FGMRES (Section 3.3.1)
   T *x = nullptr, *b = nullptr, *r = nullptr;
 };
 
@@ -363,6 +364,11 @@ struct Cycle : CycleBase {
   int dim = 2;
   int nr = 1, nr_max = 1;  // right-hand sides of the current application / allocated for
   Timing* tm = nullptr;
+  // relaxation wrapper workspace, shared by the levels (they relax one at a time):
+  // basis V (m + 1 vectors), directions Z (m), w, FP64 partial sums, H, beta, y
+  T *kv = nullptr, *kz = nullptr, *kw = nullptr;
+  double *kpart = nullptr, *kh = nullptr, *kbeta = nullptr, *ky = nullptr;
+  int kblk = 512;
   // Scott-Vogelius pressure transfers (Section 3.1): P0^p duplication, R0^p = M_cg^-1 (P0^p)^T M_dg
   bool sv = false;
   int64_t np0 = 0, np1 = 0;
@@ -498,7 +504,55 @@ struct Cycle : CycleBase {
   }
 
   // `sweeps` relaxation sweeps on L (Vanka or DLSC); x_zero: L.x is to be taken as 0
+  // One relaxation wrapped in FGMRES (Section 3.3.1): m = krylov_its iterations
+  // of right-preconditioned flexible GMRES on K e = b - K x from e = 0, each
+  // preconditioned by one undamped Vanka sweep; Arnoldi by modified
+  // Gram-Schmidt with FP64 sums; the small least-squares problem on the device;
+  // then x += Z y.  No host synchronisation (the cycle stays capturable).
+  void krylov_relax(Level<T>& L, bool x_zero, hipStream_t s) {
+    const int m = par.krylov_its;
+    const int64_t n = L.n;
+    const unsigned nb = (unsigned)std::min<int64_t>(kblk, std::max<int64_t>(1, (n + 255) / 256));
+    double* part[2] = {kpart, kpart + kblk};
+    const T* r0 = L.b;
+    if (!x_zero) {
+      spmv<1>(L.K, L.x, L.b, L.r, s);
+      r0 = L.r;
+    }
+    // beta = ||r0||, v_0 = r0 / beta
+    hipLaunchKernelGGL((k_mgs_step<T>), dim3(nb), dim3(256), 0, s, n, const_cast<T*>(r0), nullptr, nullptr, nullptr,
+                       nullptr, part[0], 1);
+    hipLaunchKernelGGL((k_normalize<T>), dim3(nb), dim3(256), 0, s, n, part[0], (int)nb, kbeta, r0, kv);
+    launch_check();
+    for (int j = 0; j < m; ++j) {
+      T* vj = kv + (int64_t)j * n;
+      T* zj = kz + (int64_t)j * n;
+      patch_solve(L, vj, s);  // z_j = M v_j: one undamped sweep from zero
+      pull(L, (T)1, zj, 0, s);
+      spmv<0>(L.K, zj, nullptr, kw, s);  // w = K z_j
+      for (int i = 0; i <= j + 1; ++i) {
+        const T* vprev = i > 0 ? kv + (int64_t)(i - 1) * n : nullptr;
+        double* hprev = i > 0 ? kh + (size_t)(i - 1) * m + j : nullptr;
+        const double* pprev = i > 0 ? part[(i - 1) & 1] : nullptr;
+        const T* vnext = i <= j ? kv + (int64_t)i * n : nullptr;
+        hipLaunchKernelGGL((k_mgs_step<T>), dim3(nb), dim3(256), 0, s, n, kw, vprev, hprev, pprev, vnext,
+                           part[i & 1], i <= j ? 0 : 1);
+      }
+      hipLaunchKernelGGL((k_normalize<T>), dim3(nb), dim3(256), 0, s, n, part[(j + 1) & 1], (int)nb,
+                         kh + (size_t)(j + 1) * m + j, kw, kv + (int64_t)(j + 1) * n);
+      launch_check();
+    }
+    hipLaunchKernelGGL(k_krylov_ls, dim3(1), dim3(64), 0, s, m, kh, kbeta, ky);
+    if (x_zero) hipLaunchKernelGGL((k_fill<T>), dim3(blocks_for(n, 256)), dim3(256), 0, s, n, L.x, (T)0);
+    hipLaunchKernelGGL((k_update_x<T>), dim3(blocks_for(n, 256)), dim3(256), 0, s, n, m, kz, ky, L.x);
+    launch_check();
+  }
+
   void relax_level(Level<T>& L, int sweeps, T omega, bool x_zero, hipStream_t s) {
+    if (L.krylov) {
+      krylov_relax(L, x_zero, s);
+      return;
+    }
     if (L.dl.on) {
       if (x_zero) {
         hipLaunchKernelGGL((k_fill<T>), dim3(blocks_for(L.n * nr, 256)), dim3(256), 0, s, L.n * nr, L.x, (T)0);
@@ -593,26 +647,28 @@ struct Cycle : CycleBase {
         rin = L.r;
       }
       patch_solve(L, rin, s);
-      const int acc = (k == 0 && x_zero) ? 0 : 1;
-      if (nr > 1) {
-        const unsigned nb = blocks_for(L.n * nr, 256);
-        if (L.pt.ell_c)
-          hipLaunchKernelGGL((k_vanka_pull_ell_nr<T>), dim3(nb), dim3(256), 0, s, (int)L.n, nr, L.pt.ell_width,
-                             L.pt.ell_c, L.pt.Ynr, omega, L.x, acc);
-        else
-          hipLaunchKernelGGL((k_vanka_pull_nr<T>), dim3(nb), dim3(256), 0, s, (int)L.n, nr, L.pt.inv_ptr_c,
-                             L.pt.inv_pos_c, L.pt.Ynr, L.pt.w, omega, L.x, acc);
-        launch_check();
-        continue;
-      }
-      if (L.pt.ell)
-        hipLaunchKernelGGL((k_vanka_pull_ell<T>), dim3(blocks_for(L.n, 256)), dim3(256), 0, s, (int)L.n,
-                           L.pt.ell_width, L.pt.ell, L.pt.Y, omega, L.x, acc);
-      else
-        hipLaunchKernelGGL((k_vanka_pull<T>), dim3(blocks_for(L.n, 256)), dim3(256), 0, s, (int)L.n, L.pt.inv_ptr,
-                           L.pt.inv_pos, L.pt.Y, L.pt.w, omega, L.x, acc);
-      launch_check();
+      pull(L, omega, L.x, (k == 0 && x_zero) ? 0 : 1, s);
     }
+  }
+
+  // x (+)= omega W sum of the patch outputs, per DoF (acc = 0: overwrite)
+  void pull(Level<T>& L, T omega, T* x, int acc, hipStream_t s) {
+    if (nr > 1) {
+      const unsigned nb = blocks_for(L.n * nr, 256);
+      if (L.pt.ell_c)
+        hipLaunchKernelGGL((k_vanka_pull_ell_nr<T>), dim3(nb), dim3(256), 0, s, (int)L.n, nr, L.pt.ell_width,
+                           L.pt.ell_c, L.pt.Ynr, omega, x, acc);
+      else
+        hipLaunchKernelGGL((k_vanka_pull_nr<T>), dim3(nb), dim3(256), 0, s, (int)L.n, nr, L.pt.inv_ptr_c,
+                           L.pt.inv_pos_c, L.pt.Ynr, L.pt.w, omega, x, acc);
+    } else if (L.pt.ell) {
+      hipLaunchKernelGGL((k_vanka_pull_ell<T>), dim3(blocks_for(L.n, 256)), dim3(256), 0, s, (int)L.n,
+                         L.pt.ell_width, L.pt.ell, L.pt.Y, omega, x, acc);
+    } else {
+      hipLaunchKernelGGL((k_vanka_pull<T>), dim3(blocks_for(L.n, 256)), dim3(256), 0, s, (int)L.n, L.pt.inv_ptr,
+                         L.pt.inv_pos, L.pt.Y, L.pt.w, omega, x, acc);
+    }
+    launch_check();
   }
 
   // cycle on level l >= 1 with right-hand side lev[l].b, result in lev[l].x
@@ -650,7 +706,11 @@ struct Cycle : CycleBase {
     if (L.relax && par.nu2 > 0) relax_level(L, par.nu2, om, false, s);
   }
 
-  void set_nr(int k) override { nr = k; }
+  void set_nr(int k) override {
+    if (k > 1 && par.krylov_its > 0)
+      throw MasError(MAS_EINVAL, "the FGMRES-wrapped relaxation takes one right-hand side per call");
+    nr = k;
+  }
 
   void apply(const double* r, double* z, hipStream_t s) override {
     Level<T>& L0 = lev[0];
@@ -1059,6 +1119,25 @@ std::unique_ptr<Cycle<T>> build_cycle(mas_handle* h, const std::vector<Csr>& Ks,
       }
     }
   }
+  // relaxation wrapper (Section 3.3.1): every Vanka level except the Scott-Vogelius K0
+  if (h->par.krylov_its > 0) {
+    const int m = h->par.krylov_its;
+    int64_t nmax = 0;
+    for (size_t l = 0; l + 1 < nl; ++l) {
+      Level<T>& L = cyc->lev[l];
+      L.krylov = L.relax && !L.dl.on && L.pt.np > 0 && !(h->disc == MAS_SV && l == 0);
+      if (L.krylov) nmax = std::max(nmax, L.n);
+    }
+    if (nmax > 0) {
+      cyc->kv = ar.alloc<T>((size_t)(m + 1) * nmax);
+      cyc->kz = ar.alloc<T>((size_t)m * nmax);
+      cyc->kw = ar.alloc<T>((size_t)nmax);
+      cyc->kpart = ar.alloc<double>((size_t)2 * cyc->kblk);
+      cyc->kh = ar.alloc<double>((size_t)(m + 1) * m);
+      cyc->kbeta = ar.alloc<double>(1);
+      cyc->ky = ar.alloc<double>((size_t)m);
+    }
+  }
   // lanes per row of every sparse product, timed on the operands
   for (size_t l = 0; l + 1 < nl; ++l) {
     Level<T>& L = cyc->lev[l];
@@ -1131,6 +1210,7 @@ void analyze_impl(mas_handle* h, const mas_problem* pr) {
   h->n0 = n0;
   if (par.restart < 1 || par.restart > 200) throw MasError(MAS_EINVAL, "restart must be in [1, 200]");
   if (par.nrhs_max < 1 || par.nrhs_max > 64) throw MasError(MAS_EINVAL, "nrhs_max must be in [1, 64]");
+  if (par.krylov_its < 0 || par.krylov_its > 8) throw MasError(MAS_EINVAL, "krylov_its must be in [0, 8]");
   if (par.max_coarse < 1 || par.max_levels < 1) throw MasError(MAS_EINVAL, "bad coarsening limits");
   std::vector<int64_t> free0, dir0, free1;
   std::vector<int8_t> f0, f1;
@@ -1417,7 +1497,7 @@ void release_device(mas_handle* h) {
 // *out = x . y (or ||x|| when take_sqrt and x == y), reduced on the device
 void dev_dot(mas_handle* h, const double* x, const double* y, int64_t n, hipStream_t s, double* out_dev,
              bool take_sqrt) {
-  hipLaunchKernelGGL(k_mgs_step, dim3(h->nblk_dot), dim3(256), 0, s, n, const_cast<double*>(x), nullptr, nullptr,
+  hipLaunchKernelGGL(k_mgs_step<double>, dim3(h->nblk_dot), dim3(256), 0, s, n, const_cast<double*>(x), nullptr, nullptr,
                      nullptr, take_sqrt ? nullptr : y, h->partial, take_sqrt ? 1 : 0);
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, h->nblk_dot, h->partial, out_dev, take_sqrt ? 1 : 0);
   launch_check();
@@ -1439,10 +1519,10 @@ void inner_iteration(mas_handle* h, int j, hipStream_t s) {
     double* hprev = i > 0 ? h->hdev + (i - 1) : nullptr;
     const double* pprev = i > 0 ? part[(i - 1) & 1] : nullptr;
     const double* vnext = i <= j ? h->V + (int64_t)i * n : nullptr;
-    hipLaunchKernelGGL(k_mgs_step, dim3(h->nblk_dot), dim3(256), 0, s, n, w, vprev, hprev, pprev, vnext,
+    hipLaunchKernelGGL(k_mgs_step<double>, dim3(h->nblk_dot), dim3(256), 0, s, n, w, vprev, hprev, pprev, vnext,
                        part[i & 1], i <= j ? 0 : 1);
   }
-  hipLaunchKernelGGL(k_normalize, dim3(h->nblk_dot), dim3(256), 0, s, n, part[(j + 1) & 1], h->nblk_dot,
+  hipLaunchKernelGGL(k_normalize<double>, dim3(h->nblk_dot), dim3(256), 0, s, n, part[(j + 1) & 1], h->nblk_dot,
                      h->hdev + j + 1, w, h->V + (int64_t)(j + 1) * n);
   launch_check();
   HIPCHECK(hipMemcpyAsync(h->hhost, h->hdev, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1542,7 +1622,7 @@ int fgmres(mas_handle* h, const double* b, double* x, double rtol, int max_it, m
     }
     std::memcpy(h->hhost, y.data(), k * sizeof(double));
     HIPCHECK(hipMemcpyAsync(h->ydev, h->hhost, k * sizeof(double), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_update_x, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, k, h->Z, h->ydev, x);
+    hipLaunchKernelGGL(k_update_x<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, k, h->Z, h->ydev, x);
     launch_check();
     csr_launch<double, 1>(h->K0full, x, b, r, s);
     dev_dot(h, r, r, n, s, h->hdev, true);
@@ -1804,6 +1884,7 @@ void mas_default_params(int32_t dim, int32_t disc, int32_t relax, mas_params* ou
   p.seed = 0x5EED;
   p.mass_rtol = 1e-14;
   p.nrhs_max = 1;
+  p.krylov_its = 0;
   *out = p;
 }
 

@@ -40,7 +40,8 @@ class mas_params(C.Structure):
                 ("omega0", C.c_double), ("omega", C.c_double), ("eta_u", C.c_double), ("eta_p", C.c_double),
                 ("cheb_deg", C.c_int32 * 3), ("precision", C.c_int32), ("restart", C.c_int32),
                 ("max_coarse", C.c_int32), ("max_levels", C.c_int32), ("theta", C.c_double),
-                ("seed", C.c_uint64), ("mass_rtol", C.c_double), ("nrhs_max", C.c_int32)]
+                ("seed", C.c_uint64), ("mass_rtol", C.c_double), ("nrhs_max", C.c_int32),
+                ("krylov_its", C.c_int32)]
 
 
 class mas_solve_info(C.Structure):

@@ -35,6 +35,14 @@ CASES = {
                         dict(max_coarse=30, relax="dlsc", schedule="skip1")),
     "sv6": (dict(dim=2, n=6, disc="SV", seed=4, forcing="gaussian", bc="zero"), dict(max_coarse=40)),
     "sv8_lid": (dict(dim=2, n=8, disc="SV", jitter=0.2, seed=4, forcing="gaussian", bc="lid"), dict(max_coarse=40)),
+    # relaxation wrapped in FGMRES(2) (Section 3.3.1); SV keeps the damped sweep on K0
+    "th24_lid_kry": (dict(dim=2, n=24, jitter=0.2, seed=2, forcing="gaussian", bc="lid"),
+                     dict(max_coarse=40, krylov_its=2)),
+    "th3d4_kry": (dict(dim=3, n=4, forcing="smooth", bc="zero", seed=3), dict(max_coarse=40, krylov_its=2)),
+    "th16_skip1_kry3": (dict(dim=2, n=16, jitter=0.2, seed=5, forcing="gaussian", bc="lid"),
+                        dict(max_coarse=30, schedule="skip1", krylov_its=3)),
+    "sv8_lid_kry": (dict(dim=2, n=8, disc="SV", jitter=0.2, seed=4, forcing="gaussian", bc="lid"),
+                    dict(max_coarse=40, krylov_its=2)),
 }
 SCHED = {"all": mas.MAS_DC_ALL, "skip1": mas.MAS_DC_SKIP1, "skip0": mas.MAS_DC_SKIP0}
 
@@ -51,7 +59,7 @@ def build(name, precision=mas.MAS_FP64):
     mp = mas.default_params(P.dim, disc, mrelax, theta=par.theta, max_coarse=par.max_coarse,
                             max_levels=par.max_levels, omega0=par.omega0, omega=par.omega,
                             eta_u=par.eta_u, eta_p=par.eta_p, schedule=SCHED[par.schedule],
-                            precision=precision, seed=par.seed)
+                            precision=precision, seed=par.seed, krylov_its=par.krylov_its)
     print(f"[case {name}] n0={P.n0} precision={precision}", flush=True)
     return P, par, mp
 
@@ -106,7 +114,7 @@ def test_full_block_levels_match_oracle(name, monkeypatch):
 
 
 @pytest.mark.parametrize("name", ["th16_2lvl", "th24_lid", "th3d4", "th16_skip1", "th24_dlsc", "th3d4_dlsc",
-                                  "sv6", "sv8_lid"])
+                                  "sv6", "sv8_lid", "th24_lid_kry", "th3d4_kry", "sv8_lid_kry"])
 def test_solve_fp64_matches_oracle(name):
     P, par, mp = build(name)
     pre = dc.DCPreconditioner(P, par)
@@ -129,7 +137,7 @@ def test_solve_fp64_matches_oracle(name):
     h.close()
 
 
-@pytest.mark.parametrize("name", ["th16_3lvl", "th24_lid", "th3d4", "th24_dlsc", "sv8_lid"])
+@pytest.mark.parametrize("name", ["th16_3lvl", "th24_lid", "th3d4", "th24_dlsc", "sv8_lid", "th24_lid_kry"])
 def test_solve_fp32_cycle_reaches_1e8(name):
     P, par, mp = build(name, precision=mas.MAS_FP32)
     h = mas.Handle(P, mp)
@@ -177,4 +185,14 @@ def test_nan_rhs_is_reported():
     with pytest.raises(mas.MasError) as e:
         h.solve(b, x)
     assert e.value.code == mas.MAS_ENAN
+    h.close()
+
+
+def test_wrapped_relaxation_refuses_batches():
+    P = make_problem(dim=2, n=8, nrhs=2, forcing="gaussian", bc="zero", seed=1)
+    h = mas.Handle(P, mas.default_params(2, max_coarse=30, krylov_its=2, nrhs_max=2))
+    B = torch.tensor(P.b, device=DEV)
+    with pytest.raises(mas.MasError) as e:
+        h.apply(B, torch.empty_like(B), nrhs=2)
+    assert e.value.code == mas.MAS_EINVAL
     h.close()
