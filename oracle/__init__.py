@@ -11,7 +11,8 @@ Tuminaro, arXiv 2306.06795), written from the paper:
   dlsc.py    Chebyshev semi-iteration and the DLSC sweep (Algorithm 2,
              Section 3.3.2, Table 3)
   dc.py      the defect-correction cycle, eq. (3.1) with eq. (3.2) and the
-             multilevel eq. (3.4); schedules DC-all / DC-skip1 / DC-skip0
+             multilevel eq. (3.4); schedules DC-all / DC-skip1 / DC-skip0, and
+             HO-AMG (Algorithm 1 applied to K0, the remark after it)
   fgmres.py  restarted, right-preconditioned FGMRES(20) (Section 4)
   sparse.py  structural sparse products, a counter-based generator
 

@@ -15,7 +15,12 @@ Transfers (Section 3.1): Taylor-Hood P0 = R0 = I.  Scott-Vogelius: velocity
 identity, P0^p duplicates a continuous P1 pressure onto the discontinuous
 DoFs, R0^p = M_cg^{-1} (P0^p)^T M_dg (an L2 projection, solved exactly here).
 Schedules (Section 4): "all" relaxes on every level but the coarsest,
-"skip1" skips level 1, "skip0" skips level 0.
+"skip1" skips level 1, "skip0" skips level 0.  "ho" is HO-AMG (the remark
+after Algorithm 1, compared in Section 4): Algorithm 1 is applied to K0
+itself, so the hierarchy's finest entry is K0 and the defect-correction
+level 0 is left out (no relaxation there and no eta weights): one monolithic
+AMG V-cycle on K0.  Taylor-Hood only (the remark reports that algebraic
+coarsening of the discontinuous SV pressure does not give a usable method).
 Dirichlet rows are identity rows: the preconditioner returns r there.
 """
 from __future__ import annotations
@@ -34,7 +39,7 @@ from .sparse import submatrix
 @dataclass
 class Params:
     relax: str = "vanka"  # "vanka" or "dlsc"
-    schedule: str = "all"  # "all", "skip1", "skip0"
+    schedule: str = "all"  # "all", "skip1", "skip0", "ho"
     nu1: int = 1
     nu2: int = 1
     omega0: float = 0.5
@@ -58,11 +63,17 @@ class DCPreconditioner:
         self.n0 = prob.n0
         self.free0 = np.nonzero(~prob.dir0)[0]
         self.dir0 = np.nonzero(prob.dir0)[0]
-        free1 = np.nonzero(~prob.dir1)[0]
         self.K0 = submatrix(prob.K0, self.free0, self.free0)
         self.f0 = prob.field0[self.free0]
-        K1 = submatrix(prob.K1, free1, free1)
-        f1 = prob.field1[free1]
+        self.ho = par.schedule == "ho"
+        if self.ho:
+            if prob.disc != "TH":
+                raise ValueError("HO-AMG (Algorithm 1 on K0) is defined for Taylor-Hood only")
+            K1, f1 = self.K0, self.f0  # Algorithm 1's input is K0 itself
+        else:
+            free1 = np.nonzero(~prob.dir1)[0]
+            K1 = submatrix(prob.K1, free1, free1)
+            f1 = prob.field1[free1]
         self.levels = stokes_hierarchy(K1, f1, prob.Ap, d, par.theta, par.max_coarse, par.max_levels)
         self.nvel = int((self.f0 < d).sum())
         assert self.nvel == int((f1 < d).sum())
@@ -70,7 +81,7 @@ class DCPreconditioner:
         relax_l = [True] * (L + 1)  # index 0 = K0, 1.. = hierarchy entries; the coarsest is solved
         if par.schedule == "skip1":
             relax_l[1] = False
-        elif par.schedule == "skip0":
+        elif par.schedule in ("skip0", "ho"):
             relax_l[0] = False
         self.relax_on = relax_l
         cheb = par.cheb or ((3, 3, 6) if d == 2 else (4, 4, 16))
@@ -88,7 +99,8 @@ class DCPreconditioner:
                     self.relax.append(vanka.patches_single_seed(K, f, d))
             else:
                 nv = int((f < d).sum())
-                mu = prob.mu_diag0[self.free0[:nv]] if l == 0 else np.ones(nv)
+                on_k0 = l == 0 or (self.ho and l == 1)  # M_u = diag(P2 mass) wherever the operator is K0
+                mu = prob.mu_diag0[self.free0[:nv]] if on_k0 else np.ones(nv)
                 self.relax.append(DLSCLevel(K, f, d, mu, cheb, par.seed + 2 * l))
         # coarsest level: dense LU of the (bordered) operator
         last = self.levels[-1]
@@ -116,7 +128,9 @@ class DCPreconditioner:
         R = self.relax[l]
         if isinstance(R, vanka.Patches):
             if self.par.krylov_its > 0 and not (self.disc == "SV" and l == 0):
-                return vanka.krylov_relax(K, R, b, x, self.par.krylov_its)  # one wrapped relaxation
+                for _ in range(sweeps):  # nu wrapped relaxations (one each in V(1,1))
+                    x = vanka.krylov_relax(K, R, b, x, self.par.krylov_its)
+                return x
             for _ in range(sweeps):
                 x = vanka.sweep(K, R, b, x, omega)
             return x
@@ -147,12 +161,13 @@ class DCPreconditioner:
 
     def restrict0(self, r0: np.ndarray) -> np.ndarray:
         p, nv = self.par, self.nvel
+        eta_u, eta_p = (1.0, 1.0) if self.ho else (p.eta_u, p.eta_p)
         out = np.empty(self.levels[0].K.shape[0])
-        out[:nv] = p.eta_u * r0[:nv]
+        out[:nv] = eta_u * r0[:nv]
         if self.disc == "TH":
-            out[nv:] = p.eta_p * r0[nv:]
+            out[nv:] = eta_p * r0[nv:]
         else:
-            out[nv:] = p.eta_p * self.Mcg_lu.solve(self.Pp.T @ (self.Mdg @ r0[nv:]))
+            out[nv:] = eta_p * self.Mcg_lu.solve(self.Pp.T @ (self.Mdg @ r0[nv:]))
         return out
 
     def prolong0(self, x1: np.ndarray) -> np.ndarray:

@@ -364,6 +364,81 @@ def test_two_level_cycle_equals_dense_formula():
     assert np.all(z[pre.dir0] == r[pre.dir0])
 
 
+def test_ho_amg_one_level_is_the_exact_solve_of_k0():
+    """HO-AMG (Algorithm 1 applied to K0): with the coarsening limit above the
+    problem size the hierarchy is K0 alone, solved exactly (bordered with the
+    constant pressure), so K0 z = r up to a constant in the pressure rows, the
+    null vector of the enclosed-flow K0.  Built from K1 it would solve K1."""
+    P = make_problem(dim=2, n=4, jitter=0.2, seed=2, forcing="gaussian", bc="lid")
+    pre = dc.DCPreconditioner(P, dc.default_params(P, schedule="ho", max_coarse=10 ** 6))
+    assert len(pre.levels) == 1 and not pre.relax_on[0]
+    r = np.random.default_rng(4).standard_normal(P.n0)
+    z = pre.apply(r)
+    f = pre.free0
+    nv = pre.nvel
+
+    def off_null(v):
+        v = v.copy()
+        v[nv:] -= v[nv:].mean()
+        return v
+
+    assert np.linalg.norm(off_null(r[f] - pre.K0 @ z[f])) <= 1e-10 * np.linalg.norm(r)
+    K1f = P.K1.tocsr()[f][:, f]
+    assert np.linalg.norm(off_null(r[f] - K1f @ z[f])) > 1e-3 * np.linalg.norm(r)  # K1 is another operator
+
+
+@pytest.mark.parametrize("relax_its", [0, 2])
+def test_ho_amg_two_level_cycle_equals_dense_formula(relax_its):
+    """Two-level HO-AMG with Vanka, written with dense matrices: x1 = w M r,
+    x2 = x1 + P Kc^+ P^T (r - K0 x1) with Kc = P^T K0 P, x3 = x2 + w M (r - K0 x2).
+    No eta weights and no extra relaxation on a defect-correction level.  With
+    the wrapped relaxation (relax_its = 2) only the coarse-correction identity
+    P^T (r - K0 x2) in span{Kc's null vector} is checked."""
+    P = make_problem(dim=2, n=4, jitter=0.2, seed=2, forcing="gaussian", bc="lid")
+    par = dc.default_params(P, schedule="ho", max_coarse=5, max_levels=2, eta_u=0.3, eta_p=3.0,
+                            krylov_its=relax_its, nu2=1 if relax_its == 0 else 0)
+    pre = dc.DCPreconditioner(P, par)
+    assert len(pre.levels) == 2
+    K0 = pre.K0.toarray()
+    assert (pre.levels[0].K != pre.K0).nnz == 0
+    Pm = pre.levels[0].P.toarray()
+    Kc = Pm.T @ K0 @ Pm
+    r = np.random.default_rng(3).standard_normal(P.n0)
+    rf = r[pre.free0]
+    nv = pre.nvel
+    z = pre.apply(r)[pre.free0]
+    if relax_its == 0:
+        M = _dense_vanka(pre.K0, pre.relax[1])
+        w = par.omega
+        x1 = w * M @ rf
+        x2 = x1 + Pm @ (np.linalg.pinv(Kc) @ (Pm.T @ (rf - K0 @ x1)))
+        x3 = x2 + w * M @ (rf - K0 @ x2)
+        d = z - x3
+        d[nv:] -= d[nv:].mean()  # bordered solve vs pseudo-inverse: a constant pressure
+        assert np.linalg.norm(d) <= 1e-9 * np.linalg.norm(x3)
+    else:
+        g = Pm.T @ (rf - K0 @ z)  # no post-relaxation: z is the coarse-corrected iterate
+        nc = np.zeros(Kc.shape[0])
+        nc[pre.levels[1].field == P.dim] = pre.levels[1].null_p
+        nc /= np.linalg.norm(nc)
+        assert np.linalg.norm(g - (nc @ g) * nc) <= 1e-10 * np.linalg.norm(rf)
+
+
+def test_ho_amg_is_a_working_preconditioner_and_refuses_sv():
+    """The remark after Algorithm 1: HO-AMG is a usable preconditioner for
+    Taylor-Hood; it is not defined here for the discontinuous SV pressure."""
+    P = make_problem(dim=2, n=8, jitter=0.2, seed=2, forcing="gaussian", bc="lid")
+    for relax in ("vanka", "dlsc"):
+        pre = dc.DCPreconditioner(P, dc.default_params(P, relax=relax, schedule="ho", max_coarse=20))
+        res = fgmres.solve(P, pre, rtol=1e-10, max_it=200)
+        assert res.converged and res.iters <= 40, (relax, res.iters)
+        ref = bordered_direct(P)
+        assert np.linalg.norm(res.x - ref) <= 1e-7 * np.linalg.norm(ref)
+    S = make_problem(dim=2, n=4, disc="SV", seed=4, forcing="gaussian", bc="zero")
+    with pytest.raises(ValueError):
+        dc.DCPreconditioner(S, dc.default_params(S, schedule="ho"))
+
+
 def test_apply_is_linear():
     P = make_problem(dim=2, n=8, jitter=0.2, seed=2, forcing="gaussian", bc="lid")
     pre = dc.DCPreconditioner(P, dc.default_params(P, max_coarse=20))
