@@ -52,7 +52,12 @@ enum mas_status {
 
 enum mas_disc { MAS_TH = 0, MAS_SV = 1 };                 /* Section 2.1 */
 enum mas_relax { MAS_RELAX_VANKA = 0, MAS_RELAX_DLSC = 1 };/* Sections 3.3.1, 3.3.2 */
-enum mas_schedule { MAS_DC_ALL = 0, MAS_DC_SKIP1 = 1, MAS_DC_SKIP0 = 2 }; /* Section 4 */
+/* Section 4.  MAS_HO_AMG: Algorithm 1 applied to K0 itself (the remark after
+ * Algorithm 1, compared in Section 4): the hierarchy starts at K0, there is no
+ * defect-correction level, eta_u/eta_p and omega0 are not used (omega on every
+ * level), and K1/field1/dir1 of mas_problem are not read (Ap is).  Taylor-Hood
+ * only: mas_setup/mas_analyze return MAS_EINVAL for Scott-Vogelius. */
+enum mas_schedule { MAS_DC_ALL = 0, MAS_DC_SKIP1 = 1, MAS_DC_SKIP0 = 2, MAS_HO_AMG = 3 };
 enum mas_precision { MAS_FP64 = 0, MAS_FP32 = 1 };        /* number type of the cycle */
 
 /* CSR matrix in host memory: row pointers int64 (nrows+1), column indices
@@ -92,7 +97,8 @@ typedef struct {
 typedef struct {
   int32_t relax;          /* mas_relax on levels >= 0 */
   int32_t schedule;       /* mas_schedule */
-  int32_t nu1, nu2;       /* pre/post relaxation sweeps per level */
+  int32_t nu1, nu2;       /* pre/post relaxation sweeps per level (wrapped relaxations when
+                             krylov_its > 0) */
   double omega0, omega;   /* Vanka damping on K0 and on the K1 hierarchy */
   double eta_u, eta_p;    /* residual weights of eq. (3.2) */
   int32_t cheb_deg[3];    /* DLSC Chebyshev degrees (momentum, continuity, pressure; Table 3) */
@@ -105,7 +111,7 @@ typedef struct {
   double mass_rtol;       /* relative tolerance of the SV pressure-mass solve */
   int32_t nrhs_max;       /* most right-hand sides one mas_apply / mas_solve may carry (1..64) */
   int32_t krylov_its;     /* 0: damped stationary Vanka sweeps (omega0, omega); k = 1..8: each
-                             pre/post relaxation is k iterations of FGMRES preconditioned by one
+                             wrapped relaxation is k iterations of FGMRES preconditioned by one
                              undamped Vanka sweep (Section 3.3.1), on every Vanka level except
                              K0 of Scott-Vogelius (stationary there); one right-hand side per call */
 } mas_params;

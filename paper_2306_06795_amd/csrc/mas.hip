@@ -549,8 +549,8 @@ struct Cycle : CycleBase {
   }
 
   void relax_level(Level<T>& L, int sweeps, T omega, bool x_zero, hipStream_t s) {
-    if (L.krylov) {
-      krylov_relax(L, x_zero, s);
+    if (L.krylov) {  // sweeps wrapped relaxations
+      for (int k = 0; k < sweeps; ++k) krylov_relax(L, x_zero && k == 0, s);
       return;
     }
     if (L.dl.on) {
@@ -1201,12 +1201,22 @@ void analyze_impl(mas_handle* h, const mas_problem* pr) {
   if (par.relax != MAS_RELAX_VANKA && par.relax != MAS_RELAX_DLSC) throw MasError(MAS_EINVAL, "unknown relaxation");
   for (int q = 0; q < 3; ++q)
     if (par.relax == MAS_RELAX_DLSC && par.cheb_deg[q] < 1) throw MasError(MAS_EINVAL, "Chebyshev degrees must be >= 1");
+  if (par.schedule < MAS_DC_ALL || par.schedule > MAS_HO_AMG) throw MasError(MAS_EINVAL, "unknown schedule");
+  // HO-AMG (the remark after Algorithm 1): the hierarchy is built from K0 itself
+  const bool ho = par.schedule == MAS_HO_AMG;
+  if (ho && pr->disc != MAS_TH) throw MasError(MAS_EINVAL, "HO-AMG is supported for Taylor-Hood only");
+  if (ho) {  // no defect-correction level: b1 = r0 exactly
+    h->par.eta_u = 1.0;
+    h->par.eta_p = 1.0;
+  }
   Csr K0 = get_csr(pr->K0, "K0");
-  Csr K1 = get_csr(pr->K1, "K1");
+  Csr K1 = ho ? K0 : get_csr(pr->K1, "K1");
+  const int8_t* field1 = ho ? pr->field0 : pr->field1;
+  const uint8_t* dir1 = ho ? pr->dir0 : pr->dir1;
   Csr Ap = get_csr(pr->Ap, "Ap");
   const int64_t n0 = K0.nr, n1 = K1.nr;
   if (K0.nc != n0 || K1.nc != n1 || Ap.nr != Ap.nc) throw MasError(MAS_EINVAL, "operators must be square");
-  if (!pr->field0 || !pr->field1 || !pr->dir0 || !pr->dir1) throw MasError(MAS_EINVAL, "missing field or Dirichlet map");
+  if (!pr->field0 || !field1 || !pr->dir0 || !dir1) throw MasError(MAS_EINVAL, "missing field or Dirichlet map");
   h->n0 = n0;
   if (par.restart < 1 || par.restart > 200) throw MasError(MAS_EINVAL, "restart must be in [1, 200]");
   if (par.nrhs_max < 1 || par.nrhs_max > 64) throw MasError(MAS_EINVAL, "nrhs_max must be in [1, 64]");
@@ -1228,11 +1238,11 @@ void analyze_impl(mas_handle* h, const mas_problem* pr) {
     }
   }
   for (int64_t i = 0; i < n1; ++i) {
-    if (pr->field1[i] < 0 || pr->field1[i] > d) throw MasError(MAS_EINVAL, "field1 out of range");
-    if (i > 0 && pr->field1[i] < pr->field1[i - 1]) throw MasError(MAS_EINVAL, "K1 unknowns must be field-blocked");
-    if (!pr->dir1[i]) {
+    if (field1[i] < 0 || field1[i] > d) throw MasError(MAS_EINVAL, "field1 out of range");
+    if (i > 0 && field1[i] < field1[i - 1]) throw MasError(MAS_EINVAL, "K1 unknowns must be field-blocked");
+    if (!dir1[i]) {
       free1.push_back(i);
-      f1.push_back(pr->field1[i]);
+      f1.push_back(field1[i]);
     }
   }
   h->nu0 = nu0;
@@ -1279,7 +1289,7 @@ void analyze_impl(mas_handle* h, const mas_problem* pr) {
   std::vector<bool> relax(nl, true);
   relax[nl - 1] = false;
   if (par.schedule == MAS_DC_SKIP1 && nl > 2) relax[1] = false;
-  if (par.schedule == MAS_DC_SKIP0) relax[0] = false;
+  if (par.schedule == MAS_DC_SKIP0 || ho) relax[0] = false;
   if (par.schedule == MAS_DC_SKIP1 && nl == 2) relax[1] = false;
   std::vector<PatchSet> patches(nl);
   std::vector<HostDlsc> dl(nl);
@@ -1311,7 +1321,7 @@ void analyze_impl(mas_handle* h, const mas_problem* pr) {
     D.B = submatrix(Ks[l], ip, iv);
     D.Bt = transpose(D.B);
     D.minv.assign(iv.size(), 1.0);
-    if (l == 0 && pr->mu_diag0) {
+    if ((l == 0 || (ho && l == 1)) && pr->mu_diag0) {  // the level whose operator is K0
       int64_t q = 0;
       for (int64_t i = 0; i < n0; ++i) {
         if (pr->field0[i] >= d || pr->dir0[i]) continue;

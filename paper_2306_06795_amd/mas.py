@@ -18,7 +18,7 @@ MAS_OK, MAS_NOT_CONVERGED = 0, 1
 MAS_EINVAL, MAS_ESINGULAR_PATCH, MAS_ENOMEM, MAS_EHIP, MAS_ENAN = -1, -2, -3, -4, -5
 MAS_TH, MAS_SV = 0, 1
 MAS_RELAX_VANKA, MAS_RELAX_DLSC = 0, 1
-MAS_DC_ALL, MAS_DC_SKIP1, MAS_DC_SKIP0 = 0, 1, 2
+MAS_DC_ALL, MAS_DC_SKIP1, MAS_DC_SKIP0, MAS_HO_AMG = 0, 1, 2, 3
 MAS_FP64, MAS_FP32 = 0, 1
 
 

@@ -65,22 +65,28 @@ def test_default_params_follow_the_paper():
     assert list(p3.cheb_deg) == [4, 4, 16] and p3.nu1 == 2
 
 
+SCHED = {"all": mas.MAS_DC_ALL, "ho": mas.MAS_HO_AMG}
+
+
 def _same_params(prob, **over):
     par = dc.default_params(prob, **over)
     mp = mas.default_params(prob.dim, mas.MAS_SV if prob.disc == "SV" else mas.MAS_TH, theta=par.theta,
-                            max_coarse=par.max_coarse, max_levels=par.max_levels)
+                            max_coarse=par.max_coarse, max_levels=par.max_levels, schedule=SCHED[par.schedule])
     return par, mp
 
 
-@pytest.mark.parametrize("kw,mc", [
-    (dict(dim=2, n=16), 300),
-    (dict(dim=2, n=16), 30),
-    (dict(dim=2, n=24, jitter=0.2, seed=2, forcing="gaussian", bc="lid"), 40),
-    (dict(dim=3, n=4, forcing="smooth", bc="zero", seed=3), 40),
+@pytest.mark.parametrize("kw,mc,sched", [
+    (dict(dim=2, n=16), 300, "all"),
+    (dict(dim=2, n=16), 30, "all"),
+    (dict(dim=2, n=24, jitter=0.2, seed=2, forcing="gaussian", bc="lid"), 40, "all"),
+    (dict(dim=3, n=4, forcing="smooth", bc="zero", seed=3), 40, "all"),
+    # HO-AMG: the hierarchy below K0 is Algorithm 1 applied to K0 itself
+    (dict(dim=2, n=24, jitter=0.2, seed=2, forcing="gaussian", bc="lid"), 40, "ho"),
+    (dict(dim=3, n=4, forcing="smooth", bc="zero", seed=3), 40, "ho"),
 ])
-def test_host_hierarchy_matches_oracle(kw, mc):
+def test_host_hierarchy_matches_oracle(kw, mc, sched):
     P = make_problem(**kw)
-    par, mp = _same_params(P, max_coarse=mc)
+    par, mp = _same_params(P, max_coarse=mc, schedule=sched)
     pre = dc.DCPreconditioner(P, par)
     h = mas.Handle(P, mp, analyze_only=True)
     info = h.info()
@@ -92,8 +98,11 @@ def test_host_hierarchy_matches_oracle(kw, mc):
         assert np.array_equal(Kl.indptr, K.indptr) and np.array_equal(Kl.indices, K.indices), f"level {l} pattern"
         scale = np.abs(K.data).max()
         assert np.abs(Kl.data - K.data).max() <= 1e-13 * scale, f"level {l} values"
-    # patch counts on relaxed levels
+    # patch counts on relaxed levels (HO-AMG relaxes no defect-correction level 0)
     for l, R in enumerate(pre.relax):
+        if not pre.relax_on[l]:
+            assert info["n_patches"][l] == 0
+            continue
         assert info["n_patches"][l] == len(R.dofs)
         assert info["patch_dofs"][l] == sum(d.size for d in R.dofs)
     h.close()
@@ -113,6 +122,13 @@ def test_analyze_rejects_bad_input():
     with pytest.raises(mas.MasError) as e:
         mas.Handle(bad2, mp, analyze_only=True)
     assert e.value.code == mas.MAS_EINVAL and "non-finite" in str(e.value)
+    sv = make_problem(dim=2, n=4, disc="SV", seed=4, forcing="gaussian", bc="zero")
+    with pytest.raises(mas.MasError) as e:  # HO-AMG is defined for Taylor-Hood only
+        mas.Handle(sv, mas.default_params(2, mas.MAS_SV, schedule=mas.MAS_HO_AMG), analyze_only=True)
+    assert e.value.code == mas.MAS_EINVAL and "Taylor-Hood" in str(e.value)
+    with pytest.raises(mas.MasError) as e:
+        mas.Handle(P, mas.default_params(2, schedule=7), analyze_only=True)
+    assert e.value.code == mas.MAS_EINVAL and "schedule" in str(e.value)
     h = mas.Handle(P, mp, analyze_only=True)
     with pytest.raises(mas.MasError):
         import torch

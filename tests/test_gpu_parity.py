@@ -43,8 +43,20 @@ CASES = {
                         dict(max_coarse=30, schedule="skip1", krylov_its=3)),
     "sv8_lid_kry": (dict(dim=2, n=8, disc="SV", jitter=0.2, seed=4, forcing="gaussian", bc="lid"),
                     dict(max_coarse=40, krylov_its=2)),
+    # two wrapped relaxations before, none after
+    "th16_kry_nu20": (dict(dim=2, n=16, jitter=0.2, seed=5, forcing="gaussian", bc="lid"),
+                      dict(max_coarse=30, krylov_its=2, nu1=2, nu2=0)),
+    # HO-AMG: Algorithm 1 applied to K0 itself (the remark after Algorithm 1)
+    "th16_ho": (dict(dim=2, n=16), dict(max_coarse=30, schedule="ho")),
+    "th24_lid_ho": (dict(dim=2, n=24, jitter=0.2, seed=2, forcing="gaussian", bc="lid"),
+                    dict(max_coarse=40, schedule="ho")),
+    "th3d4_ho": (dict(dim=3, n=4, forcing="smooth", bc="zero", seed=3), dict(max_coarse=40, schedule="ho")),
+    "th24_ho_dlsc": (dict(dim=2, n=24, jitter=0.2, seed=2, forcing="gaussian", bc="lid"),
+                     dict(max_coarse=40, schedule="ho", relax="dlsc")),
+    "th24_lid_ho_kry": (dict(dim=2, n=24, jitter=0.2, seed=2, forcing="gaussian", bc="lid"),
+                        dict(max_coarse=40, schedule="ho", krylov_its=2)),
 }
-SCHED = {"all": mas.MAS_DC_ALL, "skip1": mas.MAS_DC_SKIP1, "skip0": mas.MAS_DC_SKIP0}
+SCHED = {"all": mas.MAS_DC_ALL, "skip1": mas.MAS_DC_SKIP1, "skip0": mas.MAS_DC_SKIP0, "ho": mas.MAS_HO_AMG}
 
 
 def build(name, precision=mas.MAS_FP64):
@@ -59,6 +71,7 @@ def build(name, precision=mas.MAS_FP64):
     mp = mas.default_params(P.dim, disc, mrelax, theta=par.theta, max_coarse=par.max_coarse,
                             max_levels=par.max_levels, omega0=par.omega0, omega=par.omega,
                             eta_u=par.eta_u, eta_p=par.eta_p, schedule=SCHED[par.schedule],
+                            nu1=par.nu1, nu2=par.nu2,
                             precision=precision, seed=par.seed, krylov_its=par.krylov_its)
     print(f"[case {name}] n0={P.n0} precision={precision}", flush=True)
     return P, par, mp
@@ -114,7 +127,8 @@ def test_full_block_levels_match_oracle(name, monkeypatch):
 
 
 @pytest.mark.parametrize("name", ["th16_2lvl", "th24_lid", "th3d4", "th16_skip1", "th24_dlsc", "th3d4_dlsc",
-                                  "sv6", "sv8_lid", "th24_lid_kry", "th3d4_kry", "sv8_lid_kry"])
+                                  "sv6", "sv8_lid", "th24_lid_kry", "th3d4_kry", "sv8_lid_kry",
+                                  "th24_lid_ho", "th3d4_ho", "th24_ho_dlsc", "th24_lid_ho_kry"])
 def test_solve_fp64_matches_oracle(name):
     P, par, mp = build(name)
     pre = dc.DCPreconditioner(P, par)
@@ -137,7 +151,8 @@ def test_solve_fp64_matches_oracle(name):
     h.close()
 
 
-@pytest.mark.parametrize("name", ["th16_3lvl", "th24_lid", "th3d4", "th24_dlsc", "sv8_lid", "th24_lid_kry"])
+@pytest.mark.parametrize("name", ["th16_3lvl", "th24_lid", "th3d4", "th24_dlsc", "sv8_lid", "th24_lid_kry",
+                                  "th24_lid_ho"])
 def test_solve_fp32_cycle_reaches_1e8(name):
     P, par, mp = build(name, precision=mas.MAS_FP32)
     h = mas.Handle(P, mp)
@@ -156,6 +171,14 @@ def test_solve_fp32_cycle_reaches_1e8(name):
     assert abs(info64[0]["iters"] - info[0]["iters"]) <= 2
     h.close()
     h64.close()
+
+
+def test_ho_amg_refuses_scott_vogelius():
+    P = make_problem(dim=2, n=6, disc="SV", seed=4, forcing="gaussian", bc="zero")
+    mp = mas.default_params(2, mas.MAS_SV, schedule=mas.MAS_HO_AMG, max_coarse=40)
+    with pytest.raises(mas.MasError) as e:
+        mas.Handle(P, mp)
+    assert e.value.code == mas.MAS_EINVAL and "Taylor-Hood" in str(e.value)
 
 
 def test_singular_patch_is_reported():
