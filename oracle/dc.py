@@ -21,6 +21,10 @@ itself, so the hierarchy's finest entry is K0 and the defect-correction
 level 0 is left out (no relaxation there and no eta weights): one monolithic
 AMG V-cycle on K0.  Taylor-Hood only (the remark reports that algebraic
 coarsening of the discontinuous SV pressure does not give a usable method).
+Relaxation kinds: "vanka" (Section 3.3.1) and "dlsc" (Section 3.3.2) on every
+relaxed level, and "vanka-dlsc", the hybrid of the Scott-Vogelius parameter
+study (Section 4, Table 4): Vanka on K0 (nu1/nu2 sweeps, omega0) and nu_dlsc
+DLSC sweeps on the levels of the K1 hierarchy.
 Dirichlet rows are identity rows: the preconditioner returns r there.
 """
 from __future__ import annotations
@@ -38,7 +42,7 @@ from .sparse import submatrix
 
 @dataclass
 class Params:
-    relax: str = "vanka"  # "vanka" or "dlsc"
+    relax: str = "vanka"  # "vanka", "dlsc" or "vanka-dlsc" (Vanka on K0, DLSC below)
     schedule: str = "all"  # "all", "skip1", "skip0", "ho"
     nu1: int = 1
     nu2: int = 1
@@ -51,6 +55,7 @@ class Params:
     max_coarse: int = 300
     max_levels: int = 10
     seed: int = 0x5EED
+    nu_dlsc: int = 2  # "vanka-dlsc": DLSC sweeps pre and post on the K1 hierarchy (two, Section 4)
     krylov_its: int = 0  # >0: FGMRES(krylov_its)-wrapped Vanka instead of damped sweeps (Section 3.3.1);
                          # Scott-Vogelius keeps the stationary sweep on K0
 
@@ -89,7 +94,7 @@ class DCPreconditioner:
         self.relax = []
         ops = [(self.K0, self.f0)] + [(lv.K, lv.field) for lv in self.levels[:-1]]
         for l, (K, f) in enumerate(ops):
-            if par.relax == "vanka":
+            if par.relax == "vanka" or (par.relax == "vanka-dlsc" and l == 0):
                 if l == 0 and self.disc == "SV":
                     pos = -np.ones(self.n0, dtype=np.int64)
                     pos[self.free0] = np.arange(self.free0.size)
@@ -150,13 +155,14 @@ class DCPreconditioner:
         p = self.par
         x = np.zeros_like(b)
         relax = self.relax_on[j + 1]
+        nu1, nu2 = (p.nu_dlsc, p.nu_dlsc) if p.relax == "vanka-dlsc" else (p.nu1, p.nu2)
         if relax:
-            x = self._relax(j + 1, lv.K, b, x, p.nu1, p.omega)
+            x = self._relax(j + 1, lv.K, b, x, nu1, p.omega)
         r = b - lv.K @ x
         xc = self._vcycle(j + 1, lv.P.T @ r)
         x = x + lv.P @ xc
         if relax:
-            x = self._relax(j + 1, lv.K, b, x, p.nu2, p.omega)
+            x = self._relax(j + 1, lv.K, b, x, nu2, p.omega)
         return x
 
     def restrict0(self, r0: np.ndarray) -> np.ndarray:
@@ -194,7 +200,9 @@ class DCPreconditioner:
 
 
 def default_params(prob, relax: str = "vanka", **over) -> Params:
-    if prob.disc == "SV":
+    if prob.disc == "SV" and relax == "vanka-dlsc":  # Table 4, structured, Vanka-DLSC row
+        p = Params(relax=relax, omega0=0.87, omega=0.5, eta_u=1.0, eta_p=2.96)
+    elif prob.disc == "SV":
         p = Params(relax=relax, omega0=0.78, omega=0.5, eta_u=1.0, eta_p=2.68)
     else:
         p = Params(relax=relax)

@@ -439,6 +439,74 @@ def test_ho_amg_is_a_working_preconditioner_and_refuses_sv():
         dc.DCPreconditioner(S, dc.default_params(S, schedule="ho"))
 
 
+def _dense_sweep_map(level, n):
+    """D with x_new = x + D (b - K x) for one DLSC sweep, read off the sweep
+    from x = 0 (a DLSC sweep is affine in b and x: each stage is a fixed
+    polynomial in its operator applied to a residual)."""
+    D = np.zeros((n, n))
+    for i in range(n):
+        e = np.zeros(n)
+        e[i] = 1.0
+        D[:, i] = level.relax(e, np.zeros(n), 1)
+    return D
+
+
+@pytest.mark.parametrize("kw", [dict(dim=2, n=4, disc="SV", seed=4, forcing="gaussian", bc="zero"),
+                                dict(dim=2, n=6, jitter=0.2, seed=2, forcing="gaussian", bc="lid")])
+def test_vanka_dlsc_hybrid_is_vanka_on_k0_and_dlsc_below(kw):
+    """The Vanka-DLSC hybrid (Section 4, Table 4): with the K1 hierarchy cut to
+    K1 and one exactly solved coarse level, apply(r) = x3 with
+    x1 = w0 M0 r, x2 = x1 + P0 y(eta R0 (r - K0 x1)), x3 = x2 + w0 M0 (r - K0 x2),
+    where y(b1) runs nu_dlsc = 2 DLSC sweeps on K1 from zero, the Galerkin
+    coarse correction, and 2 more DLSC sweeps (dense matrices throughout)."""
+    P = make_problem(**kw)
+    par = dc.default_params(P, relax="vanka-dlsc", max_coarse=5, max_levels=2)
+    if P.disc == "SV":
+        assert (par.omega0, par.eta_u, par.eta_p) == (0.87, 1.0, 2.96)  # Table 4, structured
+    pre = dc.DCPreconditioner(P, par)
+    assert len(pre.levels) == 2
+    assert isinstance(pre.relax[0], vanka.Patches) and isinstance(pre.relax[1], dlsc.DLSCLevel)
+    K0 = pre.K0.toarray()
+    K1 = pre.levels[0].K.toarray()
+    n1 = K1.shape[0]
+    Pm = pre.levels[0].P.toarray()
+    Kc = Pm.T @ K1 @ Pm
+    D = _dense_sweep_map(pre.relax[1], n1)
+    M0 = _dense_vanka(pre.K0, pre.relax[0])
+    r = np.random.default_rng(5).standard_normal(P.n0)
+    rf = r[pre.free0]
+    w = par.omega0
+
+    def y_of(b1):
+        y = np.zeros(n1)
+        for _ in range(2):
+            y = y + D @ (b1 - K1 @ y)
+        y = y + Pm @ (np.linalg.pinv(Kc) @ (Pm.T @ (b1 - K1 @ y)))
+        for _ in range(2):
+            y = y + D @ (b1 - K1 @ y)
+        return y
+
+    x1 = w * M0 @ rf
+    x2 = x1 + pre.prolong0(y_of(pre.restrict0(rf - K0 @ x1)))
+    x3 = x2 + w * M0 @ (rf - K0 @ x2)
+    d = pre.apply(r)[pre.free0] - x3
+    nv = pre.nvel
+    d[nv:] -= d[nv:].mean()  # bordered coarse solve vs pseudo-inverse: a constant pressure
+    assert np.linalg.norm(d) <= 1e-9 * np.linalg.norm(x3)
+
+
+@pytest.mark.parametrize("kw", [dict(dim=2, n=6, disc="SV", seed=4, forcing="gaussian", bc="zero"),
+                                dict(dim=2, n=8, jitter=0.2, seed=2, forcing="gaussian", bc="lid"),
+                                dict(dim=3, n=3, seed=3, forcing="smooth", bc="zero")])
+def test_vanka_dlsc_hybrid_solves(kw):
+    P = make_problem(**kw)
+    pre = dc.DCPreconditioner(P, dc.default_params(P, relax="vanka-dlsc", max_coarse=20))
+    res = fgmres.solve(P, pre, rtol=1e-11, max_it=400)
+    assert res.converged
+    ref = bordered_direct(P)
+    assert np.linalg.norm(res.x - ref) <= 1e-7 * np.linalg.norm(ref)
+
+
 def test_apply_is_linear():
     P = make_problem(dim=2, n=8, jitter=0.2, seed=2, forcing="gaussian", bc="lid")
     pre = dc.DCPreconditioner(P, dc.default_params(P, max_coarse=20))
