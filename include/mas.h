@@ -51,7 +51,10 @@ enum mas_status {
 };
 
 enum mas_disc { MAS_TH = 0, MAS_SV = 1 };                 /* Section 2.1 */
-enum mas_relax { MAS_RELAX_VANKA = 0, MAS_RELAX_DLSC = 1 };/* Sections 3.3.1, 3.3.2 */
+/* Sections 3.3.1, 3.3.2; MAS_RELAX_VANKA_DLSC is the hybrid of the Scott-Vogelius
+ * parameter study (Section 4, Table 4): Vanka on K0 (nu1/nu2 sweeps, omega0) and
+ * nu_dlsc DLSC sweeps on every relaxed level of the K1 hierarchy. */
+enum mas_relax { MAS_RELAX_VANKA = 0, MAS_RELAX_DLSC = 1, MAS_RELAX_VANKA_DLSC = 2 };
 /* Section 4.  MAS_HO_AMG: Algorithm 1 applied to K0 itself (the remark after
  * Algorithm 1, compared in Section 4): the hierarchy starts at K0, there is no
  * defect-correction level, eta_u/eta_p and omega0 are not used (omega on every
@@ -114,6 +117,8 @@ typedef struct {
                              wrapped relaxation is k iterations of FGMRES preconditioned by one
                              undamped Vanka sweep (Section 3.3.1), on every Vanka level except
                              K0 of Scott-Vogelius (stationary there); one right-hand side per call */
+  int32_t nu_dlsc;        /* MAS_RELAX_VANKA_DLSC: DLSC sweeps pre and post on the K1 hierarchy
+                             (2, the DLSC sweep count of Section 4); unused otherwise */
 } mas_params;
 
 typedef struct {

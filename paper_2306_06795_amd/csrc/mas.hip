@@ -686,8 +686,10 @@ struct Cycle : CycleBase {
     }
     const T om = (T)par.omega;
     bool x_zero = true;
-    if (L.relax && par.nu1 > 0) {
-      relax_level(L, par.nu1, om, true, s);
+    const int nu1 = par.relax == MAS_RELAX_VANKA_DLSC ? par.nu_dlsc : par.nu1;
+    const int nu2 = par.relax == MAS_RELAX_VANKA_DLSC ? par.nu_dlsc : par.nu2;
+    if (L.relax && nu1 > 0) {
+      relax_level(L, nu1, om, true, s);
       x_zero = false;
     }
     Level<T>& C = lev[l + 1];
@@ -703,7 +705,7 @@ struct Cycle : CycleBase {
     } else {
       spmv<2>(L.P, C.x, nullptr, L.x, s);
     }
-    if (L.relax && par.nu2 > 0) relax_level(L, par.nu2, om, false, s);
+    if (L.relax && nu2 > 0) relax_level(L, nu2, om, false, s);
   }
 
   void set_nr(int k) override {
@@ -1198,9 +1200,12 @@ void analyze_impl(mas_handle* h, const mas_problem* pr) {
   h->dim = d;
   h->disc = pr->disc;
   const mas_params& par = h->par;
-  if (par.relax != MAS_RELAX_VANKA && par.relax != MAS_RELAX_DLSC) throw MasError(MAS_EINVAL, "unknown relaxation");
+  if (par.relax != MAS_RELAX_VANKA && par.relax != MAS_RELAX_DLSC && par.relax != MAS_RELAX_VANKA_DLSC)
+    throw MasError(MAS_EINVAL, "unknown relaxation");
   for (int q = 0; q < 3; ++q)
-    if (par.relax == MAS_RELAX_DLSC && par.cheb_deg[q] < 1) throw MasError(MAS_EINVAL, "Chebyshev degrees must be >= 1");
+    if (par.relax != MAS_RELAX_VANKA && par.cheb_deg[q] < 1) throw MasError(MAS_EINVAL, "Chebyshev degrees must be >= 1");
+  if (par.relax == MAS_RELAX_VANKA_DLSC && (par.nu_dlsc < 0 || par.nu_dlsc > 16))
+    throw MasError(MAS_EINVAL, "nu_dlsc must be in [0, 16]");
   if (par.schedule < MAS_DC_ALL || par.schedule > MAS_HO_AMG) throw MasError(MAS_EINVAL, "unknown schedule");
   // HO-AMG (the remark after Algorithm 1): the hierarchy is built from K0 itself
   const bool ho = par.schedule == MAS_HO_AMG;
@@ -1295,7 +1300,7 @@ void analyze_impl(mas_handle* h, const mas_problem* pr) {
   std::vector<HostDlsc> dl(nl);
   for (size_t l = 0; l + 1 < nl; ++l) {
     if (!relax[l]) continue;
-    if (par.relax == MAS_RELAX_VANKA) {
+    if (par.relax == MAS_RELAX_VANKA || (par.relax == MAS_RELAX_VANKA_DLSC && l == 0)) {
       if (l == 0 && pr->disc == MAS_SV) {
         // three pressure seeds per element (Section 3.3.1)
         if (!pr->elem_p0 || pr->n_elem <= 0) throw MasError(MAS_EINVAL, "elem_p0 is required for Scott-Vogelius");
@@ -1877,7 +1882,10 @@ void mas_default_params(int32_t dim, int32_t disc, int32_t relax, mas_params* ou
   p.omega = 0.5;
   p.eta_u = 1.0;
   p.eta_p = 1.0;
-  if (disc == MAS_SV) {  // Table 4, structured meshes, Vanka on all levels
+  if (disc == MAS_SV && relax == MAS_RELAX_VANKA_DLSC) {  // Table 4, structured meshes, Vanka-DLSC
+    p.omega0 = 0.87;
+    p.eta_p = 2.96;
+  } else if (disc == MAS_SV) {  // Table 4, structured meshes, Vanka on all levels
     p.omega0 = 0.78;
     p.eta_p = 2.68;
   }
@@ -1895,6 +1903,7 @@ void mas_default_params(int32_t dim, int32_t disc, int32_t relax, mas_params* ou
   p.mass_rtol = 1e-14;
   p.nrhs_max = 1;
   p.krylov_its = 0;
+  p.nu_dlsc = 2;
   *out = p;
 }
 

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "lib", "libmas.so")
 MAS_OK, MAS_NOT_CONVERGED = 0, 1
 MAS_EINVAL, MAS_ESINGULAR_PATCH, MAS_ENOMEM, MAS_EHIP, MAS_ENAN = -1, -2, -3, -4, -5
 MAS_TH, MAS_SV = 0, 1
-MAS_RELAX_VANKA, MAS_RELAX_DLSC = 0, 1
+MAS_RELAX_VANKA, MAS_RELAX_DLSC, MAS_RELAX_VANKA_DLSC = 0, 1, 2
 MAS_DC_ALL, MAS_DC_SKIP1, MAS_DC_SKIP0, MAS_HO_AMG = 0, 1, 2, 3
 MAS_FP64, MAS_FP32 = 0, 1
 
@@ -41,7 +41,7 @@ class mas_params(C.Structure):
                 ("cheb_deg", C.c_int32 * 3), ("precision", C.c_int32), ("restart", C.c_int32),
                 ("max_coarse", C.c_int32), ("max_levels", C.c_int32), ("theta", C.c_double),
                 ("seed", C.c_uint64), ("mass_rtol", C.c_double), ("nrhs_max", C.c_int32),
-                ("krylov_its", C.c_int32)]
+                ("krylov_its", C.c_int32), ("nu_dlsc", C.c_int32)]
 
 
 class mas_solve_info(C.Structure):

@@ -63,6 +63,8 @@ def test_default_params_follow_the_paper():
     assert (p.omega0, p.eta_p, p.eta_u, p.restart) == (0.78, 2.68, 1.0, 20)
     p3 = mas.default_params(3, mas.MAS_TH, mas.MAS_RELAX_DLSC)
     assert list(p3.cheb_deg) == [4, 4, 16] and p3.nu1 == 2
+    ph = mas.default_params(2, mas.MAS_SV, mas.MAS_RELAX_VANKA_DLSC)  # Table 4, Vanka-DLSC row
+    assert (ph.omega0, ph.eta_p, ph.eta_u, ph.nu1, ph.nu_dlsc) == (0.87, 2.96, 1.0, 1, 2)
 
 
 SCHED = {"all": mas.MAS_DC_ALL, "ho": mas.MAS_HO_AMG}

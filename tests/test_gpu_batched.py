@@ -20,11 +20,14 @@ CASES = {
     "th3d3": (dict(dim=3, n=3, forcing="smooth", bc="zero", seed=3, nrhs=3), "vanka"),
     # level-2 patches of up to 424 DoFs: factor records too large for LDS (global-memory path)
     "th3d6": (dict(dim=3, n=6, forcing="smooth", bc="zero", seed=3, nrhs=6), "vanka"),
+    # Vanka on K0 (element patches), DLSC below
+    "sv6_hyb": (dict(dim=2, n=6, disc="SV", seed=4, forcing="gaussian", bc="zero", nrhs=5), "vanka-dlsc"),
 }
+RELAX = {"vanka": mas.MAS_RELAX_VANKA, "dlsc": mas.MAS_RELAX_DLSC, "vanka-dlsc": mas.MAS_RELAX_VANKA_DLSC}
 
 
 def handle(P, relax, precision, nrhs_max):
-    mrelax = mas.MAS_RELAX_DLSC if relax == "dlsc" else mas.MAS_RELAX_VANKA
+    mrelax = RELAX[relax]
     disc = mas.MAS_SV if P.disc == "SV" else mas.MAS_TH
     mp = mas.default_params(P.dim, disc, mrelax, max_coarse=30, precision=precision, nrhs_max=nrhs_max)
     return mas.Handle(P, mp)

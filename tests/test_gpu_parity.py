@@ -55,7 +55,16 @@ CASES = {
                      dict(max_coarse=40, schedule="ho", relax="dlsc")),
     "th24_lid_ho_kry": (dict(dim=2, n=24, jitter=0.2, seed=2, forcing="gaussian", bc="lid"),
                         dict(max_coarse=40, schedule="ho", krylov_its=2)),
+    # Vanka on K0, DLSC on the K1 hierarchy (Section 4, Table 4)
+    "sv6_hyb": (dict(dim=2, n=6, disc="SV", seed=4, forcing="gaussian", bc="zero"),
+                dict(max_coarse=40, relax="vanka-dlsc")),
+    "sv8_lid_hyb": (dict(dim=2, n=8, disc="SV", jitter=0.2, seed=4, forcing="gaussian", bc="lid"),
+                    dict(max_coarse=40, relax="vanka-dlsc")),
+    "th24_lid_hyb": (dict(dim=2, n=24, jitter=0.2, seed=2, forcing="gaussian", bc="lid"),
+                     dict(max_coarse=40, relax="vanka-dlsc")),
+    "th3d4_hyb": (dict(dim=3, n=4, forcing="smooth", bc="zero", seed=3), dict(max_coarse=40, relax="vanka-dlsc")),
 }
+RELAX = {"vanka": mas.MAS_RELAX_VANKA, "dlsc": mas.MAS_RELAX_DLSC, "vanka-dlsc": mas.MAS_RELAX_VANKA_DLSC}
 SCHED = {"all": mas.MAS_DC_ALL, "skip1": mas.MAS_DC_SKIP1, "skip0": mas.MAS_DC_SKIP0, "ho": mas.MAS_HO_AMG}
 
 
@@ -66,12 +75,12 @@ def build(name, precision=mas.MAS_FP64):
     over = dict(over)
     par = dc.default_params(P, relax=relax, **over)
     CASES[name][1]["relax"] = relax
-    mrelax = mas.MAS_RELAX_DLSC if relax == "dlsc" else mas.MAS_RELAX_VANKA
+    mrelax = RELAX[relax]
     disc = mas.MAS_SV if P.disc == "SV" else mas.MAS_TH
     mp = mas.default_params(P.dim, disc, mrelax, theta=par.theta, max_coarse=par.max_coarse,
                             max_levels=par.max_levels, omega0=par.omega0, omega=par.omega,
                             eta_u=par.eta_u, eta_p=par.eta_p, schedule=SCHED[par.schedule],
-                            nu1=par.nu1, nu2=par.nu2,
+                            nu1=par.nu1, nu2=par.nu2, nu_dlsc=par.nu_dlsc,
                             precision=precision, seed=par.seed, krylov_its=par.krylov_its)
     print(f"[case {name}] n0={P.n0} precision={precision}", flush=True)
     return P, par, mp
@@ -128,7 +137,8 @@ def test_full_block_levels_match_oracle(name, monkeypatch):
 
 @pytest.mark.parametrize("name", ["th16_2lvl", "th24_lid", "th3d4", "th16_skip1", "th24_dlsc", "th3d4_dlsc",
                                   "sv6", "sv8_lid", "th24_lid_kry", "th3d4_kry", "sv8_lid_kry",
-                                  "th24_lid_ho", "th3d4_ho", "th24_ho_dlsc", "th24_lid_ho_kry"])
+                                  "th24_lid_ho", "th3d4_ho", "th24_ho_dlsc", "th24_lid_ho_kry",
+                                  "sv6_hyb", "sv8_lid_hyb", "th24_lid_hyb", "th3d4_hyb"])
 def test_solve_fp64_matches_oracle(name):
     P, par, mp = build(name)
     pre = dc.DCPreconditioner(P, par)
@@ -152,7 +162,7 @@ def test_solve_fp64_matches_oracle(name):
 
 
 @pytest.mark.parametrize("name", ["th16_3lvl", "th24_lid", "th3d4", "th24_dlsc", "sv8_lid", "th24_lid_kry",
-                                  "th24_lid_ho"])
+                                  "th24_lid_ho", "sv8_lid_hyb"])
 def test_solve_fp32_cycle_reaches_1e8(name):
     P, par, mp = build(name, precision=mas.MAS_FP32)
     h = mas.Handle(P, mp)
