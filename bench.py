@@ -38,7 +38,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="th2d_256")
-    ap.add_argument("--relax", default="vanka", choices=["vanka", "dlsc"])
+    ap.add_argument("--relax", default="vanka", choices=["vanka", "dlsc", "vanka-dlsc"])
+    ap.add_argument("--schedule", default="all", choices=["all", "skip1", "skip0", "ho"],
+                    help="DC-all / DC-skip1 / DC-skip0, or HO-AMG (Algorithm 1 applied to K0)")
+    ap.add_argument("--krylov-its", type=int, default=0,
+                    help="FGMRES-wrapped Vanka relaxation with this many iterations (0: stationary sweeps)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -77,12 +81,12 @@ def measured_traffic(config, precision, relax, kind):
     return None
 
 
-def cpu_baseline(prob, its_gpu, sample_its):
+def cpu_baseline(prob, its_gpu, sample_its, relax="vanka", krylov_its=0, schedule="all"):
     """The oracle on the host: setup untimed, then ``sample_its`` FGMRES
     iterations of the same workload (first right-hand side) timed and scaled to
     one full solve."""
     from oracle import dc, fgmres
-    pre = dc.DCPreconditioner(prob, dc.default_params(prob))
+    pre = dc.DCPreconditioner(prob, dc.default_params(prob, relax, krylov_its=krylov_its, schedule=schedule))
     b0 = prob.b if prob.b.ndim == 1 else np.ascontiguousarray(prob.b[:, 0])
     pre.apply(b0)  # untimed: builds the oracle's dense patch matrices once
     t0 = time.perf_counter()
@@ -244,11 +248,19 @@ def main():
     t0 = time.perf_counter()
     prob = make_config(a.config)
     t_gen = time.perf_counter() - t0
-    relax = mas.MAS_RELAX_VANKA if a.relax == "vanka" else mas.MAS_RELAX_DLSC
+    relax = {"vanka": mas.MAS_RELAX_VANKA, "dlsc": mas.MAS_RELAX_DLSC, "vanka-dlsc": mas.MAS_RELAX_VANKA_DLSC}[a.relax]
     prec = mas.MAS_FP64 if a.precision == "fp64" else mas.MAS_FP32
     nrhs = prob.nrhs
+    if a.krylov_its and (a.relax != "vanka" or nrhs != 1):
+        sys.exit("--krylov-its wraps the Vanka relaxation of a single right-hand side")
+    rname = a.relax + (f"+fgmres{a.krylov_its}" if a.krylov_its else "")
+    label = rname
+    sched = {"all": mas.MAS_DC_ALL, "skip1": mas.MAS_DC_SKIP1, "skip0": mas.MAS_DC_SKIP0, "ho": mas.MAS_HO_AMG}
+    method = "HO-AMG" if a.schedule == "ho" else f"DC-{a.schedule}"
+    if a.schedule != "all":
+        label += f"+{a.schedule}"
     mp = mas.default_params(prob.dim, mas.MAS_SV if prob.disc == "SV" else mas.MAS_TH, relax, precision=prec,
-                            nrhs_max=nrhs)
+                            nrhs_max=nrhs, krylov_its=a.krylov_its, schedule=sched[a.schedule])
     t0 = time.perf_counter()
     h = mas.Handle(prob, mp)
     torch.cuda.synchronize()
@@ -322,22 +334,22 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if prec == mas.MAS_FP64 else "f32 cycle / f64 FGMRES",
         "data": "synthetic",
-        "config": {"workload": f"{a.config}: {WORKLOADS.get(a.config, a.config)}, {a.relax} DC-all, "
+        "config": {"workload": f"{a.config}: {WORKLOADS.get(a.config, a.config)}, {rname} {method}, "
                                f"FGMRES(20) rtol {a.rtol:g}",
-                   "n0": prob.n0, "levels": info["n"], "relax": a.relax, "cycle_precision": a.precision},
+                   "n0": prob.n0, "levels": info["n"], "relax": label, "cycle_precision": a.precision},
         "iters": iters[-1],
         "true_relres": relres,
         "vcycle_ms": vcycle_ms,
         "setup_s": t_setup,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(a.config, a.precision, a.relax, kind),
+                     "traffic": measured_traffic(a.config, a.precision, label, kind),
                      "kernel": kernel, "avg_launch_ms": avg_launch_ms,
                      "algorithmic_bytes_per_launch": avg_bytes, "launches_timed": k_launches,
                      "share_of_timed_kernels": k_ms / max(1e-12, total_ms)},
     }
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, its_last, a.cpu_sample_its)
+        out["cpu_baseline"] = cpu_baseline(prob, its_last, a.cpu_sample_its, a.relax, a.krylov_its, a.schedule)
     print(json.dumps(out))
     h.close()
 
