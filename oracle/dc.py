@@ -55,6 +55,8 @@ class Params:
     max_coarse: int = 300
     max_levels: int = 10
     seed: int = 0x5EED
+    dlsc_amg: int = 0  # >0: the DLSC continuity and pressure stages take one SA V-cycle on S with this many
+                       # weighted-Jacobi sweeps before and after the coarse correction (Section 4)
     nu_dlsc: int = 2  # "vanka-dlsc": DLSC sweeps pre and post on the K1 hierarchy (two, Section 4)
     krylov_its: int = 0  # >0: FGMRES(krylov_its)-wrapped Vanka instead of damped sweeps (Section 3.3.1);
                          # Scott-Vogelius keeps the stationary sweep on K0
@@ -106,7 +108,10 @@ class DCPreconditioner:
                 nv = int((f < d).sum())
                 on_k0 = l == 0 or (self.ho and l == 1)  # M_u = diag(P2 mass) wherever the operator is K0
                 mu = prob.mu_diag0[self.free0[:nv]] if on_k0 else np.ones(nv)
-                self.relax.append(DLSCLevel(K, f, d, mu, cheb, par.seed + 2 * l))
+                amg = None
+                if par.dlsc_amg > 0:
+                    amg = (par.theta, par.max_coarse, par.max_levels, par.dlsc_amg, bool(prob.p_nullspace))
+                self.relax.append(DLSCLevel(K, f, d, mu, cheb, par.seed + 2 * l, amg))
         # coarsest level: dense LU of the (bordered) operator
         last = self.levels[-1]
         Kc = last.K.toarray()

@@ -507,6 +507,77 @@ def test_vanka_dlsc_hybrid_solves(kw):
     assert np.linalg.norm(res.x - ref) <= 1e-7 * np.linalg.norm(ref)
 
 
+def _poisson2d(m, neumann=False):
+    """5-point Laplacian on an m x m grid (Dirichlet: diagonal 4; Neumann: the
+    graph Laplacian, singular with the constants as null space)."""
+    T = sp.diags([-np.ones(m - 1), 2 * np.ones(m), -np.ones(m - 1)], [-1, 0, 1])
+    if neumann:
+        T = T.tolil()
+        T[0, 0] = T[m - 1, m - 1] = 1.0
+    I = sp.identity(m)
+    return sp.csr_matrix(sp.kron(T, I) + sp.kron(I, T))
+
+
+def test_sa_vcycle_jacobi_weight_closed_form_and_two_level_formula():
+    """SA V-cycle with weighted Jacobi (the DLSC AMG stages, Section 4).  On the
+    Dirichlet 5-point Laplacian every row has s_ii = 4 and the largest absolute
+    row sum is 8, so the weight is (4/3)/2 and w D^-1 = 1/6 on every row.  The
+    two-level cycle equals x1 = 2 Jacobi sweeps from 0, x2 = x1 + P Sc^-1 P^T (b - S x1),
+    x3 = 2 Jacobi sweeps from x2, with Sc = P^T S P (dense)."""
+    S = _poisson2d(12)
+    v = dlsc.SAVcycle(S, 0.02, 20, 2, 2, False)
+    assert len(v.ops) == 2
+    assert np.allclose(v.wdinv[0], 1.0 / 6.0, rtol=0, atol=1e-15)
+    Sd = S.toarray()
+    P = v.Ps[0].toarray()
+    Sc = P.T @ Sd @ P
+    b = np.random.default_rng(0).standard_normal(S.shape[0])
+    x = np.zeros_like(b)
+    for _ in range(2):
+        x = x + (b - Sd @ x) / 6.0
+    x = x + P @ np.linalg.solve(Sc, P.T @ (b - Sd @ x))
+    for _ in range(2):
+        x = x + (b - Sd @ x) / 6.0
+    assert np.linalg.norm(v.apply(b) - x) <= 1e-12 * np.linalg.norm(x)
+
+
+def test_sa_vcycle_one_level_exact_symmetric_and_convergent():
+    # one level: the bordered exact solve of the singular Neumann Laplacian
+    S = _poisson2d(8, neumann=True)
+    n = S.shape[0]
+    b = np.random.default_rng(1).standard_normal(n)
+    b -= b.mean()  # consistent right-hand side
+    v1 = dlsc.SAVcycle(S, 0.02, 10 ** 6, 10, 2, True)
+    assert len(v1.ops) == 1
+    y = v1.apply(b)
+    assert np.linalg.norm(S @ y - b) <= 1e-10 * np.linalg.norm(b) and abs(y.sum()) <= 1e-10
+    # several levels: the cycle is a symmetric operator and a convergent iteration on range(S)
+    S = _poisson2d(16, neumann=True)
+    n = S.shape[0]
+    v = dlsc.SAVcycle(S, 0.02, 10, 10, 2, True)
+    assert len(v.ops) >= 3
+    V = np.column_stack([v.apply(e) for e in np.eye(n)])
+    assert np.linalg.norm(V - V.T) <= 1e-10 * np.linalg.norm(V)
+    Q = np.eye(n) - np.ones((n, n)) / n  # projector onto range(S)
+    E = Q @ (np.eye(n) - V @ S.toarray()) @ Q
+    # ~0.55 here; four Jacobi sweeps without the coarse correction would give ~0.99
+    assert np.max(np.abs(np.linalg.eigvals(E))) < 0.8
+
+
+@pytest.mark.parametrize("kw", [dict(dim=2, n=8, jitter=0.2, seed=2, forcing="gaussian", bc="lid"),
+                                dict(dim=3, n=3, seed=3, forcing="smooth", bc="zero"),
+                                dict(dim=2, n=6, disc="SV", seed=4, forcing="gaussian", bc="zero")])
+def test_dlsc_with_amg_stages_solves(kw):
+    P = make_problem(**kw)
+    relax = "vanka-dlsc" if P.disc == "SV" else "dlsc"
+    pre = dc.DCPreconditioner(P, dc.default_params(P, relax=relax, max_coarse=20, dlsc_amg=2))
+    assert all(R.svc is not None for R in pre.relax if isinstance(R, dlsc.DLSCLevel))
+    res = fgmres.solve(P, pre, rtol=1e-11, max_it=400)
+    assert res.converged
+    ref = bordered_direct(P)
+    assert np.linalg.norm(res.x - ref) <= 1e-7 * np.linalg.norm(ref)
+
+
 def test_apply_is_linear():
     P = make_problem(dim=2, n=8, jitter=0.2, seed=2, forcing="gaussian", bc="lid")
     pre = dc.DCPreconditioner(P, dc.default_params(P, max_coarse=20))
