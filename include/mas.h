@@ -119,6 +119,10 @@ typedef struct {
                              K0 of Scott-Vogelius (stationary there); one right-hand side per call */
   int32_t nu_dlsc;        /* MAS_RELAX_VANKA_DLSC: DLSC sweeps pre and post on the K1 hierarchy
                              (2, the DLSC sweep count of Section 4); unused otherwise */
+  int32_t dlsc_amg;       /* 0: DLSC continuity and pressure-correction stages by Chebyshev (Table 3);
+                             k = 1..8: each by one smoothed-aggregation V-cycle on B M^-1 B^T with k
+                             weighted-Jacobi sweeps (weight 4/3 over the largest absolute row sum of
+                             D^-1 S) before and after the coarse correction (Section 4) */
 } mas_params;
 
 typedef struct {

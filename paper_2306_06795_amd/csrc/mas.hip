@@ -293,6 +293,16 @@ struct DDlsc {
   T *ru = nullptr, *vs = nullptr, *tmp = nullptr, *t1 = nullptr, *t2 = nullptr;  // velocity-sized
   T *rp = nullptr, *q = nullptr, *dp = nullptr;                                 // pressure-sized
   T *cd = nullptr, *cd2 = nullptr, *cres = nullptr;                             // Chebyshev work (max size)
+  // AMG stages (Section 4): a smoothed-aggregation hierarchy of S with weighted Jacobi
+  struct SLev {
+    int64_t n = 0;
+    DCsr<T> S, P, R;          // S_k; P: S_k <- S_{k+1}, R = P^T
+    T* wdinv = nullptr;       // (4/3) / rho_k / diag(S_k)
+    T *x = nullptr, *b = nullptr, *res = nullptr, *d1 = nullptr, *d2 = nullptr, *corr = nullptr;
+  };
+  std::vector<SLev> sh;       // empty: Chebyshev stages
+  double* sinv = nullptr;     // dense inverse of the (bordered) coarsest S
+  int64_t sld = 0;
 };
 
 template <typename T>
@@ -476,6 +486,60 @@ struct Cycle : CycleBase {
     return cs;
   }
 
+  // y = one V-cycle of smoothed aggregation with weighted Jacobi for S_k y = b
+  // (the DLSC AMG stages, Section 4).  Jacobi in residual form is the fused
+  // Chebyshev step with a = 0 and c = 1 (the weight is folded into wdinv):
+  // res -= S d, d = wdinv res, acc += d.
+  void s_vcycle(DDlsc<T>& D, size_t k, const T* b, T* x, hipStream_t s) {
+    auto& L = D.sh[k];
+    const int64_t n = L.n * nr;
+    const unsigned nb = blocks_for(n, 256);
+    if (k + 1 == D.sh.size()) {
+      if (nr == 1)
+        hipLaunchKernelGGL((k_dense_gemv<T>), dim3(blocks_for(L.n * WAVE, 256)), dim3(256), 0, s, (int)L.n,
+                           (int)D.sld, D.sinv, b, x);
+      else
+        hipLaunchKernelGGL((k_dense_gemm<T>), dim3(nb), dim3(256), 0, s, (int)L.n, (int)D.sld, nr, D.sinv, b, x);
+      launch_check();
+      return;
+    }
+    const int nu = par.dlsc_amg;
+    const ChebStep<T> jac{(T)0, (T)1, L.wdinv, nullptr, nullptr};
+    // pre-relaxation from x = 0: d = wdinv b, x = d, res = b
+    hipLaunchKernelGGL((k_cheb_init<T>), dim3(nb), dim3(256), 0, s, n, b, (T)1, L.wdinv, L.d1, L.res, x, nr);
+    launch_check();
+    T* dc = L.d1;
+    T* dn = L.d2;
+    for (int j = 1; j < nu; ++j) {
+      ChebStep<T> cs = jac;
+      cs.dnew = dn;
+      cs.acc = x;
+      spmv<4>(L.S, dc, nullptr, L.res, s, cs);
+      std::swap(dc, dn);
+    }
+    spmv<3>(L.S, dc, nullptr, L.res, s);  // res = b - S x
+    auto& C = D.sh[k + 1];
+    spmv<0>(L.R, L.res, nullptr, C.b, s);
+    s_vcycle(D, k + 1, C.b, C.x, s);
+    spmv<2>(L.P, C.x, nullptr, x, s);  // x += P x_c
+    // post-relaxation: the corrections accumulate in corr, then x += corr
+    ChebStep<T> st{(T)1, (T)1, nullptr, L.d1, L.corr};
+    st.res = L.res;
+    st.cinv = L.wdinv;
+    spmv<1>(L.S, x, b, L.res, s, st);  // res = b - S x, d = wdinv res, corr = d
+    dc = L.d1;
+    dn = L.d2;
+    for (int j = 1; j < nu; ++j) {
+      ChebStep<T> cs = jac;
+      cs.dnew = dn;
+      cs.acc = L.corr;
+      spmv<4>(L.S, dc, nullptr, L.res, s, cs);
+      std::swap(dc, dn);
+    }
+    hipLaunchKernelGGL((k_axpby<T>), dim3(nb), dim3(256), 0, s, n, (T)1, L.corr, (T)1, x);
+    launch_check();
+  }
+
   // one DLSC sweep (Algorithm 2) on level L: x = (u, p), b = (f, g)
   void dlsc_sweep(Level<T>& L, hipStream_t s) {
     DDlsc<T>& D = L.dl;
@@ -490,13 +554,24 @@ struct Cycle : CycleBase {
     spmv<3>(D.Bt, p, nullptr, D.ru, s, cheb_start(D.lamA, D.vs, D));
     chebyshev(D.A, D.ru, D.vs, D.lamA, par.cheb_deg[0], D, s, true);  // momentum
     hipLaunchKernelGGL((k_add<T>), dim3(bv), dim3(256), 0, s, nv, u, D.vs, D.tmp);
-    spmv<1>(D.B, D.tmp, g, D.rp, s, cheb_start(D.lamS, D.q, D));  // rp = g - B (u + v*)
-    chebyshev(D.S, D.rp, D.q, D.lamS, par.cheb_deg[1], D, s, true);  // continuity
+    const bool amg = !D.sh.empty();
+    if (amg) {
+      spmv<1>(D.B, D.tmp, g, D.rp, s);  // rp = g - B (u + v*)
+      s_vcycle(D, 0, D.rp, D.q, s);     // continuity
+    } else {
+      spmv<1>(D.B, D.tmp, g, D.rp, s, cheb_start(D.lamS, D.q, D));  // rp = g - B (u + v*)
+      chebyshev(D.S, D.rp, D.q, D.lamS, par.cheb_deg[1], D, s, true);  // continuity
+    }
     // scaled products (MODE 5: y = a m (A x)) fold the M^-1 scalings and the sign in
     spmv<5>(D.Bt, D.q, nullptr, D.t1, s, ChebStep<T>{(T)1, (T)0, D.minv, nullptr, nullptr});  // t1 = M^-1 B^T q
     spmv<5>(D.A, D.t1, nullptr, D.t2, s, ChebStep<T>{(T)1, (T)0, D.minv, nullptr, nullptr});  // t2 = M^-1 A t1
-    spmv<5>(D.B, D.t2, nullptr, D.rp, s, cheb_start(D.lamS, D.dp, D, (T)-1));  // rp = -B t2
-    chebyshev(D.S, D.rp, D.dp, D.lamS, par.cheb_deg[2], D, s, true);  // pressure correction
+    if (amg) {
+      spmv<5>(D.B, D.t2, nullptr, D.rp, s, ChebStep<T>{(T)-1, (T)0, nullptr, nullptr, nullptr});  // rp = -B t2
+      s_vcycle(D, 0, D.rp, D.dp, s);  // pressure correction
+    } else {
+      spmv<5>(D.B, D.t2, nullptr, D.rp, s, cheb_start(D.lamS, D.dp, D, (T)-1));  // rp = -B t2
+      chebyshev(D.S, D.rp, D.dp, D.lamS, par.cheb_deg[2], D, s, true);  // pressure correction
+    }
     // u += v* + M^-1 B^T q, p += dp (u and p are contiguous in L.x)
     hipLaunchKernelGGL((k_dlsc_update<T>), dim3(blocks_for(nv + np, 256)), dim3(256), 0, s, nv, np, u, D.vs, D.t1,
                        D.dp);
@@ -762,6 +837,11 @@ struct HostDlsc {
   Csr A, B, Bt, S;            // velocity block, divergence block, its transpose, B M^-1 B^T
   std::vector<double> minv;   // M_u^-1 (diagonal)
   double lamA = 0.0, lamS = 0.0;
+  // AMG stages: S_0 = S, S_{k+1} = P_k^T S_k P_k, Jacobi scalings, dense (bordered) coarsest
+  std::vector<Csr> Sk, Pk;
+  std::vector<std::vector<double>> wdinv;
+  std::vector<double> sc_dense;
+  int64_t sc_ld = 0;
 };
 
 struct HostPlan {
@@ -1118,6 +1198,24 @@ std::unique_ptr<Cycle<T>> build_cycle(mas_handle* h, const std::vector<Csr>& Ks,
         D.cd = ar.alloc<T>(std::max(D.nv, D.np) * R);
         D.cd2 = ar.alloc<T>(std::max(D.nv, D.np) * R);
         D.cres = ar.alloc<T>(std::max(D.nv, D.np) * R);
+        if (!H.Sk.empty()) {
+          D.sh.resize(H.Sk.size());
+          for (size_t k = 0; k < H.Sk.size(); ++k) {
+            auto& Lk = D.sh[k];
+            Lk.n = H.Sk[k].nr;
+            Lk.x = ar.alloc<T>(Lk.n * R);
+            Lk.b = ar.alloc<T>(Lk.n * R);
+            if (k + 1 == H.Sk.size()) break;
+            Lk.S = upload_csr<T>(ar, H.Sk[k], s);
+            Lk.P = upload_csr<T>(ar, H.Pk[k], s);
+            Lk.R = upload_csr<T>(ar, transpose(H.Pk[k]), s);
+            Lk.wdinv = ar.upload<T>(H.wdinv[k], s);
+            for (T** v : {&Lk.res, &Lk.d1, &Lk.d2, &Lk.corr}) *v = ar.alloc<T>(Lk.n * R);
+          }
+          D.sinv = ar.upload<double>(H.sc_dense, s);
+          dense_inverse(ar, D.sinv, (int)H.sc_ld, s);
+          D.sld = H.sc_ld;
+        }
       }
     }
   }
@@ -1149,6 +1247,12 @@ std::unique_ptr<Cycle<T>> build_cycle(mas_handle* h, const std::vector<Csr>& Ks,
       autotune_team<T>(L.dl.S, L.dl.rp, L.dl.q, s);
       autotune_team<T>(L.dl.B, L.dl.ru, L.dl.rp, s);
       autotune_team<T>(L.dl.Bt, L.dl.rp, L.dl.ru, s);
+      for (size_t k = 0; k + 1 < L.dl.sh.size(); ++k) {
+        auto& Sl = L.dl.sh[k];
+        autotune_team<T>(Sl.S, Sl.x, Sl.res, s);
+        autotune_team<T>(Sl.R, Sl.res, L.dl.sh[k + 1].b, s);
+        autotune_team<T>(Sl.P, L.dl.sh[k + 1].x, Sl.x, s);
+      }
     }
     if (l >= 1) {
       Level<T>& C = cyc->lev[l + 1];
@@ -1192,6 +1296,50 @@ std::unique_ptr<Cycle<T>> build_cycle(mas_handle* h, const std::vector<Csr>& Ks,
   return cyc;
 }
 
+// The smoothed-aggregation hierarchy of S for the DLSC AMG stages (Section 4):
+// Algorithm 1's scalar SA on S, Galerkin products, Jacobi weight (4/3) / rho
+// with rho = max_i sum_j |s_ij| / s_ii per level, and the coarsest operator as
+// a dense matrix, bordered with its near-null vector when S is singular.
+void s_hierarchy(HostDlsc& D, const mas_params& par, bool singular) {
+  std::vector<std::vector<double>> Bs;
+  sa_field(D.S, par.theta, par.max_coarse, par.max_levels, D.Pk, Bs);
+  D.Sk.assign(1, D.S);
+  for (const Csr& P : D.Pk) D.Sk.push_back(galerkin(P, D.Sk.back()));
+  D.wdinv.clear();
+  for (size_t k = 0; k + 1 < D.Sk.size(); ++k) {
+    const Csr& A = D.Sk[k];
+    std::vector<double> d(A.nr, 0.0), w(A.nr);
+    double rho = 0.0;
+    for (int64_t i = 0; i < A.nr; ++i) {
+      double sum = 0.0;
+      for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e) {
+        sum += std::fabs(A.val[e]);
+        if (A.ind[e] == i) d[i] = A.val[e];
+      }
+      if (!(d[i] > 0.0)) throw MasError(MAS_EINVAL, "B M^-1 B^T has a non-positive diagonal entry");
+      rho = std::max(rho, sum / d[i]);
+    }
+    for (int64_t i = 0; i < A.nr; ++i) w[i] = (4.0 / 3.0) / rho / d[i];
+    D.wdinv.push_back(std::move(w));
+  }
+  const Csr& C = D.Sk.back();
+  const int64_t m = C.nr, ld = singular ? m + 1 : m;
+  D.sc_ld = ld;
+  D.sc_dense.assign((size_t)ld * ld, 0.0);
+  for (int64_t i = 0; i < m; ++i)
+    for (int64_t e = C.ptr[i]; e < C.ptr[i + 1]; ++e) D.sc_dense[i * ld + C.ind[e]] = C.val[e];
+  if (singular) {
+    const std::vector<double>& nv = Bs.back();
+    double nn = 0.0;
+    for (double v : nv) nn += v * v;
+    nn = std::sqrt(nn);
+    for (int64_t i = 0; i < m; ++i) {
+      D.sc_dense[i * ld + m] = nv[i] / nn;
+      D.sc_dense[m * ld + i] = nv[i] / nn;
+    }
+  }
+}
+
 void analyze_impl(mas_handle* h, const mas_problem* pr) {
   const int d = pr->dim;
   if (d != 2 && d != 3) throw MasError(MAS_EINVAL, "dim must be 2 or 3");
@@ -1206,6 +1354,7 @@ void analyze_impl(mas_handle* h, const mas_problem* pr) {
     if (par.relax != MAS_RELAX_VANKA && par.cheb_deg[q] < 1) throw MasError(MAS_EINVAL, "Chebyshev degrees must be >= 1");
   if (par.relax == MAS_RELAX_VANKA_DLSC && (par.nu_dlsc < 0 || par.nu_dlsc > 16))
     throw MasError(MAS_EINVAL, "nu_dlsc must be in [0, 16]");
+  if (par.dlsc_amg < 0 || par.dlsc_amg > 8) throw MasError(MAS_EINVAL, "dlsc_amg must be in [0, 8]");
   if (par.schedule < MAS_DC_ALL || par.schedule > MAS_HO_AMG) throw MasError(MAS_EINVAL, "unknown schedule");
   // HO-AMG (the remark after Algorithm 1): the hierarchy is built from K0 itself
   const bool ho = par.schedule == MAS_HO_AMG;
@@ -1341,6 +1490,7 @@ void analyze_impl(mas_handle* h, const mas_problem* pr) {
     D.S = spgemm(BM, D.Bt);
     D.lamA = lanczos_max(D.A, par.seed + 2 * l, 20);
     D.lamS = lanczos_max(D.S, par.seed + 2 * l + 1, 20);
+    if (par.dlsc_amg > 0) s_hierarchy(D, par, pr->p_nullspace != 0);
   }
   // coarsest operator, bordered with the coarse pressure null vector
   const Csr& KL = Ks.back();
@@ -1904,6 +2054,7 @@ void mas_default_params(int32_t dim, int32_t disc, int32_t relax, mas_params* ou
   p.nrhs_max = 1;
   p.krylov_its = 0;
   p.nu_dlsc = 2;
+  p.dlsc_amg = 0;
   *out = p;
 }
 

@@ -41,7 +41,7 @@ class mas_params(C.Structure):
                 ("cheb_deg", C.c_int32 * 3), ("precision", C.c_int32), ("restart", C.c_int32),
                 ("max_coarse", C.c_int32), ("max_levels", C.c_int32), ("theta", C.c_double),
                 ("seed", C.c_uint64), ("mass_rtol", C.c_double), ("nrhs_max", C.c_int32),
-                ("krylov_its", C.c_int32), ("nu_dlsc", C.c_int32)]
+                ("krylov_its", C.c_int32), ("nu_dlsc", C.c_int32), ("dlsc_amg", C.c_int32)]
 
 
 class mas_solve_info(C.Structure):

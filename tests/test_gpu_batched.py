@@ -22,14 +22,18 @@ CASES = {
     "th3d6": (dict(dim=3, n=6, forcing="smooth", bc="zero", seed=3, nrhs=6), "vanka"),
     # Vanka on K0 (element patches), DLSC below
     "sv6_hyb": (dict(dim=2, n=6, disc="SV", seed=4, forcing="gaussian", bc="zero", nrhs=5), "vanka-dlsc"),
+    # DLSC with SA V-cycle stages (Section 4)
+    "th12_dlsc_amg": (dict(dim=2, n=12, jitter=0.2, seed=2, forcing="gaussian", bc="lid", nrhs=4), "dlsc+amg"),
 }
 RELAX = {"vanka": mas.MAS_RELAX_VANKA, "dlsc": mas.MAS_RELAX_DLSC, "vanka-dlsc": mas.MAS_RELAX_VANKA_DLSC}
 
 
 def handle(P, relax, precision, nrhs_max):
-    mrelax = RELAX[relax]
+    amg = 2 if relax.endswith("+amg") else 0
+    mrelax = RELAX[relax.removesuffix("+amg")]
     disc = mas.MAS_SV if P.disc == "SV" else mas.MAS_TH
-    mp = mas.default_params(P.dim, disc, mrelax, max_coarse=30, precision=precision, nrhs_max=nrhs_max)
+    mp = mas.default_params(P.dim, disc, mrelax, max_coarse=30, precision=precision, nrhs_max=nrhs_max,
+                            dlsc_amg=amg)
     return mas.Handle(P, mp)
 
 

@@ -63,6 +63,13 @@ CASES = {
     "th24_lid_hyb": (dict(dim=2, n=24, jitter=0.2, seed=2, forcing="gaussian", bc="lid"),
                      dict(max_coarse=40, relax="vanka-dlsc")),
     "th3d4_hyb": (dict(dim=3, n=4, forcing="smooth", bc="zero", seed=3), dict(max_coarse=40, relax="vanka-dlsc")),
+    # DLSC continuity and pressure stages by an SA V-cycle with weighted Jacobi (Section 4)
+    "th24_dlsc_amg": (dict(dim=2, n=24, jitter=0.2, seed=2, forcing="gaussian", bc="lid"),
+                      dict(max_coarse=40, relax="dlsc", dlsc_amg=2)),
+    "th3d4_dlsc_amg3": (dict(dim=3, n=4, forcing="smooth", bc="zero", seed=3),
+                        dict(max_coarse=20, relax="dlsc", dlsc_amg=3)),
+    "sv8_lid_hyb_amg": (dict(dim=2, n=8, disc="SV", jitter=0.2, seed=4, forcing="gaussian", bc="lid"),
+                        dict(max_coarse=20, relax="vanka-dlsc", dlsc_amg=2)),
 }
 RELAX = {"vanka": mas.MAS_RELAX_VANKA, "dlsc": mas.MAS_RELAX_DLSC, "vanka-dlsc": mas.MAS_RELAX_VANKA_DLSC}
 SCHED = {"all": mas.MAS_DC_ALL, "skip1": mas.MAS_DC_SKIP1, "skip0": mas.MAS_DC_SKIP0, "ho": mas.MAS_HO_AMG}
@@ -80,7 +87,7 @@ def build(name, precision=mas.MAS_FP64):
     mp = mas.default_params(P.dim, disc, mrelax, theta=par.theta, max_coarse=par.max_coarse,
                             max_levels=par.max_levels, omega0=par.omega0, omega=par.omega,
                             eta_u=par.eta_u, eta_p=par.eta_p, schedule=SCHED[par.schedule],
-                            nu1=par.nu1, nu2=par.nu2, nu_dlsc=par.nu_dlsc,
+                            nu1=par.nu1, nu2=par.nu2, nu_dlsc=par.nu_dlsc, dlsc_amg=par.dlsc_amg,
                             precision=precision, seed=par.seed, krylov_its=par.krylov_its)
     print(f"[case {name}] n0={P.n0} precision={precision}", flush=True)
     return P, par, mp
@@ -138,7 +145,8 @@ def test_full_block_levels_match_oracle(name, monkeypatch):
 @pytest.mark.parametrize("name", ["th16_2lvl", "th24_lid", "th3d4", "th16_skip1", "th24_dlsc", "th3d4_dlsc",
                                   "sv6", "sv8_lid", "th24_lid_kry", "th3d4_kry", "sv8_lid_kry",
                                   "th24_lid_ho", "th3d4_ho", "th24_ho_dlsc", "th24_lid_ho_kry",
-                                  "sv6_hyb", "sv8_lid_hyb", "th24_lid_hyb", "th3d4_hyb"])
+                                  "sv6_hyb", "sv8_lid_hyb", "th24_lid_hyb", "th3d4_hyb",
+                                  "th24_dlsc_amg", "th3d4_dlsc_amg3", "sv8_lid_hyb_amg"])
 def test_solve_fp64_matches_oracle(name):
     P, par, mp = build(name)
     pre = dc.DCPreconditioner(P, par)
@@ -162,7 +170,7 @@ def test_solve_fp64_matches_oracle(name):
 
 
 @pytest.mark.parametrize("name", ["th16_3lvl", "th24_lid", "th3d4", "th24_dlsc", "sv8_lid", "th24_lid_kry",
-                                  "th24_lid_ho", "sv8_lid_hyb"])
+                                  "th24_lid_ho", "sv8_lid_hyb", "th24_dlsc_amg"])
 def test_solve_fp32_cycle_reaches_1e8(name):
     P, par, mp = build(name, precision=mas.MAS_FP32)
     h = mas.Handle(P, mp)
