@@ -43,6 +43,8 @@ def parse():
                     help="DC-all / DC-skip1 / DC-skip0, or HO-AMG (Algorithm 1 applied to K0)")
     ap.add_argument("--krylov-its", type=int, default=0,
                     help="FGMRES-wrapped Vanka relaxation with this many iterations (0: stationary sweeps)")
+    ap.add_argument("--dlsc-amg", type=int, default=0,
+                    help="DLSC continuity/pressure stages by one SA V-cycle with this many Jacobi sweeps (0: Chebyshev)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -81,12 +83,13 @@ def measured_traffic(config, precision, relax, kind):
     return None
 
 
-def cpu_baseline(prob, its_gpu, sample_its, relax="vanka", krylov_its=0, schedule="all"):
+def cpu_baseline(prob, its_gpu, sample_its, relax="vanka", krylov_its=0, schedule="all", dlsc_amg=0):
     """The oracle on the host: setup untimed, then ``sample_its`` FGMRES
     iterations of the same workload (first right-hand side) timed and scaled to
     one full solve."""
     from oracle import dc, fgmres
-    pre = dc.DCPreconditioner(prob, dc.default_params(prob, relax, krylov_its=krylov_its, schedule=schedule))
+    pre = dc.DCPreconditioner(prob, dc.default_params(prob, relax, krylov_its=krylov_its, schedule=schedule,
+                                                          dlsc_amg=dlsc_amg))
     b0 = prob.b if prob.b.ndim == 1 else np.ascontiguousarray(prob.b[:, 0])
     pre.apply(b0)  # untimed: builds the oracle's dense patch matrices once
     t0 = time.perf_counter()
@@ -253,14 +256,15 @@ def main():
     nrhs = prob.nrhs
     if a.krylov_its and (a.relax != "vanka" or nrhs != 1):
         sys.exit("--krylov-its wraps the Vanka relaxation of a single right-hand side")
-    rname = a.relax + (f"+fgmres{a.krylov_its}" if a.krylov_its else "")
+    rname = a.relax + (f"+fgmres{a.krylov_its}" if a.krylov_its else "") + (f"+amg{a.dlsc_amg}" if a.dlsc_amg else "")
     label = rname
     sched = {"all": mas.MAS_DC_ALL, "skip1": mas.MAS_DC_SKIP1, "skip0": mas.MAS_DC_SKIP0, "ho": mas.MAS_HO_AMG}
     method = "HO-AMG" if a.schedule == "ho" else f"DC-{a.schedule}"
     if a.schedule != "all":
         label += f"+{a.schedule}"
     mp = mas.default_params(prob.dim, mas.MAS_SV if prob.disc == "SV" else mas.MAS_TH, relax, precision=prec,
-                            nrhs_max=nrhs, krylov_its=a.krylov_its, schedule=sched[a.schedule])
+                            nrhs_max=nrhs, krylov_its=a.krylov_its, schedule=sched[a.schedule],
+                            dlsc_amg=a.dlsc_amg)
     t0 = time.perf_counter()
     h = mas.Handle(prob, mp)
     torch.cuda.synchronize()
@@ -349,7 +353,8 @@ def main():
                      "share_of_timed_kernels": k_ms / max(1e-12, total_ms)},
     }
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, its_last, a.cpu_sample_its, a.relax, a.krylov_its, a.schedule)
+        out["cpu_baseline"] = cpu_baseline(prob, its_last, a.cpu_sample_its, a.relax, a.krylov_its, a.schedule,
+                                          a.dlsc_amg)
     print(json.dumps(out))
     h.close()
 
