@@ -19,7 +19,7 @@ HIP_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),
 ]
-HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-I", os.path.join(ROOT, "include")]
+HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-pthread", "-I", os.path.join(ROOT, "include")]
 
 
 def _run(cmd):
@@ -40,7 +40,7 @@ def build(verbose: bool = False) -> str:
     _run(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, "host.cpp"), "-o", host_o])
     _run([hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, "mas.hip"), "-o", mas_o])
     tmp = LIB + ".tmp"
-    _run([hipcc, "-shared", "-fPIC", "--offload-arch=gfx950", mas_o, host_o, "-o", tmp])
+    _run([hipcc, "-shared", "-fPIC", "--offload-arch=gfx950", mas_o, host_o, "-pthread", "-o", tmp])
     os.replace(tmp, LIB)
     if verbose:
         print("built", LIB)

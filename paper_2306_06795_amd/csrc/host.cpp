@@ -3,19 +3,46 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <numeric>
 #include <stdexcept>
+#include <thread>
 
 namespace mas {
+
+int setup_threads() {
+  static const int n = [] {
+    int t = (int)std::thread::hardware_concurrency();
+    if (const char* e = std::getenv("MAS_SETUP_THREADS")) t = std::atoi(e);
+    return std::max(1, std::min(t, 16));
+  }();
+  return n;
+}
+
+// f(lo, hi) over [0, n) in contiguous chunks, one per thread
+void parallel_rows(int64_t n, const std::function<void(int64_t, int64_t)>& f) {
+  const int64_t nt = std::min<int64_t>(setup_threads(), std::max<int64_t>(1, n / 4096));
+  if (nt <= 1) {
+    f(0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int64_t t = 0; t < nt; ++t) th.emplace_back(f, n * t / nt, n * (t + 1) / nt);
+  for (auto& x : th) x.join();
+}
 
 Csr csr_copy(int64_t nr, int64_t nc, const int64_t* ptr, const int32_t* ind, const double* val) {
   Csr A;
   A.nr = nr;
   A.nc = nc;
   A.ptr.assign(ptr, ptr + nr + 1);
-  int64_t nnz = A.ptr[nr];
-  A.ind.assign(ind, ind + nnz);
-  A.val.assign(val, val + nnz);
+  const int64_t nnz = A.ptr[nr];
+  A.ind.resize(nnz);
+  A.val.resize(nnz);
+  parallel_rows(nnz, [&](int64_t lo, int64_t hi) {
+    std::copy(ind + lo, ind + hi, A.ind.begin() + lo);
+    std::copy(val + lo, val + hi, A.val.begin() + lo);
+  });
   return A;
 }
 
@@ -26,26 +53,31 @@ Csr submatrix(const Csr& A, const std::vector<int64_t>& rows, const std::vector<
   B.nr = (int64_t)rows.size();
   B.nc = (int64_t)cols.size();
   B.ptr.assign(B.nr + 1, 0);
-  for (int64_t r = 0; r < B.nr; ++r) {
-    int64_t i = rows[r];
-    int64_t c = 0;
-    for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e)
-      if (cmap[A.ind[e]] >= 0) ++c;
-    B.ptr[r + 1] = B.ptr[r] + c;
-  }
+  parallel_rows(B.nr, [&](int64_t lo, int64_t hi) {
+    for (int64_t r = lo; r < hi; ++r) {
+      const int64_t i = rows[r];
+      int64_t c = 0;
+      for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e)
+        if (cmap[A.ind[e]] >= 0) ++c;
+      B.ptr[r + 1] = c;
+    }
+  });
+  for (int64_t r = 0; r < B.nr; ++r) B.ptr[r + 1] += B.ptr[r];
   B.ind.resize(B.ptr[B.nr]);
   B.val.resize(B.ptr[B.nr]);
-  for (int64_t r = 0; r < B.nr; ++r) {
-    int64_t i = rows[r], o = B.ptr[r];
-    for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e) {
-      int64_t j = cmap[A.ind[e]];
-      if (j >= 0) {  // cols ascending -> mapped indices stay sorted
-        B.ind[o] = (int32_t)j;
-        B.val[o] = A.val[e];
-        ++o;
+  parallel_rows(B.nr, [&](int64_t lo, int64_t hi) {
+    for (int64_t r = lo; r < hi; ++r) {
+      int64_t i = rows[r], o = B.ptr[r];
+      for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e) {
+        const int64_t j = cmap[A.ind[e]];
+        if (j >= 0) {  // cols ascending -> mapped indices stay sorted
+          B.ind[o] = (int32_t)j;
+          B.val[o] = A.val[e];
+          ++o;
+        }
       }
     }
-  }
+  });
   return B;
 }
 
@@ -68,56 +100,63 @@ Csr transpose(const Csr& A) {
   return T;
 }
 
+// Rows are independent and each entry is summed in the order of A's row, so the
+// result does not depend on the number of threads.
 Csr spgemm(const Csr& A, const Csr& B) {
   if (A.nc != B.nr) throw std::runtime_error("spgemm: shape mismatch");
   Csr C;
   C.nr = A.nr;
   C.nc = B.nc;
   C.ptr.assign(C.nr + 1, 0);
-  std::vector<int64_t> mark(B.nc, -1);
-  for (int64_t i = 0; i < A.nr; ++i) {
-    int64_t c = 0;
-    for (int64_t a = A.ptr[i]; a < A.ptr[i + 1]; ++a) {
-      int64_t k = A.ind[a];
-      for (int64_t b = B.ptr[k]; b < B.ptr[k + 1]; ++b) {
-        int64_t j = B.ind[b];
-        if (mark[j] != i) {
-          mark[j] = i;
-          ++c;
+  parallel_rows(A.nr, [&](int64_t lo, int64_t hi) {
+    std::vector<int64_t> mark(B.nc, -1);
+    for (int64_t i = lo; i < hi; ++i) {
+      int64_t c = 0;
+      for (int64_t a = A.ptr[i]; a < A.ptr[i + 1]; ++a) {
+        const int64_t k = A.ind[a];
+        for (int64_t b = B.ptr[k]; b < B.ptr[k + 1]; ++b) {
+          const int64_t j = B.ind[b];
+          if (mark[j] != i) {
+            mark[j] = i;
+            ++c;
+          }
         }
       }
+      C.ptr[i + 1] = c;
     }
-    C.ptr[i + 1] = C.ptr[i] + c;
-  }
+  });
+  for (int64_t i = 0; i < C.nr; ++i) C.ptr[i + 1] += C.ptr[i];
   C.ind.resize(C.ptr[C.nr]);
   C.val.resize(C.ptr[C.nr]);
-  std::fill(mark.begin(), mark.end(), -1);
-  std::vector<double> acc(B.nc, 0.0);
-  std::vector<int32_t> cols;
-  for (int64_t i = 0; i < A.nr; ++i) {
-    cols.clear();
-    for (int64_t a = A.ptr[i]; a < A.ptr[i + 1]; ++a) {
-      int64_t k = A.ind[a];
-      double av = A.val[a];
-      for (int64_t b = B.ptr[k]; b < B.ptr[k + 1]; ++b) {
-        int64_t j = B.ind[b];
-        if (mark[j] != i) {
-          mark[j] = i;
-          cols.push_back((int32_t)j);
-          acc[j] = av * B.val[b];
-        } else {
-          acc[j] += av * B.val[b];
+  parallel_rows(A.nr, [&](int64_t lo, int64_t hi) {
+    std::vector<int64_t> mark(B.nc, -1);
+    std::vector<double> acc(B.nc, 0.0);
+    std::vector<int32_t> cols;
+    for (int64_t i = lo; i < hi; ++i) {
+      cols.clear();
+      for (int64_t a = A.ptr[i]; a < A.ptr[i + 1]; ++a) {
+        const int64_t k = A.ind[a];
+        const double av = A.val[a];
+        for (int64_t b = B.ptr[k]; b < B.ptr[k + 1]; ++b) {
+          const int64_t j = B.ind[b];
+          if (mark[j] != i) {
+            mark[j] = i;
+            cols.push_back((int32_t)j);
+            acc[j] = av * B.val[b];
+          } else {
+            acc[j] += av * B.val[b];
+          }
         }
       }
+      std::sort(cols.begin(), cols.end());
+      int64_t o = C.ptr[i];
+      for (int32_t j : cols) {
+        C.ind[o] = j;
+        C.val[o] = acc[j];
+        ++o;
+      }
     }
-    std::sort(cols.begin(), cols.end());
-    int64_t o = C.ptr[i];
-    for (int32_t j : cols) {
-      C.ind[o] = j;
-      C.val[o] = acc[j];
-      ++o;
-    }
-  }
+  });
   return C;
 }
 

@@ -4,16 +4,39 @@
 #pragma once
 #include <cstdint>
 #include <functional>
+#include <memory>
 #include <string>
+#include <utility>
 #include <vector>
 
 namespace mas {
 
+// Allocator whose value-less construct leaves the element uninitialised: large
+// products are sized first and filled by several threads, which then also do
+// the first touch of their pages.
+template <class T>
+struct NoInit : std::allocator<T> {
+  template <class U>
+  struct rebind {
+    using other = NoInit<U>;
+  };
+  NoInit() = default;
+  template <class U>
+  NoInit(const NoInit<U>&) {}
+  template <class U, class... A>
+  void construct(U* p, A&&... a) {
+    if constexpr (sizeof...(A) == 0)
+      ::new ((void*)p) U;
+    else
+      ::new ((void*)p) U(std::forward<A>(a)...);
+  }
+};
+
 struct Csr {
   int64_t nr = 0, nc = 0;
   std::vector<int64_t> ptr;  // nr + 1
-  std::vector<int32_t> ind;  // sorted within each row
-  std::vector<double> val;
+  std::vector<int32_t, NoInit<int32_t>> ind;  // sorted within each row
+  std::vector<double, NoInit<double>> val;
   int64_t nnz() const { return ptr.empty() ? 0 : ptr[nr]; }
 };
 
@@ -26,6 +49,10 @@ Csr csr_copy(int64_t nr, int64_t nc, const int64_t* ptr, const int32_t* ind, con
 // rows/cols: kept indices (ascending); structure of A restricted to them, explicit zeros kept
 Csr submatrix(const Csr& A, const std::vector<int64_t>& rows, const std::vector<int64_t>& cols);
 Csr transpose(const Csr& A);
+// threads of the host setup: hardware threads, or MAS_SETUP_THREADS, at most 16
+int setup_threads();
+// f(lo, hi) over [0, n) in contiguous ascending chunks, one per thread
+void parallel_rows(int64_t n, const std::function<void(int64_t, int64_t)>& f);
 // C = A B with the structural pattern of the product (no entry dropped)
 Csr spgemm(const Csr& A, const Csr& B);
 Csr galerkin(const Csr& P, const Csr& A);  // P^T A P

@@ -3,6 +3,8 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
+#include <chrono>
 #include <map>
 #include <cmath>
 #include <cstdio>
@@ -86,8 +88,8 @@ struct DevArena {
     bytes += n * sizeof(T);
     return (T*)p;
   }
-  template <typename T, typename S>
-  T* upload(const std::vector<S>& v, hipStream_t s) {
+  template <typename T, typename S, typename Al>
+  T* upload(const std::vector<S, Al>& v, hipStream_t s) {
     std::vector<T> tmp(v.begin(), v.end());
     T* d = alloc<T>(tmp.size());
     if (!tmp.empty()) {
@@ -870,7 +872,6 @@ struct mas_handle {
   DCsr<double> K0full;
   std::unique_ptr<CycleBase> cyc;
   mas_hier_info info{};
-  std::vector<Csr> host_levels;  // free level operators (for export)
   int32_t p_nullspace = 0;
   double* pw = nullptr;  // pressure weights (np0)
   double pw_sum = 0.0;
@@ -892,18 +893,46 @@ namespace {
 Csr get_csr(const mas_csr& c, const char* name) {
   if (!c.indptr || !c.indices || !c.data || c.nrows <= 0 || c.ncols <= 0)
     throw MasError(MAS_EINVAL, std::string("missing matrix ") + name);
+  if (c.indptr[0] != 0) throw MasError(MAS_EINVAL, std::string(name) + ": bad indptr");
+  for (int64_t i = 0; i < c.nrows; ++i)
+    if (c.indptr[i + 1] < c.indptr[i]) throw MasError(MAS_EINVAL, std::string(name) + ": bad indptr");
   Csr A = csr_copy(c.nrows, c.ncols, c.indptr, c.indices, c.data);
-  for (int64_t i = 0; i < A.nr; ++i) {
-    if (A.ptr[i + 1] < A.ptr[i]) throw MasError(MAS_EINVAL, std::string(name) + ": bad indptr");
-    for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e) {
-      if (A.ind[e] < 0 || A.ind[e] >= A.nc) throw MasError(MAS_EINVAL, std::string(name) + ": column out of range");
-      if (e > A.ptr[i] && A.ind[e] <= A.ind[e - 1])
-        throw MasError(MAS_EINVAL, std::string(name) + ": columns not sorted/unique");
-      if (!std::isfinite(A.val[e])) throw MasError(MAS_EINVAL, std::string(name) + ": non-finite value");
-    }
-  }
+  // row checks in parallel; the first failing row (in row order) names the error
+  const int nt = setup_threads();
+  std::vector<std::pair<int64_t, std::string>> bad(nt + 1, {INT64_MAX, std::string()});
+  std::atomic<int> slot{0};
+  parallel_rows(A.nr, [&](int64_t lo, int64_t hi) {
+    auto& mine = bad[std::min(slot.fetch_add(1), nt)];
+    for (int64_t i = lo; i < hi && mine.first == INT64_MAX; ++i)
+      for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e) {
+        const char* why = nullptr;
+        if (A.ind[e] < 0 || A.ind[e] >= A.nc) why = ": column out of range";
+        else if (e > A.ptr[i] && A.ind[e] <= A.ind[e - 1]) why = ": columns not sorted/unique";
+        else if (!std::isfinite(A.val[e])) why = ": non-finite value";
+        if (why) {
+          mine = {i, std::string(name) + why};
+          break;
+        }
+      }
+  });
+  const auto first = std::min_element(bad.begin(), bad.end(),
+                                      [](const auto& a, const auto& b) { return a.first < b.first; });
+  if (first->first != INT64_MAX) throw MasError(MAS_EINVAL, first->second);
   return A;
 }
+
+// Phase timings of the setup on stderr when MAS_TRACE_SETUP is set.
+struct SetupTrace {
+  bool on = std::getenv("MAS_TRACE_SETUP") != nullptr;
+  std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+  void mark(const char* what) {
+    if (!on) return;
+    const auto now = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "[mas setup] %-28s %9.1f ms\n", what,
+                 std::chrono::duration<double, std::milli>(now - t).count());
+    t = now;
+  }
+};
 
 // dense inverse of an n x n FP64 matrix on the device (Gauss-Jordan, partial pivoting)
 void dense_inverse(DevArena& ar, double* A, int n, hipStream_t s) {
@@ -1151,6 +1180,7 @@ std::unique_ptr<Cycle<T>> build_cycle(mas_handle* h, const std::vector<Csr>& Ks,
                                       const Csr& Kc_bordered, const std::vector<int64_t>& free0,
                                       const std::vector<int64_t>& dir0, hipStream_t s) {
   DevArena& ar = h->arena;
+  SetupTrace tr;
   auto cyc = std::make_unique<Cycle<T>>();
   cyc->par = h->par;
   cyc->dim = h->dim;
@@ -1219,6 +1249,8 @@ std::unique_ptr<Cycle<T>> build_cycle(mas_handle* h, const std::vector<Csr>& Ks,
       }
     }
   }
+  if (tr.on) HIPCHECK(hipStreamSynchronize(s));
+  tr.mark("device: levels, factorisation");
   // relaxation wrapper (Section 3.3.1): every Vanka level except the Scott-Vogelius K0
   if (h->par.krylov_its > 0) {
     const int m = h->par.krylov_its;
@@ -1260,6 +1292,8 @@ std::unique_ptr<Cycle<T>> build_cycle(mas_handle* h, const std::vector<Csr>& Ks,
       autotune_team<T>(L.P, C.x, L.x, s);
     }
   }
+  if (tr.on) HIPCHECK(hipStreamSynchronize(s));
+  tr.mark("device: product autotune");
   // coarsest: dense inverse of the bordered operator
   const int64_t nb = Kc_bordered.nr;
   std::vector<double> dense((size_t)nb * nb, 0.0);
@@ -1267,6 +1301,7 @@ std::unique_ptr<Cycle<T>> build_cycle(mas_handle* h, const std::vector<Csr>& Ks,
     for (int64_t e = Kc_bordered.ptr[i]; e < Kc_bordered.ptr[i + 1]; ++e) dense[i * nb + Kc_bordered.ind[e]] = Kc_bordered.val[e];
   cyc->Cinv = ar.upload<double>(dense, s);
   dense_inverse(ar, cyc->Cinv, (int)nb, s);
+  tr.mark("device: coarsest inverse");
   cyc->ld = nb;
   cyc->nc_dense = nb;
   cyc->free0 = ar.upload<int64_t>(free0, s);
@@ -1341,6 +1376,7 @@ void s_hierarchy(HostDlsc& D, const mas_params& par, bool singular) {
 }
 
 void analyze_impl(mas_handle* h, const mas_problem* pr) {
+  SetupTrace tr;
   const int d = pr->dim;
   if (d != 2 && d != 3) throw MasError(MAS_EINVAL, "dim must be 2 or 3");
   if (pr->disc != MAS_TH && pr->disc != MAS_SV) throw MasError(MAS_EINVAL, "unknown discretisation");
@@ -1402,6 +1438,7 @@ void analyze_impl(mas_handle* h, const mas_problem* pr) {
   h->nu0 = nu0;
   Csr K0f = submatrix(K0, free0, free0);
   Csr K1f = submatrix(K1, free1, free1);
+  tr.mark("validation, free blocks");
   // the two velocity spaces share their nodes (Section 3.1)
   int64_t nv0 = 0, nv1 = 0;
   for (auto f : f0) nv0 += (f < d);
@@ -1421,8 +1458,11 @@ void analyze_impl(mas_handle* h, const mas_problem* pr) {
     sa_field(Af, par.theta, par.max_coarse, par.max_levels, fP[f], fB[f]);
     lmax = std::min(lmax, fP[f].size() + 1);
   }
+  tr.mark("smoothed aggregation");
   // levels: 0 = K0f, 1 = K1f, 2.. = Galerkin
-  std::vector<Csr> Ks{K0f, K1f};
+  std::vector<Csr> Ks;
+  Ks.push_back(std::move(K0f));
+  Ks.push_back(std::move(K1f));
   std::vector<Csr> Ps{Csr(), Csr()};
   std::vector<std::vector<int8_t>> fields{f0, f1};
   for (size_t l = 0; l + 1 < lmax; ++l) {
@@ -1438,6 +1478,7 @@ void analyze_impl(mas_handle* h, const mas_problem* pr) {
     fields.push_back(std::move(fc));
   }
   const size_t nl = Ks.size();  // includes the coarsest
+  tr.mark("Galerkin products");
   if (nl > 16) throw MasError(MAS_EINVAL, "too many levels");
   // relaxation schedule (Section 4): index 0 = K0, 1 = K1, ...
   std::vector<bool> relax(nl, true);
@@ -1492,6 +1533,7 @@ void analyze_impl(mas_handle* h, const mas_problem* pr) {
     D.lamS = lanczos_max(D.S, par.seed + 2 * l + 1, 20);
     if (par.dlsc_amg > 0) s_hierarchy(D, par, pr->p_nullspace != 0);
   }
+  tr.mark("patches / DLSC operators");
   // coarsest operator, bordered with the coarse pressure null vector
   const Csr& KL = Ks.back();
   Csr Kb = KL;
@@ -1582,7 +1624,6 @@ void analyze_impl(mas_handle* h, const mas_problem* pr) {
     in.p_nnz[l] = (l >= 2) ? Ps[l - 1].nnz() : 0;
   }
   in.coarse_n = Kb.nr;
-  h->host_levels = Ks;
   pl.Ks = std::move(Ks);
   pl.Ps = std::move(Ps);
   pl.fields = std::move(fields);
@@ -2234,11 +2275,11 @@ int mas_scale_rows(mas_handle* h, double* x, int32_t nrhs, const double* s_u, co
 
 int mas_export_level(const mas_handle* h, int32_t level, int64_t* nrows, int64_t* nnz, int64_t* indptr,
                      int32_t* indices, double* data) {
-  if (!h || level < 0 || level >= (int32_t)h->host_levels.size()) {
+  if (!h || level < 0 || level >= (int32_t)h->plan.Ks.size()) {
     g_last_error = "bad level";
     return MAS_EINVAL;
   }
-  const Csr& A = h->host_levels[level];
+  const Csr& A = h->plan.Ks[level];
   if (nrows) *nrows = A.nr;
   if (nnz) *nnz = A.nnz();
   if (indptr) std::memcpy(indptr, A.ptr.data(), (A.nr + 1) * sizeof(int64_t));
