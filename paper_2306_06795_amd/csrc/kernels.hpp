@@ -1284,4 +1284,85 @@ __global__ void k_update_x(int64_t n, int k, const T* __restrict__ Z, const doub
   x[i] = (T)s;
 }
 
+// ---------------------------------------------------------------------------
+// Sparse product C = A B for the Galerkin operators of the setup (Algorithm 1),
+// one row of C per 64-thread workgroup.  The entries of A's row are taken in
+// order; for each, the lanes add a_ik b_kj into an LDS hash table keyed by j
+// (the columns of one row of B are distinct, so no two lanes touch one entry in
+// a step).  Every c_ij is therefore summed in the order of A's row, with the
+// products and the sums rounded separately, as the host product does: the two
+// give the same bits.  PASS 0 counts the distinct columns of each row into cnt;
+// PASS 1 writes them, sorted, from Cp[i].  A row with more than `cap` distinct
+// columns (cap <= kSpgSlots * 3 / 4) gets over[i] = 1 in PASS 0 and is left to
+// the host.
+constexpr int kSpgSlots = 2048;
+
+template <int PASS>
+__global__ void __launch_bounds__(64) k_spgemm_row(int64_t n, const int64_t* __restrict__ Ap,
+                                                   const int* __restrict__ Ai, const double* __restrict__ Av,
+                                                   const int64_t* __restrict__ Bp, const int* __restrict__ Bi,
+                                                   const double* __restrict__ Bv, int cap, int64_t* __restrict__ cnt,
+                                                   int* __restrict__ over, const int64_t* __restrict__ Cp,
+                                                   int* __restrict__ Ci, double* __restrict__ Cv) {
+#pragma clang fp contract(off)
+  __shared__ int key[kSpgSlots];
+  __shared__ double val[kSpgSlots];
+  __shared__ int nkeys, full;
+  const int64_t i = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (i >= n) return;  // uniform over the workgroup
+  if (PASS == 1 && over[i]) return;
+  for (int t = lane; t < kSpgSlots; t += 64) key[t] = -1;
+  if (lane == 0) {
+    nkeys = 0;
+    full = 0;
+  }
+  __syncthreads();
+  for (int64_t a = Ap[i]; a < Ap[i + 1]; ++a) {
+    const int k = Ai[a];
+    const double av = Av[a];
+    for (int64_t b = Bp[k] + lane; b < Bp[k + 1]; b += 64) {
+      const int j = Bi[b];
+      const double pr = av * Bv[b];
+      unsigned h = ((unsigned)j * 2654435761u) >> 21;  // top 11 bits: a slot in [0, 2048)
+      for (int probe = 0; probe < kSpgSlots; ++probe, h = (h + 1) & (kSpgSlots - 1)) {
+        const int old = atomicCAS(&key[h], -1, j);
+        if (old == -1) {  // new column
+          val[h] = pr;
+          if (atomicAdd(&nkeys, 1) >= cap) full = 1;
+          break;
+        }
+        if (old == j) {
+          val[h] = val[h] + pr;
+          break;
+        }
+      }
+    }
+    __syncthreads();
+    if (full) break;  // uniform: read after the barrier
+  }
+  if (PASS == 0) {
+    if (lane == 0) {
+      cnt[i] = full ? 0 : nkeys;
+      over[i] = full ? 1 : 0;
+    }
+    return;
+  }
+  // PASS 1: rank of each column among the row's columns gives its position
+  const int64_t base = Cp[i], m = Cp[i + 1] - Cp[i];
+  for (int t = lane; t < kSpgSlots; t += 64) {
+    const int j = key[t];
+    if (j < 0) continue;
+    int r = 0;
+    for (int u = 0; u < kSpgSlots; ++u) {
+      const int q = key[u];
+      r += (q >= 0 && q < j) ? 1 : 0;
+    }
+    if (r < m) {
+      Ci[base + r] = j;
+      Cv[base + r] = val[t];
+    }
+  }
+}
+
 }  // namespace mas

@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <numeric>
 #include <stdexcept>
 #include <string>
 #include <type_traits>
@@ -90,9 +91,13 @@ struct DevArena {
   }
   template <typename T, typename S, typename Al>
   T* upload(const std::vector<S, Al>& v, hipStream_t s) {
-    std::vector<T> tmp(v.begin(), v.end());
-    T* d = alloc<T>(tmp.size());
-    if (!tmp.empty()) {
+    T* d = alloc<T>(v.size());
+    if (v.empty()) return d;
+    if constexpr (std::is_same<T, S>::value) {
+      HIPCHECK(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+      HIPCHECK(hipStreamSynchronize(s));
+    } else {
+      std::vector<T> tmp(v.begin(), v.end());
       HIPCHECK(hipMemcpyAsync(d, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice, s));
       HIPCHECK(hipStreamSynchronize(s));
     }
@@ -934,6 +939,74 @@ struct SetupTrace {
   }
 };
 
+// C = A B on the device (k_spgemm_row): the same pattern and the same bits as
+// the host product.  Rows whose distinct columns overflow the kernel's LDS
+// table are computed on the host.  Host matrices in and out; the device
+// buffers live only for the call.
+Csr device_spgemm(const Csr& A, const Csr& B, hipStream_t s) {
+  if (A.nc != B.nr) throw MasError(MAS_EINVAL, "spgemm: shape mismatch");
+  if (A.nr == 0) return spgemm(A, B);
+  DevArena ar;
+  const int64_t n = A.nr;
+  const int64_t* Ap = ar.upload<int64_t>(A.ptr, s);
+  const int* Ai = ar.upload<int>(A.ind, s);
+  const double* Av = ar.upload<double>(A.val, s);
+  const int64_t* Bp = ar.upload<int64_t>(B.ptr, s);
+  const int* Bi = ar.upload<int>(B.ind, s);
+  const double* Bv = ar.upload<double>(B.val, s);
+  int64_t* cnt = ar.alloc<int64_t>(n);
+  int* over = ar.alloc<int>(n);
+  int cap = kSpgSlots * 3 / 4;
+  if (const char* e = std::getenv("MAS_SPGEMM_CAP")) cap = std::max(1, std::min(cap, std::atoi(e)));
+  hipLaunchKernelGGL(k_spgemm_row<0>, dim3((unsigned)n), dim3(64), 0, s, n, Ap, Ai, Av, Bp, Bi, Bv, cap, cnt, over,
+                     nullptr, nullptr, nullptr);
+  launch_check();
+  std::vector<int64_t> hc(n);
+  std::vector<int> ho(n);
+  HIPCHECK(hipMemcpyAsync(hc.data(), cnt, n * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipMemcpyAsync(ho.data(), over, n * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  // rows left to the host
+  std::vector<int64_t> rows;
+  for (int64_t i = 0; i < n; ++i)
+    if (ho[i]) rows.push_back(i);
+  Csr H;
+  if (!rows.empty()) {
+    std::vector<int64_t> all(A.nc);
+    std::iota(all.begin(), all.end(), 0);
+    H = spgemm(submatrix(A, rows, all), B);
+    for (size_t q = 0; q < rows.size(); ++q) hc[rows[q]] = H.ptr[q + 1] - H.ptr[q];
+  }
+  Csr C;
+  C.nr = n;
+  C.nc = B.nc;
+  C.ptr.assign(n + 1, 0);
+  for (int64_t i = 0; i < n; ++i) C.ptr[i + 1] = C.ptr[i] + hc[i];
+  const int64_t nnz = C.ptr[n];
+  if (nnz >= (int64_t)INT32_MAX) throw MasError(MAS_EINVAL, "Galerkin product too large for 32-bit offsets");
+  C.ind.resize(nnz);
+  C.val.resize(nnz);
+  const int64_t* Cp = ar.upload<int64_t>(C.ptr, s);
+  int* Ci = ar.alloc<int>(nnz);
+  double* Cv = ar.alloc<double>(nnz);
+  hipLaunchKernelGGL(k_spgemm_row<1>, dim3((unsigned)n), dim3(64), 0, s, n, Ap, Ai, Av, Bp, Bi, Bv, cap, cnt, over,
+                     Cp, Ci, Cv);
+  launch_check();
+  HIPCHECK(hipMemcpyAsync(C.ind.data(), Ci, nnz * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipMemcpyAsync(C.val.data(), Cv, nnz * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  for (size_t q = 0; q < rows.size(); ++q) {
+    const int64_t i = rows[q];
+    std::copy(H.ind.begin() + H.ptr[q], H.ind.begin() + H.ptr[q + 1], C.ind.begin() + C.ptr[i]);
+    std::copy(H.val.begin() + H.ptr[q], H.val.begin() + H.ptr[q + 1], C.val.begin() + C.ptr[i]);
+  }
+  return C;
+}
+
+Csr device_galerkin(const Csr& P, const Csr& A, hipStream_t s) {
+  return device_spgemm(transpose(P), device_spgemm(A, P, s), s);
+}
+
 // dense inverse of an n x n FP64 matrix on the device (Gauss-Jordan, partial pivoting)
 void dense_inverse(DevArena& ar, double* A, int n, hipStream_t s) {
   double* rowk = ar.alloc<double>(n);
@@ -1375,8 +1448,13 @@ void s_hierarchy(HostDlsc& D, const mas_params& par, bool singular) {
   }
 }
 
-void analyze_impl(mas_handle* h, const mas_problem* pr) {
+// dev: a device may be used; with MAS_DEVICE_GALERKIN set, the Galerkin
+// products of the level operators then run on it (stream s), with the same
+// result as the host's, bit for bit.  Off by default: with the CSR arrays
+// moved through pageable host memory, the threaded host product is faster.
+void analyze_impl(mas_handle* h, const mas_problem* pr, bool dev = false, hipStream_t s = nullptr) {
   SetupTrace tr;
+  dev = dev && std::getenv("MAS_DEVICE_GALERKIN") != nullptr;
   const int d = pr->dim;
   if (d != 2 && d != 3) throw MasError(MAS_EINVAL, "dim must be 2 or 3");
   if (pr->disc != MAS_TH && pr->disc != MAS_SV) throw MasError(MAS_EINVAL, "unknown discretisation");
@@ -1469,7 +1547,7 @@ void analyze_impl(mas_handle* h, const mas_problem* pr) {
     std::vector<const Csr*> bl;
     for (int f = 0; f <= d; ++f) bl.push_back(&fP[f][l]);
     Csr P = block_diag(bl);
-    Csr Kc = galerkin(P, Ks.back());
+    Csr Kc = dev ? device_galerkin(P, Ks.back(), s) : galerkin(P, Ks.back());
     std::vector<int8_t> fc;
     for (int f = 0; f <= d; ++f) fc.insert(fc.end(), (size_t)fP[f][l].nc, (int8_t)f);
     Ps.back() = P;  // P of the finer level
@@ -1478,7 +1556,7 @@ void analyze_impl(mas_handle* h, const mas_problem* pr) {
     fields.push_back(std::move(fc));
   }
   const size_t nl = Ks.size();  // includes the coarsest
-  tr.mark("Galerkin products");
+  tr.mark(dev ? "Galerkin products (device)" : "Galerkin products");
   if (nl > 16) throw MasError(MAS_EINVAL, "too many levels");
   // relaxation schedule (Section 4): index 0 = K0, 1 = K1, ...
   std::vector<bool> relax(nl, true);
@@ -2108,7 +2186,7 @@ int mas_setup(const mas_problem* prob, const mas_params* par, void* stream, mas_
   auto h = std::make_unique<mas_handle>();
   h->par = *par;
   try {
-    analyze_impl(h.get(), prob);
+    analyze_impl(h.get(), prob, true, (hipStream_t)stream);
     upload_impl(h.get(), (hipStream_t)stream);
   } catch (const MasError& e) {
     release_device(h.get());
