@@ -83,6 +83,23 @@ def measured_traffic(config, precision, relax, kind):
     return None
 
 
+def stream_copy_gbs(torch, dev, mib=1024, reps=10):
+    """Device-to-device copy bandwidth (read + write bytes per second, GB/s)."""
+    src = torch.ones(mib << 18, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record(st)
+    torch.cuda.synchronize()
+    gbs = 2.0 * (mib << 20) * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    return gbs
+
+
 def cpu_baseline(prob, its_gpu, sample_its, relax="vanka", krylov_its=0, schedule="all", dlsc_amg=0):
     """The oracle on the host: setup untimed, then ``sample_its`` FGMRES
     iterations of the same workload (first right-hand side) timed and scaled to
@@ -298,13 +315,20 @@ def main():
     z = torch.empty_like(r)
     h.apply(r, z, nrhs=nrhs)
     st = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(st)
-    for _ in range(nrep):
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(nrep + 1)]
+    ev[0].record(st)
+    for k in range(nrep):
         h.apply(r, z, nrhs=nrhs)
-    e1.record(st)
+        ev[k + 1].record(st)
     torch.cuda.synchronize()
-    vcycle_ms = e0.elapsed_time(e1) / nrep
+    per = sorted(ev[k].elapsed_time(ev[k + 1]) for k in range(nrep))
+    vcycle_ms = ev[0].elapsed_time(ev[nrep]) / nrep
+    # algorithmic bytes of one cycle: its timed patch kernels and sparse products
+    h.set_timing(True)
+    h.apply(r, z, nrhs=nrhs)
+    cyc_bytes = sum(v[2] for v in h.timing().values())
+    h.set_timing(False)
+    copy_gbs = stream_copy_gbs(torch, dev)
     h.set_timing(True)
     h.solve(b, x, rtol=a.rtol, nrhs=nrhs)
     tm = h.timing()
@@ -344,10 +368,15 @@ def main():
         "iters": iters[-1],
         "true_relres": relres,
         "vcycle_ms": vcycle_ms,
+        "vcycle": {"mean_ms": vcycle_ms, "median_ms": per[nrep // 2], "min_ms": per[0], "applies": nrep,
+                   "algorithmic_bytes": cyc_bytes,
+                   "hbm_frac": cyc_bytes / (per[nrep // 2] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                   "copy_frac": cyc_bytes / (per[nrep // 2] * 1e-3) / 1e9 / copy_gbs},
         "setup_s": t_setup,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(a.config, a.precision, label, kind),
+                     "measured_copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
                      "kernel": kernel, "avg_launch_ms": avg_launch_ms,
                      "algorithmic_bytes_per_launch": avg_bytes, "launches_timed": k_launches,
                      "share_of_timed_kernels": k_ms / max(1e-12, total_ms)},

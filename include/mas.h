@@ -215,7 +215,8 @@ int mas_export_level(const mas_handle* h, int32_t level, int64_t* nrows, int64_t
                      int64_t* indptr, int32_t* indices, double* data);
 
 /* Event timing of the cycle's kernel launches during mas_solve / mas_apply
- * (for measurement; it disables graph replay while on).  mas_get_timing fills
+ * (for measurement; while on, graph replay is off and both calls synchronise
+ * their stream before returning).  mas_get_timing fills
  * up to n (at most 18) values, three per kernel kind k: out[3k] summed time
  * (ms), out[3k+1] launches, out[3k+2] their summed algorithmic bytes.  Kinds:
  * 0 thread-per-patch bucket kernel, 1 wavefront-per-patch kernel, 2 batched

@@ -2245,6 +2245,10 @@ int mas_apply(mas_handle* h, const double* r, double* z, int32_t nrhs, void* str
     h->cyc->set_nr(nrhs);
     h->cyc->apply(r, z, s);
     h->cyc->set_nr(1);
+    if (h->tm.on) {  // the timed launches of this application, for mas_get_timing
+      HIPCHECK(hipStreamSynchronize(s));
+      h->tm.collect();
+    }
   } catch (const MasError& e) {
     h->cyc->set_nr(1);
     return fail(e);
