@@ -871,8 +871,14 @@ __global__ void k_vanka_pull_ell(int n, int width, const int* __restrict__ pos, 
 }
 
 // ---------------------------------------------------------------------------
-// FP64 block factorisation of every patch (setup).  One wavefront per patch.
+// FP64 block factorisation of every patch (setup).  One workgroup per patch.
 // W: work area of max_nc^2 + 2 * max_nv * MAX_NS doubles (LDS or global).
+// use_lds: 1 = W in LDS; 0 = W in global memory; 2 = W in global memory and
+// the Gauss-Jordan inversion blocked by kGjBlock pivots, whose pivot-block
+// inverse, pivot rows and pivot columns are staged in LDS (dynamic LDS of
+// (kGjBlock^2 + 2 kGjBlock max_nc) doubles): the block is read and written
+// once per kGjBlock pivots instead of once per pivot.
+constexpr int kGjBlock = 16;
 __device__ __forceinline__ int find_sorted(const int* a, int n, int key) {
   int lo = 0, hi = n - 1;
   while (lo <= hi) {
@@ -896,7 +902,7 @@ __global__ void __launch_bounds__(TPB) k_vanka_factor(int64_t np, const int64_t*
                                                       int64_t* __restrict__ bad, int full) {
   extern __shared__ double smem_d[];
   for (int64_t p = blockIdx.x; p < np; p += gridDim.x) {
-    double* W = use_lds ? smem_d : gwork + (int64_t)blockIdx.x * work_stride;
+    double* W = use_lds == 1 ? smem_d : gwork + (int64_t)blockIdx.x * work_stride;
     double* Bm = W + (work_stride - 2 * (int64_t)max_nv * MAX_NS);  // ns x nv
     double* U = Bm + (int64_t)max_nv * MAX_NS;                      // nv x ns (row k: U[k*ns+s])
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
@@ -939,7 +945,73 @@ __global__ void __launch_bounds__(TPB) k_vanka_factor(int64_t np, const int64_t*
       // writes the pivot column.
       double scale = 0.0;
       for (int i = 0; i < n; ++i) scale = fmax(scale, fabs(W[(int64_t)i * n + i]));
-      for (int k = 0; k < n; ++k) {
+      if (use_lds == 2) {
+        // Blocked Gauss-Jordan: with K the next b pivots, W = [A11 A12; A21 A22]
+        // becomes [A11^-1, A11^-1 A12; -A21 A11^-1, A22 - A21 A11^-1 A12],
+        // the same as b single-pivot steps.
+        constexpr int BS = kGjBlock;
+        double* Pk = smem_d;         // b x b pivot block, then its inverse
+        double* RB = Pk + BS * BS;   // b x n: A11^-1 [A11 A12] rows (A11^-1 inside K)
+        double* CB = RB + BS * n;    // n x b: the old pivot columns
+        for (int kb = 0; kb < n; kb += BS) {
+          const int b = min(BS, n - kb);
+          if (tid < b * b) Pk[tid] = W[(int64_t)(kb + tid / b) * n + kb + tid % b];
+          __syncthreads();
+          for (int k = 0; k < b; ++k) {  // single-pivot steps on the b x b block: read, then write
+            const double akk = Pk[k * b + k];
+            const double dk = 1.0 / akk;
+            double v = 0.0;
+            if (tid < b * b) {
+              const int i = tid / b, j = tid % b;
+              const double pik = Pk[i * b + k], pkj = Pk[k * b + j];
+              if (i == k) v = (j == k) ? dk : pkj * dk;
+              else v = (j == k) ? -pik * dk : Pk[tid] - pik * (pkj * dk);
+            }
+            if (tid == 0 && !(akk > piv_tol * scale)) atomicMin((unsigned long long*)bad, (unsigned long long)p);
+            __syncthreads();
+            if (tid < b * b) Pk[tid] = v;
+            __syncthreads();
+          }
+          for (int64_t q = tid; q < (int64_t)b * n; q += TPB) {
+            const int t = (int)(q / n), j = (int)(q % n);
+            double v = 0.0;
+            if (j >= kb && j < kb + b) {
+              v = Pk[t * b + (j - kb)];
+            } else {
+              for (int u = 0; u < b; ++u) v += Pk[t * b + u] * W[(int64_t)(kb + u) * n + j];
+            }
+            RB[q] = v;
+          }
+          for (int64_t q = tid; q < (int64_t)n * b; q += TPB) CB[q] = W[(q / b) * n + kb + q % b];
+          __syncthreads();
+          for (int i = wv; i < n; i += NW) {
+            double ci[BS];
+#pragma unroll
+            for (int u = 0; u < BS; ++u) ci[u] = u < b ? CB[(int64_t)i * b + u] : 0.0;
+            const bool in_k = i >= kb && i < kb + b;
+            double* wi = W + (int64_t)i * n;
+            for (int j = lane; j < n; j += WAVE) {
+              double v;
+              if (in_k) {
+                v = RB[(int64_t)(i - kb) * n + j];
+              } else if (j >= kb && j < kb + b) {
+                v = 0.0;
+#pragma unroll
+                for (int u = 0; u < BS; ++u)
+                  if (u < b) v -= ci[u] * Pk[u * b + (j - kb)];
+              } else {
+                v = wi[j];
+#pragma unroll
+                for (int u = 0; u < BS; ++u)
+                  if (u < b) v -= ci[u] * RB[(int64_t)u * n + j];
+              }
+              wi[j] = v;
+            }
+          }
+          __syncthreads();
+        }
+      }
+      for (int k = 0; k < (use_lds == 2 ? 0 : n); ++k) {
         const double akk = W[(int64_t)k * n + k];
         if (!(akk > piv_tol * scale)) {
           if (tid == 0) atomicMin((unsigned long long*)bad, (unsigned long long)p);

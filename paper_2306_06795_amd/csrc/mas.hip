@@ -1230,10 +1230,17 @@ void build_patches(DevArena& ar, Level<T>& L, const PatchSet& ps, const DCsr<dou
     hipLaunchKernelGGL((k_vanka_factor<T, 256>), dim3(grid), dim3(256), lds_bytes, s, np, d.off, d.dims, d.foff,
                        d.fstride, d.dofs, K64.ptr, K64.ind, K64.val, d.fac, gwork, stride, 1, max_nv, 1e-14, bad,
                        d.full);
-  else
-    hipLaunchKernelGGL((k_vanka_factor<T, 1024>), dim3(grid), dim3(1024), 0, s, np, d.off, d.dims, d.foff,
-                       d.fstride, d.dofs, K64.ptr, K64.ind, K64.val, d.fac, gwork, stride, 0, max_nv, 1e-14, bad,
-                       d.full);
+  else {
+    // blocks in global memory: blocked Gauss-Jordan with LDS panels when they fit
+    const size_t panel = (size_t)(kGjBlock * kGjBlock + 2 * kGjBlock * max_nc) * sizeof(double);
+    int dev = 0, max_lds = 0;
+    HIPCHECK(hipGetDevice(&dev));
+    HIPCHECK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const bool blocked = panel <= (size_t)max_lds && std::getenv("MAS_FACTOR_UNBLOCKED") == nullptr;
+    hipLaunchKernelGGL((k_vanka_factor<T, 1024>), dim3(grid), dim3(1024), blocked ? panel : 0, s, np, d.off, d.dims,
+                       d.foff, d.fstride, d.dofs, K64.ptr, K64.ind, K64.val, d.fac, gwork, stride, blocked ? 2 : 0,
+                       max_nv, 1e-14, bad, d.full);
+  }
   launch_check();
   int64_t hbad = 0;
   HIPCHECK(hipMemcpyAsync(&hbad, bad, sizeof(int64_t), hipMemcpyDeviceToHost, s));
