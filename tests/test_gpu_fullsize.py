@@ -1,0 +1,113 @@
+"""The benchmark workloads at full size, in the configuration bench.py times
+(default parameters of each workload): one FP64 cycle application of the
+256x256 Taylor-Hood cavity against the oracle, element by element; and, for
+every workload, properties that hold at any size -- the true residual of the
+solve computed on the host, the zero-mean pressure, FP32 against FP64 cycles,
+and batched right-hand sides against the same columns solved alone."""
+import time
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import dc  # noqa: E402
+from paper_2306_06795_amd import mas  # noqa: E402
+from paper_2306_06795_amd.inputs import make_config  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def params(P, **over):
+    disc = mas.MAS_SV if P.disc == "SV" else mas.MAS_TH
+    return mas.default_params(P.dim, disc, **over)
+
+
+def true_res(P, x, b):
+    return np.linalg.norm(b - P.K0 @ x) / np.linalg.norm(b)
+
+
+def test_th2d_256_apply_matches_oracle_and_solve():
+    t0 = time.perf_counter()
+    P = make_config("th2d_256")
+    print(f"[fullsize th2d_256] n0={P.n0} generated in {time.perf_counter() - t0:.1f}s", flush=True)
+    h = mas.Handle(P, params(P))
+    r = np.random.default_rng(11).standard_normal(P.n0)
+    z = torch.empty(P.n0, dtype=torch.float64, device=DEV)
+    h.apply(torch.tensor(r, device=DEV), z)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pre = dc.DCPreconditioner(P, dc.default_params(P))
+    ref = pre.apply(r)
+    print(f"  oracle setup + apply {time.perf_counter() - t0:.1f}s", flush=True)
+    err = np.linalg.norm(z.cpu().numpy() - ref) / np.linalg.norm(ref)
+    print(f"  apply rel err {err:.2e}", flush=True)
+    assert err <= 1e-11
+    b = torch.tensor(P.b, device=DEV)
+    x = torch.empty_like(b)
+    rc, info = h.solve(b, x, rtol=1e-8)
+    xs = x.cpu().numpy()
+    res = true_res(P, xs, P.b)
+    print(f"  solve {info[0]['iters']} its, true relres {res:.2e}", flush=True)
+    assert rc == mas.MAS_OK and res <= 1e-8 and abs(res - info[0]["relres"]) <= 1e-3 * res
+    nu = P.meta["n_u"]
+    assert abs(P.p_weight0 @ xs[nu:]) <= 1e-12 * np.abs(xs).max()
+    h.close()
+
+
+@pytest.mark.parametrize("relax", ["dlsc", "vanka-dlsc"])
+def test_th2d_256_dlsc_solves(relax):
+    P = make_config("th2d_256")
+    rl = mas.MAS_RELAX_DLSC if relax == "dlsc" else mas.MAS_RELAX_VANKA_DLSC
+    print(f"[fullsize th2d_256 {relax}]", flush=True)
+    h = mas.Handle(P, params(P, relax=rl))
+    b = torch.tensor(P.b, device=DEV)
+    x = torch.empty_like(b)
+    rc, info = h.solve(b, x, rtol=1e-8)
+    res = true_res(P, x.cpu().numpy(), P.b)
+    print(f"  {info[0]['iters']} its, true relres {res:.2e}", flush=True)
+    assert rc == mas.MAS_OK and res <= 1e-8
+    h.close()
+
+
+def test_th3d_32_fp32_cycle_reaches_1e8_like_fp64():
+    t0 = time.perf_counter()
+    P = make_config("th3d_32")
+    print(f"[fullsize th3d_32] n0={P.n0} generated in {time.perf_counter() - t0:.1f}s", flush=True)
+    b = torch.tensor(P.b, device=DEV)
+    its = {}
+    for prec in (mas.MAS_FP32, mas.MAS_FP64):
+        h = mas.Handle(P, params(P, precision=prec))
+        x = torch.empty_like(b)
+        rc, info = h.solve(b, x, rtol=1e-8)
+        res = true_res(P, x.cpu().numpy(), P.b)
+        print(f"  precision {prec}: {info[0]['iters']} its, true relres {res:.2e}", flush=True)
+        assert rc == mas.MAS_OK and res <= 1e-8
+        its[prec] = info[0]["iters"]
+        h.close()
+    assert abs(its[mas.MAS_FP32] - its[mas.MAS_FP64]) <= 2
+
+
+def test_sv2d_128x64_batch_of_64_equals_columns_alone():
+    t0 = time.perf_counter()
+    P = make_config("sv2d_128x64")
+    nr = P.b.shape[1]
+    print(f"[fullsize sv2d_128x64] n0={P.n0} nrhs={nr} generated in {time.perf_counter() - t0:.1f}s", flush=True)
+    h = mas.Handle(P, params(P, precision=mas.MAS_FP32, nrhs_max=nr))
+    B = torch.tensor(P.b, device=DEV)
+    X = torch.empty_like(B)
+    rc, info = h.solve(B, X, rtol=1e-8, nrhs=nr)
+    Xs = X.cpu().numpy()
+    worst = max(true_res(P, Xs[:, k], P.b[:, k]) for k in range(nr))
+    print(f"  batch: iterations {min(i['iters'] for i in info)}..{max(i['iters'] for i in info)}, "
+          f"worst true relres {worst:.2e}", flush=True)
+    assert rc == mas.MAS_OK and worst <= 1e-8
+    for k in (0, nr - 1):
+        b = torch.tensor(np.ascontiguousarray(P.b[:, k]), device=DEV)
+        x = torch.empty_like(b)
+        _, i1 = h.solve(b, x, rtol=1e-8)
+        xs = x.cpu().numpy()
+        assert abs(i1[0]["iters"] - info[k]["iters"]) <= 1, (k, i1, info[k])
+        assert np.linalg.norm(xs - Xs[:, k]) <= 1e-6 * np.linalg.norm(xs), k
+    h.close()
