@@ -309,6 +309,18 @@ def main():
                        for k in range(nrhs)))
     print(f"[bench] timed {a.steps} solves in {dt:.3f}s, iters {iters}, true relres {relres:.2e}",
           file=sys.stderr, flush=True)
+    err64 = None
+    if prec == mas.MAS_FP32:  # error of the mixed-precision result against the FP64 cycle's (to 1e-10)
+        mp64 = mas.default_params(prob.dim, mas.MAS_SV if prob.disc == "SV" else mas.MAS_TH, relax,
+                                  precision=mas.MAS_FP64, nrhs_max=nrhs, krylov_its=a.krylov_its,
+                                  schedule=sched[a.schedule], dlsc_amg=a.dlsc_amg)
+        h64 = mas.Handle(prob, mp64)
+        x64 = torch.empty_like(b)
+        h64.solve(b, x64, rtol=1e-10, nrhs=nrhs)
+        X64 = x64.cpu().numpy().reshape(prob.n0, -1)
+        err64 = float(max(np.linalg.norm(xx[:, k] - X64[:, k]) / np.linalg.norm(X64[:, k]) for k in range(nrhs)))
+        h64.close()
+        del x64
     # V-cycle (one preconditioner application) time, and the patch kernel measured with HIP events
     nrep = 20
     r = torch.randn(prob.n0 * nrhs, dtype=torch.float64, device=dev)
@@ -367,6 +379,7 @@ def main():
                    "n0": prob.n0, "levels": info["n"], "relax": label, "cycle_precision": a.precision},
         "iters": iters[-1],
         "true_relres": relres,
+        "err_vs_fp64_cycle": err64,
         "vcycle_ms": vcycle_ms,
         "vcycle": {"mean_ms": vcycle_ms, "median_ms": per[nrep // 2], "min_ms": per[0], "applies": nrep,
                    "algorithmic_bytes": cyc_bytes,
