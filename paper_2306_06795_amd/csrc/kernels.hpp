@@ -39,10 +39,19 @@ __device__ __forceinline__ T wave_sum(T v) {
 
 // Load of data a launch reads once (matrix entries, factor records): non-
 // temporal, so the stream does not evict the level vectors that the same
-// launch gathers (measured: the 256x256 TH FP64 cycle 3.4% faster).
+// launch gathers (measured: the 256x256 TH FP64 cycle 3.4% faster).  Used
+// only for operators and factor records far larger than the caches that a
+// cycle reads once per relaxation; re-read or small data keeps plain loads.
 template <typename T>
 __device__ __forceinline__ T ld_stream(const T* p) {
   return __builtin_nontemporal_load(p);
+}
+// the same where the choice is a template parameter (operators re-read within
+// a cycle, or small enough to stay cached, keep plain loads)
+template <bool NT, typename T>
+__device__ __forceinline__ T ldv(const T* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
 }
 
 // ---------------------------------------------------------------------------
@@ -104,7 +113,7 @@ __device__ __forceinline__ void store_row(int64_t e, int64_t row, T s, const T* 
 // MODE 0: y = A x   MODE 1: y = b - A x   MODE 2: y += A x   MODE 3: y -= A x
 // MODE 4: Chebyshev step (ChebStep)   MODE 5: y = a m (A x), m = cs.dinv per row (or 1)
 // MODES 1, 3, 5 start a Chebyshev iteration from the stored value when cs.res is set
-template <typename T, int TEAM, int MODE>
+template <typename T, int TEAM, int MODE, bool NT = false>
 __global__ void __launch_bounds__(256) k_csr(int n, const int* __restrict__ ptr, const int* __restrict__ ind,
                                              const T* __restrict__ val, const T* __restrict__ x,
                                              const T* __restrict__ b, T* __restrict__ y, ChebStep<T> cs) {
@@ -114,7 +123,8 @@ __global__ void __launch_bounds__(256) k_csr(int n, const int* __restrict__ ptr,
   T s = 0;
   if (row < n) {
     const int e1 = ptr[row + 1];
-    for (int e = ptr[row] + lane; e < e1; e += TEAM) s += ld_stream(&val[e]) * x[ld_stream(&ind[e])];
+    for (int e = ptr[row] + lane; e < e1; e += TEAM)
+      s += ldv<NT>(&val[e]) * x[ldv<NT>(&ind[e])];
   }
 #pragma unroll
   for (int o = TEAM / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
@@ -124,7 +134,7 @@ __global__ void __launch_bounds__(256) k_csr(int n, const int* __restrict__ ptr,
 // Sliced ELL, 64 rows per slice (one wavefront, one lane per row), entries of a
 // slice stored column-major so that every load of the wavefront is one
 // contiguous segment; padded entries have value 0 and a valid column.
-template <typename T, int MODE>
+template <typename T, int MODE, bool NT = false>
 __global__ void __launch_bounds__(256) k_sell(int n, int64_t nslices, const int64_t* __restrict__ soff,
                                               const int* __restrict__ swidth, const int* __restrict__ ind,
                                               const T* __restrict__ val, const T* __restrict__ x,
@@ -139,14 +149,14 @@ __global__ void __launch_bounds__(256) k_sell(int n, int64_t nslices, const int6
   int c = 0;
   for (; c + 3 < w; c += 4) {
     const int64_t e = base + (int64_t)c * 64;
-    s0 += ld_stream(&val[e]) * x[ld_stream(&ind[e])];
-    s1 += ld_stream(&val[e + 64]) * x[ld_stream(&ind[e + 64])];
-    s2 += ld_stream(&val[e + 128]) * x[ld_stream(&ind[e + 128])];
-    s3 += ld_stream(&val[e + 192]) * x[ld_stream(&ind[e + 192])];
+    s0 += ldv<NT>(&val[e]) * x[ldv<NT>(&ind[e])];
+    s1 += ldv<NT>(&val[e + 64]) * x[ldv<NT>(&ind[e + 64])];
+    s2 += ldv<NT>(&val[e + 128]) * x[ldv<NT>(&ind[e + 128])];
+    s3 += ldv<NT>(&val[e + 192]) * x[ldv<NT>(&ind[e + 192])];
   }
   for (; c < w; ++c) {
     const int64_t e = base + (int64_t)c * 64;
-    s0 += ld_stream(&val[e]) * x[ld_stream(&ind[e])];
+    s0 += ldv<NT>(&val[e]) * x[ldv<NT>(&ind[e])];
   }
   const T s = (s0 + s1) + (s2 + s3);
   if (row < n) store_row<T, MODE>(row, row, s, x, b, y, cs);
@@ -660,7 +670,7 @@ __global__ void k_add3(int64_t n, T* __restrict__ x, const T* __restrict__ y, co
 // x_i = K_i^-1 V_i r into Y at the patch's offset.  Large patches take four
 // wavefronts: four times the loads in flight while the record is staged and
 // one velocity row per thread afterwards.
-template <typename T, bool STAGE, int TPB>
+template <typename T, bool STAGE, int TPB, bool NT = false>
 __global__ void __launch_bounds__(TPB) k_vanka_apply(int64_t np, const int64_t* __restrict__ off,
                                                     const int4* __restrict__ dims,
                                                     const int64_t* __restrict__ foff,
@@ -706,7 +716,7 @@ __global__ void __launch_bounds__(TPB) k_vanka_apply(int64_t np, const int64_t* 
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int64_t k = k0 + u * TPB + tid;
-        v[u] = k < nf ? ld_stream(&fac[f0 + k]) : (T)0;
+        v[u] = k < nf ? ldv<NT>(&fac[f0 + k]) : (T)0;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -781,7 +791,7 @@ __global__ void __launch_bounds__(TPB) k_vanka_apply(int64_t np, const int64_t* 
 // at similar rates, the accesses in flight at any time cover a few contiguous
 // regions (a per-wavefront blocked layout measured 3x slower).  Uhat and S^-1 are applied first, then the packed A^-1
 // blocks are streamed: x_u = Uhat y_p + A^-1 b_u.
-template <typename T, int N0, int N1, int N2, int NS>
+template <typename T, int N0, int N1, int N2, int NS, bool NT = false>
 __global__ void __launch_bounds__(256) k_vanka_tpp(int64_t P, int64_t Ppad, const int* __restrict__ dofs,
                                                   const T* __restrict__ fac, const T* __restrict__ r,
                                                   T* __restrict__ Y) {
@@ -800,7 +810,7 @@ __global__ void __launch_bounds__(256) k_vanka_tpp(int64_t P, int64_t Ppad, cons
   for (int s = 0; s < NS; ++s)
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
-      u[s * NV + k] = ld_stream(&f[(int64_t)(FA + s * NV + k) * Ppad]);
+      u[s * NV + k] = ldv<NT>(&f[(int64_t)(FA + s * NV + k) * Ppad]);
       t[s] += u[s * NV + k] * b[k];
     }
 #pragma unroll
@@ -809,7 +819,7 @@ __global__ void __launch_bounds__(256) k_vanka_tpp(int64_t P, int64_t Ppad, cons
 #pragma unroll
     for (int q = 0; q < NS; ++q) {
       const int a = s < q ? s : q, c = s < q ? q : s;
-      acc += ld_stream(&f[(int64_t)(FA + NV * NS + c * (c + 1) / 2 + a) * Ppad]) * t[q];
+      acc += ldv<NT>(&f[(int64_t)(FA + NV * NS + c * (c + 1) / 2 + a) * Ppad]) * t[q];
     }
     yp[s] = acc;
   }
@@ -824,7 +834,7 @@ __global__ void __launch_bounds__(256) k_vanka_tpp(int64_t P, int64_t Ppad, cons
 #define MAS_BLOCK(CS, N)                                   \
   _Pragma("unroll") for (int j = 0; j < (N); ++j)          \
     _Pragma("unroll") for (int i = 0; i <= j; ++i) {       \
-      const T a = ld_stream(&f[(int64_t)(q++) * Ppad]);                \
+      const T a = ldv<NT>(&f[(int64_t)(q++) * Ppad]);                \
       y[(CS) + i] += a * b[(CS) + j];                      \
       if (i != j) y[(CS) + j] += a * b[(CS) + i];          \
     }

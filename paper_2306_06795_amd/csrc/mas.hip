@@ -51,6 +51,8 @@ inline void launch_check() {
 inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 constexpr size_t kMaxLds = 64 * 1024;  // dynamic LDS per workgroup used by the patch kernels
+// operators and factor stores from this size on are read with non-temporal loads
+constexpr double kStreamBytes = 64.0 * 1024 * 1024;
 constexpr int kNrKT = 4;                // right-hand sides per thread in the batched patch kernel
 constexpr int kWidePatch = 128;         // patches of this many DoFs or more get a 256-thread workgroup
 constexpr int kFullPatch = 512;         // levels with patches this large store full velocity blocks
@@ -127,6 +129,7 @@ struct DCsr {
   int* sind = nullptr;
   T* sval = nullptr;
   bool use_sell = false;
+  bool stream = false;  // non-temporal loads of the entries (large, read once per use in a cycle)
 };
 
 template <typename T>
@@ -178,27 +181,39 @@ DCsr<T> upload_csr(DevArena& A, const Csr& C, hipStream_t s) {
   return d;
 }
 
-template <typename T, int MODE>
-void csr_launch(const DCsr<T>& A, const T* x, const T* b, T* y, hipStream_t s, ChebStep<T> cs = {}) {
-  if (A.n == 0) return;
+template <typename T, int MODE, bool NT>
+void csr_launch_nt(const DCsr<T>& A, const T* x, const T* b, T* y, hipStream_t s, ChebStep<T> cs) {
   const int bs = 256;
   if (A.use_sell) {
-    hipLaunchKernelGGL((k_sell<T, MODE>), dim3(blocks_for(A.nslices * 64, bs)), dim3(bs), 0, s, (int)A.n, A.nslices,
-                       A.soff, A.swidth, A.sind, A.sval, x, b, y, cs);
+    hipLaunchKernelGGL((k_sell<T, MODE, NT>), dim3(blocks_for(A.nslices * 64, bs)), dim3(bs), 0, s, (int)A.n,
+                       A.nslices, A.soff, A.swidth, A.sind, A.sval, x, b, y, cs);
     launch_check();
     return;
   }
   const unsigned nb = blocks_for(A.n * (int64_t)A.team, bs);
   switch (A.team) {
-#define CASE(TM) \
-  case TM:                                                                                                 \
-    hipLaunchKernelGGL((k_csr<T, TM, MODE>), dim3(nb), dim3(bs), 0, s, (int)A.n, A.ptr, A.ind, A.val, x, b, y, cs); \
+#define CASE(TM)                                                                                            \
+  case TM:                                                                                                  \
+    hipLaunchKernelGGL((k_csr<T, TM, MODE, NT>), dim3(nb), dim3(bs), 0, s, (int)A.n, A.ptr, A.ind, A.val, x, b, y, \
+                       cs);                                                                                 \
     break;
     CASE(2) CASE(4) CASE(8) CASE(16) CASE(32) CASE(64)
 #undef CASE
     default: throw MasError(MAS_EINVAL, "bad team size");
   }
   launch_check();
+}
+
+template <typename T, int MODE>
+void csr_launch(const DCsr<T>& A, const T* x, const T* b, T* y, hipStream_t s, ChebStep<T> cs = {}) {
+  if (A.n == 0) return;
+  if constexpr (MODE <= 1) {  // products and residuals of large level operators stream their entries
+    if (A.stream) {
+      csr_launch_nt<T, MODE, true>(A, x, b, y, s, cs);
+      return;
+    }
+  }
+  csr_launch_nt<T, MODE, false>(A, x, b, y, s, cs);
 }
 
 // Pick the lanes-per-row of a CSR product by timing every choice once on the
@@ -286,6 +301,7 @@ struct DPatches {
   int* inv_ptr_c = nullptr;
   int* inv_pos_c = nullptr;
   T* Ynr = nullptr;
+  bool stream = false;  // non-temporal loads of the factor records (far larger than the caches)
   int nr_chunk = 0;  // right-hand sides per workgroup of the batched patch kernel (LDS bound)
   bool nr_stage = true;  // the batched kernel stages factor records in LDS
 };
@@ -688,9 +704,14 @@ struct Cycle : CycleBase {
       fast_fac += rec * fb.P;
       fast_slots += (double)(nvb + nsd) * fb.P;
       if (timed) tm->begin(e0, e1, s);
-#define MAS_TPP(A, B, C, D)                                                                                    \
-  if (fb.shape[0] == A && fb.shape[1] == B && fb.shape[2] == C && fb.shape[3] == D) {                         \
-    hipLaunchKernelGGL((k_vanka_tpp<T, A, B, C, D>), dim3(nb), dim3(256), 0, s, fb.P, fb.Ppad, d, f, rin, y); \
+#define MAS_TPP(A, B, C, D)                                                                                     \
+  if (fb.shape[0] == A && fb.shape[1] == B && fb.shape[2] == C && fb.shape[3] == D) {                          \
+    if (pt.stream)                                                                                             \
+      hipLaunchKernelGGL((k_vanka_tpp<T, A, B, C, D, true>), dim3(nb), dim3(256), 0, s, fb.P, fb.Ppad, d, f, rin, \
+                         y);                                                                                   \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_vanka_tpp<T, A, B, C, D, false>), dim3(nb), dim3(256), 0, s, fb.P, fb.Ppad, d, f,   \
+                         rin, y);                                                                              \
   } else
       MAS_FAST_SHAPES(MAS_TPP) { throw MasError(MAS_EINVAL, "unknown patch bucket shape"); }
 #undef MAS_TPP
@@ -707,12 +728,18 @@ struct Cycle : CycleBase {
 #define MAS_GENERIC(ST, TB)                                                                                     \
   hipLaunchKernelGGL((k_vanka_apply<T, ST, TB>), dim3((unsigned)ng), dim3(TB), shm, s, ng, pt.off + pt.g0,     \
                      pt.dims + pt.g0, pt.foff + pt.g0, pt.dofs, pt.fac, rin, pt.Y, pt.max_m, pt.yshift, pt.full)
-      if (stage && wide) MAS_GENERIC(true, 256);
+#define MAS_GENERIC_NT(TB)                                                                                       \
+  hipLaunchKernelGGL((k_vanka_apply<T, true, TB, true>), dim3((unsigned)ng), dim3(TB), shm, s, ng, pt.off + pt.g0, \
+                     pt.dims + pt.g0, pt.foff + pt.g0, pt.dofs, pt.fac, rin, pt.Y, pt.max_m, pt.yshift, pt.full)
+      if (stage && wide && pt.stream) MAS_GENERIC_NT(256);
+      else if (stage && pt.stream) MAS_GENERIC_NT(WAVE);
+      else if (stage && wide) MAS_GENERIC(true, 256);
       else if (stage) MAS_GENERIC(true, WAVE);
       else if (pt.max_m >= kFullPatch) MAS_GENERIC(false, 1024);
       else if (wide) MAS_GENERIC(false, 256);
       else MAS_GENERIC(false, WAVE);
 #undef MAS_GENERIC
+#undef MAS_GENERIC_NT
       launch_check();
       if (timed)
         tm->end(e0, e1, s, patch_bytes(L, (double)pt.nfac_alg - fast_fac, (double)pt.ndofs - fast_slots), TK_GENERIC);
@@ -1139,6 +1166,7 @@ void build_patches(DevArena& ar, Level<T>& L, const PatchSet& ps, const DCsr<dou
   }
   d.nfac = fcur;
   d.nfac_alg = d.full ? alg : ps.foff.back();
+  d.stream = (double)d.nfac * sizeof(T) >= kStreamBytes;
   if (!d.full) d.max_f = ps.max_f;
   d.ny = ycur;
   // ---- DoF -> output positions, in patch order (deterministic sums)
@@ -1279,6 +1307,8 @@ std::unique_ptr<Cycle<T>> build_cycle(mas_handle* h, const std::vector<Csr>& Ks,
     L.r = ar.alloc<T>((size_t)L.n * cyc->nr_max);
     if (l + 1 < nl) {
       L.K = upload_csr<T>(ar, Ks[l], s);
+      // the residual product of a Vanka level reads K once per relaxation
+      L.K.stream = L.relax && dlsc[l].A.nr == 0 && (double)L.K.nnz * (sizeof(T) + 4) >= kStreamBytes;
       if (l >= 1) {
         L.P = upload_csr<T>(ar, Ps[l], s);
         L.R = upload_csr<T>(ar, transpose(Ps[l]), s);
@@ -1726,6 +1756,7 @@ void upload_impl(mas_handle* h, hipStream_t s) {
   const mas_params& par = h->par;
   const int64_t n0 = h->n0;
   h->K0full = upload_csr<double>(h->arena, pl.K0, s);
+  h->K0full.stream = (double)h->K0full.nnz * 12.0 >= kStreamBytes;  // one FGMRES product per iteration
   {
     double* tx = h->arena.alloc<double>(n0);
     double* ty = h->arena.alloc<double>(n0);
