@@ -1270,13 +1270,38 @@ __global__ void __launch_bounds__(256) k_mgs_step(int64_t n, T* __restrict__ w, 
                                                  const T* __restrict__ vnext, double* __restrict__ partial_out,
                                                  int mode) {
   __shared__ double sh[4];
+  // the first four elements of this thread are loaded before the reduction of
+  // the previous partials, so their latency overlaps it
+  constexpr int K = 4;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, st = (int64_t)gridDim.x * blockDim.x;
+  double wk[K], pk[K], nk[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int64_t i = i0 + k * st;
+    const bool ok = i < n;
+    wk[k] = ok ? (double)w[i] : 0.0;
+    pk[k] = (ok && vprev) ? (double)vprev[i] : 0.0;
+    nk[k] = (ok && mode == 0) ? (double)vnext[i] : 0.0;
+  }
   double a = 0.0;
   if (prev_partial) {
     a = sum_partials(gridDim.x, prev_partial);
     if (blockIdx.x == 0 && threadIdx.x == 0) *hprev = a;
   }
   double s = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int64_t i = i0 + k * st;
+    if (i < n) {
+      double wi = wk[k];
+      if (vprev) {
+        wi -= a * pk[k];
+        w[i] = (T)wi;
+      }
+      s += wi * (mode == 0 ? nk[k] : wi);
+    }
+  }
+  for (int64_t i = i0 + K * st; i < n; i += st) {
     double wi = w[i];
     if (vprev) {
       wi -= a * (double)vprev[i];
@@ -1295,10 +1320,17 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_normalize(int64_t n, const double* __restrict__ partial, int nb,
                                                   double* __restrict__ hout, const T* __restrict__ w,
                                                   T* __restrict__ v) {
+  constexpr int K = 4;  // first elements loaded before the reduction (latency overlap)
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, st = (int64_t)gridDim.x * blockDim.x;
+  double wk[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) wk[k] = i0 + k * st < n ? (double)w[i0 + k * st] : 0.0;
   const double nrm = sqrt(sum_partials(nb, partial));
   if (blockIdx.x == 0 && threadIdx.x == 0) *hout = nrm;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    v[i] = nrm != 0.0 ? (T)((double)w[i] / nrm) : (T)0;
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (i0 + k * st < n) v[i0 + k * st] = nrm != 0.0 ? (T)(wk[k] / nrm) : (T)0;
+  for (int64_t i = i0 + K * st; i < n; i += st) v[i] = nrm != 0.0 ? (T)((double)w[i] / nrm) : (T)0;
 }
 
 // Least-squares step of the relaxation wrapper (one thread): Givens rotations
