@@ -137,3 +137,38 @@ def test_analyze_rejects_bad_input():
         t = torch.zeros(P.n0, dtype=torch.float64)
         h.apply(t, t, stream=0)
     h.close()
+
+
+_THREADS_SCRIPT = r"""
+import sys
+import numpy as np
+from paper_2306_06795_amd import mas
+from paper_2306_06795_amd.inputs import make_problem
+P = make_problem(dim=2, n=64, jitter=0.2, seed=2, forcing="gaussian", bc="lid")  # ~33k rows: 7 threads split
+h = mas.Handle(P, mas.default_params(2, max_coarse=30), analyze_only=True)
+out = {}
+for l in range(h.info()["n_levels"]):
+    K = h.export_level(l)
+    out[f"p{l}"], out[f"i{l}"], out[f"v{l}"] = K.indptr, K.indices, K.data
+np.savez(sys.argv[1], **out)
+"""
+
+
+def test_host_analysis_is_independent_of_the_thread_count(tmp_path):
+    """The row-parallel host setup gives the same hierarchy, bit for bit, with
+    one thread and with several (each run is its own process: the thread
+    count is read once per process)."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    res = {}
+    for t in ("1", "7"):
+        f = tmp_path / f"h{t}.npz"
+        env = dict(os.environ, MAS_SETUP_THREADS=t, PYTHONPATH=root)
+        subprocess.run([sys.executable, "-c", _THREADS_SCRIPT, str(f)], check=True, env=env, cwd=root, timeout=300)
+        res[t] = np.load(f)
+    a, b = res["1"], res["7"]
+    assert sorted(a.files) == sorted(b.files) and len(a.files) >= 9
+    for k in a.files:
+        assert np.array_equal(a[k].view(np.uint8), b[k].view(np.uint8)), k
