@@ -578,6 +578,103 @@ __global__ void __launch_bounds__(256) k_normalize_nr(int64_t n, int nr, const d
   }
 }
 
+// Classical Gram-Schmidt for the FGMRES Arnoldi step, for nr interleaved
+// columns (entry (row, k) at row * nr + k; nr = 1 for one right-hand side).
+// It yields the same Hessenberg column as modified Gram-Schmidt in exact
+// arithmetic with about half the vector traffic: all the dots in one sweep,
+// then one update.  k_cgs_dots_nr: part[(i * gridDim.x + b) * nr + k] = block
+// b's share of v_i(:, k) . w(:, k) for i < j1, 16 basis vectors per sweep of w.
+constexpr int kCgsChunk = 16;
+
+// Sum of v over the threads of a 256-thread block that hold column k = tid %
+// nrp (nrp a power of two <= 64): shuffles over the lanes of one column in a
+// wavefront, then the four wavefronts through red[u][wave][k].  Valid in the
+// threads tid < nrp after the caller's __syncthreads.
+__device__ __forceinline__ void cgs_wave_part(double v, int nrp, double (*red)[4][64], int u) {
+  for (int o = WAVE / 2; o >= nrp; o >>= 1) v += __shfl_xor(v, o);
+  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+  if (lane < nrp) red[u][wv][lane] = v;
+}
+
+__global__ void __launch_bounds__(256) k_cgs_dots_nr(int64_t n, int nr, int nrp, int j1, const double* __restrict__ V,
+                                                    const double* __restrict__ w, double* __restrict__ part) {
+  __shared__ double red[kCgsChunk][4][64];
+  const int k = threadIdx.x % nrp, g = threadIdx.x / nrp, ng = 256 / nrp;
+  const bool col = k < nr;
+  const int64_t stride = (int64_t)gridDim.x * ng, nn = n * nr;
+  for (int i0 = 0; i0 < j1; i0 += kCgsChunk) {
+    const int na = min(kCgsChunk, j1 - i0);
+    double acc[kCgsChunk];
+#pragma unroll
+    for (int u = 0; u < kCgsChunk; ++u) acc[u] = 0.0;
+    if (col)
+      for (int64_t r = (int64_t)blockIdx.x * ng + g; r < n; r += stride) {
+        const int64_t e = r * nr + k;
+        const double we = w[e];
+#pragma unroll
+        for (int u = 0; u < kCgsChunk; ++u)
+          if (u < na) acc[u] += V[(int64_t)(i0 + u) * nn + e] * we;
+      }
+#pragma unroll
+    for (int u = 0; u < kCgsChunk; ++u)
+      if (u < na) cgs_wave_part(acc[u], nrp, red, u);
+    __syncthreads();
+    for (int t = threadIdx.x; t < na * nrp; t += 256) {
+      const int u = t / nrp, kk = t % nrp;
+      if (kk < nr)
+        part[((int64_t)(i0 + u) * gridDim.x + blockIdx.x) * nr + kk] =
+            red[u][0][kk] + red[u][1][kk] + red[u][2][kk] + red[u][3][kk];
+    }
+    __syncthreads();
+  }
+}
+
+// h[i * nr + k] = sum over the nb blocks of the dot partials; one wavefront per (i, k)
+__global__ void __launch_bounds__(64) k_cgs_final_nr(int nb, int nr, int j1, const double* __restrict__ part,
+                                                     double* __restrict__ h) {
+  const int t = blockIdx.x;  // (i, k)
+  if (t >= j1 * nr) return;
+  const int i = t / nr, k = t % nr;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += WAVE) s += part[((int64_t)i * nb + b) * nr + k];
+  s = wave_sum(s);
+  if (threadIdx.x == 0) h[t] = s;
+}
+
+// w(:, k) -= sum_{i < j1} h[i * nr + k] v_i(:, k); partial_out[b * nr + k] = block
+// b's share of |w(:, k)|^2 (the layout k_normalize_nr reduces)
+__global__ void __launch_bounds__(256) k_cgs_update_nr(int64_t n, int nr, int nrp, int j1,
+                                                      const double* __restrict__ V, const double* __restrict__ h,
+                                                      double* __restrict__ w, double* __restrict__ partial_out) {
+  __shared__ double red[1][4][64];
+  const int k = threadIdx.x % nrp, g = threadIdx.x / nrp, ng = 256 / nrp;
+  const bool col = k < nr;
+  const int64_t stride = (int64_t)gridDim.x * ng, nn = n * nr;
+  double s = 0.0;
+  for (int i0 = 0; i0 < j1; i0 += kCgsChunk) {
+    const int na = min(kCgsChunk, j1 - i0);
+    const bool last = i0 + kCgsChunk >= j1;
+    double hk[kCgsChunk];
+#pragma unroll
+    for (int u = 0; u < kCgsChunk; ++u) hk[u] = (col && u < na) ? h[(i0 + u) * nr + k] : 0.0;
+    if (col)
+      for (int64_t r = (int64_t)blockIdx.x * ng + g; r < n; r += stride) {
+        const int64_t e = r * nr + k;
+        double we = w[e];
+#pragma unroll
+        for (int u = 0; u < kCgsChunk; ++u)
+          if (u < na) we -= hk[u] * V[(int64_t)(i0 + u) * nn + e];
+        w[e] = we;
+        if (last) s += we * we;
+      }
+  }
+  cgs_wave_part(s, nrp, red, 0);
+  __syncthreads();
+  if (threadIdx.x < nr)
+    partial_out[(int64_t)blockIdx.x * nr + threadIdx.x] =
+        red[0][0][threadIdx.x] + red[0][1][threadIdx.x] + red[0][2][threadIdx.x] + red[0][3][threadIdx.x];
+}
+
 // out[k] = sum_b partial[b * nr + k] (sqrt if take_sqrt)
 __global__ void k_reduce_final_nr(int nb, int nr, const double* __restrict__ partial, double* __restrict__ out,
                                   int take_sqrt) {

@@ -909,6 +909,8 @@ struct mas_handle {
   double pw_sum = 0.0;
   // FGMRES work
   double *V = nullptr, *Z = nullptr, *w = nullptr, *partial = nullptr, *hdev = nullptr, *ydev = nullptr;
+  double* cpart = nullptr;  // classical Gram-Schmidt dot partials ((m + 1) x blocks x right-hand sides)
+  bool use_mgs = false;     // MAS_MGS: modified Gram-Schmidt instead
   double* hhost = nullptr;  // pinned
   int nblk_dot = 512;
   hipStream_t gs = nullptr;     // internal stream: solves run here (graphs cannot capture the null stream)
@@ -1778,6 +1780,8 @@ void upload_impl(mas_handle* h, hipStream_t s) {
   h->Z = h->arena.alloc<double>((size_t)m * n0 * R);
   h->w = h->arena.alloc<double>((size_t)n0 * R);
   h->partial = h->arena.alloc<double>((size_t)2 * h->nblk_dot * R);
+  h->cpart = h->arena.alloc<double>((size_t)(m + 1) * h->nblk_dot * R);
+  h->use_mgs = std::getenv("MAS_MGS") != nullptr;
   h->hdev = h->arena.alloc<double>((size_t)(m + 2) * R);
   h->ydev = h->arena.alloc<double>((size_t)(m + 1) * R);
   HIPCHECK(hipHostMalloc((void**)&h->hhost, (size_t)(m + 2) * R * sizeof(double), hipHostMallocDefault));
@@ -1836,15 +1840,24 @@ void inner_iteration(mas_handle* h, int j, hipStream_t s) {
   double* w = h->w;
   csr_launch<double, 0>(h->K0full, zj, nullptr, w, s);
   double* part[2] = {h->partial, h->partial + h->nblk_dot};
-  for (int i = 0; i <= j + 1; ++i) {
-    const double* vprev = i > 0 ? h->V + (int64_t)(i - 1) * n : nullptr;
-    double* hprev = i > 0 ? h->hdev + (i - 1) : nullptr;
-    const double* pprev = i > 0 ? part[(i - 1) & 1] : nullptr;
-    const double* vnext = i <= j ? h->V + (int64_t)i * n : nullptr;
-    hipLaunchKernelGGL(k_mgs_step<double>, dim3(h->nblk_dot), dim3(256), 0, s, n, w, vprev, hprev, pprev, vnext,
-                       part[i & 1], i <= j ? 0 : 1);
+  int pn = 0;  // the partial buffer the normalisation reads
+  if (h->use_mgs) {  // modified Gram-Schmidt, one kernel per basis vector
+    for (int i = 0; i <= j + 1; ++i) {
+      const double* vprev = i > 0 ? h->V + (int64_t)(i - 1) * n : nullptr;
+      double* hprev = i > 0 ? h->hdev + (i - 1) : nullptr;
+      const double* pprev = i > 0 ? part[(i - 1) & 1] : nullptr;
+      const double* vnext = i <= j ? h->V + (int64_t)i * n : nullptr;
+      hipLaunchKernelGGL(k_mgs_step<double>, dim3(h->nblk_dot), dim3(256), 0, s, n, w, vprev, hprev, pprev, vnext,
+                         part[i & 1], i <= j ? 0 : 1);
+    }
+    pn = (j + 1) & 1;
+  } else {  // classical Gram-Schmidt: every dot in one sweep, then one update
+    hipLaunchKernelGGL(k_cgs_dots_nr, dim3(h->nblk_dot), dim3(256), 0, s, n, 1, 1, j + 1, h->V, w, h->cpart);
+    hipLaunchKernelGGL(k_cgs_final_nr, dim3(j + 1), dim3(64), 0, s, h->nblk_dot, 1, j + 1, h->cpart, h->hdev);
+    hipLaunchKernelGGL(k_cgs_update_nr, dim3(h->nblk_dot), dim3(256), 0, s, n, 1, 1, j + 1, h->V, h->hdev, w,
+                       part[0]);
   }
-  hipLaunchKernelGGL(k_normalize<double>, dim3(h->nblk_dot), dim3(256), 0, s, n, part[(j + 1) & 1], h->nblk_dot,
+  hipLaunchKernelGGL(k_normalize<double>, dim3(h->nblk_dot), dim3(256), 0, s, n, part[pn], h->nblk_dot,
                      h->hdev + j + 1, w, h->V + (int64_t)(j + 1) * n);
   launch_check();
   HIPCHECK(hipMemcpyAsync(h->hhost, h->hdev, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -2043,15 +2056,24 @@ int fgmres_nr(mas_handle* h, const double* b, double* x, int nr, const double* r
       hipLaunchKernelGGL((k_spmm<double, 0>), dim3(blocks_for(n * nr, 256)), dim3(256), 0, s, n, nr, h->K0full.ptr,
                          h->K0full.ind, h->K0full.val, zj, nullptr, w, ChebStep<double>{});
       double* part[2] = {h->partial, h->partial + (size_t)nb * nr};
-      for (int i = 0; i <= j + 1; ++i) {
-        const double* vprev = i > 0 ? h->V + (int64_t)(i - 1) * n * nr : nullptr;
-        double* hprev = i > 0 ? h->hdev + (size_t)(i - 1) * nr : nullptr;
-        const double* pprev = i > 0 ? part[(i - 1) & 1] : nullptr;
-        const double* vnext = i <= j ? h->V + (int64_t)i * n * nr : nullptr;
-        hipLaunchKernelGGL(k_mgs_step_nr, dim3(nb), dim3(256), 0, s, n, nr, nrp, w, vprev, hprev, pprev, vnext,
-                           part[i & 1], i <= j ? 0 : 1);
+      int pn = 0;
+      if (h->use_mgs) {
+        for (int i = 0; i <= j + 1; ++i) {
+          const double* vprev = i > 0 ? h->V + (int64_t)(i - 1) * n * nr : nullptr;
+          double* hprev = i > 0 ? h->hdev + (size_t)(i - 1) * nr : nullptr;
+          const double* pprev = i > 0 ? part[(i - 1) & 1] : nullptr;
+          const double* vnext = i <= j ? h->V + (int64_t)i * n * nr : nullptr;
+          hipLaunchKernelGGL(k_mgs_step_nr, dim3(nb), dim3(256), 0, s, n, nr, nrp, w, vprev, hprev, pprev, vnext,
+                             part[i & 1], i <= j ? 0 : 1);
+        }
+        pn = (j + 1) & 1;
+      } else {
+        hipLaunchKernelGGL(k_cgs_dots_nr, dim3(nb), dim3(256), 0, s, n, nr, nrp, j + 1, h->V, w, h->cpart);
+        hipLaunchKernelGGL(k_cgs_final_nr, dim3((unsigned)((j + 1) * nr)), dim3(64), 0, s, (int)nb, nr, j + 1,
+                           h->cpart, h->hdev);
+        hipLaunchKernelGGL(k_cgs_update_nr, dim3(nb), dim3(256), 0, s, n, nr, nrp, j + 1, h->V, h->hdev, w, part[0]);
       }
-      hipLaunchKernelGGL(k_normalize_nr, dim3(nb), dim3(256), 0, s, n, nr, part[(j + 1) & 1], (int)nb,
+      hipLaunchKernelGGL(k_normalize_nr, dim3(nb), dim3(256), 0, s, n, nr, part[pn], (int)nb,
                          h->hdev + (size_t)(j + 1) * nr, w, h->V + (int64_t)(j + 1) * n * nr);
       launch_check();
       HIPCHECK(hipMemcpyAsync(h->hhost, h->hdev, (size_t)(j + 2) * nr * sizeof(double), hipMemcpyDeviceToHost, s));
