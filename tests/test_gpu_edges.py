@@ -101,3 +101,27 @@ def test_argument_errors():
             h.solve(b, x, **kw)
         assert e.value.code == mas.MAS_EINVAL, kw
     h.close()
+
+
+@pytest.mark.parametrize("nrhs", [1, 5])
+def test_classical_and_modified_gram_schmidt_agree(nrhs, monkeypatch):
+    """FGMRES with classical Gram-Schmidt (default) and modified (MAS_MGS):
+    same iteration counts, solutions equal to rounding."""
+    P = make_problem(dim=2, n=16, forcing="gaussian", bc="lid", jitter=0.2, seed=6, nrhs=nrhs)
+    B = torch.tensor(P.b, device=DEV)
+    out = {}
+    for mgs in (False, True):
+        if mgs:
+            monkeypatch.setenv("MAS_MGS", "1")
+        else:
+            monkeypatch.delenv("MAS_MGS", raising=False)
+        h = handle(P, nrhs_max=nrhs)
+        X = torch.empty_like(B)
+        rc, info = h.solve(B, X, rtol=1e-10, nrhs=nrhs)
+        assert rc == mas.MAS_OK
+        out[mgs] = (X.cpu().numpy(), [i["iters"] for i in info])
+        h.close()
+    (xc, ic), (xm, im) = out[False], out[True]
+    print(f"[edges] nrhs={nrhs} its classical {ic} modified {im}", flush=True)
+    assert ic == im
+    assert np.linalg.norm(xc - xm) <= 1e-9 * np.linalg.norm(xm)
