@@ -309,6 +309,21 @@ def main():
                        for k in range(nrhs)))
     print(f"[bench] timed {a.steps} solves in {dt:.3f}s, iters {iters}, true relres {relres:.2e}",
           file=sys.stderr, flush=True)
+    eager = None
+    if prob.n0 < 20000:  # small systems are launch-bound: the same solves without the iteration graphs
+        os.environ["MAS_NO_GRAPHS"] = "1"
+        he = mas.Handle(prob, mp)
+        os.environ.pop("MAS_NO_GRAPHS")
+        xe = torch.empty_like(b)
+        he.solve(b, xe, rtol=a.rtol, nrhs=nrhs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            he.solve(b, xe, rtol=a.rtol, nrhs=nrhs)
+        torch.cuda.synchronize()
+        eager = {"ms_per_step": 1e3 * (time.perf_counter() - t0) / a.steps,
+                 "note": "same solves with every kernel launched from the host (no graph replay)"}
+        he.close()
     err64 = None
     if prec == mas.MAS_FP32:  # error of the mixed-precision result against the FP64 cycle's (to 1e-10)
         mp64 = mas.default_params(prob.dim, mas.MAS_SV if prob.disc == "SV" else mas.MAS_TH, relax,
@@ -380,6 +395,7 @@ def main():
         "iters": iters[-1],
         "true_relres": relres,
         "err_vs_fp64_cycle": err64,
+        "eager": eager,
         "vcycle_ms": vcycle_ms,
         "vcycle": {"mean_ms": vcycle_ms, "median_ms": per[nrep // 2], "min_ms": per[0], "applies": nrep,
                    "algorithmic_bytes": cyc_bytes,
