@@ -147,6 +147,27 @@ __global__ void __launch_bounds__(256) k_sell(int n, int64_t nslices, const int6
   const int w = swidth[slice];
   T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
   int c = 0;
+  for (; c + 7 < w; c += 8) {  // eight entries in flight
+    const int64_t e = base + (int64_t)c * 64;
+    int q[8];
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      q[u] = ldv<NT>(&ind[e + 64 * u]);
+      v[u] = ldv<NT>(&val[e + 64 * u]);
+    }
+    T g[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) g[u] = x[q[u]];
+    s0 += v[0] * g[0];
+    s1 += v[1] * g[1];
+    s2 += v[2] * g[2];
+    s3 += v[3] * g[3];
+    s0 += v[4] * g[4];
+    s1 += v[5] * g[5];
+    s2 += v[6] * g[6];
+    s3 += v[7] * g[7];
+  }
   for (; c + 3 < w; c += 4) {
     const int64_t e = base + (int64_t)c * 64;
     s0 += ldv<NT>(&val[e]) * x[ldv<NT>(&ind[e])];
