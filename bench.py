@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--serve-workers", type=int, default=4)
     ap.add_argument("--serve-small-gb", type=float, default=0.0)
     ap.add_argument("--serve-baseline-open", action="store_true")
+    ap.add_argument("--serve-relax-3d", default="vanka-dlsc", choices=["vanka", "vanka-dlsc"],
+                    help="relaxation of the 3D meshes of the serving stream (2D meshes: Vanka)")
     return ap.parse_args()
 
 
@@ -160,8 +162,13 @@ def bench_serve(a):
     t_gen = time.perf_counter() - t0
     full = int(torch.cuda.get_device_properties(0).total_memory * 0.8)
 
+    def policy(P):
+        if P.dim == 3 and a.serve_relax_3d == "vanka-dlsc":
+            return {"relax": mas.MAS_RELAX_VANKA_DLSC}
+        return {}
+
     def server(budget, precision, max_batch, workers):
-        srv = serving.StokesServer(budget, max_batch=max_batch, workers=workers, precision=precision)
+        srv = serving.StokesServer(budget, max_batch=max_batch, workers=workers, precision=precision, params=policy)
         for k, P in probs.items():
             srv.add_mesh(k, P)
         srv.start()
@@ -230,7 +237,8 @@ def bench_serve(a):
                                "128^2/256^2 and 3D 8^3/12^3/16^3/24^3, viscosity log-uniform [1e-2,1], Gaussian "
                                "forcing, homogeneous Dirichlet, FGMRES(20) rtol 1e-8",
                    "arrival_rate_per_s": rate, "load_factor": a.serve_load, "max_batch": a.serve_batch,
-                   "workers": a.serve_workers, "hbm_budget_gib": full / 2**30},
+                   "workers": a.serve_workers, "hbm_budget_gib": full / 2**30,
+                   "relaxation": f"2D Vanka, 3D {a.serve_relax_3d}"},
         "p50_ms": main_run["p50_ms"],
         "p99_ms": main_run["p99_ms"],
         "closed_loop": closed,

@@ -122,10 +122,12 @@ class StokesServer:
     """``device`` (streams, arrays) and ``handle_factory(problem, params)``
     (an analysed handle with upload/release/info/scale_rows/solve/close) default
     to torch on cuda:0 and libmas; other implementations serve to test the
-    scheduling on the host."""
+    scheduling on the host.  ``params``: overrides of the libmas parameters,
+    a dict for every mesh or a function of the problem giving one (e.g. a
+    different relaxation for 3D meshes)."""
 
     def __init__(self, hbm_budget: int, max_batch: int = 32, workers: int = 4,
-                 precision: int = mas.MAS_FP32, params: dict | None = None, device=None, handle_factory=None):
+                 precision: int = mas.MAS_FP32, params=None, device=None, handle_factory=None):
         self.device = device
         self.handle_factory = handle_factory or _analysed_handle
         self.budget = int(hbm_budget)
@@ -153,8 +155,8 @@ class StokesServer:
         estimate from the analysis.  The exact size replaces it at the first
         upload."""
         disc = mas.MAS_SV if problem.disc == "SV" else mas.MAS_TH
-        par = mas.default_params(problem.dim, disc, precision=self.precision, nrhs_max=self.max_batch,
-                                 **self.params)
+        extra = self.params(problem) if callable(self.params) else self.params
+        par = mas.default_params(problem.dim, disc, precision=self.precision, nrhs_max=self.max_batch, **extra)
         h = self.handle_factory(problem, par)
         est = int(device_bytes) if device_bytes else estimate_device_bytes(h.info(), self.precision,
                                                                              self.max_batch)
