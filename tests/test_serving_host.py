@@ -203,3 +203,22 @@ def test_failures_stay_in_their_batch():
             assert "memory" in r.error
     # the failed upload gave its reservation back; a and b stay resident
     assert st["resident_bytes"] == 2 * (1 << 20), st
+
+
+def test_parameters_may_depend_on_the_mesh():
+    """params as a function of the problem: each mesh's analysis gets its own."""
+    seen = {}
+
+    def factory(key):
+        def make(P, par):
+            seen[key] = (par.relax, par.nrhs_max)
+            return ExactHandle(P, par, key)
+        return make
+
+    srv = serving.StokesServer(1 << 40, max_batch=8, workers=1, device=HostDevice(),
+                               params=lambda P: {"relax": 2} if P.meta["n"] == 8 else {})
+    for k, n in MESHES.items():
+        srv.handle_factory = factory(k)
+        srv.add_mesh(k, mesh(n))
+    srv.shutdown()
+    assert seen == {"a": (0, 8), "b": (2, 8), "c": (0, 8)}
