@@ -132,6 +132,20 @@ struct DCsr {
   bool stream = false;  // non-temporal loads of the entries (large, read once per use in a cycle)
 };
 
+// CSR arrays only (no sliced-ELL copy): operators the factorisation reads once
+template <typename T>
+DCsr<T> upload_csr_plain(DevArena& A, const Csr& C, hipStream_t s) {
+  if (C.nnz() >= (int64_t)INT32_MAX) throw MasError(MAS_EINVAL, "matrix too large for 32-bit offsets");
+  DCsr<T> d;
+  d.n = C.nr;
+  d.m = C.nc;
+  d.nnz = C.nnz();
+  d.ptr = A.upload<int>(C.ptr, s);
+  d.ind = A.upload<int>(C.ind, s);
+  d.val = A.upload<T>(C.val, s);
+  return d;
+}
+
 template <typename T>
 DCsr<T> upload_csr(DevArena& A, const Csr& C, hipStream_t s) {
   if (C.nnz() >= (int64_t)INT32_MAX) throw MasError(MAS_EINVAL, "matrix too large for 32-bit offsets");
@@ -158,20 +172,26 @@ DCsr<T> upload_csr(DevArena& A, const Csr& C, hipStream_t s) {
     soff[sl + 1] = soff[sl] + (int64_t)w * 64;
   }
   if (ns > 0 && soff[ns] <= (int64_t)(1.3 * (double)C.nnz()) + 64) {
-    std::vector<int> sind(soff[ns], 0);
-    std::vector<double> sval(soff[ns], 0.0);
-    for (int64_t sl = 0; sl < ns; ++sl)
-      for (int lane = 0; lane < 64; ++lane) {
-        const int64_t r = sl * 64 + lane;
-        int c = 0;
-        if (r < C.nr)
-          for (int64_t e = C.ptr[r]; e < C.ptr[r + 1]; ++e, ++c) {
-            sind[soff[sl] + (int64_t)c * 64 + lane] = C.ind[e];
-            sval[soff[sl] + (int64_t)c * 64 + lane] = C.val[e];
+    // slices are independent: filled over threads, every slot written once (padding: value 0)
+    std::vector<int, NoInit<int>> sind(soff[ns]);
+    std::vector<T, NoInit<T>> sval(soff[ns]);
+    parallel_rows(ns, [&](int64_t lo, int64_t hi) {
+      for (int64_t sl = lo; sl < hi; ++sl)
+        for (int lane = 0; lane < 64; ++lane) {
+          const int64_t r = sl * 64 + lane;
+          int c = 0;
+          if (r < C.nr)
+            for (int64_t e = C.ptr[r]; e < C.ptr[r + 1]; ++e, ++c) {
+              sind[soff[sl] + (int64_t)c * 64 + lane] = C.ind[e];
+              sval[soff[sl] + (int64_t)c * 64 + lane] = (T)C.val[e];
+            }
+          const int pad_col = (r < C.nr && C.ptr[r + 1] > C.ptr[r]) ? C.ind[C.ptr[r]] : 0;
+          for (; c < sw[sl]; ++c) {
+            sind[soff[sl] + (int64_t)c * 64 + lane] = pad_col;
+            sval[soff[sl] + (int64_t)c * 64 + lane] = (T)0;
           }
-        const int pad_col = (r < C.nr && C.ptr[r + 1] > C.ptr[r]) ? C.ind[C.ptr[r]] : 0;
-        for (; c < sw[sl]; ++c) sind[soff[sl] + (int64_t)c * 64 + lane] = pad_col;
-      }
+        }
+    });
     d.nslices = ns;
     d.soff = A.upload<int64_t>(soff, s);
     d.swidth = A.upload<int>(sw, s);
@@ -959,10 +979,10 @@ Csr get_csr(const mas_csr& c, const char* name) {
 struct SetupTrace {
   bool on = std::getenv("MAS_TRACE_SETUP") != nullptr;
   std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
-  void mark(const char* what) {
+  void mark(const std::string& what) {
     if (!on) return;
     const auto now = std::chrono::steady_clock::now();
-    std::fprintf(stderr, "[mas setup] %-28s %9.1f ms\n", what,
+    std::fprintf(stderr, "[mas setup] %-36s %9.1f ms\n", what.c_str(),
                  std::chrono::duration<double, std::milli>(now - t).count());
     t = now;
   }
@@ -1315,11 +1335,17 @@ std::unique_ptr<Cycle<T>> build_cycle(mas_handle* h, const std::vector<Csr>& Ks,
         L.P = upload_csr<T>(ar, Ps[l], s);
         L.R = upload_csr<T>(ar, transpose(Ps[l]), s);
       }
+      if (tr.on) HIPCHECK(hipStreamSynchronize(s));
+      tr.mark("device: level " + std::to_string(l) + " operators");
       if (L.relax && !patches[l].off.empty()) {
-        DCsr<double> K64;
-        if constexpr (std::is_same<T, double>::value) K64 = L.K;
-        else K64 = upload_csr<double>(ar, Ks[l], s);
-        build_patches<T>(ar, L, patches[l], K64, (int)l, cyc->nr_max, s);
+        if constexpr (std::is_same<T, double>::value) {
+          build_patches<T>(ar, L, patches[l], L.K, (int)l, cyc->nr_max, s);
+        } else {  // the FP64 operator lives only while the patches are factorised
+          DevArena tmp;
+          const DCsr<double> K64 = upload_csr_plain<double>(tmp, Ks[l], s);
+          build_patches<T>(ar, L, patches[l], K64, (int)l, cyc->nr_max, s);
+        }
+        tr.mark("device: level " + std::to_string(l) + " patches");
       }
       if (L.relax && dlsc[l].A.nr > 0) {
         const HostDlsc& H = dlsc[l];
