@@ -588,6 +588,33 @@ def test_apply_is_linear():
     assert np.linalg.norm(lhs - rhs) <= 1e-12 * np.linalg.norm(rhs)
 
 
+@pytest.mark.parametrize("kw,relax,nu", [
+    (dict(dim=2, n=8, jitter=0.2, seed=2, bc="lid"), "vanka", 0.05),
+    (dict(dim=2, n=8, jitter=0.2, seed=2, bc="lid"), "dlsc", 0.05),
+    (dict(dim=2, n=8, jitter=0.2, seed=2, bc="lid"), "vanka-dlsc", 20.0),
+    (dict(dim=2, n=6, disc="SV", seed=4, bc="zero"), "vanka", 0.05),
+    (dict(dim=3, n=3, seed=3, bc="lid"), "vanka", 20.0),
+])
+def test_viscosity_scaling_of_the_preconditioner(kw, relax, nu):
+    """K_nu = S K_1 S on the free block, S = diag(sqrt(nu) I_u, I_p / sqrt(nu)):
+    every piece of the cycle (Galerkin products, strength of connection,
+    Gershgorin and Chebyshev bounds, patch solves, the bordered coarse solve)
+    is built from the nu = 1 one by the same diagonal scaling, so the whole
+    preconditioner satisfies B_nu = S^-1 B_1 S^-1.  Dirichlet rows are identity
+    rows in both operators and pass through unchanged."""
+    P1 = make_problem(nu=1.0, forcing="gaussian", **kw)
+    Pn = make_problem(nu=nu, forcing="gaussian", **kw)
+    B1 = dc.DCPreconditioner(P1, dc.default_params(P1, relax, max_coarse=20))
+    Bn = dc.DCPreconditioner(Pn, dc.default_params(Pn, relax, max_coarse=20))
+    n_u = P1.meta["n_u"]
+    s = np.r_[np.full(n_u, np.sqrt(nu)), np.full(P1.n0 - n_u, 1.0 / np.sqrt(nu))]
+    s[P1.dir0] = 1.0
+    r = np.random.default_rng(1).standard_normal(P1.n0)
+    zn = Bn.apply(r)
+    assert np.linalg.norm(zn - B1.apply(r / s) / s) <= 1e-13 * np.linalg.norm(zn)
+    assert np.array_equal(zn[P1.dir0], r[P1.dir0])
+
+
 def test_skip0_iterations_invariant_to_eta():
     """Section 4.1: with no relaxation on K0, eta only scales the preconditioner."""
     P = make_problem(dim=2, n=8, jitter=0.2, seed=2, forcing="gaussian", bc="lid")
