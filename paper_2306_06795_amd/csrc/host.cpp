@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <future>
 #include <numeric>
 #include <stdexcept>
 #include <thread>
@@ -197,27 +198,43 @@ void spmv(const Csr& A, const double* x, double* y) {
 
 static std::vector<double> diagonal(const Csr& A) {
   std::vector<double> d(A.nr, 0.0);
-  for (int64_t i = 0; i < A.nr; ++i)
-    for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e)
-      if (A.ind[e] == i) d[i] = A.val[e];
+  parallel_rows(A.nr, [&](int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi; ++i)
+      for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e)
+        if (A.ind[e] == i) d[i] = A.val[e];
+  });
   return d;
 }
 
-// strong neighbours: j != i with a_ij^2 >= theta^2 (a_ii a_jj)
+// strong neighbours: j != i with a_ij^2 >= theta^2 (a_ii a_jj); rows counted,
+// then filled, in parallel (the pattern does not depend on the thread count)
 static Csr strength(const Csr& A, double theta) {
   std::vector<double> d = diagonal(A);
   const double th2 = theta * theta;
+  auto strong = [&](int64_t i, int64_t e) {
+    const int64_t j = A.ind[e];
+    const double v = A.val[e];
+    return j != i && v * v >= th2 * (d[i] * d[j]);
+  };
   Csr S;
   S.nr = S.nc = A.nr;
   S.ptr.assign(A.nr + 1, 0);
-  for (int64_t i = 0; i < A.nr; ++i) {
-    for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e) {
-      int64_t j = A.ind[e];
-      double v = A.val[e];
-      if (j != i && v * v >= th2 * (d[i] * d[j])) S.ind.push_back((int32_t)j);
+  parallel_rows(A.nr, [&](int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi; ++i) {
+      int64_t c = 0;
+      for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e) c += strong(i, e);
+      S.ptr[i + 1] = c;
     }
-    S.ptr[i + 1] = (int64_t)S.ind.size();
-  }
+  });
+  for (int64_t i = 0; i < A.nr; ++i) S.ptr[i + 1] += S.ptr[i];
+  S.ind.resize(S.ptr[A.nr]);
+  parallel_rows(A.nr, [&](int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi; ++i) {
+      int64_t o = S.ptr[i];
+      for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e)
+        if (strong(i, e)) S.ind[o++] = A.ind[e];
+    }
+  });
   S.val.assign(S.ind.size(), 1.0);
   return S;
 }
@@ -296,29 +313,56 @@ void sa_field(const Csr& A0, double theta, int max_coarse, int max_levels, std::
     }
     T.ptr[A.nr] = A.nr;
     // P = (I - omega D^-1 A) T, omega = (4/3) / max_i sum_j |a_ij| / a_ii
+    // (row sums in row order, so the bound does not depend on the thread count)
     std::vector<double> d = diagonal(A);
+    std::vector<double> ratio(A.nr);
+    parallel_rows(A.nr, [&](int64_t lo, int64_t hi) {
+      for (int64_t i = lo; i < hi; ++i) {
+        double s = 0.0;
+        for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e) s += std::fabs(A.val[e]);
+        ratio[i] = s / d[i];
+      }
+    });
     double rho = 0.0;
-    for (int64_t i = 0; i < A.nr; ++i) {
-      double s = 0.0;
-      for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e) s += std::fabs(A.val[e]);
-      rho = std::max(rho, s / d[i]);
-    }
+    for (int64_t i = 0; i < A.nr; ++i) rho = std::max(rho, ratio[i]);
     const double omega = (4.0 / 3.0) / rho;
     Csr DA = A;
-    for (int64_t i = 0; i < A.nr; ++i)
-      for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e) DA.val[e] = A.val[e] / d[i];
+    parallel_rows(A.nr, [&](int64_t lo, int64_t hi) {
+      for (int64_t i = lo; i < hi; ++i)
+        for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e) DA.val[e] = A.val[e] / d[i];
+    });
     Csr P = spgemm(DA, T);
-    for (int64_t i = 0; i < P.nr; ++i)
-      for (int64_t e = P.ptr[i]; e < P.ptr[i + 1]; ++e) {
-        double v = -omega * P.val[e];
-        if (P.ind[e] == agg[i]) v += T.val[i];
-        P.val[e] = v;
-      }
+    parallel_rows(P.nr, [&](int64_t lo, int64_t hi) {
+      for (int64_t i = lo; i < hi; ++i)
+        for (int64_t e = P.ptr[i]; e < P.ptr[i + 1]; ++e) {
+          double v = -omega * P.val[e];
+          if (P.ind[e] == agg[i]) v += T.val[i];
+          P.val[e] = v;
+        }
+    });
     A = galerkin(P, A);
     Ps.push_back(std::move(P));
     B = Bc;
     Bs.push_back(B);
   }
+}
+
+// One hierarchy per field, the fields on threads of their own (each field's
+// hierarchy is the same as when built alone).
+void sa_fields(const std::vector<Csr>& A, double theta, int max_coarse, int max_levels,
+               std::vector<std::vector<Csr>>& Ps, std::vector<std::vector<std::vector<double>>>& Bs) {
+  const size_t nf = A.size();
+  Ps.assign(nf, {});
+  Bs.assign(nf, {});
+  if (setup_threads() <= 1 || nf <= 1) {
+    for (size_t f = 0; f < nf; ++f) sa_field(A[f], theta, max_coarse, max_levels, Ps[f], Bs[f]);
+    return;
+  }
+  std::vector<std::future<void>> jobs;
+  for (size_t f = 0; f < nf; ++f)
+    jobs.push_back(std::async(std::launch::async, [&, f] { sa_field(A[f], theta, max_coarse, max_levels, Ps[f], Bs[f]); }));
+  for (auto& j : jobs) j.wait();
+  for (auto& j : jobs) j.get();  // rethrows the first field's error, if any
 }
 
 // ---------------------------------------------------------------------------

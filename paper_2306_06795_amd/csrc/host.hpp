@@ -67,6 +67,9 @@ struct FieldLevel {
 std::vector<int32_t> aggregate(const Csr& A, double theta, int32_t* n_agg);
 void sa_field(const Csr& A, double theta, int max_coarse, int max_levels,
               std::vector<Csr>& Ps, std::vector<std::vector<double>>& Bs);
+// sa_field for several fields at once, one thread per field.
+void sa_fields(const std::vector<Csr>& A, double theta, int max_coarse, int max_levels,
+               std::vector<std::vector<Csr>>& Ps, std::vector<std::vector<std::vector<double>>>& Bs);
 
 // ---- Vanka patches of one level (velocity rows sorted, then the seeds)
 struct PatchSet {

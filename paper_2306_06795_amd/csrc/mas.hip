@@ -1593,14 +1593,15 @@ void analyze_impl(mas_handle* h, const mas_problem* pr, bool dev = false, hipStr
   std::vector<std::vector<int64_t>> blocks(d + 1);
   for (int64_t i = 0; i < (int64_t)f1.size(); ++i) blocks[f1[i]].push_back(i);
   if ((int64_t)blocks[d].size() != Ap.nr) throw MasError(MAS_EINVAL, "Ap size does not match K1's pressure block");
-  std::vector<std::vector<Csr>> fP(d + 1);
-  std::vector<std::vector<std::vector<double>>> fB(d + 1);
-  size_t lmax = SIZE_MAX;
-  for (int f = 0; f <= d; ++f) {
-    Csr Af = (f < d) ? submatrix(K1f, blocks[f], blocks[f]) : Ap;
-    sa_field(Af, par.theta, par.max_coarse, par.max_levels, fP[f], fB[f]);
-    lmax = std::min(lmax, fP[f].size() + 1);
+  std::vector<std::vector<Csr>> fP;
+  std::vector<std::vector<std::vector<double>>> fB;
+  {
+    std::vector<Csr> Af;
+    for (int f = 0; f <= d; ++f) Af.push_back((f < d) ? submatrix(K1f, blocks[f], blocks[f]) : Ap);
+    sa_fields(Af, par.theta, par.max_coarse, par.max_levels, fP, fB);
   }
+  size_t lmax = SIZE_MAX;
+  for (int f = 0; f <= d; ++f) lmax = std::min(lmax, fP[f].size() + 1);
   tr.mark("smoothed aggregation");
   // levels: 0 = K0f, 1 = K1f, 2.. = Galerkin
   std::vector<Csr> Ks;
