@@ -171,12 +171,18 @@ int mas_upload(mas_handle* h, void* stream);
 
 /* Free every device resource of the handle (waits for the device first),
  * keeping the host analysis so that mas_upload can restore it without
- * repeating Algorithm 1.  mas_get_info then reports device_bytes = 0. */
+ * repeating Algorithm 1.  mas_get_info then reports device_bytes = 0.
+ * Errors: MAS_EINVAL for a NULL handle; releasing a released handle is a
+ * no-op. */
 int mas_release(mas_handle* h);
 
 /* z = B r: one defect-correction cycle (eq. (3.1)) applied to nrhs right-hand
- * sides.  r, z: device FP64, n0 x nrhs row-major (right-hand side fastest).
- * Dirichlet rows are returned unchanged (z_D = r_D).  Asynchronous. */
+ * sides.  r, z: device FP64, n0 x nrhs row-major (right-hand side fastest),
+ * owned by the caller and not retained; r is only read, and z must not
+ * overlap it.  Dirichlet rows are returned unchanged (z_D = r_D).
+ * Asynchronous on `stream` (NULL: the default stream).  Errors: MAS_EINVAL for
+ * NULL arguments, an analysed-only handle or nrhs outside [1, nrhs_max];
+ * MAS_EHIP when a launch fails (the contents of z are then undefined). */
 int mas_apply(mas_handle* h, const double* r, double* z, int32_t nrhs, void* stream);
 
 /* FGMRES for K0 x = b from x0 = 0 (Section 4).  b, x: device FP64 n0 x nrhs.
@@ -195,7 +201,8 @@ int mas_solve(mas_handle* h, const double* b, double* x, int32_t nrhs, double rt
 int mas_solve_rtols(mas_handle* h, const double* b, double* x, int32_t nrhs, const double* rtol,
                     int32_t max_it, mas_solve_info* info, void* stream);
 
-/* Sizes of the built hierarchy. */
+/* Sizes of the built hierarchy (host structure owned by the caller), and the
+ * device bytes the handle holds.  Errors: MAS_EINVAL for NULL arguments. */
 int mas_get_info(const mas_handle* h, mas_hier_info* out);
 
 /* x (device FP64, n0 x nrhs row-major): velocity rows of column k times s_u[k],
@@ -209,8 +216,11 @@ int mas_get_info(const mas_handle* h, mas_hier_info* out);
 int mas_scale_rows(mas_handle* h, double* x, int32_t nrhs, const double* s_u, const double* s_p,
                    int32_t dirichlet_inverse, void* stream);
 
-/* Copy level l's operator (0 = free K0, 1 = free K1, ...) to host CSR.  Call
- * with indptr == NULL to get the sizes. */
+/* Copy level l's operator (0 = free K0, 1 = free K1, ...) to host CSR arrays
+ * the caller owns and sizes: indptr nrows + 1, indices and data nnz.  Any of
+ * the five output pointers may be NULL and is then skipped (first call with
+ * the arrays NULL to get the sizes).  Works on analysed-only handles.
+ * Errors: MAS_EINVAL for a NULL handle or a level outside [0, n_levels). */
 int mas_export_level(const mas_handle* h, int32_t level, int64_t* nrows, int64_t* nnz,
                      int64_t* indptr, int32_t* indices, double* data);
 
@@ -225,9 +235,11 @@ int mas_export_level(const mas_handle* h, int32_t level, int64_t* nrows, int64_t
  * bytes: factor records, DoF lists, patch outputs, and each distinct level
  * vector entry read once; sparse products: values, column and row indices,
  * vectors. */
-int mas_set_timing(mas_handle* h, int32_t enable);
-int mas_get_timing(const mas_handle* h, double* out, int32_t n);
+int mas_set_timing(mas_handle* h, int32_t enable);  /* resets the sums; MAS_EINVAL: NULL */
+int mas_get_timing(const mas_handle* h, double* out, int32_t n);  /* MAS_EINVAL: NULL */
 
+/* Free the handle, its device memory and its host analysis (waits for the
+ * device first).  NULL is accepted and ignored. */
 int mas_destroy(mas_handle* h);
 const char* mas_error_string(int status);
 const char* mas_last_error(void);

@@ -172,3 +172,42 @@ def test_host_analysis_is_independent_of_the_thread_count(tmp_path):
     assert sorted(a.files) == sorted(b.files) and len(a.files) >= 9
     for k in a.files:
         assert np.array_equal(a[k].view(np.uint8), b[k].view(np.uint8)), k
+
+
+def test_documented_refusals_need_no_gpu():
+    """The argument checks of the C-ABI return their documented status before
+    any device call: NULL handles and arrays, levels out of range, and the
+    device calls of an analysed-only handle."""
+    import ctypes as C
+    lib = mas.lib
+    P = make_problem(dim=2, n=4)
+    h = mas.Handle(P, mas.default_params(2), analyze_only=True)
+    hi = mas.mas_hier_info()
+    assert lib.mas_get_info(None, C.byref(hi)) == mas.MAS_EINVAL
+    assert lib.mas_get_info(h.h, None) == mas.MAS_EINVAL
+    assert lib.mas_release(None) == mas.MAS_EINVAL
+    assert lib.mas_upload(None, None) == mas.MAS_EINVAL
+    assert lib.mas_set_timing(None, 1) == mas.MAS_EINVAL
+    out = (C.c_double * 18)()
+    assert lib.mas_get_timing(None, out, 18) == mas.MAS_EINVAL
+    assert lib.mas_destroy(None) == mas.MAS_OK
+    # export: sizes first (arrays NULL), then a level out of range
+    L = h.info()["n_levels"]
+    nr, nnz = C.c_int64(), C.c_int64()
+    assert lib.mas_export_level(h.h, 0, C.byref(nr), C.byref(nnz), None, None, None) == mas.MAS_OK
+    assert nr.value == int((~P.dir0).sum()) and nnz.value > 0
+    assert lib.mas_export_level(h.h, L, C.byref(nr), C.byref(nnz), None, None, None) == mas.MAS_EINVAL
+    assert lib.mas_export_level(h.h, -1, C.byref(nr), C.byref(nnz), None, None, None) == mas.MAS_EINVAL
+    # device calls on an analysed-only handle (host buffers: never dereferenced)
+    buf = np.zeros(P.n0, np.float64)
+    p = C.c_void_p(buf.ctypes.data)
+    info = (mas.mas_solve_info * 1)()
+    assert lib.mas_solve(h.h, p, p, 1, 1e-8, 10, info, None) == mas.MAS_EINVAL
+    tol = (C.c_double * 1)(1e-8)
+    assert lib.mas_solve_rtols(h.h, p, p, 1, tol, 10, info, None) == mas.MAS_EINVAL
+    one = (C.c_double * 1)(1.0)
+    assert lib.mas_scale_rows(h.h, p, 1, one, one, 0, None) == mas.MAS_EINVAL
+    assert lib.mas_apply(h.h, p, p, 1, None) == mas.MAS_EINVAL
+    assert b"analysed only" in lib.mas_last_error()
+    assert lib.mas_release(h.h) == mas.MAS_OK  # nothing on the device: a no-op
+    h.close()
