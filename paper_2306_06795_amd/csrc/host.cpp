@@ -130,11 +130,8 @@ Csr spgemm(const Csr& A, const Csr& B) {
   C.ind.resize(C.ptr[C.nr]);
   C.val.resize(C.ptr[C.nr]);
   parallel_rows(A.nr, [&](int64_t lo, int64_t hi) {
-    struct Slot {
-      int64_t mark;  // last row that touched the column
-      double acc;
-    };
-    std::vector<Slot> slot(B.nc, Slot{-1, 0.0});  // mark and sum share a cache line
+    std::vector<int64_t> mark(B.nc, -1);
+    std::vector<double> acc(B.nc, 0.0);
     std::vector<int32_t> cols;
     for (int64_t i = lo; i < hi; ++i) {
       cols.clear();
@@ -142,13 +139,13 @@ Csr spgemm(const Csr& A, const Csr& B) {
         const int64_t k = A.ind[a];
         const double av = A.val[a];
         for (int64_t b = B.ptr[k]; b < B.ptr[k + 1]; ++b) {
-          Slot& q = slot[B.ind[b]];
-          if (q.mark != i) {
-            q.mark = i;
-            cols.push_back(B.ind[b]);
-            q.acc = av * B.val[b];
+          const int64_t j = B.ind[b];
+          if (mark[j] != i) {
+            mark[j] = i;
+            cols.push_back((int32_t)j);
+            acc[j] = av * B.val[b];
           } else {
-            q.acc += av * B.val[b];
+            acc[j] += av * B.val[b];
           }
         }
       }
@@ -156,7 +153,7 @@ Csr spgemm(const Csr& A, const Csr& B) {
       int64_t o = C.ptr[i];
       for (int32_t j : cols) {
         C.ind[o] = j;
-        C.val[o] = slot[j].acc;
+        C.val[o] = acc[j];
         ++o;
       }
     }
