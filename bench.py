@@ -45,6 +45,8 @@ def parse():
                     help="FGMRES-wrapped Vanka relaxation with this many iterations (0: stationary sweeps)")
     ap.add_argument("--dlsc-amg", type=int, default=0,
                     help="DLSC continuity/pressure stages by one SA V-cycle with this many Jacobi sweeps (0: Chebyshev)")
+    ap.add_argument("--theta", type=float, default=None,
+                    help="strength-of-connection threshold of Algorithm 1 (default: the library's)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -102,13 +104,14 @@ def stream_copy_gbs(torch, dev, mib=1024, reps=10):
     return gbs
 
 
-def cpu_baseline(prob, its_gpu, sample_its, relax="vanka", krylov_its=0, schedule="all", dlsc_amg=0):
+def cpu_baseline(prob, its_gpu, sample_its, relax="vanka", krylov_its=0, schedule="all", dlsc_amg=0, theta=None):
     """The oracle on the host: setup untimed, then ``sample_its`` FGMRES
     iterations of the same workload (first right-hand side) timed and scaled to
     one full solve."""
     from oracle import dc, fgmres
+    over = {} if theta is None else {"theta": theta}
     pre = dc.DCPreconditioner(prob, dc.default_params(prob, relax, krylov_its=krylov_its, schedule=schedule,
-                                                          dlsc_amg=dlsc_amg))
+                                                          dlsc_amg=dlsc_amg, **over))
     b0 = prob.b if prob.b.ndim == 1 else np.ascontiguousarray(prob.b[:, 0])
     pre.apply(b0)  # untimed: builds the oracle's dense patch matrices once
     t0 = time.perf_counter()
@@ -287,9 +290,12 @@ def main():
     method = "HO-AMG" if a.schedule == "ho" else f"DC-{a.schedule}"
     if a.schedule != "all":
         label += f"+{a.schedule}"
+    over = {} if a.theta is None else {"theta": a.theta}
+    if a.theta is not None:  # another hierarchy: no counter figure of the default one applies
+        label += f"+theta{a.theta:g}"
     mp = mas.default_params(prob.dim, mas.MAS_SV if prob.disc == "SV" else mas.MAS_TH, relax, precision=prec,
                             nrhs_max=nrhs, krylov_its=a.krylov_its, schedule=sched[a.schedule],
-                            dlsc_amg=a.dlsc_amg)
+                            dlsc_amg=a.dlsc_amg, **over)
     t0 = time.perf_counter()
     h = mas.Handle(prob, mp)
     torch.cuda.synchronize()
@@ -336,7 +342,7 @@ def main():
     if prec == mas.MAS_FP32:  # error of the mixed-precision result against the FP64 cycle's (to 1e-10)
         mp64 = mas.default_params(prob.dim, mas.MAS_SV if prob.disc == "SV" else mas.MAS_TH, relax,
                                   precision=mas.MAS_FP64, nrhs_max=nrhs, krylov_its=a.krylov_its,
-                                  schedule=sched[a.schedule], dlsc_amg=a.dlsc_amg)
+                                  schedule=sched[a.schedule], dlsc_amg=a.dlsc_amg, **over)
         h64 = mas.Handle(prob, mp64)
         x64 = torch.empty_like(b)
         h64.solve(b, x64, rtol=1e-10, nrhs=nrhs)
@@ -420,7 +426,7 @@ def main():
     }
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, its_last, a.cpu_sample_its, a.relax, a.krylov_its, a.schedule,
-                                          a.dlsc_amg)
+                                          a.dlsc_amg, a.theta)
     print(json.dumps(out))
     h.close()
 
