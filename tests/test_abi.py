@@ -211,3 +211,30 @@ def test_documented_refusals_need_no_gpu():
     assert b"analysed only" in lib.mas_last_error()
     assert lib.mas_release(h.h) == mas.MAS_OK  # nothing on the device: a no-op
     h.close()
+
+
+@pytest.mark.parametrize("kw", [dict(dim=2, n=1), dict(dim=3, n=1), dict(dim=2, n=1, disc="SV", seed=1)])
+def test_single_cell_meshes_analyse_under_every_variant(kw):
+    """Degenerate inputs: one square or cube (2 / 11 free unknowns for
+    Taylor-Hood).  Every relaxation and schedule either builds a two-level
+    hierarchy whose coarsest level is K1 itself (solved exactly) or refuses
+    with its documented error (HO-AMG on Scott-Vogelius)."""
+    bc = "zero" if kw.get("disc") == "SV" else "lid"
+    P = make_problem(forcing="gaussian", bc=bc, **kw)
+    disc = mas.MAS_SV if P.disc == "SV" else mas.MAS_TH
+    nfree = int((~P.dir0).sum())
+    for relax in (mas.MAS_RELAX_VANKA, mas.MAS_RELAX_DLSC, mas.MAS_RELAX_VANKA_DLSC):
+        for sched in (mas.MAS_DC_ALL, mas.MAS_DC_SKIP1, mas.MAS_DC_SKIP0, mas.MAS_HO_AMG):
+            par = mas.default_params(P.dim, disc, relax, schedule=sched)
+            if disc == mas.MAS_SV and sched == mas.MAS_HO_AMG:
+                with pytest.raises(mas.MasError) as e:
+                    mas.Handle(P, par, analyze_only=True)
+                assert e.value.code == mas.MAS_EINVAL
+                continue
+            h = mas.Handle(P, par, analyze_only=True)
+            i = h.info()
+            h.close()
+            assert i["n_levels"] == 2 and i["n"][0] == nfree
+            assert i["n_patches"][1] == 0  # the coarsest level is not relaxed
+            vanka_on_k0 = relax != mas.MAS_RELAX_DLSC and sched not in (mas.MAS_DC_SKIP0, mas.MAS_HO_AMG)
+            assert (i["n_patches"][0] > 0) == vanka_on_k0
