@@ -153,7 +153,9 @@ void mas_default_params(int32_t dim, int32_t disc, int32_t relax, mas_params* ou
  * aggregation), the Vanka patches of every relaxed level with their block
  * factorisation computed on the GPU in FP64 (eqs. (3.6)-(3.8)), or the DLSC
  * operators, and the dense coarsest-level inverse.
- * Errors: MAS_EINVAL, MAS_ESINGULAR_PATCH, MAS_ENOMEM, MAS_EHIP. */
+ * Errors: MAS_EINVAL (also when a field's coarsening stops above
+ * max(max_coarse, 4096) unknowns, which the dense coarsest solve would not
+ * take), MAS_ESINGULAR_PATCH, MAS_ENOMEM, MAS_EHIP. */
 int mas_setup(const mas_problem* prob, const mas_params* par, void* stream, mas_handle** out);
 
 /* Host-only analysis: the hierarchy (Algorithm 1) and the patches, without

@@ -7,6 +7,7 @@
 #include <future>
 #include <numeric>
 #include <stdexcept>
+#include <string>
 #include <thread>
 
 namespace mas {
@@ -345,6 +346,16 @@ void sa_field(const Csr& A0, double theta, int max_coarse, int max_levels, std::
     B = Bc;
     Bs.push_back(B);
   }
+  // The coarsest level is solved through a dense inverse.  A coarsening that
+  // stopped far above max_coarse (too few strong connections for the
+  // threshold, or max_levels reached) is refused instead of inverting a matrix
+  // of that size; a max_coarse at least as large accepts it.
+  constexpr int64_t kMaxDenseField = 4096;
+  if (A.nr > std::max<int64_t>(max_coarse, kMaxDenseField))
+    throw std::runtime_error("smoothed aggregation stopped at " + std::to_string(A.nr) +
+                             " unknowns of one field, more than the dense coarsest solve takes (" +
+                             std::to_string(std::max<int64_t>(max_coarse, kMaxDenseField)) +
+                             "): lower theta, or raise max_levels or max_coarse");
 }
 
 // One hierarchy per field, the fields on threads of their own (each field's

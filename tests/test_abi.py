@@ -238,3 +238,17 @@ def test_single_cell_meshes_analyse_under_every_variant(kw):
             assert i["n_patches"][1] == 0  # the coarsest level is not relaxed
             vanka_on_k0 = relax != mas.MAS_RELAX_DLSC and sched not in (mas.MAS_DC_SKIP0, mas.MAS_HO_AMG)
             assert (i["n_patches"][0] > 0) == vanka_on_k0
+
+
+def test_stalled_coarsening_is_refused_before_a_huge_dense_solve():
+    """The coarsest level is inverted densely: a threshold that leaves (almost)
+    no strong connections stops the coarsening at the fine size, and the
+    analysis refuses it (EINVAL, naming the cause) unless max_coarse accepts a
+    coarsest level that large."""
+    P = make_problem(dim=2, n=48, jitter=0.2, seed=2, forcing="gaussian", bc="lid")
+    with pytest.raises(mas.MasError) as e:
+        mas.Handle(P, mas.default_params(2, theta=0.9), analyze_only=True)
+    assert e.value.code == mas.MAS_EINVAL and "coarsest" in str(e.value)
+    h = mas.Handle(P, mas.default_params(2, theta=0.9, max_coarse=10 ** 6), analyze_only=True)
+    assert h.info()["n_levels"] == 2
+    h.close()
