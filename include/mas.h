@@ -104,7 +104,7 @@ typedef struct {
                              krylov_its > 0) */
   double omega0, omega;   /* Vanka damping on K0 and on the K1 hierarchy */
   double eta_u, eta_p;    /* residual weights of eq. (3.2) */
-  int32_t cheb_deg[3];    /* DLSC Chebyshev degrees (momentum, continuity, pressure; Table 3) */
+  int32_t cheb_deg[3];    /* DLSC Chebyshev degrees (momentum, continuity, pressure; Table 2) */
   int32_t precision;      /* mas_precision of the cycle (FGMRES is always FP64) */
   int32_t restart;        /* FGMRES restart length (20 in Section 4) */
   int32_t max_coarse;     /* per-field coarsest size of smoothed aggregation */
@@ -119,10 +119,10 @@ typedef struct {
                              K0 of Scott-Vogelius (stationary there); one right-hand side per call */
   int32_t nu_dlsc;        /* MAS_RELAX_VANKA_DLSC: DLSC sweeps pre and post on the K1 hierarchy
                              (2, the DLSC sweep count of Section 4); unused otherwise */
-  int32_t dlsc_amg;       /* 0: DLSC continuity and pressure-correction stages by Chebyshev (Table 3);
+  int32_t dlsc_amg;       /* 0: DLSC continuity and pressure-correction stages by Chebyshev (Table 2);
                              k = 1..8: each by one smoothed-aggregation V-cycle on B M^-1 B^T with k
                              weighted-Jacobi sweeps (weight 4/3 over the largest absolute row sum of
-                             D^-1 S) before and after the coarse correction (Section 4) */
+                             D^-1 S) before and after the coarse correction (Section 5) */
 } mas_params;
 
 typedef struct {
@@ -146,7 +146,7 @@ typedef struct {
   int64_t device_bytes;   /* device memory held by the handle (0 after mas_analyze) */
 } mas_hier_info;
 
-/* Default parameters: Section 4 / Tables 3 and 4 where the paper fixes them. */
+/* Default parameters: Section 4 / Tables 2 and 4 where the paper fixes them. */
 void mas_default_params(int32_t dim, int32_t disc, int32_t relax, mas_params* out);
 
 /* Build the hierarchy (Algorithm 1 on K1 and A_p, per-field smoothed

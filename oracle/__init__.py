@@ -9,7 +9,7 @@ Tuminaro, arXiv 2306.06795), written from the paper:
   vanka.py   algebraic Vanka patches and additive Vanka with a dense LU solve
              of every full patch matrix (Section 3.3.1)
   dlsc.py    Chebyshev semi-iteration and the DLSC sweep (Algorithm 2,
-             Section 3.3.2, Table 3)
+             Section 3.3.2, Table 2)
   dc.py      the defect-correction cycle, eq. (3.1) with eq. (3.2) and the
              multilevel eq. (3.4); schedules DC-all / DC-skip1 / DC-skip0, and
              HO-AMG (Algorithm 1 applied to K0, the remark after it)

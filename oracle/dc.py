@@ -51,7 +51,8 @@ class Params:
     eta_u: float = 1.0
     eta_p: float = 1.0
     cheb: tuple | None = None  # DLSC Chebyshev degrees (momentum, continuity, pressure)
-    theta: float = 0.02
+    soc: str = "evolution"  # strength of connection: "evolution" (Section 3.2) or "symmetric"
+    theta: float = 0.02  # threshold of the symmetric measure (not read by the evolution measure)
     max_coarse: int = 300
     max_levels: int = 10
     seed: int = 0x5EED
@@ -81,7 +82,8 @@ class DCPreconditioner:
             free1 = np.nonzero(~prob.dir1)[0]
             K1 = submatrix(prob.K1, free1, free1)
             f1 = prob.field1[free1]
-        self.levels = stokes_hierarchy(K1, f1, prob.Ap, d, par.theta, par.max_coarse, par.max_levels)
+        self.levels = stokes_hierarchy(K1, f1, prob.Ap, d, par.theta, par.max_coarse, par.max_levels,
+                                       par.soc)
         self.nvel = int((self.f0 < d).sum())
         assert self.nvel == int((f1 < d).sum())
         L = len(self.levels)
@@ -110,7 +112,8 @@ class DCPreconditioner:
                 mu = prob.mu_diag0[self.free0[:nv]] if on_k0 else np.ones(nv)
                 amg = None
                 if par.dlsc_amg > 0:
-                    amg = (par.theta, par.max_coarse, par.max_levels, par.dlsc_amg, bool(prob.p_nullspace))
+                    amg = (par.theta, par.max_coarse, par.max_levels, par.dlsc_amg, bool(prob.p_nullspace),
+                           par.soc)
                 self.relax.append(DLSCLevel(K, f, d, mu, cheb, par.seed + 2 * l, amg))
         # coarsest level: dense LU of the (bordered) operator
         last = self.levels[-1]

@@ -1,5 +1,5 @@
 """Chebyshev polynomial relaxation and the DLSC sweep (Algorithm 2,
-Section 3.3.2, Table 3).  Test infrastructure (oracle).
+Section 3.3.2, Table 2).  Test infrastructure (oracle).
 
 Readings:
   * Chebyshev "degree k" on [a, b] = [0.5^d lambda, 1.1 lambda] is k steps of
@@ -10,7 +10,7 @@ Readings:
     reorthogonalisation) from a SplitMix64 start vector.
   * The sign of the pressure correction is the one of Algorithm 2:
     delta p solves S delta p = -(B M^-1 A M^-1 B^T) q, S = B M^-1 B^T.
-  * AMG stages (Section 4, the application problems): the continuity and
+  * AMG stages (Section 5, the application problems): the continuity and
     pressure-correction stages may instead take one smoothed-aggregation
     V-cycle on S (Algorithm 1's scalar SA, constants as near-null vector)
     with `sweeps` weighted-Jacobi sweeps before and after the coarse
@@ -77,9 +77,10 @@ def chebyshev(matvec, r: np.ndarray, lo: float, hi: float, degree: int) -> np.nd
 class SAVcycle:
     """One V-cycle of smoothed aggregation with weighted Jacobi for S y = r."""
 
-    def __init__(self, S, theta: float, max_coarse: int, max_levels: int, sweeps: int, singular: bool):
+    def __init__(self, S, theta: float, max_coarse: int, max_levels: int, sweeps: int, singular: bool,
+                 soc: str = "evolution"):
         S = csr(S)
-        Ps, Bs = field_hierarchy(S, theta, max_coarse, max_levels)
+        Ps, Bs = field_hierarchy(S, theta, max_coarse, max_levels, soc)
         self.ops = [S]
         for P in Ps:
             self.ops.append(galerkin(P, self.ops[-1]))
@@ -140,7 +141,7 @@ class DLSCLevel:
         self.lam_A = lanczos_max(lambda v: self.A @ v, self.iv.size, seed)
         self.lam_S = lanczos_max(self.S, self.ip.size, seed + 1)
         self.svc = None
-        if amg is not None:  # (theta, max_coarse, max_levels, sweeps, singular)
+        if amg is not None:  # (theta, max_coarse, max_levels, sweeps, singular, soc)
             Bt = csr(self.B.T)
             S = pattern_product(self.B, csr(sp.diags(self.minv) @ Bt))
             self.svc = SAVcycle(S, *amg)

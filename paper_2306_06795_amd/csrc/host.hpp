@@ -1,6 +1,6 @@
 // Host-side setup of libmas: sparse matrices, per-field smoothed aggregation
 // (Algorithm 1), algebraic Vanka patches (Section 3.3.1), Lanczos estimates
-// for the Chebyshev intervals (Table 3).  Plain C++17, no HIP.
+// for the Chebyshev intervals (Table 2).  Plain C++17, no HIP.
 #pragma once
 #include <cstdint>
 #include <functional>

@@ -228,7 +228,7 @@ __global__ void k_axpby(int64_t n, T a, const T* __restrict__ x, T b, T* __restr
 }
 
 // ---------------------------------------------------------------------------
-// Chebyshev semi-iteration and DLSC helpers (Algorithm 2, Table 3)
+// Chebyshev semi-iteration and DLSC helpers (Algorithm 2, Table 2)
 
 // d = D^-1 r / theta, res = r, y = d   (D^-1 = dinv, identity when null; nr
 // right-hand sides interleaved, entry i belongs to row i / nr)

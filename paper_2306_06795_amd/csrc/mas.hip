@@ -336,7 +336,7 @@ struct DDlsc {
   T *ru = nullptr, *vs = nullptr, *tmp = nullptr, *t1 = nullptr, *t2 = nullptr;  // velocity-sized
   T *rp = nullptr, *q = nullptr, *dp = nullptr;                                 // pressure-sized
   T *cd = nullptr, *cd2 = nullptr, *cres = nullptr;                             // Chebyshev work (max size)
-  // AMG stages (Section 4): a smoothed-aggregation hierarchy of S with weighted Jacobi
+  // AMG stages (Section 5): a smoothed-aggregation hierarchy of S with weighted Jacobi
   struct SLev {
     int64_t n = 0;
     DCsr<T> S, P, R;          // S_k; P: S_k <- S_{k+1}, R = P^T
@@ -513,7 +513,7 @@ struct Cycle : CycleBase {
     }
   }
 
-  // DLSC inner solves: interval [0.5^dim lam, 1.1 lam] (Table 3)
+  // DLSC inner solves: interval [0.5^dim lam, 1.1 lam] (Table 2)
   void chebyshev(DCsr<T>& X, const T* r, T* y, double lam, int deg, DDlsc<T>& D, hipStream_t s,
                  bool started = false) {
     chebyshev_iv(X, r, y, std::pow(0.5, dim) * lam, 1.1 * lam, deg, nullptr, D.cd, D.cd2, D.cres, s, started);
@@ -530,7 +530,7 @@ struct Cycle : CycleBase {
   }
 
   // y = one V-cycle of smoothed aggregation with weighted Jacobi for S_k y = b
-  // (the DLSC AMG stages, Section 4).  Jacobi in residual form is the fused
+  // (the DLSC AMG stages, Section 5).  Jacobi in residual form is the fused
   // Chebyshev step with a = 0 and c = 1 (the weight is folded into wdinv):
   // res -= S d, d = wdinv res, acc += d.
   void s_vcycle(DDlsc<T>& D, size_t k, const T* b, T* x, hipStream_t s) {
@@ -1469,7 +1469,7 @@ std::unique_ptr<Cycle<T>> build_cycle(mas_handle* h, const std::vector<Csr>& Ks,
   return cyc;
 }
 
-// The smoothed-aggregation hierarchy of S for the DLSC AMG stages (Section 4):
+// The smoothed-aggregation hierarchy of S for the DLSC AMG stages (Section 5):
 // Algorithm 1's scalar SA on S, Galerkin products, Jacobi weight (4/3) / rho
 // with rho = max_i sum_j |s_ij| / s_ii per level, and the coarsest operator as
 // a dense matrix, bordered with its near-null vector when S is singular.

@@ -174,7 +174,7 @@ def test_wrapped_cycle_converges_and_sv_keeps_stationary_k0():
 
 
 # --------------------------------------------------------------------------
-# Chebyshev and DLSC (Algorithm 2, Table 3)
+# Chebyshev and DLSC (Algorithm 2, Table 2)
 
 def cheb_T(k, x):
     return np.cos(k * np.arccos(x)) if abs(x) <= 1 else np.cosh(k * np.arccosh(abs(x))) * (np.sign(x) ** k)
