@@ -62,6 +62,19 @@ enum mas_relax { MAS_RELAX_VANKA = 0, MAS_RELAX_DLSC = 1, MAS_RELAX_VANKA_DLSC =
  * only: mas_setup/mas_analyze return MAS_EINVAL for Scott-Vogelius. */
 enum mas_schedule { MAS_DC_ALL = 0, MAS_DC_SKIP1 = 1, MAS_DC_SKIP0 = 2, MAS_HO_AMG = 3 };
 enum mas_precision { MAS_FP64 = 0, MAS_FP32 = 1 };        /* number type of the cycle */
+/* Strength of connection of Algorithm 1.  MAS_SOC_EVOLUTION: the evolution
+ * measure Section 3.2 uses (Olson, Schroder, Tuminaro, NLAA 2010): two Jacobi
+ * steps z_i = (I - dt D^-1 A)^2 e_i, dt = 1 / max_i sum_j |a_ij| / a_ii; for a
+ * stored neighbour j, s_ij = |zt_j - z_i[j]| / |z_i[j]| with zt = z_i[i] B / B_i
+ * (B the level's near-null vector), infinite when z_i[j] = 0 or zt_j z_i[j] <= 0,
+ * floored at 1e-4; j is strong for i when s_ij <= soc_eps min_k s_ik; the graph
+ * is symmetrised (union).  MAS_SOC_SYMMETRIC: a_ij^2 >= theta^2 a_ii a_jj, the
+ * classical measure Section 3.2 reports needed tuning. */
+enum mas_soc { MAS_SOC_EVOLUTION = 0, MAS_SOC_SYMMETRIC = 1 };
+/* Orthogonalisation of the FGMRES Arnoldi step (Section 4): classical
+ * Gram-Schmidt in one pass (every dot product of the step in one sweep over
+ * the basis), or modified Gram-Schmidt (one basis vector at a time). */
+enum mas_gram_schmidt { MAS_GS_CLASSICAL = 0, MAS_GS_MODIFIED = 1 };
 
 /* CSR matrix in host memory: row pointers int64 (nrows+1), column indices
  * int32 (sorted within each row), values FP64.  Explicitly stored zeros are
@@ -109,7 +122,7 @@ typedef struct {
   int32_t restart;        /* FGMRES restart length (20 in Section 4) */
   int32_t max_coarse;     /* per-field coarsest size of smoothed aggregation */
   int32_t max_levels;     /* per-field maximum number of levels */
-  double theta;           /* strength threshold: a_ij^2 >= theta^2 a_ii a_jj */
+  double theta;           /* threshold of MAS_SOC_SYMMETRIC: a_ij^2 >= theta^2 a_ii a_jj */
   uint64_t seed;          /* SplitMix64 seed of the Lanczos start vectors */
   double mass_rtol;       /* relative tolerance of the SV pressure-mass solve */
   int32_t nrhs_max;       /* most right-hand sides one mas_apply / mas_solve may carry (1..64) */
@@ -123,6 +136,23 @@ typedef struct {
                              k = 1..8: each by one smoothed-aggregation V-cycle on B M^-1 B^T with k
                              weighted-Jacobi sweeps (weight 4/3 over the largest absolute row sum of
                              D^-1 S) before and after the coarse correction (Section 5) */
+  int32_t soc;            /* mas_soc (MAS_SOC_EVOLUTION) */
+  double soc_eps;         /* evolution filter epsilon (4) */
+  int32_t gram_schmidt;   /* mas_gram_schmidt of mas_solve (MAS_GS_CLASSICAL) */
+  int32_t autotune;       /* 1: each sparse product's kernel (sliced-ELL or CSR, lanes per row) is
+                             chosen by timing at setup, so the summation order of a row may differ
+                             between setups; 0: a fixed rule of the operator's shape (the same
+                             choice, bit for bit the same results, in every setup) */
+  int32_t graphs;         /* 1: each FGMRES iteration replays a captured hipGraph; 0: eager launches
+                             (same results) */
+  int32_t full_patch_min; /* patch size from which a level without fixed-shape buckets stores its
+                             A_c^-1 blocks full instead of packed (512) */
+  int32_t bucket_min;     /* fewest patches of one fixed shape that get a thread-per-patch bucket
+                             (64); smaller groups take the generic patch kernel */
+  int32_t factor_blocked; /* 1: blocked Gauss-Jordan for patch blocks whose panel fits in LDS;
+                             0: single-pivot Gauss-Jordan everywhere */
+  int32_t device_galerkin;/* 1: the Galerkin products of Algorithm 1 run on the device (same
+                             values as the host's, bit for bit); 0: on the host */
 } mas_params;
 
 typedef struct {

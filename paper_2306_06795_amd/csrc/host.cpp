@@ -207,23 +207,34 @@ static std::vector<double> diagonal(const Csr& A) {
   return d;
 }
 
-// strong neighbours: j != i with a_ij^2 >= theta^2 (a_ii a_jj); rows counted,
-// then filled, in parallel (the pattern does not depend on the thread count)
-static Csr strength(const Csr& A, double theta) {
-  std::vector<double> d = diagonal(A);
-  const double th2 = theta * theta;
-  auto strong = [&](int64_t i, int64_t e) {
-    const int64_t j = A.ind[e];
-    const double v = A.val[e];
-    return j != i && v * v >= th2 * (d[i] * d[j]);
-  };
+// Gershgorin bound max_i sum_j |a_ij| / a_ii of rho(D^-1 A), each row summed in
+// row order (the same bound sets the evolution time step and the smoothing
+// weight; it does not depend on the thread count).
+static double gershgorin_rho(const Csr& A, const std::vector<double>& d) {
+  std::vector<double> ratio(A.nr);
+  parallel_rows(A.nr, [&](int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi; ++i) {
+      double s = 0.0;
+      for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e) s += std::fabs(A.val[e]);
+      ratio[i] = s / d[i];
+    }
+  });
+  double rho = 0.0;
+  for (int64_t i = 0; i < A.nr; ++i) rho = std::max(rho, ratio[i]);
+  return rho;
+}
+
+// Strong-pattern builder: keep(i, e) decides entry e of row i; rows are counted,
+// then filled, in parallel.
+template <class Keep>
+static Csr select_entries(const Csr& A, Keep keep) {
   Csr S;
   S.nr = S.nc = A.nr;
   S.ptr.assign(A.nr + 1, 0);
   parallel_rows(A.nr, [&](int64_t lo, int64_t hi) {
     for (int64_t i = lo; i < hi; ++i) {
       int64_t c = 0;
-      for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e) c += strong(i, e);
+      for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e) c += keep(i, e) ? 1 : 0;
       S.ptr[i + 1] = c;
     }
   });
@@ -233,15 +244,113 @@ static Csr strength(const Csr& A, double theta) {
     for (int64_t i = lo; i < hi; ++i) {
       int64_t o = S.ptr[i];
       for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e)
-        if (strong(i, e)) S.ind[o++] = A.ind[e];
+        if (keep(i, e)) S.ind[o++] = A.ind[e];
     }
   });
   S.val.assign(S.ind.size(), 1.0);
   return S;
 }
 
-std::vector<int32_t> aggregate(const Csr& A, double theta, int32_t* n_agg) {
-  Csr S = strength(A, theta);
+// Classical symmetric strength: j != i with a_ij^2 >= theta^2 (a_ii a_jj).
+static Csr strength_symmetric(const Csr& A, double theta) {
+  std::vector<double> d = diagonal(A);
+  const double th2 = theta * theta;
+  return select_entries(A, [&](int64_t i, int64_t e) {
+    const int64_t j = A.ind[e];
+    const double v = A.val[e];
+    return j != i && v * v >= th2 * (d[i] * d[j]);
+  });
+}
+
+// Evolution strength (Section 3.2; Olson, Schroder, Tuminaro, NLAA 2010), two
+// relaxation steps.  With J = I - dt D^-1 A (dt = 1 / Gershgorin bound), the
+// evolved delta of point i is z_i = J J e_i, so for a stored neighbour j
+//   z_i[j] = sum_m J[j][m] J[m][i]      (m over row j of A, ascending),
+// read from row j of A and column i of A (row i of A^T, held as a dense
+// column of J per row i in a thread-private scratch).  The near-null vector
+// B gives the constrained approximation zt_j = z_i[i] B_j / B_i, and
+//   s_ij = max(|zt_j - z_i[j]| / |z_i[j]|, 1e-4),
+// infinite when z_i[j] = 0 or zt_j z_i[j] <= 0.  Row i keeps j when
+// s_ij <= eps * min_m s_im (finite), and the graph is the union of the kept
+// pairs and their transposes.
+static Csr strength_evolution(const Csr& A, const std::vector<double>& B, double eps) {
+  const int64_t n = A.nr;
+  std::vector<double> d = diagonal(A);
+  const double dt = 1.0 / gershgorin_rho(A, d);
+  const Csr At = transpose(A);
+  // J[r][c] for stored (r, c) of A: delta_rc - dt * ((1 / d_r) a_rc)
+  auto jv = [&](int64_t r, int64_t c, double a) { return (r == c ? 1.0 : 0.0) - dt * ((1.0 / d[r]) * a); };
+  std::vector<double> s(A.nnz());
+  std::vector<char> keep(A.nnz(), 0);
+  parallel_rows(n, [&](int64_t lo, int64_t hi) {
+    std::vector<double> colJ(n, 0.0);
+    std::vector<int64_t> mark(n, -1);
+    for (int64_t i = lo; i < hi; ++i) {
+      // column i of J: J[m][i] for m with a_mi stored
+      for (int64_t e = At.ptr[i]; e < At.ptr[i + 1]; ++e) {
+        const int64_t m = At.ind[e];
+        colJ[m] = jv(m, i, At.val[e]);
+        mark[m] = i;
+      }
+      auto zcol = [&](int64_t r) {  // z_i[r] = sum_m J[r][m] J[m][i]
+        double z = 0.0;
+        for (int64_t e = A.ptr[r]; e < A.ptr[r + 1]; ++e) {
+          const int64_t m = A.ind[e];
+          if (mark[m] == i) z += jv(r, m, A.val[e]) * colJ[m];
+        }
+        return z;
+      };
+      const double zii = zcol(i);
+      double smin = INFINITY;
+      for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e) {
+        const int64_t j = A.ind[e];
+        s[e] = INFINITY;
+        if (j == i) continue;
+        const double zij = zcol(j);
+        const double zt = zii * B[j] / B[i];
+        if (zij != 0.0 && zt * zij > 0.0) s[e] = std::max(std::fabs(zt - zij) / std::fabs(zij), 1e-4);
+        smin = std::min(smin, s[e]);
+      }
+      for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e)
+        keep[e] = A.ind[e] != i && std::isfinite(s[e]) && s[e] <= eps * smin;
+    }
+  });
+  Csr S1 = select_entries(A, [&](int64_t, int64_t e) { return keep[e] != 0; });
+  const Csr S1t = transpose(S1);
+  // union of S1 and its transpose, rows sorted
+  Csr S;
+  S.nr = S.nc = n;
+  S.ptr.assign(n + 1, 0);
+  auto merge = [&](int64_t i, int32_t* out) {
+    int64_t a = S1.ptr[i], ae = S1.ptr[i + 1], b = S1t.ptr[i], be = S1t.ptr[i + 1], c = 0;
+    while (a < ae || b < be) {
+      int32_t v;
+      if (b >= be || (a < ae && S1.ind[a] < S1t.ind[b])) v = S1.ind[a++];
+      else if (a >= ae || S1t.ind[b] < S1.ind[a]) v = S1t.ind[b++];
+      else { v = S1.ind[a++]; ++b; }
+      if (out) out[c] = v;
+      ++c;
+    }
+    return c;
+  };
+  parallel_rows(n, [&](int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi; ++i) S.ptr[i + 1] = merge(i, nullptr);
+  });
+  for (int64_t i = 0; i < n; ++i) S.ptr[i + 1] += S.ptr[i];
+  S.ind.resize(S.ptr[n]);
+  parallel_rows(n, [&](int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi; ++i) merge(i, &S.ind[S.ptr[i]]);
+  });
+  S.val.assign(S.ind.size(), 1.0);
+  return S;
+}
+
+Csr strength_graph(const Csr& A, const std::vector<double>& B, const SocParams& soc) {
+  if (soc.kind == 1) return strength_symmetric(A, soc.theta);
+  return strength_evolution(A, B, soc.eps);
+}
+
+std::vector<int32_t> aggregate(const Csr& S, int32_t* n_agg) {
   const int64_t n = S.nr;
   std::vector<int32_t> agg(n, -1);
   std::vector<char> first(n, 0);
@@ -285,7 +394,7 @@ std::vector<int32_t> aggregate(const Csr& A, double theta, int32_t* n_agg) {
   return agg;
 }
 
-void sa_field(const Csr& A0, double theta, int max_coarse, int max_levels, std::vector<Csr>& Ps,
+void sa_field(const Csr& A0, const SocParams& soc, int max_coarse, int max_levels, std::vector<Csr>& Ps,
               std::vector<std::vector<double>>& Bs) {
   Ps.clear();
   Bs.clear();
@@ -294,7 +403,7 @@ void sa_field(const Csr& A0, double theta, int max_coarse, int max_levels, std::
   Csr A = A0;
   while (A.nr > max_coarse && (int)Ps.size() + 1 < max_levels) {
     int32_t nc = 0;
-    std::vector<int32_t> agg = aggregate(A, theta, &nc);
+    std::vector<int32_t> agg = aggregate(strength_graph(A, B, soc), &nc);
     if (nc >= A.nr) break;
     // tentative interpolation from the near-null vector
     std::vector<double> nrm2(nc, 0.0);
@@ -314,19 +423,8 @@ void sa_field(const Csr& A0, double theta, int max_coarse, int max_levels, std::
     }
     T.ptr[A.nr] = A.nr;
     // P = (I - omega D^-1 A) T, omega = (4/3) / max_i sum_j |a_ij| / a_ii
-    // (row sums in row order, so the bound does not depend on the thread count)
     std::vector<double> d = diagonal(A);
-    std::vector<double> ratio(A.nr);
-    parallel_rows(A.nr, [&](int64_t lo, int64_t hi) {
-      for (int64_t i = lo; i < hi; ++i) {
-        double s = 0.0;
-        for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e) s += std::fabs(A.val[e]);
-        ratio[i] = s / d[i];
-      }
-    });
-    double rho = 0.0;
-    for (int64_t i = 0; i < A.nr; ++i) rho = std::max(rho, ratio[i]);
-    const double omega = (4.0 / 3.0) / rho;
+    const double omega = (4.0 / 3.0) / gershgorin_rho(A, d);
     Csr DA = A;
     parallel_rows(A.nr, [&](int64_t lo, int64_t hi) {
       for (int64_t i = lo; i < hi; ++i)
@@ -346,32 +444,30 @@ void sa_field(const Csr& A0, double theta, int max_coarse, int max_levels, std::
     B = Bc;
     Bs.push_back(B);
   }
-  // The coarsest level is solved through a dense inverse.  A coarsening that
-  // stopped far above max_coarse (too few strong connections for the
-  // threshold, or max_levels reached) is refused instead of inverting a matrix
-  // of that size; a max_coarse at least as large accepts it.
-  constexpr int64_t kMaxDenseField = 4096;
-  if (A.nr > std::max<int64_t>(max_coarse, kMaxDenseField))
-    throw std::runtime_error("smoothed aggregation stopped at " + std::to_string(A.nr) +
-                             " unknowns of one field, more than the dense coarsest solve takes (" +
-                             std::to_string(std::max<int64_t>(max_coarse, kMaxDenseField)) +
-                             "): lower theta, or raise max_levels or max_coarse");
+}
+
+void check_dense_coarse(int64_t n, int max_coarse, const char* what) {
+  const int64_t lim = std::max<int64_t>(max_coarse, kMaxDenseCoarse);
+  if (n > lim)
+    throw std::runtime_error(std::string(what) + ": smoothed aggregation stopped at " + std::to_string(n) +
+                             " unknowns, more than the dense coarsest solve takes (" + std::to_string(lim) +
+                             "): raise max_levels or max_coarse, or use the evolution strength measure");
 }
 
 // One hierarchy per field, the fields on threads of their own (each field's
 // hierarchy is the same as when built alone).
-void sa_fields(const std::vector<Csr>& A, double theta, int max_coarse, int max_levels,
+void sa_fields(const std::vector<Csr>& A, const SocParams& soc, int max_coarse, int max_levels,
                std::vector<std::vector<Csr>>& Ps, std::vector<std::vector<std::vector<double>>>& Bs) {
   const size_t nf = A.size();
   Ps.assign(nf, {});
   Bs.assign(nf, {});
   if (setup_threads() <= 1 || nf <= 1) {
-    for (size_t f = 0; f < nf; ++f) sa_field(A[f], theta, max_coarse, max_levels, Ps[f], Bs[f]);
+    for (size_t f = 0; f < nf; ++f) sa_field(A[f], soc, max_coarse, max_levels, Ps[f], Bs[f]);
     return;
   }
   std::vector<std::future<void>> jobs;
   for (size_t f = 0; f < nf; ++f)
-    jobs.push_back(std::async(std::launch::async, [&, f] { sa_field(A[f], theta, max_coarse, max_levels, Ps[f], Bs[f]); }));
+    jobs.push_back(std::async(std::launch::async, [&, f] { sa_field(A[f], soc, max_coarse, max_levels, Ps[f], Bs[f]); }));
   for (auto& j : jobs) j.wait();
   for (auto& j : jobs) j.get();  // rethrows the first field's error, if any
 }

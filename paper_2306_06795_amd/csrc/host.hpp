@@ -60,16 +60,27 @@ Csr block_diag(const std::vector<const Csr*>& blocks);
 void spmv(const Csr& A, const double* x, double* y);
 
 // ---- smoothed aggregation for one scalar field
-struct FieldLevel {
-  Csr P;                 // interpolation to this level's matrix from the next coarser one
-  std::vector<double> B; // near-null vector on the coarse side
+// Strength of connection: kind 0 = evolution measure (Section 3.2) with filter
+// eps, kind 1 = symmetric a_ij^2 >= theta^2 a_ii a_jj.
+struct SocParams {
+  int kind = 0;
+  double theta = 0.02;
+  double eps = 4.0;
 };
-std::vector<int32_t> aggregate(const Csr& A, double theta, int32_t* n_agg);
-void sa_field(const Csr& A, double theta, int max_coarse, int max_levels,
+// strong off-diagonal pairs of A (symmetric pattern, values 1); B: near-null vector
+Csr strength_graph(const Csr& A, const std::vector<double>& B, const SocParams& soc);
+// standard three-pass aggregation of a strength graph, nodes in index order
+std::vector<int32_t> aggregate(const Csr& S, int32_t* n_agg);
+void sa_field(const Csr& A, const SocParams& soc, int max_coarse, int max_levels,
               std::vector<Csr>& Ps, std::vector<std::vector<double>>& Bs);
 // sa_field for several fields at once, one thread per field.
-void sa_fields(const std::vector<Csr>& A, double theta, int max_coarse, int max_levels,
+void sa_fields(const std::vector<Csr>& A, const SocParams& soc, int max_coarse, int max_levels,
                std::vector<std::vector<Csr>>& Ps, std::vector<std::vector<std::vector<double>>>& Bs);
+// Largest matrix the dense coarsest solve takes (rows, border included) unless
+// max_coarse is larger: a coarsening that stalls above it is refused
+// (std::runtime_error naming `what`) instead of inverting a matrix of that size.
+constexpr int64_t kMaxDenseCoarse = 4096;
+void check_dense_coarse(int64_t n, int max_coarse, const char* what);
 
 // ---- Vanka patches of one level (velocity rows sorted, then the seeds)
 struct PatchSet {

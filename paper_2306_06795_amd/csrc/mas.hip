@@ -30,6 +30,14 @@ static thread_local std::string g_last_error;
 
 namespace {
 
+SocParams soc_params(const mas_params& p) {
+  SocParams c;
+  c.kind = p.soc;
+  c.theta = p.theta;
+  c.eps = p.soc_eps;
+  return c;
+}
+
 struct MasError : std::runtime_error {
   int code;
   MasError(int c, const std::string& m) : std::runtime_error(m), code(c) {}
@@ -239,8 +247,8 @@ void csr_launch(const DCsr<T>& A, const T* x, const T* b, T* y, hipStream_t s, C
 // Pick the lanes-per-row of a CSR product by timing every choice once on the
 // actual operand (setup-time autotuning; vectors may hold any values).
 template <typename T>
-void autotune_team(DCsr<T>& A, const T* x, T* y, hipStream_t s) {
-  if (A.n == 0 || A.nnz < 4096 || std::getenv("MAS_NO_AUTOTUNE")) {
+void autotune_team(DCsr<T>& A, const T* x, T* y, hipStream_t s, bool on) {
+  if (A.n == 0 || A.nnz < 4096 || !on) {
     A.use_sell = A.nslices > 0;
     return;
   }
@@ -1079,7 +1087,7 @@ void dense_inverse(DevArena& ar, double* A, int n, hipStream_t s) {
 
 template <typename T>
 void build_patches(DevArena& ar, Level<T>& L, const PatchSet& ps, const DCsr<double>& K64, int level, int nr_max,
-                   hipStream_t s) {
+                   const mas_params& par, hipStream_t s) {
   DPatches<T>& d = L.pt;
   const int64_t np = ps.np();
   d.np = np;
@@ -1100,8 +1108,7 @@ void build_patches(DevArena& ar, Level<T>& L, const PatchSet& ps, const DCsr<dou
       if (is_fast_shape(q)) by[{q[0], q[1], q[2], q[3]}].push_back(p);
       else generic.push_back(p);
     }
-    const char* env_min = std::getenv("MAS_TPP_MIN_PATCHES");
-    const int64_t min_bucket = env_min ? std::atoll(env_min) : 64;
+    const int64_t min_bucket = std::max<int64_t>(1, par.bucket_min);
     for (auto& kv : by) {
       if ((int64_t)kv.second.size() >= min_bucket) {
         gshape.push_back(kv.first);
@@ -1159,8 +1166,7 @@ void build_patches(DevArena& ar, Level<T>& L, const PatchSet& ps, const DCsr<dou
   // Levels of very large patches keep full velocity blocks: twice the values of
   // the packed triangle, but every row sweep of the patch kernels reads them
   // with consecutive addresses across threads.
-  int full_min = kFullPatch;
-  if (const char* e = std::getenv("MAS_FULL_PATCH")) full_min = std::max(1, std::atoi(e));  // threshold override
+  const int full_min = std::max(1, par.full_patch_min);
   d.full = (groups.empty() && ps.max_m >= full_min) ? 1 : 0;
   int64_t alg = 0;
   d.max_f = 0;
@@ -1203,8 +1209,7 @@ void build_patches(DevArena& ar, Level<T>& L, const PatchSet& ps, const DCsr<dou
   int width = 0;
   for (int64_t j = 0; j < n; ++j) width = std::max(width, cnt[j]);
   const double avg = n ? (double)dofs.size() / (double)n : 1.0;
-  const bool force_csr = std::getenv("MAS_PULL_CSR") != nullptr;
-  if (!force_csr && width <= 16 && width <= 2.5 * avg + 1) {
+  if (width <= 16 && width <= 2.5 * avg + 1) {
     std::vector<int32_t> ell((size_t)width * n, -1);
     for (int64_t j = 0; j < n; ++j)
       for (int32_t q = iptr[j]; q < iptr[j + 1]; ++q) ell[(size_t)(q - iptr[j]) * n + j] = ipos[q];
@@ -1286,7 +1291,7 @@ void build_patches(DevArena& ar, Level<T>& L, const PatchSet& ps, const DCsr<dou
     int dev = 0, max_lds = 0;
     HIPCHECK(hipGetDevice(&dev));
     HIPCHECK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    const bool blocked = panel <= (size_t)max_lds && std::getenv("MAS_FACTOR_UNBLOCKED") == nullptr;
+    const bool blocked = panel <= (size_t)max_lds && par.factor_blocked != 0;
     hipLaunchKernelGGL((k_vanka_factor<T, 1024>), dim3(grid), dim3(1024), blocked ? panel : 0, s, np, d.off, d.dims,
                        d.foff, d.fstride, d.dofs, K64.ptr, K64.ind, K64.val, d.fac, gwork, stride, blocked ? 2 : 0,
                        max_nv, 1e-14, bad, d.full);
@@ -1311,6 +1316,7 @@ std::unique_ptr<Cycle<T>> build_cycle(mas_handle* h, const std::vector<Csr>& Ks,
                                       const std::vector<int64_t>& dir0, hipStream_t s) {
   DevArena& ar = h->arena;
   SetupTrace tr;
+  const bool tune = h->par.autotune != 0;
   auto cyc = std::make_unique<Cycle<T>>();
   cyc->par = h->par;
   cyc->dim = h->dim;
@@ -1339,11 +1345,11 @@ std::unique_ptr<Cycle<T>> build_cycle(mas_handle* h, const std::vector<Csr>& Ks,
       tr.mark("device: level " + std::to_string(l) + " operators");
       if (L.relax && !patches[l].off.empty()) {
         if constexpr (std::is_same<T, double>::value) {
-          build_patches<T>(ar, L, patches[l], L.K, (int)l, cyc->nr_max, s);
+          build_patches<T>(ar, L, patches[l], L.K, (int)l, cyc->nr_max, h->par, s);
         } else {  // the FP64 operator lives only while the patches are factorised
           DevArena tmp;
           const DCsr<double> K64 = upload_csr_plain<double>(tmp, Ks[l], s);
-          build_patches<T>(ar, L, patches[l], K64, (int)l, cyc->nr_max, s);
+          build_patches<T>(ar, L, patches[l], K64, (int)l, cyc->nr_max, h->par, s);
         }
         tr.mark("device: level " + std::to_string(l) + " patches");
       }
@@ -1411,23 +1417,23 @@ std::unique_ptr<Cycle<T>> build_cycle(mas_handle* h, const std::vector<Csr>& Ks,
   // lanes per row of every sparse product, timed on the operands
   for (size_t l = 0; l + 1 < nl; ++l) {
     Level<T>& L = cyc->lev[l];
-    autotune_team<T>(L.K, L.x, L.r, s);
+    autotune_team<T>(L.K, L.x, L.r, s, tune);
     if (L.dl.on) {
-      autotune_team<T>(L.dl.A, L.dl.ru, L.dl.vs, s);
-      autotune_team<T>(L.dl.S, L.dl.rp, L.dl.q, s);
-      autotune_team<T>(L.dl.B, L.dl.ru, L.dl.rp, s);
-      autotune_team<T>(L.dl.Bt, L.dl.rp, L.dl.ru, s);
+      autotune_team<T>(L.dl.A, L.dl.ru, L.dl.vs, s, tune);
+      autotune_team<T>(L.dl.S, L.dl.rp, L.dl.q, s, tune);
+      autotune_team<T>(L.dl.B, L.dl.ru, L.dl.rp, s, tune);
+      autotune_team<T>(L.dl.Bt, L.dl.rp, L.dl.ru, s, tune);
       for (size_t k = 0; k + 1 < L.dl.sh.size(); ++k) {
         auto& Sl = L.dl.sh[k];
-        autotune_team<T>(Sl.S, Sl.x, Sl.res, s);
-        autotune_team<T>(Sl.R, Sl.res, L.dl.sh[k + 1].b, s);
-        autotune_team<T>(Sl.P, L.dl.sh[k + 1].x, Sl.x, s);
+        autotune_team<T>(Sl.S, Sl.x, Sl.res, s, tune);
+        autotune_team<T>(Sl.R, Sl.res, L.dl.sh[k + 1].b, s, tune);
+        autotune_team<T>(Sl.P, L.dl.sh[k + 1].x, Sl.x, s, tune);
       }
     }
     if (l >= 1) {
       Level<T>& C = cyc->lev[l + 1];
-      autotune_team<T>(L.R, L.r, C.b, s);
-      autotune_team<T>(L.P, C.x, L.x, s);
+      autotune_team<T>(L.R, L.r, C.b, s, tune);
+      autotune_team<T>(L.P, C.x, L.x, s, tune);
     }
   }
   if (tr.on) HIPCHECK(hipStreamSynchronize(s));
@@ -1475,7 +1481,7 @@ std::unique_ptr<Cycle<T>> build_cycle(mas_handle* h, const std::vector<Csr>& Ks,
 // a dense matrix, bordered with its near-null vector when S is singular.
 void s_hierarchy(HostDlsc& D, const mas_params& par, bool singular) {
   std::vector<std::vector<double>> Bs;
-  sa_field(D.S, par.theta, par.max_coarse, par.max_levels, D.Pk, Bs);
+  sa_field(D.S, soc_params(par), par.max_coarse, par.max_levels, D.Pk, Bs);
   D.Sk.assign(1, D.S);
   for (const Csr& P : D.Pk) D.Sk.push_back(galerkin(P, D.Sk.back()));
   D.wdinv.clear();
@@ -1497,6 +1503,7 @@ void s_hierarchy(HostDlsc& D, const mas_params& par, bool singular) {
   }
   const Csr& C = D.Sk.back();
   const int64_t m = C.nr, ld = singular ? m + 1 : m;
+  check_dense_coarse(ld, par.max_coarse, "B M^-1 B^T of the DLSC AMG stages");
   D.sc_ld = ld;
   D.sc_dense.assign((size_t)ld * ld, 0.0);
   for (int64_t i = 0; i < m; ++i)
@@ -1519,7 +1526,7 @@ void s_hierarchy(HostDlsc& D, const mas_params& par, bool singular) {
 // moved through pageable host memory, the threaded host product is faster.
 void analyze_impl(mas_handle* h, const mas_problem* pr, bool dev = false, hipStream_t s = nullptr) {
   SetupTrace tr;
-  dev = dev && std::getenv("MAS_DEVICE_GALERKIN") != nullptr;
+  dev = dev && h->par.device_galerkin != 0;
   const int d = pr->dim;
   if (d != 2 && d != 3) throw MasError(MAS_EINVAL, "dim must be 2 or 3");
   if (pr->disc != MAS_TH && pr->disc != MAS_SV) throw MasError(MAS_EINVAL, "unknown discretisation");
@@ -1555,6 +1562,11 @@ void analyze_impl(mas_handle* h, const mas_problem* pr, bool dev = false, hipStr
   if (par.nrhs_max < 1 || par.nrhs_max > 64) throw MasError(MAS_EINVAL, "nrhs_max must be in [1, 64]");
   if (par.krylov_its < 0 || par.krylov_its > 8) throw MasError(MAS_EINVAL, "krylov_its must be in [0, 8]");
   if (par.max_coarse < 1 || par.max_levels < 1) throw MasError(MAS_EINVAL, "bad coarsening limits");
+  if (par.soc != MAS_SOC_EVOLUTION && par.soc != MAS_SOC_SYMMETRIC) throw MasError(MAS_EINVAL, "unknown soc");
+  if (!(par.soc_eps > 0.0) || !std::isfinite(par.soc_eps)) throw MasError(MAS_EINVAL, "soc_eps must be positive");
+  if (par.gram_schmidt != MAS_GS_CLASSICAL && par.gram_schmidt != MAS_GS_MODIFIED)
+    throw MasError(MAS_EINVAL, "unknown gram_schmidt");
+  if (par.full_patch_min < 1 || par.bucket_min < 1) throw MasError(MAS_EINVAL, "full_patch_min and bucket_min must be >= 1");
   std::vector<int64_t> free0, dir0, free1;
   std::vector<int8_t> f0, f1;
   int64_t nu0 = 0, np0 = 0;
@@ -1598,11 +1610,19 @@ void analyze_impl(mas_handle* h, const mas_problem* pr, bool dev = false, hipStr
   {
     std::vector<Csr> Af;
     for (int f = 0; f <= d; ++f) Af.push_back((f < d) ? submatrix(K1f, blocks[f], blocks[f]) : Ap);
-    sa_fields(Af, par.theta, par.max_coarse, par.max_levels, fP, fB);
+    sa_fields(Af, soc_params(par), par.max_coarse, par.max_levels, fP, fB);
   }
   size_t lmax = SIZE_MAX;
   for (int f = 0; f <= d; ++f) lmax = std::min(lmax, fP[f].size() + 1);
   tr.mark("smoothed aggregation");
+  {
+    // the coarsest level is the one after lmax - 1 coarsenings of every field
+    // (a field that coarsened further is cut there), inverted densely with
+    // its border
+    int64_t nL = pr->p_nullspace ? 1 : 0;
+    for (int f = 0; f <= d; ++f) nL += lmax >= 2 ? fP[f][lmax - 2].nc : (int64_t)blocks[f].size();
+    check_dense_coarse(nL, par.max_coarse, "coarsest saddle operator");
+  }
   // levels: 0 = K0f, 1 = K1f, 2.. = Galerkin
   std::vector<Csr> Ks;
   Ks.push_back(std::move(K0f));
@@ -1783,6 +1803,7 @@ void analyze_impl(mas_handle* h, const mas_problem* pr, bool dev = false, hipStr
 void upload_impl(mas_handle* h, hipStream_t s) {
   HostPlan& pl = h->plan;
   const mas_params& par = h->par;
+  const bool tune = par.autotune != 0;
   const int64_t n0 = h->n0;
   h->K0full = upload_csr<double>(h->arena, pl.K0, s);
   h->K0full.stream = (double)h->K0full.nnz * 12.0 >= kStreamBytes;  // one FGMRES product per iteration
@@ -1790,7 +1811,7 @@ void upload_impl(mas_handle* h, hipStream_t s) {
     double* tx = h->arena.alloc<double>(n0);
     double* ty = h->arena.alloc<double>(n0);
     HIPCHECK(hipMemsetAsync(tx, 0, n0 * sizeof(double), s));
-    autotune_team<double>(h->K0full, tx, ty, s);
+    autotune_team<double>(h->K0full, tx, ty, s, tune);
   }
   if (par.precision == MAS_FP32)
     h->cyc = build_cycle<float>(h, pl.Ks, pl.Ps, pl.fields, pl.patches, pl.dlsc, pl.relax, pl.Kb, pl.free0, pl.dir0,
@@ -1808,7 +1829,7 @@ void upload_impl(mas_handle* h, hipStream_t s) {
   h->w = h->arena.alloc<double>((size_t)n0 * R);
   h->partial = h->arena.alloc<double>((size_t)2 * h->nblk_dot * R);
   h->cpart = h->arena.alloc<double>((size_t)(m + 1) * h->nblk_dot * R);
-  h->use_mgs = std::getenv("MAS_MGS") != nullptr;
+  h->use_mgs = par.gram_schmidt == MAS_GS_MODIFIED;
   h->hdev = h->arena.alloc<double>((size_t)(m + 2) * R);
   h->ydev = h->arena.alloc<double>((size_t)(m + 1) * R);
   HIPCHECK(hipHostMalloc((void**)&h->hhost, (size_t)(m + 2) * R * sizeof(double), hipHostMallocDefault));
@@ -1816,7 +1837,7 @@ void upload_impl(mas_handle* h, hipStream_t s) {
   HIPCHECK(hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming));
   HIPCHECK(hipEventCreateWithFlags(&h->ev_out, hipEventDisableTiming));
   h->iter_graph.assign(m, nullptr);
-  h->use_graphs = std::getenv("MAS_NO_GRAPHS") == nullptr;
+  h->use_graphs = par.graphs != 0;
   HIPCHECK(hipStreamSynchronize(s));
   h->on_device = true;  // the host plan stays: mas_release / mas_upload rebuild from it
 }
@@ -2261,6 +2282,15 @@ void mas_default_params(int32_t dim, int32_t disc, int32_t relax, mas_params* ou
   p.krylov_its = 0;
   p.nu_dlsc = 2;
   p.dlsc_amg = 0;
+  p.soc = MAS_SOC_EVOLUTION;
+  p.soc_eps = 4.0;
+  p.gram_schmidt = MAS_GS_CLASSICAL;
+  p.autotune = 1;
+  p.graphs = 1;
+  p.full_patch_min = kFullPatch;
+  p.bucket_min = 64;
+  p.factor_blocked = 1;
+  p.device_galerkin = 0;
   *out = p;
 }
 

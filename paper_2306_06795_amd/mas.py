@@ -20,6 +20,8 @@ MAS_TH, MAS_SV = 0, 1
 MAS_RELAX_VANKA, MAS_RELAX_DLSC, MAS_RELAX_VANKA_DLSC = 0, 1, 2
 MAS_DC_ALL, MAS_DC_SKIP1, MAS_DC_SKIP0, MAS_HO_AMG = 0, 1, 2, 3
 MAS_FP64, MAS_FP32 = 0, 1
+MAS_SOC_EVOLUTION, MAS_SOC_SYMMETRIC = 0, 1
+MAS_GS_CLASSICAL, MAS_GS_MODIFIED = 0, 1
 
 
 class mas_csr(C.Structure):
@@ -41,7 +43,10 @@ class mas_params(C.Structure):
                 ("cheb_deg", C.c_int32 * 3), ("precision", C.c_int32), ("restart", C.c_int32),
                 ("max_coarse", C.c_int32), ("max_levels", C.c_int32), ("theta", C.c_double),
                 ("seed", C.c_uint64), ("mass_rtol", C.c_double), ("nrhs_max", C.c_int32),
-                ("krylov_its", C.c_int32), ("nu_dlsc", C.c_int32), ("dlsc_amg", C.c_int32)]
+                ("krylov_its", C.c_int32), ("nu_dlsc", C.c_int32), ("dlsc_amg", C.c_int32),
+                ("soc", C.c_int32), ("soc_eps", C.c_double), ("gram_schmidt", C.c_int32), ("autotune", C.c_int32),
+                ("graphs", C.c_int32), ("full_patch_min", C.c_int32), ("bucket_min", C.c_int32),
+                ("factor_blocked", C.c_int32), ("device_galerkin", C.c_int32)]
 
 
 class mas_solve_info(C.Structure):

@@ -40,8 +40,9 @@ def test_struct_layout_matches_c():
 int main(void) {
   printf("%zu %zu %zu %zu %zu\n", sizeof(mas_csr), sizeof(mas_problem), sizeof(mas_params),
          sizeof(mas_solve_info), sizeof(mas_hier_info));
-  printf("%zu %zu %zu %zu\n", offsetof(mas_problem, p_nullspace), offsetof(mas_problem, Mcg),
-         offsetof(mas_params, cheb_deg), offsetof(mas_params, mass_rtol));
+  printf("%zu %zu %zu %zu %zu %zu\n", offsetof(mas_problem, p_nullspace), offsetof(mas_problem, Mcg),
+         offsetof(mas_params, cheb_deg), offsetof(mas_params, mass_rtol), offsetof(mas_params, soc_eps),
+         offsetof(mas_params, device_galerkin));
   return 0;
 }
 '''
@@ -55,7 +56,8 @@ int main(void) {
     assert sizes[:5] == [C.sizeof(mas.mas_csr), C.sizeof(mas.mas_problem), C.sizeof(mas.mas_params),
                          C.sizeof(mas.mas_solve_info), C.sizeof(mas.mas_hier_info)]
     assert sizes[5:] == [mas.mas_problem.p_nullspace.offset, mas.mas_problem.Mcg.offset,
-                         mas.mas_params.cheb_deg.offset, mas.mas_params.mass_rtol.offset]
+                         mas.mas_params.cheb_deg.offset, mas.mas_params.mass_rtol.offset,
+                         mas.mas_params.soc_eps.offset, mas.mas_params.device_galerkin.offset]
 
 
 def test_default_params_follow_the_paper():
@@ -68,27 +70,33 @@ def test_default_params_follow_the_paper():
 
 
 SCHED = {"all": mas.MAS_DC_ALL, "ho": mas.MAS_HO_AMG}
+SOC = {"evolution": mas.MAS_SOC_EVOLUTION, "symmetric": mas.MAS_SOC_SYMMETRIC}
 
 
 def _same_params(prob, **over):
     par = dc.default_params(prob, **over)
     mp = mas.default_params(prob.dim, mas.MAS_SV if prob.disc == "SV" else mas.MAS_TH, theta=par.theta,
-                            max_coarse=par.max_coarse, max_levels=par.max_levels, schedule=SCHED[par.schedule])
+                            max_coarse=par.max_coarse, max_levels=par.max_levels, schedule=SCHED[par.schedule],
+                            soc=SOC[par.soc])
     return par, mp
 
 
-@pytest.mark.parametrize("kw,mc,sched", [
-    (dict(dim=2, n=16), 300, "all"),
-    (dict(dim=2, n=16), 30, "all"),
-    (dict(dim=2, n=24, jitter=0.2, seed=2, forcing="gaussian", bc="lid"), 40, "all"),
-    (dict(dim=3, n=4, forcing="smooth", bc="zero", seed=3), 40, "all"),
+@pytest.mark.parametrize("kw,mc,sched,soc", [
+    (dict(dim=2, n=16), 300, "all", "evolution"),
+    (dict(dim=2, n=16), 30, "all", "evolution"),
+    (dict(dim=2, n=24, jitter=0.2, seed=2, forcing="gaussian", bc="lid"), 40, "all", "evolution"),
+    (dict(dim=2, n=24, jitter=0.2, seed=2, forcing="gaussian", bc="lid"), 40, "all", "symmetric"),
+    (dict(dim=3, n=4, forcing="smooth", bc="zero", seed=3), 40, "all", "evolution"),
+    (dict(dim=3, n=5, forcing="smooth", bc="zero", seed=3), 20, "all", "evolution"),
+    (dict(dim=3, n=4, forcing="smooth", bc="zero", seed=3), 40, "all", "symmetric"),
+    (dict(dim=2, n=12, disc="SV", seed=4, forcing="gaussian", bc="zero"), 30, "all", "evolution"),
     # HO-AMG: the hierarchy below K0 is Algorithm 1 applied to K0 itself
-    (dict(dim=2, n=24, jitter=0.2, seed=2, forcing="gaussian", bc="lid"), 40, "ho"),
-    (dict(dim=3, n=4, forcing="smooth", bc="zero", seed=3), 40, "ho"),
+    (dict(dim=2, n=24, jitter=0.2, seed=2, forcing="gaussian", bc="lid"), 40, "ho", "evolution"),
+    (dict(dim=3, n=4, forcing="smooth", bc="zero", seed=3), 40, "ho", "evolution"),
 ])
-def test_host_hierarchy_matches_oracle(kw, mc, sched):
+def test_host_hierarchy_matches_oracle(kw, mc, sched, soc):
     P = make_problem(**kw)
-    par, mp = _same_params(P, max_coarse=mc, schedule=sched)
+    par, mp = _same_params(P, max_coarse=mc, schedule=sched, soc=soc)
     pre = dc.DCPreconditioner(P, par)
     h = mas.Handle(P, mp, analyze_only=True)
     info = h.info()
@@ -246,9 +254,29 @@ def test_stalled_coarsening_is_refused_before_a_huge_dense_solve():
     analysis refuses it (EINVAL, naming the cause) unless max_coarse accepts a
     coarsest level that large."""
     P = make_problem(dim=2, n=48, jitter=0.2, seed=2, forcing="gaussian", bc="lid")
+    sym = dict(theta=0.9, soc=mas.MAS_SOC_SYMMETRIC)
     with pytest.raises(mas.MasError) as e:
-        mas.Handle(P, mas.default_params(2, theta=0.9), analyze_only=True)
+        mas.Handle(P, mas.default_params(2, **sym), analyze_only=True)
     assert e.value.code == mas.MAS_EINVAL and "coarsest" in str(e.value)
-    h = mas.Handle(P, mas.default_params(2, theta=0.9, max_coarse=10 ** 6), analyze_only=True)
+    h = mas.Handle(P, mas.default_params(2, max_coarse=10 ** 6, **sym), analyze_only=True)
     assert h.info()["n_levels"] == 2
+    h.close()
+
+
+def test_coarsest_size_is_checked_where_the_fields_are_cut():
+    """The hierarchy depth is the minimum over the fields (Algorithm 1), so a
+    field that stops early cuts the others short.  With max_coarse = 2500 the
+    2401 pressures of the 48 x 48 mesh are not coarsened at all, while each
+    velocity component (9025 free nodes) coarsens below the limit on its own:
+    the level actually inverted is K1 itself (20,451 rows with the border),
+    which the analysis refuses even though every field's own coarsest level is
+    below the limit."""
+    P = make_problem(dim=2, n=48, jitter=0.2, seed=2, forcing="gaussian", bc="lid")
+    assert P.meta["n_p1"] == 2401
+    with pytest.raises(mas.MasError) as e:
+        mas.Handle(P, mas.default_params(2, max_coarse=2500), analyze_only=True)
+    assert e.value.code == mas.MAS_EINVAL and "coarsest" in str(e.value)
+    h = mas.Handle(P, mas.default_params(2, max_coarse=300), analyze_only=True)
+    i = h.info()
+    assert i["coarse_n"] <= 4096 and i["n_levels"] >= 3
     h.close()
