@@ -325,9 +325,9 @@ def main():
           file=sys.stderr, flush=True)
     eager = None
     if prob.n0 < 20000:  # small systems are launch-bound: the same solves without the iteration graphs
-        os.environ["MAS_NO_GRAPHS"] = "1"
+        mp.graphs = 0
         he = mas.Handle(prob, mp)
-        os.environ.pop("MAS_NO_GRAPHS")
+        mp.graphs = 1
         xe = torch.empty_like(b)
         he.solve(b, xe, rtol=a.rtol, nrhs=nrhs)
         torch.cuda.synchronize()

@@ -136,7 +136,9 @@ typedef struct {
                              k = 1..8: each by one smoothed-aggregation V-cycle on B M^-1 B^T with k
                              weighted-Jacobi sweeps (weight 4/3 over the largest absolute row sum of
                              D^-1 S) before and after the coarse correction (Section 5) */
-  int32_t soc;            /* mas_soc (MAS_SOC_EVOLUTION) */
+  int32_t soc;            /* mas_soc (default: MAS_SOC_EVOLUTION for Taylor-Hood, MAS_SOC_SYMMETRIC
+                             for Scott-Vogelius, whose Alfeld-mesh pressure the evolution measure
+                             coarsens at about half the velocity rate) */
   double soc_eps;         /* evolution filter epsilon (4) */
   int32_t gram_schmidt;   /* mas_gram_schmidt of mas_solve (MAS_GS_CLASSICAL) */
   int32_t autotune;       /* 1: each sparse product's kernel (sliced-ELL or CSR, lanes per row) is

@@ -208,10 +208,17 @@ class DCPreconditioner:
 
 
 def default_params(prob, relax: str = "vanka", **over) -> Params:
+    """Section 4 defaults.  Strength of connection: the evolution measure of
+    Section 3.2 for Taylor-Hood.  Scott-Vogelius keeps the symmetric measure:
+    on the Alfeld meshes the evolution measure coarsens the continuous
+    pressure of K1 at about half the velocity rate, and the stationary
+    omega = 0.5 Vanka sweeps then diverge on the coarse saddle levels (the
+    paper's own coarse-level relaxation is wrapped in FGMRES, which
+    converges with either measure)."""
     if prob.disc == "SV" and relax == "vanka-dlsc":  # Table 4, structured, Vanka-DLSC row
-        p = Params(relax=relax, omega0=0.87, omega=0.5, eta_u=1.0, eta_p=2.96)
+        p = Params(relax=relax, omega0=0.87, omega=0.5, eta_u=1.0, eta_p=2.96, soc="symmetric")
     elif prob.disc == "SV":
-        p = Params(relax=relax, omega0=0.78, omega=0.5, eta_u=1.0, eta_p=2.68)
+        p = Params(relax=relax, omega0=0.78, omega=0.5, eta_u=1.0, eta_p=2.68, soc="symmetric")
     else:
         p = Params(relax=relax)
     if relax == "dlsc":

@@ -2282,7 +2282,11 @@ void mas_default_params(int32_t dim, int32_t disc, int32_t relax, mas_params* ou
   p.krylov_its = 0;
   p.nu_dlsc = 2;
   p.dlsc_amg = 0;
-  p.soc = MAS_SOC_EVOLUTION;
+  // evolution strength (Section 3.2) for Taylor-Hood; Scott-Vogelius keeps the
+  // symmetric measure: on Alfeld meshes the evolution measure coarsens the K1
+  // pressure at about half the velocity rate, and stationary omega = 0.5 Vanka
+  // then diverges on the coarse saddle levels
+  p.soc = disc == MAS_SV ? MAS_SOC_SYMMETRIC : MAS_SOC_EVOLUTION;
   p.soc_eps = 4.0;
   p.gram_schmidt = MAS_GS_CLASSICAL;
   p.autotune = 1;

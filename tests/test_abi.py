@@ -67,6 +67,12 @@ def test_default_params_follow_the_paper():
     assert list(p3.cheb_deg) == [4, 4, 16] and p3.nu1 == 2
     ph = mas.default_params(2, mas.MAS_SV, mas.MAS_RELAX_VANKA_DLSC)  # Table 4, Vanka-DLSC row
     assert (ph.omega0, ph.eta_p, ph.eta_u, ph.nu1, ph.nu_dlsc) == (0.87, 2.96, 1.0, 1, 2)
+    # evolution strength (Section 3.2) for Taylor-Hood; SV keeps the symmetric measure
+    assert mas.default_params(3).soc == mas.MAS_SOC_EVOLUTION and mas.default_params(2).soc_eps == 4.0
+    assert p.soc == ph.soc == mas.MAS_SOC_SYMMETRIC
+    for prob in (make_problem(dim=2, n=4), make_problem(dim=2, n=2, disc="SV", seed=1)):
+        par = dc.default_params(prob)
+        assert SOC[par.soc] == mas.default_params(2, mas.MAS_SV if prob.disc == "SV" else mas.MAS_TH).soc
 
 
 SCHED = {"all": mas.MAS_DC_ALL, "ho": mas.MAS_HO_AMG}

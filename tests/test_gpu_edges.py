@@ -104,18 +104,14 @@ def test_argument_errors():
 
 
 @pytest.mark.parametrize("nrhs", [1, 5])
-def test_classical_and_modified_gram_schmidt_agree(nrhs, monkeypatch):
-    """FGMRES with classical Gram-Schmidt (default) and modified (MAS_MGS):
+def test_classical_and_modified_gram_schmidt_agree(nrhs):
+    """FGMRES with classical Gram-Schmidt (default) and modified (gram_schmidt):
     same iteration counts, solutions equal to rounding."""
     P = make_problem(dim=2, n=16, forcing="gaussian", bc="lid", jitter=0.2, seed=6, nrhs=nrhs)
     B = torch.tensor(P.b, device=DEV)
     out = {}
     for mgs in (False, True):
-        if mgs:
-            monkeypatch.setenv("MAS_MGS", "1")
-        else:
-            monkeypatch.delenv("MAS_MGS", raising=False)
-        h = handle(P, nrhs_max=nrhs)
+        h = handle(P, nrhs_max=nrhs, gram_schmidt=mas.MAS_GS_MODIFIED if mgs else mas.MAS_GS_CLASSICAL)
         X = torch.empty_like(B)
         rc, info = h.solve(B, X, rtol=1e-10, nrhs=nrhs)
         assert rc == mas.MAS_OK

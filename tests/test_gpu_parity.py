@@ -114,12 +114,12 @@ def test_apply_fp64_matches_oracle(name):
 
 
 @pytest.mark.parametrize("name", ["th3d4", "th3d6_3lvl"])
-def test_full_block_levels_match_oracle(name, monkeypatch):
+def test_full_block_levels_match_oracle(name):
     """Levels of very large patches store full velocity blocks; a lowered
     threshold puts every 3D level of these cases on that path, single and
     batched, FP64 and FP32."""
-    monkeypatch.setenv("MAS_FULL_PATCH", "100")
     P, par, mp = build(name)
+    mp.full_patch_min = 100
     pre = dc.DCPreconditioner(P, par)
     rng = np.random.default_rng(13)
     R = rng.standard_normal((P.n0, 3))

@@ -1,5 +1,5 @@
 """Galerkin products of the setup on the device (Algorithm 1, opt-in with
-MAS_DEVICE_GALERKIN): the hierarchy a handle builds through mas_setup with
+device_galerkin = 1): the hierarchy a handle builds through mas_setup with
 device products must equal, bit for bit, the one mas_analyze builds on the
 host -- also when rows overflow the kernel's LDS table and are finished on the
 host."""
@@ -31,7 +31,7 @@ def test_device_galerkin_equals_host_bitwise(name, cap, monkeypatch):
     kw, over = CASES[name]
     P = make_problem(**kw)
     mp = mas.default_params(P.dim, mas.MAS_SV if P.disc == "SV" else mas.MAS_TH, max_coarse=20, **over)
-    monkeypatch.setenv("MAS_DEVICE_GALERKIN", "1")
+    mp.device_galerkin = 1
     if cap:  # rows with more than 4 distinct columns are finished on the host
         monkeypatch.setenv("MAS_SPGEMM_CAP", cap)
     print(f"[setup {name}] cap={cap}", flush=True)
