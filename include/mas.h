@@ -108,6 +108,22 @@ typedef struct {
   mas_csr Pp0;            /* np0 x np1 duplication P1 -> P1disc */
   mas_csr Mdg;            /* np0 x np0 P1disc mass */
   mas_csr Mcg;            /* np1 x np1 P1 mass */
+  /* Optional prebuilt hierarchy (Algorithm 1 skipped; for parity runs that
+   * must use a hierarchy built elsewhere).  n_prebuilt = 0: smoothed
+   * aggregation builds the hierarchy.  n_prebuilt = L > 0: L coarsening steps,
+   * prebuilt_P[l * (dim + 1) + f] (host CSR) interpolates field f (0..dim-1:
+   * velocity components, dim: pressure) from hierarchy level l + 1 to level l,
+   * level 0 being K1 on its free DoFs (K0 for MAS_HO_AMG); its rows are the
+   * field's DoFs of the finer level in increasing order, its columns the
+   * field's DoFs of the coarser level.  The coarse operators are the Galerkin
+   * products of eq. (3.4).  prebuilt_null_p (required when p_nullspace is set):
+   * the pressure near-null vector on the coarsest level (columns of the last
+   * pressure interpolation), used to border the coarsest solve.  Borrowed for
+   * the call like every host array.  The smoothed-aggregation hierarchies of
+   * the DLSC AMG stages (dlsc_amg > 0) are still built by the library. */
+  int32_t n_prebuilt;
+  const mas_csr* prebuilt_P;
+  const double* prebuilt_null_p;
 } mas_problem;
 
 typedef struct {
@@ -202,6 +218,24 @@ int mas_analyze(const mas_problem* prob, const mas_params* par, mas_handle** out
  * handle is left analysed-only.  Errors: MAS_ENOMEM, MAS_ESINGULAR_PATCH,
  * MAS_EHIP. */
 int mas_upload(mas_handle* h, void* stream);
+
+/* Device bytes mas_upload_ws needs for an analysed (not uploaded) handle: its
+ * operators, factors, level vectors and FGMRES basis plus the peak of the
+ * setup's temporary work areas, each piece rounded to 256 bytes.  Computed
+ * on the host from the analysis (no device is touched; the handle stays
+ * analysed-only).  Errors: MAS_EINVAL for NULL arguments or a handle already
+ * on the device. */
+int mas_workspace_size(mas_handle* h, size_t* bytes);
+
+/* mas_upload into caller-owned device memory: every device array of the
+ * handle (and the setup's temporaries) is carved from dev_ws, which must be
+ * 256-byte aligned, at least mas_workspace_size bytes, and stay allocated and
+ * untouched by the caller until mas_release or mas_destroy returns.  The
+ * library allocates only its pinned host staging (a few KB), one internal
+ * stream and two events.  Errors: MAS_EINVAL (NULL or misaligned dev_ws, or a
+ * handle already on the device), MAS_ENOMEM (ws_bytes too small; the message
+ * names the bytes needed so far), MAS_ESINGULAR_PATCH, MAS_EHIP. */
+int mas_upload_ws(mas_handle* h, void* dev_ws, size_t ws_bytes, void* stream);
 
 /* Free every device resource of the handle (waits for the device first),
  * keeping the host analysis so that mas_upload can restore it without

@@ -77,15 +77,23 @@ def submatrix(A: sp.csr_matrix, rows: np.ndarray, cols: np.ndarray) -> sp.csr_ma
 
 
 def dense_blocks(A: sp.csr_matrix, idx: np.ndarray) -> np.ndarray:
-    """Stack of dense principal submatrices A[idx[k]][:, idx[k]] for an (N, m) index array."""
+    """Stack of dense principal submatrices A[idx[k]][:, idx[k]] for an (N, m)
+    index array: for each patch, its rows of A are read and every stored entry
+    whose column lies in the patch is placed at (local row, local column)."""
     A = csr(A)
-    n = A.shape[1]
-    row = np.repeat(np.arange(A.shape[0]), np.diff(A.indptr)).astype(np.int64)
-    key = row * n + A.indices
     N, m = idx.shape
-    q = (idx[:, :, None].astype(np.int64) * n + idx[:, None, :]).ravel()
-    pos = np.searchsorted(key, q)
-    pos = np.minimum(pos, key.size - 1)
-    hit = key[pos] == q
-    out = np.where(hit, A.data[pos], 0.0)
-    return out.reshape(N, m, m)
+    out = np.zeros((N, m, m))
+    pos = -np.ones(A.shape[1], dtype=np.int64)  # global column -> local position (current patch)
+    local = np.arange(m)
+    for k in range(N):
+        d = idx[k]
+        pos[d] = local
+        lo = A.indptr[d]
+        cnt = A.indptr[d + 1] - lo
+        ent = np.repeat(lo - np.cumsum(cnt) + cnt, cnt) + np.arange(int(cnt.sum()))  # entries of rows d
+        rows = np.repeat(local, cnt)
+        cols = pos[A.indices[ent]]
+        keep = cols >= 0
+        out[k, rows[keep], cols[keep]] = A.data[ent[keep]]
+        pos[d] = -1
+    return out

@@ -60,6 +60,7 @@ def _finish(dofs, n_seed, n) -> Patches:
 
 
 CACHE_ENTRIES = 2 * 10 ** 8  # keep dense patch matrices between sweeps below this size
+PROGRESS = False  # print a line per group of patches solved (long full-size runs)
 
 
 def _buckets(K: sp.csr_matrix, P: Patches, chunk: int):
@@ -84,11 +85,15 @@ def sweep(K: sp.csr_matrix, P: Patches, b: np.ndarray, x: np.ndarray, omega: flo
     """One additive Vanka sweep; returns the updated x (x may be all zeros)."""
     r = b - K @ x
     upd = np.zeros_like(x)
-    for idx, Ki in _buckets(K, P, chunk):
+    groups = _buckets(K, P, chunk)
+    for g, (idx, Ki) in enumerate(groups):
         if Ki is None:
             Ki = dense_blocks(K, idx)
         yi = np.linalg.solve(Ki, r[idx][..., None])[..., 0]  # dense LU per patch
         np.add.at(upd, idx.ravel(), (P.weight[idx] * yi).ravel())
+        if PROGRESS and (g + 1) % 32 == 0 or (PROGRESS and g + 1 == len(groups)):
+            print(f"    [oracle] sweep over {K.shape[0]} DoFs: group {g + 1}/{len(groups)} "
+                  f"({idx.shape[0]} patches of {idx.shape[1]} DoFs)", flush=True)
     return x + omega * upd
 
 

@@ -87,12 +87,48 @@ static bool is_fast_shape(const int32_t* d) {
 // ---------------------------------------------------------------------------
 // device memory owned by a handle
 
+// Device memory of a handle.
+//  OWN:    every allocation is a hipMalloc of its own, returned by release().
+//  BUFFER: allocations are carved, 256-byte aligned, from a caller-owned buffer:
+//          persistent ones upward from its start, temporaries (setup work
+//          areas) downward from its end, given back when their scope closes.
+//          A request beyond the buffer throws MAS_ENOMEM.
+//  DRY:    nothing is allocated and no device work is issued; the bytes a
+//          BUFFER would need (peak of both ends) are counted.  The pointers
+//          handed out are never dereferenced: every device operation of the
+//          upload path checks dry() first.
 struct DevArena {
-  std::vector<void*> ptrs;
-  size_t bytes = 0;
+  enum Mode { OWN, BUFFER, DRY };
+  static constexpr size_t kAlign = 256;
+  Mode mode = OWN;
+  std::vector<void*> ptrs;  // OWN allocations
+  size_t bytes = 0;         // persistent bytes held
+  char* base = nullptr;     // BUFFER start (DRY: a fake, never-dereferenced base)
+  size_t cap = 0, lo = 0, hi = 0, peak = 0;
+  bool dry() const { return mode == DRY; }
+  static size_t round(size_t nb) { return (nb + kAlign - 1) / kAlign * kAlign; }
+  void* carve(size_t nb, bool temp) {
+    nb = round(std::max<size_t>(nb, 1));
+    if (mode == BUFFER && lo + hi + nb > cap)
+      throw MasError(MAS_ENOMEM, "workspace of " + std::to_string(cap) + " bytes is too small (at least " +
+                                     std::to_string(lo + hi + nb) + " needed so far; mas_workspace_size gives the "
+                                     "total)");
+    void* p;
+    if (temp) {
+      hi += nb;
+      p = base + (mode == BUFFER ? cap - hi : (size_t)1 << 40) ;
+    } else {
+      p = base + lo;
+      lo += nb;
+      bytes += nb;
+    }
+    peak = std::max(peak, lo + hi);
+    return p;
+  }
   template <typename T>
   T* alloc(size_t n) {
     if (n == 0) n = 1;
+    if (mode != OWN) return (T*)carve(n * sizeof(T), false);
     void* p = nullptr;
     HIPCHECK(hipMalloc(&p, n * sizeof(T)));
     ptrs.push_back(p);
@@ -102,7 +138,7 @@ struct DevArena {
   template <typename T, typename S, typename Al>
   T* upload(const std::vector<S, Al>& v, hipStream_t s) {
     T* d = alloc<T>(v.size());
-    if (v.empty()) return d;
+    if (v.empty() || dry()) return d;
     if constexpr (std::is_same<T, S>::value) {
       HIPCHECK(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
       HIPCHECK(hipStreamSynchronize(s));
@@ -113,12 +149,52 @@ struct DevArena {
     }
     return d;
   }
+  // BUFFER / DRY over [buf, buf + cap) (DRY: buf is a fake base, cap unused)
+  void use_buffer(void* buf, size_t c, bool count_only) {
+    release();
+    mode = count_only ? DRY : BUFFER;
+    base = count_only ? (char*)((size_t)1 << 44) : (char*)buf;
+    cap = c;
+  }
   void release() {
     for (void* p : ptrs) (void)hipFree(p);
     ptrs.clear();
     bytes = 0;
+    lo = hi = peak = 0;
+    mode = OWN;
+    base = nullptr;
+    cap = 0;
   }
   ~DevArena() { release(); }
+};
+
+// Setup work memory that lives until the scope closes: its own hipMallocs for
+// an OWN arena, the top end of the buffer otherwise.  The upload path
+// synchronises its stream before a scope closes.
+struct TempScope {
+  DevArena& parent;
+  DevArena own;  // OWN-mode allocations
+  size_t hi0;
+  explicit TempScope(DevArena& p) : parent(p), hi0(p.hi) {}
+  template <typename T>
+  T* alloc(size_t n) {
+    if (parent.mode == DevArena::OWN) return own.alloc<T>(n);
+    return (T*)parent.carve(std::max<size_t>(n, 1) * sizeof(T), true);
+  }
+  template <typename T, typename S, typename Al>
+  T* upload(const std::vector<S, Al>& v, hipStream_t s) {
+    if (parent.mode == DevArena::OWN) return own.upload<T>(v, s);
+    T* d = alloc<T>(v.size());
+    if (v.empty() || dry()) return d;
+    std::vector<T> tmp(v.begin(), v.end());
+    HIPCHECK(hipMemcpyAsync(d, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    return d;
+  }
+  bool dry() const { return parent.dry(); }
+  ~TempScope() {
+    if (parent.mode != DevArena::OWN) parent.hi = hi0;
+  }
 };
 
 // Sparse operator on the device: CSR (TEAM lanes per row) and, when the
@@ -141,16 +217,16 @@ struct DCsr {
 };
 
 // CSR arrays only (no sliced-ELL copy): operators the factorisation reads once
-template <typename T>
-DCsr<T> upload_csr_plain(DevArena& A, const Csr& C, hipStream_t s) {
+template <typename T, typename Ar>
+DCsr<T> upload_csr_plain(Ar& A, const Csr& C, hipStream_t s) {
   if (C.nnz() >= (int64_t)INT32_MAX) throw MasError(MAS_EINVAL, "matrix too large for 32-bit offsets");
   DCsr<T> d;
   d.n = C.nr;
   d.m = C.nc;
   d.nnz = C.nnz();
-  d.ptr = A.upload<int>(C.ptr, s);
-  d.ind = A.upload<int>(C.ind, s);
-  d.val = A.upload<T>(C.val, s);
+  d.ptr = A.template upload<int>(C.ptr, s);
+  d.ind = A.template upload<int>(C.ind, s);
+  d.val = A.template upload<T>(C.val, s);
   return d;
 }
 
@@ -1066,10 +1142,12 @@ Csr device_galerkin(const Csr& P, const Csr& A, hipStream_t s) {
 
 // dense inverse of an n x n FP64 matrix on the device (Gauss-Jordan, partial pivoting)
 void dense_inverse(DevArena& ar, double* A, int n, hipStream_t s) {
-  double* rowk = ar.alloc<double>(n);
-  double* colk = ar.alloc<double>(n);
-  int* perm = ar.alloc<int>(n);
-  int* flag = ar.alloc<int>(1);
+  TempScope tmp(ar);
+  double* rowk = tmp.alloc<double>(n);
+  double* colk = tmp.alloc<double>(n);
+  int* perm = tmp.alloc<int>(n);
+  int* flag = tmp.alloc<int>(1);
+  if (ar.dry()) return;
   HIPCHECK(hipMemsetAsync(flag, 0, sizeof(int), s));
   for (int k = 0; k < n; ++k) {
     hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, s, n, k, A, perm, flag);
@@ -1255,8 +1333,10 @@ void build_patches(DevArena& ar, Level<T>& L, const PatchSet& ps, const DCsr<dou
   d.off = ar.upload<int64_t>(off, s);
   {
     int4* dd = ar.alloc<int4>(np);
-    HIPCHECK(hipMemcpyAsync(dd, dims.data(), dims.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    HIPCHECK(hipStreamSynchronize(s));
+    if (!ar.dry()) {
+      HIPCHECK(hipMemcpyAsync(dd, dims.data(), dims.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+      HIPCHECK(hipStreamSynchronize(s));
+    }
     d.dims = dd;
   }
   d.foff = ar.upload<int64_t>(foff, s);
@@ -1273,12 +1353,14 @@ void build_patches(DevArena& ar, Level<T>& L, const PatchSet& ps, const DCsr<dou
   }
   const int64_t stride = (int64_t)max_nc * max_nc + 2 * (int64_t)max_nv * MAX_NS;
   const size_t lds_bytes = (size_t)stride * sizeof(double);
-  int64_t* bad = ar.alloc<int64_t>(1);
+  TempScope work(ar);  // factorisation work areas, released at the end of this level
+  int64_t* bad = work.alloc<int64_t>(1);
   int64_t init = INT64_MAX;
-  HIPCHECK(hipMemcpyAsync(bad, &init, sizeof(int64_t), hipMemcpyHostToDevice, s));
   const bool use_lds = lds_bytes <= kMaxLds;
   const unsigned grid = use_lds ? (unsigned)std::min<int64_t>(np, 65536) : (unsigned)std::min<int64_t>(np, 1024);
-  double* gwork = use_lds ? nullptr : ar.alloc<double>((size_t)stride * grid);
+  double* gwork = use_lds ? nullptr : work.alloc<double>((size_t)stride * grid);
+  if (ar.dry()) return;
+  HIPCHECK(hipMemcpyAsync(bad, &init, sizeof(int64_t), hipMemcpyHostToDevice, s));
   // 4 (blocks in LDS) or 16 (blocks in global memory) wavefronts per patch: the
   // row updates of a Gauss-Jordan step are split between them
   if (use_lds)
@@ -1316,7 +1398,7 @@ std::unique_ptr<Cycle<T>> build_cycle(mas_handle* h, const std::vector<Csr>& Ks,
                                       const std::vector<int64_t>& dir0, hipStream_t s) {
   DevArena& ar = h->arena;
   SetupTrace tr;
-  const bool tune = h->par.autotune != 0;
+  const bool tune = h->par.autotune != 0 && !ar.dry();
   auto cyc = std::make_unique<Cycle<T>>();
   cyc->par = h->par;
   cyc->dim = h->dim;
@@ -1341,13 +1423,13 @@ std::unique_ptr<Cycle<T>> build_cycle(mas_handle* h, const std::vector<Csr>& Ks,
         L.P = upload_csr<T>(ar, Ps[l], s);
         L.R = upload_csr<T>(ar, transpose(Ps[l]), s);
       }
-      if (tr.on) HIPCHECK(hipStreamSynchronize(s));
+      if (tr.on && !ar.dry()) HIPCHECK(hipStreamSynchronize(s));
       tr.mark("device: level " + std::to_string(l) + " operators");
       if (L.relax && !patches[l].off.empty()) {
         if constexpr (std::is_same<T, double>::value) {
           build_patches<T>(ar, L, patches[l], L.K, (int)l, cyc->nr_max, h->par, s);
         } else {  // the FP64 operator lives only while the patches are factorised
-          DevArena tmp;
+          TempScope tmp(ar);
           const DCsr<double> K64 = upload_csr_plain<double>(tmp, Ks[l], s);
           build_patches<T>(ar, L, patches[l], K64, (int)l, cyc->nr_max, h->par, s);
         }
@@ -1393,7 +1475,7 @@ std::unique_ptr<Cycle<T>> build_cycle(mas_handle* h, const std::vector<Csr>& Ks,
       }
     }
   }
-  if (tr.on) HIPCHECK(hipStreamSynchronize(s));
+  if (tr.on && !ar.dry()) HIPCHECK(hipStreamSynchronize(s));
   tr.mark("device: levels, factorisation");
   // relaxation wrapper (Section 3.3.1): every Vanka level except the Scott-Vogelius K0
   if (h->par.krylov_its > 0) {
@@ -1436,7 +1518,7 @@ std::unique_ptr<Cycle<T>> build_cycle(mas_handle* h, const std::vector<Csr>& Ks,
       autotune_team<T>(L.P, C.x, L.x, s, tune);
     }
   }
-  if (tr.on) HIPCHECK(hipStreamSynchronize(s));
+  if (tr.on && !ar.dry()) HIPCHECK(hipStreamSynchronize(s));
   tr.mark("device: product autotune");
   // coarsest: dense inverse of the bordered operator
   const int64_t nb = Kc_bordered.nr;
@@ -1607,7 +1689,35 @@ void analyze_impl(mas_handle* h, const mas_problem* pr, bool dev = false, hipStr
   if ((int64_t)blocks[d].size() != Ap.nr) throw MasError(MAS_EINVAL, "Ap size does not match K1's pressure block");
   std::vector<std::vector<Csr>> fP;
   std::vector<std::vector<std::vector<double>>> fB;
-  {
+  if (pr->n_prebuilt > 0) {
+    // a hierarchy built elsewhere: the per-field interpolations replace the
+    // smoothed aggregation; only the coarsest pressure near-null vector is read
+    if (!pr->prebuilt_P) throw MasError(MAS_EINVAL, "n_prebuilt > 0 needs prebuilt_P");
+    const int L = pr->n_prebuilt;
+    if (L + 1 > 16) throw MasError(MAS_EINVAL, "too many prebuilt levels");
+    fP.assign(d + 1, {});
+    fB.assign(d + 1, {});
+    for (int f = 0; f <= d; ++f) {
+      for (int l = 0; l < L; ++l) {
+        Csr P = get_csr(pr->prebuilt_P[(size_t)l * (d + 1) + f], "prebuilt_P");
+        const int64_t rows = l == 0 ? (int64_t)blocks[f].size() : fP[f][l - 1].nc;
+        if (P.nr != rows || P.nc < 1 || P.nc > P.nr)
+          throw MasError(MAS_EINVAL, "prebuilt_P[" + std::to_string(l * (d + 1) + f) + "] is " +
+                                         std::to_string(P.nr) + " x " + std::to_string(P.nc) + "; it needs " +
+                                         std::to_string(rows) + " rows (the field's DoFs of the finer level) and "
+                                         "at most as many columns");
+        fP[f].push_back(std::move(P));
+      }
+      fB[f].resize(L + 1);
+    }
+    if (pr->p_nullspace) {
+      if (!pr->prebuilt_null_p) throw MasError(MAS_EINVAL, "prebuilt_null_p is required with p_nullspace");
+      const int64_t nc = fP[d][L - 1].nc;
+      fB[d][L].assign(pr->prebuilt_null_p, pr->prebuilt_null_p + nc);
+      for (double v : fB[d][L])
+        if (!std::isfinite(v)) throw MasError(MAS_EINVAL, "prebuilt_null_p has a non-finite entry");
+    }
+  } else {
     std::vector<Csr> Af;
     for (int f = 0; f <= d; ++f) Af.push_back((f < d) ? submatrix(K1f, blocks[f], blocks[f]) : Ap);
     sa_fields(Af, soc_params(par), par.max_coarse, par.max_levels, fP, fB);
@@ -1803,15 +1913,18 @@ void analyze_impl(mas_handle* h, const mas_problem* pr, bool dev = false, hipStr
 void upload_impl(mas_handle* h, hipStream_t s) {
   HostPlan& pl = h->plan;
   const mas_params& par = h->par;
-  const bool tune = par.autotune != 0;
+  const bool dry = h->arena.dry();
+  const bool tune = par.autotune != 0 && !dry;
   const int64_t n0 = h->n0;
   h->K0full = upload_csr<double>(h->arena, pl.K0, s);
   h->K0full.stream = (double)h->K0full.nnz * 12.0 >= kStreamBytes;  // one FGMRES product per iteration
   {
-    double* tx = h->arena.alloc<double>(n0);
-    double* ty = h->arena.alloc<double>(n0);
-    HIPCHECK(hipMemsetAsync(tx, 0, n0 * sizeof(double), s));
+    TempScope tmp(h->arena);
+    double* tx = tmp.alloc<double>(n0);
+    double* ty = tmp.alloc<double>(n0);
+    if (!dry) HIPCHECK(hipMemsetAsync(tx, 0, n0 * sizeof(double), s));
     autotune_team<double>(h->K0full, tx, ty, s, tune);
+    if (!dry) HIPCHECK(hipStreamSynchronize(s));
   }
   if (par.precision == MAS_FP32)
     h->cyc = build_cycle<float>(h, pl.Ks, pl.Ps, pl.fields, pl.patches, pl.dlsc, pl.relax, pl.Kb, pl.free0, pl.dir0,
@@ -1832,6 +1945,7 @@ void upload_impl(mas_handle* h, hipStream_t s) {
   h->use_mgs = par.gram_schmidt == MAS_GS_MODIFIED;
   h->hdev = h->arena.alloc<double>((size_t)(m + 2) * R);
   h->ydev = h->arena.alloc<double>((size_t)(m + 1) * R);
+  if (dry) return;  // workspace query: sizes only, the handle stays analysed-only
   HIPCHECK(hipHostMalloc((void**)&h->hhost, (size_t)(m + 2) * R * sizeof(double), hipHostMallocDefault));
   HIPCHECK(hipStreamCreateWithFlags(&h->gs, hipStreamNonBlocking));
   HIPCHECK(hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming));
@@ -1844,8 +1958,10 @@ void upload_impl(mas_handle* h, hipStream_t s) {
 
 // Frees every device resource of the handle; the host analysis stays.
 void release_device(mas_handle* h) {
-  if (!h->on_device && !h->gs && !h->hhost && h->arena.ptrs.empty()) return;  // nothing on the device
-  (void)hipDeviceSynchronize();  // work of the caller's streams may still read the handle's arrays
+  // work of the caller's streams may still read the handle's arrays (a caller
+  // workspace too); a DRY arena never reached the device
+  if (h->on_device || h->gs || h->hhost || !h->arena.ptrs.empty() || h->arena.mode == DevArena::BUFFER)
+    (void)hipDeviceSynchronize();
   for (hipGraphExec_t& g : h->iter_graph)
     if (g) (void)hipGraphExecDestroy(g);
   h->iter_graph.clear();
@@ -1858,7 +1974,7 @@ void release_device(mas_handle* h) {
   h->gs = nullptr;
   h->ev_in = h->ev_out = nullptr;
   h->hhost = nullptr;
-  h->V = h->Z = h->w = h->partial = h->hdev = h->ydev = nullptr;
+  h->V = h->Z = h->w = h->partial = h->hdev = h->ydev = h->cpart = nullptr;
   h->pw = nullptr;
   h->dir_idx = nullptr;
   h->K0full = DCsr<double>{};
@@ -2524,6 +2640,64 @@ int mas_upload(mas_handle* h, void* stream) {
   }
   if (h->on_device) return MAS_OK;
   try {
+    upload_impl(h, (hipStream_t)stream);
+  } catch (const MasError& e) {
+    release_device(h);
+    return fail(e);
+  } catch (const std::bad_alloc&) {
+    release_device(h);
+    g_last_error = "host allocation failed";
+    return MAS_ENOMEM;
+  } catch (const std::exception& e) {
+    release_device(h);
+    g_last_error = e.what();
+    return MAS_EINVAL;
+  }
+  return MAS_OK;
+}
+
+int mas_workspace_size(mas_handle* h, size_t* bytes) {
+  if (!h || !bytes) {
+    g_last_error = "null argument";
+    return MAS_EINVAL;
+  }
+  if (h->on_device) {
+    g_last_error = "the handle is on the device: query the workspace size before mas_upload_ws";
+    return MAS_EINVAL;
+  }
+  int rc = MAS_OK;
+  try {
+    h->arena.use_buffer(nullptr, 0, true);
+    upload_impl(h, nullptr);  // sizes only: nothing is allocated or launched
+    *bytes = h->arena.peak;
+  } catch (const MasError& e) {
+    rc = fail(e);
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    rc = MAS_ENOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    rc = MAS_EINVAL;
+  }
+  release_device(h);  // drops the counted (never dereferenced) pointers
+  return rc;
+}
+
+int mas_upload_ws(mas_handle* h, void* dev_ws, size_t ws_bytes, void* stream) {
+  if (!h || !dev_ws) {
+    g_last_error = "null argument";
+    return MAS_EINVAL;
+  }
+  if (h->on_device) {
+    g_last_error = "the handle is already on the device";
+    return MAS_EINVAL;
+  }
+  if ((uintptr_t)dev_ws % DevArena::kAlign != 0) {
+    g_last_error = "dev_ws must be 256-byte aligned";
+    return MAS_EINVAL;
+  }
+  try {
+    h->arena.use_buffer(dev_ws, ws_bytes, false);
     upload_impl(h, (hipStream_t)stream);
   } catch (const MasError& e) {
     release_device(h);

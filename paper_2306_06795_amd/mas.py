@@ -34,7 +34,8 @@ class mas_problem(C.Structure):
                 ("field0", C.c_void_p), ("field1", C.c_void_p), ("dir0", C.c_void_p), ("dir1", C.c_void_p),
                 ("p_nullspace", C.c_int32), ("p_weight0", C.c_void_p), ("mu_diag0", C.c_void_p),
                 ("n_elem", C.c_int64), ("elem_p0", C.c_void_p), ("Pp0", mas_csr), ("Mdg", mas_csr),
-                ("Mcg", mas_csr)]
+                ("Mcg", mas_csr), ("n_prebuilt", C.c_int32), ("prebuilt_P", C.c_void_p),
+                ("prebuilt_null_p", C.c_void_p)]
 
 
 class mas_params(C.Structure):
@@ -75,6 +76,8 @@ def _load():
     lib.mas_setup.argtypes = [P(mas_problem), P(mas_params), C.c_void_p, P(C.c_void_p)]
     lib.mas_analyze.argtypes = [P(mas_problem), P(mas_params), P(C.c_void_p)]
     lib.mas_upload.argtypes = [C.c_void_p, C.c_void_p]
+    lib.mas_workspace_size.argtypes = [C.c_void_p, P(C.c_size_t)]
+    lib.mas_upload_ws.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
     lib.mas_release.argtypes = [C.c_void_p]
     lib.mas_apply.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]
     lib.mas_solve.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_int32,
@@ -93,7 +96,8 @@ def _load():
     lib.mas_error_string.restype = C.c_char_p
     lib.mas_last_error.argtypes = []
     lib.mas_last_error.restype = C.c_char_p
-    for name in ("mas_setup", "mas_analyze", "mas_scale_rows", "mas_apply", "mas_solve", "mas_get_info", "mas_export_level", "mas_set_timing",
+    for name in ("mas_setup", "mas_analyze", "mas_upload", "mas_release", "mas_workspace_size", "mas_upload_ws",
+                 "mas_solve_rtols", "mas_scale_rows", "mas_apply", "mas_solve", "mas_get_info", "mas_export_level", "mas_set_timing",
                  "mas_get_timing", "mas_destroy"):
         getattr(lib, name).restype = C.c_int
     return lib
@@ -101,7 +105,8 @@ def _load():
 
 lib = _load()
 
-EXPORTED = ("mas_default_params", "mas_setup", "mas_analyze", "mas_upload", "mas_release", "mas_apply", "mas_solve", "mas_solve_rtols",
+EXPORTED = ("mas_default_params", "mas_setup", "mas_analyze", "mas_upload", "mas_workspace_size", "mas_upload_ws",
+            "mas_release", "mas_apply", "mas_solve", "mas_solve_rtols",
             "mas_get_info", "mas_scale_rows", "mas_export_level", "mas_set_timing", "mas_get_timing", "mas_destroy",
             "mas_error_string", "mas_last_error")
 
@@ -149,8 +154,11 @@ def _arr(a, dtype, keep: list):
     return a.ctypes.data
 
 
-def make_problem_struct(prob, keep: list) -> mas_problem:
-    """mas_problem from an object with the fields of include/mas.h (a StokesProblem)."""
+def make_problem_struct(prob, keep: list, prebuilt=None) -> mas_problem:
+    """mas_problem from an object with the fields of include/mas.h (a StokesProblem).
+    prebuilt: None, or (Ps, null_p) with Ps[l][f] the interpolation of field f
+    from hierarchy level l + 1 to level l (scipy sparse) and null_p the
+    coarsest pressure near-null vector."""
     s = mas_problem()
     s.dim = prob.dim
     s.disc = MAS_SV if prob.disc == "SV" else MAS_TH
@@ -170,6 +178,14 @@ def make_problem_struct(prob, keep: list) -> mas_problem:
         s.Pp0 = _csr(prob.Pp0, keep)
         s.Mdg = _csr(prob.Mdg, keep)
         s.Mcg = _csr(prob.Mcg, keep)
+    if prebuilt is not None:
+        Ps, null_p = prebuilt
+        flat = [_csr(P, keep) for level in Ps for P in level]
+        arr = (mas_csr * len(flat))(*flat)
+        keep.append(arr)
+        s.n_prebuilt = len(Ps)
+        s.prebuilt_P = C.cast(arr, C.c_void_p)
+        s.prebuilt_null_p = _arr(null_p, np.float64, keep)
     return s
 
 
@@ -183,9 +199,9 @@ def _stream(stream):
 class Handle:
     """Owns one mas_handle.  Device arrays are torch tensors (float64, on the GPU)."""
 
-    def __init__(self, prob, params: mas_params, stream=None, analyze_only: bool = False):
+    def __init__(self, prob, params: mas_params, stream=None, analyze_only: bool = False, prebuilt=None):
         keep: list = []
-        s = make_problem_struct(prob, keep)
+        s = make_problem_struct(prob, keep, prebuilt)
         h = C.c_void_p()
         if analyze_only:
             _check(lib.mas_analyze(C.byref(s), C.byref(params), C.byref(h)))
@@ -202,6 +218,18 @@ class Handle:
     def release(self):
         """Free the device memory, keep the host analysis."""
         _check(lib.mas_release(self.h))
+
+    def workspace_size(self) -> int:
+        """Device bytes upload_ws needs (analysed handle; no device is touched)."""
+        n = C.c_size_t()
+        _check(lib.mas_workspace_size(self.h, C.byref(n)))
+        return n.value
+
+    def upload_ws(self, ws, stream=None):
+        """Device half of the setup inside a caller-owned device tensor ``ws``
+        (kept alive by the caller until release/close)."""
+        _check(lib.mas_upload_ws(self.h, C.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
+                                 _stream(stream)))
 
     def apply(self, r, z, nrhs: int = 1, stream=None):
         _check(lib.mas_apply(self.h, C.c_void_p(r.data_ptr()), C.c_void_p(z.data_ptr()), nrhs, _stream(stream)))

@@ -201,6 +201,12 @@ def test_documented_refusals_need_no_gpu():
     assert lib.mas_get_info(h.h, None) == mas.MAS_EINVAL
     assert lib.mas_release(None) == mas.MAS_EINVAL
     assert lib.mas_upload(None, None) == mas.MAS_EINVAL
+    sz = C.c_size_t()
+    assert lib.mas_workspace_size(None, C.byref(sz)) == mas.MAS_EINVAL
+    assert lib.mas_workspace_size(h.h, None) == mas.MAS_EINVAL
+    assert lib.mas_upload_ws(None, C.c_void_p(256), 1024, None) == mas.MAS_EINVAL
+    assert lib.mas_upload_ws(h.h, None, 1024, None) == mas.MAS_EINVAL
+    assert lib.mas_upload_ws(h.h, C.c_void_p(0x1004), 1 << 20, None) == mas.MAS_EINVAL  # misaligned
     assert lib.mas_set_timing(None, 1) == mas.MAS_EINVAL
     out = (C.c_double * 18)()
     assert lib.mas_get_timing(None, out, 18) == mas.MAS_EINVAL
@@ -285,4 +291,73 @@ def test_coarsest_size_is_checked_where_the_fields_are_cut():
     h = mas.Handle(P, mas.default_params(2, max_coarse=300), analyze_only=True)
     i = h.info()
     assert i["coarse_n"] <= 4096 and i["n_levels"] >= 3
+    h.close()
+
+
+def oracle_prebuilt(pre):
+    """Per-field interpolations of the oracle's hierarchy (Ps[l][f]) and the
+    coarsest pressure near-null vector, in the form mas_problem.prebuilt_P takes."""
+    from oracle.sparse import submatrix
+    d = pre.dim
+    Ps = []
+    for l, lv in enumerate(pre.levels[:-1]):
+        fine, coarse = lv.field, pre.levels[l + 1].field
+        Ps.append([submatrix(lv.P, np.nonzero(fine == f)[0], np.nonzero(coarse == f)[0]) for f in range(d + 1)])
+    return Ps, pre.levels[-1].null_p
+
+
+@pytest.mark.parametrize("kw,soc", [
+    (dict(dim=2, n=24, jitter=0.2, seed=2, forcing="gaussian", bc="lid"), "symmetric"),
+    (dict(dim=2, n=24, jitter=0.2, seed=2, forcing="gaussian", bc="lid"), "evolution"),
+    (dict(dim=3, n=5, forcing="smooth", bc="zero", seed=3), "symmetric"),
+    (dict(dim=2, n=10, disc="SV", seed=4, forcing="gaussian", bc="zero"), "evolution"),
+])
+def test_prebuilt_hierarchy_gives_the_oracle_levels(kw, soc):
+    """A hierarchy injected through prebuilt_P / prebuilt_null_p replaces
+    Algorithm 1: the library's levels are the oracle's (patterns equal, values
+    to rounding), whatever strength measure the library's own parameters name."""
+    P = make_problem(**kw)
+    par = dc.default_params(P, max_coarse=30, soc=soc)
+    pre = dc.DCPreconditioner(P, par)
+    other = "evolution" if soc == "symmetric" else "symmetric"
+    _, mp = _same_params(P, max_coarse=30, soc=other)
+    h = mas.Handle(P, mp, analyze_only=True, prebuilt=oracle_prebuilt(pre))
+    info = h.info()
+    assert info["n_levels"] == 1 + len(pre.levels)
+    for l, K in enumerate([pre.K0] + [lv.K for lv in pre.levels]):
+        Kl = h.export_level(l)
+        assert np.array_equal(Kl.indptr, K.indptr) and np.array_equal(Kl.indices, K.indices), l
+        assert np.abs(Kl.data - K.data).max() <= 1e-13 * np.abs(K.data).max(), l
+    h.close()
+
+
+def test_prebuilt_hierarchy_is_validated():
+    P = make_problem(dim=2, n=12, jitter=0.2, seed=2, forcing="gaussian", bc="lid")
+    pre = dc.DCPreconditioner(P, dc.default_params(P, max_coarse=30))
+    Ps, null_p = oracle_prebuilt(pre)
+    mp = mas.default_params(2, max_coarse=30)
+    bad = [list(level) for level in Ps]
+    bad[0][1] = bad[0][1][1:]  # one row short
+    for prebuilt in ((bad, null_p), (Ps, None)):
+        with pytest.raises(mas.MasError) as e:
+            mas.Handle(P, mp, analyze_only=True, prebuilt=prebuilt)
+        assert e.value.code == mas.MAS_EINVAL
+
+
+def test_workspace_size_is_computed_on_the_host():
+    """mas_workspace_size sizes mas_upload_ws from the analysis alone: no device
+    is touched (this runs without one), the handle stays analysed-only, the
+    answer is reproducible and grows with the right-hand sides a call may carry."""
+    P = make_problem(dim=3, n=4, forcing="smooth", bc="zero", seed=3)
+    sizes = []
+    for nr in (1, 4):
+        h = mas.Handle(P, mas.default_params(3, max_coarse=40, nrhs_max=nr), analyze_only=True)
+        a, b = h.workspace_size(), h.workspace_size()
+        assert a == b and a > 0 and a % 256 == 0
+        assert h.info()["device_bytes"] == 0
+        sizes.append(a)
+        h.close()
+    assert sizes[1] > sizes[0]
+    h = mas.Handle(P, mas.default_params(3, max_coarse=40, precision=mas.MAS_FP32), analyze_only=True)
+    assert 0 < h.workspace_size() < sizes[0]
     h.close()

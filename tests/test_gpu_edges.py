@@ -10,6 +10,7 @@ torch = pytest.importorskip("torch")
 
 from oracle import dc  # noqa: E402
 from paper_2306_06795_amd import mas  # noqa: E402
+from parity import assert_parity  # noqa: E402
 from paper_2306_06795_amd.inputs import make_problem  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -75,7 +76,7 @@ def test_two_level_hierarchy_matches_oracle():
     h.apply(torch.tensor(r, device=DEV), z)
     torch.cuda.synchronize()
     ref = pre.apply(r)
-    assert np.linalg.norm(z.cpu().numpy() - ref) <= 1e-11 * np.linalg.norm(ref)
+    assert_parity(z.cpu().numpy(), ref, P.field0, 1e-11, "two-level")
     h.close()
 
 

@@ -1,9 +1,12 @@
 """The benchmark workloads at full size, in the configuration bench.py times
-(default parameters of each workload): one FP64 cycle application of the
-256x256 Taylor-Hood cavity against the oracle, element by element; and, for
-every workload, properties that hold at any size -- the true residual of the
-solve computed on the host, the zero-mean pressure, FP32 against FP64 cycles,
-and batched right-hand sides against the same columns solved alone."""
+(default parameters of each workload): FP64 cycle applications against the
+oracle's, element by element and per field, for the 256x256 Taylor-Hood
+cavity, the 32^3 Taylor-Hood cube (the oracle solving every patch with a dense
+LU on the fly) and sampled columns of the 64-right-hand-side Scott-Vogelius
+batch (FP64 and the FP32 cycle the bench times); and, for every workload,
+properties that hold at any size -- the true residual of the solve computed on
+the host, the zero-mean pressure, FP32 against FP64 cycles, and batched
+right-hand sides against the same columns solved alone."""
 import time
 
 import numpy as np
@@ -11,7 +14,8 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
-from oracle import dc  # noqa: E402
+from oracle import dc, vanka  # noqa: E402
+from parity import assert_parity  # noqa: E402
 from paper_2306_06795_amd import mas  # noqa: E402
 from paper_2306_06795_amd.inputs import make_config  # noqa: E402
 
@@ -41,9 +45,7 @@ def test_th2d_256_apply_matches_oracle_and_solve():
     pre = dc.DCPreconditioner(P, dc.default_params(P))
     ref = pre.apply(r)
     print(f"  oracle setup + apply {time.perf_counter() - t0:.1f}s", flush=True)
-    err = np.linalg.norm(z.cpu().numpy() - ref) / np.linalg.norm(ref)
-    print(f"  apply rel err {err:.2e}", flush=True)
-    assert err <= 1e-11
+    assert_parity(z.cpu().numpy(), ref, P.field0, 1e-11, "th2d_256 apply")
     b = torch.tensor(P.b, device=DEV)
     x = torch.empty_like(b)
     rc, info = h.solve(b, x, rtol=1e-8)
@@ -111,3 +113,58 @@ def test_sv2d_128x64_batch_of_64_equals_columns_alone():
         assert abs(i1[0]["iters"] - info[k]["iters"]) <= 1, (k, i1, info[k])
         assert np.linalg.norm(xs - Xs[:, k]) <= 1e-6 * np.linalg.norm(xs), k
     h.close()
+
+
+@pytest.mark.slow
+def test_th3d_32_fp64_apply_matches_oracle():
+    """One FP64 cycle application at 32^3 (859,812 unknowns; ~4,300 coarse
+    patches of ~725 DoFs, each solved by the oracle with a dense LU: about five
+    minutes of oracle time, hence marked slow)."""
+    t0 = time.perf_counter()
+    P = make_config("th3d_32")
+    print(f"[fullsize th3d_32 apply] n0={P.n0} generated in {time.perf_counter() - t0:.1f}s", flush=True)
+    h = mas.Handle(P, params(P))
+    r = np.random.default_rng(17).standard_normal(P.n0)
+    z = torch.empty(P.n0, dtype=torch.float64, device=DEV)
+    h.apply(torch.tensor(r, device=DEV), z)
+    torch.cuda.synchronize()
+    zs = z.cpu().numpy()
+    h.close()
+    t0 = time.perf_counter()
+    pre = dc.DCPreconditioner(P, dc.default_params(P))
+    print(f"  oracle setup {time.perf_counter() - t0:.1f}s, levels {[lv.K.shape[0] for lv in pre.levels]}",
+          flush=True)
+    vanka.PROGRESS = True
+    try:
+        t0 = time.perf_counter()
+        ref = pre.apply(r)
+    finally:
+        vanka.PROGRESS = False
+    print(f"  oracle apply {time.perf_counter() - t0:.1f}s", flush=True)
+    assert_parity(zs, ref, P.field0, 1e-11, "th3d_32 apply")
+
+
+def test_sv2d_128x64_batched_columns_match_oracle_apply():
+    """Columns of one batched cycle application over the 64 right-hand sides
+    against the oracle's apply of each column: FP64 to 1e-11, and the FP32
+    cycle the bench times to 1e-5."""
+    P = make_config("sv2d_128x64")
+    nr = P.b.shape[1]
+    R = np.random.default_rng(19).standard_normal((P.n0, nr))
+    print(f"[fullsize sv2d_128x64 apply] n0={P.n0} nrhs={nr}", flush=True)
+    Z = {}
+    for prec in (mas.MAS_FP64, mas.MAS_FP32):
+        h = mas.Handle(P, params(P, precision=prec, nrhs_max=nr))
+        Rd = torch.tensor(R, device=DEV)
+        Zd = torch.empty_like(Rd)
+        h.apply(Rd, Zd, nrhs=nr)
+        torch.cuda.synchronize()
+        Z[prec] = Zd.cpu().numpy()
+        h.close()
+    pre = dc.DCPreconditioner(P, dc.default_params(P))
+    for k in (0, 31, nr - 1):
+        t0 = time.perf_counter()
+        ref = pre.apply(np.ascontiguousarray(R[:, k]))
+        print(f"  column {k}: oracle apply {time.perf_counter() - t0:.1f}s", flush=True)
+        assert_parity(Z[mas.MAS_FP64][:, k], ref, P.field0, 1e-11, f"FP64 column {k}")
+        assert_parity(Z[mas.MAS_FP32][:, k], ref, P.field0, 1e-5, f"FP32 column {k}")

@@ -300,3 +300,16 @@ def test_vertex_star_patches_closed_form(n):
                     assert offs == star
         assert len(pt.dofs) == P.meta["n_p1"]
     assert nv == int((~P.dir0[: 2 * nn]).sum())
+
+
+def test_dense_patch_blocks_are_the_principal_submatrices():
+    """The oracle's dense patch matrices equal scipy's fancy-indexed submatrix
+    A[idx][:, idx] (explicit zeros included as zeros)."""
+    from oracle.sparse import dense_blocks
+    rng = np.random.default_rng(0)
+    A = sp.random(120, 120, density=0.08, random_state=3, format="csr")
+    A = sp.csr_matrix(A + A.T + sp.identity(120))
+    A.sort_indices()
+    idx = np.stack([np.sort(rng.choice(120, 13, replace=False)) for _ in range(25)])
+    D = dense_blocks(A, idx)
+    assert np.array_equal(D, np.stack([A[i][:, i].toarray() for i in idx]))
