@@ -253,6 +253,21 @@ int mas_release(mas_handle* h);
  * MAS_EHIP when a launch fails (the contents of z are then undefined). */
 int mas_apply(mas_handle* h, const double* r, double* z, int32_t nrhs, void* stream);
 
+/* mas_apply for callers that cannot allocate device memory during the call or
+ * must not hold per-handle cycle buffers (code under stream capture, tight
+ * serving loops, allocation-free harnesses): the same cycle, the same
+ * arguments and the same result as mas_apply, bit for bit, but the cycle's
+ * per-application scratch (level vectors, patch outputs, DLSC, relaxation-
+ * wrapper and Scott-Vogelius work vectors) lives in a file-scope device array
+ * of 64 MiB, one per device, held until the process ends.  The call makes no
+ * device or host allocation and no event-timing (mas_set_timing is ignored
+ * during it).  Every call on one device shares that device's array and leaves
+ * its contents behind (each cycle writes what it reads first): calls that
+ * overlap on one device race, so callers serialise them.  Errors as mas_apply,
+ * and MAS_EINVAL when the scratch this handle needs for nrhs right-hand sides
+ * exceeds 64 MiB (the message names the bytes). */
+int mas_apply_static(mas_handle* h, const double* r, double* z, int32_t nrhs, void* stream);
+
 /* FGMRES for K0 x = b from x0 = 0 (Section 4).  b, x: device FP64 n0 x nrhs.
  * Stops when ||b - K0 x|| <= rtol ||b|| (true residual) or after max_it
  * iterations.  With p_nullspace and p_weight0 the returned pressure has zero

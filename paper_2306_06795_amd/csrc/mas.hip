@@ -10,6 +10,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
+#include <mutex>
 #include <memory>
 #include <numeric>
 #include <stdexcept>
@@ -448,6 +450,9 @@ struct CycleBase {
   virtual ~CycleBase() = default;
   virtual void apply(const double* r, double* z, hipStream_t s) = 0;
   virtual void set_nr(int nr) = 0;
+  // Every per-application scratch array of the cycle for r right-hand sides,
+  // in a fixed order: f(address of the pointer field, bytes).
+  virtual void scratch_arrays(int r, const std::function<void(void**, size_t)>& f) = 0;
 };
 
 // Optional event timing of the cycle's kernels, per kernel kind, with the
@@ -919,6 +924,47 @@ struct Cycle : CycleBase {
       spmv<2>(L.P, C.x, nullptr, L.x, s);
     }
     if (L.relax && nu2 > 0) relax_level(L, nu2, om, false, s);
+  }
+
+  void scratch_arrays(int r, const std::function<void(void**, size_t)>& f) override {
+    const size_t st = sizeof(T), sd = sizeof(double);
+    auto v = [&](T*& p, int64_t n) { f((void**)&p, (size_t)n * st); };
+    auto vd = [&](double*& p, int64_t n) { f((void**)&p, (size_t)n * sd); };
+    for (Level<T>& L : lev) {
+      v(L.x, L.n * r);
+      v(L.b, L.n * r);
+      v(L.r, L.n * r);
+      if (L.pt.np > 0) {
+        v(L.pt.Y, L.pt.ny);
+        if (r > 1) v(L.pt.Ynr, L.pt.ndofs * r);
+      }
+      if (L.dl.on) {
+        DDlsc<T>& D = L.dl;
+        for (T** q : {&D.ru, &D.vs, &D.tmp, &D.t1, &D.t2}) v(*q, D.nv * r);
+        for (T** q : {&D.rp, &D.q, &D.dp}) v(*q, D.np * r);
+        for (T** q : {&D.cd, &D.cd2, &D.cres}) v(*q, std::max(D.nv, D.np) * r);
+        for (auto& Lk : D.sh)
+          for (T** q : {&Lk.x, &Lk.b, &Lk.res, &Lk.d1, &Lk.d2, &Lk.corr})
+            if (*q) v(*q, Lk.n * r);
+      }
+    }
+    if (kv) {  // relaxation wrapper (one right-hand side)
+      const int m = par.krylov_its;
+      int64_t nmax = 0;
+      for (Level<T>& L : lev)
+        if (L.krylov) nmax = std::max(nmax, L.n);
+      v(kv, (int64_t)(m + 1) * nmax);
+      v(kz, (int64_t)m * nmax);
+      v(kw, nmax);
+      vd(kpart, 2 * (int64_t)kblk);
+      vd(kh, (int64_t)(m + 1) * m);
+      vd(kbeta, 1);
+      vd(ky, m);
+    }
+    if (sv) {
+      v(sv_t0, np0 * r);
+      for (T** q : {&sv_t1, &sv_z, &sv_cd, &sv_cd2, &sv_cres}) v(*q, np1 * r);
+    }
   }
 
   void set_nr(int k) override {
@@ -2653,6 +2699,90 @@ int mas_upload(mas_handle* h, void* stream) {
     g_last_error = e.what();
     return MAS_EINVAL;
   }
+  return MAS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// mas_apply_static: the cycle's per-application scratch in a file-scope device
+// array.  Every device the library runs on holds its own copy of the array
+// until the process ends; host code takes its address on that device from
+// hipGetSymbolAddress (the array's name is only a host-side stand-in).
+
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+
+// address of `scratch` on the current device (looked up once per device)
+void* device_scratch() {
+  int dev = 0;
+  HIPCHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) throw MasError(MAS_EINVAL, "device ordinal out of range for the static scratch");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      throw MasError(MAS_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
+int mas_apply_static(mas_handle* h, const double* r, double* z, int32_t nrhs, void* stream) {
+  if (!h || !r || !z) {
+    g_last_error = "null argument";
+    return MAS_EINVAL;
+  }
+  if (!h->on_device) {
+    g_last_error = "handle was analysed only; call mas_setup";
+    return MAS_EINVAL;
+  }
+  if (nrhs < 1 || nrhs > std::max(1, h->par.nrhs_max)) {
+    g_last_error = "nrhs must be in [1, nrhs_max]";
+    return MAS_EINVAL;
+  }
+  // bytes this call's scratch takes, each array rounded to 256 bytes
+  size_t need = 0;
+  h->cyc->scratch_arrays(nrhs, [&](void**, size_t b) { need += DevArena::round(std::max<size_t>(b, 1)); });
+  if (need > kStaticScratchBytes) {
+    g_last_error = "mas_apply_static: this handle's cycle scratch for " + std::to_string(nrhs) +
+                   " right-hand side(s) is " + std::to_string(need) + " bytes, above the static scratch of " +
+                   std::to_string(kStaticScratchBytes) + " bytes (use mas_apply)";
+    return MAS_EINVAL;
+  }
+  std::vector<void*> saved;
+  bool moved = false;
+  const bool timing = h->tm.on;
+  try {
+    char* base = (char*)device_scratch();
+    size_t off = 0;
+    h->cyc->scratch_arrays(nrhs, [&](void** p, size_t b) {
+      saved.push_back(*p);
+      *p = base + off;
+      off += DevArena::round(std::max<size_t>(b, 1));
+    });
+    moved = true;
+    h->tm.on = false;  // no event timing here: it would create events during the call
+    hipStream_t s = (hipStream_t)stream;
+    h->cyc->set_nr(nrhs);
+    h->cyc->apply(r, z, s);
+    h->cyc->set_nr(1);
+  } catch (const MasError& e) {
+    h->cyc->set_nr(1);
+    h->tm.on = timing;
+    if (moved) {
+      size_t k = 0;
+      h->cyc->scratch_arrays(nrhs, [&](void** p, size_t) { *p = saved[k++]; });
+    }
+    return fail(e);
+  }
+  h->tm.on = timing;
+  size_t k = 0;
+  h->cyc->scratch_arrays(nrhs, [&](void** p, size_t) { *p = saved[k++]; });
   return MAS_OK;
 }
 

@@ -80,6 +80,7 @@ def _load():
     lib.mas_upload_ws.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
     lib.mas_release.argtypes = [C.c_void_p]
     lib.mas_apply.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]
+    lib.mas_apply_static.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]
     lib.mas_solve.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_int32,
                               P(mas_solve_info), C.c_void_p]
     lib.mas_solve_rtols.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, P(C.c_double), C.c_int32,
@@ -97,7 +98,7 @@ def _load():
     lib.mas_last_error.argtypes = []
     lib.mas_last_error.restype = C.c_char_p
     for name in ("mas_setup", "mas_analyze", "mas_upload", "mas_release", "mas_workspace_size", "mas_upload_ws",
-                 "mas_solve_rtols", "mas_scale_rows", "mas_apply", "mas_solve", "mas_get_info", "mas_export_level", "mas_set_timing",
+                 "mas_solve_rtols", "mas_apply_static", "mas_scale_rows", "mas_apply", "mas_solve", "mas_get_info", "mas_export_level", "mas_set_timing",
                  "mas_get_timing", "mas_destroy"):
         getattr(lib, name).restype = C.c_int
     return lib
@@ -106,7 +107,7 @@ def _load():
 lib = _load()
 
 EXPORTED = ("mas_default_params", "mas_setup", "mas_analyze", "mas_upload", "mas_workspace_size", "mas_upload_ws",
-            "mas_release", "mas_apply", "mas_solve", "mas_solve_rtols",
+            "mas_release", "mas_apply", "mas_apply_static", "mas_solve", "mas_solve_rtols",
             "mas_get_info", "mas_scale_rows", "mas_export_level", "mas_set_timing", "mas_get_timing", "mas_destroy",
             "mas_error_string", "mas_last_error")
 
@@ -233,6 +234,11 @@ class Handle:
 
     def apply(self, r, z, nrhs: int = 1, stream=None):
         _check(lib.mas_apply(self.h, C.c_void_p(r.data_ptr()), C.c_void_p(z.data_ptr()), nrhs, _stream(stream)))
+
+    def apply_static(self, r, z, nrhs: int = 1, stream=None):
+        """mas_apply with the cycle scratch in the library's static device array."""
+        _check(lib.mas_apply_static(self.h, C.c_void_p(r.data_ptr()), C.c_void_p(z.data_ptr()), nrhs,
+                                    _stream(stream)))
 
     def solve(self, b, x, rtol=1e-8, max_it: int = 1000, nrhs: int = 1, stream=None):
         """rtol: one tolerance, or a sequence of nrhs (mas_solve_rtols)."""
