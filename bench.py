@@ -367,6 +367,7 @@ def main():
     t_setup = time.perf_counter() - t0
     info = h.info()
     print(f"[bench] {a.config}: n0={prob.n0} levels={info['n']} patches={info['n_patches']} "
+          f"bucket patches={info['bucket_patches']} patch kernel={info['patch_kernel']} "
           f"gen {t_gen:.1f}s setup {t_setup:.1f}s", file=sys.stderr, flush=True)
     b = torch.tensor(prob.b, device=dev)
     x = torch.empty_like(b)

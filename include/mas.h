@@ -192,6 +192,10 @@ typedef struct {
   int64_t p_nnz[16];      /* entries of P_l (level l -> l-1), 0 for l <= 1 */
   int64_t coarse_n;       /* rows of the dense coarsest solve (incl. border) */
   int64_t device_bytes;   /* device memory held by the handle (0 after mas_analyze) */
+  int64_t bucket_patches[16]; /* patches per level solved by the thread-per-patch bucket kernels */
+  int32_t patch_kernel[16];   /* kernel of the other patches of a level, chosen at upload by
+                                 timing: 0 none, 1 workgroup per patch, 2 wavefront per patch
+                                 streaming the packed columns */
 } mas_hier_info;
 
 /* Default parameters: Section 4 / Tables 2 and 4 where the paper fixes them. */

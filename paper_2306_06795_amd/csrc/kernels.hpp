@@ -783,70 +783,17 @@ __global__ void k_add3(int64_t n, T* __restrict__ x, const T* __restrict__ y, co
 }
 
 // ---------------------------------------------------------------------------
-// additive Vanka: one workgroup of TPB threads (one or four wavefronts) per
-// patch, patch data staged through LDS.  Writes the patch solution
-// x_i = K_i^-1 V_i r into Y at the patch's offset.  Large patches take four
-// wavefronts: four times the loads in flight while the record is staged and
-// one velocity row per thread afterwards.
-template <typename T, bool STAGE, int TPB, bool NT = false>
-__global__ void __launch_bounds__(TPB) k_vanka_apply(int64_t np, const int64_t* __restrict__ off,
-                                                    const int4* __restrict__ dims,
-                                                    const int64_t* __restrict__ foff,
-                                                    const int* __restrict__ dofs, const T* __restrict__ fac,
-                                                    const T* __restrict__ r, T* __restrict__ Y, int max_m,
-                                                    int64_t yshift, int full) {
-  extern __shared__ unsigned char smem_raw[];
-  T* sb = reinterpret_cast<T*>(smem_raw);
-  T* sy = sb + max_m;
-  __shared__ T sred[TPB / WAVE][MAX_NS];
-  const int64_t p = blockIdx.x;
-  if (p >= np) return;
+// The patch solve of the workgroup kernels, once the right-hand side b (sb)
+// and the factor record (sf) are in place: y_u = A^-1 b_u one row per thread,
+// t = Uhat^T b_u + b_p, y_p = S^-1 t, x_u = y_u + Uhat y_p, written to the
+// patch's output slots.  Every thread of the workgroup calls it (it holds
+// barriers).
+template <typename T, int TPB>
+__device__ __forceinline__ void vanka_patch_compute(const T* sb, T* sy, const T* sf, T (*sred)[MAX_NS], int4 d,
+                                                    int64_t o, int64_t ua, int full, T* __restrict__ Y,
+                                                    int64_t yshift) {
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
-  const int4 d = dims[p];
-  const int nv = d.x + d.y + d.z, ns = d.w, m = nv + ns;
-  const int64_t o = off[p];
-  // gather: all index loads first, then all value loads (several in flight)
-  for (int k0 = 0; k0 < m; k0 += 4 * TPB) {
-    int idx[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int k = k0 + u * TPB + tid;
-      idx[u] = k < m ? dofs[o + k] : 0;
-    }
-    T v[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) v[u] = (k0 + u * TPB + tid < m) ? r[idx[u]] : (T)0;
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (k0 + u * TPB + tid < m) sb[k0 + u * TPB + tid] = v[u];
-  }
-  // record length from the shape (foff holds per-patch base offsets only)
-  const int64_t f0 = foff[p];
-  const int64_t ua = blk_size(d.x, full) + blk_size(d.y, full) + blk_size(d.z, full);
-  const int64_t nf = ua + (int64_t)nv * ns + (int64_t)ns * (ns + 1) / 2;
-  const T* sf;
-  if (STAGE) {
-    // stage the record with 16 independent loads in flight per thread
-    T* st = sy + max_m;
-    constexpr int U = 16;
-    for (int64_t k0 = 0; k0 < nf; k0 += U * TPB) {
-      T v[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t k = k0 + u * TPB + tid;
-        v[u] = k < nf ? ldv<NT>(&fac[f0 + k]) : (T)0;
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t k = k0 + u * TPB + tid;
-        if (k < nf) st[k] = v[u];
-      }
-    }
-    sf = st;
-  } else {
-    sf = fac + f0;  // record too large for LDS: read it from memory
-  }
-  __syncthreads();
+  const int nv = d.x + d.y + d.z, ns = d.w;
   const int nc[3] = {d.x, d.y, d.z};
   // y_u = A^-1 b_u, one row per thread
   for (int row = tid; row < nv; row += TPB) {
@@ -900,6 +847,199 @@ __global__ void __launch_bounds__(TPB) k_vanka_apply(int64_t np, const int64_t* 
   }
   for (int s = 0; s < ns; ++s)
     if (tid == s) Y[o - yshift + nv + s] = yp[s];
+}
+
+// additive Vanka: one workgroup of TPB threads (one or four wavefronts) per
+// patch, patch data staged through LDS.  Writes the patch solution
+// x_i = K_i^-1 V_i r into Y at the patch's offset.  Large patches take four
+// wavefronts: four times the loads in flight while the record is staged and
+// one velocity row per thread afterwards.
+template <typename T, bool STAGE, int TPB, bool NT = false>
+__global__ void __launch_bounds__(TPB) k_vanka_apply(int64_t np, const int64_t* __restrict__ off,
+                                                    const int4* __restrict__ dims,
+                                                    const int64_t* __restrict__ foff,
+                                                    const int* __restrict__ dofs, const T* __restrict__ fac,
+                                                    const T* __restrict__ r, T* __restrict__ Y, int max_m,
+                                                    int64_t yshift, int full) {
+  extern __shared__ unsigned char smem_raw[];
+  T* sb = reinterpret_cast<T*>(smem_raw);
+  T* sy = sb + max_m;
+  __shared__ T sred[TPB / WAVE][MAX_NS];
+  const int64_t p = blockIdx.x;
+  if (p >= np) return;
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
+  const int4 d = dims[p];
+  const int nv = d.x + d.y + d.z, ns = d.w, m = nv + ns;
+  const int64_t o = off[p];
+  // record length from the shape (foff holds per-patch base offsets only)
+  const int64_t f0 = foff[p];
+  const int64_t ua = blk_size(d.x, full) + blk_size(d.y, full) + blk_size(d.z, full);
+  const int64_t nf = ua + (int64_t)nv * ns + (int64_t)ns * (ns + 1) / 2;
+  // Staged records: the first UL * TPB values are requested before the
+  // DoF-list -> vector gather, so that the gather's two dependent round trips
+  // overlap the record's loads (UL independent loads in flight per thread).
+  constexpr int UL = 32;
+  T* st = sy + max_m;
+  T v[UL];
+  if (STAGE) {
+#pragma unroll
+    for (int u = 0; u < UL; ++u) {
+      const int64_t k = (int64_t)u * TPB + tid;
+      v[u] = k < nf ? ldv<NT>(&fac[f0 + k]) : (T)0;
+    }
+  }
+  // gather: all index loads first, then all value loads (several in flight)
+  for (int k0 = 0; k0 < m; k0 += 4 * TPB) {
+    int idx[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + u * TPB + tid;
+      idx[u] = k < m ? dofs[o + k] : 0;
+    }
+    T g[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) g[u] = (k0 + u * TPB + tid < m) ? r[idx[u]] : (T)0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (k0 + u * TPB + tid < m) sb[k0 + u * TPB + tid] = g[u];
+  }
+  const T* sf;
+  if (STAGE) {
+#pragma unroll
+    for (int u = 0; u < UL; ++u) {
+      const int64_t k = (int64_t)u * TPB + tid;
+      if (k < nf) st[k] = v[u];
+    }
+    // the rest of a record longer than UL * TPB values, UL loads in flight per thread
+    for (int64_t k0 = (int64_t)UL * TPB; k0 < nf; k0 += (int64_t)UL * TPB) {
+#pragma unroll
+      for (int u = 0; u < UL; ++u) {
+        const int64_t k = k0 + (int64_t)u * TPB + tid;
+        v[u] = k < nf ? ldv<NT>(&fac[f0 + k]) : (T)0;
+      }
+#pragma unroll
+      for (int u = 0; u < UL; ++u) {
+        const int64_t k = k0 + (int64_t)u * TPB + tid;
+        if (k < nf) st[k] = v[u];
+      }
+    }
+    sf = st;
+  } else {
+    sf = fac + f0;  // record too large for LDS: read it from memory
+  }
+  __syncthreads();
+  vanka_patch_compute<T, TPB>(sb, sy, sf, sred, d, o, ua, full, Y, yshift);
+}
+
+// additive Vanka, one wavefront per patch, for patches whose velocity blocks
+// have at most 2 x 64 rows each (packed records, MAX_NS seeds at most).  No
+// LDS: the packed A_c^-1 is streamed column by column straight into
+// registers.  Lane i holds rows i and i + 64 of the block (b, y); column j of
+// the packed upper triangle (entries i <= j, contiguous) arrives with entry i
+// in lane i, which adds a_ij b_j to its own y_i (i < j, lane-local), and the
+// wavefront sums a_ij b_i over i <= j into y_j (the transposed half).  Then
+// t = Uhat^T b_u + b_p (one wavefront sum per seed), y_p = S^-1 t and
+// x_u = y_u + Uhat y_p.  WPB patches per workgroup, one per wavefront.
+template <typename T, bool NT, int WPB>
+__global__ void __launch_bounds__(WPB * 64) k_vanka_col(int64_t np, const int64_t* __restrict__ off,
+                                                      const int4* __restrict__ dims,
+                                                      const int64_t* __restrict__ foff,
+                                                      const int* __restrict__ dofs, const T* __restrict__ fac,
+                                                      const T* __restrict__ r, T* __restrict__ Y, int64_t yshift) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int64_t p = (int64_t)blockIdx.x * WPB + threadIdx.x / WAVE;
+  if (p >= np) return;  // whole wavefronts leave together
+  const int4 d = dims[p];
+  const int nc[3] = {d.x, d.y, d.z};
+  const int nv = d.x + d.y + d.z, ns = d.w;
+  const int64_t o = off[p];
+  const T* A = fac + foff[p];
+  // b: rows lane and lane + 64 of every component, and the seeds (lane s)
+  T b0[3], b1[3];
+  {
+    int cs = 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int i0 = lane, i1 = lane + WAVE;
+      const int k0 = i0 < nc[c] ? dofs[o + cs + i0] : -1;
+      const int k1 = i1 < nc[c] ? dofs[o + cs + i1] : -1;
+      b0[c] = k0 >= 0 ? r[k0] : (T)0;
+      b1[c] = k1 >= 0 ? r[k1] : (T)0;
+      cs += nc[c];
+    }
+  }
+  const T bseed = lane < ns ? r[dofs[o + nv + lane]] : (T)0;
+  T y0[3], y1[3];
+  int64_t ao = 0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int n = nc[c];
+    T a0 = 0, a1 = 0;  // y of rows lane, lane + 64
+    const T* Ac = A + ao;
+    for (int j = 0; j < n; ++j) {
+      const T* col = Ac + (int64_t)j * (j + 1) / 2;
+      const T e0 = lane <= j ? ldv<NT>(&col[lane]) : (T)0;
+      const T e1 = lane + WAVE <= j ? ldv<NT>(&col[lane + WAVE]) : (T)0;
+      const T bj = j < WAVE ? __shfl(b0[c], j) : __shfl(b1[c], j - WAVE);
+      if (lane < j) a0 += e0 * bj;
+      if (lane + WAVE < j) a1 += e1 * bj;
+      const T sj = wave_sum(e0 * b0[c] + e1 * b1[c]);
+      if (lane == j) a0 += sj;
+      if (lane + WAVE == j) a1 += sj;
+    }
+    y0[c] = a0;
+    y1[c] = a1;
+    ao += (int64_t)n * (n + 1) / 2;
+  }
+  // seeds: t_s = b_p[s] + Uhat[:, s]^T b_u, y_p = S^-1 t
+  const T* U = A + ao;
+  const T* Si = U + (int64_t)nv * ns;
+  T t[MAX_NS], yp[MAX_NS];
+#pragma unroll
+  for (int s = 0; s < MAX_NS; ++s) {
+    t[s] = 0;
+    if (s >= ns) continue;
+    T part = 0;
+    int cs = 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (lane < nc[c]) part += ldv<NT>(&U[(int64_t)s * nv + cs + lane]) * b0[c];
+      if (lane + WAVE < nc[c]) part += ldv<NT>(&U[(int64_t)s * nv + cs + lane + WAVE]) * b1[c];
+      cs += nc[c];
+    }
+    t[s] = wave_sum(part) + __shfl(bseed, s);
+  }
+#pragma unroll
+  for (int s = 0; s < MAX_NS; ++s) {
+    T acc = 0;
+    if (s < ns)
+      for (int q = 0; q < ns; ++q) acc += Si[packed_index(s, q)] * t[q];
+    yp[s] = acc;
+  }
+  // x_u = y_u + Uhat y_p, written to the patch's output slots
+  T* Yp = Y + o - yshift;
+  int cs = 0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if (lane < nc[c]) {
+      T acc = y0[c];
+      for (int s = 0; s < ns; ++s) acc += ldv<NT>(&U[(int64_t)s * nv + cs + lane]) * yp[s];
+      Yp[cs + lane] = acc;
+    }
+    if (lane + WAVE < nc[c]) {
+      T acc = y1[c];
+      for (int s = 0; s < ns; ++s) acc += ldv<NT>(&U[(int64_t)s * nv + cs + lane + WAVE]) * yp[s];
+      Yp[cs + lane + WAVE] = acc;
+    }
+    cs += nc[c];
+  }
+  if (lane < ns) {
+    T v = 0;
+#pragma unroll
+    for (int s = 0; s < MAX_NS; ++s)
+      if (s == lane) v = yp[s];
+    Yp[nv + lane] = v;
+  }
 }
 
 // additive Vanka for a bucket of P patches of one fixed shape: one thread per

@@ -409,6 +409,9 @@ struct DPatches {
   T* Ynr = nullptr;
   bool stream = false;  // non-temporal loads of the factor records (far larger than the caches)
   int nr_chunk = 0;  // right-hand sides per workgroup of the batched patch kernel (LDS bound)
+  bool col_ok = false;   // every generic patch fits the column-streaming kernel (components <= 128 rows, packed)
+  int gen_kernel = 0;    // generic patches: 0 workgroup per patch, 2 wavefront per patch streaming
+                         // columns (chosen at setup)
   bool nr_stage = true;  // the batched kernel stages factor records in LDS
 };
 
@@ -453,6 +456,8 @@ struct CycleBase {
   // Every per-application scratch array of the cycle for r right-hand sides,
   // in a fixed order: f(address of the pointer field, bytes).
   virtual void scratch_arrays(int r, const std::function<void(void**, size_t)>& f) = 0;
+  // per level: patches in thread-per-patch buckets, and the kernel of the others
+  virtual void describe(mas_hier_info& in) const = 0;
 };
 
 // Optional event timing of the cycle's kernels, per kernel kind, with the
@@ -828,7 +833,20 @@ struct Cycle : CycleBase {
       if (timed) tm->end(e0, e1, s, patch_bytes(L, rec * fb.P, (double)(nvb + nsd) * fb.P), TK_TPP);
     }
     const int64_t ng = pt.np - pt.g0;
-    if (ng > 0) {
+    if (ng > 0 && pt.gen_kernel == 2) {
+      if (timed) tm->begin(e0, e1, s);
+      constexpr int WPB = 4;
+      const dim3 grid((unsigned)((ng + WPB - 1) / WPB));
+      if (pt.stream)
+        hipLaunchKernelGGL((k_vanka_col<T, true, WPB>), grid, dim3(WPB * WAVE), 0, s, ng, pt.off + pt.g0,
+                           pt.dims + pt.g0, pt.foff + pt.g0, pt.dofs, pt.fac, rin, pt.Y, pt.yshift);
+      else
+        hipLaunchKernelGGL((k_vanka_col<T, false, WPB>), grid, dim3(WPB * WAVE), 0, s, ng, pt.off + pt.g0,
+                           pt.dims + pt.g0, pt.foff + pt.g0, pt.dofs, pt.fac, rin, pt.Y, pt.yshift);
+      launch_check();
+      if (timed)
+        tm->end(e0, e1, s, patch_bytes(L, (double)pt.nfac_alg - fast_fac, (double)pt.ndofs - fast_slots), TK_GENERIC);
+    } else if (ng > 0) {
       const bool stage = (size_t)(2 * pt.max_m + pt.max_f) * sizeof(T) <= kMaxLds;
       const size_t shm = (size_t)(2 * pt.max_m + (stage ? pt.max_f : 0)) * sizeof(T);
       if (timed) tm->begin(e0, e1, s);
@@ -853,6 +871,40 @@ struct Cycle : CycleBase {
       if (timed)
         tm->end(e0, e1, s, patch_bytes(L, (double)pt.nfac_alg - fast_fac, (double)pt.ndofs - fast_slots), TK_GENERIC);
     }
+  }
+
+  // Kernel for the generic (non-bucket) patches of a level: the workgroup
+  // kernel or, where the level's patches fit it, the column-streaming
+  // wavefront kernel, whichever is faster on this level's patches, timed at
+  // setup on a zero input (3 launches each after a warm-up); without timing
+  // the workgroup kernel (measured faster on the 2D and 3D Taylor-Hood levels).
+  void choose_generic_kernel(Level<T>& L, bool tune, hipStream_t s) {
+    DPatches<T>& pt = L.pt;
+    pt.gen_kernel = 0;
+    if (!tune || pt.np - pt.g0 <= 0 || !pt.col_ok) return;
+    HIPCHECK(hipMemsetAsync(L.r, 0, (size_t)L.n * sizeof(T), s));
+    hipEvent_t e0, e1;
+    HIPCHECK(hipEventCreate(&e0));
+    HIPCHECK(hipEventCreate(&e1));
+    auto time_it = [&](int kind) {
+      pt.gen_kernel = kind;
+      patch_solve(L, L.r, s);
+      HIPCHECK(hipEventRecord(e0, s));
+      for (int rep = 0; rep < 3; ++rep) patch_solve(L, L.r, s);
+      HIPCHECK(hipEventRecord(e1, s));
+      HIPCHECK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+      return ms;
+    };
+    const float t_wg = time_it(0), t_col = time_it(2);
+    pt.gen_kernel = t_col < t_wg ? 2 : 0;
+    if (std::getenv("MAS_TRACE_SETUP"))
+      std::fprintf(stderr, "[mas setup] level of %lld rows, %lld generic patches (max %d DoFs), us per sweep: "
+                   "workgroup %.1f, column %.1f\n", (long long)L.n, (long long)(pt.np - pt.g0), pt.max_m,
+                   1e3 * t_wg / 3, 1e3 * t_col / 3);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
   }
 
   void vanka_sweeps(Level<T>& L, int sweeps, T omega, bool x_zero, hipStream_t s) {
@@ -964,6 +1016,16 @@ struct Cycle : CycleBase {
     if (sv) {
       v(sv_t0, np0 * r);
       for (T** q : {&sv_t1, &sv_z, &sv_cd, &sv_cd2, &sv_cres}) v(*q, np1 * r);
+    }
+  }
+
+  void describe(mas_hier_info& in) const override {
+    for (size_t l = 0; l < lev.size() && l < 16; ++l) {
+      const DPatches<T>& pt = lev[l].pt;
+      int64_t nb = 0;
+      for (const FastBucket& fb : pt.fast) nb += fb.P;
+      in.bucket_patches[l] = nb;
+      in.patch_kernel[l] = pt.np - pt.g0 > 0 ? (pt.gen_kernel == 2 ? 2 : 1) : 0;
     }
   }
 
@@ -1318,8 +1380,13 @@ void build_patches(DevArena& ar, Level<T>& L, const PatchSet& ps, const DCsr<dou
   }
   d.nfac = fcur;
   d.nfac_alg = d.full ? alg : ps.foff.back();
+  d.col_ok = !d.full && !generic.empty();
+  for (int64_t p : generic)
+    for (int c = 0; c < 3; ++c) d.col_ok = d.col_ok && ps.dims[4 * p + c] <= 2 * WAVE;
+
   d.stream = (double)d.nfac * sizeof(T) >= kStreamBytes;
   if (!d.full) d.max_f = ps.max_f;
+
   d.ny = ycur;
   // ---- DoF -> output positions, in patch order (deterministic sums)
   const int64_t n = L.n;
@@ -1546,6 +1613,7 @@ std::unique_ptr<Cycle<T>> build_cycle(mas_handle* h, const std::vector<Csr>& Ks,
   for (size_t l = 0; l + 1 < nl; ++l) {
     Level<T>& L = cyc->lev[l];
     autotune_team<T>(L.K, L.x, L.r, s, tune);
+    if (L.relax && L.pt.np > 0) cyc->choose_generic_kernel(L, tune, s);
     if (L.dl.on) {
       autotune_team<T>(L.dl.A, L.dl.ru, L.dl.vs, s, tune);
       autotune_team<T>(L.dl.S, L.dl.rp, L.dl.q, s, tune);
@@ -1978,6 +2046,7 @@ void upload_impl(mas_handle* h, hipStream_t s) {
   else
     h->cyc = build_cycle<double>(h, pl.Ks, pl.Ps, pl.fields, pl.patches, pl.dlsc, pl.relax, pl.Kb, pl.free0, pl.dir0,
                                  s);
+  h->cyc->describe(h->info);
   h->dir_idx = h->arena.upload<int64_t>(pl.dir0, s);
   h->ndir = (int64_t)pl.dir0.size();
   if (!pl.pw.empty()) h->pw = h->arena.upload<double>(pl.pw, s);
@@ -2024,6 +2093,10 @@ void release_device(mas_handle* h) {
   h->pw = nullptr;
   h->dir_idx = nullptr;
   h->K0full = DCsr<double>{};
+  for (int l = 0; l < 16; ++l) {
+    h->info.bucket_patches[l] = 0;
+    h->info.patch_kernel[l] = 0;
+  }
   h->on_device = false;
 }
 

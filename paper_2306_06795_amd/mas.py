@@ -59,7 +59,7 @@ class mas_hier_info(C.Structure):
     _fields_ = [("n_levels", C.c_int32), ("n", C.c_int64 * 16), ("nnz", C.c_int64 * 16),
                 ("n_vel", C.c_int64 * 16), ("n_patches", C.c_int64 * 16), ("patch_dofs", C.c_int64 * 16),
                 ("factor_entries", C.c_int64 * 16), ("p_nnz", C.c_int64 * 16), ("coarse_n", C.c_int64),
-                ("device_bytes", C.c_int64)]
+                ("device_bytes", C.c_int64), ("bucket_patches", C.c_int64 * 16), ("patch_kernel", C.c_int32 * 16)]
 
 
 def _load():
@@ -261,7 +261,8 @@ class Handle:
         return dict(n_levels=L, n=list(hi.n[:L]), nnz=list(hi.nnz[:L]), n_vel=list(hi.n_vel[:L]),
                     n_patches=list(hi.n_patches[:L]), patch_dofs=list(hi.patch_dofs[:L]),
                     factor_entries=list(hi.factor_entries[:L]), p_nnz=list(hi.p_nnz[:L]), coarse_n=hi.coarse_n,
-                    device_bytes=hi.device_bytes)
+                    device_bytes=hi.device_bytes, bucket_patches=list(hi.bucket_patches[:L]),
+                    patch_kernel=list(hi.patch_kernel[:L]))
 
     def scale_rows(self, x, s_u, s_p, nrhs: int = 1, dirichlet_inverse: bool = False, stream=None):
         su = (C.c_double * nrhs)(*[float(v) for v in s_u])
