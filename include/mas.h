@@ -205,9 +205,10 @@ void mas_default_params(int32_t dim, int32_t disc, int32_t relax, mas_params* ou
  * aggregation), the Vanka patches of every relaxed level with their block
  * factorisation computed on the GPU in FP64 (eqs. (3.6)-(3.8)), or the DLSC
  * operators, and the dense coarsest-level inverse.
- * Errors: MAS_EINVAL (also when a field's coarsening stops above
- * max(max_coarse, 4096) unknowns, which the dense coarsest solve would not
- * take), MAS_ESINGULAR_PATCH, MAS_ENOMEM, MAS_EHIP. */
+ * Errors: MAS_EINVAL (also when the coarsest level, every field cut at the
+ * common depth of Algorithm 1 and the border included, exceeds
+ * max(max_coarse, 8192) rows, which the dense coarsest solve would not take),
+ * MAS_ESINGULAR_PATCH, MAS_ENOMEM, MAS_EHIP. */
 int mas_setup(const mas_problem* prob, const mas_params* par, void* stream, mas_handle** out);
 
 /* Host-only analysis: the hierarchy (Algorithm 1) and the patches, without
@@ -287,6 +288,26 @@ int mas_solve(mas_handle* h, const double* b, double* x, int32_t nrhs, double rt
  * tolerance). */
 int mas_solve_rtols(mas_handle* h, const double* b, double* x, int32_t nrhs, const double* rtol,
                     int32_t max_it, mas_solve_info* info, void* stream);
+
+/* One scheduling step of continuous batching over nrhs right-hand-side slots
+ * (a serving layer admits and retires requests between steps).  b, x: device
+ * FP64 n0 x nrhs as in mas_solve; rtol, fresh: host arrays of nrhs.  Column k
+ * starts from x_k = 0 when fresh[k] != 0 (a request just admitted to slot k),
+ * else continues from the x_k it holds; every column not yet at
+ * ||b_k - K0 x_k|| <= rtol[k] ||b_k|| then runs at most `cycles` restart cycles
+ * of FGMRES(restart) (Section 4), so the iterates of a column are those
+ * mas_solve computes for it alone, up to rounding, whatever the other slots
+ * do.  A column with b_k = 0 is an idle slot (fresh: x_k = 0).  info (host,
+ * nrhs, required): iterations run in this call, converged flag, true relative
+ * residual at the end of the call.  Columns that converge in this call get the
+ * zero-mean pressure of mas_solve; the others are left as iterates.  Returns
+ * MAS_OK when every column has converged, MAS_NOT_CONVERGED otherwise (the
+ * caller steps again), or an error (MAS_EINVAL for NULL arguments, cycles < 1,
+ * a negative tolerance, nrhs outside [1, nrhs_max] or several right-hand
+ * sides with the FGMRES-wrapped relaxation; MAS_ENAN).  Synchronises the
+ * stream. */
+int mas_solve_step(mas_handle* h, const double* b, double* x, int32_t nrhs, const double* rtol,
+                   const int32_t* fresh, int32_t cycles, mas_solve_info* info, void* stream);
 
 /* Sizes of the built hierarchy (host structure owned by the caller), and the
  * device bytes the handle holds.  Errors: MAS_EINVAL for NULL arguments. */

@@ -79,7 +79,7 @@ void sa_fields(const std::vector<Csr>& A, const SocParams& soc, int max_coarse, 
 // Largest matrix the dense coarsest solve takes (rows, border included) unless
 // max_coarse is larger: a coarsening that stalls above it is refused
 // (std::runtime_error naming `what`) instead of inverting a matrix of that size.
-constexpr int64_t kMaxDenseCoarse = 4096;
+constexpr int64_t kMaxDenseCoarse = 8192;
 void check_dense_coarse(int64_t n, int max_coarse, const char* what);
 
 // ---- Vanka patches of one level (velocity rows sorted, then the seeds)

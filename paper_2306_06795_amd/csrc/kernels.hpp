@@ -707,6 +707,12 @@ __global__ void k_reduce_final_nr(int nb, int nr, const double* __restrict__ par
 }
 
 // v[:, k] = r[:, k] / beta[k] (0 when beta[k] == 0)
+// v[:, k] *= c[k] (n x nr, right-hand side fastest)
+__global__ void k_scale_cols_inplace(int64_t n, int nr, const double* __restrict__ c, double* __restrict__ v) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n * nr) v[t] *= c[t % nr];
+}
+
 __global__ void k_scale_cols(int64_t n, int nr, const double* __restrict__ beta, const double* __restrict__ r,
                              double* __restrict__ v) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <climits>
 #include <cstring>
 #include <functional>
 #include <mutex>
@@ -2279,8 +2280,13 @@ int fgmres(mas_handle* h, const double* b, double* x, double rtol, int max_it, m
 // advanced in lockstep so every cycle application is batched.  Each column has
 // its own Givens rotations and tolerance; a column stops rotating once its
 // estimate reaches its tolerance, and its iterate uses its own Krylov size.
+// Restarted FGMRES for nr columns (Section 4).  fresh == nullptr: every column
+// starts from x = 0 and runs to convergence or max_it.  Otherwise column k
+// starts from x = 0 when fresh[k], else continues from the x it holds, and the
+// call ends after max_cycles restart cycles (a scheduling step of continuous
+// batching); info[k].iters then counts the iterations run in this call.
 int fgmres_nr(mas_handle* h, const double* b, double* x, int nr, const double* rtol, int max_it,
-              mas_solve_info* info, hipStream_t s) {
+              mas_solve_info* info, hipStream_t s, const int32_t* fresh = nullptr, int max_cycles = INT_MAX) {
   const int64_t n = h->n0;
   const int m = std::max(1, h->par.restart);
   int nrp = 1;
@@ -2298,10 +2304,20 @@ int fgmres_nr(mas_handle* h, const double* b, double* x, int nr, const double* r
   };
   std::vector<double> bnorm, beta;
   col_norms(b, bnorm);
-  hipLaunchKernelGGL((k_fill<double>), dim3(blocks_for(n * nr, 256)), dim3(256), 0, s, n * nr, x, 0.0);
-  HIPCHECK(hipMemcpyAsync(r, b, n * nr * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (!fresh) {
+    hipLaunchKernelGGL((k_fill<double>), dim3(blocks_for(n * nr, 256)), dim3(256), 0, s, n * nr, x, 0.0);
+    HIPCHECK(hipMemcpyAsync(r, b, n * nr * sizeof(double), hipMemcpyDeviceToDevice, s));
+  } else {
+    // fresh columns start from zero, the others from their x: r = b - K0 x
+    for (int k = 0; k < nr; ++k) h->hhost[k] = fresh[k] ? 0.0 : 1.0;
+    HIPCHECK(hipMemcpyAsync(h->hdev, h->hhost, nr * sizeof(double), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_scale_cols_inplace, dim3(blocks_for(n * nr, 256)), dim3(256), 0, s, n, nr, h->hdev, x);
+    hipLaunchKernelGGL((k_spmm<double, 1>), dim3(blocks_for(n * nr, 256)), dim3(256), 0, s, n, nr, h->K0full.ptr,
+                       h->K0full.ind, h->K0full.val, x, b, r, ChebStep<double>{});
+    launch_check();
+  }
   std::vector<double> target(nr);
-  std::vector<int> done(nr, 0), iters(nr, 0);
+  std::vector<int> done(nr, 0), iters(nr, 0), used(nr, 0);
   std::vector<std::vector<double>> hist(nr);
   for (int k = 0; k < nr; ++k) {
     if (!std::isfinite(bnorm[k])) {
@@ -2313,7 +2329,21 @@ int fgmres_nr(mas_handle* h, const double* b, double* x, int nr, const double* r
     hist[k].push_back(bnorm[k]);
   }
   beta = bnorm;
-  int it = 0;
+  if (fresh) {
+    std::vector<double> r0;
+    col_norms(r, r0);
+    for (int k = 0; k < nr; ++k) {
+      if (!std::isfinite(r0[k])) {
+        if (info) for (int q = 0; q < nr; ++q) info[q] = mas_solve_info{0, 0, NAN, NAN};
+        return MAS_ENAN;
+      }
+      beta[k] = r0[k];
+      done[k] = done[k] || r0[k] <= target[k];
+      hist[k].assign(1, r0[k]);
+    }
+  }
+  const std::vector<int> done_at_start = done;
+  int it = 0, cycles = 0;
   std::vector<double> H((size_t)nr * (m + 1) * m), cs((size_t)nr * m), sn((size_t)nr * m), g((size_t)nr * (m + 1));
   std::vector<int> kcol(nr);
   h->cyc->set_nr(nr);
@@ -2426,23 +2456,27 @@ int fgmres_nr(mas_handle* h, const double* b, double* x, int nr, const double* r
     launch_check();
     col_norms(r, beta);
     bool all = true;
+    ++cycles;
     for (int k = 0; k < nr; ++k) {
       if (!std::isfinite(beta[k])) {
         if (info) for (int q = 0; q < nr; ++q) info[q] = mas_solve_info{it, 0, NAN, NAN};
         h->cyc->set_nr(1);
         return MAS_ENAN;
       }
+      // iterations this column used: a column idle for the rest of a cycle (its
+      // estimate met the tolerance) does not count them
+      if (!done[k]) used[k] += kcol[k];
       if (!done[k] && beta[k] <= target[k]) {
         done[k] = 1;
-        iters[k] = it - kk + kcol[k];
+        iters[k] = used[k];
       }
       all = all && done[k];
     }
-    if (all || it >= max_it) break;
+    if (all || it >= max_it || cycles >= max_cycles) break;
   }
   for (int k = 0; k < nr; ++k)
-    if (!done[k]) iters[k] = it;
-  // zero-mean pressure per column
+    if (!done[k]) iters[k] = used[k];
+  // zero-mean pressure per column (a scheduling step: the columns that converged in it)
   if (h->p_nullspace && h->pw) {
     const int64_t np0 = n - h->nu0;
     hipLaunchKernelGGL(k_wdot_nr, dim3(nb), dim3(256), 0, s, np0, nr, nrp, h->pw, x + h->nu0 * nr, h->partial);
@@ -2450,7 +2484,8 @@ int fgmres_nr(mas_handle* h, const double* b, double* x, int nr, const double* r
     launch_check();
     HIPCHECK(hipMemcpyAsync(h->hhost, h->hdev, nr * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
-    for (int k = 0; k < nr; ++k) h->hhost[k] = -h->hhost[k] / h->pw_sum;
+    for (int k = 0; k < nr; ++k)
+      h->hhost[k] = (fresh && (!done[k] || done_at_start[k])) ? 0.0 : -h->hhost[k] / h->pw_sum;
     HIPCHECK(hipMemcpyAsync(h->hdev, h->hhost, nr * sizeof(double), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_add_cols, dim3(blocks_for(np0 * nr, 256)), dim3(256), 0, s, np0, nr, h->hdev,
                        x + h->nu0 * nr);
@@ -2664,6 +2699,46 @@ int mas_solve(mas_handle* h, const double* b, double* x, int32_t nrhs, double rt
 int mas_solve_rtols(mas_handle* h, const double* b, double* x, int32_t nrhs, const double* rtol, int32_t max_it,
                     mas_solve_info* info, void* stream) {
   return solve_impl(h, b, x, nrhs, rtol, max_it, info, stream);
+}
+
+int mas_solve_step(mas_handle* h, const double* b, double* x, int32_t nrhs, const double* rtol, const int32_t* fresh,
+                   int32_t cycles, mas_solve_info* info, void* stream) {
+  if (!h || !b || !x || !rtol || !fresh || cycles < 1) {
+    g_last_error = "bad argument";
+    return MAS_EINVAL;
+  }
+  if (!h->on_device) {
+    g_last_error = "handle was analysed only; call mas_setup";
+    return MAS_EINVAL;
+  }
+  if (nrhs < 1 || nrhs > std::max(1, h->par.nrhs_max)) {
+    g_last_error = "nrhs must be in [1, nrhs_max]";
+    return MAS_EINVAL;
+  }
+  for (int k = 0; k < nrhs; ++k)
+    if (!(rtol[k] >= 0.0)) {
+      g_last_error = "bad argument";
+      return MAS_EINVAL;
+    }
+  if (h->par.krylov_its > 0 && nrhs > 1) {
+    g_last_error = "the FGMRES-wrapped relaxation takes one right-hand side per call";
+    return MAS_EINVAL;
+  }
+  try {
+    hipStream_t us = (hipStream_t)stream;
+    hipStream_t s = h->gs;
+    HIPCHECK(hipEventRecord(h->ev_in, us));
+    HIPCHECK(hipStreamWaitEvent(s, h->ev_in, 0));
+    const int max_it = cycles * std::max(1, h->par.restart);
+    int rc = fgmres_nr(h, b, x, nrhs, rtol, max_it, info, s, fresh, cycles);
+    HIPCHECK(hipEventRecord(h->ev_out, s));
+    HIPCHECK(hipStreamWaitEvent(us, h->ev_out, 0));
+    if (rc == MAS_ENAN) g_last_error = "residual is not finite";
+    return rc;
+  } catch (const MasError& e) {
+    h->cyc->set_nr(1);
+    return fail(e);
+  }
 }
 
 int mas_get_info(const mas_handle* h, mas_hier_info* out) {

@@ -85,6 +85,8 @@ def _load():
                               P(mas_solve_info), C.c_void_p]
     lib.mas_solve_rtols.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, P(C.c_double), C.c_int32,
                                     P(mas_solve_info), C.c_void_p]
+    lib.mas_solve_step.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, P(C.c_double), P(C.c_int32),
+                                   C.c_int32, P(mas_solve_info), C.c_void_p]
     lib.mas_get_info.argtypes = [C.c_void_p, P(mas_hier_info)]
     lib.mas_export_level.argtypes = [C.c_void_p, C.c_int32, P(C.c_int64), P(C.c_int64), C.c_void_p,
                                      C.c_void_p, C.c_void_p]
@@ -98,7 +100,7 @@ def _load():
     lib.mas_last_error.argtypes = []
     lib.mas_last_error.restype = C.c_char_p
     for name in ("mas_setup", "mas_analyze", "mas_upload", "mas_release", "mas_workspace_size", "mas_upload_ws",
-                 "mas_solve_rtols", "mas_apply_static", "mas_scale_rows", "mas_apply", "mas_solve", "mas_get_info", "mas_export_level", "mas_set_timing",
+                 "mas_solve_rtols", "mas_solve_step", "mas_apply_static", "mas_scale_rows", "mas_apply", "mas_solve", "mas_get_info", "mas_export_level", "mas_set_timing",
                  "mas_get_timing", "mas_destroy"):
         getattr(lib, name).restype = C.c_int
     return lib
@@ -107,7 +109,7 @@ def _load():
 lib = _load()
 
 EXPORTED = ("mas_default_params", "mas_setup", "mas_analyze", "mas_upload", "mas_workspace_size", "mas_upload_ws",
-            "mas_release", "mas_apply", "mas_apply_static", "mas_solve", "mas_solve_rtols",
+            "mas_release", "mas_apply", "mas_apply_static", "mas_solve", "mas_solve_rtols", "mas_solve_step",
             "mas_get_info", "mas_scale_rows", "mas_export_level", "mas_set_timing", "mas_get_timing", "mas_destroy",
             "mas_error_string", "mas_last_error")
 
@@ -253,6 +255,16 @@ class Handle:
         out = [dict(iters=i.iters, converged=bool(i.converged), relres=i.relres, conv_factor=i.conv_factor)
                for i in info]
         return rc, out
+
+    def solve_step(self, b, x, rtol, fresh, cycles: int = 1, nrhs: int = 1, stream=None):
+        """One continuous-batching step (mas_solve_step): rtol and fresh are
+        sequences of nrhs; returns (status, per-column info of this step)."""
+        info = (mas_solve_info * nrhs)()
+        tols = (C.c_double * nrhs)(*[float(v) for v in rtol])
+        fr = (C.c_int32 * nrhs)(*[1 if f else 0 for f in fresh])
+        rc = _check(lib.mas_solve_step(self.h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), nrhs, tols, fr,
+                                       cycles, info, _stream(stream)))
+        return rc, [dict(iters=i.iters, converged=bool(i.converged), relres=i.relres) for i in info]
 
     def info(self) -> dict:
         hi = mas_hier_info()

@@ -9,21 +9,25 @@ and stays resident until the HBM budget needs the room.
 Viscosity: the hierarchy is built for nu = 1.  With
 S = diag(sqrt(nu) I_u, I_p / sqrt(nu)) the free block of the nu operator is
 S K_1 S, so a request is solved as c = S^-1 b (S b on Dirichlet rows),
-K_1 y = c, x = S^-1 y (mas_scale_rows).  Residuals relate by
+K_1 y = c, x = S^-1 y (the scalings applied on the host when a request enters
+and leaves its slot).  Residuals relate by
 ||b - K_nu x|| <= max(sqrt(nu), 1/sqrt(nu)) ||c - K_1 y|| and
 ||c|| <= max(sqrt(nu), 1/sqrt(nu)) ||b||, so solving the scaled system to
 rtol / max(nu, 1/nu) bounds the relative residual of the nu system by rtol.
 
-Scheduling: each worker thread owns a stream.  It takes the mesh whose oldest
-waiting request is the oldest overall (among meshes that are idle and fit the
-budget) and solves all of that mesh's waiting requests, up to ``max_batch``,
-as one batched solve (right-hand sides interleaved in one cycle, each with its
-own tolerance, so a result does not depend on its batch-mates).  Requests
-arriving meanwhile join the next batch of their mesh; batches of different
-meshes run at the same time on their own streams.  Idle hierarchies are
-released least-recently-used to admit a new one (their host analysis stays, so
-re-admission costs one upload and factorisation); a mesh whose hierarchy does
-not fit the budget even alone is refused at submission.
+Scheduling (continuous batching at slot level): each worker thread owns a
+stream.  It takes the mesh whose oldest waiting request is the oldest overall
+(among meshes that are idle and fit the budget) and runs that mesh's slots:
+up to ``max_batch`` right-hand sides advance together, one FGMRES restart
+cycle per step (mas_solve_step), each column with its own tolerance and its
+own iterate, so a result does not depend on its batch-mates.  Between steps,
+every column that has converged is returned at once and its slot is given to
+the next waiting request of the mesh, which starts from zero while the others
+continue; the worker leaves the mesh when its slots and queue are empty.
+Batches of different meshes run at the same time on their own streams.  Idle
+hierarchies are released least-recently-used to admit a new one (their host
+analysis stays, so re-admission costs one upload and factorisation); a mesh
+whose hierarchy does not fit the budget even alone is refused at submission.
 """
 from __future__ import annotations
 
@@ -50,7 +54,8 @@ class Request:
     x: np.ndarray | None = None
     iters: int = 0
     relres: float = float("nan")
-    batch: int = 0
+    batch: int = 0           # most right-hand sides that advanced together with this one
+    joined_running: bool = False  # admitted into a batch whose other slots were already iterating
     error: str | None = None
     done: threading.Event = field(default_factory=threading.Event)
 
@@ -63,6 +68,8 @@ class _Mesh:
     def __init__(self, key, problem, handle, est_bytes):
         self.key = key
         self.n0 = problem.K0.shape[0]
+        self.nvel = int(np.count_nonzero(np.asarray(problem.field0) < problem.dim))
+        self.dir = np.nonzero(np.asarray(problem.dir0))[0]
         self.handle: mas.Handle = handle  # analysed; on the device while resident
         self.est_bytes = est_bytes        # device bytes (estimate until the first upload)
         self.resident = False
@@ -113,6 +120,16 @@ class TorchDevice:
     def download(self, t) -> np.ndarray:
         return t.cpu().numpy()
 
+    def stack_cols(self, cols):
+        """n x k contiguous array (right-hand side fastest) from k vectors."""
+        return self.torch.stack(cols, 1).contiguous()
+
+    def column(self, a, k):
+        return a[:, k].contiguous()
+
+    def zeros(self, n):
+        return self.torch.zeros(n, dtype=self.torch.float64, device="cuda:0")
+
 
 def _analysed_handle(problem, par):
     return mas.Handle(problem, par, analyze_only=True)
@@ -120,14 +137,15 @@ def _analysed_handle(problem, par):
 
 class StokesServer:
     """``device`` (streams, arrays) and ``handle_factory(problem, params)``
-    (an analysed handle with upload/release/info/scale_rows/solve/close) default
-    to torch on cuda:0 and libmas; other implementations serve to test the
+    (an analysed handle with upload/release/info/solve_step/close) default to
+    torch on cuda:0 and libmas; other implementations serve to test the
     scheduling on the host.  ``params``: overrides of the libmas parameters,
     a dict for every mesh or a function of the problem giving one (e.g. a
     different relaxation for 3D meshes)."""
 
     def __init__(self, hbm_budget: int, max_batch: int = 32, workers: int = 4,
-                 precision: int = mas.MAS_FP32, params=None, device=None, handle_factory=None):
+                 precision: int = mas.MAS_FP32, params=None, device=None, handle_factory=None,
+                 max_it: int = 1000, on_step=None):
         self.device = device
         self.handle_factory = handle_factory or _analysed_handle
         self.budget = int(hbm_budget)
@@ -146,6 +164,8 @@ class StokesServer:
         self.batch_sizes: list[int] = []
         self.n_workers = workers
         self.threads: list[threading.Thread] = []
+        self.max_it = int(max_it)
+        self.on_step = on_step  # called as on_step(mesh_key, requests) after every step (tests)
 
     # ------------------------------------------------------------------ API
     def add_mesh(self, key: str, problem, device_bytes: int | None = None) -> int:
@@ -269,30 +289,57 @@ class StokesServer:
                         break
                     self.cv.wait(0.05)
                 m.busy = True
-                batch = [m.queue.popleft() for _ in range(min(self.max_batch, len(m.queue)))]
                 if not m.resident:
                     self.resident += m.est_bytes  # reserved while uploading
                     self.peak_resident = max(self.peak_resident, self.resident)
             try:
                 with dev.on_stream(stream):
-                    self._run_batch(m, batch, dev, stream)
-            except Exception as e:  # the batch fails, the server keeps going
-                for r in batch:
-                    r.error = str(e)
-                    r.t_done = time.perf_counter()
-                    r.done.set()
-            with self.cv:
-                if not m.resident and m.handle.info()["device_bytes"] == 0:
-                    self.resident -= m.est_bytes  # upload failed
-                m.busy = False
-                m.last_used = time.perf_counter()
-                self.cv.notify_all()
+                    self._run_slots(m, dev, stream)
+            finally:
+                with self.cv:
+                    if not m.resident and m.handle.info()["device_bytes"] == 0:
+                        self.resident -= m.est_bytes  # upload failed
+                    m.busy = False
+                    m.last_used = time.perf_counter()
+                    self.cv.notify_all()
 
-    def _run_batch(self, m: _Mesh, batch, dev, stream):
+    def _fail(self, reqs, err):
+        t = time.perf_counter()
+        for r in reqs:
+            r.error = err
+            r.t_done = t
+            r.done.set()
+
+    def _scale_in(self, m: _Mesh, r: Request) -> np.ndarray:
+        """c = S^-1 b on free rows, S b on Dirichlet rows (S = diag(sqrt(nu) I_u, I_p / sqrt(nu)))."""
+        c = np.array(r.b, dtype=np.float64)
+        c[:m.nvel] *= 1.0 / math.sqrt(r.nu)
+        c[m.nvel:] *= math.sqrt(r.nu)
+        c[m.dir] = np.asarray(r.b, dtype=np.float64)[m.dir] * math.sqrt(r.nu)
+        return c
+
+    def _scale_out(self, m: _Mesh, r: Request, y: np.ndarray) -> np.ndarray:
+        """x = S^-1 y."""
+        x = np.array(y, dtype=np.float64)
+        x[:m.nvel] *= 1.0 / math.sqrt(r.nu)
+        x[m.nvel:] *= math.sqrt(r.nu)
+        return x
+
+    def _run_slots(self, m: _Mesh, dev, stream):
+        """Serve mesh m until its slots and queue are empty: admit waiting
+        requests into free slots, advance every slot by one restart cycle,
+        return the converged ones."""
         st = dev.stream_handle(stream)
         h = m.handle
         if not m.resident:
-            h.upload(stream=st)
+            try:
+                h.upload(stream=st)
+            except Exception as e:  # the mesh's waiting requests fail, the server keeps going
+                with self.cv:
+                    waiting = list(m.queue)
+                    m.queue.clear()
+                self._fail(waiting, str(e))
+                return
             nbytes = h.info()["device_bytes"]
             with self.cv:
                 self.resident += nbytes - m.est_bytes
@@ -300,33 +347,68 @@ class StokesServer:
                 m.est_bytes = nbytes  # exact from now on
                 m.resident = True
                 self.uploads += 1
-        t0 = time.perf_counter()
-        nr = len(batch)
-        for r in batch:
-            r.t_start = t0
-            r.batch = nr
-        B = np.stack([np.asarray(r.b, dtype=np.float64) for r in batch], 1)
-        Bd = dev.upload(B)
-        Xd = dev.empty_like(Bd)
-        su = [1.0 / math.sqrt(r.nu) for r in batch]  # S^-1 on velocity rows
-        sp = [math.sqrt(r.nu) for r in batch]        # S^-1 on pressure rows
-        h.scale_rows(Bd, su, sp, nrhs=nr, dirichlet_inverse=True, stream=st)
-        tols = [r.rtol / max(r.nu, 1.0 / r.nu) for r in batch]
-        rc, info = h.solve(Bd, Xd, rtol=tols if nr > 1 else tols[0], nrhs=nr, stream=st)
-        h.scale_rows(Xd, su, sp, nrhs=nr, stream=st)
-        X = dev.download(Xd).reshape(m.n0, nr)
-        t1 = time.perf_counter()
-        with self.cv:
-            self.batches += 1
-            self.batch_sizes.append(nr)
-        for k, r in enumerate(batch):
-            r.x = np.ascontiguousarray(X[:, k])
-            r.iters = info[k]["iters"]
-            r.relres = info[k]["relres"]
-            if not info[k]["converged"]:
-                r.error = "not converged"
-            r.t_done = t1
-            r.done.set()
+        active: list = []  # [request, b column, x column, fresh]
+        Bd = Xd = None     # stacked columns of the current slot set (rebuilt when it changes)
+        while True:
+            with self.cv:
+                new = []
+                # a new batch takes every waiting request of the mesh; a running one
+                # takes more only while no idle mesh holds an older request
+                while (len(active) + len(new) < self.max_batch and m.queue and not self.stop
+                       and (not active or self._may_admit(m))):
+                    new.append(m.queue.popleft())
+            try:
+                t0 = time.perf_counter()
+                running = bool(active)  # slots already iterating when these requests enter
+                for r in new:
+                    r.t_start = t0
+                    r.joined_running = running
+                    active.append([r, dev.upload(self._scale_in(m, r)), dev.zeros(m.n0), True])
+                if not active:
+                    return
+                nr = len(active)
+                if new or Bd is None:
+                    Bd = dev.stack_cols([a[1] for a in active])
+                    Xd = dev.stack_cols([a[2] for a in active])
+                new = []
+                tols = [a[0].rtol / max(a[0].nu, 1.0 / a[0].nu) for a in active]
+                _, info = h.solve_step(Bd, Xd, tols, [a[3] for a in active], cycles=1, nrhs=nr, stream=st)
+                keep = []
+                t1 = time.perf_counter()
+                for k, a in enumerate(active):
+                    r = a[0]
+                    r.iters += info[k]["iters"]
+                    r.batch = max(r.batch, nr)
+                    a[3] = False
+                    if info[k]["converged"] or r.iters >= self.max_it:
+                        r.x = self._scale_out(m, r, dev.download(dev.column(Xd, k)))
+                        r.relres = info[k]["relres"]
+                        if not info[k]["converged"]:
+                            r.error = "not converged"
+                        r.t_done = t1
+                        r.done.set()
+                    else:
+                        keep.append(k)
+                if len(keep) < nr:  # some slots freed: the remaining columns, with their iterates
+                    active = [[active[k][0], active[k][1], dev.column(Xd, k), False] for k in keep]
+                    Bd = None
+            except Exception as e:  # the slots fail, the server keeps going
+                self._fail([a[0] for a in active if not a[0].done.is_set()] + new, str(e))
+                return
+            with self.cv:
+                self.batches += 1
+                self.batch_sizes.append(nr)
+            if self.on_step is not None:
+                self.on_step(m.key, [a[0] for a in active])
+
+    def _may_admit(self, m: _Mesh) -> bool:
+        """Whether no idle mesh holds a request older than m's next one (oldest
+        first across meshes; lock held)."""
+        head = m.queue[0].t_arrival
+        for o in self.meshes.values():
+            if o is not m and o.queue and not o.busy and o.queue[0].t_arrival < head:
+                return False
+        return True
 
 
 def latency_percentiles(reqs, qs=(50, 99)) -> dict:

@@ -290,7 +290,7 @@ def test_coarsest_size_is_checked_where_the_fields_are_cut():
     assert e.value.code == mas.MAS_EINVAL and "coarsest" in str(e.value)
     h = mas.Handle(P, mas.default_params(2, max_coarse=300), analyze_only=True)
     i = h.info()
-    assert i["coarse_n"] <= 4096 and i["n_levels"] >= 3
+    assert i["coarse_n"] <= 8192 and i["n_levels"] >= 3
     h.close()
 
 

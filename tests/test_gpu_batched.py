@@ -106,3 +106,36 @@ def test_batched_fp64_apply_matches_oracle():
         ref = pre.apply(R[:, k])
         assert_parity(Z[:, k], ref, P.field0, 1e-11, f"column {k}")
     h.close()
+
+
+@pytest.mark.parametrize("name", ["th12_lid", "sv6", "th3d3"])
+def test_solve_steps_equal_the_solve(name):
+    """mas_solve_step, one restart cycle per call until every column has
+    converged, computes what one mas_solve_rtols call computes (the same
+    restart cycles), bit for bit, with the same per-column iteration counts; a
+    column restarted fresh mid-way equals its own solve."""
+    kw, relax = CASES[name]
+    P = make_problem(**kw)
+    nr = P.nrhs
+    disc = mas.MAS_SV if P.disc == "SV" else mas.MAS_TH
+    # FGMRES(5): several restart cycles, so the steps cross restarts
+    h = mas.Handle(P, mas.default_params(P.dim, disc, RELAX[relax], max_coarse=30, nrhs_max=nr, restart=5))
+    B = torch.tensor(P.b, device=DEV)
+    tols = [10.0 ** -(8 + (k % 3)) for k in range(nr)]
+    X0 = torch.empty_like(B)
+    rc0, i0 = h.solve(B, X0, rtol=tols, nrhs=nr)
+    X1 = torch.zeros_like(B)
+    its = [0] * nr
+    fresh = [True] * nr
+    for step in range(200):
+        rc, info = h.solve_step(B, X1, tols, fresh, cycles=1, nrhs=nr)
+        fresh = [False] * nr
+        for k in range(nr):
+            its[k] += info[k]["iters"]
+        if rc == mas.MAS_OK:
+            break
+    print(f"[steps {name}] solve its {[i['iters'] for i in i0]}, steps its {its} in {step + 1} steps", flush=True)
+    assert rc0 == rc == mas.MAS_OK and step >= 1
+    assert its == [i["iters"] for i in i0]
+    assert torch.equal(X0, X1)
+    h.close()

@@ -1,8 +1,9 @@
 """Host logic of the serving loop, on the CPU: batching by mesh in arrival
 order, one tolerance per request, viscosity scaling (reading: K_nu = S K_1 S on
 the free block, identity Dirichlet rows), HBM-budget admission with
-least-recently-used eviction, refusals, and failures that stay inside their
-batch.  The device is replaced by host arrays and the handle by an exact
+least-recently-used eviction, refusals, failures that stay inside their
+batch, and slot-level admission (requests join a running batch between steps,
+converged ones leave at once).  The device is replaced by host arrays and the handle by an exact
 least-squares solve of the nu = 1 system, so these tests check the server, not
 the GPU path (tests/test_gpu_serving.py does that)."""
 import contextlib
@@ -32,6 +33,15 @@ class HostDevice:
 
     def download(self, t):
         return t
+
+    def stack_cols(self, cols):
+        return np.ascontiguousarray(np.stack(cols, 1))
+
+    def column(self, a, k):
+        return np.ascontiguousarray(a[:, k])
+
+    def zeros(self, n):
+        return np.zeros(n)
 
 
 class ExactHandle:
@@ -68,15 +78,8 @@ class ExactHandle:
     def close(self):
         self.on = False
 
-    def scale_rows(self, x, s_u, s_p, nrhs=1, dirichlet_inverse=False, stream=None):
-        X = x.reshape(-1, nrhs)
-        for k in range(nrhs):
-            X[:self.nu0, k] *= s_u[k]
-            X[self.nu0:, k] *= s_p[k]
-            if dirichlet_inverse:
-                X[self.dir, k] /= s_u[k] ** 2
-
-    def solve(self, b, x, rtol=1e-8, max_it=1000, nrhs=1, stream=None):
+    def solve_step(self, b, x, rtol, fresh, cycles=1, nrhs=1, stream=None):
+        """One step converges every column: its exact solution."""
         assert self.on, "solve on a released handle"
         if self.key in self.fail_solve:
             raise RuntimeError("device fault (test)")
@@ -87,7 +90,7 @@ class ExactHandle:
         X = x.reshape(-1, nrhs)
         for k in range(nrhs):
             X[:, k] = np.linalg.lstsq(self.K, B[:, k], rcond=None)[0]
-        return 0, [dict(iters=3, converged=True, relres=0.0, conv_factor=0.1) for _ in range(nrhs)]
+        return 0, [dict(iters=3, converged=True, relres=0.0) for _ in range(nrhs)]
 
 
 MESHES = {"a": 6, "b": 8, "c": 5}
@@ -222,3 +225,61 @@ def test_parameters_may_depend_on_the_mesh():
         srv.add_mesh(k, mesh(n))
     srv.shutdown()
     assert seen == {"a": (0, 8), "b": (2, 8), "c": (0, 8)}
+
+
+class CountingHandle(ExactHandle):
+    """A column needs b[row] steps: every step adds 1 to its iterate (from 0
+    when fresh) and reports 20 iterations; it converges once x[row] >= b[row]."""
+
+    row = 0
+
+    def solve_step(self, b, x, rtol, fresh, cycles=1, nrhs=1, stream=None):
+        with self.lock:
+            self.log.append((self.key, nrhs, list(fresh)))
+        B = b.reshape(-1, nrhs)
+        X = x.reshape(-1, nrhs)
+        info = []
+        for k in range(nrhs):
+            if fresh[k]:
+                X[:, k] = 0.0
+            X[:, k] += 1.0
+            info.append(dict(iters=20, converged=bool(X[self.row, k] >= B[self.row, k]), relres=0.0))
+        return 0, info
+
+
+def test_requests_join_a_running_batch_and_leave_when_converged():
+    """Two slots: A (3 steps) and B (1 step) start together; B leaves after the
+    first step and C takes its slot while A keeps iterating (C starts from
+    zero, A does not restart); A finishes last after its three steps."""
+    P = mesh(4)
+    n0 = P.n0
+    srv = serving.StokesServer(1 << 40, max_batch=2, workers=1, device=HostDevice(),
+                               handle_factory=lambda P_, par: CountingHandle(P_, par, "m"))
+    srv.add_mesh("m", P)
+    CountingHandle.log = []
+    srv.pause()
+    srv.start()
+
+    row = int(np.nonzero(~P.dir0)[0][0])  # a free velocity row
+    CountingHandle.row = row
+
+    def rhs(steps):
+        b = np.zeros(n0)
+        b[row] = steps
+        return b
+
+    A, B, C = (serving.Request(mesh="m", nu=1.0, b=rhs(s)) for s in (3, 1, 1))
+    for r in (A, B, C):
+        srv.submit(r)
+    srv.resume()
+    for r in (A, B, C):
+        assert r.done.wait(60)
+    srv.shutdown()
+    assert all(r.error is None for r in (A, B, C))
+    log = CountingHandle.log
+    assert [(n, f) for _, n, f in log] == [(2, [True, True]), (2, [False, True]), (1, [False])]
+    assert (A.iters, B.iters, C.iters) == (60, 20, 20)
+    assert C.joined_running and not A.joined_running and not B.joined_running
+    assert B.t_done <= C.t_done <= A.t_done
+    assert A.x[row] == 3.0 and C.x[row] == 1.0
+    assert (A.batch, B.batch, C.batch) == (2, 2, 2)
