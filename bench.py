@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--theta", type=float, default=None,
                     help="strength-of-connection threshold of Algorithm 1 (default: the library's)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--bucket-min", type=int, default=None,
+                    help="fewest patches of one shape that get a thread-per-patch bucket (default: the library's)")
+    ap.add_argument("--mesh-n", type=int, default=None, help="another mesh size of the chosen workload family")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-companion", action="store_true",
                     help="skip the FP32-cycle solves reported beside an FP64 run")
@@ -342,8 +345,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     t0 = time.perf_counter()
-    prob = make_config(a.config)
+    prob = make_config(a.config) if a.mesh_n is None else make_config(a.config, n=a.mesh_n)
     t_gen = time.perf_counter() - t0
+    if a.mesh_n is not None:
+        a.config = f"{a.config}@n={a.mesh_n}"
     relax = {"vanka": mas.MAS_RELAX_VANKA, "dlsc": mas.MAS_RELAX_DLSC, "vanka-dlsc": mas.MAS_RELAX_VANKA_DLSC}[a.relax]
     prec = mas.MAS_FP64 if a.precision == "fp64" else mas.MAS_FP32
     nrhs = prob.nrhs
@@ -355,9 +360,12 @@ def main():
     method = "HO-AMG" if a.schedule == "ho" else f"DC-{a.schedule}"
     if a.schedule != "all":
         label += f"+{a.schedule}"
-    over = {} if a.theta is None else {"theta": a.theta}
+    over = {} if a.theta is None else {"theta": a.theta, "soc": mas.MAS_SOC_SYMMETRIC}
     if a.theta is not None:  # another hierarchy: no counter figure of the default one applies
         label += f"+theta{a.theta:g}"
+    if a.bucket_min is not None:
+        over["bucket_min"] = a.bucket_min
+        label += f"+bucket{a.bucket_min}"
     mp = mas.default_params(prob.dim, mas.MAS_SV if prob.disc == "SV" else mas.MAS_TH, relax, precision=prec,
                             nrhs_max=nrhs, krylov_its=a.krylov_its, schedule=sched[a.schedule],
                             dlsc_amg=a.dlsc_amg, **over)

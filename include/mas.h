@@ -166,7 +166,8 @@ typedef struct {
   int32_t full_patch_min; /* patch size from which a level without fixed-shape buckets stores its
                              A_c^-1 blocks full instead of packed (512) */
   int32_t bucket_min;     /* fewest patches of one fixed shape that get a thread-per-patch bucket
-                             (64); smaller groups take the generic patch kernel */
+                             (32768: a bucket pays only once its threads fill the GPU); smaller
+                             groups take the generic patch kernels */
   int32_t factor_blocked; /* 1: blocked Gauss-Jordan for patch blocks whose panel fits in LDS;
                              0: single-pivot Gauss-Jordan everywhere */
   int32_t device_galerkin;/* 1: the Galerkin products of Algorithm 1 run on the device (same
@@ -196,6 +197,8 @@ typedef struct {
   int32_t patch_kernel[16];   /* kernel of the other patches of a level, chosen at upload by
                                  timing: 0 none, 1 workgroup per patch, 2 wavefront per patch
                                  streaming the packed columns */
+  int32_t bucket_shapes[16][16]; /* per level, up to 4 bucketed shapes (velocity DoFs per
+                                    component x3, seeds), zero-padded, in launch order */
 } mas_hier_info;
 
 /* Default parameters: Section 4 / Tables 2 and 4 where the paper fixes them. */

@@ -79,6 +79,14 @@ size_t nr_lds_bytes(int64_t max_m, int C, int64_t f) {
 // thread-per-patch kernel: interior 2D Taylor-Hood / P1isoP2 patches, interior
 // Scott-Vogelius element patches and the small P1isoP2/P1 patches of the
 // barycentric mesh.
+// Patch shapes (DoFs per velocity component, seeds) with a thread-per-patch
+// bucket kernel: the interior vertex patches of 2D Taylor-Hood and P1iso
+// levels and the element patches of Scott-Vogelius K0, the dominant shapes of
+// those levels' patch-shape histograms (larger or 3D shapes would not fit one
+// thread's registers).  A level buckets a listed shape it holds at least
+// bucket_min times: with a thread per patch a bucket pays only once it fills
+// the GPU (measured on 2D Taylor-Hood: 64k patches 48.9 vs 40.3 solves/s
+// with / without the bucket, 16k patches 91.9 vs 101.6, 3.7k 167 vs 239).
 #define MAS_FAST_SHAPES(X) X(19, 19, 0, 1) X(6, 6, 0, 3) X(10, 10, 0, 1)
 static bool is_fast_shape(const int32_t* d) {
 #define MAS_IS(A, B, C, D) if (d[0] == A && d[1] == B && d[2] == C && d[3] == D) return true;
@@ -1026,6 +1034,8 @@ struct Cycle : CycleBase {
       int64_t nb = 0;
       for (const FastBucket& fb : pt.fast) nb += fb.P;
       in.bucket_patches[l] = nb;
+      for (int q = 0; q < 4; ++q)
+        for (int c = 0; c < 4; ++c) in.bucket_shapes[l][4 * q + c] = q < (int)pt.fast.size() ? pt.fast[q].shape[c] : 0;
       in.patch_kernel[l] = pt.np - pt.g0 > 0 ? (pt.gen_kernel == 2 ? 2 : 1) : 0;
     }
   }
@@ -2097,6 +2107,7 @@ void release_device(mas_handle* h) {
   for (int l = 0; l < 16; ++l) {
     h->info.bucket_patches[l] = 0;
     h->info.patch_kernel[l] = 0;
+    for (int q = 0; q < 16; ++q) h->info.bucket_shapes[l][q] = 0;
   }
   h->on_device = false;
 }
@@ -2562,7 +2573,7 @@ void mas_default_params(int32_t dim, int32_t disc, int32_t relax, mas_params* ou
   p.autotune = 1;
   p.graphs = 1;
   p.full_patch_min = kFullPatch;
-  p.bucket_min = 64;
+  p.bucket_min = 32768;
   p.factor_blocked = 1;
   p.device_galerkin = 0;
   *out = p;

@@ -59,7 +59,8 @@ class mas_hier_info(C.Structure):
     _fields_ = [("n_levels", C.c_int32), ("n", C.c_int64 * 16), ("nnz", C.c_int64 * 16),
                 ("n_vel", C.c_int64 * 16), ("n_patches", C.c_int64 * 16), ("patch_dofs", C.c_int64 * 16),
                 ("factor_entries", C.c_int64 * 16), ("p_nnz", C.c_int64 * 16), ("coarse_n", C.c_int64),
-                ("device_bytes", C.c_int64), ("bucket_patches", C.c_int64 * 16), ("patch_kernel", C.c_int32 * 16)]
+                ("device_bytes", C.c_int64), ("bucket_patches", C.c_int64 * 16), ("patch_kernel", C.c_int32 * 16),
+                ("bucket_shapes", (C.c_int32 * 16) * 16)]
 
 
 def _load():
@@ -274,7 +275,9 @@ class Handle:
                     n_patches=list(hi.n_patches[:L]), patch_dofs=list(hi.patch_dofs[:L]),
                     factor_entries=list(hi.factor_entries[:L]), p_nnz=list(hi.p_nnz[:L]), coarse_n=hi.coarse_n,
                     device_bytes=hi.device_bytes, bucket_patches=list(hi.bucket_patches[:L]),
-                    patch_kernel=list(hi.patch_kernel[:L]))
+                    patch_kernel=list(hi.patch_kernel[:L]),
+                    bucket_shapes=[[tuple(hi.bucket_shapes[l][4 * q:4 * q + 4]) for q in range(4)
+                                    if hi.bucket_shapes[l][4 * q + 3] > 0] for l in range(L)])
 
     def scale_rows(self, x, s_u, s_p, nrhs: int = 1, dirichlet_inverse: bool = False, stream=None):
         su = (C.c_double * nrhs)(*[float(v) for v in s_u])

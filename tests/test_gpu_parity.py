@@ -241,3 +241,29 @@ def test_wrapped_relaxation_refuses_batches():
         h.apply(B, torch.empty_like(B), nrhs=2)
     assert e.value.code == mas.MAS_EINVAL
     h.close()
+
+
+@pytest.mark.parametrize("name,shapes", [
+    ("th24_lid", {(19, 19, 0, 1)}),
+    ("sv8_lid", {(6, 6, 0, 3)}),
+])
+def test_bucket_shapes_match_oracle(name, shapes):
+    """bucket_min = 1: every patch of a compiled bucket shape goes to the
+    thread-per-patch kernels, the others to the generic ones; the cycle still
+    equals the oracle's, FP64 and FP32."""
+    P, par, mp = build(name)
+    mp.bucket_min = 1
+    pre = dc.DCPreconditioner(P, par)
+    r = np.random.default_rng(23).standard_normal(P.n0)
+    ref = pre.apply(r)
+    for precision, tol in ((mas.MAS_FP64, 1e-11), (mas.MAS_FP32, 1e-5)):
+        mp.precision = precision
+        h = mas.Handle(P, mp)
+        got = set(h.info()["bucket_shapes"][0])
+        print(f"  precision {precision}: level-0 buckets {sorted(got)}", flush=True)
+        assert shapes <= got
+        z = torch.empty(P.n0, dtype=torch.float64, device=DEV)
+        h.apply(torch.tensor(r, device=DEV), z)
+        torch.cuda.synchronize()
+        assert_parity(z.cpu().numpy(), ref, P.field0, tol, f"buckets precision {precision}")
+        h.close()
