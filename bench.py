@@ -461,7 +461,7 @@ def main():
     avg_bytes = k_bytes / k_launches
     achieved = avg_bytes / (avg_launch_ms * 1e-3) / 1e9
     kernel = {"tpp": "k_vanka_tpp (thread-per-patch bucket kernel)",
-              "generic": "k_vanka_apply (wavefront-per-patch kernel)",
+              "generic": "k_vanka_apply / k_vanka_col (workgroup- or wavefront-per-patch kernel, chosen per level)",
               "batched": "k_vanka_apply_nr (batched patch kernel)",
               "sell": "k_sell (sliced-ELL sparse product)",
               "csr": "k_csr (CSR sparse product)",
