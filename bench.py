@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--theta", type=float, default=None,
                     help="strength-of-connection threshold of Algorithm 1 (default: the library's)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--share-blocks", type=int, default=None, choices=[0, 1],
+                    help="0: one A^-1 per velocity component even where the components' blocks are identical")
     ap.add_argument("--bucket-min", type=int, default=None,
                     help="fewest patches of one shape that get a thread-per-patch bucket (default: the library's)")
     ap.add_argument("--mesh-n", type=int, default=None, help="another mesh size of the chosen workload family")
@@ -366,6 +368,9 @@ def main():
     if a.bucket_min is not None:
         over["bucket_min"] = a.bucket_min
         label += f"+bucket{a.bucket_min}"
+    if a.share_blocks is not None:
+        over["share_blocks"] = a.share_blocks
+        label += f"+share{a.share_blocks}"
     mp = mas.default_params(prob.dim, mas.MAS_SV if prob.disc == "SV" else mas.MAS_TH, relax, precision=prec,
                             nrhs_max=nrhs, krylov_its=a.krylov_its, schedule=sched[a.schedule],
                             dlsc_amg=a.dlsc_amg, **over)

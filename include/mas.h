@@ -172,6 +172,10 @@ typedef struct {
                              0: single-pivot Gauss-Jordan everywhere */
   int32_t device_galerkin;/* 1: the Galerkin products of Algorithm 1 run on the device (same
                              values as the host's, bit for bit); 0: on the host */
+  int32_t share_blocks;   /* 1: a level whose patches have identical velocity blocks in every
+                             component (the vector Laplacian with the same boundary conditions on
+                             each component, Section 2; checked bit for bit by the analysis)
+                             stores one A^-1 per patch for all components; 0: one per component */
 } mas_params;
 
 typedef struct {
@@ -188,8 +192,7 @@ typedef struct {
   int64_t n_vel[16];      /* velocity rows per level */
   int64_t n_patches[16];  /* Vanka patches per relaxed level (0 if none) */
   int64_t patch_dofs[16]; /* sum of patch sizes per level */
-  int64_t factor_entries[16]; /* stored factor values per level (packed symmetric blocks; full
-                                 blocks on levels whose patches reach 512 DoFs) */
+  int64_t factor_entries[16]; /* stored factor values per level (layout: patch_layout) */
   int64_t p_nnz[16];      /* entries of P_l (level l -> l-1), 0 for l <= 1 */
   int64_t coarse_n;       /* rows of the dense coarsest solve (incl. border) */
   int64_t device_bytes;   /* device memory held by the handle (0 after mas_analyze) */
@@ -199,6 +202,10 @@ typedef struct {
                                  streaming the packed columns */
   int32_t bucket_shapes[16][16]; /* per level, up to 4 bucketed shapes (velocity DoFs per
                                     component x3, seeds), zero-padded, in launch order */
+  int32_t patch_layout[16];   /* per level, bits of the factor records' A^-1 part: 1 = blocks
+                                 stored full (n x n) instead of packed upper triangles (levels
+                                 of patches of full_patch_min DoFs or more, no buckets);
+                                 2 = one block for every velocity component (share_blocks) */
 } mas_hier_info;
 
 /* Default parameters: Section 4 / Tables 2 and 4 where the paper fixes them. */

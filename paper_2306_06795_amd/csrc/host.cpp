@@ -2,8 +2,10 @@
 #include "host.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
+#include <cstring>
 #include <future>
 #include <numeric>
 #include <stdexcept>
@@ -555,6 +557,62 @@ PatchSet patches_element_seeds(const Csr& K, const std::vector<int8_t>& field, i
   }
   finish_patches(ps, K.nr);
   return ps;
+}
+
+bool identical_component_blocks(const Csr& K, const std::vector<int8_t>& field, int dim, const PatchSet& ps) {
+  if (dim < 2 || ps.np() == 0) return false;
+  std::vector<std::vector<int32_t>> idx(dim);  // DoFs of each component, ascending
+  for (int64_t i = 0; i < K.nr; ++i)
+    if (field[i] < dim) idx[field[i]].push_back((int32_t)i);
+  const size_t m = idx[0].size();
+  for (int c = 1; c < dim; ++c)
+    if (idx[c].size() != m) return false;
+  std::vector<int32_t> rank(K.nr, -1);  // position of a velocity DoF within its component
+  for (int c = 0; c < dim; ++c)
+    for (size_t k = 0; k < m; ++k) rank[idx[c][k]] = (int32_t)k;
+  // row k of the component-c block against row k of the component-0 block:
+  // the same columns (by rank; rows are sorted, ranks keep the order) and the
+  // same bits
+  std::atomic<bool> same{true};
+  parallel_rows((int64_t)m, [&](int64_t lo, int64_t hi) {
+    std::vector<std::pair<int32_t, double>> a, b;
+    auto row = [&](int c, int64_t k, std::vector<std::pair<int32_t, double>>& out) {
+      out.clear();
+      const int32_t r = idx[c][k];
+      for (int64_t e = K.ptr[r]; e < K.ptr[r + 1]; ++e)
+        if (field[K.ind[e]] == c) out.emplace_back(rank[K.ind[e]], K.val[e]);
+    };
+    for (int64_t k = lo; k < hi && same.load(std::memory_order_relaxed); ++k) {
+      row(0, k, a);
+      for (int c = 1; c < dim; ++c) {
+        row(c, k, b);
+        bool eq = a.size() == b.size();
+        for (size_t q = 0; eq && q < a.size(); ++q)
+          eq = a[q].first == b[q].first && std::memcmp(&a[q].second, &b[q].second, sizeof(double)) == 0;
+        if (!eq) {
+          same.store(false, std::memory_order_relaxed);
+          break;
+        }
+      }
+    }
+  });
+  if (!same.load()) return false;
+  // every patch: equal component counts, component c's DoFs at [c n, (c + 1) n)
+  // of its velocity list, each the image of the component-0 DoF at the same place
+  for (int64_t p = 0; p < ps.np(); ++p) {
+    const int32_t* q = &ps.dims[4 * p];
+    const int32_t n = q[0];
+    if (n == 0) return false;
+    for (int c = 0; c < 3; ++c)
+      if (q[c] != (c < dim ? n : 0)) return false;
+    const int32_t* D = &ps.dofs[ps.off[p]];
+    for (int c = 0; c < dim; ++c)
+      for (int32_t i = 0; i < n; ++i) {
+        const int32_t j = D[c * n + i];
+        if (field[j] != c || (c > 0 && j != idx[c][rank[D[i]]])) return false;
+      }
+  }
+  return true;
 }
 
 // ---------------------------------------------------------------------------

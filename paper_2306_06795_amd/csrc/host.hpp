@@ -94,8 +94,18 @@ struct PatchSet {
   int64_t np() const { return (int64_t)off.size() - 1; }
   int32_t max_m = 0;
   int64_t max_f = 0;
+  bool shared = false;  // every patch's velocity blocks are identical across components
 };
 PatchSet patches_single_seed(const Csr& K, const std::vector<int8_t>& field, int dim);
+// True when, in every patch, the velocity block of each component equals the
+// component-0 block value for value (bitwise): the level's component blocks
+// of K are identical under the order-preserving map between the components'
+// DoFs (the vector Laplacian with the same boundary conditions on every
+// component, Section 2), and every patch holds, for each component, the
+// images of its component-0 DoFs.  The patch factors then hold one A^-1 for
+// all components (the block-diagonal structure of Section 3.3.1, with the
+// blocks' equality used as well).
+bool identical_component_blocks(const Csr& K, const std::vector<int8_t>& field, int dim, const PatchSet& ps);
 PatchSet patches_element_seeds(const Csr& K, const std::vector<int8_t>& field, int dim,
                                const std::vector<int32_t>& seeds, int ns);
 

@@ -21,8 +21,31 @@ constexpr int MAX_NS = 4;  // seeds per patch handled by the kernels
 
 // values of one velocity block: packed upper triangle, or the full n x n
 // matrix (levels with very large patches, read with coalesced row sweeps)
-__device__ __forceinline__ int64_t blk_size(int n, int full) {
+__host__ __device__ __forceinline__ int64_t blk_size(int n, int full) {
   return full ? (int64_t)n * n : (int64_t)n * (n + 1) / 2;
+}
+
+// Layout of the A^-1 part of a patch factor record (bits): LAYOUT_FULL, blocks
+// stored n x n (entry (i, j) at j n + i) instead of packed upper triangles
+// (entry (i, j), i <= j, at j (j + 1) / 2 + i); LAYOUT_SHARED, the velocity
+// components' blocks are identical and one block, stored once, serves all of
+// them (records then hold [A^-1 | Uhat | S^-1] instead of
+// [A_0^-1 | A_1^-1 | A_2^-1 | Uhat | S^-1]).
+constexpr int LAYOUT_FULL = 1, LAYOUT_SHARED = 2;
+// values of the A^-1 part of a record with per-component sizes n0, n1, n2
+__host__ __device__ __forceinline__ int64_t vel_entries(int n0, int n1, int n2, int layout) {
+  const int f = layout & LAYOUT_FULL;
+  return (layout & LAYOUT_SHARED) ? blk_size(n0, f) : blk_size(n0, f) + blk_size(n1, f) + blk_size(n2, f);
+}
+// offset of component c's block within the A^-1 part
+__host__ __device__ __forceinline__ int64_t comp_offset(int c, int n0, int n1, int layout) {
+  if ((layout & LAYOUT_SHARED) || c == 0) return 0;
+  const int f = layout & LAYOUT_FULL;
+  return c == 1 ? blk_size(n0, f) : blk_size(n0, f) + blk_size(n1, f);
+}
+// values of a whole record (seeds ns)
+__host__ __device__ __forceinline__ int64_t record_entries(int n0, int n1, int n2, int ns, int layout) {
+  return vel_entries(n0, n1, n2, layout) + (int64_t)(n0 + n1 + n2) * ns + (int64_t)ns * (ns + 1) / 2;
 }
 
 __device__ __forceinline__ int64_t packed_index(int i, int j) {
@@ -350,7 +373,7 @@ __global__ void __launch_bounds__(256) k_vanka_apply_nr(int64_t np, int nr, int 
                                                        const int64_t* __restrict__ fstride,
                                                        const int* __restrict__ dofs, const T* __restrict__ fac,
                                                        const T* __restrict__ r, T* __restrict__ Y, int max_m,
-                                                       int64_t max_f, int full) {
+                                                       int64_t max_f, int layout) {
   extern __shared__ unsigned char smem_raw[];
   T* sb = reinterpret_cast<T*>(smem_raw);   // max_m x C
   T* st = sb + (int64_t)max_m * C;          // MAX_NS x C: Uhat^T b_u + b_p
@@ -364,8 +387,9 @@ __global__ void __launch_bounds__(256) k_vanka_apply_nr(int64_t np, int nr, int 
   const int4 d = dims[p];
   const int n0 = d.x, n1 = d.y, n2 = d.z;
   const int nv = n0 + n1 + n2, ns = d.w, m = nv + ns;
-  const int64_t a1 = blk_size(n0, full), a2 = a1 + blk_size(n1, full);
-  const int64_t uo = a2 + blk_size(n2, full), so = uo + (int64_t)nv * ns;
+  const int full = layout & LAYOUT_FULL;
+  const int64_t a1 = comp_offset(1, n0, n1, layout), a2 = comp_offset(2, n0, n1, layout);
+  const int64_t uo = vel_entries(n0, n1, n2, layout), so = uo + (int64_t)nv * ns;
   const int64_t nf = so + (int64_t)ns * (ns + 1) / 2;
   const int64_t o = off[p], f0 = foff[p], fs = fstride[p];
   for (int j = tid; j < m; j += 256) sd[j] = dofs[o + j];
@@ -794,15 +818,56 @@ __global__ void k_add3(int64_t n, T* __restrict__ x, const T* __restrict__ y, co
 // t = Uhat^T b_u + b_p, y_p = S^-1 t, x_u = y_u + Uhat y_p, written to the
 // patch's output slots.  Every thread of the workgroup calls it (it holds
 // barriers).
+// y_u = A^-1 b_u when one block A (n x n, LAYOUT_SHARED) serves all
+// nco = nv / n velocity components: G = TPB / n thread groups (one when
+// n >= TPB); thread (g, i) sums row i of every component over the columns
+// j = g, g + G, ..., so each block entry is read once for all components; the
+// G partial sums of a row (spart: G x nv values, G nv <= 3 TPB) are added in
+// group order.  Every thread of the workgroup calls it (it holds a barrier).
 template <typename T, int TPB>
-__device__ __forceinline__ void vanka_patch_compute(const T* sb, T* sy, const T* sf, T (*sred)[MAX_NS], int4 d,
-                                                    int64_t o, int64_t ua, int full, T* __restrict__ Y,
+__device__ __forceinline__ void vanka_shared_rows(const T* sb, T* sy, const T* A, T* spart, int n, int nco,
+                                                  int full) {
+  const int tid = threadIdx.x;
+  const int G = n >= TPB ? 1 : TPB / n;
+  const int g = G == 1 ? 0 : tid / n;
+  const int i0 = G == 1 ? tid : tid - g * n;
+  if (g < G) {
+    for (int i = i0; i < n; i += (G == 1 ? TPB : n)) {
+      T acc[3] = {0, 0, 0};
+#pragma unroll 4
+      for (int j = g; j < n; j += G) {
+        const T a = full ? A[(int64_t)j * n + i] : A[packed_index(i, j)];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          if (c < nco) acc[c] += a * sb[c * n + j];
+      }
+      T* out = G == 1 ? sy : spart + (int64_t)g * nco * n;
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        if (c < nco) out[c * n + i] = acc[c];
+    }
+  }
+  if (G > 1) {
+    __syncthreads();
+    for (int t = tid; t < nco * n; t += TPB) {
+      T acc = spart[t];
+      for (int q = 1; q < G; ++q) acc += spart[(int64_t)q * nco * n + t];
+      sy[t] = acc;
+    }
+  }
+}
+
+template <typename T, int TPB>
+__device__ __forceinline__ void vanka_patch_compute(const T* sb, T* sy, const T* sf, T (*sred)[MAX_NS], T* spart,
+                                                    int4 d, int64_t o, int64_t ua, int layout, T* __restrict__ Y,
                                                     int64_t yshift) {
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
   const int nv = d.x + d.y + d.z, ns = d.w;
   const int nc[3] = {d.x, d.y, d.z};
+  const int full = layout & LAYOUT_FULL;
+  if (layout & LAYOUT_SHARED) vanka_shared_rows<T, TPB>(sb, sy, sf, spart, d.x, nv / d.x, full);
   // y_u = A^-1 b_u, one row per thread
-  for (int row = tid; row < nv; row += TPB) {
+  for (int row = tid; row < ((layout & LAYOUT_SHARED) ? 0 : nv); row += TPB) {
     int c = 0, cs = 0;
     int64_t ao = 0;
     while (row >= cs + nc[c]) {
@@ -866,10 +931,11 @@ __global__ void __launch_bounds__(TPB) k_vanka_apply(int64_t np, const int64_t* 
                                                     const int64_t* __restrict__ foff,
                                                     const int* __restrict__ dofs, const T* __restrict__ fac,
                                                     const T* __restrict__ r, T* __restrict__ Y, int max_m,
-                                                    int64_t yshift, int full) {
+                                                    int64_t yshift, int layout) {
   extern __shared__ unsigned char smem_raw[];
   T* sb = reinterpret_cast<T*>(smem_raw);
   T* sy = sb + max_m;
+  T* spart = sy + max_m;  // partial row sums of the shared-block layout (3 TPB values)
   __shared__ T sred[TPB / WAVE][MAX_NS];
   const int64_t p = blockIdx.x;
   if (p >= np) return;
@@ -879,13 +945,13 @@ __global__ void __launch_bounds__(TPB) k_vanka_apply(int64_t np, const int64_t* 
   const int64_t o = off[p];
   // record length from the shape (foff holds per-patch base offsets only)
   const int64_t f0 = foff[p];
-  const int64_t ua = blk_size(d.x, full) + blk_size(d.y, full) + blk_size(d.z, full);
+  const int64_t ua = vel_entries(d.x, d.y, d.z, layout);
   const int64_t nf = ua + (int64_t)nv * ns + (int64_t)ns * (ns + 1) / 2;
   // Staged records: the first UL * TPB values are requested before the
   // DoF-list -> vector gather, so that the gather's two dependent round trips
   // overlap the record's loads (UL independent loads in flight per thread).
   constexpr int UL = 32;
-  T* st = sy + max_m;
+  T* st = spart + ((layout & LAYOUT_SHARED) ? 3 * TPB : 0);
   T v[UL];
   if (STAGE) {
 #pragma unroll
@@ -934,7 +1000,7 @@ __global__ void __launch_bounds__(TPB) k_vanka_apply(int64_t np, const int64_t* 
     sf = fac + f0;  // record too large for LDS: read it from memory
   }
   __syncthreads();
-  vanka_patch_compute<T, TPB>(sb, sy, sf, sred, d, o, ua, full, Y, yshift);
+  vanka_patch_compute<T, TPB>(sb, sy, sf, sred, spart, d, o, ua, layout, Y, yshift);
 }
 
 // additive Vanka, one wavefront per patch, for patches whose velocity blocks
@@ -1055,12 +1121,15 @@ __global__ void __launch_bounds__(WPB * 64) k_vanka_col(int64_t np, const int64_
 // at similar rates, the accesses in flight at any time cover a few contiguous
 // regions (a per-wavefront blocked layout measured 3x slower).  Uhat and S^-1 are applied first, then the packed A^-1
 // blocks are streamed: x_u = Uhat y_p + A^-1 b_u.
-template <typename T, int N0, int N1, int N2, int NS, bool NT = false>
+// SH: LAYOUT_SHARED records (one packed block for every component, each of
+// whose N0 rows it serves; N1 and N2 are 0 or N0).
+template <typename T, int N0, int N1, int N2, int NS, bool NT = false, bool SH = false>
 __global__ void __launch_bounds__(256) k_vanka_tpp(int64_t P, int64_t Ppad, const int* __restrict__ dofs,
                                                   const T* __restrict__ fac, const T* __restrict__ r,
                                                   T* __restrict__ Y) {
   constexpr int NV = N0 + N1 + N2, M = NV + NS;
-  constexpr int FA = N0 * (N0 + 1) / 2 + N1 * (N1 + 1) / 2 + N2 * (N2 + 1) / 2;
+  static_assert(!SH || ((N1 == 0 || N1 == N0) && (N2 == 0 || N2 == N0)), "shared blocks need equal components");
+  constexpr int FA = SH ? N0 * (N0 + 1) / 2 : N0 * (N0 + 1) / 2 + N1 * (N1 + 1) / 2 + N2 * (N2 + 1) / 2;
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= P) return;
   const T* f = fac + p;
@@ -1102,9 +1171,24 @@ __global__ void __launch_bounds__(256) k_vanka_tpp(int64_t P, int64_t Ppad, cons
       y[(CS) + i] += a * b[(CS) + j];                      \
       if (i != j) y[(CS) + j] += a * b[(CS) + i];          \
     }
-  MAS_BLOCK(0, N0)
-  MAS_BLOCK(N0, N1)
-  MAS_BLOCK(N0 + N1, N2)
+  if constexpr (SH) {
+    constexpr int NCO = NV / N0;
+#pragma unroll
+    for (int j = 0; j < N0; ++j)
+#pragma unroll
+      for (int i = 0; i <= j; ++i) {
+        const T a = ldv<NT>(&f[(int64_t)(q++) * Ppad]);
+#pragma unroll
+        for (int c = 0; c < NCO; ++c) {
+          y[c * N0 + i] += a * b[c * N0 + j];
+          if (i != j) y[c * N0 + j] += a * b[c * N0 + i];
+        }
+      }
+  } else {
+    MAS_BLOCK(0, N0)
+    MAS_BLOCK(N0, N1)
+    MAS_BLOCK(N0 + N1, N2)
+  }
 #undef MAS_BLOCK
 #pragma unroll
   for (int k = 0; k < NV; ++k) Y[(int64_t)k * Ppad + p] = y[k];
@@ -1181,8 +1265,10 @@ __global__ void __launch_bounds__(TPB) k_vanka_factor(int64_t np, const int64_t*
                                                       const double* __restrict__ kval, TO* __restrict__ fac,
                                                       double* __restrict__ gwork, int64_t work_stride,
                                                       int use_lds, int max_nv, double piv_tol,
-                                                      int64_t* __restrict__ bad, int full) {
+                                                      int64_t* __restrict__ bad, int layout) {
   extern __shared__ double smem_d[];
+  const int full = layout & LAYOUT_FULL;
+  const bool shared = (layout & LAYOUT_SHARED) != 0;
   for (int64_t p = blockIdx.x; p < np; p += gridDim.x) {
     double* W = use_lds == 1 ? smem_d : gwork + (int64_t)blockIdx.x * work_stride;
     double* Bm = W + (work_stride - 2 * (int64_t)max_nv * MAX_NS);  // ns x nv
@@ -1211,9 +1297,12 @@ __global__ void __launch_bounds__(TPB) k_vanka_factor(int64_t np, const int64_t*
     for (int c = 0; c < 3; ++c) {
       const int n = nc[c];
       if (n == 0) continue;
-      for (int64_t k = tid; k < (int64_t)n * n; k += TPB) W[k] = 0.0;
+      // shared blocks: the components after the first reuse the inverse in W
+      // (their blocks equal the first one), only U_c is theirs
+      const bool invert = !shared || c == 0;
+      for (int64_t k = tid; k < (invert ? (int64_t)n * n : 0); k += TPB) W[k] = 0.0;
       __syncthreads();
-      for (int i = tid; i < n; i += TPB) {
+      for (int i = tid; i < (invert ? n : 0); i += TPB) {
         const int row = P[cs + i];
         for (int e = kptr[row]; e < kptr[row + 1]; ++e) {
           int j = find_sorted(P + cs, n, kind[e]);
@@ -1227,7 +1316,7 @@ __global__ void __launch_bounds__(TPB) k_vanka_factor(int64_t np, const int64_t*
       // writes the pivot column.
       double scale = 0.0;
       for (int i = 0; i < n; ++i) scale = fmax(scale, fabs(W[(int64_t)i * n + i]));
-      if (use_lds == 2) {
+      if (use_lds == 2 && invert) {
         // Blocked Gauss-Jordan: with K the next b pivots, W = [A11 A12; A21 A22]
         // becomes [A11^-1, A11^-1 A12; -A21 A11^-1, A22 - A21 A11^-1 A12],
         // the same as b single-pivot steps.
@@ -1293,7 +1382,7 @@ __global__ void __launch_bounds__(TPB) k_vanka_factor(int64_t np, const int64_t*
           __syncthreads();
         }
       }
-      for (int k = 0; k < (use_lds == 2 ? 0 : n); ++k) {
+      for (int k = 0; k < (use_lds == 2 || !invert ? 0 : n); ++k) {
         const double akk = W[(int64_t)k * n + k];
         if (!(akk > piv_tol * scale)) {
           if (tid == 0) atomicMin((unsigned long long*)bad, (unsigned long long)p);
@@ -1317,7 +1406,7 @@ __global__ void __launch_bounds__(TPB) k_vanka_factor(int64_t np, const int64_t*
         __syncthreads();
       }
       // symmetrise the inverse: both halves take the mean of the pair
-      for (int64_t q = tid; q < (int64_t)n * (n + 1) / 2; q += TPB) {
+      for (int64_t q = tid; q < (invert ? (int64_t)n * (n + 1) / 2 : 0); q += TPB) {
         int j = (int)((sqrt(8.0 * (double)q + 1.0) - 1.0) * 0.5);
         while ((int64_t)j * (j + 1) / 2 > q) --j;
         while ((int64_t)(j + 1) * (j + 2) / 2 <= q) ++j;
@@ -1328,7 +1417,7 @@ __global__ void __launch_bounds__(TPB) k_vanka_factor(int64_t np, const int64_t*
         if (!full) out[(ao + q) * fs] = (TO)v;  // packed upper
       }
       __syncthreads();
-      if (full)
+      if (full && invert)
         for (int64_t q = tid; q < (int64_t)n * n; q += TPB) out[(ao + q) * fs] = (TO)W[q];
       // U_c = A_c^-1 B_c^T (column i of the symmetric inverse, read along rows j)
       for (int i = tid; i < n; i += TPB)
@@ -1338,7 +1427,7 @@ __global__ void __launch_bounds__(TPB) k_vanka_factor(int64_t np, const int64_t*
           U[(int64_t)(cs + i) * ns + s] = acc;
         }
       __syncthreads();
-      ao += blk_size(n, full);
+      if (invert) ao += blk_size(n, full);
       cs += n;
     }
     // S = -B U (ns x ns), inverted by one lane with partial pivoting

@@ -402,7 +402,8 @@ struct DPatches {
   int64_t g0 = 0, yshift = 0;
   int max_m = 0;
   int64_t max_f = 0;
-  int full = 0;  // velocity blocks stored as full matrices (levels of very large patches)
+  int layout = 0;  // LAYOUT_FULL: blocks stored n x n (very large patches); LAYOUT_SHARED: one
+                  // A^-1 per patch for all velocity components (identical blocks)
   std::vector<FastBucket> fast;
   // DoF -> outputs map: CSR (inv_ptr, inv_pos) or slot-major ELL (ell, width)
   int* inv_ptr = nullptr;
@@ -806,10 +807,10 @@ struct Cycle : CycleBase {
       if (timed) tm->begin(e0, e1, s);
       if (pt.nr_stage)
         hipLaunchKernelGGL((k_vanka_apply_nr<T, kNrKT, true>), grid, dim3(256), shm, s, pt.np, nr, C, pt.off, pt.dims,
-                           pt.foff, pt.fstride, pt.dofs, pt.fac, rin, pt.Ynr, pt.max_m, pt.max_f, pt.full);
+                           pt.foff, pt.fstride, pt.dofs, pt.fac, rin, pt.Ynr, pt.max_m, pt.max_f, pt.layout);
       else
         hipLaunchKernelGGL((k_vanka_apply_nr<T, kNrKT, false>), grid, dim3(256), shm, s, pt.np, nr, C, pt.off, pt.dims,
-                           pt.foff, pt.fstride, pt.dofs, pt.fac, rin, pt.Ynr, pt.max_m, pt.max_f, pt.full);
+                           pt.foff, pt.fstride, pt.dofs, pt.fac, rin, pt.Ynr, pt.max_m, pt.max_f, pt.layout);
       launch_check();
       if (timed) tm->end(e0, e1, s, patch_bytes(L, (double)pt.nfac_alg, (double)pt.ndofs), TK_BATCHED);
       return;
@@ -822,22 +823,23 @@ struct Cycle : CycleBase {
       T* y = pt.Y + fb.ybase;
       const int n0 = fb.shape[0], n1 = fb.shape[1], n2 = fb.shape[2], nsd = fb.shape[3];
       const int nvb = n0 + n1 + n2;
-      const double rec = (double)n0 * (n0 + 1) / 2 + (double)n1 * (n1 + 1) / 2 + (double)n2 * (n2 + 1) / 2 +
-                         (double)nvb * nsd + (double)nsd * (nsd + 1) / 2;
+      const double rec = (double)record_entries(n0, n1, n2, nsd, pt.layout);
       fast_fac += rec * fb.P;
       fast_slots += (double)(nvb + nsd) * fb.P;
       if (timed) tm->begin(e0, e1, s);
-#define MAS_TPP(A, B, C, D)                                                                                     \
-  if (fb.shape[0] == A && fb.shape[1] == B && fb.shape[2] == C && fb.shape[3] == D) {                          \
-    if (pt.stream)                                                                                             \
-      hipLaunchKernelGGL((k_vanka_tpp<T, A, B, C, D, true>), dim3(nb), dim3(256), 0, s, fb.P, fb.Ppad, d, f, rin, \
-                         y);                                                                                   \
-    else                                                                                                       \
-      hipLaunchKernelGGL((k_vanka_tpp<T, A, B, C, D, false>), dim3(nb), dim3(256), 0, s, fb.P, fb.Ppad, d, f,   \
-                         rin, y);                                                                              \
+#define MAS_TPP_GO(A, B, C, D, NT, SH) \
+  hipLaunchKernelGGL((k_vanka_tpp<T, A, B, C, D, NT, SH>), dim3(nb), dim3(256), 0, s, fb.P, fb.Ppad, d, f, rin, y)
+#define MAS_TPP(A, B, C, D)                                                            \
+  if (fb.shape[0] == A && fb.shape[1] == B && fb.shape[2] == C && fb.shape[3] == D) { \
+    const bool sh = (pt.layout & LAYOUT_SHARED) != 0;                                   \
+    if (pt.stream && sh) MAS_TPP_GO(A, B, C, D, true, true);                            \
+    else if (pt.stream) MAS_TPP_GO(A, B, C, D, true, false);                            \
+    else if (sh) MAS_TPP_GO(A, B, C, D, false, true);                                   \
+    else MAS_TPP_GO(A, B, C, D, false, false);                                          \
   } else
       MAS_FAST_SHAPES(MAS_TPP) { throw MasError(MAS_EINVAL, "unknown patch bucket shape"); }
 #undef MAS_TPP
+#undef MAS_TPP_GO
       launch_check();
       if (timed) tm->end(e0, e1, s, patch_bytes(L, rec * fb.P, (double)(nvb + nsd) * fb.P), TK_TPP);
     }
@@ -856,23 +858,27 @@ struct Cycle : CycleBase {
       if (timed)
         tm->end(e0, e1, s, patch_bytes(L, (double)pt.nfac_alg - fast_fac, (double)pt.ndofs - fast_slots), TK_GENERIC);
     } else if (ng > 0) {
-      const bool stage = (size_t)(2 * pt.max_m + pt.max_f) * sizeof(T) <= kMaxLds;
-      const size_t shm = (size_t)(2 * pt.max_m + (stage ? pt.max_f : 0)) * sizeof(T);
-      if (timed) tm->begin(e0, e1, s);
       // four wavefronts per patch for large patches (more loads in flight, a row per thread)
       const bool wide = pt.max_m >= kWidePatch;
+      const bool sh = (pt.layout & LAYOUT_SHARED) != 0;
+      // LDS: b and y (max_m each), the shared layout's partial row sums (3 TPB), the staged record
+      const int tb_stage = wide ? 256 : WAVE;
+      const bool stage = (size_t)(2 * pt.max_m + (sh ? 3 * tb_stage : 0) + pt.max_f) * sizeof(T) <= kMaxLds;
+      const int tb = stage ? tb_stage : (pt.max_m >= kFullPatch ? 1024 : tb_stage);
+      const size_t shm = (size_t)(2 * pt.max_m + (sh ? 3 * tb : 0) + (stage ? pt.max_f : 0)) * sizeof(T);
+      if (timed) tm->begin(e0, e1, s);
 #define MAS_GENERIC(ST, TB)                                                                                     \
   hipLaunchKernelGGL((k_vanka_apply<T, ST, TB>), dim3((unsigned)ng), dim3(TB), shm, s, ng, pt.off + pt.g0,     \
-                     pt.dims + pt.g0, pt.foff + pt.g0, pt.dofs, pt.fac, rin, pt.Y, pt.max_m, pt.yshift, pt.full)
+                     pt.dims + pt.g0, pt.foff + pt.g0, pt.dofs, pt.fac, rin, pt.Y, pt.max_m, pt.yshift, pt.layout)
 #define MAS_GENERIC_NT(TB)                                                                                       \
   hipLaunchKernelGGL((k_vanka_apply<T, true, TB, true>), dim3((unsigned)ng), dim3(TB), shm, s, ng, pt.off + pt.g0, \
-                     pt.dims + pt.g0, pt.foff + pt.g0, pt.dofs, pt.fac, rin, pt.Y, pt.max_m, pt.yshift, pt.full)
-      if (stage && wide && pt.stream) MAS_GENERIC_NT(256);
+                     pt.dims + pt.g0, pt.foff + pt.g0, pt.dofs, pt.fac, rin, pt.Y, pt.max_m, pt.yshift, pt.layout)
+      if (stage && tb == 256 && pt.stream) MAS_GENERIC_NT(256);
       else if (stage && pt.stream) MAS_GENERIC_NT(WAVE);
-      else if (stage && wide) MAS_GENERIC(true, 256);
+      else if (stage && tb == 256) MAS_GENERIC(true, 256);
       else if (stage) MAS_GENERIC(true, WAVE);
-      else if (pt.max_m >= kFullPatch) MAS_GENERIC(false, 1024);
-      else if (wide) MAS_GENERIC(false, 256);
+      else if (tb == 1024) MAS_GENERIC(false, 1024);
+      else if (tb == 256) MAS_GENERIC(false, 256);
       else MAS_GENERIC(false, WAVE);
 #undef MAS_GENERIC
 #undef MAS_GENERIC_NT
@@ -1282,6 +1288,30 @@ void dense_inverse(DevArena& ar, double* A, int n, hipStream_t s) {
   if (hflag) throw MasError(MAS_ESINGULAR_PATCH, "coarsest-level operator is singular");
 }
 
+// Patch shapes of a level that get thread-per-patch buckets: listed fast
+// shapes held at least bucket_min times.
+static bool has_buckets(const PatchSet& ps, const mas_params& par) {
+  std::map<std::array<int, 4>, int64_t> cnt;
+  for (int64_t p = 0; p < ps.np(); ++p) {
+    const int32_t* q = &ps.dims[4 * p];
+    if (is_fast_shape(q)) cnt[{q[0], q[1], q[2], q[3]}]++;
+  }
+  for (auto& kv : cnt)
+    if (kv.second >= std::max<int64_t>(1, par.bucket_min)) return true;
+  return false;
+}
+
+// Record layout of a level's patch factors.  Identical component blocks
+// (found by the host analysis) are stored once.  Levels of very large patches
+// without buckets keep full blocks: twice the values of the packed triangle,
+// but every row sweep of the patch kernels reads them with consecutive
+// addresses across threads.
+static int patch_layout(const PatchSet& ps, bool buckets, const mas_params& par) {
+  int layout = ps.shared ? LAYOUT_SHARED : 0;
+  if (!buckets && ps.max_m >= std::max(1, par.full_patch_min)) layout |= LAYOUT_FULL;
+  return layout;
+}
+
 template <typename T>
 void build_patches(DevArena& ar, Level<T>& L, const PatchSet& ps, const DCsr<double>& K64, int level, int nr_max,
                    const mas_params& par, hipStream_t s) {
@@ -1316,6 +1346,8 @@ void build_patches(DevArena& ar, Level<T>& L, const PatchSet& ps, const DCsr<dou
     }
     std::sort(generic.begin(), generic.end());
   }
+  const int layout = patch_layout(ps, !groups.empty(), par);
+  d.layout = layout;
   std::vector<int64_t> order;
   for (auto& g : groups) order.insert(order.end(), g.begin(), g.end());
   const int64_t g0 = (int64_t)order.size();
@@ -1335,7 +1367,7 @@ void build_patches(DevArena& ar, Level<T>& L, const PatchSet& ps, const DCsr<dou
     fb.P = (int64_t)groups[b].size();
     fb.Ppad = (fb.P + 63) / 64 * 64;
     const int M = fb.shape[0] + fb.shape[1] + fb.shape[2] + fb.shape[3];
-    const int64_t F = ps.foff[groups[b][0] + 1] - ps.foff[groups[b][0]];
+    const int64_t F = record_entries(fb.shape[0], fb.shape[1], fb.shape[2], fb.shape[3], layout);
     fb.fbase = fcur;
     fb.ybase = ycur;
     // interleaved across the bucket: element q of patch i at q * Ppad + i
@@ -1360,27 +1392,12 @@ void build_patches(DevArena& ar, Level<T>& L, const PatchSet& ps, const DCsr<dou
   }
   d.g0 = g0;
   d.yshift = (int64_t)dofs.size() - ycur;  // generic outputs follow the fast buckets in Y
-  // Levels of very large patches keep full velocity blocks: twice the values of
-  // the packed triangle, but every row sweep of the patch kernels reads them
-  // with consecutive addresses across threads.
-  const int full_min = std::max(1, par.full_patch_min);
-  d.full = (groups.empty() && ps.max_m >= full_min) ? 1 : 0;
-  int64_t alg = 0;
-  d.max_f = 0;
   for (int64_t p : generic) {
     for (int c = 0; c < 4; ++c) dims[4 * pnew + c] = ps.dims[4 * p + c];
     foff[pnew] = fcur;
     fstr[pnew] = 1;
-    int64_t rec = ps.foff[p + 1] - ps.foff[p];
-    if (d.full) {
-      const int32_t* q = &ps.dims[4 * p];
-      const int64_t nvp = q[0] + q[1] + q[2];
-      rec = (int64_t)q[0] * q[0] + (int64_t)q[1] * q[1] + (int64_t)q[2] * q[2] + nvp * q[3] +
-            (int64_t)q[3] * (q[3] + 1) / 2;
-    }
-    fcur += rec;
-    alg += rec;
-    d.max_f = std::max(d.max_f, rec);
+    const int32_t* q = &ps.dims[4 * p];
+    fcur += record_entries(q[0], q[1], q[2], q[3], layout);
     for (int64_t k = ps.off[p]; k < ps.off[p + 1]; ++k) {
       ypos.push_back(ycur);
       ++ycur;
@@ -1390,13 +1407,21 @@ void build_patches(DevArena& ar, Level<T>& L, const PatchSet& ps, const DCsr<dou
     ++pnew;
   }
   d.nfac = fcur;
-  d.nfac_alg = d.full ? alg : ps.foff.back();
-  d.col_ok = !d.full && !generic.empty();
+  // stored values without the buckets' padding, and the longest record
+  d.nfac_alg = 0;
+  d.max_f = 0;
+  for (int64_t p = 0; p < np; ++p) {
+    const int32_t* q = &ps.dims[4 * p];
+    const int64_t rec = record_entries(q[0], q[1], q[2], q[3], layout);
+    d.nfac_alg += rec;
+    d.max_f = std::max(d.max_f, rec);
+  }
+  // the column-streaming kernel takes packed, per-component blocks of at most 2 x 64 rows
+  d.col_ok = layout == 0 && !generic.empty();
   for (int64_t p : generic)
     for (int c = 0; c < 3; ++c) d.col_ok = d.col_ok && ps.dims[4 * p + c] <= 2 * WAVE;
 
   d.stream = (double)d.nfac * sizeof(T) >= kStreamBytes;
-  if (!d.full) d.max_f = ps.max_f;
 
   d.ny = ycur;
   // ---- DoF -> output positions, in patch order (deterministic sums)
@@ -1490,7 +1515,7 @@ void build_patches(DevArena& ar, Level<T>& L, const PatchSet& ps, const DCsr<dou
   if (use_lds)
     hipLaunchKernelGGL((k_vanka_factor<T, 256>), dim3(grid), dim3(256), lds_bytes, s, np, d.off, d.dims, d.foff,
                        d.fstride, d.dofs, K64.ptr, K64.ind, K64.val, d.fac, gwork, stride, 1, max_nv, 1e-14, bad,
-                       d.full);
+                       d.layout);
   else {
     // blocks in global memory: blocked Gauss-Jordan with LDS panels when they fit
     const size_t panel = (size_t)(kGjBlock * kGjBlock + 2 * kGjBlock * max_nc) * sizeof(double);
@@ -1500,7 +1525,7 @@ void build_patches(DevArena& ar, Level<T>& L, const PatchSet& ps, const DCsr<dou
     const bool blocked = panel <= (size_t)max_lds && par.factor_blocked != 0;
     hipLaunchKernelGGL((k_vanka_factor<T, 1024>), dim3(grid), dim3(1024), blocked ? panel : 0, s, np, d.off, d.dims,
                        d.foff, d.fstride, d.dofs, K64.ptr, K64.ind, K64.val, d.fac, gwork, stride, blocked ? 2 : 0,
-                       max_nv, 1e-14, bad, d.full);
+                       max_nv, 1e-14, bad, d.layout);
   }
   launch_check();
   int64_t hbad = 0;
@@ -1905,6 +1930,7 @@ void analyze_impl(mas_handle* h, const mas_problem* pr, bool dev = false, hipStr
       } else {
         patches[l] = patches_single_seed(Ks[l], fields[l], d);
       }
+      patches[l].shared = h->par.share_blocks != 0 && identical_component_blocks(Ks[l], fields[l], d, patches[l]);
       continue;
     }
     // DLSC (Algorithm 2): blocks of K_l, M_u = diag(P2 mass) on K0, I on the iso levels
@@ -2008,17 +2034,15 @@ void analyze_impl(mas_handle* h, const mas_problem* pr, bool dev = false, hipStr
     if (relax[l] && !patches[l].off.empty()) {
       in.n_patches[l] = patches[l].np();
       in.patch_dofs[l] = (int64_t)patches[l].dofs.size();
-      in.factor_entries[l] = patches[l].foff.back();
-      if (patches[l].max_m >= kFullPatch) {  // stored as full blocks (unless fixed-shape buckets exist)
-        int64_t fe = 0;
-        const PatchSet& ps = patches[l];
-        for (int64_t p = 0; p < ps.np(); ++p) {
-          const int32_t* q = &ps.dims[4 * p];
-          fe += (int64_t)q[0] * q[0] + (int64_t)q[1] * q[1] + (int64_t)q[2] * q[2] +
-                (int64_t)(q[0] + q[1] + q[2]) * q[3] + (int64_t)q[3] * (q[3] + 1) / 2;
-        }
-        in.factor_entries[l] = fe;
+      const PatchSet& ps = patches[l];
+      const int layout = patch_layout(ps, has_buckets(ps, h->par), h->par);
+      int64_t fe = 0;
+      for (int64_t p = 0; p < ps.np(); ++p) {
+        const int32_t* q = &ps.dims[4 * p];
+        fe += record_entries(q[0], q[1], q[2], q[3], layout);
       }
+      in.factor_entries[l] = fe;
+      in.patch_layout[l] = layout;
     }
     in.p_nnz[l] = (l >= 2) ? Ps[l - 1].nnz() : 0;
   }
@@ -2576,6 +2600,7 @@ void mas_default_params(int32_t dim, int32_t disc, int32_t relax, mas_params* ou
   p.bucket_min = 32768;
   p.factor_blocked = 1;
   p.device_galerkin = 0;
+  p.share_blocks = 1;
   *out = p;
 }
 

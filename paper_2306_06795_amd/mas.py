@@ -47,7 +47,7 @@ class mas_params(C.Structure):
                 ("krylov_its", C.c_int32), ("nu_dlsc", C.c_int32), ("dlsc_amg", C.c_int32),
                 ("soc", C.c_int32), ("soc_eps", C.c_double), ("gram_schmidt", C.c_int32), ("autotune", C.c_int32),
                 ("graphs", C.c_int32), ("full_patch_min", C.c_int32), ("bucket_min", C.c_int32),
-                ("factor_blocked", C.c_int32), ("device_galerkin", C.c_int32)]
+                ("factor_blocked", C.c_int32), ("device_galerkin", C.c_int32), ("share_blocks", C.c_int32)]
 
 
 class mas_solve_info(C.Structure):
@@ -60,7 +60,7 @@ class mas_hier_info(C.Structure):
                 ("n_vel", C.c_int64 * 16), ("n_patches", C.c_int64 * 16), ("patch_dofs", C.c_int64 * 16),
                 ("factor_entries", C.c_int64 * 16), ("p_nnz", C.c_int64 * 16), ("coarse_n", C.c_int64),
                 ("device_bytes", C.c_int64), ("bucket_patches", C.c_int64 * 16), ("patch_kernel", C.c_int32 * 16),
-                ("bucket_shapes", (C.c_int32 * 16) * 16)]
+                ("bucket_shapes", (C.c_int32 * 16) * 16), ("patch_layout", C.c_int32 * 16)]
 
 
 def _load():
@@ -275,7 +275,7 @@ class Handle:
                     n_patches=list(hi.n_patches[:L]), patch_dofs=list(hi.patch_dofs[:L]),
                     factor_entries=list(hi.factor_entries[:L]), p_nnz=list(hi.p_nnz[:L]), coarse_n=hi.coarse_n,
                     device_bytes=hi.device_bytes, bucket_patches=list(hi.bucket_patches[:L]),
-                    patch_kernel=list(hi.patch_kernel[:L]),
+                    patch_kernel=list(hi.patch_kernel[:L]), patch_layout=list(hi.patch_layout[:L]),
                     bucket_shapes=[[tuple(hi.bucket_shapes[l][4 * q:4 * q + 4]) for q in range(4)
                                     if hi.bucket_shapes[l][4 * q + 3] > 0] for l in range(L)])
 

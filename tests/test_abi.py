@@ -344,6 +344,56 @@ def test_prebuilt_hierarchy_is_validated():
         assert e.value.code == mas.MAS_EINVAL
 
 
+@pytest.mark.parametrize("kw", [
+    dict(dim=2, n=24, jitter=0.2, seed=2, forcing="gaussian", bc="lid"),
+    dict(dim=3, n=4, forcing="smooth", bc="zero", seed=3),
+    dict(dim=2, n=8, disc="SV", jitter=0.2, seed=4, forcing="gaussian", bc="lid"),
+])
+def test_identical_component_blocks_are_found_on_the_host(kw):
+    """Every patch of these problems has identical velocity blocks in all
+    components (vector Laplacian, the same Dirichlet data on each component):
+    the analysis marks each relaxed level shared and counts one packed block
+    per patch; with share_blocks = 0, or once the y-velocity unknowns are
+    rescaled (blocks differ by a factor 4), one block per component.  Counts
+    from the oracle's patches and the level fields."""
+    import dataclasses
+    import scipy.sparse as sp
+    P = make_problem(**kw)
+    par, mp = _same_params(P, max_coarse=40)
+    pre = dc.DCPreconditioner(P, par)
+    fields = [pre.f0] + [lv.field for lv in pre.levels]
+
+    def expected(shared):
+        out = []
+        for l, R in enumerate(pre.relax):
+            f = fields[l]
+            tot = 0
+            for dofs, ns in zip(R.dofs, R.n_seed):
+                nc = [int(np.sum(f[dofs] == c)) for c in range(P.dim)]
+                nv = sum(nc)
+                blocks = nc[:1] if shared else nc
+                tot += sum(n * (n + 1) // 2 for n in blocks) + nv * ns + ns * (ns + 1) // 2
+            out.append(tot)
+        return out
+
+    for share, want_layout in ((1, 2), (0, 0)):
+        mp.share_blocks = share
+        h = mas.Handle(P, mp, analyze_only=True)
+        info = h.info()
+        n = len(pre.relax)
+        assert info["patch_layout"][:n] == [want_layout] * n
+        assert info["factor_entries"][:n] == expected(share == 1)
+        h.close()
+    d0 = np.where((P.field0 == 1) & ~P.dir0, 2.0, 1.0)
+    d1 = np.where((P.field1 == 1) & ~P.dir1, 2.0, 1.0)
+    Q = dataclasses.replace(P, K0=(sp.diags(d0) @ P.K0 @ sp.diags(d0)).tocsr(),
+                            K1=(sp.diags(d1) @ P.K1 @ sp.diags(d1)).tocsr())
+    mp.share_blocks = 1
+    h = mas.Handle(Q, mp, analyze_only=True)
+    assert not any(v & 2 for v in h.info()["patch_layout"])
+    h.close()
+
+
 def test_workspace_size_is_computed_on_the_host():
     """mas_workspace_size sizes mas_upload_ws from the analysis alone: no device
     is touched (this runs without one), the handle stays analysed-only, the
