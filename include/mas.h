@@ -176,6 +176,13 @@ typedef struct {
                              component (the vector Laplacian with the same boundary conditions on
                              each component, Section 2; checked bit for bit by the analysis)
                              stores one A^-1 per patch for all components; 0: one per component */
+  int32_t patch_kernel;   /* kernel of the patches outside the thread-per-patch buckets: 0 the
+                             fastest on each level, timed at upload (autotune = 1; the workgroup
+                             kernel with autotune = 0); 1 workgroup per patch; 2 wavefront per
+                             patch streaming the packed columns of per-component blocks; 3
+                             wavefront per patch on shared blocks.  A level the requested kernel
+                             does not take (2: shared or full blocks, or components above 128
+                             rows; 3: blocks not shared, full, or above 128 rows) uses 1 */
 } mas_params;
 
 typedef struct {
@@ -199,7 +206,8 @@ typedef struct {
   int64_t bucket_patches[16]; /* patches per level solved by the thread-per-patch bucket kernels */
   int32_t patch_kernel[16];   /* kernel of the other patches of a level, chosen at upload by
                                  timing: 0 none, 1 workgroup per patch, 2 wavefront per patch
-                                 streaming the packed columns */
+                                 streaming the packed columns of per-component blocks, 3
+                                 wavefront per patch streaming the columns of a shared block */
   int32_t bucket_shapes[16][16]; /* per level, up to 4 bucketed shapes (velocity DoFs per
                                     component x3, seeds), zero-padded, in launch order */
   int32_t patch_layout[16];   /* per level, bits of the factor records' A^-1 part: 1 = blocks

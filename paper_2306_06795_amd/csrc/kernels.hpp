@@ -821,51 +821,86 @@ __global__ void k_add3(int64_t n, T* __restrict__ x, const T* __restrict__ y, co
 // y_u = A^-1 b_u when one block A (n x n, LAYOUT_SHARED) serves all
 // nco = nv / n velocity components: G = TPB / n thread groups (one when
 // n >= TPB); thread (g, i) sums row i of every component over the columns
-// j = g, g + G, ..., so each block entry is read once for all components; the
-// G partial sums of a row (spart: G x nv values, G nv <= 3 TPB) are added in
-// group order.  Every thread of the workgroup calls it (it holds a barrier).
+// j = g, g + G, ..., so each block entry is read once for all components.
+// After a barrier, groups 1..G-1 leave their sums in part ((G - 1) nco n
+// values, which may be the LDS copy of A itself, no longer read) and group 0
+// adds them in group order.  Every thread of the workgroup calls it (it holds
+// barriers).
+// the sums of row i of every component over the columns j = g, g + G, ...:
+// component count and storage are template arguments, so the unrolled loop
+// holds no branch and its loads are issued together
+template <typename T, int NCO, bool FULL>
+__device__ __forceinline__ void shared_row_sums(const T* sb, const T* A, int n, int i, int g, int G,
+                                                T (&acc)[3]) {
+#pragma unroll 8
+  for (int j = g; j < n; j += G) {
+    const T a = FULL ? A[(int64_t)j * n + i] : A[packed_index(i, j)];
+#pragma unroll
+    for (int c = 0; c < NCO; ++c) acc[c] += a * sb[c * n + j];
+  }
+}
+
+// y_u = A^-1 b_u when one block A (n x n, LAYOUT_SHARED) serves all
+// nco = nv / n velocity components: G = TPB / n thread groups (one when
+// n >= TPB); thread (g, i) sums row i of every component over the columns
+// j = g, g + G, ..., so each block entry is read once for all components.
+// After a barrier, groups 1..G-1 leave their sums in part ((G - 1) nco n
+// values, which may be the LDS copy of A itself, no longer read) and group 0
+// adds them in group order.  Every thread of the workgroup calls it (it holds
+// barriers).
 template <typename T, int TPB>
-__device__ __forceinline__ void vanka_shared_rows(const T* sb, T* sy, const T* A, T* spart, int n, int nco,
+__device__ __forceinline__ void vanka_shared_rows(const T* sb, T* sy, const T* A, T* part, int n, int nco,
                                                   int full) {
   const int tid = threadIdx.x;
   const int G = n >= TPB ? 1 : TPB / n;
   const int g = G == 1 ? 0 : tid / n;
   const int i0 = G == 1 ? tid : tid - g * n;
-  if (g < G) {
-    for (int i = i0; i < n; i += (G == 1 ? TPB : n)) {
-      T acc[3] = {0, 0, 0};
-#pragma unroll 4
-      for (int j = g; j < n; j += G) {
-        const T a = full ? A[(int64_t)j * n + i] : A[packed_index(i, j)];
+  T acc[3] = {0, 0, 0};
+  for (int i = i0; g < G && i < n; i += (G == 1 ? TPB : n)) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-          if (c < nco) acc[c] += a * sb[c * n + j];
-      }
-      T* out = G == 1 ? sy : spart + (int64_t)g * nco * n;
+    for (int c = 0; c < 3; ++c) acc[c] = 0;
+    if (nco == 3 && full) shared_row_sums<T, 3, true>(sb, A, n, i, g, G, acc);
+    else if (nco == 3) shared_row_sums<T, 3, false>(sb, A, n, i, g, G, acc);
+    else if (full) shared_row_sums<T, 2, true>(sb, A, n, i, g, G, acc);
+    else shared_row_sums<T, 2, false>(sb, A, n, i, g, G, acc);
+    if (G == 1)
 #pragma unroll
       for (int c = 0; c < 3; ++c)
-        if (c < nco) out[c * n + i] = acc[c];
-    }
+        if (c < nco) sy[c * n + i] = acc[c];
   }
   if (G > 1) {
+    __syncthreads();  // every read of A done: part may overwrite it
+    if (g >= 1 && g < G)
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        if (c < nco) part[(int64_t)(g - 1) * nco * n + c * n + i0] = acc[c];
     __syncthreads();
-    for (int t = tid; t < nco * n; t += TPB) {
-      T acc = spart[t];
-      for (int q = 1; q < G; ++q) acc += spart[(int64_t)q * nco * n + t];
-      sy[t] = acc;
-    }
+    if (g == 0)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (c >= nco) continue;
+        T v = acc[c];
+        for (int q = 1; q < G; ++q) v += part[(int64_t)(q - 1) * nco * n + c * n + i0];
+        sy[c * n + i0] = v;
+      }
   }
 }
 
 template <typename T, int TPB>
 __device__ __forceinline__ void vanka_patch_compute(const T* sb, T* sy, const T* sf, T (*sred)[MAX_NS], T* spart,
                                                     int4 d, int64_t o, int64_t ua, int layout, T* __restrict__ Y,
-                                                    int64_t yshift) {
+                                                    int64_t yshift, bool stage_rec) {
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
   const int nv = d.x + d.y + d.z, ns = d.w;
   const int nc[3] = {d.x, d.y, d.z};
   const int full = layout & LAYOUT_FULL;
-  if (layout & LAYOUT_SHARED) vanka_shared_rows<T, TPB>(sb, sy, sf, spart, d.x, nv / d.x, full);
+  if (layout & LAYOUT_SHARED) {
+    // the partial sums go to the staged copy of A when they fit there (the
+    // host then allocates no separate area)
+    const int n = d.x, G = n >= TPB ? 1 : TPB / n;
+    const bool in_rec = stage_rec && (int64_t)(G - 1) * nv <= blk_size(n, full);
+    vanka_shared_rows<T, TPB>(sb, sy, sf, in_rec ? const_cast<T*>(sf) : spart, n, nv / n, full);
+  }
   // y_u = A^-1 b_u, one row per thread
   for (int row = tid; row < ((layout & LAYOUT_SHARED) ? 0 : nv); row += TPB) {
     int c = 0, cs = 0;
@@ -925,17 +960,17 @@ __device__ __forceinline__ void vanka_patch_compute(const T* sb, T* sy, const T*
 // x_i = K_i^-1 V_i r into Y at the patch's offset.  Large patches take four
 // wavefronts: four times the loads in flight while the record is staged and
 // one velocity row per thread afterwards.
-template <typename T, bool STAGE, int TPB, bool NT = false>
+template <typename T, bool STAGE, int TPB, bool NT = false, int UL = 32>
 __global__ void __launch_bounds__(TPB) k_vanka_apply(int64_t np, const int64_t* __restrict__ off,
                                                     const int4* __restrict__ dims,
                                                     const int64_t* __restrict__ foff,
                                                     const int* __restrict__ dofs, const T* __restrict__ fac,
                                                     const T* __restrict__ r, T* __restrict__ Y, int max_m,
-                                                    int64_t yshift, int layout) {
+                                                    int64_t yshift, int layout, int spart_len) {
   extern __shared__ unsigned char smem_raw[];
   T* sb = reinterpret_cast<T*>(smem_raw);
   T* sy = sb + max_m;
-  T* spart = sy + max_m;  // partial row sums of the shared-block layout (3 TPB values)
+  T* spart = sy + max_m;  // partial row sums of the shared-block layout (spart_len values: 0 or 3 TPB)
   __shared__ T sred[TPB / WAVE][MAX_NS];
   const int64_t p = blockIdx.x;
   if (p >= np) return;
@@ -949,9 +984,9 @@ __global__ void __launch_bounds__(TPB) k_vanka_apply(int64_t np, const int64_t* 
   const int64_t nf = ua + (int64_t)nv * ns + (int64_t)ns * (ns + 1) / 2;
   // Staged records: the first UL * TPB values are requested before the
   // DoF-list -> vector gather, so that the gather's two dependent round trips
-  // overlap the record's loads (UL independent loads in flight per thread).
-  constexpr int UL = 32;
-  T* st = spart + ((layout & LAYOUT_SHARED) ? 3 * TPB : 0);
+  // overlap the record's loads (UL independent loads in flight per thread;
+  // the host picks UL to cover the level's longest record where it can).
+  T* st = spart + spart_len;
   T v[UL];
   if (STAGE) {
 #pragma unroll
@@ -1000,7 +1035,7 @@ __global__ void __launch_bounds__(TPB) k_vanka_apply(int64_t np, const int64_t* 
     sf = fac + f0;  // record too large for LDS: read it from memory
   }
   __syncthreads();
-  vanka_patch_compute<T, TPB>(sb, sy, sf, sred, spart, d, o, ua, layout, Y, yshift);
+  vanka_patch_compute<T, TPB>(sb, sy, sf, sred, spart, d, o, ua, layout, Y, yshift, STAGE);
 }
 
 // additive Vanka, one wavefront per patch, for patches whose velocity blocks
@@ -1104,6 +1139,176 @@ __global__ void __launch_bounds__(WPB * 64) k_vanka_col(int64_t np, const int64_
       Yp[cs + lane + WAVE] = acc;
     }
     cs += nc[c];
+  }
+  if (lane < ns) {
+    T v = 0;
+#pragma unroll
+    for (int s = 0; s < MAX_NS; ++s)
+      if (s == lane) v = yp[s];
+    Yp[nv + lane] = v;
+  }
+}
+
+// Orders a wavefront's LDS writes before its later LDS reads (the waves of a
+// workgroup then work independently, with no workgroup barrier).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Eight sums over the 64 lanes at once: v[0..7] per lane; a butterfly whose
+// first three steps halve the values each lane carries (4 + 2 + 1 exchanges)
+// and whose last three add within groups of 8 lanes (3 exchanges), instead of
+// 8 x 6 exchanges for eight separate reductions.  On return every lane l holds
+// the sum over all lanes of v[l >> 3].
+template <typename T>
+__device__ __forceinline__ T transpose_sum8(const T (&v)[8], int lane) {
+  const bool h5 = lane & 32, h4 = lane & 16, h3 = lane & 8;
+  T a[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {  // a[k]: entry 4 h5 + k, summed over lanes l, l ^ 32
+    const T send = h5 ? v[k] : v[k + 4];
+    a[k] = (h5 ? v[k + 4] : v[k]) + __shfl_xor(send, 32);
+  }
+  T b[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {  // b[k]: entry 4 h5 + 2 h4 + k, over four lanes
+    const T send = h4 ? a[k] : a[k + 2];
+    b[k] = (h4 ? a[k + 2] : a[k]) + __shfl_xor(send, 16);
+  }
+  const T send = h3 ? b[0] : b[1];
+  T c = (h3 ? b[1] : b[0]) + __shfl_xor(send, 8);  // entry 4 h5 + 2 h4 + h3, over eight lanes
+  c += __shfl_xor(c, 4);
+  c += __shfl_xor(c, 2);
+  c += __shfl_xor(c, 1);
+  return c;
+}
+
+// additive Vanka, one wavefront per patch, for records with one packed A^-1
+// block serving every velocity component (LAYOUT_SHARED; NCO components) of
+// at most 64 TT rows.
+// No workgroup barrier and no record staging: lane l owns rows l, l + 64, ...
+// of the block and streams each packed column j (entries i <= j, contiguous)
+// straight from memory; it adds a_ij b_c[j] to its own rows (every component
+// c) and a_ij b_c[i], i < j, to a partial sum of column j, whose lane sums
+// (the transposed half of the symmetric block) are formed eight columns at a
+// time by transpose_sum8.  Then t = Uhat^T b_u + b_p, y_p = S^-1 t and
+// x_u = y_u + Uhat y_p.  WPB patches per workgroup, each wavefront with its
+// own LDS (b and y of its patch, 2 max_m values).
+template <typename T, int TT, int NCO, bool NT, int WPB>
+__global__ void __launch_bounds__(WPB * 64) k_vanka_wave(int64_t np, const int64_t* __restrict__ off,
+                                                       const int4* __restrict__ dims,
+                                                       const int64_t* __restrict__ foff,
+                                                       const int* __restrict__ dofs, const T* __restrict__ fac,
+                                                       const T* __restrict__ r, T* __restrict__ Y, int max_m,
+                                                       int64_t yshift) {
+  extern __shared__ unsigned char smem_raw[];
+  const int w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+  const int64_t p = (int64_t)blockIdx.x * WPB + w;
+  if (p >= np) return;  // whole wavefronts leave together
+  T* sb = reinterpret_cast<T*>(smem_raw) + (int64_t)w * 2 * max_m;  // b of the patch
+  T* sy = sb + max_m;                                                 // column sums, then y_u
+  const int4 d = dims[p];
+  const int n = d.x, nv = d.x + d.y + d.z, ns = d.w, m = nv + ns;  // nv = NCO n
+  const int64_t o = off[p];
+  const T* A = fac + foff[p];
+  const T* U = A + (int64_t)n * (n + 1) / 2;
+  const T* Si = U + (int64_t)nv * ns;
+  // gather b: the index loads first, then the value loads
+  for (int k0 = 0; k0 < m; k0 += 4 * WAVE) {
+    int idx[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + u * WAVE + lane;
+      idx[u] = k < m ? dofs[o + k] : 0;
+    }
+    T g[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) g[u] = k0 + u * WAVE + lane < m ? r[idx[u]] : (T)0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (k0 + u * WAVE + lane < m) sb[k0 + u * WAVE + lane] = g[u];
+  }
+  wave_sync();
+  T acc[TT][NCO], bi[TT][NCO];
+#pragma unroll
+  for (int t = 0; t < TT; ++t)
+#pragma unroll
+    for (int c = 0; c < NCO; ++c) {
+      const int i = WAVE * t + lane;
+      acc[t][c] = 0;
+      bi[t][c] = i < n ? sb[c * n + i] : (T)0;
+    }
+  for (int j0 = 0; j0 < n; j0 += 8) {
+    T q[NCO][8];
+#pragma unroll
+    for (int jj = 0; jj < 8; ++jj) {
+      const int j = j0 + jj;
+      const bool live = j < n;
+      const int64_t cb = (int64_t)j * (j + 1) / 2;
+      T e[TT];
+#pragma unroll
+      for (int t = 0; t < TT; ++t) {
+        const int i = WAVE * t + lane;
+        e[t] = (live && i <= j) ? ldv<NT>(&A[cb + i]) : (T)0;
+      }
+#pragma unroll
+      for (int c = 0; c < NCO; ++c) {
+        const T bj = live ? sb[c * n + j] : (T)0;
+        T qs = 0;
+#pragma unroll
+        for (int t = 0; t < TT; ++t) {
+          acc[t][c] += e[t] * bj;
+          if (WAVE * t + lane < j) qs += e[t] * bi[t][c];
+        }
+        q[c][jj] = qs;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NCO; ++c) {
+      const T sum = transpose_sum8(q[c], lane);
+      const int j = j0 + (lane >> 3);
+      if ((lane & 7) == 0 && j < n) sy[c * n + j] = sum;
+    }
+  }
+  wave_sync();
+#pragma unroll
+  for (int t = 0; t < TT; ++t)
+#pragma unroll
+    for (int c = 0; c < NCO; ++c) {
+      const int i = WAVE * t + lane;
+      if (i < n) sy[c * n + i] += acc[t][c];
+    }
+  wave_sync();
+  // seeds: t = Uhat^T b_u + b_p, y_p = S^-1 t
+  T ts[MAX_NS], yp[MAX_NS];
+#pragma unroll
+  for (int s = 0; s < MAX_NS; ++s) ts[s] = 0;
+  for (int k = lane; k < nv; k += WAVE) {
+    const T bk = sb[k];
+#pragma unroll
+    for (int s = 0; s < MAX_NS; ++s)
+      if (s < ns) ts[s] += U[(int64_t)s * nv + k] * bk;
+  }
+#pragma unroll
+  for (int s = 0; s < MAX_NS; ++s)
+    if (s < ns) ts[s] = wave_sum(ts[s]) + sb[nv + s];
+#pragma unroll
+  for (int s = 0; s < MAX_NS; ++s) {
+    T a = 0;
+#pragma unroll
+    for (int q = 0; q < MAX_NS; ++q)
+      if (s < ns && q < ns) a += Si[packed_index(s, q)] * ts[q];
+    yp[s] = a;
+  }
+  T* Yp = Y + o - yshift;
+  for (int k = lane; k < nv; k += WAVE) {
+    T a = sy[k];
+#pragma unroll
+    for (int s = 0; s < MAX_NS; ++s)
+      if (s < ns) a += U[(int64_t)s * nv + k] * yp[s];
+    Yp[k] = a;
   }
   if (lane < ns) {
     T v = 0;

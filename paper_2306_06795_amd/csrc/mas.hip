@@ -67,6 +67,7 @@ constexpr double kStreamBytes = 64.0 * 1024 * 1024;
 constexpr int kNrKT = 4;                // right-hand sides per thread in the batched patch kernel
 constexpr int kWidePatch = 128;         // patches of this many DoFs or more get a 256-thread workgroup
 constexpr int kFullPatch = 512;         // levels with patches this large store full velocity blocks
+constexpr int kWavePb = 4;              // patches (wavefronts) per workgroup of the shared-block wave kernel
 
 // LDS of the batched patch kernel: m x C block, two MAX_NS x C blocks, the
 // staged record (f values) and the patch DoF list
@@ -421,7 +422,11 @@ struct DPatches {
   int nr_chunk = 0;  // right-hand sides per workgroup of the batched patch kernel (LDS bound)
   bool col_ok = false;   // every generic patch fits the column-streaming kernel (components <= 128 rows, packed)
   int gen_kernel = 0;    // generic patches: 0 workgroup per patch, 2 wavefront per patch streaming
-                         // columns (chosen at setup)
+                         // columns, 3 wavefront per patch on shared blocks (chosen at setup)
+  int wave_tt = 0;       // row tiles of 64 of the shared-block wavefront kernel (0: not usable)
+  int nco = 0;           // velocity components a shared block serves
+  bool parts_fit[2] = {true, true};  // shared blocks: every generic patch's partial row sums fit in
+                                     // its staged copy of A (workgroups of 64 / 256 threads)
   bool nr_stage = true;  // the batched kernel stages factor records in LDS
 };
 
@@ -844,7 +849,26 @@ struct Cycle : CycleBase {
       if (timed) tm->end(e0, e1, s, patch_bytes(L, rec * fb.P, (double)(nvb + nsd) * fb.P), TK_TPP);
     }
     const int64_t ng = pt.np - pt.g0;
-    if (ng > 0 && pt.gen_kernel == 2) {
+    if (ng > 0 && pt.gen_kernel == 3) {
+      if (timed) tm->begin(e0, e1, s);
+      const dim3 grid((unsigned)((ng + kWavePb - 1) / kWavePb));
+      const size_t shm = (size_t)kWavePb * 2 * pt.max_m * sizeof(T);
+#define MAS_WAVE(TT, NC, NT)                                                                                          \
+  hipLaunchKernelGGL((k_vanka_wave<T, TT, NC, NT, kWavePb>), grid, dim3(kWavePb * WAVE), shm, s, ng,                \
+                     pt.off + pt.g0, pt.dims + pt.g0, pt.foff + pt.g0, pt.dofs, pt.fac, rin, pt.Y, pt.max_m, pt.yshift)
+#define MAS_WAVE_NC(TT, NT)            \
+  if (pt.nco == 3) MAS_WAVE(TT, 3, NT); \
+  else MAS_WAVE(TT, 2, NT)
+      if (pt.wave_tt == 1 && pt.stream) { MAS_WAVE_NC(1, true); }
+      else if (pt.wave_tt == 1) { MAS_WAVE_NC(1, false); }
+      else if (pt.stream) { MAS_WAVE_NC(2, true); }
+      else { MAS_WAVE_NC(2, false); }
+#undef MAS_WAVE
+#undef MAS_WAVE_NC
+      launch_check();
+      if (timed)
+        tm->end(e0, e1, s, patch_bytes(L, (double)pt.nfac_alg - fast_fac, (double)pt.ndofs - fast_slots), TK_GENERIC);
+    } else if (ng > 0 && pt.gen_kernel == 2) {
       if (timed) tm->begin(e0, e1, s);
       constexpr int WPB = 4;
       const dim3 grid((unsigned)((ng + WPB - 1) / WPB));
@@ -861,27 +885,34 @@ struct Cycle : CycleBase {
       // four wavefronts per patch for large patches (more loads in flight, a row per thread)
       const bool wide = pt.max_m >= kWidePatch;
       const bool sh = (pt.layout & LAYOUT_SHARED) != 0;
-      // LDS: b and y (max_m each), the shared layout's partial row sums (3 TPB), the staged record
+      // LDS: b and y (max_m each), the shared layout's partial row sums (3 TPB
+      // values, unless every patch's fit in its staged copy of A), the staged record
       const int tb_stage = wide ? 256 : WAVE;
-      const bool stage = (size_t)(2 * pt.max_m + (sh ? 3 * tb_stage : 0) + pt.max_f) * sizeof(T) <= kMaxLds;
+      const int sp_stage = sh && !pt.parts_fit[wide ? 1 : 0] ? 3 * tb_stage : 0;
+      const bool stage = (size_t)(2 * pt.max_m + sp_stage + pt.max_f) * sizeof(T) <= kMaxLds;
       const int tb = stage ? tb_stage : (pt.max_m >= kFullPatch ? 1024 : tb_stage);
-      const size_t shm = (size_t)(2 * pt.max_m + (sh ? 3 * tb : 0) + (stage ? pt.max_f : 0)) * sizeof(T);
+      const int sp = stage ? sp_stage : (sh ? 3 * tb : 0);
+      const size_t shm = (size_t)(2 * pt.max_m + sp + (stage ? pt.max_f : 0)) * sizeof(T);
+      // loads in flight per thread while a record is staged: enough for the
+      // level's longest record where that takes at most 16
+      const int ul = pt.max_f <= 8 * tb ? 8 : pt.max_f <= 16 * tb ? 16 : 32;
       if (timed) tm->begin(e0, e1, s);
-#define MAS_GENERIC(ST, TB)                                                                                     \
-  hipLaunchKernelGGL((k_vanka_apply<T, ST, TB>), dim3((unsigned)ng), dim3(TB), shm, s, ng, pt.off + pt.g0,     \
-                     pt.dims + pt.g0, pt.foff + pt.g0, pt.dofs, pt.fac, rin, pt.Y, pt.max_m, pt.yshift, pt.layout)
-#define MAS_GENERIC_NT(TB)                                                                                       \
-  hipLaunchKernelGGL((k_vanka_apply<T, true, TB, true>), dim3((unsigned)ng), dim3(TB), shm, s, ng, pt.off + pt.g0, \
-                     pt.dims + pt.g0, pt.foff + pt.g0, pt.dofs, pt.fac, rin, pt.Y, pt.max_m, pt.yshift, pt.layout)
-      if (stage && tb == 256 && pt.stream) MAS_GENERIC_NT(256);
-      else if (stage && pt.stream) MAS_GENERIC_NT(WAVE);
-      else if (stage && tb == 256) MAS_GENERIC(true, 256);
-      else if (stage) MAS_GENERIC(true, WAVE);
-      else if (tb == 1024) MAS_GENERIC(false, 1024);
-      else if (tb == 256) MAS_GENERIC(false, 256);
-      else MAS_GENERIC(false, WAVE);
+#define MAS_GENERIC(ST, TB, NT, U)                                                                                \
+  hipLaunchKernelGGL((k_vanka_apply<T, ST, TB, NT, U>), dim3((unsigned)ng), dim3(TB), shm, s, ng, pt.off + pt.g0, \
+                     pt.dims + pt.g0, pt.foff + pt.g0, pt.dofs, pt.fac, rin, pt.Y, pt.max_m, pt.yshift, pt.layout, sp)
+#define MAS_GENERIC_UL(ST, TB, NT)           \
+  if (ul == 8) MAS_GENERIC(ST, TB, NT, 8);   \
+  else if (ul == 16) MAS_GENERIC(ST, TB, NT, 16); \
+  else MAS_GENERIC(ST, TB, NT, 32)
+      if (stage && tb == 256 && pt.stream) { MAS_GENERIC_UL(true, 256, true); }
+      else if (stage && pt.stream) { MAS_GENERIC_UL(true, WAVE, true); }
+      else if (stage && tb == 256) { MAS_GENERIC_UL(true, 256, false); }
+      else if (stage) { MAS_GENERIC_UL(true, WAVE, false); }
+      else if (tb == 1024) MAS_GENERIC(false, 1024, false, 8);
+      else if (tb == 256) MAS_GENERIC(false, 256, false, 8);
+      else MAS_GENERIC(false, WAVE, false, 8);
 #undef MAS_GENERIC
-#undef MAS_GENERIC_NT
+#undef MAS_GENERIC_UL
       launch_check();
       if (timed)
         tm->end(e0, e1, s, patch_bytes(L, (double)pt.nfac_alg - fast_fac, (double)pt.ndofs - fast_slots), TK_GENERIC);
@@ -896,7 +927,13 @@ struct Cycle : CycleBase {
   void choose_generic_kernel(Level<T>& L, bool tune, hipStream_t s) {
     DPatches<T>& pt = L.pt;
     pt.gen_kernel = 0;
-    if (!tune || pt.np - pt.g0 <= 0 || !pt.col_ok) return;
+    const int want = par.patch_kernel;
+    if (want == 2 || want == 3) {  // requested: taken where the level allows it
+      if (want == 2 && pt.col_ok) pt.gen_kernel = 2;
+      if (want == 3 && pt.wave_tt > 0) pt.gen_kernel = 3;
+      return;
+    }
+    if (want == 1 || !tune || pt.np - pt.g0 <= 0 || (!pt.col_ok && pt.wave_tt == 0)) return;
     HIPCHECK(hipMemsetAsync(L.r, 0, (size_t)L.n * sizeof(T), s));
     hipEvent_t e0, e1;
     HIPCHECK(hipEventCreate(&e0));
@@ -912,12 +949,19 @@ struct Cycle : CycleBase {
       HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
       return ms;
     };
-    const float t_wg = time_it(0), t_col = time_it(2);
-    pt.gen_kernel = t_col < t_wg ? 2 : 0;
+    // candidates: 0 workgroup per patch, 2 column-streaming wavefront (packed
+    // per-component blocks), 3 wavefront per patch on shared blocks
+    const float t_wg = time_it(0);
+    float best = t_wg, t_col = -1.f, t_wave = -1.f;
+    int pick = 0;
+    if (pt.col_ok && (t_col = time_it(2)) < best) best = t_col, pick = 2;
+    if (pt.wave_tt > 0 && (t_wave = time_it(3)) < best) best = t_wave, pick = 3;
+    pt.gen_kernel = pick;
     if (std::getenv("MAS_TRACE_SETUP"))
       std::fprintf(stderr, "[mas setup] level of %lld rows, %lld generic patches (max %d DoFs), us per sweep: "
-                   "workgroup %.1f, column %.1f\n", (long long)L.n, (long long)(pt.np - pt.g0), pt.max_m,
-                   1e3 * t_wg / 3, 1e3 * t_col / 3);
+                   "workgroup %.1f, column %.1f, wave %.1f -> kernel %d\n", (long long)L.n,
+                   (long long)(pt.np - pt.g0), pt.max_m, 1e3 * t_wg / 3,
+                   t_col < 0 ? -1.0 : 1e3 * t_col / 3, t_wave < 0 ? -1.0 : 1e3 * t_wave / 3, pick);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
   }
@@ -1042,7 +1086,7 @@ struct Cycle : CycleBase {
       in.bucket_patches[l] = nb;
       for (int q = 0; q < 4; ++q)
         for (int c = 0; c < 4; ++c) in.bucket_shapes[l][4 * q + c] = q < (int)pt.fast.size() ? pt.fast[q].shape[c] : 0;
-      in.patch_kernel[l] = pt.np - pt.g0 > 0 ? (pt.gen_kernel == 2 ? 2 : 1) : 0;
+      in.patch_kernel[l] = pt.np - pt.g0 > 0 ? (pt.gen_kernel == 0 ? 1 : pt.gen_kernel) : 0;
     }
   }
 
@@ -1420,6 +1464,30 @@ void build_patches(DevArena& ar, Level<T>& L, const PatchSet& ps, const DCsr<dou
   d.col_ok = layout == 0 && !generic.empty();
   for (int64_t p : generic)
     for (int c = 0; c < 3; ++c) d.col_ok = d.col_ok && ps.dims[4 * p + c] <= 2 * WAVE;
+  // shared blocks, workgroup kernel: where the partial row sums of a patch's
+  // thread groups (G = TPB / n groups) fit in the LDS copy of its block
+  d.parts_fit[0] = d.parts_fit[1] = true;
+  if (layout & LAYOUT_SHARED)
+    for (int64_t p : generic) {
+      const int32_t* q = &ps.dims[4 * p];
+      const int64_t nvp = q[0] + q[1] + q[2];
+      const int tbs[2] = {WAVE, 256};
+      for (int k = 0; k < 2; ++k) {
+        const int64_t G = q[0] >= tbs[k] ? 1 : tbs[k] / q[0];
+        if ((G - 1) * nvp > blk_size(q[0], layout & LAYOUT_FULL)) d.parts_fit[k] = false;
+      }
+    }
+  // the shared-block wavefront kernel: packed shared blocks of at most 2 x 64 rows
+  d.wave_tt = 0;
+  if (layout == LAYOUT_SHARED && !generic.empty()) {
+    int maxn = 0;
+    for (int64_t p : generic) maxn = std::max(maxn, (int)ps.dims[4 * p]);
+    const int tt = (maxn + WAVE - 1) / WAVE;
+    if (tt <= 2 && (ps.dim == 2 || ps.dim == 3) && (size_t)kWavePb * 2 * ps.max_m * sizeof(T) <= kMaxLds) {
+      d.wave_tt = tt;
+      d.nco = ps.dim;
+    }
+  }
 
   d.stream = (double)d.nfac * sizeof(T) >= kStreamBytes;
 
@@ -1799,6 +1867,7 @@ void analyze_impl(mas_handle* h, const mas_problem* pr, bool dev = false, hipStr
   if (par.gram_schmidt != MAS_GS_CLASSICAL && par.gram_schmidt != MAS_GS_MODIFIED)
     throw MasError(MAS_EINVAL, "unknown gram_schmidt");
   if (par.full_patch_min < 1 || par.bucket_min < 1) throw MasError(MAS_EINVAL, "full_patch_min and bucket_min must be >= 1");
+  if (par.patch_kernel < 0 || par.patch_kernel > 3) throw MasError(MAS_EINVAL, "patch_kernel must be 0..3");
   std::vector<int64_t> free0, dir0, free1;
   std::vector<int8_t> f0, f1;
   int64_t nu0 = 0, np0 = 0;
@@ -2601,6 +2670,7 @@ void mas_default_params(int32_t dim, int32_t disc, int32_t relax, mas_params* ou
   p.factor_blocked = 1;
   p.device_galerkin = 0;
   p.share_blocks = 1;
+  p.patch_kernel = 0;
   *out = p;
 }
 

@@ -47,7 +47,8 @@ class mas_params(C.Structure):
                 ("krylov_its", C.c_int32), ("nu_dlsc", C.c_int32), ("dlsc_amg", C.c_int32),
                 ("soc", C.c_int32), ("soc_eps", C.c_double), ("gram_schmidt", C.c_int32), ("autotune", C.c_int32),
                 ("graphs", C.c_int32), ("full_patch_min", C.c_int32), ("bucket_min", C.c_int32),
-                ("factor_blocked", C.c_int32), ("device_galerkin", C.c_int32), ("share_blocks", C.c_int32)]
+                ("factor_blocked", C.c_int32), ("device_galerkin", C.c_int32), ("share_blocks", C.c_int32),
+                ("patch_kernel", C.c_int32)]
 
 
 class mas_solve_info(C.Structure):

@@ -51,18 +51,25 @@ def test_shared_and_per_component_layouts_match_oracle(name, over):
     R = np.random.default_rng(29).standard_normal((P.n0, 3))
     refs = [pre.apply(R[:, k]) for k in range(3)]
     mp.nrhs_max = 3
-    for share in (1, 0):
+    # (share_blocks, patch_kernel): the workgroup kernel on both layouts, the
+    # shared-block wavefront kernel, the per-component column kernel
+    for share, kern in ((1, 1), (1, 3), (0, 1), (0, 2)):
         for precision, tol in ((mas.MAS_FP64, 1e-11), (mas.MAS_FP32, 1e-5)):
-            mp.share_blocks, mp.precision = share, precision
+            mp.share_blocks, mp.patch_kernel, mp.precision = share, kern, precision
             h = mas.Handle(P, mp)
             info = h.info()
             relaxed = [l for l in range(info["n_levels"]) if info["n_patches"][l] > 0]
-            print(f"[{name} {over}] share {share} precision {precision}: layouts {info['patch_layout']}", flush=True)
+            print(f"[{name} {over}] share {share} kernel {kern} precision {precision}: layouts "
+                  f"{info['patch_layout']} kernels {info['patch_kernel']}", flush=True)
             assert relaxed and all(bool(info["patch_layout"][l] & SHARED) == bool(share) for l in relaxed)
+            assert all(info["patch_kernel"][l] in (0, 1, kern) for l in relaxed)
+            if kern > 1 and "full_patch_min" not in over:  # packed blocks: the kernel applies somewhere
+                assert any(info["patch_kernel"][l] == kern for l in relaxed)
             for nr in (1, 3):
                 Z = apply(h, R, nr)
                 for k in range(nr):
-                    assert_parity(Z[:, k], refs[k], P.field0, tol, f"share {share} prec {precision} nr {nr} col {k}")
+                    assert_parity(Z[:, k], refs[k], P.field0, tol,
+                                  f"share {share} kernel {kern} prec {precision} nr {nr} col {k}")
             h.close()
 
 
