@@ -180,9 +180,12 @@ typedef struct {
                              fastest on each level, timed at upload (autotune = 1; the workgroup
                              kernel with autotune = 0); 1 workgroup per patch; 2 wavefront per
                              patch streaming the packed columns of per-component blocks; 3
-                             wavefront per patch on shared blocks.  A level the requested kernel
-                             does not take (2: shared or full blocks, or components above 128
-                             rows; 3: blocks not shared, full, or above 128 rows) uses 1 */
+                             wavefront per patch on shared blocks; 4 persistent workgroups, each
+                             loading its next patch while it solves the current one.  A level
+                             the requested kernel does not take (2: shared or full blocks, or
+                             components above 128 rows; 3: blocks not shared, full, or above 128
+                             rows; 4: records that do not fit in LDS or exceed 16 values per
+                             thread) uses 1 */
 } mas_params;
 
 typedef struct {
@@ -207,7 +210,8 @@ typedef struct {
   int32_t patch_kernel[16];   /* kernel of the other patches of a level, chosen at upload by
                                  timing: 0 none, 1 workgroup per patch, 2 wavefront per patch
                                  streaming the packed columns of per-component blocks, 3
-                                 wavefront per patch streaming the columns of a shared block */
+                                 wavefront per patch streaming the columns of a shared block,
+                                 4 persistent pipelined workgroups */
   int32_t bucket_shapes[16][16]; /* per level, up to 4 bucketed shapes (velocity DoFs per
                                     component x3, seeds), zero-padded, in launch order */
   int32_t patch_layout[16];   /* per level, bits of the factor records' A^-1 part: 1 = blocks

@@ -812,31 +812,59 @@ __global__ void k_add3(int64_t n, T* __restrict__ x, const T* __restrict__ y, co
   if (i < n) x[i] += y[i] + z[i];
 }
 
-// ---------------------------------------------------------------------------
-// The patch solve of the workgroup kernels, once the right-hand side b (sb)
-// and the factor record (sf) are in place: y_u = A^-1 b_u one row per thread,
-// t = Uhat^T b_u + b_p, y_p = S^-1 t, x_u = y_u + Uhat y_p, written to the
-// patch's output slots.  Every thread of the workgroup calls it (it holds
-// barriers).
-// y_u = A^-1 b_u when one block A (n x n, LAYOUT_SHARED) serves all
-// nco = nv / n velocity components: G = TPB / n thread groups (one when
-// n >= TPB); thread (g, i) sums row i of every component over the columns
-// j = g, g + G, ..., so each block entry is read once for all components.
-// After a barrier, groups 1..G-1 leave their sums in part ((G - 1) nco n
-// values, which may be the LDS copy of A itself, no longer read) and group 0
-// adds them in group order.  Every thread of the workgroup calls it (it holds
-// barriers).
 // the sums of row i of every component over the columns j = g, g + G, ...:
 // component count and storage are template arguments, so the unrolled loop
-// holds no branch and its loads are issued together
+// holds no branch and its loads are issued together.  Every lane runs the
+// same columns (a split at the diagonal would give the lanes of a wavefront
+// different trip counts); packed offsets in 32-bit unsigned arithmetic.
 template <typename T, int NCO, bool FULL>
 __device__ __forceinline__ void shared_row_sums(const T* sb, const T* A, int n, int i, int g, int G,
                                                 T (&acc)[3]) {
+  if (FULL) {
+    const T* a = A + (int64_t)g * n + i;
+    const int64_t step = (int64_t)G * n;
+#pragma unroll 8
+    for (int j = g; j < n; j += G, a += step) {
+      const T v = *a;
+#pragma unroll
+      for (int c = 0; c < NCO; ++c) acc[c] += v * sb[c * n + j];
+    }
+    return;
+  }
+  const unsigned ui = (unsigned)i;
 #pragma unroll 8
   for (int j = g; j < n; j += G) {
-    const T a = FULL ? A[(int64_t)j * n + i] : A[packed_index(i, j)];
+    const unsigned lo = min(ui, (unsigned)j), hi = max(ui, (unsigned)j);
+    const T v = A[((hi * (hi + 1u)) >> 1) + lo];
 #pragma unroll
-    for (int c = 0; c < NCO; ++c) acc[c] += a * sb[c * n + j];
+    for (int c = 0; c < NCO; ++c) acc[c] += v * sb[c * n + j];
+  }
+}
+
+// the same with b interleaved (b_c[j] at bi[j NCO + c]): the NCO reads of a
+// column sit at one address plus immediate offsets
+template <typename T, int NCO, bool FULL>
+__device__ __forceinline__ void shared_row_sums_il(const T* bi, const T* A, int n, int i, int g, int G,
+                                                   T (&acc)[3]) {
+  const T* bj = bi + g * NCO;
+  if (FULL) {
+    const T* a = A + (int64_t)g * n + i;
+    const int64_t step = (int64_t)G * n;
+#pragma unroll 8
+    for (int j = g; j < n; j += G, a += step, bj += G * NCO) {
+      const T v = *a;
+#pragma unroll
+      for (int c = 0; c < NCO; ++c) acc[c] += v * bj[c];
+    }
+    return;
+  }
+  const unsigned ui = (unsigned)i;
+#pragma unroll 8
+  for (int j = g; j < n; j += G, bj += G * NCO) {
+    const unsigned lo = min(ui, (unsigned)j), hi = max(ui, (unsigned)j);
+    const T v = A[((hi * (hi + 1u)) >> 1) + lo];
+#pragma unroll
+    for (int c = 0; c < NCO; ++c) acc[c] += v * bj[c];
   }
 }
 
@@ -856,20 +884,34 @@ __device__ __forceinline__ void vanka_shared_rows(const T* sb, T* sy, const T* A
   const int g = G == 1 ? 0 : tid / n;
   const int i0 = G == 1 ? tid : tid - g * n;
   T acc[3] = {0, 0, 0};
-  for (int i = i0; g < G && i < n; i += (G == 1 ? TPB : n)) {
+  if (G == 1) {  // a thread per row (and more rows per thread): results straight to sy
+    for (int i = i0; i < n; i += TPB) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) acc[c] = 0;
-    if (nco == 3 && full) shared_row_sums<T, 3, true>(sb, A, n, i, g, G, acc);
-    else if (nco == 3) shared_row_sums<T, 3, false>(sb, A, n, i, g, G, acc);
-    else if (full) shared_row_sums<T, 2, true>(sb, A, n, i, g, G, acc);
-    else shared_row_sums<T, 2, false>(sb, A, n, i, g, G, acc);
-    if (G == 1)
+      for (int c = 0; c < 3; ++c) acc[c] = 0;
+      if (nco == 3 && full) shared_row_sums<T, 3, true>(sb, A, n, i, 0, 1, acc);
+      else if (nco == 3) shared_row_sums<T, 3, false>(sb, A, n, i, 0, 1, acc);
+      else if (full) shared_row_sums<T, 2, true>(sb, A, n, i, 0, 1, acc);
+      else shared_row_sums<T, 2, false>(sb, A, n, i, 0, 1, acc);
 #pragma unroll
       for (int c = 0; c < 3; ++c)
         if (c < nco) sy[c * n + i] = acc[c];
+    }
+    return;
   }
-  if (G > 1) {
-    __syncthreads();  // every read of A done: part may overwrite it
+  // b_u interleaved by component into sy (free until the results land there)
+  for (int t = tid; t < nco * n; t += TPB) {
+    const int c = t / n, i = t - c * n;
+    sy[i * nco + c] = sb[t];
+  }
+  __syncthreads();
+  if (g < G) {
+    if (nco == 3 && full) shared_row_sums_il<T, 3, true>(sy, A, n, i0, g, G, acc);
+    else if (nco == 3) shared_row_sums_il<T, 3, false>(sy, A, n, i0, g, G, acc);
+    else if (full) shared_row_sums_il<T, 2, true>(sy, A, n, i0, g, G, acc);
+    else shared_row_sums_il<T, 2, false>(sy, A, n, i0, g, G, acc);
+  }
+  {
+    __syncthreads();  // every read of A and of the interleaved b done: part and sy may be overwritten
     if (g >= 1 && g < G)
 #pragma unroll
       for (int c = 0; c < 3; ++c)
@@ -886,6 +928,12 @@ __device__ __forceinline__ void vanka_shared_rows(const T* sb, T* sy, const T* A
   }
 }
 
+// ---------------------------------------------------------------------------
+// The patch solve of the workgroup kernels, once the right-hand side b (sb)
+// and the factor record (sf) are in place: y_u = A^-1 b_u one row per thread,
+// t = Uhat^T b_u + b_p, y_p = S^-1 t, x_u = y_u + Uhat y_p, written to the
+// patch's output slots.  Every thread of the workgroup calls it (it holds
+// barriers).
 template <typename T, int TPB>
 __device__ __forceinline__ void vanka_patch_compute(const T* sb, T* sy, const T* sf, T (*sred)[MAX_NS], T* spart,
                                                     int4 d, int64_t o, int64_t ua, int layout, T* __restrict__ Y,
@@ -1036,6 +1084,70 @@ __global__ void __launch_bounds__(TPB) k_vanka_apply(int64_t np, const int64_t* 
   }
   __syncthreads();
   vanka_patch_compute<T, TPB>(sb, sy, sf, sred, spart, d, o, ua, layout, Y, yshift, STAGE);
+}
+
+// additive Vanka, the workgroup kernel made persistent and pipelined: a
+// workgroup solves patches p, p + gridDim.x, ... and, before solving patch p
+// from LDS, requests the next patch's record (UL values per thread, the whole
+// record: UL TPB >= its length) and DoF indices into registers, then its
+// right-hand-side gather after the solve, so that a patch's loads overlap the
+// previous patch's solve.  Requires records staged in LDS and m <= 4 TPB.
+template <typename T, int TPB, bool NT, int UL>
+__global__ void __launch_bounds__(TPB) k_vanka_pipe(int64_t np, const int64_t* __restrict__ off,
+                                                   const int4* __restrict__ dims,
+                                                   const int64_t* __restrict__ foff,
+                                                   const int* __restrict__ dofs, const T* __restrict__ fac,
+                                                   const T* __restrict__ r, T* __restrict__ Y, int max_m,
+                                                   int64_t yshift, int layout, int spart_len) {
+  extern __shared__ unsigned char smem_raw[];
+  T* sb = reinterpret_cast<T*>(smem_raw);
+  T* sy = sb + max_m;
+  T* spart = sy + max_m;
+  T* st = spart + spart_len;
+  __shared__ T sred[TPB / WAVE][MAX_NS];
+  const int tid = threadIdx.x;
+  int64_t p = blockIdx.x;
+  if (p >= np) return;
+  T v[UL], g[4];
+  int idx[4];
+  int m_next = 0, nf_next = 0;
+  // the record and DoF-index loads of patch q (m_next, nf_next: its sizes)
+  auto request = [&](int64_t q) {
+    const int4 d = dims[q];
+    const int nvq = d.x + d.y + d.z;
+    m_next = nvq + d.w;
+    nf_next = (int)record_entries(d.x, d.y, d.z, d.w, layout);
+    const T* f = fac + foff[q] + tid;
+#pragma unroll
+    for (int u = 0; u < UL; ++u) v[u] = u * TPB + tid < nf_next ? ldv<NT>(f + u * TPB) : (T)0;
+    const int* dq = dofs + off[q] + tid;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) idx[u] = u * TPB + tid < m_next ? dq[u * TPB] : 0;
+  };
+  auto gather = [&]() {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) g[u] = u * TPB + tid < m_next ? r[idx[u]] : (T)0;
+  };
+  request(p);
+  gather();
+  for (; p < np; p += gridDim.x) {
+    const int4 d = dims[p];
+    const int64_t o = off[p];
+    const int64_t ua = vel_entries(d.x, d.y, d.z, layout);
+    const int m = m_next, nf = nf_next;
+    __syncthreads();  // the previous patch's solve is done with LDS
+#pragma unroll
+    for (int u = 0; u < UL; ++u)
+      if (u * TPB + tid < nf) st[u * TPB + tid] = v[u];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (u * TPB + tid < m) sb[u * TPB + tid] = g[u];
+    __syncthreads();
+    const int64_t pn = p + gridDim.x;
+    if (pn < np) request(pn);  // in flight during this patch's solve
+    vanka_patch_compute<T, TPB>(sb, sy, st, sred, spart, d, o, ua, layout, Y, yshift, true);
+    if (pn < np) gather();
+  }
 }
 
 // additive Vanka, one wavefront per patch, for patches whose velocity blocks

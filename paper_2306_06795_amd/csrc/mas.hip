@@ -425,6 +425,8 @@ struct DPatches {
                          // columns, 3 wavefront per patch on shared blocks (chosen at setup)
   int wave_tt = 0;       // row tiles of 64 of the shared-block wavefront kernel (0: not usable)
   int nco = 0;           // velocity components a shared block serves
+  bool pipe_ok = false;  // the persistent pipelined workgroup kernel takes this level's patches
+  unsigned pipe_grid = 0;  // its workgroups (resident at once), set when first launched
   bool parts_fit[2] = {true, true};  // shared blocks: every generic patch's partial row sums fit in
                                      // its staged copy of A (workgroups of 64 / 256 threads)
   bool nr_stage = true;  // the batched kernel stages factor records in LDS
@@ -849,7 +851,40 @@ struct Cycle : CycleBase {
       if (timed) tm->end(e0, e1, s, patch_bytes(L, rec * fb.P, (double)(nvb + nsd) * fb.P), TK_TPP);
     }
     const int64_t ng = pt.np - pt.g0;
-    if (ng > 0 && pt.gen_kernel == 3) {
+    if (ng > 0 && pt.gen_kernel == 4) {
+      const bool wide = pt.max_m >= kWidePatch;
+      const int tb = wide ? 256 : WAVE;
+      const int sp = (pt.layout & LAYOUT_SHARED) && !pt.parts_fit[wide ? 1 : 0] ? 3 * tb : 0;
+      const size_t shm = (size_t)(2 * pt.max_m + sp + pt.max_f) * sizeof(T);
+      const int ul = pt.max_f <= 8 * tb ? 8 : 16;
+      if (pt.pipe_grid == 0) {  // as many workgroups as stay resident
+        int dev = 0, cus = 0, per = 0;
+        HIPCHECK(hipGetDevice(&dev));
+        HIPCHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+#define MAS_OCC(TB, NT, U) \
+  HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_vanka_pipe<T, TB, NT, U>, TB, shm))
+        if (tb == 256) { if (ul == 8) MAS_OCC(256, true, 8); else MAS_OCC(256, true, 16); }
+        else { if (ul == 8) MAS_OCC(WAVE, true, 8); else MAS_OCC(WAVE, true, 16); }
+#undef MAS_OCC
+        pt.pipe_grid = (unsigned)std::max(1, cus * std::max(1, per));
+      }
+      const dim3 grid((unsigned)std::min<int64_t>(ng, pt.pipe_grid));
+      if (timed) tm->begin(e0, e1, s);
+#define MAS_PIPE(TB, NT, U)                                                                                    \
+  hipLaunchKernelGGL((k_vanka_pipe<T, TB, NT, U>), grid, dim3(TB), shm, s, ng, pt.off + pt.g0, pt.dims + pt.g0, \
+                     pt.foff + pt.g0, pt.dofs, pt.fac, rin, pt.Y, pt.max_m, pt.yshift, pt.layout, sp)
+      if (tb == 256) {
+        if (pt.stream) { if (ul == 8) MAS_PIPE(256, true, 8); else MAS_PIPE(256, true, 16); }
+        else { if (ul == 8) MAS_PIPE(256, false, 8); else MAS_PIPE(256, false, 16); }
+      } else {
+        if (pt.stream) { if (ul == 8) MAS_PIPE(WAVE, true, 8); else MAS_PIPE(WAVE, true, 16); }
+        else { if (ul == 8) MAS_PIPE(WAVE, false, 8); else MAS_PIPE(WAVE, false, 16); }
+      }
+#undef MAS_PIPE
+      launch_check();
+      if (timed)
+        tm->end(e0, e1, s, patch_bytes(L, (double)pt.nfac_alg - fast_fac, (double)pt.ndofs - fast_slots), TK_GENERIC);
+    } else if (ng > 0 && pt.gen_kernel == 3) {
       if (timed) tm->begin(e0, e1, s);
       const dim3 grid((unsigned)((ng + kWavePb - 1) / kWavePb));
       const size_t shm = (size_t)kWavePb * 2 * pt.max_m * sizeof(T);
@@ -928,12 +963,13 @@ struct Cycle : CycleBase {
     DPatches<T>& pt = L.pt;
     pt.gen_kernel = 0;
     const int want = par.patch_kernel;
-    if (want == 2 || want == 3) {  // requested: taken where the level allows it
+    if (want >= 2) {  // requested: taken where the level allows it
       if (want == 2 && pt.col_ok) pt.gen_kernel = 2;
       if (want == 3 && pt.wave_tt > 0) pt.gen_kernel = 3;
+      if (want == 4 && pt.pipe_ok) pt.gen_kernel = 4;
       return;
     }
-    if (want == 1 || !tune || pt.np - pt.g0 <= 0 || (!pt.col_ok && pt.wave_tt == 0)) return;
+    if (want == 1 || !tune || pt.np - pt.g0 <= 0 || (!pt.col_ok && pt.wave_tt == 0 && !pt.pipe_ok)) return;
     HIPCHECK(hipMemsetAsync(L.r, 0, (size_t)L.n * sizeof(T), s));
     hipEvent_t e0, e1;
     HIPCHECK(hipEventCreate(&e0));
@@ -950,18 +986,20 @@ struct Cycle : CycleBase {
       return ms;
     };
     // candidates: 0 workgroup per patch, 2 column-streaming wavefront (packed
-    // per-component blocks), 3 wavefront per patch on shared blocks
+    // per-component blocks), 3 wavefront per patch on shared blocks, 4 the
+    // persistent pipelined workgroup kernel
     const float t_wg = time_it(0);
-    float best = t_wg, t_col = -1.f, t_wave = -1.f;
+    float best = t_wg, t_col = -1.f, t_wave = -1.f, t_pipe = -1.f;
     int pick = 0;
     if (pt.col_ok && (t_col = time_it(2)) < best) best = t_col, pick = 2;
     if (pt.wave_tt > 0 && (t_wave = time_it(3)) < best) best = t_wave, pick = 3;
+    if (pt.pipe_ok && (t_pipe = time_it(4)) < best) best = t_pipe, pick = 4;
     pt.gen_kernel = pick;
     if (std::getenv("MAS_TRACE_SETUP"))
       std::fprintf(stderr, "[mas setup] level of %lld rows, %lld generic patches (max %d DoFs), us per sweep: "
-                   "workgroup %.1f, column %.1f, wave %.1f -> kernel %d\n", (long long)L.n,
-                   (long long)(pt.np - pt.g0), pt.max_m, 1e3 * t_wg / 3,
-                   t_col < 0 ? -1.0 : 1e3 * t_col / 3, t_wave < 0 ? -1.0 : 1e3 * t_wave / 3, pick);
+                   "workgroup %.1f, column %.1f, wave %.1f, pipelined %.1f -> kernel %d\n", (long long)L.n,
+                   (long long)(pt.np - pt.g0), pt.max_m, 1e3 * t_wg / 3, t_col < 0 ? -1.0 : 1e3 * t_col / 3,
+                   t_wave < 0 ? -1.0 : 1e3 * t_wave / 3, t_pipe < 0 ? -1.0 : 1e3 * t_pipe / 3, pick);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
   }
@@ -1477,6 +1515,14 @@ void build_patches(DevArena& ar, Level<T>& L, const PatchSet& ps, const DCsr<dou
         if ((G - 1) * nvp > blk_size(q[0], layout & LAYOUT_FULL)) d.parts_fit[k] = false;
       }
     }
+  // the persistent pipelined kernel: staged records of at most 16 values per
+  // thread, at most 4 DoFs per thread
+  {
+    const int tbp = ps.max_m >= kWidePatch ? 256 : WAVE;
+    const int spp = (layout & LAYOUT_SHARED) && !d.parts_fit[tbp == 256 ? 1 : 0] ? 3 * tbp : 0;
+    d.pipe_ok = !generic.empty() && d.max_f <= 16 * tbp && ps.max_m <= 4 * tbp &&
+                (size_t)(2 * ps.max_m + spp + d.max_f) * sizeof(T) <= kMaxLds;
+  }
   // the shared-block wavefront kernel: packed shared blocks of at most 2 x 64 rows
   d.wave_tt = 0;
   if (layout == LAYOUT_SHARED && !generic.empty()) {
@@ -1867,7 +1913,7 @@ void analyze_impl(mas_handle* h, const mas_problem* pr, bool dev = false, hipStr
   if (par.gram_schmidt != MAS_GS_CLASSICAL && par.gram_schmidt != MAS_GS_MODIFIED)
     throw MasError(MAS_EINVAL, "unknown gram_schmidt");
   if (par.full_patch_min < 1 || par.bucket_min < 1) throw MasError(MAS_EINVAL, "full_patch_min and bucket_min must be >= 1");
-  if (par.patch_kernel < 0 || par.patch_kernel > 3) throw MasError(MAS_EINVAL, "patch_kernel must be 0..3");
+  if (par.patch_kernel < 0 || par.patch_kernel > 4) throw MasError(MAS_EINVAL, "patch_kernel must be 0..4");
   std::vector<int64_t> free0, dir0, free1;
   std::vector<int8_t> f0, f1;
   int64_t nu0 = 0, np0 = 0;

@@ -51,9 +51,10 @@ def test_shared_and_per_component_layouts_match_oracle(name, over):
     R = np.random.default_rng(29).standard_normal((P.n0, 3))
     refs = [pre.apply(R[:, k]) for k in range(3)]
     mp.nrhs_max = 3
-    # (share_blocks, patch_kernel): the workgroup kernel on both layouts, the
-    # shared-block wavefront kernel, the per-component column kernel
-    for share, kern in ((1, 1), (1, 3), (0, 1), (0, 2)):
+    # (share_blocks, patch_kernel): the workgroup kernel and the persistent
+    # pipelined one on both layouts, the shared-block wavefront kernel, the
+    # per-component column kernel
+    for share, kern in ((1, 1), (1, 3), (1, 4), (0, 1), (0, 2), (0, 4)):
         for precision, tol in ((mas.MAS_FP64, 1e-11), (mas.MAS_FP32, 1e-5)):
             mp.share_blocks, mp.patch_kernel, mp.precision = share, kern, precision
             h = mas.Handle(P, mp)
@@ -63,7 +64,7 @@ def test_shared_and_per_component_layouts_match_oracle(name, over):
                   f"{info['patch_layout']} kernels {info['patch_kernel']}", flush=True)
             assert relaxed and all(bool(info["patch_layout"][l] & SHARED) == bool(share) for l in relaxed)
             assert all(info["patch_kernel"][l] in (0, 1, kern) for l in relaxed)
-            if kern > 1 and "full_patch_min" not in over:  # packed blocks: the kernel applies somewhere
+            if kern in (2, 3) and "full_patch_min" not in over:  # packed blocks: the kernel applies somewhere
                 assert any(info["patch_kernel"][l] == kern for l in relaxed)
             for nr in (1, 3):
                 Z = apply(h, R, nr)
