@@ -969,38 +969,54 @@ __device__ __forceinline__ void vanka_patch_compute(const T* sb, T* sy, const T*
   }
   const T* U = sf + ua;
   const T* Si = U + (int64_t)nv * ns;
+  // seeds: t = Uhat^T b_u + b_p, y_p = S^-1 t.  The seed arrays are indexed
+  // only by unrolled loop counters (ns <= MAX_NS as a predicate), so they stay
+  // in registers without index-dependent branches.
   T t[MAX_NS], yp[MAX_NS];
-  for (int s = 0; s < ns; ++s) {
-    T part = 0;
-    for (int k = tid; k < nv; k += TPB) part += U[(int64_t)s * nv + k] * sb[k];
-    part = wave_sum(part);
-    if (TPB == WAVE) {
-      t[s] = part + sb[nv + s];
-    } else {
-      if (lane == 0) sred[wv][s] = part;
+#pragma unroll
+  for (int s = 0; s < MAX_NS; ++s) {
+    t[s] = 0;
+    if (s < ns) {
+      T part = 0;
+      for (int k = tid; k < nv; k += TPB) part += U[(int64_t)s * nv + k] * sb[k];
+      part = wave_sum(part);
+      if (TPB == WAVE) t[s] = part + sb[nv + s];
+      else if (lane == 0) sred[wv][s] = part;
     }
   }
   if (TPB > WAVE) {
     __syncthreads();
-    for (int s = 0; s < ns; ++s) {
-      T acc = sred[0][s];
-      for (int q = 1; q < TPB / WAVE; ++q) acc += sred[q][s];
-      t[s] = acc + sb[nv + s];
-    }
+#pragma unroll
+    for (int s = 0; s < MAX_NS; ++s)
+      if (s < ns) {
+        T acc = sred[0][s];
+        for (int q = 1; q < TPB / WAVE; ++q) acc += sred[q][s];
+        t[s] = acc + sb[nv + s];
+      }
   }
-  for (int s = 0; s < ns; ++s) {
+#pragma unroll
+  for (int s = 0; s < MAX_NS; ++s) {
     T acc = 0;
-    for (int q = 0; q < ns; ++q) acc += Si[packed_index(s, q)] * t[q];
+#pragma unroll
+    for (int q = 0; q < MAX_NS; ++q)
+      if (s < ns && q < ns) acc += Si[packed_index(s, q)] * t[q];
     yp[s] = acc;
   }
   __syncthreads();
   for (int row = tid; row < nv; row += TPB) {
     T acc = sy[row];
-    for (int s = 0; s < ns; ++s) acc += U[(int64_t)s * nv + row] * yp[s];
+#pragma unroll
+    for (int s = 0; s < MAX_NS; ++s)
+      if (s < ns) acc += U[(int64_t)s * nv + row] * yp[s];
     Y[o - yshift + row] = acc;
   }
-  for (int s = 0; s < ns; ++s)
-    if (tid == s) Y[o - yshift + nv + s] = yp[s];
+  if (tid < ns) {
+    T v = 0;
+#pragma unroll
+    for (int s = 0; s < MAX_NS; ++s)
+      if (s == tid) v = yp[s];
+    Y[o - yshift + nv + tid] = v;
+  }
 }
 
 // additive Vanka: one workgroup of TPB threads (one or four wavefronts) per
@@ -1036,35 +1052,31 @@ __global__ void __launch_bounds__(TPB) k_vanka_apply(int64_t np, const int64_t* 
   // the host picks UL to cover the level's longest record where it can).
   T* st = spart + spart_len;
   T v[UL];
+  // Loads and stores past the end of the record (or of the DoF list) are
+  // clamped to its last element instead of guarded: no branch per load, and
+  // the extra stores write that element's own value again.
+  const int lastf = (int)min<int64_t>(nf, (int64_t)UL * TPB) - 1;
   if (STAGE) {
+    const T* src = fac + f0;
 #pragma unroll
-    for (int u = 0; u < UL; ++u) {
-      const int64_t k = (int64_t)u * TPB + tid;
-      v[u] = k < nf ? ldv<NT>(&fac[f0 + k]) : (T)0;
-    }
+    for (int u = 0; u < UL; ++u) v[u] = ldv<NT>(src + min(u * TPB + tid, lastf));
   }
   // gather: all index loads first, then all value loads (several in flight)
   for (int k0 = 0; k0 < m; k0 += 4 * TPB) {
+    const int lastm = min(m - k0, 4 * TPB) - 1;
     int idx[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int k = k0 + u * TPB + tid;
-      idx[u] = k < m ? dofs[o + k] : 0;
-    }
+    for (int u = 0; u < 4; ++u) idx[u] = dofs[o + k0 + min(u * TPB + tid, lastm)];
     T g[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) g[u] = (k0 + u * TPB + tid < m) ? r[idx[u]] : (T)0;
+    for (int u = 0; u < 4; ++u) g[u] = r[idx[u]];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (k0 + u * TPB + tid < m) sb[k0 + u * TPB + tid] = g[u];
+    for (int u = 0; u < 4; ++u) sb[k0 + min(u * TPB + tid, lastm)] = g[u];
   }
   const T* sf;
   if (STAGE) {
 #pragma unroll
-    for (int u = 0; u < UL; ++u) {
-      const int64_t k = (int64_t)u * TPB + tid;
-      if (k < nf) st[k] = v[u];
-    }
+    for (int u = 0; u < UL; ++u) st[min(u * TPB + tid, lastf)] = v[u];
     // the rest of a record longer than UL * TPB values, UL loads in flight per thread
     for (int64_t k0 = (int64_t)UL * TPB; k0 < nf; k0 += (int64_t)UL * TPB) {
 #pragma unroll
@@ -1117,16 +1129,16 @@ __global__ void __launch_bounds__(TPB) k_vanka_pipe(int64_t np, const int64_t* _
     const int nvq = d.x + d.y + d.z;
     m_next = nvq + d.w;
     nf_next = (int)record_entries(d.x, d.y, d.z, d.w, layout);
-    const T* f = fac + foff[q] + tid;
+    const T* f = fac + foff[q];
 #pragma unroll
-    for (int u = 0; u < UL; ++u) v[u] = u * TPB + tid < nf_next ? ldv<NT>(f + u * TPB) : (T)0;
-    const int* dq = dofs + off[q] + tid;
+    for (int u = 0; u < UL; ++u) v[u] = ldv<NT>(f + min(u * TPB + tid, nf_next - 1));
+    const int* dq = dofs + off[q];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) idx[u] = u * TPB + tid < m_next ? dq[u * TPB] : 0;
+    for (int u = 0; u < 4; ++u) idx[u] = dq[min(u * TPB + tid, m_next - 1)];
   };
   auto gather = [&]() {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) g[u] = u * TPB + tid < m_next ? r[idx[u]] : (T)0;
+    for (int u = 0; u < 4; ++u) g[u] = r[idx[u]];
   };
   request(p);
   gather();
@@ -1137,11 +1149,9 @@ __global__ void __launch_bounds__(TPB) k_vanka_pipe(int64_t np, const int64_t* _
     const int m = m_next, nf = nf_next;
     __syncthreads();  // the previous patch's solve is done with LDS
 #pragma unroll
-    for (int u = 0; u < UL; ++u)
-      if (u * TPB + tid < nf) st[u * TPB + tid] = v[u];
+    for (int u = 0; u < UL; ++u) st[min(u * TPB + tid, nf - 1)] = v[u];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (u * TPB + tid < m) sb[u * TPB + tid] = g[u];
+    for (int u = 0; u < 4; ++u) sb[min(u * TPB + tid, m - 1)] = g[u];
     __syncthreads();
     const int64_t pn = p + gridDim.x;
     if (pn < np) request(pn);  // in flight during this patch's solve

@@ -930,13 +930,14 @@ struct Cycle : CycleBase {
       const size_t shm = (size_t)(2 * pt.max_m + sp + (stage ? pt.max_f : 0)) * sizeof(T);
       // loads in flight per thread while a record is staged: enough for the
       // level's longest record where that takes at most 16
-      const int ul = pt.max_f <= 8 * tb ? 8 : pt.max_f <= 16 * tb ? 16 : 32;
+      const int ul = pt.max_f <= 8 * tb ? 8 : pt.max_f <= 12 * tb ? 12 : pt.max_f <= 16 * tb ? 16 : 32;
       if (timed) tm->begin(e0, e1, s);
 #define MAS_GENERIC(ST, TB, NT, U)                                                                                \
   hipLaunchKernelGGL((k_vanka_apply<T, ST, TB, NT, U>), dim3((unsigned)ng), dim3(TB), shm, s, ng, pt.off + pt.g0, \
                      pt.dims + pt.g0, pt.foff + pt.g0, pt.dofs, pt.fac, rin, pt.Y, pt.max_m, pt.yshift, pt.layout, sp)
-#define MAS_GENERIC_UL(ST, TB, NT)           \
-  if (ul == 8) MAS_GENERIC(ST, TB, NT, 8);   \
+#define MAS_GENERIC_UL(ST, TB, NT)                \
+  if (ul == 8) MAS_GENERIC(ST, TB, NT, 8);        \
+  else if (ul == 12) MAS_GENERIC(ST, TB, NT, 12); \
   else if (ul == 16) MAS_GENERIC(ST, TB, NT, 16); \
   else MAS_GENERIC(ST, TB, NT, 32)
       if (stage && tb == 256 && pt.stream) { MAS_GENERIC_UL(true, 256, true); }
