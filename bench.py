@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--theta", type=float, default=None,
                     help="strength-of-connection threshold of Algorithm 1 (default: the library's)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--patch-kernel", type=int, default=None, choices=[0, 1, 2, 3, 4],
+                    help="kernel of the patches outside the buckets (0: timed at setup)")
     ap.add_argument("--share-blocks", type=int, default=None, choices=[0, 1],
                     help="0: one A^-1 per velocity component even where the components' blocks are identical")
     ap.add_argument("--bucket-min", type=int, default=None,
@@ -371,6 +373,8 @@ def main():
     if a.share_blocks is not None:
         over["share_blocks"] = a.share_blocks
         label += f"+share{a.share_blocks}"
+    if a.patch_kernel is not None:
+        over["patch_kernel"] = a.patch_kernel
     mp = mas.default_params(prob.dim, mas.MAS_SV if prob.disc == "SV" else mas.MAS_TH, relax, precision=prec,
                             nrhs_max=nrhs, krylov_its=a.krylov_its, schedule=sched[a.schedule],
                             dlsc_amg=a.dlsc_amg, **over)

@@ -427,8 +427,11 @@ struct DPatches {
   int nco = 0;           // velocity components a shared block serves
   bool pipe_ok = false;  // the persistent pipelined workgroup kernel takes this level's patches
   unsigned pipe_grid = 0;  // its workgroups (resident at once), set when first launched
-  bool parts_fit[2] = {true, true};  // shared blocks: every generic patch's partial row sums fit in
-                                     // its staged copy of A (workgroups of 64 / 256 threads)
+  bool parts_fit[3] = {true, true, true};  // shared blocks: every generic patch's partial row sums
+                                           // fit in its staged copy of A (workgroups of 64 / 128 /
+                                           // 256 threads)
+  int wg_tb = 256;       // threads per patch of the workgroup kernel on levels of large patches
+                         // (128 or 256, timed at setup)
   bool nr_stage = true;  // the batched kernel stages factor records in LDS
 };
 
@@ -854,7 +857,7 @@ struct Cycle : CycleBase {
     if (ng > 0 && pt.gen_kernel == 4) {
       const bool wide = pt.max_m >= kWidePatch;
       const int tb = wide ? 256 : WAVE;
-      const int sp = (pt.layout & LAYOUT_SHARED) && !pt.parts_fit[wide ? 1 : 0] ? 3 * tb : 0;
+      const int sp = (pt.layout & LAYOUT_SHARED) && !pt.parts_fit[wide ? 2 : 0] ? 3 * tb : 0;
       const size_t shm = (size_t)(2 * pt.max_m + sp + pt.max_f) * sizeof(T);
       const int ul = pt.max_f <= 8 * tb ? 8 : 16;
       if (pt.pipe_grid == 0) {  // as many workgroups as stay resident
@@ -922,15 +925,17 @@ struct Cycle : CycleBase {
       const bool sh = (pt.layout & LAYOUT_SHARED) != 0;
       // LDS: b and y (max_m each), the shared layout's partial row sums (3 TPB
       // values, unless every patch's fit in its staged copy of A), the staged record
-      const int tb_stage = wide ? 256 : WAVE;
-      const int sp_stage = sh && !pt.parts_fit[wide ? 1 : 0] ? 3 * tb_stage : 0;
+      const int tb_stage = wide ? pt.wg_tb : WAVE;
+      const int fit_k = tb_stage == 256 ? 2 : tb_stage == 128 ? 1 : 0;
+      const int sp_stage = sh && !pt.parts_fit[fit_k] ? 3 * tb_stage : 0;
       const bool stage = (size_t)(2 * pt.max_m + sp_stage + pt.max_f) * sizeof(T) <= kMaxLds;
       const int tb = stage ? tb_stage : (pt.max_m >= kFullPatch ? 1024 : tb_stage);
       const int sp = stage ? sp_stage : (sh ? 3 * tb : 0);
       const size_t shm = (size_t)(2 * pt.max_m + sp + (stage ? pt.max_f : 0)) * sizeof(T);
       // loads in flight per thread while a record is staged: enough for the
       // level's longest record where that takes at most 16
-      const int ul = pt.max_f <= 8 * tb ? 8 : pt.max_f <= 12 * tb ? 12 : pt.max_f <= 16 * tb ? 16 : 32;
+      const int ul = pt.max_f <= 8 * tb ? 8 : pt.max_f <= 12 * tb ? 12 : pt.max_f <= 16 * tb ? 16
+                     : pt.max_f <= 24 * tb ? 24 : 32;
       if (timed) tm->begin(e0, e1, s);
 #define MAS_GENERIC(ST, TB, NT, U)                                                                                \
   hipLaunchKernelGGL((k_vanka_apply<T, ST, TB, NT, U>), dim3((unsigned)ng), dim3(TB), shm, s, ng, pt.off + pt.g0, \
@@ -939,10 +944,13 @@ struct Cycle : CycleBase {
   if (ul == 8) MAS_GENERIC(ST, TB, NT, 8);        \
   else if (ul == 12) MAS_GENERIC(ST, TB, NT, 12); \
   else if (ul == 16) MAS_GENERIC(ST, TB, NT, 16); \
+  else if (ul == 24) MAS_GENERIC(ST, TB, NT, 24); \
   else MAS_GENERIC(ST, TB, NT, 32)
       if (stage && tb == 256 && pt.stream) { MAS_GENERIC_UL(true, 256, true); }
+      else if (stage && tb == 128 && pt.stream) { MAS_GENERIC_UL(true, 128, true); }
       else if (stage && pt.stream) { MAS_GENERIC_UL(true, WAVE, true); }
       else if (stage && tb == 256) { MAS_GENERIC_UL(true, 256, false); }
+      else if (stage && tb == 128) { MAS_GENERIC_UL(true, 128, false); }
       else if (stage) { MAS_GENERIC_UL(true, WAVE, false); }
       else if (tb == 1024) MAS_GENERIC(false, 1024, false, 8);
       else if (tb == 256) MAS_GENERIC(false, 256, false, 8);
@@ -970,7 +978,10 @@ struct Cycle : CycleBase {
       if (want == 4 && pt.pipe_ok) pt.gen_kernel = 4;
       return;
     }
-    if (want == 1 || !tune || pt.np - pt.g0 <= 0 || (!pt.col_ok && pt.wave_tt == 0 && !pt.pipe_ok)) return;
+    pt.wg_tb = 256;
+    if (!tune || pt.np - pt.g0 <= 0 || (pt.max_m < kWidePatch && (want == 1 || (!pt.col_ok && pt.wave_tt == 0 &&
+                                                                               !pt.pipe_ok))))
+      return;
     HIPCHECK(hipMemsetAsync(L.r, 0, (size_t)L.n * sizeof(T), s));
     hipEvent_t e0, e1;
     HIPCHECK(hipEventCreate(&e0));
@@ -989,17 +1000,25 @@ struct Cycle : CycleBase {
     // candidates: 0 workgroup per patch, 2 column-streaming wavefront (packed
     // per-component blocks), 3 wavefront per patch on shared blocks, 4 the
     // persistent pipelined workgroup kernel
-    const float t_wg = time_it(0);
+    // the workgroup kernel with 256 and, on levels of large patches, 128 threads per patch
+    pt.wg_tb = 256;
+    float t_wg = time_it(0);
+    if (pt.max_m >= kWidePatch) {
+      pt.wg_tb = 128;
+      const float t128 = time_it(0);
+      if (t128 < t_wg) t_wg = t128;
+      else pt.wg_tb = 256;
+    }
     float best = t_wg, t_col = -1.f, t_wave = -1.f, t_pipe = -1.f;
     int pick = 0;
-    if (pt.col_ok && (t_col = time_it(2)) < best) best = t_col, pick = 2;
-    if (pt.wave_tt > 0 && (t_wave = time_it(3)) < best) best = t_wave, pick = 3;
-    if (pt.pipe_ok && (t_pipe = time_it(4)) < best) best = t_pipe, pick = 4;
+    if (want != 1 && pt.col_ok && (t_col = time_it(2)) < best) best = t_col, pick = 2;
+    if (want != 1 && pt.wave_tt > 0 && (t_wave = time_it(3)) < best) best = t_wave, pick = 3;
+    if (want != 1 && pt.pipe_ok && (t_pipe = time_it(4)) < best) best = t_pipe, pick = 4;
     pt.gen_kernel = pick;
     if (std::getenv("MAS_TRACE_SETUP"))
       std::fprintf(stderr, "[mas setup] level of %lld rows, %lld generic patches (max %d DoFs), us per sweep: "
-                   "workgroup %.1f, column %.1f, wave %.1f, pipelined %.1f -> kernel %d\n", (long long)L.n,
-                   (long long)(pt.np - pt.g0), pt.max_m, 1e3 * t_wg / 3, t_col < 0 ? -1.0 : 1e3 * t_col / 3,
+                   "workgroup %.1f (%d threads), column %.1f, wave %.1f, pipelined %.1f -> kernel %d\n", (long long)L.n,
+                   (long long)(pt.np - pt.g0), pt.max_m, 1e3 * t_wg / 3, pt.wg_tb, t_col < 0 ? -1.0 : 1e3 * t_col / 3,
                    t_wave < 0 ? -1.0 : 1e3 * t_wave / 3, t_pipe < 0 ? -1.0 : 1e3 * t_pipe / 3, pick);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1505,13 +1524,13 @@ void build_patches(DevArena& ar, Level<T>& L, const PatchSet& ps, const DCsr<dou
     for (int c = 0; c < 3; ++c) d.col_ok = d.col_ok && ps.dims[4 * p + c] <= 2 * WAVE;
   // shared blocks, workgroup kernel: where the partial row sums of a patch's
   // thread groups (G = TPB / n groups) fit in the LDS copy of its block
-  d.parts_fit[0] = d.parts_fit[1] = true;
+  d.parts_fit[0] = d.parts_fit[1] = d.parts_fit[2] = true;
   if (layout & LAYOUT_SHARED)
     for (int64_t p : generic) {
       const int32_t* q = &ps.dims[4 * p];
       const int64_t nvp = q[0] + q[1] + q[2];
-      const int tbs[2] = {WAVE, 256};
-      for (int k = 0; k < 2; ++k) {
+      const int tbs[3] = {WAVE, 128, 256};
+      for (int k = 0; k < 3; ++k) {
         const int64_t G = q[0] >= tbs[k] ? 1 : tbs[k] / q[0];
         if ((G - 1) * nvp > blk_size(q[0], layout & LAYOUT_FULL)) d.parts_fit[k] = false;
       }
@@ -1520,7 +1539,7 @@ void build_patches(DevArena& ar, Level<T>& L, const PatchSet& ps, const DCsr<dou
   // thread, at most 4 DoFs per thread
   {
     const int tbp = ps.max_m >= kWidePatch ? 256 : WAVE;
-    const int spp = (layout & LAYOUT_SHARED) && !d.parts_fit[tbp == 256 ? 1 : 0] ? 3 * tbp : 0;
+    const int spp = (layout & LAYOUT_SHARED) && !d.parts_fit[tbp == 256 ? 2 : 0] ? 3 * tbp : 0;
     d.pipe_ok = !generic.empty() && d.max_f <= 16 * tbp && ps.max_m <= 4 * tbp &&
                 (size_t)(2 * ps.max_m + spp + d.max_f) * sizeof(T) <= kMaxLds;
   }
