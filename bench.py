@@ -51,7 +51,7 @@ def parse():
     ap.add_argument("--theta", type=float, default=None,
                     help="strength-of-connection threshold of Algorithm 1 (default: the library's)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
-    ap.add_argument("--patch-kernel", type=int, default=None, choices=[0, 1, 2, 3, 4],
+    ap.add_argument("--patch-kernel", type=int, default=None, choices=[0, 1, 2, 3, 4, 5],
                     help="kernel of the patches outside the buckets (0: timed at setup)")
     ap.add_argument("--share-blocks", type=int, default=None, choices=[0, 1],
                     help="0: one A^-1 per velocity component even where the components' blocks are identical")

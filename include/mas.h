@@ -181,11 +181,14 @@ typedef struct {
                              kernel with autotune = 0); 1 workgroup per patch; 2 wavefront per
                              patch streaming the packed columns of per-component blocks; 3
                              wavefront per patch on shared blocks; 4 persistent workgroups, each
-                             loading its next patch while it solves the current one.  A level
-                             the requested kernel does not take (2: shared or full blocks, or
-                             components above 128 rows; 3: blocks not shared, full, or above 128
-                             rows; 4: records that do not fit in LDS or exceed 16 values per
-                             thread) uses 1 */
+                             loading its next patch while it solves the current one; 5 panels of
+                             a packed shared block streamed through LDS (the kernel of levels
+                             whose packed shared records are too large for LDS, taken there also
+                             by 0).  A
+                             level the requested kernel does not take (2: shared or full blocks,
+                             or components above 128 rows; 3: blocks not shared, full, or above
+                             128 rows; 4: records that do not fit in LDS or exceed 16 values per
+                             thread; 5: blocks not shared or above 1024 rows) uses 1 */
 } mas_params;
 
 typedef struct {
@@ -211,7 +214,8 @@ typedef struct {
                                  timing: 0 none, 1 workgroup per patch, 2 wavefront per patch
                                  streaming the packed columns of per-component blocks, 3
                                  wavefront per patch streaming the columns of a shared block,
-                                 4 persistent pipelined workgroups */
+                                 4 persistent pipelined workgroups, 5 panels of a shared block
+                                 streamed through LDS */
   int32_t bucket_shapes[16][16]; /* per level, up to 4 bucketed shapes (velocity DoFs per
                                     component x3, seeds), zero-padded, in launch order */
   int32_t patch_layout[16];   /* per level, bits of the factor records' A^-1 part: 1 = blocks

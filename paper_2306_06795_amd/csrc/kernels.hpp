@@ -928,46 +928,14 @@ __device__ __forceinline__ void vanka_shared_rows(const T* sb, T* sy, const T* A
   }
 }
 
-// ---------------------------------------------------------------------------
-// The patch solve of the workgroup kernels, once the right-hand side b (sb)
-// and the factor record (sf) are in place: y_u = A^-1 b_u one row per thread,
-// t = Uhat^T b_u + b_p, y_p = S^-1 t, x_u = y_u + Uhat y_p, written to the
-// patch's output slots.  Every thread of the workgroup calls it (it holds
-// barriers).
+// The seed part of a patch solve, once y_u = A^-1 b_u is in sy (Uhat and S^-1
+// at U, read where they are: LDS or memory): t = Uhat^T b_u + b_p,
+// y_p = S^-1 t, x_u = y_u + Uhat y_p, written to the patch's output slots.
+// Every thread of the workgroup calls it (it holds barriers).
 template <typename T, int TPB>
-__device__ __forceinline__ void vanka_patch_compute(const T* sb, T* sy, const T* sf, T (*sred)[MAX_NS], T* spart,
-                                                    int4 d, int64_t o, int64_t ua, int layout, T* __restrict__ Y,
-                                                    int64_t yshift, bool stage_rec) {
+__device__ __forceinline__ void vanka_patch_seeds(const T* sb, const T* sy, const T* U, T (*sred)[MAX_NS],
+                                                  int nv, int ns, int64_t o, T* __restrict__ Y, int64_t yshift) {
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
-  const int nv = d.x + d.y + d.z, ns = d.w;
-  const int nc[3] = {d.x, d.y, d.z};
-  const int full = layout & LAYOUT_FULL;
-  if (layout & LAYOUT_SHARED) {
-    // the partial sums go to the staged copy of A when they fit there (the
-    // host then allocates no separate area)
-    const int n = d.x, G = n >= TPB ? 1 : TPB / n;
-    const bool in_rec = stage_rec && (int64_t)(G - 1) * nv <= blk_size(n, full);
-    vanka_shared_rows<T, TPB>(sb, sy, sf, in_rec ? const_cast<T*>(sf) : spart, n, nv / n, full);
-  }
-  // y_u = A^-1 b_u, one row per thread
-  for (int row = tid; row < ((layout & LAYOUT_SHARED) ? 0 : nv); row += TPB) {
-    int c = 0, cs = 0;
-    int64_t ao = 0;
-    while (row >= cs + nc[c]) {
-      ao += blk_size(nc[c], full);
-      cs += nc[c];
-      ++c;
-    }
-    const int i = row - cs;
-    const T* A = sf + ao;
-    T acc = 0;
-    if (full)  // entry (i, j) at j n + i: consecutive threads read consecutive values
-      for (int j = 0; j < nc[c]; ++j) acc += A[(int64_t)j * nc[c] + i] * sb[cs + j];
-    else
-      for (int j = 0; j < nc[c]; ++j) acc += A[packed_index(i, j)] * sb[cs + j];
-    sy[row] = acc;
-  }
-  const T* U = sf + ua;
   const T* Si = U + (int64_t)nv * ns;
   // seeds: t = Uhat^T b_u + b_p, y_p = S^-1 t.  The seed arrays are indexed
   // only by unrolled loop counters (ns <= MAX_NS as a predicate), so they stay
@@ -1017,6 +985,49 @@ __device__ __forceinline__ void vanka_patch_compute(const T* sb, T* sy, const T*
       if (s == tid) v = yp[s];
     Y[o - yshift + nv + tid] = v;
   }
+}
+
+
+// ---------------------------------------------------------------------------
+// The patch solve of the workgroup kernels, once the right-hand side b (sb)
+// and the factor record (sf) are in place: y_u = A^-1 b_u one row per thread,
+// t = Uhat^T b_u + b_p, y_p = S^-1 t, x_u = y_u + Uhat y_p, written to the
+// patch's output slots.  Every thread of the workgroup calls it (it holds
+// barriers).
+template <typename T, int TPB>
+__device__ __forceinline__ void vanka_patch_compute(const T* sb, T* sy, const T* sf, T (*sred)[MAX_NS], T* spart,
+                                                    int4 d, int64_t o, int64_t ua, int layout, T* __restrict__ Y,
+                                                    int64_t yshift, bool stage_rec) {
+  const int tid = threadIdx.x;
+  const int nv = d.x + d.y + d.z, ns = d.w;
+  const int nc[3] = {d.x, d.y, d.z};
+  const int full = layout & LAYOUT_FULL;
+  if (layout & LAYOUT_SHARED) {
+    // the partial sums go to the staged copy of A when they fit there (the
+    // host then allocates no separate area)
+    const int n = d.x, G = n >= TPB ? 1 : TPB / n;
+    const bool in_rec = stage_rec && (int64_t)(G - 1) * nv <= blk_size(n, full);
+    vanka_shared_rows<T, TPB>(sb, sy, sf, in_rec ? const_cast<T*>(sf) : spart, n, nv / n, full);
+  }
+  // y_u = A^-1 b_u, one row per thread
+  for (int row = tid; row < ((layout & LAYOUT_SHARED) ? 0 : nv); row += TPB) {
+    int c = 0, cs = 0;
+    int64_t ao = 0;
+    while (row >= cs + nc[c]) {
+      ao += blk_size(nc[c], full);
+      cs += nc[c];
+      ++c;
+    }
+    const int i = row - cs;
+    const T* A = sf + ao;
+    T acc = 0;
+    if (full)  // entry (i, j) at j n + i: consecutive threads read consecutive values
+      for (int j = 0; j < nc[c]; ++j) acc += A[(int64_t)j * nc[c] + i] * sb[cs + j];
+    else
+      for (int j = 0; j < nc[c]; ++j) acc += A[packed_index(i, j)] * sb[cs + j];
+    sy[row] = acc;
+  }
+  vanka_patch_seeds<T, TPB>(sb, sy, sf + ua, sred, nv, ns, o, Y, yshift);
 }
 
 // additive Vanka: one workgroup of TPB threads (one or four wavefronts) per
@@ -1158,6 +1169,130 @@ __global__ void __launch_bounds__(TPB) k_vanka_pipe(int64_t np, const int64_t* _
     vanka_patch_compute<T, TPB>(sb, sy, st, sred, spart, d, o, ua, layout, Y, yshift, true);
     if (pn < np) gather();
   }
+}
+
+// additive Vanka for patches too large for LDS whose one packed A^-1 block
+// serves NCO velocity components (LAYOUT_SHARED, n <= TPB rows): the block is
+// streamed in panels of consecutive columns (a panel of packed columns is one
+// contiguous range of the record, at most PL TPB values), each copied into LDS
+// with coalesced loads; the next panel's loads are issued into registers
+// before the current panel is used.  From a panel, thread group g of row i
+// adds a_ij b_c[j] for its columns j >= i (j = g mod G, G = TPB / n groups;
+// consecutive rows read consecutive LDS words), and wavefronts sum
+// a_ij b_c[i] over i < j for the panel's columns (the transposed half, one
+// column per wavefront at a time).  Then the seed part as in the other
+// workgroup kernels.  Half the bytes of storing the block full.
+template <typename T, int NCO, bool NT, int TPB, int PL>
+__global__ void __launch_bounds__(TPB) k_vanka_panel(int64_t np, const int64_t* __restrict__ off,
+                                                    const int4* __restrict__ dims,
+                                                    const int64_t* __restrict__ foff,
+                                                    const int* __restrict__ dofs, const T* __restrict__ fac,
+                                                    const T* __restrict__ r, T* __restrict__ Y, int max_m,
+                                                    int64_t yshift) {
+  extern __shared__ unsigned char smem_raw[];
+  T* sb = reinterpret_cast<T*>(smem_raw);  // b (m values)
+  T* sy = sb + max_m;                      // column sums of the transposed half, then y_u
+  T* pan = sy + max_m;                     // one panel (PL TPB values), then partial row sums
+  __shared__ T sred[TPB / WAVE][MAX_NS];
+  constexpr int CAP = PL * TPB, NW = TPB / WAVE;
+  const int64_t p = blockIdx.x;
+  if (p >= np) return;
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
+  const int4 d = dims[p];
+  const int n = d.x, nv = NCO * n, ns = d.w, m = nv + ns;
+  const int64_t o = off[p];
+  const T* A = fac + foff[p];
+  auto tri = [](int j) { return (int)(((unsigned)j * (unsigned)(j + 1)) >> 1); };
+  // last column + 1 of the panel that starts at column j0: at most CAP values
+  auto panel_end = [&](int j0) {
+    const double lim = (double)CAP + (double)tri(j0);
+    int j1 = (int)((sqrt(8.0 * lim + 1.0) - 1.0) * 0.5);  // tri(j1) <= lim, up to rounding
+    while (j1 > j0 && tri(j1) > lim) --j1;
+    while (j1 < n && tri(j1 + 1) <= lim) ++j1;
+    return min(max(j1, j0 + 1), n);
+  };
+  T pv[PL];
+  int J0 = 0, J1 = panel_end(0);
+  auto request = [&](int j0, int j1) {
+    const T* src = A + tri(j0);
+    const int last = tri(j1) - tri(j0) - 1;
+#pragma unroll
+    for (int u = 0; u < PL; ++u) pv[u] = ldv<NT>(src + min(u * TPB + tid, last));
+  };
+  request(J0, J1);
+  // gather b (clamped, as in the other kernels)
+  for (int k0 = 0; k0 < m; k0 += 4 * TPB) {
+    const int lastm = min(m - k0, 4 * TPB) - 1;
+    int idx[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) idx[u] = dofs[o + k0 + min(u * TPB + tid, lastm)];
+    T g[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) g[u] = r[idx[u]];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) sb[k0 + min(u * TPB + tid, lastm)] = g[u];
+  }
+  const int G = TPB / n;  // n <= TPB
+  const int g = tid / n, i0 = tid - g * n;
+  T acc[NCO];
+#pragma unroll
+  for (int c = 0; c < NCO; ++c) acc[c] = 0;
+  for (;;) {
+    const int j0 = J0, j1 = J1, base = tri(j0), cnt = tri(j1) - base;
+    __syncthreads();  // the previous panel is done with
+#pragma unroll
+    for (int u = 0; u < PL; ++u) pan[min(u * TPB + tid, cnt - 1)] = pv[u];
+    __syncthreads();
+    if (j1 < n) {  // the next panel's loads, in flight while this one is used
+      J0 = j1;
+      J1 = panel_end(j1);
+      request(J0, J1);
+    }
+    // row i0 over this panel's columns j >= i0 with j = g (mod G)
+    if (g < G) {
+      int j = max(j0, i0);
+      j += (g - j % G + G) % G;
+      for (; j < j1; j += G) {
+        const T a = pan[tri(j) - base + i0];
+#pragma unroll
+        for (int c = 0; c < NCO; ++c) acc[c] += a * sb[c * n + j];
+      }
+    }
+    // column j: sum over i < j of a_ij b_c[i], one wavefront per column
+    for (int j = j0 + wv; j < j1; j += NW) {
+      const T* col = pan + (tri(j) - base);
+      T sc[NCO];
+#pragma unroll
+      for (int c = 0; c < NCO; ++c) sc[c] = 0;
+      for (int i = lane; i < j; i += WAVE) {
+        const T a = col[i];
+#pragma unroll
+        for (int c = 0; c < NCO; ++c) sc[c] += a * sb[c * n + i];
+      }
+#pragma unroll
+      for (int c = 0; c < NCO; ++c) {
+        const T v = wave_sum(sc[c]);
+        if (lane == 0) sy[c * n + j] = v;
+      }
+    }
+    if (j1 >= n) break;
+  }
+  // y_u: the row sums of all groups plus the column sums (partials of groups
+  // 1..G-1 in the panel area, free now)
+  __syncthreads();
+  if (g >= 1 && g < G)
+#pragma unroll
+    for (int c = 0; c < NCO; ++c) pan[(g - 1) * nv + c * n + i0] = acc[c];
+  __syncthreads();
+  if (g == 0)
+#pragma unroll
+    for (int c = 0; c < NCO; ++c) {
+      T v = acc[c] + sy[c * n + i0];
+      for (int q = 1; q < G; ++q) v += pan[(q - 1) * nv + c * n + i0];
+      sy[c * n + i0] = v;
+    }
+  __syncthreads();
+  vanka_patch_seeds<T, TPB>(sb, sy, A + tri(n), sred, nv, ns, o, Y, yshift);
 }
 
 // additive Vanka, one wavefront per patch, for patches whose velocity blocks

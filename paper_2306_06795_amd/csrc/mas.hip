@@ -68,6 +68,8 @@ constexpr int kNrKT = 4;                // right-hand sides per thread in the ba
 constexpr int kWidePatch = 128;         // patches of this many DoFs or more get a 256-thread workgroup
 constexpr int kFullPatch = 512;         // levels with patches this large store full velocity blocks
 constexpr int kWavePb = 4;              // patches (wavefronts) per workgroup of the shared-block wave kernel
+constexpr int kPanelTpb = 1024;         // threads per patch of the panel kernel (largest shared block rows)
+constexpr int kPanelBytes = 32 * 1024;  // LDS of one panel of the panel kernel
 
 // LDS of the batched patch kernel: m x C block, two MAX_NS x C blocks, the
 // staged record (f values) and the patch DoF list
@@ -426,6 +428,8 @@ struct DPatches {
   int wave_tt = 0;       // row tiles of 64 of the shared-block wavefront kernel (0: not usable)
   int nco = 0;           // velocity components a shared block serves
   bool pipe_ok = false;  // the persistent pipelined workgroup kernel takes this level's patches
+  bool panel_ok = false;   // the panel kernel takes this level's patches (shared packed blocks)
+  bool panel_auto = false; // ... and is the level's kernel (records too large to stage in LDS)
   unsigned pipe_grid = 0;  // its workgroups (resident at once), set when first launched
   bool parts_fit[3] = {true, true, true};  // shared blocks: every generic patch's partial row sums
                                            // fit in its staged copy of A (workgroups of 64 / 128 /
@@ -854,7 +858,23 @@ struct Cycle : CycleBase {
       if (timed) tm->end(e0, e1, s, patch_bytes(L, rec * fb.P, (double)(nvb + nsd) * fb.P), TK_TPP);
     }
     const int64_t ng = pt.np - pt.g0;
-    if (ng > 0 && pt.gen_kernel == 4) {
+    if (ng > 0 && pt.gen_kernel == 5) {
+      constexpr int PL = kPanelBytes / kPanelTpb / (int)sizeof(T);
+      const size_t shm = (size_t)2 * pt.max_m * sizeof(T) + kPanelBytes;
+      if (timed) tm->begin(e0, e1, s);
+#define MAS_PANEL(NC, NT)                                                                                          \
+  hipLaunchKernelGGL((k_vanka_panel<T, NC, NT, kPanelTpb, PL>), dim3((unsigned)ng), dim3(kPanelTpb), shm, s, ng,  \
+                     pt.off + pt.g0, pt.dims + pt.g0, pt.foff + pt.g0, pt.dofs, pt.fac, rin, pt.Y, pt.max_m,        \
+                     pt.yshift)
+      if (pt.nco == 3 && pt.stream) MAS_PANEL(3, true);
+      else if (pt.nco == 3) MAS_PANEL(3, false);
+      else if (pt.stream) MAS_PANEL(2, true);
+      else MAS_PANEL(2, false);
+#undef MAS_PANEL
+      launch_check();
+      if (timed)
+        tm->end(e0, e1, s, patch_bytes(L, (double)pt.nfac_alg - fast_fac, (double)pt.ndofs - fast_slots), TK_GENERIC);
+    } else if (ng > 0 && pt.gen_kernel == 4) {
       const bool wide = pt.max_m >= kWidePatch;
       const int tb = wide ? 256 : WAVE;
       const int sp = (pt.layout & LAYOUT_SHARED) && !pt.parts_fit[wide ? 2 : 0] ? 3 * tb : 0;
@@ -976,6 +996,13 @@ struct Cycle : CycleBase {
       if (want == 2 && pt.col_ok) pt.gen_kernel = 2;
       if (want == 3 && pt.wave_tt > 0) pt.gen_kernel = 3;
       if (want == 4 && pt.pipe_ok) pt.gen_kernel = 4;
+      if (want == 5 && pt.panel_ok) pt.gen_kernel = 5;
+      return;
+    }
+    // levels of packed shared blocks too large for LDS: the panel kernel (the
+    // workgroup kernel would read such blocks uncoalesced)
+    if (pt.panel_auto && want == 0) {
+      pt.gen_kernel = 5;
       return;
     }
     pt.wg_tb = 256;
@@ -1543,17 +1570,26 @@ void build_patches(DevArena& ar, Level<T>& L, const PatchSet& ps, const DCsr<dou
     d.pipe_ok = !generic.empty() && d.max_f <= 16 * tbp && ps.max_m <= 4 * tbp &&
                 (size_t)(2 * ps.max_m + spp + d.max_f) * sizeof(T) <= kMaxLds;
   }
+  // the panel kernel: packed shared blocks of at most kPanelTpb rows, records too large to stage
+  {
+    int maxn = 0;
+    for (int64_t p : generic) maxn = std::max(maxn, (int)ps.dims[4 * p]);
+    const int tbs = ps.max_m >= kWidePatch ? 256 : WAVE;
+    const bool stageable = (size_t)(2 * ps.max_m + 3 * tbs + d.max_f) * sizeof(T) <= kMaxLds;
+    d.panel_ok = layout == LAYOUT_SHARED && !generic.empty() && maxn <= kPanelTpb &&
+                 (ps.dim == 2 || ps.dim == 3) && (size_t)2 * ps.max_m * sizeof(T) + kPanelBytes <= kMaxLds;
+    d.panel_auto = d.panel_ok && !stageable;
+  }
   // the shared-block wavefront kernel: packed shared blocks of at most 2 x 64 rows
   d.wave_tt = 0;
   if (layout == LAYOUT_SHARED && !generic.empty()) {
     int maxn = 0;
     for (int64_t p : generic) maxn = std::max(maxn, (int)ps.dims[4 * p]);
     const int tt = (maxn + WAVE - 1) / WAVE;
-    if (tt <= 2 && (ps.dim == 2 || ps.dim == 3) && (size_t)kWavePb * 2 * ps.max_m * sizeof(T) <= kMaxLds) {
+    if (tt <= 2 && (ps.dim == 2 || ps.dim == 3) && (size_t)kWavePb * 2 * ps.max_m * sizeof(T) <= kMaxLds)
       d.wave_tt = tt;
-      d.nco = ps.dim;
-    }
   }
+  if (layout & LAYOUT_SHARED) d.nco = ps.dim;
 
   d.stream = (double)d.nfac * sizeof(T) >= kStreamBytes;
 
@@ -1933,7 +1969,7 @@ void analyze_impl(mas_handle* h, const mas_problem* pr, bool dev = false, hipStr
   if (par.gram_schmidt != MAS_GS_CLASSICAL && par.gram_schmidt != MAS_GS_MODIFIED)
     throw MasError(MAS_EINVAL, "unknown gram_schmidt");
   if (par.full_patch_min < 1 || par.bucket_min < 1) throw MasError(MAS_EINVAL, "full_patch_min and bucket_min must be >= 1");
-  if (par.patch_kernel < 0 || par.patch_kernel > 4) throw MasError(MAS_EINVAL, "patch_kernel must be 0..4");
+  if (par.patch_kernel < 0 || par.patch_kernel > 5) throw MasError(MAS_EINVAL, "patch_kernel must be 0..5");
   std::vector<int64_t> free0, dir0, free1;
   std::vector<int8_t> f0, f1;
   int64_t nu0 = 0, np0 = 0;

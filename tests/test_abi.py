@@ -146,7 +146,7 @@ def test_analyze_rejects_bad_input():
         mas.Handle(P, mas.default_params(2, schedule=7), analyze_only=True)
     assert e.value.code == mas.MAS_EINVAL and "schedule" in str(e.value)
     with pytest.raises(mas.MasError) as e:
-        mas.Handle(P, mas.default_params(2, patch_kernel=5), analyze_only=True)
+        mas.Handle(P, mas.default_params(2, patch_kernel=6), analyze_only=True)
     assert e.value.code == mas.MAS_EINVAL and "patch_kernel" in str(e.value)
     h = mas.Handle(P, mp, analyze_only=True)
     with pytest.raises(mas.MasError):

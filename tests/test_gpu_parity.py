@@ -27,6 +27,8 @@ CASES = {
     "th24_lid": (dict(dim=2, n=24, jitter=0.2, seed=2, forcing="gaussian", bc="lid"), dict(max_coarse=40)),
     "th3d4": (dict(dim=3, n=4, forcing="smooth", bc="zero", seed=3), dict(max_coarse=40)),
     "th3d6_3lvl": (dict(dim=3, n=6, forcing="smooth", bc="zero", seed=3), dict(max_coarse=30)),
+    # coarse patches of ~105 rows per component: shared blocks too large for LDS, streamed in panels
+    "th3d8_big": (dict(dim=3, n=8, forcing="smooth", bc="zero", seed=3), dict(max_coarse=40)),
     "th16_skip1": (dict(dim=2, n=16, jitter=0.2, seed=5, forcing="gaussian", bc="lid"),
                    dict(max_coarse=30, schedule="skip1")),
     "th16_skip0": (dict(dim=2, n=16, jitter=0.2, seed=5, forcing="gaussian", bc="lid"),
@@ -118,28 +120,32 @@ def test_apply_fp64_matches_oracle(name):
 @pytest.mark.parametrize("name", ["th3d4", "th3d6_3lvl"])
 def test_full_block_levels_match_oracle(name):
     """Levels of very large patches store full velocity blocks; a lowered
-    threshold puts every 3D level of these cases on that path, single and
-    batched, FP64 and FP32."""
+    threshold puts every 3D level of these cases on that path (per-component
+    and shared blocks), single and batched, FP64 and FP32."""
     P, par, mp = build(name)
     mp.full_patch_min = 100
     pre = dc.DCPreconditioner(P, par)
     rng = np.random.default_rng(13)
     R = rng.standard_normal((P.n0, 3))
     refs = [pre.apply(R[:, k]) for k in range(3)]
-    for precision, tol in ((mas.MAS_FP64, 1e-11), (mas.MAS_FP32, 1e-5)):
-        mp.precision = precision
-        mp.nrhs_max = 3
-        h = mas.Handle(P, mp)
-        for nr in (1, 3):
-            Rd = torch.tensor(np.ascontiguousarray(R[:, :nr]), device=DEV)
-            Zd = torch.empty_like(Rd)
-            h.apply(Rd, Zd, nrhs=nr)
-            torch.cuda.synchronize()
-            Z = Zd.cpu().numpy().reshape(P.n0, nr)
-            for k in range(nr):
-                assert_parity(Z[:, k], refs[k], P.field0, tol, f"precision {precision} nrhs {nr} column {k}")
-        h.close()
+    for share in (1, 0):
+        for precision, tol in ((mas.MAS_FP64, 1e-11), (mas.MAS_FP32, 1e-5)):
+            mp.precision, mp.share_blocks = precision, share
+            mp.nrhs_max = 3
+            h = mas.Handle(P, mp)
+            assert all(v & 1 for v, npat in zip(h.info()["patch_layout"], h.info()["n_patches"]) if npat)
+            for nr in (1, 3):
+                Rd = torch.tensor(np.ascontiguousarray(R[:, :nr]), device=DEV)
+                Zd = torch.empty_like(Rd)
+                h.apply(Rd, Zd, nrhs=nr)
+                torch.cuda.synchronize()
+                Z = Zd.cpu().numpy().reshape(P.n0, nr)
+                for k in range(nr):
+                    assert_parity(Z[:, k], refs[k], P.field0, tol,
+                                  f"share {share} precision {precision} nrhs {nr} column {k}")
+            h.close()
     mp.nrhs_max = 1
+    mp.share_blocks = 1
 
 
 @pytest.mark.parametrize("name", ["th16_2lvl", "th24_lid", "th3d4", "th16_skip1", "th24_dlsc", "th3d4_dlsc",

@@ -41,6 +41,7 @@ def apply(h, R, nr):
     ("sv8_lid", {"bucket_min": 1}),     # 6/6/3-seed buckets
     ("th3d4", {}),
     ("th3d6_3lvl", {"full_patch_min": 100}),  # every 3D level stores full blocks
+    ("th3d8_big", {}),                  # coarse records too large for LDS: panels
     ("th16_ho", {}),
 ])
 def test_shared_and_per_component_layouts_match_oracle(name, over):
@@ -52,9 +53,9 @@ def test_shared_and_per_component_layouts_match_oracle(name, over):
     refs = [pre.apply(R[:, k]) for k in range(3)]
     mp.nrhs_max = 3
     # (share_blocks, patch_kernel): the workgroup kernel and the persistent
-    # pipelined one on both layouts, the shared-block wavefront kernel, the
-    # per-component column kernel
-    for share, kern in ((1, 1), (1, 3), (1, 4), (0, 1), (0, 2), (0, 4)):
+    # pipelined one on both layouts, the shared-block wavefront and panel
+    # kernels, the per-component column kernel
+    for share, kern in ((1, 1), (1, 3), (1, 4), (1, 5), (0, 1), (0, 2), (0, 4)):
         for precision, tol in ((mas.MAS_FP64, 1e-11), (mas.MAS_FP32, 1e-5)):
             mp.share_blocks, mp.patch_kernel, mp.precision = share, kern, precision
             h = mas.Handle(P, mp)
@@ -64,7 +65,8 @@ def test_shared_and_per_component_layouts_match_oracle(name, over):
                   f"{info['patch_layout']} kernels {info['patch_kernel']}", flush=True)
             assert relaxed and all(bool(info["patch_layout"][l] & SHARED) == bool(share) for l in relaxed)
             assert all(info["patch_kernel"][l] in (0, 1, kern) for l in relaxed)
-            if kern in (2, 3) and "full_patch_min" not in over:  # packed blocks: the kernel applies somewhere
+            if kern in (2, 3, 5) and (share or kern == 2) and "full_patch_min" not in over:
+                # packed blocks: the kernel applies somewhere
                 assert any(info["patch_kernel"][l] == kern for l in relaxed)
             for nr in (1, 3):
                 Z = apply(h, R, nr)
