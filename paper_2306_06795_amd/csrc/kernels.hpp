@@ -628,7 +628,8 @@ __global__ void __launch_bounds__(256) k_normalize_nr(int64_t n, int nr, const d
 // It yields the same Hessenberg column as modified Gram-Schmidt in exact
 // arithmetic with about half the vector traffic: all the dots in one sweep,
 // then one update.  k_cgs_dots_nr: part[(i * gridDim.x + b) * nr + k] = block
-// b's share of v_i(:, k) . w(:, k) for i < j1, 16 basis vectors per sweep of w.
+// b's share of v_i(:, k) . w(:, k), at most kCgsChunk basis vectors per sweep
+// of w.
 constexpr int kCgsChunk = 16;
 
 // Sum of v over the threads of a 256-thread block that hold column k = tid %
@@ -641,36 +642,34 @@ __device__ __forceinline__ void cgs_wave_part(double v, int nrp, double (*red)[4
   if (lane < nrp) red[u][wv][lane] = v;
 }
 
-__global__ void __launch_bounds__(256) k_cgs_dots_nr(int64_t n, int nr, int nrp, int j1, const double* __restrict__ V,
+// One chunk of NA basis vectors v_i0 .. v_{i0+NA-1} per launch (the width a
+// template argument, so the unrolled loop issues its NA loads together).
+template <int NA>
+__global__ void __launch_bounds__(256) k_cgs_dots_nr(int64_t n, int nr, int nrp, int i0, const double* __restrict__ V,
                                                     const double* __restrict__ w, double* __restrict__ part) {
-  __shared__ double red[kCgsChunk][4][64];
+  __shared__ double red[NA][4][64];
   const int k = threadIdx.x % nrp, g = threadIdx.x / nrp, ng = 256 / nrp;
   const bool col = k < nr;
   const int64_t stride = (int64_t)gridDim.x * ng, nn = n * nr;
-  for (int i0 = 0; i0 < j1; i0 += kCgsChunk) {
-    const int na = min(kCgsChunk, j1 - i0);
-    double acc[kCgsChunk];
+  const double* Vc = V + (int64_t)i0 * nn;
+  double acc[NA];
 #pragma unroll
-    for (int u = 0; u < kCgsChunk; ++u) acc[u] = 0.0;
-    if (col)
-      for (int64_t r = (int64_t)blockIdx.x * ng + g; r < n; r += stride) {
-        const int64_t e = r * nr + k;
-        const double we = w[e];
+  for (int u = 0; u < NA; ++u) acc[u] = 0.0;
+  if (col)
+    for (int64_t r = (int64_t)blockIdx.x * ng + g; r < n; r += stride) {
+      const int64_t e = r * nr + k;
+      const double we = w[e];
 #pragma unroll
-        for (int u = 0; u < kCgsChunk; ++u)
-          if (u < na) acc[u] += V[(int64_t)(i0 + u) * nn + e] * we;
-      }
-#pragma unroll
-    for (int u = 0; u < kCgsChunk; ++u)
-      if (u < na) cgs_wave_part(acc[u], nrp, red, u);
-    __syncthreads();
-    for (int t = threadIdx.x; t < na * nrp; t += 256) {
-      const int u = t / nrp, kk = t % nrp;
-      if (kk < nr)
-        part[((int64_t)(i0 + u) * gridDim.x + blockIdx.x) * nr + kk] =
-            red[u][0][kk] + red[u][1][kk] + red[u][2][kk] + red[u][3][kk];
+      for (int u = 0; u < NA; ++u) acc[u] += Vc[(int64_t)u * nn + e] * we;
     }
-    __syncthreads();
+#pragma unroll
+  for (int u = 0; u < NA; ++u) cgs_wave_part(acc[u], nrp, red, u);
+  __syncthreads();
+  for (int t = threadIdx.x; t < NA * nrp; t += 256) {
+    const int u = t / nrp, kk = t % nrp;
+    if (kk < nr)
+      part[((int64_t)(i0 + u) * gridDim.x + blockIdx.x) * nr + kk] =
+          red[u][0][kk] + red[u][1][kk] + red[u][2][kk] + red[u][3][kk];
   }
 }
 
@@ -686,33 +685,32 @@ __global__ void __launch_bounds__(64) k_cgs_final_nr(int nb, int nr, int j1, con
   if (threadIdx.x == 0) h[t] = s;
 }
 
-// w(:, k) -= sum_{i < j1} h[i * nr + k] v_i(:, k); partial_out[b * nr + k] = block
-// b's share of |w(:, k)|^2 (the layout k_normalize_nr reduces)
-__global__ void __launch_bounds__(256) k_cgs_update_nr(int64_t n, int nr, int nrp, int j1,
+// w(:, k) -= sum_{i0 <= i < i0 + NA} h[i * nr + k] v_i(:, k), one chunk per
+// launch; with last set, partial_out[b * nr + k] = block b's share of
+// |w(:, k)|^2 (the layout k_normalize_nr reduces)
+template <int NA>
+__global__ void __launch_bounds__(256) k_cgs_update_nr(int64_t n, int nr, int nrp, int i0, int last,
                                                       const double* __restrict__ V, const double* __restrict__ h,
                                                       double* __restrict__ w, double* __restrict__ partial_out) {
   __shared__ double red[1][4][64];
   const int k = threadIdx.x % nrp, g = threadIdx.x / nrp, ng = 256 / nrp;
   const bool col = k < nr;
   const int64_t stride = (int64_t)gridDim.x * ng, nn = n * nr;
+  const double* Vc = V + (int64_t)i0 * nn;
+  double hk[NA];
+#pragma unroll
+  for (int u = 0; u < NA; ++u) hk[u] = col ? h[(i0 + u) * nr + k] : 0.0;
   double s = 0.0;
-  for (int i0 = 0; i0 < j1; i0 += kCgsChunk) {
-    const int na = min(kCgsChunk, j1 - i0);
-    const bool last = i0 + kCgsChunk >= j1;
-    double hk[kCgsChunk];
+  if (col)
+    for (int64_t r = (int64_t)blockIdx.x * ng + g; r < n; r += stride) {
+      const int64_t e = r * nr + k;
+      double we = w[e];
 #pragma unroll
-    for (int u = 0; u < kCgsChunk; ++u) hk[u] = (col && u < na) ? h[(i0 + u) * nr + k] : 0.0;
-    if (col)
-      for (int64_t r = (int64_t)blockIdx.x * ng + g; r < n; r += stride) {
-        const int64_t e = r * nr + k;
-        double we = w[e];
-#pragma unroll
-        for (int u = 0; u < kCgsChunk; ++u)
-          if (u < na) we -= hk[u] * V[(int64_t)(i0 + u) * nn + e];
-        w[e] = we;
-        if (last) s += we * we;
-      }
-  }
+      for (int u = 0; u < NA; ++u) we -= hk[u] * Vc[(int64_t)u * nn + e];
+      w[e] = we;
+      s += we * we;
+    }
+  if (!last) return;  // uniform over the launch
   cgs_wave_part(s, nrp, red, 0);
   __syncthreads();
   if (threadIdx.x < nr)

@@ -1390,6 +1390,40 @@ Csr device_spgemm(const Csr& A, const Csr& B, hipStream_t s) {
   return C;
 }
 
+// Classical Gram-Schmidt of one Arnoldi step over the j1 basis vectors V
+// (nr interleaved columns): the dots in chunks of at most kCgsChunk vectors
+// (one launch per chunk, its width a template argument), their block sums,
+// then the update in the same chunks; the last chunk leaves the partial norms
+// of w in part_out.
+static void cgs_step(int64_t n, int nr, int nrp, int j1, const double* V, double* w, double* cpart, double* hdev,
+                     double* part_out, unsigned nb, hipStream_t s) {
+#define MAS_CGS_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+  for (int i0 = 0; i0 < j1; i0 += kCgsChunk) {
+    const int na = std::min(kCgsChunk, j1 - i0);
+    switch (na) {
+#define MAS_DOTS(NA) \
+  case NA: hipLaunchKernelGGL((k_cgs_dots_nr<NA>), dim3(nb), dim3(256), 0, s, n, nr, nrp, i0, V, w, cpart); break;
+      MAS_CGS_CASES(MAS_DOTS)
+#undef MAS_DOTS
+    }
+  }
+  hipLaunchKernelGGL(k_cgs_final_nr, dim3((unsigned)(j1 * nr)), dim3(64), 0, s, (int)nb, nr, j1, cpart, hdev);
+  for (int i0 = 0; i0 < j1; i0 += kCgsChunk) {
+    const int na = std::min(kCgsChunk, j1 - i0);
+    const int last = i0 + na >= j1 ? 1 : 0;
+    switch (na) {
+#define MAS_UPD(NA)                                                                                             \
+  case NA:                                                                                                      \
+    hipLaunchKernelGGL((k_cgs_update_nr<NA>), dim3(nb), dim3(256), 0, s, n, nr, nrp, i0, last, V, hdev, w, \
+                       part_out);                                                                               \
+    break;
+      MAS_CGS_CASES(MAS_UPD)
+#undef MAS_UPD
+    }
+  }
+#undef MAS_CGS_CASES
+}
+
 Csr device_galerkin(const Csr& P, const Csr& A, hipStream_t s) {
   return device_spgemm(transpose(P), device_spgemm(A, P, s), s);
 }
@@ -2342,10 +2376,7 @@ void inner_iteration(mas_handle* h, int j, hipStream_t s) {
     }
     pn = (j + 1) & 1;
   } else {  // classical Gram-Schmidt: every dot in one sweep, then one update
-    hipLaunchKernelGGL(k_cgs_dots_nr, dim3(h->nblk_dot), dim3(256), 0, s, n, 1, 1, j + 1, h->V, w, h->cpart);
-    hipLaunchKernelGGL(k_cgs_final_nr, dim3(j + 1), dim3(64), 0, s, h->nblk_dot, 1, j + 1, h->cpart, h->hdev);
-    hipLaunchKernelGGL(k_cgs_update_nr, dim3(h->nblk_dot), dim3(256), 0, s, n, 1, 1, j + 1, h->V, h->hdev, w,
-                       part[0]);
+    cgs_step(n, 1, 1, j + 1, h->V, w, h->cpart, h->hdev, part[0], (unsigned)h->nblk_dot, s);
   }
   hipLaunchKernelGGL(k_normalize<double>, dim3(h->nblk_dot), dim3(256), 0, s, n, part[pn], h->nblk_dot,
                      h->hdev + j + 1, w, h->V + (int64_t)(j + 1) * n);
@@ -2587,10 +2618,7 @@ int fgmres_nr(mas_handle* h, const double* b, double* x, int nr, const double* r
         }
         pn = (j + 1) & 1;
       } else {
-        hipLaunchKernelGGL(k_cgs_dots_nr, dim3(nb), dim3(256), 0, s, n, nr, nrp, j + 1, h->V, w, h->cpart);
-        hipLaunchKernelGGL(k_cgs_final_nr, dim3((unsigned)((j + 1) * nr)), dim3(64), 0, s, (int)nb, nr, j + 1,
-                           h->cpart, h->hdev);
-        hipLaunchKernelGGL(k_cgs_update_nr, dim3(nb), dim3(256), 0, s, n, nr, nrp, j + 1, h->V, h->hdev, w, part[0]);
+        cgs_step(n, nr, nrp, j + 1, h->V, w, h->cpart, h->hdev, part[0], (unsigned)nb, s);
       }
       hipLaunchKernelGGL(k_normalize_nr, dim3(nb), dim3(256), 0, s, n, nr, part[pn], (int)nb,
                          h->hdev + (size_t)(j + 1) * nr, w, h->V + (int64_t)(j + 1) * n * nr);
