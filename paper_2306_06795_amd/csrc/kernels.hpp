@@ -601,9 +601,11 @@ __global__ void __launch_bounds__(256) k_normalize_nr(int64_t n, int nr, const d
                                                      double* __restrict__ v) {
   __shared__ double nrm[64];
   __shared__ double sh[256];
+  // each thread keeps one column k (tid % nrp) for the whole kernel: no index
+  // division per element
+  const int nrp = nr <= 1 ? 1 : 1 << (32 - __clz(nr - 1));
+  const int k = threadIdx.x % nrp, g = threadIdx.x / nrp, ng = 256 / nrp;
   {  // the block's threads split the partial sums of each column
-    const int nrp = nr <= 1 ? 1 : 1 << (32 - __clz(nr - 1));
-    const int k = threadIdx.x % nrp, g = threadIdx.x / nrp, ng = 256 / nrp;
     double t = 0.0;
     if (k < nr)
       for (int b = g; b < nb; b += ng) t += partial[(int64_t)b * nr + k];
@@ -617,9 +619,12 @@ __global__ void __launch_bounds__(256) k_normalize_nr(int64_t n, int nr, const d
     }
     __syncthreads();
   }
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n * nr; t += (int64_t)gridDim.x * blockDim.x) {
-    const double q = nrm[t % nr];
-    v[t] = q != 0.0 ? w[t] / q : 0.0;
+  if (k >= nr) return;
+  const double q = nrm[k];
+  const int64_t stride = (int64_t)gridDim.x * ng;
+  for (int64_t r = (int64_t)blockIdx.x * ng + g; r < n; r += stride) {
+    const int64_t e = r * nr + k;
+    v[e] = q != 0.0 ? w[e] / q : 0.0;
   }
 }
 
