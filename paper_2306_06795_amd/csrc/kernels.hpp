@@ -1661,6 +1661,90 @@ __global__ void __launch_bounds__(256) k_vanka_tpp(int64_t P, int64_t Ppad, cons
   for (int s = 0; s < NS; ++s) Y[(int64_t)(NV + s) * Ppad + p] = yp[s];
 }
 
+// additive Vanka for a bucket of patches of one fixed shape with nr
+// right-hand sides: one wavefront per patch and one lane per right-hand side
+// (grid.y chunks of 64).  The record (interleaved across the bucket, element q
+// of patch p at q Ppad + p) is read with wave-uniform loads, b and y stay in
+// registers, and every gather and output row is one contiguous run of the
+// right-hand sides of a DoF.  The operations and their order are those of
+// k_vanka_tpp for each right-hand side.  Y: slot s of patch p at
+// (off[p] + s) nr + k.
+template <typename T, int N0, int N1, int N2, int NS, bool SH, int WPB>
+__global__ void __launch_bounds__(WPB * 64) k_vanka_rhs(int64_t P, int64_t Ppad, int nr, const int* __restrict__ dofs,
+                                                      const T* __restrict__ fac, const int64_t* __restrict__ off,
+                                                      const T* __restrict__ r, T* __restrict__ Y) {
+  constexpr int NV = N0 + N1 + N2, M = NV + NS;
+  static_assert(!SH || ((N1 == 0 || N1 == N0) && (N2 == 0 || N2 == N0)), "shared blocks need equal components");
+  constexpr int FA = SH ? N0 * (N0 + 1) / 2 : N0 * (N0 + 1) / 2 + N1 * (N1 + 1) / 2 + N2 * (N2 + 1) / 2;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int64_t p = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * WPB + threadIdx.x / WAVE));
+  if (p >= P) return;  // whole wavefronts
+  const int k = blockIdx.y * WAVE + lane;
+  const int kc = k < nr ? k : nr - 1;  // lanes past nr compute a copy and store nothing
+  const T* f = fac + p;
+  T b[M];
+#pragma unroll
+  for (int q = 0; q < M; ++q) b[q] = r[(int64_t)dofs[(int64_t)q * Ppad + p] * nr + kc];
+  T t[NS], yp[NS], y[NV];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) t[s] = b[NV + s];
+#pragma unroll
+  for (int s = 0; s < NS; ++s)
+#pragma unroll
+    for (int q = 0; q < NV; ++q) t[s] += f[(int64_t)(FA + s * NV + q) * Ppad] * b[q];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    T acc = 0;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+      const int a = s < q ? s : q, c = s < q ? q : s;
+      acc += f[(int64_t)(FA + NV * NS + c * (c + 1) / 2 + a) * Ppad] * t[q];
+    }
+    yp[s] = acc;
+  }
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    T acc = 0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) acc += f[(int64_t)(FA + s * NV + q) * Ppad] * yp[s];
+    y[q] = acc;
+  }
+  int e = 0;
+  if constexpr (SH) {
+    constexpr int NCO = NV / N0;
+#pragma unroll
+    for (int j = 0; j < N0; ++j)
+#pragma unroll
+      for (int i = 0; i <= j; ++i) {
+        const T a = f[(int64_t)(e++) * Ppad];
+#pragma unroll
+        for (int c = 0; c < NCO; ++c) {
+          y[c * N0 + i] += a * b[c * N0 + j];
+          if (i != j) y[c * N0 + j] += a * b[c * N0 + i];
+        }
+      }
+  } else {
+#define MAS_BLOCK_R(CS, N)                                 \
+  _Pragma("unroll") for (int j = 0; j < (N); ++j)          \
+    _Pragma("unroll") for (int i = 0; i <= j; ++i) {       \
+      const T a = f[(int64_t)(e++) * Ppad];                \
+      y[(CS) + i] += a * b[(CS) + j];                      \
+      if (i != j) y[(CS) + j] += a * b[(CS) + i];          \
+    }
+    MAS_BLOCK_R(0, N0)
+    MAS_BLOCK_R(N0, N1)
+    MAS_BLOCK_R(N0 + N1, N2)
+#undef MAS_BLOCK_R
+  }
+  if (k < nr) {
+    T* yo = Y + off[p] * nr + k;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) yo[(int64_t)q * nr] = y[q];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) yo[(int64_t)(NV + s) * nr] = yp[s];
+  }
+}
+
 // x[j] (+)= omega W_j sum of the patch values held for DoF j (deterministic
 // pull over the patch list in increasing patch order).
 template <typename T>

@@ -814,17 +814,44 @@ struct Cycle : CycleBase {
     hipEvent_t e0{}, e1{};
     if (nr > 1) {
       if (pt.nr_chunk < 1) throw MasError(MAS_EINVAL, "patches too large for the batched kernel");
-      int C = kNrKT;
-      while (C < nr && C < pt.nr_chunk) C *= 2;
-      const dim3 grid((unsigned)pt.np, (unsigned)((nr + C - 1) / C));
-      const size_t shm = nr_lds_bytes<T>(pt.max_m, C, pt.nr_stage ? pt.max_f : 0);
       if (timed) tm->begin(e0, e1, s);
-      if (pt.nr_stage)
-        hipLaunchKernelGGL((k_vanka_apply_nr<T, kNrKT, true>), grid, dim3(256), shm, s, pt.np, nr, C, pt.off, pt.dims,
-                           pt.foff, pt.fstride, pt.dofs, pt.fac, rin, pt.Ynr, pt.max_m, pt.max_f, pt.layout);
-      else
-        hipLaunchKernelGGL((k_vanka_apply_nr<T, kNrKT, false>), grid, dim3(256), shm, s, pt.np, nr, C, pt.off, pt.dims,
-                           pt.foff, pt.fstride, pt.dofs, pt.fac, rin, pt.Ynr, pt.max_m, pt.max_f, pt.layout);
+      // fixed-shape buckets: a wavefront per patch, a lane per right-hand side
+      int64_t start = 0;
+      constexpr int WPB = 4;
+      const bool sh = (pt.layout & LAYOUT_SHARED) != 0;
+      for (const FastBucket& fb : pt.fast) {
+        const dim3 gb((unsigned)((fb.P + WPB - 1) / WPB), (unsigned)((nr + WAVE - 1) / WAVE));
+        const T* f = pt.fac + fb.fbase;
+#define MAS_RHS(A, B, C2, D)                                                                                    \
+  if (fb.shape[0] == A && fb.shape[1] == B && fb.shape[2] == C2 && fb.shape[3] == D) {                        \
+    if (sh)                                                                                                    \
+      hipLaunchKernelGGL((k_vanka_rhs<T, A, B, C2, D, true, WPB>), gb, dim3(WPB * WAVE), 0, s, fb.P, fb.Ppad, nr, \
+                         fb.dofs, f, pt.off + start, rin, pt.Ynr);                                              \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_vanka_rhs<T, A, B, C2, D, false, WPB>), gb, dim3(WPB * WAVE), 0, s, fb.P, fb.Ppad,   \
+                         nr, fb.dofs, f, pt.off + start, rin, pt.Ynr);                                          \
+  } else
+        MAS_FAST_SHAPES(MAS_RHS) { throw MasError(MAS_EINVAL, "unknown patch bucket shape"); }
+#undef MAS_RHS
+        start += fb.P;
+      }
+      // the other patches: a workgroup per patch and chunk of right-hand sides
+      const int64_t ng = pt.np - pt.g0;
+      if (ng > 0) {
+        int C = kNrKT;
+        while (C < nr && C < pt.nr_chunk) C *= 2;
+        const dim3 grid((unsigned)ng, (unsigned)((nr + C - 1) / C));
+        const size_t shm = nr_lds_bytes<T>(pt.max_m, C, pt.nr_stage ? pt.max_f : 0);
+        const int64_t g0 = pt.g0;
+        if (pt.nr_stage)
+          hipLaunchKernelGGL((k_vanka_apply_nr<T, kNrKT, true>), grid, dim3(256), shm, s, ng, nr, C, pt.off + g0,
+                             pt.dims + g0, pt.foff + g0, pt.fstride + g0, pt.dofs, pt.fac, rin, pt.Ynr, pt.max_m,
+                             pt.max_f, pt.layout);
+        else
+          hipLaunchKernelGGL((k_vanka_apply_nr<T, kNrKT, false>), grid, dim3(256), shm, s, ng, nr, C, pt.off + g0,
+                             pt.dims + g0, pt.foff + g0, pt.fstride + g0, pt.dofs, pt.fac, rin, pt.Ynr, pt.max_m,
+                             pt.max_f, pt.layout);
+      }
       launch_check();
       if (timed) tm->end(e0, e1, s, patch_bytes(L, (double)pt.nfac_alg, (double)pt.ndofs), TK_BATCHED);
       return;
