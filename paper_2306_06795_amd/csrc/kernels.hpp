@@ -475,12 +475,14 @@ __global__ void __launch_bounds__(256) k_vanka_apply_nr(int64_t np, int nr, int 
 
 // x[j, k] (+)= omega / count_j * sum of the patch values held for DoF j (slot-major map)
 template <typename T>
-__global__ void k_vanka_pull_ell_nr(int n, int nr, int width, const int* __restrict__ pos, const T* __restrict__ Y,
-                                    T omega, T* __restrict__ x, int accumulate) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)n * nr) return;
-  const int64_t j = t / nr;
-  const int k = (int)(t % nr);
+__global__ void __launch_bounds__(256) k_vanka_pull_ell_nr(int n, int nr, int nrp, int width,
+                                                           const int* __restrict__ pos, const T* __restrict__ Y,
+                                                           T omega, T* __restrict__ x, int accumulate) {
+  // thread (DoF j, right-hand side k): k = tid % nrp for the whole kernel
+  const int k = threadIdx.x % nrp, g = threadIdx.x / nrp, ng = 256 / nrp;
+  const int64_t j = (int64_t)blockIdx.x * ng + g;
+  if (j >= n || k >= nr) return;
+  const int64_t t = j * nr + k;
   T acc = 0;
   int cnt = 0;
   int s = 0;
@@ -513,17 +515,31 @@ __global__ void k_vanka_pull_ell_nr(int n, int nr, int width, const int* __restr
   x[t] = accumulate ? x[t] + v : v;
 }
 
-// x[j, k] (+)= omega W_j sum ... (CSR map)
+// x[j, k] (+)= omega W_j sum ... (CSR map); thread (DoF j, right-hand side k),
+// the patch values of a DoF gathered four at a time (summed in map order)
 template <typename T>
-__global__ void k_vanka_pull_nr(int n, int nr, const int* __restrict__ inv_ptr, const int* __restrict__ inv_pos,
-                                const T* __restrict__ Y, const T* __restrict__ w, T omega, T* __restrict__ x,
-                                int accumulate) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)n * nr) return;
-  const int64_t j = t / nr;
-  const int k = (int)(t % nr);
+__global__ void __launch_bounds__(256) k_vanka_pull_nr(int n, int nr, int nrp, const int* __restrict__ inv_ptr,
+                                                       const int* __restrict__ inv_pos, const T* __restrict__ Y,
+                                                       const T* __restrict__ w, T omega, T* __restrict__ x,
+                                                       int accumulate) {
+  const int k = threadIdx.x % nrp, g = threadIdx.x / nrp, ng = 256 / nrp;
+  const int64_t j = (int64_t)blockIdx.x * ng + g;
+  if (j >= n || k >= nr) return;
+  const int64_t t = j * nr + k;
+  const int q1 = inv_ptr[j + 1];
+  int q = inv_ptr[j];
   T acc = 0;
-  for (int q = inv_ptr[j]; q < inv_ptr[j + 1]; ++q) acc += Y[(int64_t)inv_pos[q] * nr + k];
+  for (; q + 3 < q1; q += 4) {
+    int pq[4];
+    T v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) pq[u] = inv_pos[q + u];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = Y[(int64_t)pq[u] * nr + k];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc += v[u];
+  }
+  for (; q < q1; ++q) acc += Y[(int64_t)inv_pos[q] * nr + k];
   const T v = omega * w[j] * acc;
   x[t] = accumulate ? x[t] + v : v;
 }

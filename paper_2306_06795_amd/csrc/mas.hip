@@ -1095,12 +1095,13 @@ struct Cycle : CycleBase {
   // x (+)= omega W sum of the patch outputs, per DoF (acc = 0: overwrite)
   void pull(Level<T>& L, T omega, T* x, int acc, hipStream_t s) {
     if (nr > 1) {
-      const unsigned nb = blocks_for(L.n * nr, 256);
+      const int nrp = nr <= 1 ? 1 : 1 << (32 - __builtin_clz((unsigned)nr - 1));  // columns per block row
+      const unsigned nb = blocks_for(L.n, 256 / nrp);
       if (L.pt.ell_c)
-        hipLaunchKernelGGL((k_vanka_pull_ell_nr<T>), dim3(nb), dim3(256), 0, s, (int)L.n, nr, L.pt.ell_width,
+        hipLaunchKernelGGL((k_vanka_pull_ell_nr<T>), dim3(nb), dim3(256), 0, s, (int)L.n, nr, nrp, L.pt.ell_width,
                            L.pt.ell_c, L.pt.Ynr, omega, x, acc);
       else
-        hipLaunchKernelGGL((k_vanka_pull_nr<T>), dim3(nb), dim3(256), 0, s, (int)L.n, nr, L.pt.inv_ptr_c,
+        hipLaunchKernelGGL((k_vanka_pull_nr<T>), dim3(nb), dim3(256), 0, s, (int)L.n, nr, nrp, L.pt.inv_ptr_c,
                            L.pt.inv_pos_c, L.pt.Ynr, L.pt.w, omega, x, acc);
     } else if (L.pt.ell) {
       hipLaunchKernelGGL((k_vanka_pull_ell<T>), dim3(blocks_for(L.n, 256)), dim3(256), 0, s, (int)L.n,
