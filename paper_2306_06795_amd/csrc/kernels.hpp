@@ -315,14 +315,18 @@ __global__ void k_copy_idx_nr(int64_t n, int nr, const int64_t* __restrict__ idx
 // Y = A X for nr interleaved right-hand sides (CSR): one thread per (row, rhs);
 // the threads of a row read the same matrix entries and contiguous X rows.
 template <typename T, int MODE>
-__global__ void __launch_bounds__(256) k_spmm(int64_t n, int nr, const int* __restrict__ ptr,
+__global__ void __launch_bounds__(256) k_spmm(int64_t n, int nr, int nrp, const int* __restrict__ ptr,
                                               const int* __restrict__ ind, const T* __restrict__ val,
                                               const T* __restrict__ x, const T* __restrict__ b,
                                               T* __restrict__ y, ChebStep<T> cs) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n * nr) return;
-  const int64_t row = t / nr;
-  const int k = (int)(t % nr);
+  // thread (row, right-hand side k), k = tid % nrp for the whole kernel; with
+  // nrp = 64 a wavefront holds one row, whose indices and values it then
+  // reads with wave-uniform loads
+  const int k = threadIdx.x % nrp, g = threadIdx.x / nrp, ng = 256 / nrp;
+  int64_t row = (int64_t)blockIdx.x * ng + g;
+  if (nrp == WAVE) row = __builtin_amdgcn_readfirstlane((int)row);
+  if (row >= n || k >= nr) return;
+  const int64_t t = row * nr + k;
   T s = 0;
   int e = ptr[row];
   const int end = ptr[row + 1];

@@ -60,6 +60,8 @@ inline void launch_check() {
 }
 
 inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+// smallest power of two >= nr (columns of a block row in the kernels over nr right-hand sides)
+inline int nr_pow2(int nr) { return nr <= 1 ? 1 : 1 << (32 - __builtin_clz((unsigned)nr - 1)); }
 
 constexpr size_t kMaxLds = 64 * 1024;  // dynamic LDS per workgroup used by the patch kernels
 // operators and factor stores from this size on are read with non-temporal loads
@@ -593,7 +595,7 @@ struct Cycle : CycleBase {
     if (nr == 1) {
       csr_launch<T, MODE>(A, x, b, y, s, cs);
     } else if (A.n > 0) {
-      hipLaunchKernelGGL((k_spmm<T, MODE>), dim3(blocks_for(A.n * nr, 256)), dim3(256), 0, s, A.n, nr, A.ptr, A.ind,
+      hipLaunchKernelGGL((k_spmm<T, MODE>), dim3(blocks_for(A.n, 256 / nr_pow2(nr))), dim3(256), 0, s, A.n, nr, nr_pow2(nr), A.ptr, A.ind,
                          A.val, x, b, y, cs);
       launch_check();
     }
@@ -2577,7 +2579,7 @@ int fgmres_nr(mas_handle* h, const double* b, double* x, int nr, const double* r
     for (int k = 0; k < nr; ++k) h->hhost[k] = fresh[k] ? 0.0 : 1.0;
     HIPCHECK(hipMemcpyAsync(h->hdev, h->hhost, nr * sizeof(double), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_scale_cols_inplace, dim3(blocks_for(n * nr, 256)), dim3(256), 0, s, n, nr, h->hdev, x);
-    hipLaunchKernelGGL((k_spmm<double, 1>), dim3(blocks_for(n * nr, 256)), dim3(256), 0, s, n, nr, h->K0full.ptr,
+    hipLaunchKernelGGL((k_spmm<double, 1>), dim3(blocks_for(n, 256 / nr_pow2(nr))), dim3(256), 0, s, n, nr, nr_pow2(nr), h->K0full.ptr,
                        h->K0full.ind, h->K0full.val, x, b, r, ChebStep<double>{});
     launch_check();
   }
@@ -2631,7 +2633,7 @@ int fgmres_nr(mas_handle* h, const double* b, double* x, int nr, const double* r
       double* zj = h->Z + (int64_t)j * n * nr;
       h->cyc->apply(vj, zj, s);
       double* w = h->w;
-      hipLaunchKernelGGL((k_spmm<double, 0>), dim3(blocks_for(n * nr, 256)), dim3(256), 0, s, n, nr, h->K0full.ptr,
+      hipLaunchKernelGGL((k_spmm<double, 0>), dim3(blocks_for(n, 256 / nr_pow2(nr))), dim3(256), 0, s, n, nr, nr_pow2(nr), h->K0full.ptr,
                          h->K0full.ind, h->K0full.val, zj, nullptr, w, ChebStep<double>{});
       double* part[2] = {h->partial, h->partial + (size_t)nb * nr};
       int pn = 0;
@@ -2713,7 +2715,7 @@ int fgmres_nr(mas_handle* h, const double* b, double* x, int nr, const double* r
     std::memcpy(h->hhost, y.data(), y.size() * sizeof(double));
     HIPCHECK(hipMemcpyAsync(h->ydev, h->hhost, y.size() * sizeof(double), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_update_x_nr, dim3(blocks_for(n * nr, 256)), dim3(256), 0, s, n, nr, kk, h->Z, h->ydev, x);
-    hipLaunchKernelGGL((k_spmm<double, 1>), dim3(blocks_for(n * nr, 256)), dim3(256), 0, s, n, nr, h->K0full.ptr,
+    hipLaunchKernelGGL((k_spmm<double, 1>), dim3(blocks_for(n, 256 / nr_pow2(nr))), dim3(256), 0, s, n, nr, nr_pow2(nr), h->K0full.ptr,
                        h->K0full.ind, h->K0full.val, x, b, r, ChebStep<double>{});
     launch_check();
     col_norms(r, beta);
