@@ -170,8 +170,9 @@ typedef struct {
                              groups take the generic patch kernels */
   int32_t factor_blocked; /* 1: blocked Gauss-Jordan for patch blocks whose panel fits in LDS;
                              0: single-pivot Gauss-Jordan everywhere */
-  int32_t device_galerkin;/* 1: the Galerkin products of Algorithm 1 run on the device (same
-                             values as the host's, bit for bit); 0: on the host */
+  int32_t device_galerkin;/* 1 (default): in mas_setup the Galerkin products of the level
+                             operators (Algorithm 1) run on the device (same values as the host's,
+                             bit for bit); 0: on the host */
   int32_t share_blocks;   /* 1: a level whose patches have identical velocity blocks in every
                              component (the vector Laplacian with the same boundary conditions on
                              each component, Section 2; checked bit for bit by the analysis)
@@ -189,6 +190,18 @@ typedef struct {
                              or components above 128 rows; 3: blocks not shared, full, or above
                              128 rows; 4: records that do not fit in LDS or exceed 16 values per
                              thread; 5: blocks not shared or above 1024 rows) uses 1 */
+  int32_t device_sa;      /* 1: Algorithm 1's per-field smoothed aggregation runs on the device
+                             with each level operator resident there: the Gershgorin bound, the
+                             strength of connection (Section 3.2), the smoothed prolongator and the
+                             field's Galerkin product; the strength graph goes to the host, whose
+                             greedy aggregation (sequential by definition) returns the aggregates
+                             and the tentative prolongator's values; the finished prolongators come
+                             back as the hierarchy's output.  The same hierarchy as the host's, bit
+                             for bit.  Default 1; mas_analyze, which has no device, and 0: on the host */
+  int32_t spgemm_cap;     /* 0: the device sparse products of the setup keep up to 1536 distinct
+                             columns of a row in LDS and take longer rows through a global-memory
+                             kernel; k > 0: at most min(k, 1536) in LDS (a test of the long-row
+                             path) */
 } mas_params;
 
 typedef struct {

@@ -2338,7 +2338,7 @@ __global__ void k_update_x(int64_t n, int k, const T* __restrict__ Z, const doub
 // give the same bits.  PASS 0 counts the distinct columns of each row into cnt;
 // PASS 1 writes them, sorted, from Cp[i].  A row with more than `cap` distinct
 // columns (cap <= kSpgSlots * 3 / 4) gets over[i] = 1 in PASS 0 and is left to
-// the host.
+// the host product or to k_spgemm_dense.
 constexpr int kSpgSlots = 2048;
 
 template <int PASS>
@@ -2356,7 +2356,18 @@ __global__ void __launch_bounds__(64) k_spgemm_row(int64_t n, const int64_t* __r
   const int lane = threadIdx.x;
   if (i >= n) return;  // uniform over the workgroup
   if (PASS == 1 && over[i]) return;
-  for (int t = lane; t < kSpgSlots; t += 64) key[t] = -1;
+  // a table of at least twice the row's product count (the summed lengths of
+  // the rows of B it meets), 64 to kSpgSlots slots
+  int64_t bound = 0;
+  for (int64_t a = Ap[i] + lane; a < Ap[i + 1]; a += 64) {
+    const int k = Ai[a];
+    bound += Bp[k + 1] - Bp[k];
+  }
+  for (int o = 32; o > 0; o >>= 1) bound += __shfl_xor(bound, o, 64);
+  int tbits = 6;
+  while (tbits < 11 && ((int64_t)1 << tbits) < 2 * bound) ++tbits;
+  const int tsize = 1 << tbits;
+  for (int t = lane; t < tsize; t += 64) key[t] = -1;
   if (lane == 0) {
     nkeys = 0;
     full = 0;
@@ -2368,8 +2379,8 @@ __global__ void __launch_bounds__(64) k_spgemm_row(int64_t n, const int64_t* __r
     for (int64_t b = Bp[k] + lane; b < Bp[k + 1]; b += 64) {
       const int j = Bi[b];
       const double pr = av * Bv[b];
-      unsigned h = ((unsigned)j * 2654435761u) >> 21;  // top 11 bits: a slot in [0, 2048)
-      for (int probe = 0; probe < kSpgSlots; ++probe, h = (h + 1) & (kSpgSlots - 1)) {
+      unsigned h = ((unsigned)j * 2654435761u) >> (32 - tbits);  // top tbits bits: a slot in [0, tsize)
+      for (int probe = 0; probe < tsize; ++probe, h = (h + 1) & (tsize - 1)) {
         const int old = atomicCAS(&key[h], -1, j);
         if (old == -1) {  // new column
           val[h] = pr;
@@ -2392,19 +2403,348 @@ __global__ void __launch_bounds__(64) k_spgemm_row(int64_t n, const int64_t* __r
     }
     return;
   }
-  // PASS 1: rank of each column among the row's columns gives its position
-  const int64_t base = Cp[i], m = Cp[i + 1] - Cp[i];
-  for (int t = lane; t < kSpgSlots; t += 64) {
+  // PASS 1: the occupied slots packed to the front of the table in slot order
+  // (a slot moves only to a lower index, after every lane has read its own),
+  // then each column's rank among the row's columns gives its position
+  int nk = 0;
+  for (int t0 = 0; t0 < tsize; t0 += 64) {
+    const int t = t0 + lane;
     const int j = key[t];
-    if (j < 0) continue;
-    int r = 0;
-    for (int u = 0; u < kSpgSlots; ++u) {
-      const int q = key[u];
-      r += (q >= 0 && q < j) ? 1 : 0;
+    const double v = val[t];
+    const unsigned long long bal = __ballot(j >= 0);
+    const int pos = nk + __popcll(bal & ((1ull << lane) - 1ull));
+    __syncthreads();
+    if (j >= 0) {
+      key[pos] = j;
+      val[pos] = v;
     }
+    nk += __popcll(bal);
+    __syncthreads();
+  }
+  const int64_t base = Cp[i], m = Cp[i + 1] - Cp[i];
+  for (int q = lane; q < nk; q += 64) {
+    const int j = key[q];
+    int r = 0;
+    for (int u = 0; u < nk; ++u) r += key[u] < j ? 1 : 0;
     if (r < m) {
       Ci[base + r] = j;
-      Cv[base + r] = val[t];
+      Cv[base + r] = val[q];
+    }
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// Smoothed aggregation on the device (Algorithm 1, Section 3.2).  Each value
+// below is formed with the operations, and in the order, of the host setup,
+// with no contraction of products into fused multiply-adds, so the device
+// hierarchy equals the host's bit for bit.
+
+// d_i = a_ii and the Gershgorin ratio (sum_j |a_ij|, in row order) / a_ii of
+// each row; a thread per row.
+__global__ void k_sa_diag(int64_t n, const int64_t* __restrict__ Ap, const int* __restrict__ Ai,
+                          const double* __restrict__ Av, double* __restrict__ d, double* __restrict__ ratio) {
+#pragma clang fp contract(off)
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double di = 0.0, s = 0.0;
+  for (int64_t e = Ap[i]; e < Ap[i + 1]; ++e) {
+    const double v = Av[e];
+    if (Ai[e] == i) di = v;
+    s += fabs(v);
+  }
+  d[i] = di;
+  ratio[i] = s / di;
+}
+
+// Per-workgroup maxima of x (starting from 0; a NaN is never taken), for the
+// Gershgorin bound max_i ratio_i.  256 threads.
+__global__ void __launch_bounds__(256) k_sa_max(int64_t n, const double* __restrict__ x, double* __restrict__ part) {
+  __shared__ double red[256];
+  double r = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const double v = x[i];
+    r = (r < v) ? v : r;
+  }
+  red[threadIdx.x] = r;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      const double v = red[threadIdx.x + w];
+      red[threadIdx.x] = (red[threadIdx.x] < v) ? v : red[threadIdx.x];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// Symmetric strength: keep[e] for j != i with a_ij^2 >= th2 (a_ii a_jj); a
+// thread per row.
+__global__ void k_sa_soc_sym(int64_t n, const int64_t* __restrict__ Ap, const int* __restrict__ Ai,
+                             const double* __restrict__ Av, const double* __restrict__ d, double th2,
+                             unsigned char* __restrict__ keep) {
+#pragma clang fp contract(off)
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double di = d[i];
+  for (int64_t e = Ap[i]; e < Ap[i + 1]; ++e) {
+    const int j = Ai[e];
+    const double v = Av[e];
+    keep[e] = (j != i && v * v >= th2 * (di * d[j])) ? 1 : 0;
+  }
+}
+
+// Evolution strength, two steps of J = I - dt D^-1 A (Section 3.2): a
+// wavefront per row i.  For each stored (i, r), z_i[r] = sum_m J[r][m] J[m][i]
+// over row r of A in ascending m, taking the m for which a_mi is stored (found
+// by a binary search of column i in the sorted row m), which is the host's
+// sum term for term.  Then, with zt = z_i[i] B_r / B_i,
+//   s_ir = max(|zt - z_i[r]| / |z_i[r]|, 1e-4) where z_i[r] != 0 and
+//   zt z_i[r] > 0, infinite otherwise,
+// and row i keeps r != i with a finite s_ir <= eps min_m s_im.  z holds one
+// value per stored entry of A (scratch, the lane of an entry reads only what
+// it wrote).
+__global__ void __launch_bounds__(64) k_sa_soc_evol(int64_t n, const int64_t* __restrict__ Ap,
+                                                    const int* __restrict__ Ai, const double* __restrict__ Av,
+                                                    const double* __restrict__ d, const double* __restrict__ B,
+                                                    double dt, double eps, double* __restrict__ z,
+                                                    unsigned char* __restrict__ keep) {
+#pragma clang fp contract(off)
+  __shared__ double zii_s;
+  __shared__ int has_diag;
+  const int64_t i = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (i >= n) return;  // uniform over the workgroup
+  const int64_t e0 = Ap[i], e1 = Ap[i + 1];
+  auto jv = [&](int64_t r, int64_t c, double a) { return (r == c ? 1.0 : 0.0) - dt * ((1.0 / d[r]) * a); };
+  auto zcol = [&](int64_t r) {
+    double acc = 0.0;
+    for (int64_t f = Ap[r]; f < Ap[r + 1]; ++f) {
+      const int m = Ai[f];
+      int64_t lo = Ap[m], hi = Ap[m + 1];
+      const int64_t end = hi;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (Ai[mid] < i) lo = mid + 1;
+        else hi = mid;
+      }
+      if (lo < end && Ai[lo] == i) acc += jv(r, m, Av[f]) * jv(m, i, Av[lo]);
+    }
+    return acc;
+  };
+  if (lane == 0) has_diag = 0;
+  __syncthreads();
+  for (int64_t e = e0 + lane; e < e1; e += 64) {
+    const int r = Ai[e];
+    const double zr = zcol(r);
+    z[e] = zr;
+    if (r == i) {
+      zii_s = zr;
+      has_diag = 1;
+    }
+  }
+  __syncthreads();
+  if (!has_diag) {
+    if (lane == 0) zii_s = zcol(i);
+    __syncthreads();
+  }
+  const double zii = zii_s, bi = B[i];
+  double smin = INFINITY;
+  for (int64_t e = e0 + lane; e < e1; e += 64) {
+    const int j = Ai[e];
+    double s = INFINITY;
+    if (j != i) {
+      const double zij = z[e];
+      const double zt = zii * B[j] / bi;
+      if (zij != 0.0 && zt * zij > 0.0) {
+        const double q = fabs(zt - zij) / fabs(zij);
+        s = (q < 1e-4) ? 1e-4 : q;
+      }
+      smin = (s < smin) ? s : smin;
+    }
+    z[e] = s;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const double v = __shfl_xor(smin, o, 64);
+    smin = (v < smin) ? v : smin;
+  }
+  const double lim = eps * smin;
+  for (int64_t e = e0 + lane; e < e1; e += 64) {
+    const double s = z[e];
+    keep[e] = (Ai[e] != i && isfinite(s) && s <= lim) ? 1 : 0;
+  }
+}
+
+// Kept entries per row (PASS 0: counts into cnt) and their columns in row
+// order (PASS 1: from Sp[i]); a thread per row.
+template <int PASS>
+__global__ void k_sa_select(int64_t n, const int64_t* __restrict__ Ap, const int* __restrict__ Ai,
+                            const unsigned char* __restrict__ keep, int64_t* __restrict__ cnt,
+                            const int64_t* __restrict__ Sp, int* __restrict__ Si) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int64_t c = PASS == 1 ? Sp[i] : 0;
+  for (int64_t e = Ap[i]; e < Ap[i + 1]; ++e)
+    if (keep[e]) {
+      if (PASS == 1) Si[c] = Ai[e];
+      ++c;
+    }
+  if (PASS == 0) cnt[i] = c;
+}
+
+// Union of two sorted patterns row by row (S1 and its transpose): PASS 0
+// counts, PASS 1 writes from Sp[i]; a thread per row.
+template <int PASS>
+__global__ void k_sa_union(int64_t n, const int64_t* __restrict__ Xp, const int* __restrict__ Xi,
+                           const int64_t* __restrict__ Yp, const int* __restrict__ Yi, int64_t* __restrict__ cnt,
+                           const int64_t* __restrict__ Sp, int* __restrict__ Si) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int64_t a = Xp[i], b = Yp[i];
+  const int64_t ae = Xp[i + 1], be = Yp[i + 1];
+  int64_t o = PASS == 1 ? Sp[i] : 0;
+  while (a < ae || b < be) {
+    int v;
+    if (b >= be || (a < ae && Xi[a] < Yi[b])) v = Xi[a++];
+    else if (a >= ae || Yi[b] < Xi[a]) v = Yi[b++];
+    else {
+      v = Xi[a++];
+      ++b;
+    }
+    if (PASS == 1) Si[o] = v;
+    ++o;
+  }
+  if (PASS == 0) cnt[i] = o;
+}
+
+// D^-1 A: each a_ij / a_ii; a thread per row.
+__global__ void k_sa_scale(int64_t n, const int64_t* __restrict__ Ap, const double* __restrict__ Av,
+                           const double* __restrict__ d, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double di = d[i];
+  for (int64_t e = Ap[i]; e < Ap[i + 1]; ++e) out[e] = Av[e] / di;
+}
+
+// The smoothed prolongator from (D^-1 A) T: p_iJ = -omega [(D^-1 A) T]_iJ,
+// plus t_i where J is the aggregate of i; a thread per row.
+__global__ void k_sa_smooth(int64_t n, const int64_t* __restrict__ Pp, const int* __restrict__ Pi,
+                            double* __restrict__ Pv, const int* __restrict__ agg, const double* __restrict__ tv,
+                            double omega) {
+#pragma clang fp contract(off)
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int ai = agg[i];
+  for (int64_t e = Pp[i]; e < Pp[i + 1]; ++e) {
+    double v = -omega * Pv[e];
+    if (Pi[e] == ai) v += tv[i];
+    Pv[e] = v;
+  }
+}
+
+// Row index of every stored entry (for the transpose); a thread per row.
+__global__ void k_sa_rows(int64_t n, const int64_t* __restrict__ Ap, int* __restrict__ row) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int64_t e = Ap[i]; e < Ap[i + 1]; ++e) row[e] = (int)i;
+}
+
+// 0, 1, ..., n - 1.
+__global__ void k_sa_iota(int64_t n, int* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (int)i;
+}
+__global__ void k_sa_iota64(int64_t n, int64_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = i;
+}
+
+// Entries per column (the transpose's row lengths); a thread per entry.
+__global__ void k_sa_colcount(int64_t nnz, const int* __restrict__ Ai, unsigned long long* __restrict__ cnt) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nnz) atomicAdd(&cnt[Ai[e]], 1ull);
+}
+
+// Transpose entries from the stable sort by column of the entry numbers:
+// entry p of A^T is entry perm[p] of A (rows ascend within each column, as in
+// the host's transpose).
+__global__ void k_sa_gather(int64_t nnz, const int* __restrict__ perm, const int* __restrict__ row,
+                            const double* __restrict__ Av, int* __restrict__ Ti, double* __restrict__ Tv) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nnz) return;
+  const int e = perm[p];
+  Ti[p] = row[e];
+  if (Tv) Tv[p] = Av[e];
+}
+
+// C = A B for the rows k_spgemm_row leaves (over[i]: more distinct columns
+// than its LDS table holds), a workgroup per such row, rows spread over the
+// grid.  Each workgroup accumulates in its own dense slice (acc, mark) of B.nc
+// entries in global memory; as in k_spgemm_row the entries of A's row are
+// taken in order and the lanes add a_ik b_kj for distinct j of one row of B,
+// so every c_ij is summed in the host's order.  mark holds 2 i + PASS for a
+// column met in row i's pass.  PASS 0 writes the counts; PASS 1 the sorted
+// columns and values from Cp[i] (a block scan of the marks).
+template <int PASS>
+__global__ void __launch_bounds__(256) k_spgemm_dense(int64_t n, const int64_t* __restrict__ Ap,
+                                                      const int* __restrict__ Ai, const double* __restrict__ Av,
+                                                      const int64_t* __restrict__ Bp, const int* __restrict__ Bi,
+                                                      const double* __restrict__ Bv, int64_t nc,
+                                                      const int* __restrict__ over, double* __restrict__ acc_all,
+                                                      int64_t* __restrict__ mark_all, int64_t* __restrict__ cnt,
+                                                      const int64_t* __restrict__ Cp, int* __restrict__ Ci,
+                                                      double* __restrict__ Cv) {
+#pragma clang fp contract(off)
+  __shared__ unsigned long long count;
+  __shared__ int wsum[4];
+  double* acc = acc_all + (int64_t)blockIdx.x * nc;
+  int64_t* mark = mark_all + (int64_t)blockIdx.x * nc;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+    if (!over[i]) continue;  // uniform over the workgroup
+    const int64_t stamp = 2 * i + PASS;
+    if (tid == 0) count = 0;
+    __syncthreads();
+    for (int64_t a = Ap[i]; a < Ap[i + 1]; ++a) {
+      const int k = Ai[a];
+      const double av = Av[a];
+      for (int64_t b = Bp[k] + tid; b < Bp[k + 1]; b += 256) {
+        const int j = Bi[b];
+        const double pr = av * Bv[b];
+        if (mark[j] != stamp) {
+          mark[j] = stamp;
+          acc[j] = pr;
+          if (PASS == 0) atomicAdd(&count, 1ull);
+        } else {
+          acc[j] = acc[j] + pr;
+        }
+      }
+      __syncthreads();
+    }
+    if (PASS == 0) {
+      if (tid == 0) cnt[i] = (int64_t)count;
+      __syncthreads();
+      continue;
+    }
+    int64_t o = Cp[i];
+    for (int64_t j0 = 0; j0 < nc; j0 += 256) {
+      const int64_t j = j0 + tid;
+      const bool f = j < nc && mark[j] == stamp;
+      const unsigned long long bal = __ballot(f);
+      const int before = __popcll(bal & ((1ull << lane) - 1ull));
+      if (lane == 0) wsum[wave] = __popcll(bal);
+      __syncthreads();
+      int off = 0, tot = 0;
+      for (int w = 0; w < 4; ++w) {
+        off += w < wave ? wsum[w] : 0;
+        tot += wsum[w];
+      }
+      if (f) {
+        Ci[o + off + before] = (int)j;
+        Cv[o + off + before] = acc[j];
+      }
+      o += tot;
+      __syncthreads();
     }
   }
 }

@@ -12,6 +12,7 @@
 #include <climits>
 #include <cstring>
 #include <functional>
+#include <future>
 #include <mutex>
 #include <memory>
 #include <numeric>
@@ -23,6 +24,8 @@
 #include "../../include/mas.h"
 #include "host.hpp"
 #include "kernels.hpp"
+
+#include <hipcub/hipcub.hpp>
 
 using namespace mas;
 
@@ -1360,7 +1363,14 @@ struct SetupTrace {
 // the host product.  Rows whose distinct columns overflow the kernel's LDS
 // table are computed on the host.  Host matrices in and out; the device
 // buffers live only for the call.
-Csr device_spgemm(const Csr& A, const Csr& B, hipStream_t s) {
+// The LDS table's row capacity of the device sparse products: at most
+// min(cap, 3/4 of the table) distinct columns (cap <= 0: no extra limit).
+static int spgemm_table_cap(int cap) {
+  const int full = kSpgSlots * 3 / 4;
+  return cap > 0 ? std::min(cap, full) : full;
+}
+
+Csr device_spgemm(const Csr& A, const Csr& B, hipStream_t s, int cap_limit) {
   if (A.nc != B.nr) throw MasError(MAS_EINVAL, "spgemm: shape mismatch");
   if (A.nr == 0) return spgemm(A, B);
   DevArena ar;
@@ -1373,8 +1383,7 @@ Csr device_spgemm(const Csr& A, const Csr& B, hipStream_t s) {
   const double* Bv = ar.upload<double>(B.val, s);
   int64_t* cnt = ar.alloc<int64_t>(n);
   int* over = ar.alloc<int>(n);
-  int cap = kSpgSlots * 3 / 4;
-  if (const char* e = std::getenv("MAS_SPGEMM_CAP")) cap = std::max(1, std::min(cap, std::atoi(e)));
+  const int cap = spgemm_table_cap(cap_limit);
   hipLaunchKernelGGL(k_spgemm_row<0>, dim3((unsigned)n), dim3(64), 0, s, n, Ap, Ai, Av, Bp, Bi, Bv, cap, cnt, over,
                      nullptr, nullptr, nullptr);
   launch_check();
@@ -1454,8 +1463,321 @@ static void cgs_step(int64_t n, int nr, int nrp, int j1, const double* V, double
 #undef MAS_CGS_CASES
 }
 
-Csr device_galerkin(const Csr& P, const Csr& A, hipStream_t s) {
-  return device_spgemm(transpose(P), device_spgemm(A, P, s), s);
+Csr device_galerkin(const Csr& P, const Csr& A, hipStream_t s, int cap) {
+  return device_spgemm(transpose(P), device_spgemm(A, P, s, cap), s, cap);
+}
+
+// ---------------------------------------------------------------------------
+// Smoothed aggregation with the level operators resident on the device
+// (Algorithm 1; Section 3.2 for the strength of connection).  Per level: the
+// diagonal and the Gershgorin bound, the strength graph, its transfer to the
+// host for the greedy aggregation, the tentative prolongator's values from the
+// near-null vector (host, O(n)), the smoothed prolongator and the Galerkin
+// product A_c = P^T (A P), all with the host's operations in the host's order.
+// Device CSR in FP64 with 32-bit columns, rows sorted.
+struct SaMat {
+  int64_t nr = 0, nc = 0, nnz = 0;
+  int64_t* ptr = nullptr;
+  int* ind = nullptr;
+  double* val = nullptr;
+};
+
+// ptr[0] = 0, ptr[i + 1] = cnt[0] + ... + cnt[i]; returns ptr[n] (a
+// synchronising read).
+static int64_t sa_scan(const int64_t* cnt, int64_t* ptr, int64_t n, DevArena& tmp, hipStream_t s) {
+  HIPCHECK(hipMemsetAsync(ptr, 0, sizeof(int64_t), s));
+  if (n > 0) {
+    if (n >= (int64_t)INT32_MAX) throw MasError(MAS_EINVAL, "setup operator too large for 32-bit row counts");
+    size_t b = 0;
+    HIPCHECK(hipcub::DeviceScan::InclusiveSum(nullptr, b, cnt, ptr + 1, (int)n, s));
+    void* t = tmp.alloc<char>(b);
+    HIPCHECK(hipcub::DeviceScan::InclusiveSum(t, b, cnt, ptr + 1, (int)n, s));
+  }
+  int64_t last = 0;
+  HIPCHECK(hipMemcpyAsync(&last, ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  if (last >= (int64_t)INT32_MAX) throw MasError(MAS_EINVAL, "setup operator too large for 32-bit offsets");
+  return last;
+}
+
+static SaMat sa_upload(const Csr& A, DevArena& ar, hipStream_t s) {
+  SaMat M;
+  M.nr = A.nr;
+  M.nc = A.nc;
+  M.nnz = A.nnz();
+  M.ptr = ar.upload<int64_t>(A.ptr, s);
+  M.ind = ar.upload<int>(A.ind, s);
+  M.val = ar.upload<double>(A.val, s);
+  return M;
+}
+
+static Csr sa_download(const SaMat& M, hipStream_t s) {
+  Csr A;
+  A.nr = M.nr;
+  A.nc = M.nc;
+  A.ptr.resize(M.nr + 1);
+  A.ind.resize(M.nnz);
+  A.val.resize(M.nnz);
+  HIPCHECK(hipMemcpyAsync(A.ptr.data(), M.ptr, (M.nr + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  if (M.nnz > 0) {
+    HIPCHECK(hipMemcpyAsync(A.ind.data(), M.ind, M.nnz * sizeof(int), hipMemcpyDeviceToHost, s));
+    if (M.val) HIPCHECK(hipMemcpyAsync(A.val.data(), M.val, M.nnz * sizeof(double), hipMemcpyDeviceToHost, s));
+    else std::fill(A.val.begin(), A.val.end(), 1.0);
+  }
+  HIPCHECK(hipStreamSynchronize(s));
+  return A;
+}
+
+// A^T with the rows of each column ascending (the host transpose's order):
+// a stable radix sort of the entry numbers by column.  Pattern only when
+// values is false.
+static SaMat sa_transpose(const SaMat& A, bool values, DevArena& out, DevArena& tmp, hipStream_t s) {
+  SaMat T;
+  T.nr = A.nc;
+  T.nc = A.nr;
+  T.nnz = A.nnz;
+  T.ptr = out.alloc<int64_t>(T.nr + 1);
+  T.ind = out.alloc<int>(A.nnz);
+  T.val = values ? out.alloc<double>(A.nnz) : nullptr;
+  unsigned long long* cnt = tmp.alloc<unsigned long long>(std::max<int64_t>(T.nr, 1));
+  HIPCHECK(hipMemsetAsync(cnt, 0, std::max<int64_t>(T.nr, 1) * sizeof(unsigned long long), s));
+  if (A.nnz > 0) {
+    hipLaunchKernelGGL(k_sa_colcount, dim3(blocks_for(A.nnz, 256)), dim3(256), 0, s, A.nnz, A.ind, cnt);
+    launch_check();
+  }
+  sa_scan((const int64_t*)cnt, T.ptr, T.nr, tmp, s);
+  if (A.nnz == 0) return T;
+  int* row = tmp.alloc<int>(A.nnz);
+  int* seq = tmp.alloc<int>(A.nnz);
+  int* perm = tmp.alloc<int>(A.nnz);
+  unsigned* keys = tmp.alloc<unsigned>(A.nnz);
+  hipLaunchKernelGGL(k_sa_rows, dim3(blocks_for(A.nr, 256)), dim3(256), 0, s, A.nr, A.ptr, row);
+  hipLaunchKernelGGL(k_sa_iota, dim3(blocks_for(A.nnz, 256)), dim3(256), 0, s, A.nnz, seq);
+  launch_check();
+  int bits = 1;
+  while (bits < 31 && ((int64_t)1 << bits) < A.nc) ++bits;
+  size_t b = 0;
+  HIPCHECK(hipcub::DeviceRadixSort::SortPairs(nullptr, b, (const unsigned*)A.ind, keys, seq, perm, (int)A.nnz, 0,
+                                              bits, s));
+  void* t = tmp.alloc<char>(b);
+  HIPCHECK(hipcub::DeviceRadixSort::SortPairs(t, b, (const unsigned*)A.ind, keys, seq, perm, (int)A.nnz, 0, bits,
+                                              s));
+  hipLaunchKernelGGL(k_sa_gather, dim3(blocks_for(A.nnz, 256)), dim3(256), 0, s, A.nnz, perm, row, A.val, T.ind,
+                     T.val);
+  launch_check();
+  return T;
+}
+
+// C = A B, the host product's pattern and bits: k_spgemm_row for rows whose
+// distinct columns fit its LDS table, k_spgemm_dense for the others.
+static SaMat sa_spgemm(const SaMat& A, const SaMat& B, int cap_limit, DevArena& out, DevArena& tmp,
+                       hipStream_t s) {
+  if (A.nc != B.nr) throw MasError(MAS_EINVAL, "spgemm: shape mismatch");
+  SaMat C;
+  C.nr = A.nr;
+  C.nc = B.nc;
+  const int64_t n = A.nr;
+  C.ptr = out.alloc<int64_t>(n + 1);
+  if (n == 0) {
+    sa_scan(nullptr, C.ptr, 0, tmp, s);
+    return C;
+  }
+  const int cap = spgemm_table_cap(cap_limit);
+  int64_t* cnt = tmp.alloc<int64_t>(n);
+  int* over = tmp.alloc<int>(n);
+  hipLaunchKernelGGL(k_spgemm_row<0>, dim3((unsigned)n), dim3(64), 0, s, n, A.ptr, A.ind, A.val, B.ptr, B.ind,
+                     B.val, cap, cnt, over, nullptr, nullptr, nullptr);
+  launch_check();
+  int* nover_d = tmp.alloc<int>(1);
+  size_t b = 0;
+  HIPCHECK(hipcub::DeviceReduce::Sum(nullptr, b, over, nover_d, (int)n, s));
+  void* t = tmp.alloc<char>(b);
+  HIPCHECK(hipcub::DeviceReduce::Sum(t, b, over, nover_d, (int)n, s));
+  int nover = 0;
+  HIPCHECK(hipMemcpyAsync(&nover, nover_d, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  // long rows: a dense slice of B.nc columns per workgroup, at most 1 GiB
+  unsigned G = 0;
+  double* acc = nullptr;
+  int64_t* mark = nullptr;
+  if (nover > 0) {
+    const int64_t per = std::max<int64_t>(B.nc, 1) * (int64_t)(sizeof(double) + sizeof(int64_t));
+    G = (unsigned)std::max<int64_t>(1, std::min<int64_t>({(int64_t)nover, 1024, ((int64_t)1 << 30) / per}));
+    acc = tmp.alloc<double>((size_t)G * std::max<int64_t>(B.nc, 1));
+    mark = tmp.alloc<int64_t>((size_t)G * std::max<int64_t>(B.nc, 1));
+    HIPCHECK(hipMemsetAsync(mark, 0xff, (size_t)G * std::max<int64_t>(B.nc, 1) * sizeof(int64_t), s));
+    hipLaunchKernelGGL(k_spgemm_dense<0>, dim3(G), dim3(256), 0, s, n, A.ptr, A.ind, A.val, B.ptr, B.ind, B.val,
+                       B.nc, over, acc, mark, cnt, nullptr, nullptr, nullptr);
+    launch_check();
+  }
+  C.nnz = sa_scan(cnt, C.ptr, n, tmp, s);
+  C.ind = out.alloc<int>(C.nnz);
+  C.val = out.alloc<double>(C.nnz);
+  hipLaunchKernelGGL(k_spgemm_row<1>, dim3((unsigned)n), dim3(64), 0, s, n, A.ptr, A.ind, A.val, B.ptr, B.ind,
+                     B.val, cap, cnt, over, C.ptr, C.ind, C.val);
+  launch_check();
+  if (nover > 0) {
+    hipLaunchKernelGGL(k_spgemm_dense<1>, dim3(G), dim3(256), 0, s, n, A.ptr, A.ind, A.val, B.ptr, B.ind, B.val,
+                       B.nc, over, acc, mark, cnt, C.ptr, C.ind, C.val);
+    launch_check();
+  }
+  return C;
+}
+
+// The kept entries of A (pattern only).
+static SaMat sa_select(const SaMat& A, const unsigned char* keep, DevArena& out, DevArena& tmp, hipStream_t s) {
+  SaMat S;
+  S.nr = S.nc = A.nr;
+  S.ptr = out.alloc<int64_t>(A.nr + 1);
+  int64_t* cnt = tmp.alloc<int64_t>(std::max<int64_t>(A.nr, 1));
+  const unsigned g = blocks_for(std::max<int64_t>(A.nr, 1), 256);
+  hipLaunchKernelGGL(k_sa_select<0>, dim3(g), dim3(256), 0, s, A.nr, A.ptr, A.ind, keep, cnt, nullptr, nullptr);
+  launch_check();
+  S.nnz = sa_scan(cnt, S.ptr, A.nr, tmp, s);
+  S.ind = out.alloc<int>(S.nnz);
+  hipLaunchKernelGGL(k_sa_select<1>, dim3(g), dim3(256), 0, s, A.nr, A.ptr, A.ind, keep, nullptr, S.ptr, S.ind);
+  launch_check();
+  return S;
+}
+
+// The strength graph of A with near-null vector B (the host's strength_graph).
+static Csr sa_strength(const SaMat& A, const double* d, double rho, const std::vector<double>& B,
+                       const SocParams& soc, DevArena& tmp, hipStream_t s) {
+  const int64_t n = A.nr;
+  const unsigned g = blocks_for(std::max<int64_t>(n, 1), 256);
+  unsigned char* keep = tmp.alloc<unsigned char>(A.nnz);
+  if (soc.kind == 1) {
+    hipLaunchKernelGGL(k_sa_soc_sym, dim3(g), dim3(256), 0, s, n, A.ptr, A.ind, A.val, d, soc.theta * soc.theta,
+                       keep);
+    launch_check();
+    return sa_download(sa_select(A, keep, tmp, tmp, s), s);
+  }
+  const double dt = 1.0 / rho;
+  double* z = tmp.alloc<double>(A.nnz);
+  const double* Bd = tmp.upload<double>(B, s);
+  hipLaunchKernelGGL(k_sa_soc_evol, dim3((unsigned)n), dim3(64), 0, s, n, A.ptr, A.ind, A.val, d, Bd, dt, soc.eps,
+                     z, keep);
+  launch_check();
+  // the union of the kept pairs and their transposes
+  const SaMat S1 = sa_select(A, keep, tmp, tmp, s);
+  const SaMat S1t = sa_transpose(S1, false, tmp, tmp, s);
+  SaMat S;
+  S.nr = S.nc = n;
+  S.ptr = tmp.alloc<int64_t>(n + 1);
+  int64_t* cnt = tmp.alloc<int64_t>(std::max<int64_t>(n, 1));
+  hipLaunchKernelGGL(k_sa_union<0>, dim3(g), dim3(256), 0, s, n, S1.ptr, S1.ind, S1t.ptr, S1t.ind, cnt, nullptr,
+                     nullptr);
+  launch_check();
+  S.nnz = sa_scan(cnt, S.ptr, n, tmp, s);
+  S.ind = tmp.alloc<int>(S.nnz);
+  hipLaunchKernelGGL(k_sa_union<1>, dim3(g), dim3(256), 0, s, n, S1.ptr, S1.ind, S1t.ptr, S1t.ind, nullptr, S.ptr,
+                     S.ind);
+  launch_check();
+  return sa_download(S, s);
+}
+
+// sa_field (Algorithm 1 on one scalar field) with the level operators on the
+// device: the same prolongators and near-null vectors, bit for bit.
+void device_sa_field(const Csr& A0, const SocParams& soc, int max_coarse, int max_levels, int cap,
+                     std::vector<Csr>& Ps, std::vector<std::vector<double>>& Bs, hipStream_t s) {
+  Ps.clear();
+  Bs.clear();
+  std::vector<double> B(A0.nr, 1.0);
+  Bs.push_back(B);
+  auto cur = std::make_unique<DevArena>();
+  SaMat A = sa_upload(A0, *cur, s);
+  while (A.nr > max_coarse && (int)Ps.size() + 1 < max_levels) {
+    DevArena lv;  // this level's work memory
+    const int64_t n = A.nr;
+    const unsigned g = blocks_for(n, 256);
+    double* d = lv.alloc<double>(n);
+    double* ratio = lv.alloc<double>(n);
+    hipLaunchKernelGGL(k_sa_diag, dim3(g), dim3(256), 0, s, n, A.ptr, A.ind, A.val, d, ratio);
+    launch_check();
+    const unsigned nb = std::min(1024u, g);
+    double* part = lv.alloc<double>(nb);
+    hipLaunchKernelGGL(k_sa_max, dim3(nb), dim3(256), 0, s, n, ratio, part);
+    launch_check();
+    std::vector<double> hp(nb);
+    HIPCHECK(hipMemcpyAsync(hp.data(), part, nb * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    double rho = 0.0;
+    for (double v : hp) rho = std::max(rho, v);
+    int32_t nc = 0;
+    const std::vector<int32_t> agg = aggregate(sa_strength(A, d, rho, B, soc, lv, s), &nc);
+    if (nc >= A.nr) break;
+    // tentative interpolation from the near-null vector (host, one value per row)
+    std::vector<double> nrm2(nc, 0.0);
+    for (int64_t i = 0; i < n; ++i) nrm2[agg[i]] += B[i] * B[i];
+    std::vector<double> Bc(nc);
+    for (int32_t J = 0; J < nc; ++J) Bc[J] = std::sqrt(nrm2[J]);
+    std::vector<double> tv(n);
+    for (int64_t i = 0; i < n; ++i) tv[i] = B[i] / Bc[agg[i]];
+    SaMat T;
+    T.nr = T.nnz = n;
+    T.nc = nc;
+    T.ptr = lv.alloc<int64_t>(n + 1);
+    hipLaunchKernelGGL(k_sa_iota64, dim3(blocks_for(n + 1, 256)), dim3(256), 0, s, n + 1, T.ptr);
+    launch_check();
+    T.ind = lv.upload<int>(agg, s);
+    T.val = lv.upload<double>(tv, s);
+    // P = (I - omega D^-1 A) T, omega = (4/3) / rho
+    const double omega = (4.0 / 3.0) / rho;
+    SaMat DA = A;
+    DA.val = lv.alloc<double>(A.nnz);
+    hipLaunchKernelGGL(k_sa_scale, dim3(g), dim3(256), 0, s, n, A.ptr, A.val, d, DA.val);
+    launch_check();
+    SaMat P = sa_spgemm(DA, T, cap, lv, lv, s);
+    hipLaunchKernelGGL(k_sa_smooth, dim3(g), dim3(256), 0, s, n, P.ptr, P.ind, P.val, T.ind, T.val, omega);
+    launch_check();
+    // A_c = P^T (A P), kept on the device for the next level
+    auto next = std::make_unique<DevArena>();
+    const SaMat AP = sa_spgemm(A, P, cap, lv, lv, s);
+    const SaMat Pt = sa_transpose(P, true, lv, lv, s);
+    const SaMat Ac = sa_spgemm(Pt, AP, cap, *next, lv, s);
+    Ps.push_back(sa_download(P, s));  // synchronises the stream
+    A = Ac;
+    cur = std::move(next);
+    B = Bc;
+    Bs.push_back(B);
+  }
+  HIPCHECK(hipStreamSynchronize(s));
+}
+
+// device_sa_field for several fields: with setup threads, each field on a
+// host thread and a stream of its own (the host's aggregation of one field
+// overlaps the device work of the others); otherwise one after another on s.
+// Each field's hierarchy is the same either way.
+void device_sa_fields(const std::vector<Csr>& A, const SocParams& soc, int max_coarse, int max_levels, int cap,
+                      std::vector<std::vector<Csr>>& Ps, std::vector<std::vector<std::vector<double>>>& Bs,
+                      hipStream_t s) {
+  const size_t nf = A.size();
+  Ps.assign(nf, {});
+  Bs.assign(nf, {});
+  if (setup_threads() <= 1 || nf <= 1) {
+    for (size_t f = 0; f < nf; ++f) device_sa_field(A[f], soc, max_coarse, max_levels, cap, Ps[f], Bs[f], s);
+    return;
+  }
+  HIPCHECK(hipStreamSynchronize(s));
+  int device = 0;
+  HIPCHECK(hipGetDevice(&device));
+  std::vector<std::future<void>> jobs;
+  for (size_t f = 0; f < nf; ++f)
+    jobs.push_back(std::async(std::launch::async, [&, f] {
+      HIPCHECK(hipSetDevice(device));
+      hipStream_t st = nullptr;
+      HIPCHECK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      try {
+        device_sa_field(A[f], soc, max_coarse, max_levels, cap, Ps[f], Bs[f], st);
+      } catch (...) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+        throw;
+      }
+      HIPCHECK(hipStreamDestroy(st));
+    }));
+  for (auto& j : jobs) j.wait();
+  for (auto& j : jobs) j.get();  // rethrows the first field's error, if any
 }
 
 // dense inverse of an n x n FP64 matrix on the device (Gauss-Jordan, partial pivoting)
@@ -1986,12 +2308,13 @@ void s_hierarchy(HostDlsc& D, const mas_params& par, bool singular) {
   }
 }
 
-// dev: a device may be used; with MAS_DEVICE_GALERKIN set, the Galerkin
-// products of the level operators then run on it (stream s), with the same
-// result as the host's, bit for bit.  Off by default: with the CSR arrays
-// moved through pageable host memory, the threaded host product is faster.
+// dev: a device may be used (mas_setup; stream s).  With device_sa the
+// per-field smoothed aggregation, and with device_galerkin the Galerkin
+// products of the level operators, then run on it, with the same results as
+// the host's, bit for bit; mas_analyze runs both on the host.
 void analyze_impl(mas_handle* h, const mas_problem* pr, bool dev = false, hipStream_t s = nullptr) {
   SetupTrace tr;
+  const bool dev_sa = dev && h->par.device_sa != 0;
   dev = dev && h->par.device_galerkin != 0;
   const int d = pr->dim;
   if (d != 2 && d != 3) throw MasError(MAS_EINVAL, "dim must be 2 or 3");
@@ -2034,6 +2357,8 @@ void analyze_impl(mas_handle* h, const mas_problem* pr, bool dev = false, hipStr
     throw MasError(MAS_EINVAL, "unknown gram_schmidt");
   if (par.full_patch_min < 1 || par.bucket_min < 1) throw MasError(MAS_EINVAL, "full_patch_min and bucket_min must be >= 1");
   if (par.patch_kernel < 0 || par.patch_kernel > 5) throw MasError(MAS_EINVAL, "patch_kernel must be 0..5");
+  if (par.device_sa != 0 && par.device_sa != 1) throw MasError(MAS_EINVAL, "device_sa must be 0 or 1");
+  if (par.spgemm_cap < 0) throw MasError(MAS_EINVAL, "spgemm_cap must be >= 0");
   std::vector<int64_t> free0, dir0, free1;
   std::vector<int8_t> f0, f1;
   int64_t nu0 = 0, np0 = 0;
@@ -2105,11 +2430,15 @@ void analyze_impl(mas_handle* h, const mas_problem* pr, bool dev = false, hipStr
   } else {
     std::vector<Csr> Af;
     for (int f = 0; f <= d; ++f) Af.push_back((f < d) ? submatrix(K1f, blocks[f], blocks[f]) : Ap);
-    sa_fields(Af, soc_params(par), par.max_coarse, par.max_levels, fP, fB);
+    if (dev_sa) {
+      device_sa_fields(Af, soc_params(par), par.max_coarse, par.max_levels, par.spgemm_cap, fP, fB, s);
+    } else {
+      sa_fields(Af, soc_params(par), par.max_coarse, par.max_levels, fP, fB);
+    }
   }
   size_t lmax = SIZE_MAX;
   for (int f = 0; f <= d; ++f) lmax = std::min(lmax, fP[f].size() + 1);
-  tr.mark("smoothed aggregation");
+  tr.mark(dev_sa ? "smoothed aggregation (device)" : "smoothed aggregation");
   {
     // the coarsest level is the one after lmax - 1 coarsenings of every field
     // (a field that coarsened further is cut there), inverted densely with
@@ -2128,7 +2457,7 @@ void analyze_impl(mas_handle* h, const mas_problem* pr, bool dev = false, hipStr
     std::vector<const Csr*> bl;
     for (int f = 0; f <= d; ++f) bl.push_back(&fP[f][l]);
     Csr P = block_diag(bl);
-    Csr Kc = dev ? device_galerkin(P, Ks.back(), s) : galerkin(P, Ks.back());
+    Csr Kc = dev ? device_galerkin(P, Ks.back(), s, par.spgemm_cap) : galerkin(P, Ks.back());
     std::vector<int8_t> fc;
     for (int f = 0; f <= d; ++f) fc.insert(fc.end(), (size_t)fP[f][l].nc, (int8_t)f);
     Ps.back() = P;  // P of the finer level
@@ -2828,9 +3157,11 @@ void mas_default_params(int32_t dim, int32_t disc, int32_t relax, mas_params* ou
   p.full_patch_min = kFullPatch;
   p.bucket_min = 32768;
   p.factor_blocked = 1;
-  p.device_galerkin = 0;
+  p.device_galerkin = 1;
   p.share_blocks = 1;
   p.patch_kernel = 0;
+  p.device_sa = 1;
+  p.spgemm_cap = 0;
   *out = p;
 }
 

@@ -48,7 +48,7 @@ class mas_params(C.Structure):
                 ("soc", C.c_int32), ("soc_eps", C.c_double), ("gram_schmidt", C.c_int32), ("autotune", C.c_int32),
                 ("graphs", C.c_int32), ("full_patch_min", C.c_int32), ("bucket_min", C.c_int32),
                 ("factor_blocked", C.c_int32), ("device_galerkin", C.c_int32), ("share_blocks", C.c_int32),
-                ("patch_kernel", C.c_int32)]
+                ("patch_kernel", C.c_int32), ("device_sa", C.c_int32), ("spgemm_cap", C.c_int32)]
 
 
 class mas_solve_info(C.Structure):

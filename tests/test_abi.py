@@ -148,6 +148,10 @@ def test_analyze_rejects_bad_input():
     with pytest.raises(mas.MasError) as e:
         mas.Handle(P, mas.default_params(2, patch_kernel=6), analyze_only=True)
     assert e.value.code == mas.MAS_EINVAL and "patch_kernel" in str(e.value)
+    for bad, word in ((dict(device_sa=2), "device_sa"), (dict(spgemm_cap=-1), "spgemm_cap")):
+        with pytest.raises(mas.MasError) as e:
+            mas.Handle(P, mas.default_params(2, **bad), analyze_only=True)
+        assert e.value.code == mas.MAS_EINVAL and word in str(e.value)
     h = mas.Handle(P, mp, analyze_only=True)
     with pytest.raises(mas.MasError):
         import torch
