@@ -171,8 +171,9 @@ typedef struct {
   int32_t factor_blocked; /* 1: blocked Gauss-Jordan for patch blocks whose panel fits in LDS;
                              0: single-pivot Gauss-Jordan everywhere */
   int32_t device_galerkin;/* 1 (default): in mas_setup the Galerkin products of the level
-                             operators (Algorithm 1) run on the device (same values as the host's,
-                             bit for bit); 0: on the host */
+                             operators (Algorithm 1) run on the device, each operator kept there
+                             for the next product (same values as the host's, bit for bit); 0: on
+                             the host */
   int32_t share_blocks;   /* 1: a level whose patches have identical velocity blocks in every
                              component (the vector Laplacian with the same boundary conditions on
                              each component, Section 2; checked bit for bit by the analysis)

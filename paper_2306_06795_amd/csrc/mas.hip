@@ -1359,74 +1359,11 @@ struct SetupTrace {
   }
 };
 
-// C = A B on the device (k_spgemm_row): the same pattern and the same bits as
-// the host product.  Rows whose distinct columns overflow the kernel's LDS
-// table are computed on the host.  Host matrices in and out; the device
-// buffers live only for the call.
 // The LDS table's row capacity of the device sparse products: at most
 // min(cap, 3/4 of the table) distinct columns (cap <= 0: no extra limit).
 static int spgemm_table_cap(int cap) {
   const int full = kSpgSlots * 3 / 4;
   return cap > 0 ? std::min(cap, full) : full;
-}
-
-Csr device_spgemm(const Csr& A, const Csr& B, hipStream_t s, int cap_limit) {
-  if (A.nc != B.nr) throw MasError(MAS_EINVAL, "spgemm: shape mismatch");
-  if (A.nr == 0) return spgemm(A, B);
-  DevArena ar;
-  const int64_t n = A.nr;
-  const int64_t* Ap = ar.upload<int64_t>(A.ptr, s);
-  const int* Ai = ar.upload<int>(A.ind, s);
-  const double* Av = ar.upload<double>(A.val, s);
-  const int64_t* Bp = ar.upload<int64_t>(B.ptr, s);
-  const int* Bi = ar.upload<int>(B.ind, s);
-  const double* Bv = ar.upload<double>(B.val, s);
-  int64_t* cnt = ar.alloc<int64_t>(n);
-  int* over = ar.alloc<int>(n);
-  const int cap = spgemm_table_cap(cap_limit);
-  hipLaunchKernelGGL(k_spgemm_row<0>, dim3((unsigned)n), dim3(64), 0, s, n, Ap, Ai, Av, Bp, Bi, Bv, cap, cnt, over,
-                     nullptr, nullptr, nullptr);
-  launch_check();
-  std::vector<int64_t> hc(n);
-  std::vector<int> ho(n);
-  HIPCHECK(hipMemcpyAsync(hc.data(), cnt, n * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  HIPCHECK(hipMemcpyAsync(ho.data(), over, n * sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHECK(hipStreamSynchronize(s));
-  // rows left to the host
-  std::vector<int64_t> rows;
-  for (int64_t i = 0; i < n; ++i)
-    if (ho[i]) rows.push_back(i);
-  Csr H;
-  if (!rows.empty()) {
-    std::vector<int64_t> all(A.nc);
-    std::iota(all.begin(), all.end(), 0);
-    H = spgemm(submatrix(A, rows, all), B);
-    for (size_t q = 0; q < rows.size(); ++q) hc[rows[q]] = H.ptr[q + 1] - H.ptr[q];
-  }
-  Csr C;
-  C.nr = n;
-  C.nc = B.nc;
-  C.ptr.assign(n + 1, 0);
-  for (int64_t i = 0; i < n; ++i) C.ptr[i + 1] = C.ptr[i] + hc[i];
-  const int64_t nnz = C.ptr[n];
-  if (nnz >= (int64_t)INT32_MAX) throw MasError(MAS_EINVAL, "Galerkin product too large for 32-bit offsets");
-  C.ind.resize(nnz);
-  C.val.resize(nnz);
-  const int64_t* Cp = ar.upload<int64_t>(C.ptr, s);
-  int* Ci = ar.alloc<int>(nnz);
-  double* Cv = ar.alloc<double>(nnz);
-  hipLaunchKernelGGL(k_spgemm_row<1>, dim3((unsigned)n), dim3(64), 0, s, n, Ap, Ai, Av, Bp, Bi, Bv, cap, cnt, over,
-                     Cp, Ci, Cv);
-  launch_check();
-  HIPCHECK(hipMemcpyAsync(C.ind.data(), Ci, nnz * sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHECK(hipMemcpyAsync(C.val.data(), Cv, nnz * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPCHECK(hipStreamSynchronize(s));
-  for (size_t q = 0; q < rows.size(); ++q) {
-    const int64_t i = rows[q];
-    std::copy(H.ind.begin() + H.ptr[q], H.ind.begin() + H.ptr[q + 1], C.ind.begin() + C.ptr[i]);
-    std::copy(H.val.begin() + H.ptr[q], H.val.begin() + H.ptr[q + 1], C.val.begin() + C.ptr[i]);
-  }
-  return C;
 }
 
 // Classical Gram-Schmidt of one Arnoldi step over the j1 basis vectors V
@@ -1461,10 +1398,6 @@ static void cgs_step(int64_t n, int nr, int nrp, int j1, const double* V, double
     }
   }
 #undef MAS_CGS_CASES
-}
-
-Csr device_galerkin(const Csr& P, const Csr& A, hipStream_t s, int cap) {
-  return device_spgemm(transpose(P), device_spgemm(A, P, s, cap), s, cap);
 }
 
 // ---------------------------------------------------------------------------
@@ -1779,6 +1712,34 @@ void device_sa_fields(const std::vector<Csr>& A, const SocParams& soc, int max_c
   for (auto& j : jobs) j.wait();
   for (auto& j : jobs) j.get();  // rethrows the first field's error, if any
 }
+
+// The Galerkin products of the level operators (Algorithm 1),
+// K_{l+1} = P_l^T (K_l P_l), on the device: each K_l stays there for the next
+// product, and the host receives every K_{l+1} (the patch extraction and the
+// level uploads read it).  The kernels of the per-field products, so the
+// host's bits.
+struct DeviceGalerkin {
+  hipStream_t s = nullptr;
+  int cap = 0;
+  std::unique_ptr<DevArena> ar;  // holds K
+  SaMat K;
+  Csr next(const Csr& P, const Csr& Kh) {
+    if (!ar) {
+      ar = std::make_unique<DevArena>();
+      K = sa_upload(Kh, *ar, s);
+    }
+    DevArena lv;  // this product's work memory
+    const SaMat Pd = sa_upload(P, lv, s);
+    const SaMat AP = sa_spgemm(K, Pd, cap, lv, lv, s);
+    const SaMat Pt = sa_transpose(Pd, true, lv, lv, s);
+    auto nar = std::make_unique<DevArena>();
+    const SaMat Kc = sa_spgemm(Pt, AP, cap, *nar, lv, s);
+    Csr out = sa_download(Kc, s);  // synchronises the stream
+    K = Kc;
+    ar = std::move(nar);
+    return out;
+  }
+};
 
 // dense inverse of an n x n FP64 matrix on the device (Gauss-Jordan, partial pivoting)
 void dense_inverse(DevArena& ar, double* A, int n, hipStream_t s) {
@@ -2453,11 +2414,14 @@ void analyze_impl(mas_handle* h, const mas_problem* pr, bool dev = false, hipStr
   Ks.push_back(std::move(K1f));
   std::vector<Csr> Ps{Csr(), Csr()};
   std::vector<std::vector<int8_t>> fields{f0, f1};
+  DeviceGalerkin dg;
+  dg.s = s;
+  dg.cap = par.spgemm_cap;
   for (size_t l = 0; l + 1 < lmax; ++l) {
     std::vector<const Csr*> bl;
     for (int f = 0; f <= d; ++f) bl.push_back(&fP[f][l]);
     Csr P = block_diag(bl);
-    Csr Kc = dev ? device_galerkin(P, Ks.back(), s, par.spgemm_cap) : galerkin(P, Ks.back());
+    Csr Kc = dev ? dg.next(P, Ks.back()) : galerkin(P, Ks.back());
     std::vector<int8_t> fc;
     for (int f = 0; f <= d; ++f) fc.insert(fc.end(), (size_t)fP[f][l].nc, (int8_t)f);
     Ps.back() = P;  // P of the finer level

@@ -4,8 +4,8 @@ with its operators resident on the device (device_sa = 1: Gershgorin bound,
 symmetric and evolution strength of Section 3.2, smoothed prolongator, the
 field's Galerkin products).  The hierarchy a handle builds through mas_setup
 must equal, bit for bit, the one mas_analyze builds on the host -- also when
-rows overflow the product kernel's LDS table (spgemm_cap) and take the host
-(device_galerkin) or the global-memory kernel (device_sa)."""
+rows overflow the product kernel's LDS table (spgemm_cap) and take the
+global-memory product kernel."""
 import numpy as np
 import pytest
 
@@ -45,7 +45,7 @@ def test_device_galerkin_equals_host_bitwise(name, cap):
     P = make_problem(**kw)
     mp = mas.default_params(P.dim, mas.MAS_SV if P.disc == "SV" else mas.MAS_TH, max_coarse=20, **over)
     mp.device_galerkin, mp.device_sa = 1, 0
-    mp.spgemm_cap = cap  # 4: rows with more than 4 distinct columns are finished on the host
+    mp.spgemm_cap = cap  # 4: rows with more than 4 distinct columns take the global-memory product
     print(f"[setup {name}] cap={cap}", flush=True)
     hd = mas.Handle(P, mp)
     hh = mas.Handle(P, mp, analyze_only=True)
