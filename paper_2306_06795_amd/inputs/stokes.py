@@ -226,13 +226,13 @@ def make_problem(dim: int = 2, n: int = 16, disc: str = "TH", lx: float = 1.0,
 # the five workloads (sizes and seeds fixed here)
 
 def config(name: str) -> dict:
-    if name == "th2d_16":  # cfg1: manufactured solution
+    if name == "th2d_16":  # 16x16 Taylor-Hood, manufactured solution
         return dict(dim=2, n=16, disc="TH", forcing="manufactured", bc="manufactured")
-    if name == "th2d_256":  # cfg2: jittered lid-driven cavity, Gaussian forcing
+    if name == "th2d_256":  # 256x256 Taylor-Hood: jittered lid-driven cavity, Gaussian forcing
         ss = np.random.SeedSequence(2).spawn(3)
         return dict(dim=2, n=256, disc="TH", jitter=0.2, forcing="gaussian", bc="lid",
                     rng_jitter=np.random.default_rng(ss[0]), rng_forcing=np.random.default_rng(ss[1]))
-    if name == "th3d_32":  # cfg3: smooth forcing, homogeneous Dirichlet
+    if name == "th3d_32":  # 32^3 Taylor-Hood cube: smooth forcing, homogeneous Dirichlet
         return dict(dim=3, n=32, disc="TH", forcing="smooth", bc="zero", seed=3)
     if name == "sv2d_128x64":  # Alfeld refinement of 128x128, 64 right-hand sides
         # unit square: on [0,16]x[0,1] (cells of aspect 16) the SV smoother of the

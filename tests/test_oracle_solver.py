@@ -659,7 +659,7 @@ def test_fgmres_solution_matches_sparse_direct(kw, relax):
     assert abs(P.p_weight0 @ res.x[nu:]) <= 1e-13 * np.abs(res.x).max()
 
 
-def test_manufactured_solve_cfg1():
+def test_manufactured_solve_th2d_16():
     """16x16 Taylor-Hood, u = (y^2, x^2), p = x - y: the solve returns the interpolant."""
     P = make_problem(dim=2, n=16)
     pre = dc.DCPreconditioner(P, dc.default_params(P))
