@@ -1,4 +1,4 @@
-"""Setup on the device (Algorithm 1), opt-in: the Galerkin products of the
+"""Setup on the device (Algorithm 1, the default of mas_setup): the Galerkin products of the
 level operators (device_galerkin = 1), and the per-field smoothed aggregation
 with its operators resident on the device (device_sa = 1: Gershgorin bound,
 symmetric and evolution strength of Section 3.2, smoothed prolongator, the
