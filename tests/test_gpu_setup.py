@@ -81,3 +81,24 @@ def test_device_smoothed_aggregation_equals_host_bitwise(name, cap):
     assert_same_hierarchy(hb, hh)
     for h in (hd, hh, hb):
         h.close()
+
+
+@pytest.mark.parametrize("config", [
+    "th2d_256",
+    "sv2d_128x64",
+    pytest.param("th3d_32", marks=pytest.mark.slow),
+])
+def test_device_setup_equals_host_at_benchmark_size(config):
+    """The default mas_setup (smoothed aggregation and Galerkin products on the
+    device) and the host analysis build the same hierarchy, bit for bit, on
+    the benchmark workloads."""
+    from paper_2306_06795_amd.inputs import make_config
+    P = make_config(config)
+    mp = mas.default_params(P.dim, mas.MAS_SV if P.disc == "SV" else mas.MAS_TH)
+    assert mp.device_sa == 1 and mp.device_galerkin == 1
+    print(f"[device setup {config}]", flush=True)
+    hd = mas.Handle(P, mp)
+    hh = mas.Handle(P, mp, analyze_only=True)
+    assert_same_hierarchy(hd, hh)
+    hd.close()
+    hh.close()
