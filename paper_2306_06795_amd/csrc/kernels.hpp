@@ -897,15 +897,21 @@ __device__ __forceinline__ void shared_row_sums_il(const T* bi, const T* A, int 
 // j = g, g + G, ..., so each block entry is read once for all components.
 // After a barrier, groups 1..G-1 leave their sums in part ((G - 1) nco n
 // values, which may be the LDS copy of A itself, no longer read) and group 0
-// adds them in group order.  Every thread of the workgroup calls it (it holds
-// barriers).
+// adds them in group order.  split (n a row or two above TPB / 2, part in the
+// LDS copy of A): two groups over the first TPB / 2 rows, so that no
+// wavefront runs a whole row for one live lane, and each remaining row summed
+// by the whole workgroup (its wavefronts' sums added in wavefront order).
+// Every thread of the workgroup calls it (it holds barriers).
 template <typename T, int TPB>
 __device__ __forceinline__ void vanka_shared_rows(const T* sb, T* sy, const T* A, T* part, int n, int nco,
-                                                  int full) {
-  const int tid = threadIdx.x;
-  const int G = n >= TPB ? 1 : TPB / n;
-  const int g = G == 1 ? 0 : tid / n;
-  const int i0 = G == 1 ? tid : tid - g * n;
+                                                  int full, bool split) {
+  constexpr int H = TPB / 2;
+  __shared__ T xred[TPB / WAVE][2][3];
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
+  const int rows = split ? H : n;
+  const int G = split ? 2 : n >= TPB ? 1 : TPB / n;
+  const int g = G == 1 ? 0 : tid / rows;
+  const int i0 = G == 1 ? tid : tid - g * rows;
   T acc[3] = {0, 0, 0};
   if (G == 1) {  // a thread per row (and more rows per thread): results straight to sy
     for (int i = i0; i < n; i += TPB) {
@@ -933,6 +939,24 @@ __device__ __forceinline__ void vanka_shared_rows(const T* sb, T* sy, const T* A
     else if (full) shared_row_sums_il<T, 2, true>(sy, A, n, i0, g, G, acc);
     else shared_row_sums_il<T, 2, false>(sy, A, n, i0, g, G, acc);
   }
+  if (split)  // rows H .. n - 1 (at most two): a column per thread, then wavefront sums
+    for (int e = 0; e < 2; ++e) {
+      const int r = H + e;
+      if (r >= n) break;  // uniform
+      T pc[3] = {0, 0, 0};
+      for (int j = tid; j < n; j += TPB) {
+        const int lo = min(r, j), hi = max(r, j);
+        const T v = full ? A[(int64_t)j * n + r] : A[((unsigned)hi * (unsigned)(hi + 1) >> 1) + lo];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          if (c < nco) pc[c] += v * sy[j * nco + c];
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const T w = wave_sum(pc[c]);
+        if (lane == 0) xred[wv][e][c] = w;
+      }
+    }
   {
     __syncthreads();  // every read of A and of the interleaved b done: part and sy may be overwritten
     if (g >= 1 && g < G)
@@ -948,6 +972,12 @@ __device__ __forceinline__ void vanka_shared_rows(const T* sb, T* sy, const T* A
         for (int q = 1; q < G; ++q) v += part[(int64_t)(q - 1) * nco * n + c * n + i0];
         sy[c * n + i0] = v;
       }
+    if (split && tid >= H && tid < H + (n - H) * nco) {  // rows H .. n - 1
+      const int e = (tid - H) / nco, c = (tid - H) - e * nco;
+      T v = xred[0][e][c];
+      for (int q = 1; q < TPB / WAVE; ++q) v += xred[q][e][c];
+      sy[c * n + H + e] = v;
+    }
   }
 }
 
@@ -1028,9 +1058,14 @@ __device__ __forceinline__ void vanka_patch_compute(const T* sb, T* sy, const T*
   if (layout & LAYOUT_SHARED) {
     // the partial sums go to the staged copy of A when they fit there (the
     // host then allocates no separate area)
-    const int n = d.x, G = n >= TPB ? 1 : TPB / n;
+    const int n = d.x;
+    // a row or two above TPB / 2: two thread groups over the first TPB / 2 rows
+    // (their partial sums in the staged copy of A)
+    const bool split = TPB >= 2 * WAVE && n > TPB / 2 && n <= TPB / 2 + 2 && stage_rec &&
+                       (int64_t)nv <= blk_size(n, full);
+    const int G = split ? 2 : n >= TPB ? 1 : TPB / n;
     const bool in_rec = stage_rec && (int64_t)(G - 1) * nv <= blk_size(n, full);
-    vanka_shared_rows<T, TPB>(sb, sy, sf, in_rec ? const_cast<T*>(sf) : spart, n, nv / n, full);
+    vanka_shared_rows<T, TPB>(sb, sy, sf, in_rec ? const_cast<T*>(sf) : spart, n, nv / n, full, split);
   }
   // y_u = A^-1 b_u, one row per thread
   for (int row = tid; row < ((layout & LAYOUT_SHARED) ? 0 : nv); row += TPB) {
