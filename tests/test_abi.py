@@ -63,6 +63,8 @@ int main(void) {
 def test_default_params_follow_the_paper():
     p = mas.default_params(2, mas.MAS_SV)
     assert (p.omega0, p.eta_p, p.eta_u, p.restart) == (0.78, 2.68, 1.0, 20)
+    # the setup of mas_setup runs on the device by default (the same hierarchy as mas_analyze)
+    assert (p.device_sa, p.device_galerkin, p.spgemm_cap) == (1, 1, 0)
     p3 = mas.default_params(3, mas.MAS_TH, mas.MAS_RELAX_DLSC)
     assert list(p3.cheb_deg) == [4, 4, 16] and p3.nu1 == 2
     ph = mas.default_params(2, mas.MAS_SV, mas.MAS_RELAX_VANKA_DLSC)  # Table 4, Vanka-DLSC row
